@@ -1,0 +1,658 @@
+// FP64 CPU oracle for one iteration of Constrained SVGD (CSVGD) over
+// simulation parameters, after Heiden et al., "Probabilistic Inference of
+// Simulation Parameters via Parallel Differentiable Simulation".
+//
+// TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP path.  Only
+// the test suite, the smoke check and the CPU-baseline leg of the benchmark
+// may load it.  It shares no code, header, table or constant generator with
+// the GPU library, and nothing in the GPU library calls it.
+//
+// It is deliberately plain and slow: 6D spatial algebra with full 6x6
+// matrices for every model (planar ones included), forward-mode dual numbers
+// for every gradient, and a full sort for the kernel-bandwidth median.
+//
+// What each part follows (section / equation / algorithm of the paper):
+//   * aba()          Articulated Body Algorithm, App. B-A (forward dynamics).
+//   * crba_rnea()    Composite-rigid-body + recursive Newton-Euler, used only
+//                    to cross-check aba() (textbook identity H qdd = tau - C).
+//   * step()         semi-implicit Euler, App. B-A eq. "dynamics".
+//   * window()       one multiple-shooting window, Sec. III-C: rollout from
+//                    the window start state and the Gaussian observation
+//                    likelihood of eq. "combinedlikelihood".
+//   * defects        eq. "likelihood-defect" and g_def of Sec. III-E.
+//   * combination    eq. "traj_likelihood" (sum / GMM, in log space) and
+//                    App. A-B eq. "traj_likelihood_prod".
+//   * gradients      MDMM flow of Sec. III-E applied to eq. "mdmm-loss";
+//                    assembled per Algorithm 1.
+//   * bandwidth/phi  eq. "svgd_update" with the RBF kernel and the median
+//                    heuristic (Sec. III-A).
+//   * mdmm_step      Algorithm 1 update lines, with Adam or plain SGD.
+//
+// Readings taken where the paper is silent or garbled: window
+// j starts at step j*h and compares states j*h+1 .. (j+1)*h with the
+// observations of the same steps; each trajectory has its own shooting
+// states; g_def = ||(S - s_end) * u||^2 / sigma_def^2 >= 0; the SUM
+// combination includes -log K; Gaussian constants are included in reported
+// log-likelihoods; the bandwidth is med^2 / log N over the N(N-1)/2
+// distinct scaled pair distances.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "dual.hpp"
+#include "spatial.hpp"
+
+extern "C" {
+
+// Model description.  kind: 1 planar chain of point masses on massless rods
+// (joints about z, q = 0 hangs along -y), 2 seven-joint arm (modified DH)
+// carrying a box on a passive hinge about the flange x axis, 3 linear toy
+// (one prismatic unit mass, no gravity, force theta0 + theta1 * time).
+typedef struct {
+  int32_t kind;
+  int32_t n_dof;
+  int32_t M;
+  int32_t d_x;
+  int32_t obs_index[8];
+  double gravity[3];
+  double damping[8];
+  double dh_a[7], dh_alpha[7], dh_d[7];
+  double link_m[7], link_c[7][3], link_I[7][3];
+  double kp[7], kd[7], qc[7], amp[7], omega[7], phase[7];
+  double flange_d;
+  double box_m, box_c[3], box_I[3];
+  double pm_m, pm_z;
+} OrcModel;
+
+typedef struct {
+  int32_t N, K, T, n_s, h, combine;  // combine: 0 sum (GMM), 1 product
+  double dt, sigma_def, c;
+  const double* w_x;      // [d_x]   observation weights (1 / sigma_obs)
+  const double* u;        // [d_s]   defect state scales
+  const double* s0;       // [K, d_s]
+  const double* obs;      // [K, T, d_x]; row t-1 observes state t
+  const double* theta;    // [N, M]
+  const double* S;        // [N, K, n_s-1, d_s]; S[.., j-1, :] starts window j
+  const double* lam_def;  // [N, K, n_s-1]
+} OrcProblem;
+
+}  // extern "C"
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+template <class S>
+struct Chain {
+  int n;
+  Xform<S> Xtree[8];
+  int jtype[8];  // 0 revolute, 1 prismatic
+  double axis[8][3];
+  M6<S> I[8];
+};
+
+template <class S>
+M3<S> diag3(const S& a, const S& b, const S& c) {
+  M3<S> m;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) m.a[i][j] = S(0.0);
+  m.a[0][0] = a; m.a[1][1] = b; m.a[2][2] = c;
+  return m;
+}
+
+// Builds the articulated chain for parameters theta.  Planar chain: theta =
+// (m_1..m_n, l_1..l_n).  Arm: theta = (x_a, y_a, x_b, y_b), the in-plane
+// positions of the two point masses in the hinge frame.  Toy: theta drives
+// the force only.
+template <class S>
+Chain<S> build_chain(const OrcModel& md, const S* th) {
+  Chain<S> ch;
+  ch.n = md.n_dof;
+  if (md.kind == 1) {
+    const int n = md.n_dof;
+    for (int i = 0; i < n; ++i) {
+      ch.Xtree[i].E = m3ident<S>();
+      ch.Xtree[i].r = (i == 0) ? v3zero<S>() : v3<S>(S(0.0), -th[n + i - 1], S(0.0));
+      ch.jtype[i] = 0;
+      ch.axis[i][0] = 0.0; ch.axis[i][1] = 0.0; ch.axis[i][2] = 1.0;
+      ch.I[i] = rbi<S>(th[i], v3<S>(S(0.0), -th[n + i], S(0.0)), diag3<S>(S(0.0), S(0.0), S(0.0)));
+    }
+  } else if (md.kind == 2) {
+    for (int i = 0; i < 7; ++i) {
+      const double ca = std::cos(md.dh_alpha[i]), sa = std::sin(md.dh_alpha[i]);
+      // Rot_x(alpha) as an active rotation; the coordinate transform is its transpose.
+      M3<S> Rx;
+      Rx.a[0][0] = S(1.0); Rx.a[0][1] = S(0.0); Rx.a[0][2] = S(0.0);
+      Rx.a[1][0] = S(0.0); Rx.a[1][1] = S(ca);  Rx.a[1][2] = S(-sa);
+      Rx.a[2][0] = S(0.0); Rx.a[2][1] = S(sa);  Rx.a[2][2] = S(ca);
+      ch.Xtree[i].E = m3T(Rx);
+      ch.Xtree[i].r = v3<S>(S(md.dh_a[i]), S(-md.dh_d[i] * sa), S(md.dh_d[i] * ca));
+      ch.jtype[i] = 0;
+      ch.axis[i][0] = 0.0; ch.axis[i][1] = 0.0; ch.axis[i][2] = 1.0;
+      ch.I[i] = rbi<S>(S(md.link_m[i]), v3<S>(S(md.link_c[i][0]), S(md.link_c[i][1]), S(md.link_c[i][2])),
+                       diag3<S>(S(md.link_I[i][0]), S(md.link_I[i][1]), S(md.link_I[i][2])));
+    }
+    ch.Xtree[7].E = m3ident<S>();
+    ch.Xtree[7].r = v3<S>(S(0.0), S(0.0), S(md.flange_d));
+    ch.jtype[7] = 0;
+    ch.axis[7][0] = 1.0; ch.axis[7][1] = 0.0; ch.axis[7][2] = 0.0;
+    const M3<S> zero3 = diag3<S>(S(0.0), S(0.0), S(0.0));
+    M6<S> Ib = rbi<S>(S(md.box_m), v3<S>(S(md.box_c[0]), S(md.box_c[1]), S(md.box_c[2])),
+                      diag3<S>(S(md.box_I[0]), S(md.box_I[1]), S(md.box_I[2])));
+    M6<S> Ia = rbi<S>(S(md.pm_m), v3<S>(th[0], th[1], S(md.pm_z)), zero3);
+    M6<S> Ibb = rbi<S>(S(md.pm_m), v3<S>(th[2], th[3], S(md.pm_z)), zero3);
+    ch.I[7] = m6add(m6add(Ib, Ia), Ibb);
+  } else {
+    ch.Xtree[0].E = m3ident<S>();
+    ch.Xtree[0].r = v3zero<S>();
+    ch.jtype[0] = 1;
+    ch.axis[0][0] = 1.0; ch.axis[0][1] = 0.0; ch.axis[0][2] = 0.0;
+    ch.I[0] = rbi<S>(S(1.0), v3zero<S>(), diag3<S>(S(0.0), S(0.0), S(0.0)));
+  }
+  return ch;
+}
+
+// Joint torques as explicit functions of time (App. B-A: controls enter
+// f_step through t).
+template <class S>
+void joint_torque(const OrcModel& md, const S* th, double time, const S* q, const S* qd, S* tau) {
+  if (md.kind == 1) {
+    for (int i = 0; i < md.n_dof; ++i) tau[i] = -(md.damping[i] * qd[i]);
+  } else if (md.kind == 2) {
+    for (int i = 0; i < 7; ++i) {
+      const double ph = md.omega[i] * time + md.phase[i];
+      const double qdes = md.qc[i] + md.amp[i] * std::sin(ph);
+      const double qddes = md.amp[i] * md.omega[i] * std::cos(ph);
+      tau[i] = md.kp[i] * (qdes - q[i]) + md.kd[i] * (qddes - qd[i]);
+    }
+    tau[7] = -(md.damping[7] * qd[7]);
+  } else {
+    tau[0] = th[0];
+    if (md.M >= 2) tau[0] = tau[0] + th[1] * time;
+  }
+}
+
+template <class S>
+SV<S> motion_subspace(const Chain<S>& ch, int i) {
+  SV<S> s = svzero<S>();
+  const int off = (ch.jtype[i] == 0) ? 0 : 3;
+  for (int d = 0; d < 3; ++d) s.a[off + d] = S(ch.axis[i][d]);
+  return s;
+}
+
+template <class S>
+Xform<S> joint_xform(const Chain<S>& ch, int i, const S& q) {
+  Xform<S> XJ;
+  if (ch.jtype[i] == 0) {
+    XJ.E = m3T(rodrigues<S>(ch.axis[i], q));
+    XJ.r = v3zero<S>();
+  } else {
+    XJ.E = m3ident<S>();
+    XJ.r = v3<S>(q * ch.axis[i][0], q * ch.axis[i][1], q * ch.axis[i][2]);
+  }
+  return XJ;
+}
+
+// U U^T / D for the articulated-inertia update.
+template <class S>
+M6<S> m6v_outer_div(const SV<S>& Uv, const S& D) {
+  M6<S> m;
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) m.a[i][j] = Uv.a[i] * Uv.a[j] / D;
+  return m;
+}
+
+// Articulated Body Algorithm: three passes over the chain (outward
+// velocities and bias terms, inward articulated inertias, outward
+// accelerations).  Gravity enters as a fictitious base acceleration.
+template <class S>
+void aba(const Chain<S>& ch, const double g[3], const S* q, const S* qd, const S* tau, S* qdd) {
+  const int n = ch.n;
+  Xform<S> X[8];
+  SV<S> Sj[8], v[8], c[8], pA[8], U[8], a[8];
+  M6<S> IA[8];
+  S D[8], uu[8];
+  for (int i = 0; i < n; ++i) {
+    X[i] = xcompose(joint_xform(ch, i, q[i]), ch.Xtree[i]);
+    Sj[i] = motion_subspace(ch, i);
+    const SV<S> vJ = svscale(Sj[i], qd[i]);
+    const SV<S> vp = (i == 0) ? svzero<S>() : v[i - 1];
+    v[i] = svadd(m6v(xmat(X[i]), vp), vJ);
+    c[i] = crm(v[i], vJ);
+    IA[i] = ch.I[i];
+    pA[i] = crf(v[i], m6v(ch.I[i], v[i]));
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    U[i] = m6v(IA[i], Sj[i]);
+    D[i] = svdot(Sj[i], U[i]);
+    uu[i] = tau[i] - svdot(Sj[i], pA[i]);
+    if (i > 0) {
+      const M6<S> Ia = m6sub(IA[i], m6v_outer_div(U[i], D[i]));
+      const SV<S> pa = svadd(svadd(pA[i], m6v(Ia, c[i])), svscale(U[i], uu[i] / D[i]));
+      const M6<S> Xm = xmat(X[i]);
+      IA[i - 1] = m6add(IA[i - 1], m6mul(m6T(Xm), m6mul(Ia, Xm)));
+      pA[i - 1] = svadd(pA[i - 1], m6v(m6T(Xm), pa));
+    }
+  }
+  SV<S> a0 = svzero<S>();
+  for (int d = 0; d < 3; ++d) a0.a[3 + d] = S(-g[d]);
+  for (int i = 0; i < n; ++i) {
+    const SV<S> ap = (i == 0) ? a0 : a[i - 1];
+    const SV<S> a1 = svadd(m6v(xmat(X[i]), ap), c[i]);
+    qdd[i] = (uu[i] - svdot(U[i], a1)) / D[i];
+    a[i] = svadd(a1, svscale(Sj[i], qdd[i]));
+  }
+}
+
+
+// Composite-rigid-body algorithm (joint-space inertia H) and recursive
+// Newton-Euler with zero acceleration (bias C, gravity included).  Used only
+// as an independent cross-check of aba(): qdd = H^{-1} (tau - C).
+void crba_rnea(const Chain<double>& ch, const double g[3], const double* q, const double* qd,
+               double* H, double* C) {
+  const int n = ch.n;
+  Xform<double> X[8];
+  SV<double> Sj[8], v[8], a[8], f[8];
+  SV<double> a0 = svzero<double>();
+  for (int d = 0; d < 3; ++d) a0.a[3 + d] = -g[d];
+  for (int i = 0; i < n; ++i) {
+    X[i] = xcompose(joint_xform(ch, i, q[i]), ch.Xtree[i]);
+    Sj[i] = motion_subspace(ch, i);
+    const SV<double> vJ = svscale(Sj[i], qd[i]);
+    const SV<double> vp = (i == 0) ? svzero<double>() : v[i - 1];
+    const SV<double> ap = (i == 0) ? a0 : a[i - 1];
+    v[i] = svadd(m6v(xmat(X[i]), vp), vJ);
+    a[i] = svadd(m6v(xmat(X[i]), ap), crm(v[i], vJ));
+    f[i] = svadd(m6v(ch.I[i], a[i]), crf(v[i], m6v(ch.I[i], v[i])));
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    C[i] = svdot(Sj[i], f[i]);
+    if (i > 0) f[i - 1] = svadd(f[i - 1], m6v(m6T(xmat(X[i])), f[i]));
+  }
+  M6<double> IC[8];
+  for (int i = 0; i < n; ++i) IC[i] = ch.I[i];
+  for (int i = n - 1; i >= 0; --i)
+    if (i > 0) IC[i - 1] = m6add(IC[i - 1], m6mul(m6T(xmat(X[i])), m6mul(IC[i], xmat(X[i]))));
+  for (int i = 0; i < n; ++i) {
+    SV<double> F = m6v(IC[i], Sj[i]);
+    H[i * n + i] = svdot(Sj[i], F);
+    int j = i;
+    while (j > 0) {
+      F = m6v(m6T(xmat(X[j])), F);
+      j = j - 1;
+      H[i * n + j] = svdot(Sj[j], F);
+      H[j * n + i] = H[i * n + j];
+    }
+  }
+}
+
+// One semi-implicit Euler step (App. B-A eq. "dynamics"): the acceleration
+// from ABA at (q_t, qd_t, tau(t)) updates the velocity first, and the new
+// velocity updates the position.
+template <class S>
+void step(const OrcModel& md, const Chain<S>& ch, const S* th, double time, double dt, S* q, S* qd) {
+  S tau[8], qdd[8];
+  joint_torque<S>(md, th, time, q, qd, tau);
+  aba<S>(ch, md.gravity, q, qd, tau, qdd);
+  for (int i = 0; i < md.n_dof; ++i) qd[i] = qd[i] + dt * qdd[i];
+  for (int i = 0; i < md.n_dof; ++i) q[i] = q[i] + dt * qd[i];
+}
+
+// One multiple-shooting window (Sec. III-C): start at state `start` at step
+// j*h, take h steps, and accumulate the Gaussian log-likelihood
+// (eq. "combinedlikelihood") of the observations of steps j*h+1..(j+1)*h.
+// Returns the end state; optionally writes the h visited states.
+template <class S>
+S window(const OrcModel& md, const OrcProblem& pr, const S* th, const S* start, int k, int j,
+         S* end_state, double* traj /* [h, d_s] or null */) {
+  const int n = md.n_dof, ds = 2 * n;
+  const Chain<S> ch = build_chain<S>(md, th);
+  S q[8], qd[8];
+  for (int i = 0; i < n; ++i) { q[i] = start[i]; qd[i] = start[n + i]; }
+  const double log_sqrt_2pi = 0.5 * std::log(2.0 * kPi);
+  S ll(0.0);
+  for (int s = 0; s < pr.h; ++s) {
+    const int t = j * pr.h + s;  // index of the state the step starts from
+    step<S>(md, ch, th, t * pr.dt, pr.dt, q, qd);
+    const double* x_real = pr.obs + ((size_t)k * pr.T + t) * md.d_x;  // observes state t+1
+    for (int d = 0; d < md.d_x; ++d) {
+      const int si = md.obs_index[d];
+      const S x_sim = (si < n) ? q[si] : qd[si - n];
+      const S r = (x_real[d] - x_sim) * pr.w_x[d];
+      ll = ll - 0.5 * (r * r) - (log_sqrt_2pi - std::log(pr.w_x[d]));
+    }
+    if (traj)
+      for (int i = 0; i < n; ++i) {
+        traj[s * ds + i] = val(q[i]);
+        traj[s * ds + n + i] = val(qd[i]);
+      }
+  }
+  for (int i = 0; i < n; ++i) { end_state[i] = q[i]; end_state[n + i] = qd[i]; }
+  return ll;
+}
+
+const double* start_state(const OrcProblem& pr, int ds, int i, int k, int j) {
+  if (j == 0) return pr.s0 + (size_t)k * ds;
+  return pr.S + (((size_t)i * pr.K + k) * (pr.n_s - 1) + (j - 1)) * ds;
+}
+
+// Defect constraint of Sec. III-E: g_def = ||(S_{j+1} - s_end) * u||^2 / sigma_def^2.
+double defect(const OrcProblem& pr, int ds, const double* S_next, const double* s_end) {
+  double g = 0.0;
+  for (int d = 0; d < ds; ++d) {
+    const double e = (S_next[d] - s_end[d]) * pr.u[d];
+    g += e * e;
+  }
+  return g / (pr.sigma_def * pr.sigma_def);
+}
+
+// Combination over trajectories: eq. "traj_likelihood" (equally weighted
+// mixture, evaluated in log space with the 1/K weight) or App. A-B
+// eq. "traj_likelihood_prod".  Returns log p and writes the weights
+// w_k = d log p / d l_k.
+double combine(const OrcProblem& pr, const double* l_k, double* w) {
+  const int K = pr.K;
+  if (pr.combine == 1) {
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) { s += l_k[k]; w[k] = 1.0; }
+    return s;
+  }
+  double mx = l_k[0];
+  for (int k = 1; k < K; ++k) mx = std::max(mx, l_k[k]);
+  double z = 0.0;
+  for (int k = 0; k < K; ++k) z += std::exp(l_k[k] - mx);
+  for (int k = 0; k < K; ++k) w[k] = std::exp(l_k[k] - mx) / z;
+  return mx + std::log(z) - std::log((double)K);
+}
+
+template <int P>
+void window_grad(const OrcModel& md, const OrcProblem& pr, const double* th, const double* start,
+                 int k, int j, double* ll, double* dl_dth, double* dl_ds, double* send,
+                 double* dsend_dth /* [d_s][M] */, double* dsend_ds /* [d_s][d_s] */) {
+  const int M = md.M, ds = 2 * md.n_dof;
+  Dual<P> thd[16], sd[16], ed[16];
+  for (int m = 0; m < M; ++m) { thd[m] = Dual<P>(th[m]); thd[m].d[m] = 1.0; }
+  for (int d = 0; d < ds; ++d) { sd[d] = Dual<P>(start[d]); sd[d].d[M + d] = 1.0; }
+  const Dual<P> l = window<Dual<P>>(md, pr, thd, sd, k, j, ed, nullptr);
+  *ll = l.v;
+  for (int m = 0; m < M; ++m) dl_dth[m] = l.d[m];
+  for (int d = 0; d < ds; ++d) dl_ds[d] = l.d[M + d];
+  for (int d = 0; d < ds; ++d) {
+    send[d] = ed[d].v;
+    for (int m = 0; m < M; ++m) dsend_dth[d * M + m] = ed[d].d[m];
+    for (int e = 0; e < ds; ++e) dsend_ds[d * ds + e] = ed[d].d[M + e];
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_version(void) { return 1; }
+
+// Joint torques at time `time` (for tests of the controllers).
+void orc_tau(const OrcModel* md, const double* th, double time, const double* q, const double* qd, double* tau) {
+  joint_torque<double>(*md, th, time, q, qd, tau);
+}
+
+void orc_aba(const OrcModel* md, const double* th, const double* q, const double* qd, const double* tau,
+             double* qdd) {
+  const Chain<double> ch = build_chain<double>(*md, th);
+  aba<double>(ch, md->gravity, q, qd, tau, qdd);
+}
+
+void orc_crba_rnea(const OrcModel* md, const double* th, const double* q, const double* qd, double* H,
+                   double* C) {
+  const Chain<double> ch = build_chain<double>(*md, th);
+  crba_rnea(ch, md->gravity, q, qd, H, C);
+}
+
+// Single-shooting rollout of n_steps from state s0 at step index t0:
+// f_sim of Sec. II, writing states t0+1 .. t0+n_steps.
+void orc_rollout(const OrcModel* md, const double* th, const double* s0, int t0, int n_steps, double dt,
+                 double* traj) {
+  const int n = md->n_dof, ds = 2 * n;
+  const Chain<double> ch = build_chain<double>(*md, th);
+  double q[8], qd[8];
+  for (int i = 0; i < n; ++i) { q[i] = s0[i]; qd[i] = s0[n + i]; }
+  for (int s = 0; s < n_steps; ++s) {
+    step<double>(*md, ch, th, (t0 + s) * dt, dt, q, qd);
+    for (int i = 0; i < n; ++i) { traj[s * ds + i] = q[i]; traj[s * ds + n + i] = qd[i]; }
+  }
+}
+
+// Forward pass for selected particles: per-window end states, visited
+// states (optional), window log-likelihoods, defects, and the combined
+// log-likelihood with its trajectory weights.
+void orc_forward(const OrcModel* md, const OrcProblem* pr, int n_sel, const int* sel, double* traj,
+                 double* end_states, double* ll_win, double* gdef, double* logp, double* wk) {
+  const int ds = 2 * md->n_dof, K = pr->K, ns = pr->n_s, M = md->M;
+  const int units = n_sel * K * ns;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int u = 0; u < units; ++u) {
+    const int s = u / (K * ns), k = (u / ns) % K, j = u % ns;
+    const int i = sel[s];
+    const double* th = pr->theta + (size_t)i * M;
+    double* tr = traj ? traj + (((size_t)s * K + k) * pr->T + (size_t)j * pr->h) * ds : nullptr;
+    ll_win[u] = window<double>(*md, *pr, th, start_state(*pr, ds, i, k, j), k, j, end_states + (size_t)u * ds, tr);
+  }
+  for (int s = 0; s < n_sel; ++s) {
+    const int i = sel[s];
+    std::vector<double> lk(K);
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < ns; ++j) acc += ll_win[((size_t)s * K + k) * ns + j];
+      lk[k] = acc;
+      for (int j = 0; j + 1 < ns; ++j)
+        gdef[((size_t)s * K + k) * (ns - 1) + j] =
+            defect(*pr, ds, start_state(*pr, ds, i, k, j + 1), end_states + (((size_t)s * K + k) * ns + j) * ds);
+    }
+    logp[s] = combine(*pr, lk.data(), wk + (size_t)s * K);
+  }
+}
+
+// Gradients for selected particles by forward-mode dual numbers, assembled
+// into the MDMM flow of Sec. III-E / Algorithm 1:
+//   g_obs[i]  = d log p_obs / d theta                (enters phi)
+//   g_con[i]  = sum_{k,j} (lam_def + c g_def) d g_def / d theta
+//   S_dot     = w_ik d l_ikj / d S_j - d Phi / d S_j  (Phi = lam g + c/2 g^2)
+// Also returns the forward quantities of orc_forward.  Returns 0, or -1 if
+// M + d_s exceeds the compiled dual width.
+int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int* sel, double* end_states,
+                 double* ll_win, double* gdef, double* logp, double* wk, double* g_obs, double* g_con,
+                 double* S_dot, double* dl_dth_unit /* [n_sel,K,n_s,M] or null */) {
+  const int ds = 2 * md->n_dof, K = pr->K, ns = pr->n_s, M = md->M;
+  const int P = M + ds;
+  if (P > 32 || M > 16 || ds > 16) return -1;
+  const int units = n_sel * K * ns;
+  std::vector<double> dl_dth((size_t)units * M), dl_ds((size_t)units * ds);
+  std::vector<double> dse_dth((size_t)units * ds * M), dse_ds((size_t)units * ds * ds);
+#pragma omp parallel for schedule(dynamic, 2)
+  for (int u = 0; u < units; ++u) {
+    const int s = u / (K * ns), k = (u / ns) % K, j = u % ns;
+    const int i = sel[s];
+    const double* th = pr->theta + (size_t)i * M;
+    const double* st = start_state(*pr, ds, i, k, j);
+    double* a0 = &dl_dth[(size_t)u * M];
+    double* a1 = &dl_ds[(size_t)u * ds];
+    double* a2 = end_states + (size_t)u * ds;
+    double* a3 = &dse_dth[(size_t)u * ds * M];
+    double* a4 = &dse_ds[(size_t)u * ds * ds];
+    if (P <= 4) window_grad<4>(*md, *pr, th, st, k, j, &ll_win[u], a0, a1, a2, a3, a4);
+    else if (P <= 8) window_grad<8>(*md, *pr, th, st, k, j, &ll_win[u], a0, a1, a2, a3, a4);
+    else if (P <= 20) window_grad<20>(*md, *pr, th, st, k, j, &ll_win[u], a0, a1, a2, a3, a4);
+    else window_grad<32>(*md, *pr, th, st, k, j, &ll_win[u], a0, a1, a2, a3, a4);
+  }
+  if (dl_dth_unit) std::memcpy(dl_dth_unit, dl_dth.data(), sizeof(double) * units * M);
+  const double inv_s2 = 1.0 / (pr->sigma_def * pr->sigma_def);
+  for (int s = 0; s < n_sel; ++s) {
+    const int i = sel[s];
+    std::vector<double> lk(K);
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < ns; ++j) acc += ll_win[((size_t)s * K + k) * ns + j];
+      lk[k] = acc;
+    }
+    double* w = wk + (size_t)s * K;
+    logp[s] = combine(*pr, lk.data(), w);
+    for (int m = 0; m < M; ++m) { g_obs[(size_t)s * M + m] = 0.0; g_con[(size_t)s * M + m] = 0.0; }
+    for (int k = 0; k < K; ++k) {
+      for (int j = 0; j < ns; ++j) {
+        const size_t u = ((size_t)s * K + k) * ns + j;
+        for (int m = 0; m < M; ++m) g_obs[(size_t)s * M + m] += w[k] * dl_dth[u * M + m];
+      }
+      for (int j = 1; j < ns; ++j) {
+        double* sd = S_dot + (((size_t)s * K + k) * (ns - 1) + (j - 1)) * ds;
+        const size_t u = ((size_t)s * K + k) * ns + j;
+        for (int d = 0; d < ds; ++d) sd[d] = w[k] * dl_ds[u * ds + d];
+      }
+      for (int j = 0; j + 1 < ns; ++j) {
+        const size_t u = ((size_t)s * K + k) * ns + j;
+        const double* Snext = start_state(*pr, ds, i, k, j + 1);
+        const double* se = end_states + u * ds;
+        const double g = defect(*pr, ds, Snext, se);
+        gdef[((size_t)s * K + k) * (ns - 1) + j] = g;
+        const double lam = pr->lam_def[((size_t)i * K + k) * (ns - 1) + j];
+        const double mult = lam + pr->c * g;  // d Phi / d g
+        // d g / d s_end = -2 e u / sigma^2 with e = (S_next - s_end) u
+        double dg_dse[16];
+        for (int d = 0; d < ds; ++d) {
+          const double e = (Snext[d] - se[d]) * pr->u[d];
+          dg_dse[d] = -2.0 * e * pr->u[d] * inv_s2;
+        }
+        for (int m = 0; m < M; ++m) {
+          double acc = 0.0;
+          for (int d = 0; d < ds; ++d) acc += dg_dse[d] * dse_dth[(u * ds + d) * M + m];
+          g_con[(size_t)s * M + m] += mult * acc;
+        }
+        // window j's start state is a variable only for j >= 1
+        if (j >= 1) {
+          double* sd = S_dot + (((size_t)s * K + k) * (ns - 1) + (j - 1)) * ds;
+          for (int e = 0; e < ds; ++e) {
+            double acc = 0.0;
+            for (int d = 0; d < ds; ++d) acc += dg_dse[d] * dse_ds[(u * ds + d) * ds + e];
+            sd[e] -= mult * acc;
+          }
+        }
+        // direct dependence of defect j on its target S_{j+1}: d g / d S_next = +2 e u / sigma^2
+        double* sn = S_dot + (((size_t)s * K + k) * (ns - 1) + j) * ds;
+        for (int d = 0; d < ds; ++d) sn[d] -= mult * (-dg_dse[d]);
+      }
+    }
+  }
+  return 0;
+}
+
+// Median-heuristic bandwidth (Sec. III-A): distances between the N(N-1)/2
+// distinct pairs, each coordinate divided by rho_m, sorted in full; the
+// median (mean of the two middle values for an even count) gives
+// h = med^2 / log N.  N = 1 or a vanishing median gives h = 1.
+// variant 1 uses log(N+1).
+double orc_bandwidth(int N, int M, const double* theta, const double* rho, int variant, double* med_out) {
+  std::vector<double> d2;
+  d2.reserve((size_t)N * (N - 1) / 2);
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j) {
+      double s = 0.0;
+      for (int m = 0; m < M; ++m) {
+        const double z = (theta[(size_t)i * M + m] - theta[(size_t)j * M + m]) / rho[m];
+        s += z * z;
+      }
+      d2.push_back(s);
+    }
+  double med = 0.0;
+  if (!d2.empty()) {
+    std::sort(d2.begin(), d2.end());
+    const size_t P = d2.size();
+    med = 0.5 * (std::sqrt(d2[(P - 1) / 2]) + std::sqrt(d2[P / 2]));
+  }
+  if (med_out) *med_out = med;
+  const double lg = (variant == 1) ? std::log((double)N + 1.0) : std::log((double)N);
+  if (N <= 1 || med * med < 1e-300 || lg <= 0.0) return 1.0;
+  return med * med / lg;
+}
+
+// SVGD direction of eq. "svgd_update" with k(a, b) = exp(-||(a - b)/rho||^2 / h):
+// phi_i = (1/N) sum_j [ k(theta_j, theta_i) grad_j + grad_{theta_j} k(theta_j, theta_i) ].
+void orc_phi(int N, int M, const double* theta, const double* grad, const double* rho, double h, int n_sel,
+             const int* sel, double* phi) {
+  for (int s = 0; s < n_sel; ++s) {
+    const int i = sel[s];
+    for (int m = 0; m < M; ++m) phi[(size_t)s * M + m] = 0.0;
+    for (int j = 0; j < N; ++j) {
+      double d2 = 0.0;
+      for (int m = 0; m < M; ++m) {
+        const double z = (theta[(size_t)j * M + m] - theta[(size_t)i * M + m]) / rho[m];
+        d2 += z * z;
+      }
+      const double kij = std::exp(-d2 / h);
+      for (int m = 0; m < M; ++m) {
+        const double dk = kij * (2.0 / h) * (theta[(size_t)i * M + m] - theta[(size_t)j * M + m]) / (rho[m] * rho[m]);
+        phi[(size_t)s * M + m] += kij * grad[(size_t)j * M + m] + dk;
+      }
+    }
+    for (int m = 0; m < M; ++m) phi[(size_t)s * M + m] /= (double)N;
+  }
+}
+
+// One MDMM update (Sec. III-E, Algorithm 1), simultaneous for all variables:
+//   g_lim = clamp(theta, lo, hi) - theta, d g_lim / d theta = -1 outside [lo, hi]
+//   theta_dot = phi - (lam_lim + c g_lim) d g_lim/d theta - g_con
+//   lam_lim_dot = g_lim, lam_def_dot = g_def, S_dot as given.
+// optimizer 0: x += lr * x_dot.  optimizer 1: Adam on (theta, S) with -x_dot
+// as the gradient (beta1 0.9, beta2 0.999, eps 1e-8), iteration `it` >= 1.
+// Lagrange multipliers always take plain ascent steps of size eps_lam.
+void orc_mdmm_step(int N, int M, int K, int n_s, int d_s, double c, const double* lo, const double* hi,
+                   const double* phi, const double* g_con, const double* S_dot, const double* gdef,
+                   const double* lr_theta, const double* lr_S, double eps_lam, int optimizer, int it,
+                   double* theta, double* S, double* lam_lim, double* lam_def, double* adam_m, double* adam_v) {
+  const int nS = K * (n_s - 1) * d_s;
+  const int stride = M + nS;
+  const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  for (int i = 0; i < N; ++i) {
+    for (int m = 0; m < M; ++m) {
+      const size_t im = (size_t)i * M + m;
+      const double x = theta[im];
+      const double cl = std::min(std::max(x, lo[m]), hi[m]);
+      const double g = cl - x;
+      const double dgdx = (x < lo[m] || x > hi[m]) ? -1.0 : 0.0;
+      const double xdot = phi[im] - (lam_lim[im] + c * g) * dgdx - g_con[im];
+      if (optimizer == 0) {
+        theta[im] = x + lr_theta[m] * xdot;
+      } else {
+        const size_t a = (size_t)i * stride + m;
+        const double gr = -xdot;
+        adam_m[a] = b1 * adam_m[a] + (1.0 - b1) * gr;
+        adam_v[a] = b2 * adam_v[a] + (1.0 - b2) * gr * gr;
+        const double mh = adam_m[a] / (1.0 - std::pow(b1, it));
+        const double vh = adam_v[a] / (1.0 - std::pow(b2, it));
+        theta[im] = x - lr_theta[m] * mh / (std::sqrt(vh) + eps);
+      }
+      lam_lim[im] += eps_lam * g;
+    }
+    for (int e = 0; e < nS; ++e) {
+      const size_t ie = (size_t)i * nS + e;
+      const int d = e % d_s;
+      const double xdot = S_dot[ie];
+      if (optimizer == 0) {
+        S[ie] += lr_S[d] * xdot;
+      } else {
+        const size_t a = (size_t)i * stride + M + e;
+        const double gr = -xdot;
+        adam_m[a] = b1 * adam_m[a] + (1.0 - b1) * gr;
+        adam_v[a] = b2 * adam_v[a] + (1.0 - b2) * gr * gr;
+        const double mh = adam_m[a] / (1.0 - std::pow(b1, it));
+        const double vh = adam_v[a] / (1.0 - std::pow(b2, it));
+        S[ie] -= lr_S[d] * mh / (std::sqrt(vh) + eps);
+      }
+    }
+    for (int e = 0; e < K * (n_s - 1); ++e) {
+      const size_t ie = (size_t)i * K * (n_s - 1) + e;
+      lam_def[ie] += eps_lam * gdef[ie];
+    }
+  }
+}
+
+}  // extern "C"
