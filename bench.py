@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Throughput of one CSVGD iteration (Algorithm 1) on one MI355X.
+
+Workload (default): the double-pendulum problem -- N = 256 particles,
+M = 4 parameters (2 masses, 2 lengths), K = 4 observed trajectories of
+T = 400 steps at dt = 0.005 s, 10 shooting windows, random initial angles in
+[-pi, pi]; synthetic data (seeded), observations from the library's own
+rollout at the generating parameters plus Gaussian noise.
+
+A step is one full iteration over all particles: reverse-mode gradient of
+the multiple-shooting likelihood and defects (sim_batch_adjoint), the SVGD
+direction with the median-heuristic bandwidth (svgd_phi) and the MDMM/Adam
+update (svgd_step).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: value = particle-sim-steps/s = N K T per iteration x
+iterations / elapsed, plus the roofline of the dominant kernel (the fused
+window forward+adjoint kernel) and the FP64 CPU oracle timed on a bounded
+sample of the same workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--no-graph", action="store_true", help="plain launches instead of graph replay")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(pb, obs, theta, S, target_s):
+    """The FP64 oracle (forward-mode duals, OpenMP over window units) timed on
+    a bounded sample: full CSVGD iterations over a subset of particles."""
+    from oracle import oracle as orc
+
+    n_all = theta.shape[0]
+    sel_n = max(1, min(n_all, 16))
+    st = orc.State(pb, theta, S)
+    sel = np.arange(sel_n, dtype=np.int32)
+    t0 = time.perf_counter()
+    orc.gradient(pb, obs, st, sel=sel)
+    t1 = time.perf_counter() - t0
+    per_particle = t1 / sel_n
+    sel_n = int(max(1, min(n_all, target_s / max(per_particle, 1e-9))))
+    sel = np.arange(sel_n, dtype=np.int32)
+    t0 = time.perf_counter()
+    g = orc.gradient(pb, obs, st, sel=sel)
+    h, _ = orc.bandwidth(st.theta, pb.rho)
+    orc.phi(st.theta, np.zeros((n_all, pb.M)), pb.rho, h, sel=sel)
+    el = time.perf_counter() - t0
+    steps = sel_n * pb.K * pb.T
+    threads = orc.lib().orc_threads() if hasattr(orc.lib(), "orc_threads") else os.cpu_count()
+    return {
+        "value": steps / el,
+        "unit": "particle-sim-steps/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": "%d of %d particles, all %d trajectories x %d steps: forward-mode-dual gradient, bandwidth "
+                  "and phi rows, one iteration, %.1f s" % (sel_n, n_all, pb.K, pb.T, el),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the method's data-parallel path runs on a single device "
+              "(see the sharding note in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2109_08815_amd import driver, synth
+    from paper_2109_08815_amd import lib as L
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    L.lib()
+    pb = synth.make_problem(args.config)
+    print("setup %s N=%d K=%d T=%d n_s=%d" % (args.config, pb.N, pb.K, pb.T, pb.n_s), file=sys.stderr, flush=True)
+    obs = driver.gpu_observations(pb)
+    S = driver.gpu_shooting_init(pb, pb.particles)
+    job = L.Job(pb, obs, theta=pb.particles, S=S, device_iter=True)
+    run = driver.CSVGD([job])
+    for _ in range(max(1, args.warmup)):
+        run.step()
+    torch.cuda.synchronize()
+    use_graph = not args.no_graph
+    if use_graph:
+        run.capture()
+        run.replay()
+        torch.cuda.synchronize()
+
+    # ---- timed region ----
+    if not use_graph:
+        L.timing_enable(True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        if use_graph:
+            run.replay()
+        else:
+            run.step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    if use_graph:
+        # kernel timing: the same iteration with plain launches right after
+        L.timing_enable(True)
+        for _ in range(min(args.steps, 200)):
+            run.step()
+        torch.cuda.synchronize()
+    kt = L.timing_read()
+    L.timing_enable(False)
+    elapsed = max(ms / 1e3, wall) if ms > 0 else wall
+    steps_per_iter = pb.N * pb.K * pb.T
+    value = steps_per_iter * args.steps / elapsed
+
+    fwd, rev, transc = L.algorithmic_flops(L.PDS_MODEL_PLANAR, pb.n_dof)
+    flops_per_launch = steps_per_iter * (fwd + 2 * rev)
+    k_ms = float(np.mean(kt)) if len(kt) else float("nan")
+    achieved = flops_per_launch / (k_ms / 1e3) / 1e12
+    finite = bool(torch.isfinite(job.theta).all().item())
+    out = {
+        "metric": "particle-sim-steps/s (fwd+adjoint)",
+        "value": value,
+        "unit": "particle-sim-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 accumulation and median)",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s N=%d M=%d K=%d T=%d dt=%g n_s=%d" % (
+            args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain"}[args.config],
+            pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": "graph" if use_graph else "plain"},
+        "iters_per_s": args.steps / elapsed,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": None,
+            "kernel": "planar_adjoint_kernel<%d>" % pb.n_dof,
+            "kernel_ms": k_ms,
+            "flops_per_particle_step": fwd + 2 * rev,
+        },
+        "finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        th = pb.particles
+        out["cpu_baseline"] = cpu_baseline(pb, obs, th, S, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

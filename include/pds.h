@@ -1,0 +1,223 @@
+/*
+ * pds.h -- C ABI of the MI355X (gfx950) library for Constrained SVGD over
+ * simulation parameters by parallel differentiable simulation
+ * (Heiden et al., "Probabilistic Inference of Simulation Parameters via
+ * Parallel Differentiable Simulation").
+ *
+ * One CSVGD iteration (Algorithm 1) is
+ *     sim_batch_adjoint -> svgd_phi -> svgd_step
+ * over every particle of every job in a batch.  loglik_multishoot and
+ * sim_batch_forward are the forward-only paths.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Jobs.  A call takes a batch of n_jobs problems as two arrays with the same
+ *   contents: h_jobs in host memory (read during the call to size launches
+ *   and validate) and d_jobs in device memory (read by the kernels).  Both
+ *   are owned by the caller and must stay unchanged until the work queued by
+ *   the call has finished.  One job is a batch of one; 1 <= n_jobs <=
+ *   PDS_MAX_JOBS.
+ * Memory.  Every pointer inside a pds_job is caller-owned device memory,
+ *   row-major and contiguous with the shapes given below, 4-byte aligned for
+ *   float/int32 and 8-byte aligned for double arrays.  The library never
+ *   allocates or frees device memory and keeps no pointer after a call
+ *   returns.  Scratch memory comes from the caller's workspace `ws` of
+ *   `ws_bytes` bytes (256-byte aligned), sized by pds_workspace_size(); calls
+ *   that need none accept ws = NULL.
+ * Streams.  Work is queued on `stream` (a hipStream_t passed as void*; NULL
+ *   is the default stream).  Calls are asynchronous: no host synchronisation
+ *   and no host<->device copy happens inside them.  Calls are re-entrant;
+ *   concurrent calls need disjoint outputs and workspaces.
+ * Errors.  Every call returns PDS_OK (0) or a negative code; on error nothing
+ *   has been queued and pds_last_error() returns a thread-local message.
+ *   Numerical trouble is never an error: it is reported per particle in
+ *   job.flags (bit 0 a non-finite state, bit 1 a non-finite log-likelihood
+ *   or gradient, bit 2 a parameter outside its limits).  flags are OR-ed
+ *   into, never cleared, by the library.
+ *
+ * Notation: N particles, M parameters, K observed trajectories of T steps,
+ * n_s shooting windows of h = T / n_s steps, n_dof joints, d_s = 2 n_dof
+ * state components s = [q, qd], d_x observed components, U = N K n_s window
+ * units.  Window j of trajectory k starts at step j h from s0[k] (j = 0) or
+ * from the shooting state S[i,k,j-1] (j >= 1) and covers states
+ * j h + 1 .. (j + 1) h, which it compares with the observations of the same
+ * steps (Sec. III-C, eq. ms_likelihood).
+ */
+#ifndef PDS_H
+#define PDS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDS_OK 0
+#define PDS_EINVAL (-1)        /* bad shape, pointer, alignment or scalar */
+#define PDS_EUNSUPPORTED (-2)  /* model kind or size above compiled limits */
+#define PDS_EWORKSPACE (-3)    /* workspace missing or too small */
+#define PDS_ELAUNCH (-4)       /* the HIP runtime refused a launch */
+
+#define PDS_MAX_JOBS 64
+#define PDS_MAX_M 16
+#define PDS_MAX_DOF 8
+
+/* Models.  PLANAR: chain of n_dof (1..5) revolute joints about z, link i a
+ * massless rod of length l_i with a point mass m_i at its tip, q = 0 hanging
+ * along the gravity direction; theta = (m_1..m_n, l_1..l_n), M = 2 n_dof;
+ * observes x = q (d_x = n_dof); consts = [g_x, g_y, b_1..b_n] (gravity in
+ * the plane, joint damping tau_i = -b_i qd_i).
+ * ARM: reserved for the 7-joint arm with a hinged box (not in this build:
+ * calls return PDS_EUNSUPPORTED). */
+#define PDS_MODEL_PLANAR 1
+#define PDS_MODEL_ARM 2
+
+#define PDS_COMBINE_SUM 0   /* equally weighted mixture over trajectories, eq. traj_likelihood */
+#define PDS_COMBINE_PROD 1  /* product over trajectories, App. A-B eq. traj_likelihood_prod */
+
+#define PDS_OPT_SGD 0
+#define PDS_OPT_ADAM 1
+
+/* which-call selector for pds_workspace_size */
+#define PDS_CALL_FORWARD 0
+#define PDS_CALL_LOGLIK 1
+#define PDS_CALL_ADJOINT 2
+#define PDS_CALL_PHI 3
+#define PDS_CALL_STEP 4
+#define PDS_CALL_ALL 5
+
+typedef struct pds_job {
+  /* ---- shape and scalars ---- */
+  int32_t model;      /* PDS_MODEL_* */
+  int32_t n_dof;
+  int32_t M;          /* 1..PDS_MAX_M */
+  int32_t d_x;
+  int32_t N;          /* particles, >= 1 */
+  int32_t K;          /* trajectories, >= 1 */
+  int32_t T;          /* steps per trajectory, T = n_s * h */
+  int32_t n_s;        /* shooting windows, >= 1 */
+  int32_t h;          /* steps per window, >= 1 */
+  int32_t combine;    /* PDS_COMBINE_* */
+  float dt;           /* > 0 */
+  float sigma_def;    /* > 0, defect scale of eq. likelihood-defect */
+  float c;            /* >= 0, MDMM damping constant of eq. mdmm-loss */
+  float eps_lam;      /* step size of the multiplier ascent */
+  /* ---- constant inputs ---- */
+  const float* consts;    /* model constants, layout per model kind */
+  const float* lo;        /* [M] lower parameter limits (Sec. III-D) */
+  const float* hi;        /* [M] upper parameter limits */
+  const float* rho;       /* [M] kernel length scales (> 0) */
+  const float* w_x;       /* [d_x] observation weights 1 / sigma_obs (> 0) */
+  const float* u;         /* [d_s] defect state scales */
+  const float* lr_theta;  /* [M] step sizes for theta */
+  const float* lr_S;      /* [d_s] step sizes for shooting states */
+  const float* s0;        /* [K, d_s] known start states */
+  const float* obs;       /* [K, T, d_x]; row t-1 observes state t */
+  const double* seed_logp;  /* [N] adjoint seed of log p, NULL = 1 */
+  const double* seed_gdef;  /* [N, K, n_s-1] seed of g_def, NULL = lam_def + c g_def */
+  /* ---- particle state (in/out) ---- */
+  float* theta;     /* [N, M] */
+  float* S;         /* [N, K, n_s-1, d_s] shooting states */
+  float* lam_lim;   /* [N, M] */
+  float* lam_def;   /* [N, K, n_s-1] */
+  float* adam_m;    /* [N, M + K (n_s-1) d_s] */
+  float* adam_v;    /* [N, M + K (n_s-1) d_s] */
+  /* ---- outputs ---- */
+  float* end_states;  /* [N, K, n_s, d_s] last state of each window */
+  float* traj;        /* [N, K, T, d_s] visited states, or NULL (sim_batch_forward only) */
+  double* ll_win;     /* [N, K, n_s] window log-likelihoods (with Gaussian constants) */
+  double* gdef;       /* [N, K, n_s-1] defects ||(S_{j+1} - s_end) u||^2 / sigma_def^2 */
+  double* logp;       /* [N] log p_obs per particle */
+  double* wk;         /* [N, K] d log p / d l_k (mixture responsibilities, or 1) */
+  double* g_obs;      /* [N, M] seed_logp * d log p / d theta */
+  double* g_con;      /* [N, M] sum seed_gdef * d g_def / d theta */
+  float* S_dot;       /* [N, K, n_s-1, d_s] seed_logp d log p/dS - sum seed_gdef d g_def/dS */
+  float* phi;         /* [N, M] SVGD direction */
+  double* bandwidth;  /* [1] kernel bandwidth h used by phi */
+  int32_t* flags;     /* [N] per-particle status bits */
+  int32_t* iter_dev;  /* [1] Adam iteration counter in device memory, or NULL:
+                         when set, svgd_step uses *iter_dev + 1 (ignoring its
+                         `iter` argument) and then increments *iter_dev, so a
+                         captured graph can be replayed without new arguments */
+} pds_job;
+
+/* Rolls out every window (a batched f_sim of Sec. II with the semi-implicit
+ * Euler step of App. B-A eq. dynamics; forward dynamics by the Articulated
+ * Body Algorithm).  Writes end_states and, where job.traj != NULL, every
+ * visited state.  Needs no workspace. */
+int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Multiple-shooting log-likelihood (Sec. III-B/C): window rollouts, the
+ * Gaussian observation terms of eq. combinedlikelihood summed in FP64 per
+ * window (ll_win), the defects g_def of Sec. III-E, and the combination over
+ * trajectories (logp, wk).  Writes end_states, ll_win, gdef, logp, wk.
+ * Needs no workspace. */
+int loglik_multishoot(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Reverse-mode gradient of the multiple-shooting likelihood and of the
+ * defect terms (App. B-A: chain rule through f_step), recomputing each
+ * window from its start state; assembled for the MDMM flow of Sec. III-E /
+ * Algorithm 1.  Writes everything loglik_multishoot writes plus g_obs,
+ * g_con and S_dot. */
+int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* SVGD direction of eq. svgd_update with the RBF kernel
+ * k(a, b) = exp(-||(a - b) / rho||^2 / h) and the median heuristic
+ * h = med^2 / log N (Sec. III-A), med the exact FP64 median of the
+ * N (N - 1) / 2 scaled pair distances (mean of the two middle values for an
+ * even count; h = 1 for N = 1).  Uses g_obs as the score.  Writes bandwidth
+ * and phi. */
+int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+             void* stream);
+
+/* MDMM update of Sec. III-E / Algorithm 1, simultaneous for all variables:
+ * theta_dot = phi - (lam_lim + c g_lim) dg_lim/dtheta - g_con with
+ * g_lim = clamp(theta, lo, hi) - theta; S_dot as computed; lam_lim += eps_lam
+ * g_lim; lam_def += eps_lam g_def.  optimizer PDS_OPT_SGD: x += lr x_dot;
+ * PDS_OPT_ADAM: Adam (0.9, 0.999, 1e-8) on (theta, S) with -x_dot as the
+ * gradient, iteration `iter` >= 1 for bias correction.  Sets flags bit 2 for
+ * particles left outside their limits.  Needs no workspace. */
+int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int32_t optimizer,
+              int32_t iter, void* stream);
+
+/* Workspace bytes the call `which` (PDS_CALL_*) needs for this batch;
+ * PDS_CALL_ALL gives the maximum over all calls.  0 on invalid input (see
+ * pds_last_error). */
+size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which);
+
+/* Message for the last error on this thread ("" if none). */
+const char* pds_last_error(void);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t pds_version(void);
+
+/* ---- measurement helpers (not on the inference path) ---- */
+
+/* Algorithmic FLOPs of one simulation step of the given model (ABA + Euler +
+ * observation residual) and of one reverse step for one adjoint channel
+ * (reverse of the same + observation seed + FP64 parameter accumulation),
+ * counted by running the library's own step functions on the host with a
+ * counting scalar type (add, sub, mul, div = 1 each); sin/cos evaluations
+ * are returned separately.  In-window recomputation is not counted.
+ * Returns PDS_OK, PDS_EINVAL or PDS_EUNSUPPORTED. */
+int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_step, double* rev_step,
+                          double* transcendental);
+
+/* Kernel timing for benchmarks.  While enabled, every sim_batch_adjoint and
+ * loglik_multishoot call records a pair of HIP events on its stream around
+ * its window-kernel launches (a ring of 4096 pairs).  pds_timing_enable(1)
+ * clears the ring; pds_timing_read waits for the recorded events and writes
+ * up to max_n elapsed times in milliseconds, returning how many it wrote
+ * (or a negative error code). */
+int pds_timing_enable(int32_t enable);
+int pds_timing_read(float* ms, int32_t max_n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDS_H */

@@ -40,6 +40,9 @@
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include "dual.hpp"
 #include "spatial.hpp"
@@ -392,6 +395,15 @@ extern "C" {
 
 int orc_version(void) { return 1; }
 
+// Threads the OpenMP loops use.
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 // Joint torques at time `time` (for tests of the controllers).
 void orc_tau(const OrcModel* md, const double* th, double time, const double* q, const double* qd, double* tau) {
   joint_torque<double>(*md, th, time, q, qd, tau);
@@ -546,7 +558,8 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
 }
 
 // Median-heuristic bandwidth (Sec. III-A): distances between the N(N-1)/2
-// distinct pairs, each coordinate divided by rho_m, sorted in full; the
+// distinct pairs, each coordinate difference scaled by 1/rho_m, sorted in
+// full; the
 // median (mean of the two middle values for an even count) gives
 // h = med^2 / log N.  N = 1 or a vanishing median gives h = 1.
 // variant 1 uses log(N+1).
@@ -557,7 +570,7 @@ double orc_bandwidth(int N, int M, const double* theta, const double* rho, int v
     for (int j = i + 1; j < N; ++j) {
       double s = 0.0;
       for (int m = 0; m < M; ++m) {
-        const double z = (theta[(size_t)i * M + m] - theta[(size_t)j * M + m]) / rho[m];
+        const double z = (theta[(size_t)i * M + m] - theta[(size_t)j * M + m]) * (1.0 / rho[m]);
         s += z * z;
       }
       d2.push_back(s);

@@ -1,0 +1,130 @@
+// Per-particle reductions after the window kernels, all in FP64 and in a
+// fixed order (deterministic, independent of the batch a job runs in).
+//
+//   logp / wk   combination over trajectories (eq. traj_likelihood, in log
+//               space with the 1/K weight, or the product of App. A-B):
+//               l_k = sum_j l_kj; SUM: log p = logsumexp_k l_k - log K,
+//               w_k = softmax_k l_k; PROD: log p = sum_k l_k, w_k = 1.
+//   g_obs       seed_logp * sum_k w_k sum_j d l_kj / d theta.
+//   g_con       sum_{k,j} seed_gdef_kj d g_def_kj / d theta.
+//   S_dot       for shooting state S_kj (j >= 1): seed_logp w_k d l_kj / d S_kj
+//               - seed_gdef_kj d g_def_kj / d S_kj - seed_gdef_k(j-1) d g_def_k(j-1) / d S_kj,
+//               the last term the direct dependence of the previous window's
+//               defect on its target (Sec. III-E, Algorithm 1).
+#include <cmath>
+
+#include "common.h"
+
+namespace pds {
+namespace {
+
+__global__ void __launch_bounds__(256) assemble_logp_kernel(JobMap map, const pds_job* __restrict__ jobs) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int i = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
+  if (i >= J.N) return;
+  const int K = J.K, ns = J.n_s;
+  const double* lw = J.ll_win + (size_t)i * K * ns;
+  double mx = -INFINITY, lp = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double a = 0.0;
+    for (int j = 0; j < ns; ++j) a += lw[k * ns + j];
+    J.wk[(size_t)i * K + k] = a;  // temporarily hold l_k
+    mx = fmax(mx, a);
+    lp += a;
+  }
+  if (J.combine == PDS_COMBINE_PROD) {
+    for (int k = 0; k < K; ++k) J.wk[(size_t)i * K + k] = 1.0;
+  } else {
+    double z = 0.0;
+    for (int k = 0; k < K; ++k) z += exp(J.wk[(size_t)i * K + k] - mx);
+    for (int k = 0; k < K; ++k) J.wk[(size_t)i * K + k] = exp(J.wk[(size_t)i * K + k] - mx) / z;
+    lp = mx + log(z) - log((double)K);
+  }
+  J.logp[i] = lp;
+  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+}
+
+// One thread per (particle, parameter).
+__global__ void __launch_bounds__(256) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                            char* __restrict__ ws) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
+  if (t >= J.N * J.M) return;
+  const int i = t % J.N, m = t / J.N;
+  const WsLayout L = ws_layout(J);
+  const char* base = ws + map.ws_off[e];
+  const size_t U = (size_t)J.N * J.K * J.n_s;
+  const double* go = reinterpret_cast<const double*>(base + L.gth_obs) + (size_t)m * U;
+  const double* gc = reinterpret_cast<const double*>(base + L.gth_con) + (size_t)m * U;
+  double so = 0.0, sc = 0.0;
+  for (int k = 0; k < J.K; ++k) {
+    double a = 0.0;
+    for (int j = 0; j < J.n_s; ++j) {
+      const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
+      a += go[u];
+      sc += gc[u];
+    }
+    so += J.wk[(size_t)i * J.K + k] * a;
+  }
+  const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
+  J.g_obs[(size_t)i * J.M + m] = seed * so;
+  J.g_con[(size_t)i * J.M + m] = sc;
+}
+
+// One thread per shooting-state component (i, k, j >= 1, d).
+__global__ void __launch_bounds__(256) assemble_sdot_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                            char* __restrict__ ws) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int ds = 2 * J.n_dof;
+  const int nS = J.K * (J.n_s - 1) * ds;
+  const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
+  if (t >= J.N * nS) return;
+  const int i = t / nS;
+  const int r = t % nS;
+  const int d = r % ds;
+  const int kj = r / ds;
+  const int k = kj / (J.n_s - 1);
+  const int j = kj % (J.n_s - 1) + 1;  // window started by this shooting state
+  const WsLayout L = ws_layout(J);
+  const char* base = ws + map.ws_off[e];
+  const size_t U = (size_t)J.N * J.K * J.n_s;
+  const float* gso = reinterpret_cast<const float*>(base + L.gs_obs);
+  const float* gsc = reinterpret_cast<const float*>(base + L.gs_con);
+  const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
+  const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
+  double v = seed * J.wk[(size_t)i * J.K + k] * (double)gso[(size_t)d * U + u] - (double)gsc[(size_t)d * U + u];
+  // defect of window j-1, whose target is this shooting state
+  const size_t id = ((size_t)i * J.K + k) * (J.n_s - 1) + (j - 1);
+  const double g = J.gdef[id];
+  const double sg = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
+  const float s_next = J.S[id * ds + d];
+  const float s_end = J.end_states[(((size_t)i * J.K + k) * J.n_s + (j - 1)) * ds + d];
+  const double ud = J.u[d];
+  const double err = (double)(s_next - s_end) * ud;
+  v -= sg * 2.0 * err * ud / ((double)J.sigma_def * J.sigma_def);
+  J.S_dot[(size_t)i * nS + r] = (float)v;
+  if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], 2);
+}
+
+}  // namespace
+
+hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* /*ws*/, int grid, bool /*with_grad*/,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(assemble_logp_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_grad_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_sdot_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
+  return hipGetLastError();
+}
+
+}  // namespace pds

@@ -1,0 +1,391 @@
+// Host side of the C ABI declared in pds.h: argument validation, per-launch
+// job maps, workspace carving and the launch sequence of each call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace pds {
+int planar_seg_len(int h);
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+using pds::JobMap;
+using pds::WsLayout;
+
+// Timing ring of event pairs around window-kernel launches.
+constexpr int kRing = 4096;
+struct Timing {
+  bool on = false;
+  int n = 0;
+  std::vector<hipEvent_t> ev;
+};
+Timing g_timing;
+
+void timing_begin(hipStream_t s, int* slot) {
+  *slot = -1;
+  if (!g_timing.on || g_timing.n >= kRing) return;
+  *slot = g_timing.n++;
+  (void)hipEventRecord(g_timing.ev[2 * *slot], s);
+}
+void timing_end(hipStream_t s, int slot) {
+  if (slot >= 0) (void)hipEventRecord(g_timing.ev[2 * slot + 1], s);
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Which pointers a call reads or writes (bit set).
+enum : unsigned {
+  NEED_FWD = 1u,       // theta, S, s0, consts, end_states
+  NEED_LL = 2u,        // obs, w_x, u, ll_win, gdef, logp, wk
+  NEED_ADJ = 4u,       // lam_def, g_obs, g_con, S_dot
+  NEED_PHI = 8u,       // rho, g_obs, phi, bandwidth
+  NEED_STEP = 16u,     // lo, hi, lr_*, lam_lim, lam_def, adam, phi, g_con, S_dot, gdef
+};
+
+int validate_job(const pds_job& J, int idx, unsigned need) {
+#define REQ(ptr, al)                                                                          \
+  do {                                                                                        \
+    if (!(J.ptr)) return fail(PDS_EINVAL, "job %d: " #ptr " is NULL", idx);                   \
+    if (!aligned(J.ptr, al)) return fail(PDS_EINVAL, "job %d: " #ptr " is misaligned", idx);  \
+  } while (0)
+  if (J.model == PDS_MODEL_ARM) return fail(PDS_EUNSUPPORTED, "job %d: the arm model is not built in this library", idx);
+  if (J.model != PDS_MODEL_PLANAR) return fail(PDS_EINVAL, "job %d: unknown model %d", idx, J.model);
+  if (J.n_dof < 1 || J.n_dof > 5) return fail(PDS_EUNSUPPORTED, "job %d: planar n_dof %d outside 1..5", idx, J.n_dof);
+  if (J.M != 2 * J.n_dof) return fail(PDS_EINVAL, "job %d: planar model needs M = 2 n_dof (got M=%d)", idx, J.M);
+  if (J.d_x != J.n_dof) return fail(PDS_EINVAL, "job %d: planar model observes q, d_x must be n_dof", idx);
+  if (J.N < 1 || J.K < 1 || J.n_s < 1 || J.h < 1 || J.T != J.n_s * J.h)
+    return fail(PDS_EINVAL, "job %d: need N, K, n_s, h >= 1 and T = n_s h (N=%d K=%d T=%d n_s=%d h=%d)", idx, J.N,
+                J.K, J.T, J.n_s, J.h);
+  const double units = (double)J.N * J.K * J.n_s;
+  if (units > 2.0e9 || (double)J.N * J.K * (J.n_s) * (2 * J.n_dof) > 2.0e9 || (double)J.N * J.N > 4.0e12)
+    return fail(PDS_EUNSUPPORTED, "job %d: problem too large for 32-bit indexing", idx);
+  if (!(J.dt > 0.f) || !std::isfinite(J.dt)) return fail(PDS_EINVAL, "job %d: dt must be > 0", idx);
+  if (!(J.sigma_def > 0.f)) return fail(PDS_EINVAL, "job %d: sigma_def must be > 0", idx);
+  if (!(J.c >= 0.f)) return fail(PDS_EINVAL, "job %d: c must be >= 0", idx);
+  if (J.combine != PDS_COMBINE_SUM && J.combine != PDS_COMBINE_PROD)
+    return fail(PDS_EINVAL, "job %d: unknown combine %d", idx, J.combine);
+  if (need & (NEED_FWD | NEED_LL | NEED_ADJ)) {
+    REQ(consts, 4); REQ(theta, 4); REQ(s0, 4); REQ(end_states, 4);
+    if (J.n_s > 1) REQ(S, 4);
+    if (J.traj && !aligned(J.traj, 4)) return fail(PDS_EINVAL, "job %d: traj is misaligned", idx);
+  }
+  if (need & (NEED_LL | NEED_ADJ)) {
+    REQ(obs, 4); REQ(w_x, 4); REQ(u, 4); REQ(ll_win, 8); REQ(logp, 8); REQ(wk, 8);
+    if (J.n_s > 1) REQ(gdef, 8);
+  }
+  if (need & NEED_ADJ) {
+    REQ(g_obs, 8); REQ(g_con, 8);
+    if (J.n_s > 1) { REQ(S_dot, 4); if (!J.seed_gdef) REQ(lam_def, 4); }
+  }
+  if (need & NEED_PHI) { REQ(rho, 4); REQ(g_obs, 8); REQ(phi, 4); REQ(bandwidth, 8); REQ(theta, 4); }
+  if (need & NEED_STEP) {
+    REQ(theta, 4); REQ(lo, 4); REQ(hi, 4); REQ(lr_theta, 4); REQ(lam_lim, 4); REQ(phi, 4); REQ(g_con, 8);
+    REQ(adam_m, 4); REQ(adam_v, 4);
+    if (J.n_s > 1) { REQ(S, 4); REQ(S_dot, 4); REQ(lam_def, 4); REQ(gdef, 8); REQ(lr_S, 4); }
+  }
+#undef REQ
+  return PDS_OK;
+}
+
+int validate_batch(const pds_job* h_jobs, const pds_job* d_jobs, int n_jobs, unsigned need) {
+  g_err.clear();
+  if (!h_jobs || !d_jobs) return fail(PDS_EINVAL, "h_jobs and d_jobs must be non-NULL");
+  if (n_jobs < 1 || n_jobs > PDS_MAX_JOBS) return fail(PDS_EINVAL, "n_jobs %d outside 1..%d", n_jobs, PDS_MAX_JOBS);
+  if (!aligned(d_jobs, 8)) return fail(PDS_EINVAL, "d_jobs is misaligned");
+  for (int j = 0; j < n_jobs; ++j) {
+    const int rc = validate_job(h_jobs[j], j, need);
+    if (rc) return rc;
+  }
+  return PDS_OK;
+}
+
+size_t job_ws(const pds_job& J, int which) {
+  const WsLayout L = pds::ws_layout(J);
+  switch (which) {
+    case PDS_CALL_FORWARD:
+    case PDS_CALL_LOGLIK:
+    case PDS_CALL_STEP: return 0;
+    default: return L.total;
+  }
+}
+
+// Workspace offsets of every job for a call (0-sized calls give all zeros).
+std::vector<uint64_t> ws_offsets(const pds_job* h_jobs, int n, int which, size_t* total) {
+  std::vector<uint64_t> off(n);
+  size_t o = 0;
+  for (int j = 0; j < n; ++j) {
+    off[j] = o;
+    o = pds::align256(o + job_ws(h_jobs[j], which));
+  }
+  *total = o;
+  return off;
+}
+
+int check_ws(void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return PDS_OK;
+  if (!ws) return fail(PDS_EWORKSPACE, "workspace of %zu bytes required, got NULL", need);
+  if (!aligned(ws, 256)) return fail(PDS_EWORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need) return fail(PDS_EWORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  return PDS_OK;
+}
+
+// Builds a map over the jobs selected by `pick`, with `blocks(job)` blocks each.
+template <class Pick, class Blocks>
+JobMap make_map(const pds_job* h_jobs, int n, const std::vector<uint64_t>& off, Pick pick, Blocks blocks,
+                int* grid) {
+  JobMap m;
+  std::memset(&m, 0, sizeof m);
+  int b = 0;
+  for (int j = 0; j < n; ++j) {
+    if (!pick(h_jobs[j])) continue;
+    const int nb = blocks(h_jobs[j]);
+    if (nb <= 0) continue;
+    m.job[m.n] = j;
+    m.begin[m.n] = b;
+    m.ws_off[m.n] = off[j];
+    ++m.n;
+    b += nb;
+  }
+  m.begin[m.n] = b;
+  *grid = b;
+  return m;
+}
+
+int launch_rc(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(PDS_ELAUNCH, "%s: %s", what, hipGetErrorString(e));
+  return PDS_OK;
+}
+
+int div_up(long a, long b) { return (int)((a + b - 1) / b); }
+
+int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with_ll, hipStream_t s) {
+  std::vector<uint64_t> off(n, 0);
+  int slot = -1;
+  if (with_ll) timing_begin(s, &slot);
+  for (int nb = 1; nb <= 5; ++nb) {
+    int grid = 0;
+    JobMap m = make_map(
+        h_jobs, n, off, [&](const pds_job& J) { return J.n_dof == nb; },
+        [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
+    if (m.n == 0) continue;
+    int rc = launch_rc(pds::launch_planar_forward(m, nb, d_jobs, grid, with_ll, s), "planar_forward");
+    if (rc) return rc;
+  }
+  timing_end(s, slot);
+  return PDS_OK;
+}
+
+int assemble_logp(const pds_job* h_jobs, const pds_job* d_jobs, int n, hipStream_t s) {
+  std::vector<uint64_t> off(n, 0);
+  int grid = 0;
+  JobMap m = make_map(
+      h_jobs, n, off, [](const pds_job&) { return true; }, [](const pds_job& J) { return div_up(J.N, 256); },
+      &grid);
+  return launch_rc(pds::launch_assemble(m, d_jobs, nullptr, grid, false, s), "assemble_logp");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pds_version(void) { return 100; }
+
+int pds_timing_enable(int32_t enable) {
+  g_err.clear();
+  if (g_timing.ev.empty() && enable) {
+    g_timing.ev.resize(2 * kRing);
+    for (auto& e : g_timing.ev) {
+      if (hipEventCreate(&e) != hipSuccess) {
+        g_timing.ev.clear();
+        return fail(PDS_ELAUNCH, "hipEventCreate failed");
+      }
+    }
+  }
+  g_timing.on = enable != 0;
+  g_timing.n = 0;
+  return PDS_OK;
+}
+
+int pds_timing_read(float* ms, int32_t max_n) {
+  if (!ms || max_n < 0) return fail(PDS_EINVAL, "pds_timing_read: bad arguments");
+  const int n = g_timing.n < max_n ? g_timing.n : max_n;
+  for (int i = 0; i < n; ++i) {
+    if (hipEventSynchronize(g_timing.ev[2 * i + 1]) != hipSuccess) return fail(PDS_ELAUNCH, "event sync failed");
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_timing.ev[2 * i], g_timing.ev[2 * i + 1]) != hipSuccess)
+      return fail(PDS_ELAUNCH, "hipEventElapsedTime failed");
+    ms[i] = t;
+  }
+  return n;
+}
+
+const char* pds_last_error(void) { return g_err.c_str(); }
+
+size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which) {
+  g_err.clear();
+  if (!h_jobs || n_jobs < 1 || n_jobs > PDS_MAX_JOBS) {
+    fail(PDS_EINVAL, "pds_workspace_size: bad job array");
+    return 0;
+  }
+  if (which < 0 || which > PDS_CALL_ALL) {
+    fail(PDS_EINVAL, "pds_workspace_size: bad call selector %d", which);
+    return 0;
+  }
+  size_t best = 0;
+  for (int w = 0; w < PDS_CALL_ALL; ++w) {
+    if (which != PDS_CALL_ALL && w != which) continue;
+    size_t t = 0;
+    ws_offsets(h_jobs, n_jobs, w, &t);
+    if (t > best) best = t;
+  }
+  return best;
+}
+
+int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* /*ws*/,
+                      size_t /*ws_bytes*/, void* stream) {
+  int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_FWD);
+  if (rc) return rc;
+  return rollout_calls(h_jobs, d_jobs, n_jobs, false, (hipStream_t)stream);
+}
+
+int loglik_multishoot(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* /*ws*/,
+                      size_t /*ws_bytes*/, void* stream) {
+  int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_FWD | NEED_LL);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  rc = rollout_calls(h_jobs, d_jobs, n_jobs, true, s);
+  if (rc) return rc;
+  return assemble_logp(h_jobs, d_jobs, n_jobs, s);
+}
+
+int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                      void* stream) {
+  int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_FWD | NEED_LL | NEED_ADJ);
+  if (rc) return rc;
+  size_t need = 0;
+  std::vector<uint64_t> off = ws_offsets(h_jobs, n_jobs, PDS_CALL_ADJOINT, &need);
+  rc = check_ws(ws, ws_bytes, need);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = static_cast<char*>(ws);
+  int slot = -1;
+  timing_begin(s, &slot);
+  for (int nb = 1; nb <= 5; ++nb) {
+    int grid = 0;
+    size_t lds = 0;
+    JobMap m = make_map(
+        h_jobs, n_jobs, off, [&](const pds_job& J) { return J.n_dof == nb; },
+        [&](const pds_job& J) {
+          const int B = pds::planar_seg_len(J.h);
+          const int nseg = div_up(J.h, B);
+          const size_t b = (size_t)(nseg + B + 1) * (2 * nb) * pds::kWave * sizeof(float);
+          if (b > lds) lds = b;
+          return div_up((long)J.N * J.K * J.n_s, pds::kWave);
+        },
+        &grid);
+    if (m.n == 0) continue;
+    if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "window of h steps needs %zu bytes of LDS", lds);
+    rc = launch_rc(pds::launch_planar_adjoint(m, nb, d_jobs, w, grid, 0, 0, lds, s), "planar_adjoint");
+    if (rc) return rc;
+  }
+  timing_end(s, slot);
+  rc = assemble_logp(h_jobs, d_jobs, n_jobs, s);
+  if (rc) return rc;
+  int grid = 0;
+  JobMap mg = make_map(
+      h_jobs, n_jobs, off, [](const pds_job&) { return true; },
+      [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &grid);
+  rc = launch_rc(pds::launch_assemble_grad(mg, d_jobs, w, grid, s), "assemble_grad");
+  if (rc) return rc;
+  JobMap ms = make_map(
+      h_jobs, n_jobs, off, [](const pds_job& J) { return J.n_s > 1; },
+      [](const pds_job& J) { return div_up((long)J.N * J.K * (J.n_s - 1) * 2 * J.n_dof, 256); }, &grid);
+  if (ms.n > 0) {
+    rc = launch_rc(pds::launch_assemble_sdot(ms, d_jobs, w, grid, s), "assemble_sdot");
+    if (rc) return rc;
+  }
+  return PDS_OK;
+}
+
+int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+             void* stream) {
+  int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_PHI);
+  if (rc) return rc;
+  size_t need = 0;
+  std::vector<uint64_t> off = ws_offsets(h_jobs, n_jobs, PDS_CALL_PHI, &need);
+  rc = check_ws(ws, ws_bytes, need);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = static_cast<char*>(ws);
+  auto all = [](const pds_job&) { return true; };
+  int grid = 0;
+  JobMap m1 = make_map(h_jobs, n_jobs, off, all, [](const pds_job&) { return 1; }, &grid);
+  rc = launch_rc(pds::launch_hist_clear(m1, d_jobs, w, grid, s), "hist_clear");
+  if (rc) return rc;
+  int pgrid = 0;
+  JobMap mp = make_map(
+      h_jobs, n_jobs, off, all,
+      [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
+  for (int p = 0; p < pds::kRadixPasses; ++p) {
+    rc = launch_rc(pds::launch_radix_pass(mp, d_jobs, w, pgrid, p, s), "radix_pass");
+    if (rc) return rc;
+  }
+  rc = launch_rc(pds::launch_radix_pass(m1, d_jobs, w, grid, pds::kRadixPasses, s), "bandwidth");
+  if (rc) return rc;
+  rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, s), "phi_partial");
+  if (rc) return rc;
+  int rgrid = 0;
+  JobMap mr = make_map(h_jobs, n_jobs, off, all, [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &rgrid);
+  return launch_rc(pds::launch_phi_reduce(mr, d_jobs, w, rgrid, s), "phi_reduce");
+}
+
+int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int32_t optimizer, int32_t iter,
+              void* stream) {
+  int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_STEP);
+  if (rc) return rc;
+  if (optimizer != PDS_OPT_SGD && optimizer != PDS_OPT_ADAM) return fail(PDS_EINVAL, "unknown optimizer %d", optimizer);
+  for (int j = 0; j < n_jobs; ++j)
+    if (optimizer == PDS_OPT_ADAM && iter < 1 && !h_jobs[j].iter_dev)
+      return fail(PDS_EINVAL, "Adam needs iter >= 1 or a device iteration counter");
+  std::vector<uint64_t> off(n_jobs, 0);
+  int grid = 0;
+  JobMap m = make_map(
+      h_jobs, n_jobs, off, [](const pds_job&) { return true; },
+      [](const pds_job& J) {
+        const long ds = 2 * J.n_dof;
+        const long n = (long)J.N * J.M + (long)J.N * J.K * (J.n_s - 1) * ds + (long)J.N * J.K * (J.n_s - 1);
+        return div_up(n, 256);
+      },
+      &grid);
+  rc = launch_rc(pds::launch_step(m, d_jobs, grid, optimizer, iter, (hipStream_t)stream), "step");
+  if (rc) return rc;
+  int bgrid = 0;
+  JobMap mb = make_map(
+      h_jobs, n_jobs, off, [](const pds_job& J) { return J.iter_dev != nullptr; }, [](const pds_job&) { return 1; },
+      &bgrid);
+  if (mb.n == 0) return PDS_OK;
+  return launch_rc(pds::launch_iter_bump(mb, d_jobs, bgrid, (hipStream_t)stream), "iter_bump");
+}
+
+}  // extern "C"

@@ -1,0 +1,723 @@
+// Window rollouts and their reverse-mode adjoint for planar chains
+// (revolute joints about z, point masses on massless links).
+//
+// Forward dynamics is the Articulated Body Algorithm (App. B-A) written in
+// planar spatial vectors: a motion vector is (w, vx, vy), a force vector
+// (n, fx, fy), and an articulated inertia is a symmetric 3x3 stored as its
+// six unique entries [00, 01, 02, 11, 12, 22].  Each step is the
+// semi-implicit Euler update of App. B-A eq. dynamics.  Body i's frame sits
+// on joint i and turns with q_i; its parent-to-body transform rotates by q_i
+// after translating by L_i = l_{i-1} along the parent's -y axis (L_0 = 0).
+//
+// One lane owns one window unit (particle i, trajectory k, window j): the
+// whole window runs in registers, and only window start states are read
+// from memory.  The adjoint kernel keeps the state at the start of every
+// segment of B steps (checkpoints) and the states of the segment being
+// reversed in LDS, laid out [slot][component][lane] so lanes hit distinct
+// banks; each reverse step recomputes its ABA intermediates from the stored
+// state (recompute inside the window, nothing but start states in HBM).
+//
+// The reverse of one ABA evaluation is written by hand statement by
+// statement (reverse order of passes 3, 2, 1).  Two adjoint channels share
+// the primal recompute: the observation channel, seeded at every step with
+// d l / d x = r * w (unit trajectory weight), and the constraint channel,
+// seeded at the window end with seed_gdef * d g_def / d s_end.  Per-window
+// sums over steps are accumulated in FP64.
+#include <cmath>
+
+#include "common.h"
+
+namespace pds {
+namespace {
+
+__host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincosf(x, sn, cs); }
+
+template <int NB, class R = float>
+struct Planar {
+  R m[NB], l[NB], b[NB];
+  R gx, gy;
+};
+
+// Intermediates of one ABA evaluation needed by its reverse.
+template <int NB, class R = float>
+struct Tape {
+  R cs[NB], sn[NB];
+  R v[NB][3];
+  R IA[NB][6];  // final articulated inertia
+  R pA[NB][3];  // final bias force
+  R invD[NB], u[NB];
+  R ap[NB][3];  // X a_parent + c
+  R qdd[NB];
+};
+
+// Articulated Body Algorithm, planar form.  Fills the tape; qdd in T.qdd.
+template <int NB, class R = float>
+__host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q, const R* qd, Tape<NB, R>& T) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    sincos_r(q[i], &T.sn[i], &T.cs[i]);
+    R v0, v1, v2;
+    if (i == 0) {
+      v0 = qd[0]; v1 = 0.f; v2 = 0.f;
+    } else {
+      const R L = P.l[i - 1];
+      const R w = T.v[i - 1][0];
+      const R tx = T.v[i - 1][1] + w * L, ty = T.v[i - 1][2];
+      v0 = w + qd[i];
+      v1 = T.cs[i] * tx + T.sn[i] * ty;
+      v2 = -T.sn[i] * tx + T.cs[i] * ty;
+    }
+    T.v[i][0] = v0; T.v[i][1] = v1; T.v[i][2] = v2;
+    const R m = P.m[i], l = P.l[i];
+    const R h1 = m * (l * v0 + v1), h2 = m * v2;
+    T.pA[i][0] = v1 * h2 - v2 * h1;
+    T.pA[i][1] = -v0 * h2;
+    T.pA[i][2] = v0 * h1;
+    T.IA[i][0] = m * l * l; T.IA[i][1] = m * l; T.IA[i][2] = 0.f;
+    T.IA[i][3] = m;         T.IA[i][4] = 0.f;   T.IA[i][5] = m;
+  }
+#pragma unroll
+  for (int i = NB - 1; i >= 0; --i) {
+    const R invD = 1.0f / T.IA[i][0];
+    const R U1 = T.IA[i][1], U2 = T.IA[i][2];
+    const R u = -P.b[i] * qd[i] - T.pA[i][0];
+    T.invD[i] = invD;
+    T.u[i] = u;
+    if (i > 0) {
+      const R c1 = T.v[i][2] * qd[i], c2 = -T.v[i][1] * qd[i];
+      const R a = T.IA[i][3] - U1 * U1 * invD;
+      const R bb = T.IA[i][4] - U1 * U2 * invD;
+      const R d = T.IA[i][5] - U2 * U2 * invD;
+      const R k = u * invD;
+      const R pa0 = T.pA[i][0] + u;
+      const R pa1 = T.pA[i][1] + a * c1 + bb * c2 + U1 * k;
+      const R pa2 = T.pA[i][2] + bb * c1 + d * c2 + U2 * k;
+      const R cs = T.cs[i], sn = T.sn[i], L = P.l[i - 1];
+      const R A00 = a * cs * cs - 2.f * bb * cs * sn + d * sn * sn;
+      const R A01 = (a - d) * cs * sn + bb * (cs * cs - sn * sn);
+      const R A11 = a * sn * sn + 2.f * bb * cs * sn + d * cs * cs;
+      T.IA[i - 1][0] += L * L * A00;
+      T.IA[i - 1][1] += L * A00;
+      T.IA[i - 1][2] += L * A01;
+      T.IA[i - 1][3] += A00;
+      T.IA[i - 1][4] += A01;
+      T.IA[i - 1][5] += A11;
+      const R f1 = cs * pa1 - sn * pa2, f2 = sn * pa1 + cs * pa2;
+      T.pA[i - 1][0] += pa0 + L * f1;
+      T.pA[i - 1][1] += f1;
+      T.pA[i - 1][2] += f2;
+    }
+  }
+  R a0 = 0.f, a1 = -P.gx, a2 = -P.gy;  // base acceleration = -gravity
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const R L = (i == 0) ? 0.f : P.l[i - 1];
+    const R tx = a1 + a0 * L, ty = a2;
+    const R c1 = T.v[i][2] * qd[i], c2 = -T.v[i][1] * qd[i];
+    const R ap0 = a0;
+    const R ap1 = T.cs[i] * tx + T.sn[i] * ty + c1;
+    const R ap2 = -T.sn[i] * tx + T.cs[i] * ty + c2;
+    T.ap[i][0] = ap0; T.ap[i][1] = ap1; T.ap[i][2] = ap2;
+    const R qdd = (T.u[i] - (T.IA[i][0] * ap0 + T.IA[i][1] * ap1 + T.IA[i][2] * ap2)) * T.invD[i];
+    T.qdd[i] = qdd;
+    a0 = ap0 + qdd; a1 = ap1; a2 = ap2;
+  }
+}
+
+// Reverse of aba(): given qddb = d L / d qdd, accumulates d L / d q, d L / d qd
+// and d L / d (m, l).
+template <int NB, class R = float>
+__host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R* qd, const Tape<NB, R>& T,
+                                        const R* qddb_in, R* qb, R* qdb, R* mb, R* lb) {
+  R csb[NB], snb[NB], Lb[NB], taub[NB];
+  R IAb[NB][6], pAb[NB][3], vb[NB][3], cb1[NB], cb2[NB];
+  R ub[NB], Db[NB], U1b[NB], U2b[NB], invDb[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    csb[i] = snb[i] = Lb[i] = taub[i] = 0.f;
+    cb1[i] = cb2[i] = 0.f;
+    ub[i] = Db[i] = U1b[i] = U2b[i] = invDb[i] = 0.f;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) IAb[i][e] = 0.f;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) { pAb[i][e] = 0.f; vb[i][e] = 0.f; }
+  }
+  // ---- pass 3 (outward accelerations), reversed ----
+  R ab0 = 0.f, ab1 = 0.f, ab2 = 0.f;
+#pragma unroll
+  for (int i = NB - 1; i >= 0; --i) {
+    R qddb = qddb_in[i] + ab0;  // a_i = a'_i + S qdd_i
+    R apb0 = ab0, apb1 = ab1, apb2 = ab2;
+    const R D = T.IA[i][0], U1 = T.IA[i][1], U2 = T.IA[i][2], invD = T.invD[i];
+    const R ap0 = T.ap[i][0], ap1 = T.ap[i][1], ap2 = T.ap[i][2];
+    const R g = qddb * invD;
+    ub[i] += g;
+    Db[i] -= g * ap0;
+    U1b[i] -= g * ap1;
+    U2b[i] -= g * ap2;
+    apb0 -= g * D;
+    apb1 -= g * U1;
+    apb2 -= g * U2;
+    invDb[i] += qddb * (T.u[i] - (D * ap0 + U1 * ap1 + U2 * ap2));
+    cb1[i] += apb1;
+    cb2[i] += apb2;
+    R x0, x1, x2, L;
+    if (i == 0) {
+      x0 = 0.f; x1 = -P.gx; x2 = -P.gy; L = 0.f;
+    } else {
+      x0 = T.ap[i - 1][0] + T.qdd[i - 1]; x1 = T.ap[i - 1][1]; x2 = T.ap[i - 1][2]; L = P.l[i - 1];
+    }
+    const R cs = T.cs[i], sn = T.sn[i];
+    const R tx = x1 + x0 * L, ty = x2;
+    const R txb = cs * apb1 - sn * apb2, tyb = sn * apb1 + cs * apb2;
+    csb[i] += apb1 * tx + apb2 * ty;
+    snb[i] += apb1 * ty - apb2 * tx;
+    if (i > 0) Lb[i] += x0 * txb;
+    ab0 = apb0 + L * txb;
+    ab1 = txb;
+    ab2 = tyb;
+  }
+  // ---- pass 2 (inward articulated inertias), reversed ----
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const R U1 = T.IA[i][1], U2 = T.IA[i][2], invD = T.invD[i], u = T.u[i];
+    if (i > 0) {
+      const int p = i - 1;
+      const R c1 = T.v[i][2] * qd[i], c2 = -T.v[i][1] * qd[i];
+      const R a = T.IA[i][3] - U1 * U1 * invD;
+      const R bb = T.IA[i][4] - U1 * U2 * invD;
+      const R d = T.IA[i][5] - U2 * U2 * invD;
+      const R k = u * invD;
+      const R pa1 = T.pA[i][1] + a * c1 + bb * c2 + U1 * k;
+      const R pa2 = T.pA[i][2] + bb * c1 + d * c2 + U2 * k;
+      const R cs = T.cs[i], sn = T.sn[i], L = P.l[p];
+      const R A00 = a * cs * cs - 2.f * bb * cs * sn + d * sn * sn;
+      const R A01 = (a - d) * cs * sn + bb * (cs * cs - sn * sn);
+      const R f1 = cs * pa1 - sn * pa2;
+      // parent updates
+      const R A00b = L * L * IAb[p][0] + L * IAb[p][1] + IAb[p][3];
+      const R A01b = L * IAb[p][2] + IAb[p][4];
+      const R A11b = IAb[p][5];
+      Lb[i] += 2.f * L * A00 * IAb[p][0] + A00 * IAb[p][1] + A01 * IAb[p][2];
+      const R f1b = L * pAb[p][0] + pAb[p][1], f2b = pAb[p][2];
+      Lb[i] += f1 * pAb[p][0];
+      const R pab0 = pAb[p][0];
+      const R pab1 = cs * f1b + sn * f2b;
+      const R pab2 = -sn * f1b + cs * f2b;
+      csb[i] += pa1 * f1b + pa2 * f2b;
+      snb[i] += -pa2 * f1b + pa1 * f2b;
+      // rotated inertia A' -> (a, bb, d, cs, sn)
+      const R cc = cs * cs, ss = sn * sn, cn = cs * sn;
+      R abar = cc * A00b + cn * A01b + ss * A11b;
+      R bbar = -2.f * cn * A00b + (cc - ss) * A01b + 2.f * cn * A11b;
+      R dbar = ss * A00b - cn * A01b + cc * A11b;
+      csb[i] += (2.f * a * cs - 2.f * bb * sn) * A00b + ((a - d) * sn + 2.f * bb * cs) * A01b +
+                (2.f * bb * sn + 2.f * d * cs) * A11b;
+      snb[i] += (-2.f * bb * cs + 2.f * d * sn) * A00b + ((a - d) * cs - 2.f * bb * sn) * A01b +
+                (2.f * a * sn + 2.f * bb * cs) * A11b;
+      // pa = pA + Ia c + U u / D
+      R kb = 0.f;
+      pAb[i][0] += pab0;
+      ub[i] += pab0;
+      pAb[i][1] += pab1;
+      abar += pab1 * c1;
+      bbar += pab1 * c2;
+      cb1[i] += a * pab1;
+      cb2[i] += bb * pab1;
+      U1b[i] += pab1 * k;
+      kb += U1 * pab1;
+      pAb[i][2] += pab2;
+      bbar += pab2 * c1;
+      dbar += pab2 * c2;
+      cb1[i] += bb * pab2;
+      cb2[i] += d * pab2;
+      U2b[i] += pab2 * k;
+      kb += U2 * pab2;
+      ub[i] += kb * invD;
+      invDb[i] += kb * u;
+      // Ia = IA - U U^T / D (rows/columns 0 vanish identically)
+      IAb[i][3] += abar;
+      U1b[i] -= 2.f * U1 * invD * abar;
+      invDb[i] -= U1 * U1 * abar;
+      IAb[i][4] += bbar;
+      U1b[i] -= U2 * invD * bbar;
+      U2b[i] -= U1 * invD * bbar;
+      invDb[i] -= U1 * U2 * bbar;
+      IAb[i][5] += dbar;
+      U2b[i] -= 2.f * U2 * invD * dbar;
+      invDb[i] -= U2 * U2 * dbar;
+    }
+    // u = tau - pA0
+    taub[i] += ub[i];
+    pAb[i][0] -= ub[i];
+    // invD = 1 / D, D = IA00, U = (IA00, IA01, IA02)
+    Db[i] -= invD * invD * invDb[i];
+    IAb[i][0] += Db[i];
+    IAb[i][1] += U1b[i];
+    IAb[i][2] += U2b[i];
+    // rigid inertia of a point mass at (0, -l): m [l^2, l, 0, 1, 0, 1]
+    const R m = P.m[i], l = P.l[i];
+    mb[i] += l * l * IAb[i][0] + l * IAb[i][1] + IAb[i][3] + IAb[i][5];
+    lb[i] += 2.f * m * l * IAb[i][0] + m * IAb[i][1];
+  }
+  // ---- pass 1 (outward velocities and bias forces), reversed ----
+#pragma unroll
+  for (int i = NB - 1; i >= 0; --i) {
+    const R v0 = T.v[i][0], v1 = T.v[i][1], v2 = T.v[i][2];
+    const R m = P.m[i], l = P.l[i];
+    const R h1 = m * (l * v0 + v1), h2 = m * v2;
+    R vb0 = vb[i][0], vb1 = vb[i][1], vb2 = vb[i][2];
+    const R pb0 = pAb[i][0], pb1 = pAb[i][1], pb2 = pAb[i][2];
+    vb1 += pb0 * h2;
+    R h2b = pb0 * v1;
+    vb2 -= pb0 * h1;
+    R h1b = -pb0 * v2;
+    vb0 -= pb1 * h2;
+    h2b -= pb1 * v0;
+    vb0 += pb2 * h1;
+    h1b += pb2 * v0;
+    vb0 += m * l * h1b;
+    vb1 += m * h1b;
+    mb[i] += (l * v0 + v1) * h1b + v2 * h2b;
+    lb[i] += m * v0 * h1b;
+    vb2 += m * h2b;
+    // c = (0, v2 qd, -v1 qd)
+    vb2 += cb1[i] * qd[i];
+    qdb[i] += cb1[i] * v2;
+    vb1 -= cb2[i] * qd[i];
+    qdb[i] -= cb2[i] * v1;
+    // v_i = X_i v_{i-1} + (qd_i, 0, 0)
+    qdb[i] += vb0;
+    if (i > 0) {
+      const R x0 = T.v[i - 1][0], x1 = T.v[i - 1][1], x2 = T.v[i - 1][2];
+      const R L = P.l[i - 1], cs = T.cs[i], sn = T.sn[i];
+      const R tx = x1 + x0 * L, ty = x2;
+      const R txb = cs * vb1 - sn * vb2, tyb = sn * vb1 + cs * vb2;
+      csb[i] += vb1 * tx + vb2 * ty;
+      snb[i] += vb1 * ty - vb2 * tx;
+      vb[i - 1][0] += vb0 + L * txb;
+      vb[i - 1][1] += txb;
+      vb[i - 1][2] += tyb;
+      Lb[i] += x0 * txb;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    qb[i] += -T.sn[i] * csb[i] + T.cs[i] * snb[i];
+    qdb[i] += -P.b[i] * taub[i];
+    if (i > 0) lb[i - 1] += Lb[i];
+  }
+}
+
+// Semi-implicit Euler: qd' = qd + dt qdd, q' = q + dt qd'.
+template <int NB, class R = float>
+__host__ __device__ __forceinline__ void step(const Planar<NB, R>& P, R dt, R* q, R* qd) {
+  Tape<NB, R> T;
+  aba<NB, R>(P, q, qd, T);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    qd[i] = qd[i] + dt * T.qdd[i];
+    q[i] = q[i] + dt * qd[i];
+  }
+}
+
+// Reverse of one Euler step given the tape at its input state.  On entry
+// (qb, qdb) are the adjoints of the step's outputs; on exit of its inputs.
+template <int NB, class R = float>
+__host__ __device__ __forceinline__ void step_rev(const Planar<NB, R>& P, R dt, const R* qd, const Tape<NB, R>& T,
+                                         R* qb, R* qdb, R* mb, R* lb) {
+  R qddb[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    qdb[i] = qdb[i] + dt * qb[i];
+    qddb[i] = dt * qdb[i];
+  }
+  aba_rev<NB, R>(P, qd, T, qddb, qb, qdb, mb, lb);
+}
+
+template <int NB>
+__device__ __forceinline__ void load_model(const pds_job& J, const float* th, Planar<NB>& P) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    P.m[i] = th[i];
+    P.l[i] = th[NB + i];
+    P.b[i] = J.consts[2 + i];
+  }
+  P.gx = J.consts[0];
+  P.gy = J.consts[1];
+}
+
+struct Unit {
+  int i, k, j;
+};
+
+__device__ inline Unit unit_of(const pds_job& J, int u) {
+  Unit r;
+  r.i = u % J.N;
+  const int kj = u / J.N;
+  r.k = kj / J.n_s;
+  r.j = kj % J.n_s;
+  return r;
+}
+
+__device__ inline const float* start_ptr(const pds_job& J, const Unit& w, int ds) {
+  if (w.j == 0) return J.s0 + (size_t)w.k * ds;
+  return J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + (w.j - 1)) * ds;
+}
+
+__device__ inline double log_norm_const(const pds_job& J) {
+  // sum_d log(w_d / sqrt(2 pi)) per observed step
+  double c = 0.0;
+  for (int d = 0; d < J.d_x; ++d) c += log((double)J.w_x[d]) - 0.91893853320467274178;
+  return c;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                               int with_ll) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int U = J.N * J.K * J.n_s;
+  const int u = (blockIdx.x - map.begin[e]) * kWave + threadIdx.x;
+  if (u >= U) return;
+  constexpr int DS = 2 * NB;
+  const Unit w = unit_of(J, u);
+  Planar<NB> P;
+  float th[2 * NB];
+#pragma unroll
+  for (int m = 0; m < 2 * NB; ++m) th[m] = J.theta[(size_t)w.i * J.M + m];
+  load_model<NB>(J, th, P);
+  const float* st = start_ptr(J, w, DS);
+  float q[NB], qd[NB];
+#pragma unroll
+  for (int d = 0; d < NB; ++d) { q[d] = st[d]; qd[d] = st[NB + d]; }
+  const float dt = J.dt;
+  const int t0 = w.j * J.h;
+  const float* obs = J.obs + ((size_t)w.k * J.T + t0) * J.d_x;
+  float* traj = J.traj ? J.traj + (((size_t)w.i * J.K + w.k) * J.T + t0) * DS : nullptr;
+  float wx[NB];
+#pragma unroll
+  for (int d = 0; d < NB; ++d) wx[d] = J.w_x[d];
+  double ll = 0.0;
+  for (int s = 0; s < J.h; ++s) {
+    step<NB>(P, dt, q, qd);
+    if (with_ll) {
+      float acc = 0.f;
+#pragma unroll
+      for (int d = 0; d < NB; ++d) {
+        const float r = (obs[s * NB + d] - q[d]) * wx[d];
+        acc += r * r;
+      }
+      ll -= 0.5 * (double)acc;
+    }
+    if (traj) {
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { traj[s * DS + d] = q[d]; traj[s * DS + NB + d] = qd[d]; }
+    }
+  }
+  const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
+  float* es = J.end_states + iu * DS;
+#pragma unroll
+  for (int d = 0; d < NB; ++d) { es[d] = q[d]; es[NB + d] = qd[d]; }
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < NB; ++d) bad |= !isfinite(q[d]) || !isfinite(qd[d]);
+  if (with_ll) {
+    ll += (double)J.h * log_norm_const(J);
+    J.ll_win[iu] = ll;
+    if (w.j + 1 < J.n_s) {
+      const float* sn = J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j) * DS;
+      double g = 0.0;
+#pragma unroll
+      for (int d = 0; d < NB; ++d) {
+        const float e0 = (sn[d] - q[d]) * J.u[d];
+        const float e1 = (sn[NB + d] - qd[d]) * J.u[NB + d];
+        g += (double)e0 * e0 + (double)e1 * e1;
+      }
+      J.gdef[((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j] = g / ((double)J.sigma_def * J.sigma_def);
+    }
+    bad |= !isfinite(ll);
+  }
+  if (bad && J.flags) atomicOr(&J.flags[w.i], 1);
+}
+
+// Segment length of the adjoint's checkpointing: about sqrt(h).
+__host__ __device__ inline int seg_len_of(int h) {
+  int B = 1;
+  while (B * B < h) ++B;
+  return B;
+}
+
+template <int NB>
+__global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                               char* __restrict__ ws) {
+  extern __shared__ float lds[];
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int U = J.N * J.K * J.n_s;
+  const int lane = threadIdx.x;
+  const int u = (blockIdx.x - map.begin[e]) * kWave + lane;
+  if (u >= U) return;
+  constexpr int DS = 2 * NB;
+  const WsLayout L = ws_layout(J);
+  char* base = ws + map.ws_off[e];
+  double* gth_obs = reinterpret_cast<double*>(base + L.gth_obs);
+  double* gth_con = reinterpret_cast<double*>(base + L.gth_con);
+  float* gs_obs = reinterpret_cast<float*>(base + L.gs_obs);
+  float* gs_con = reinterpret_cast<float*>(base + L.gs_con);
+
+  const Unit w = unit_of(J, u);
+  Planar<NB> P;
+  float th[2 * NB];
+#pragma unroll
+  for (int m = 0; m < 2 * NB; ++m) th[m] = J.theta[(size_t)w.i * J.M + m];
+  load_model<NB>(J, th, P);
+  const float* st = start_ptr(J, w, DS);
+  float q[NB], qd[NB];
+#pragma unroll
+  for (int d = 0; d < NB; ++d) { q[d] = st[d]; qd[d] = st[NB + d]; }
+  const float dt = J.dt;
+  const int h = J.h;
+  const int B = seg_len_of(h);
+  const int nseg = (h + B - 1) / B;
+  const int t0 = w.j * h;
+  const float* obs = J.obs + ((size_t)w.k * J.T + t0) * J.d_x;
+  float wx[NB];
+#pragma unroll
+  for (int d = 0; d < NB; ++d) wx[d] = J.w_x[d];
+  // LDS slots: [0, nseg) checkpoints, [nseg, nseg + B + 1) segment states
+  auto slot = [&](int s, int d) -> float& { return lds[((size_t)s * DS + d) * kWave + lane]; };
+
+  // ---- forward sweep: log-likelihood, end state, checkpoints ----
+  double ll = 0.0;
+  for (int s = 0; s < h; ++s) {
+    if (s % B == 0) {
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { slot(s / B, d) = q[d]; slot(s / B, NB + d) = qd[d]; }
+    }
+    step<NB>(P, dt, q, qd);
+    float acc = 0.f;
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+      const float r = (obs[s * NB + d] - q[d]) * wx[d];
+      acc += r * r;
+    }
+    ll -= 0.5 * (double)acc;
+  }
+  ll += (double)h * log_norm_const(J);
+  const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
+  float* es = J.end_states + iu * DS;
+#pragma unroll
+  for (int d = 0; d < NB; ++d) { es[d] = q[d]; es[NB + d] = qd[d]; }
+  J.ll_win[iu] = ll;
+  bool bad = !isfinite(ll);
+#pragma unroll
+  for (int d = 0; d < NB; ++d) bad |= !isfinite(q[d]) || !isfinite(qd[d]);
+
+  // ---- seeds ----
+  float qb_o[NB], qdb_o[NB], qb_c[NB], qdb_c[NB];
+#pragma unroll
+  for (int d = 0; d < NB; ++d) { qb_o[d] = qdb_o[d] = qb_c[d] = qdb_c[d] = 0.f; }
+  if (w.j + 1 < J.n_s) {
+    const size_t id = ((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j;
+    const float* sn = J.S + id * DS;
+    float e0[NB], e1[NB];
+    double g = 0.0;
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+      e0[d] = (sn[d] - q[d]) * J.u[d];
+      e1[d] = (sn[NB + d] - qd[d]) * J.u[NB + d];
+      g += (double)e0[d] * e0[d] + (double)e1[d] * e1[d];
+    }
+    const double inv_s2 = 1.0 / ((double)J.sigma_def * J.sigma_def);
+    g *= inv_s2;
+    J.gdef[id] = g;
+    const double seed = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
+    // d g / d s_end = -2 e u / sigma^2
+    const float sc = (float)(-2.0 * seed * inv_s2);
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+      qb_c[d] = sc * e0[d] * J.u[d];
+      qdb_c[d] = sc * e1[d] * J.u[NB + d];
+    }
+  }
+
+  // ---- reverse sweep over segments ----
+  double gm_o[2 * NB], gm_c[2 * NB];
+#pragma unroll
+  for (int m = 0; m < 2 * NB; ++m) { gm_o[m] = 0.0; gm_c[m] = 0.0; }
+  const int segbase = nseg;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int a = sg * B;
+    const int bnd = min(h, a + B);
+#pragma unroll
+    for (int d = 0; d < NB; ++d) { q[d] = slot(sg, d); qd[d] = slot(sg, NB + d); }
+#pragma unroll
+    for (int d = 0; d < NB; ++d) { slot(segbase, d) = q[d]; slot(segbase, NB + d) = qd[d]; }
+    for (int s = a; s < bnd; ++s) {
+      step<NB>(P, dt, q, qd);
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { slot(segbase + s - a + 1, d) = q[d]; slot(segbase + s - a + 1, NB + d) = qd[d]; }
+    }
+    for (int s = bnd - 1; s >= a; --s) {
+      // observation seed at the step's output state s+1
+#pragma unroll
+      for (int d = 0; d < NB; ++d) {
+        const float x = slot(segbase + s - a + 1, d);
+        const float r = (obs[s * NB + d] - x) * wx[d];
+        qb_o[d] += r * wx[d];
+      }
+      float qs[NB], qds[NB];
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { qs[d] = slot(segbase + s - a, d); qds[d] = slot(segbase + s - a, NB + d); }
+      Tape<NB> T;
+      aba<NB>(P, qs, qds, T);
+      float mb[NB], lb[NB];
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { mb[d] = 0.f; lb[d] = 0.f; }
+      step_rev<NB>(P, dt, qds, T, qb_o, qdb_o, mb, lb);
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { gm_o[d] += (double)mb[d]; gm_o[NB + d] += (double)lb[d]; }
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { mb[d] = 0.f; lb[d] = 0.f; }
+      step_rev<NB>(P, dt, qds, T, qb_c, qdb_c, mb, lb);
+#pragma unroll
+      for (int d = 0; d < NB; ++d) { gm_c[d] += (double)mb[d]; gm_c[NB + d] += (double)lb[d]; }
+    }
+  }
+  // ---- per-unit outputs ----
+#pragma unroll
+  for (int m = 0; m < 2 * NB; ++m) {
+    gth_obs[(size_t)m * U + u] = gm_o[m];
+    gth_con[(size_t)m * U + u] = gm_c[m];
+    bad |= !isfinite(gm_o[m]) || !isfinite(gm_c[m]);
+  }
+#pragma unroll
+  for (int d = 0; d < NB; ++d) {
+    gs_obs[(size_t)d * U + u] = qb_o[d];
+    gs_obs[(size_t)(NB + d) * U + u] = qdb_o[d];
+    gs_con[(size_t)d * U + u] = qb_c[d];
+    gs_con[(size_t)(NB + d) * U + u] = qdb_c[d];
+  }
+  if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
+}
+
+}  // namespace
+
+template <int NB>
+static hipError_t fwd_nb(const JobMap& map, const pds_job* d_jobs, int grid, bool with_ll, hipStream_t s) {
+  hipLaunchKernelGGL(planar_forward_kernel<NB>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, with_ll ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_planar_forward(const JobMap& map, int nb, const pds_job* d_jobs, int grid, bool with_ll,
+                                 hipStream_t s) {
+  switch (nb) {
+    case 1: return fwd_nb<1>(map, d_jobs, grid, with_ll, s);
+    case 2: return fwd_nb<2>(map, d_jobs, grid, with_ll, s);
+    case 3: return fwd_nb<3>(map, d_jobs, grid, with_ll, s);
+    case 4: return fwd_nb<4>(map, d_jobs, grid, with_ll, s);
+    case 5: return fwd_nb<5>(map, d_jobs, grid, with_ll, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NB>
+static hipError_t adj_nb(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(planar_adjoint_kernel<NB>, dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_planar_adjoint(const JobMap& map, int nb, const pds_job* d_jobs, char* ws, int grid,
+                                 int /*seg_len*/, int /*n_seg*/, size_t lds_bytes, hipStream_t s) {
+  switch (nb) {
+    case 1: return adj_nb<1>(map, d_jobs, ws, grid, lds_bytes, s);
+    case 2: return adj_nb<2>(map, d_jobs, ws, grid, lds_bytes, s);
+    case 3: return adj_nb<3>(map, d_jobs, ws, grid, lds_bytes, s);
+    case 4: return adj_nb<4>(map, d_jobs, ws, grid, lds_bytes, s);
+    case 5: return adj_nb<5>(map, d_jobs, ws, grid, lds_bytes, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int planar_seg_len(int h) { return seg_len_of(h); }
+
+// ---------------------------------------------------------------------------
+// Algorithmic FLOP count of one step and of one reverse step, obtained by
+// running the same templated step functions on the host with a counting
+// scalar (add, sub, mul, div each 1; negation 0; sin/cos tallied apart).
+// ---------------------------------------------------------------------------
+namespace {
+struct FlopTally {
+  double flops = 0, transc = 0;
+};
+FlopTally g_tally;
+
+struct Counted {
+  float v;
+  Counted() : v(0.f) {}
+  Counted(float x) : v(x) {}  // NOLINT: implicit from literals, like float
+};
+inline Counted operator+(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v + b.v); }
+inline Counted operator-(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v - b.v); }
+inline Counted operator*(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v * b.v); }
+inline Counted operator/(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v / b.v); }
+inline Counted operator-(Counted a) { return Counted(-a.v); }
+inline Counted operator+(float a, Counted b) { return Counted(a) + b; }
+inline Counted operator-(float a, Counted b) { return Counted(a) - b; }
+inline Counted operator*(float a, Counted b) { return Counted(a) * b; }
+inline Counted operator/(float a, Counted b) { return Counted(a) / b; }
+inline Counted operator+(Counted a, float b) { return a + Counted(b); }
+inline Counted operator-(Counted a, float b) { return a - Counted(b); }
+inline Counted operator*(Counted a, float b) { return a * Counted(b); }
+inline Counted& operator+=(Counted& a, Counted b) { a = a + b; return a; }
+inline Counted& operator-=(Counted& a, Counted b) { a = a - b; return a; }
+inline void sincos_r(Counted x, Counted* sn, Counted* cs) {
+  g_tally.transc += 2;
+  float s, c;
+  sincosf(x.v, &s, &c);
+  *sn = Counted(s);
+  *cs = Counted(c);
+}
+
+template <int NB>
+void count_planar(double* fwd, double* rev, double* transc) {
+  Planar<NB, Counted> P;
+  Counted q[NB], qd[NB], qb[NB], qdb[NB], mb[NB], lb[NB];
+  for (int i = 0; i < NB; ++i) {
+    P.m[i] = Counted(1.0f); P.l[i] = Counted(1.0f); P.b[i] = Counted(0.05f);
+    q[i] = Counted(0.3f); qd[i] = Counted(0.1f); qb[i] = Counted(1.f); qdb[i] = Counted(1.f);
+  }
+  P.gx = Counted(0.f); P.gy = Counted(-9.81f);
+  g_tally = FlopTally();
+  Tape<NB, Counted> T;
+  aba<NB, Counted>(P, q, qd, T);
+  for (int i = 0; i < NB; ++i) {  // Euler update
+    qd[i] = qd[i] + Counted(0.01f) * T.qdd[i];
+    q[i] = q[i] + Counted(0.01f) * qd[i];
+  }
+  // observation residual r = (x - q) w; acc += r r; one FP64 accumulate
+  *fwd = g_tally.flops + 4.0 * NB + 1.0;
+  *transc = g_tally.transc;
+  g_tally = FlopTally();
+  step_rev<NB, Counted>(P, Counted(0.01f), qd, T, qb, qdb, mb, lb);
+  // observation seed r w per component; FP64 accumulation of the M parameter adjoints
+  *rev = g_tally.flops + 4.0 * NB + 2.0 * NB;
+}
+}  // namespace
+
+extern "C" int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_step, double* rev_step,
+                                     double* transcendental) {
+  if (model != PDS_MODEL_PLANAR || !fwd_step || !rev_step || !transcendental) return PDS_EINVAL;
+  switch (n_dof) {
+    case 1: count_planar<1>(fwd_step, rev_step, transcendental); break;
+    case 2: count_planar<2>(fwd_step, rev_step, transcendental); break;
+    case 3: count_planar<3>(fwd_step, rev_step, transcendental); break;
+    case 4: count_planar<4>(fwd_step, rev_step, transcendental); break;
+    case 5: count_planar<5>(fwd_step, rev_step, transcendental); break;
+    default: return PDS_EUNSUPPORTED;
+  }
+  return PDS_OK;
+}
+
+}  // namespace pds

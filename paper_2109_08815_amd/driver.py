@@ -1,0 +1,79 @@
+"""CSVGD driver on the GPU library: problem set-up and the iteration loop.
+
+Set-up uses the library's own rollout (sim_batch_forward) for the observed
+trajectories (rollout at the generating parameters plus the problem's noise
+draws) and for the default shooting states (each particle's own
+single-shooting state at the start of every window).  One iteration is
+Algorithm 1: sim_batch_adjoint -> svgd_phi -> svgd_step, optionally captured
+once into a HIP graph and replayed.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import lib as L
+
+
+def single_shooting(pb):
+    """Same problem with one window (n_s = 1, h = T)."""
+    return dataclasses.replace(pb, n_s=1, h=pb.T)
+
+
+def gpu_rollout(pb, theta, device="cuda"):
+    """Visited states [N, K, T, d_s] of every particle from every s0_k."""
+    ss = single_shooting(pb)
+    obs = np.zeros((pb.K, pb.T, pb.d_x))
+    job = L.Job(ss, obs, theta=np.asarray(theta), device=device, with_traj=True)
+    b = L.Batch([job])
+    L.sim_batch_forward(b)
+    torch.cuda.synchronize()
+    return job.traj
+
+
+def gpu_observations(pb, device="cuda"):
+    """Observed trajectories [K, T, d_x]: trajectory k rolled out at theta_true[k] from s0[k] plus noise."""
+    tr = gpu_rollout(pb, pb.theta_true, device)
+    k = torch.arange(pb.K, device=tr.device)
+    x = tr[k, k][:, :, torch.as_tensor(pb.obs_index, device=tr.device)]
+    return x.double().cpu().numpy() + pb.noise
+
+
+def gpu_shooting_init(pb, theta, device="cuda"):
+    """Shooting states [N, K, n_s-1, d_s] from each particle's own rollout."""
+    if pb.n_s == 1:
+        return np.zeros((theta.shape[0], pb.K, 0, pb.d_s))
+    tr = gpu_rollout(pb, theta, device)
+    idx = torch.arange(1, pb.n_s, device=tr.device) * pb.h - 1
+    return tr[:, :, idx].double().cpu().numpy()
+
+
+class CSVGD:
+    """Runs CSVGD iterations on a batch of jobs (plain launches or a replayed graph)."""
+
+    def __init__(self, jobs, optimizer=L.PDS_OPT_ADAM):
+        for j in jobs:
+            if j.iter_dev is None:
+                j.iter_dev = torch.zeros(1, dtype=torch.int32, device=j.device)
+        self.batch = L.Batch(jobs)
+        self.optimizer = optimizer
+        self.graph = None
+        self.stream = None
+
+    def step(self):
+        """One iteration with plain launches on the current stream."""
+        L.csvgd_iteration(self.batch, 0, self.optimizer)
+
+    def capture(self):
+        """Capture one iteration into a graph (after one eager warm-up call)."""
+        self.stream = torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=self.stream):
+            L.csvgd_iteration(self.batch, 0, self.optimizer)
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def replay(self):
+        self.graph.replay()

@@ -1,0 +1,254 @@
+"""Python binding of libpds (include/pds.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of libpds.so; this module only
+owns device buffers (torch tensors), fills the pds_job structs that point at
+them, and calls the C entry points with the same names.  If the library is
+missing the import of ``lib()`` raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpds.so")
+
+PDS_OK = 0
+PDS_MODEL_PLANAR = 1
+PDS_MODEL_ARM = 2
+PDS_COMBINE_SUM = 0
+PDS_COMBINE_PROD = 1
+PDS_OPT_SGD = 0
+PDS_OPT_ADAM = 1
+PDS_CALL_FORWARD, PDS_CALL_LOGLIK, PDS_CALL_ADJOINT, PDS_CALL_PHI, PDS_CALL_STEP, PDS_CALL_ALL = range(6)
+PDS_MAX_JOBS = 64
+
+_f = C.c_void_p
+
+
+class PdsJob(C.Structure):
+    """Mirror of ``pds_job`` in include/pds.h (same field order)."""
+
+    _fields_ = [
+        ("model", C.c_int32), ("n_dof", C.c_int32), ("M", C.c_int32), ("d_x", C.c_int32),
+        ("N", C.c_int32), ("K", C.c_int32), ("T", C.c_int32), ("n_s", C.c_int32), ("h", C.c_int32),
+        ("combine", C.c_int32), ("dt", C.c_float), ("sigma_def", C.c_float), ("c", C.c_float),
+        ("eps_lam", C.c_float),
+        ("consts", _f), ("lo", _f), ("hi", _f), ("rho", _f), ("w_x", _f), ("u", _f), ("lr_theta", _f),
+        ("lr_S", _f), ("s0", _f), ("obs", _f), ("seed_logp", _f), ("seed_gdef", _f),
+        ("theta", _f), ("S", _f), ("lam_lim", _f), ("lam_def", _f), ("adam_m", _f), ("adam_v", _f),
+        ("end_states", _f), ("traj", _f), ("ll_win", _f), ("gdef", _f), ("logp", _f), ("wk", _f),
+        ("g_obs", _f), ("g_con", _f), ("S_dot", _f), ("phi", _f), ("bandwidth", _f), ("flags", _f),
+        ("iter_dev", _f),
+    ]
+
+
+class PdsError(RuntimeError):
+    pass
+
+
+_lock = threading.Lock()
+_lib = None
+EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
+           "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_timing_enable",
+           "pds_timing_read")
+
+
+def lib():
+    """Load libpds.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise PdsError("libpds.so is missing: build it with `python -m paper_2109_08815_amd.build`")
+            L = C.CDLL(LIB_PATH)
+            P = C.POINTER(PdsJob)
+            for name in ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi"):
+                fn = getattr(L, name)
+                fn.argtypes = [P, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
+                fn.restype = C.c_int
+            L.svgd_step.argtypes = [P, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
+            L.svgd_step.restype = C.c_int
+            L.pds_workspace_size.argtypes = [P, C.c_int32, C.c_int32]
+            L.pds_workspace_size.restype = C.c_size_t
+            L.pds_last_error.restype = C.c_char_p
+            L.pds_version.restype = C.c_int32
+            L.pds_algorithmic_flops.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+            L.pds_algorithmic_flops.restype = C.c_int
+            L.pds_timing_enable.argtypes = [C.c_int32]
+            L.pds_timing_enable.restype = C.c_int
+            L.pds_timing_read.argtypes = [C.c_void_p, C.c_int32]
+            L.pds_timing_read.restype = C.c_int
+            _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != PDS_OK:
+        msg = lib().pds_last_error().decode()
+        raise PdsError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(a, dtype, device):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device)
+
+
+class Job:
+    """Device buffers and the pds_job struct of one inference problem."""
+
+    def __init__(self, pb, obs, theta=None, S=None, device="cuda", with_traj=False, seed_logp=None,
+                 seed_gdef=None, device_iter=False):
+        dev = torch.device(device)
+        self.pb = pb
+        self.device = dev
+        f32, f64 = torch.float32, torch.float64
+        N, K, T, ns, M, ds = pb.N, pb.K, pb.T, pb.n_s, pb.M, pb.d_s
+        if theta is None:
+            theta = pb.particles
+        N = theta.shape[0]
+        self.N = N
+        if pb.kind == 1:
+            self.model = PDS_MODEL_PLANAR
+            consts = np.concatenate([pb.gravity[:2], pb.damping[: pb.n_dof]])
+        else:
+            self.model = PDS_MODEL_ARM
+            consts = np.zeros(1)
+        self.consts = _dev(consts, f32, dev)
+        self.lo, self.hi, self.rho = (_dev(pb.lo, f32, dev), _dev(pb.hi, f32, dev), _dev(pb.rho, f32, dev))
+        self.w_x, self.u = _dev(pb.w_x, f32, dev), _dev(pb.u, f32, dev)
+        self.lr_theta, self.lr_S = _dev(pb.lr_theta, f32, dev), _dev(pb.lr_S, f32, dev)
+        self.s0 = _dev(pb.s0, f32, dev)
+        self.obs = _dev(obs, f32, dev)
+        self.theta = _dev(theta, f32, dev)
+        nsm = max(ns - 1, 0)
+        self.S = _dev(np.zeros((N, K, nsm, ds)) if S is None else S, f32, dev).reshape(N, K, nsm, ds).contiguous()
+        self.lam_lim = torch.zeros((N, M), dtype=f32, device=dev)
+        self.lam_def = torch.zeros((N, K, nsm), dtype=f32, device=dev)
+        nA = M + K * nsm * ds
+        self.adam_m = torch.zeros((N, nA), dtype=f32, device=dev)
+        self.adam_v = torch.zeros((N, nA), dtype=f32, device=dev)
+        self.end_states = torch.zeros((N, K, ns, ds), dtype=f32, device=dev)
+        self.traj = torch.zeros((N, K, T, ds), dtype=f32, device=dev) if with_traj else None
+        self.ll_win = torch.zeros((N, K, ns), dtype=f64, device=dev)
+        self.gdef = torch.zeros((N, K, max(nsm, 1)), dtype=f64, device=dev)
+        self.logp = torch.zeros(N, dtype=f64, device=dev)
+        self.wk = torch.zeros((N, K), dtype=f64, device=dev)
+        self.g_obs = torch.zeros((N, M), dtype=f64, device=dev)
+        self.g_con = torch.zeros((N, M), dtype=f64, device=dev)
+        self.S_dot = torch.zeros((N, K, max(nsm, 1), ds), dtype=f32, device=dev)
+        self.phi = torch.zeros((N, M), dtype=f32, device=dev)
+        self.bandwidth = torch.zeros(1, dtype=f64, device=dev)
+        self.flags = torch.zeros(N, dtype=torch.int32, device=dev)
+        self.iter_dev = torch.zeros(1, dtype=torch.int32, device=dev) if device_iter else None
+        self.seed_logp = None if seed_logp is None else _dev(seed_logp, f64, dev)
+        self.seed_gdef = None if seed_gdef is None else _dev(seed_gdef, f64, dev)
+
+    def struct(self) -> PdsJob:
+        pb = self.pb
+        j = PdsJob()
+        j.model, j.n_dof, j.M, j.d_x = self.model, pb.n_dof, pb.M, pb.d_x
+        j.N, j.K, j.T, j.n_s, j.h, j.combine = self.N, pb.K, pb.T, pb.n_s, pb.h, pb.combine
+        j.dt, j.sigma_def, j.c, j.eps_lam = pb.dt, pb.sigma_def, pb.c, pb.eps_lam
+        for name in ("consts", "lo", "hi", "rho", "w_x", "u", "lr_theta", "lr_S", "s0", "obs", "seed_logp",
+                     "seed_gdef", "theta", "S", "lam_lim", "lam_def", "adam_m", "adam_v", "end_states", "traj",
+                     "ll_win", "gdef", "logp", "wk", "g_obs", "g_con", "S_dot", "phi", "bandwidth", "flags",
+                     "iter_dev"):
+            setattr(j, name, _ptr(getattr(self, name)))
+        return j
+
+
+class Batch:
+    """A batch of jobs: host struct array, device copy and workspace."""
+
+    def __init__(self, jobs):
+        if not 1 <= len(jobs) <= PDS_MAX_JOBS:
+            raise PdsError("a batch holds 1..%d jobs" % PDS_MAX_JOBS)
+        self.jobs = list(jobs)
+        self.device = jobs[0].device
+        self.refresh()
+
+    def refresh(self):
+        """Rebuild the struct arrays (after buffers were replaced)."""
+        n = len(self.jobs)
+        self.h = (PdsJob * n)(*[j.struct() for j in self.jobs])
+        raw = np.frombuffer(bytes(self.h), dtype=np.uint8)
+        self.d = torch.as_tensor(raw.copy()).to(self.device)
+        need = lib().pds_workspace_size(self.h, n, PDS_CALL_ALL)
+        if need == 0 and lib().pds_last_error():
+            raise PdsError(lib().pds_last_error().decode())
+        self.ws = torch.empty(max(need, 256) + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = self.ws.data_ptr() + off
+        self.ws_bytes = need
+
+    @property
+    def n(self):
+        return len(self.jobs)
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _call(name, b: Batch, stream):
+    fn = getattr(lib(), name)
+    rc = fn(b.h, C.c_void_p(b.d.data_ptr()), b.n, C.c_void_p(b.ws_ptr), b.ws_bytes, _stream(stream))
+    _check(rc, name)
+
+
+def sim_batch_forward(b: Batch, stream=None):
+    _call("sim_batch_forward", b, stream)
+
+
+def loglik_multishoot(b: Batch, stream=None):
+    _call("loglik_multishoot", b, stream)
+
+
+def sim_batch_adjoint(b: Batch, stream=None):
+    _call("sim_batch_adjoint", b, stream)
+
+
+def svgd_phi(b: Batch, stream=None):
+    _call("svgd_phi", b, stream)
+
+
+def svgd_step(b: Batch, optimizer=PDS_OPT_ADAM, iteration=1, stream=None):
+    rc = lib().svgd_step(b.h, C.c_void_p(b.d.data_ptr()), b.n, int(optimizer), int(iteration), _stream(stream))
+    _check(rc, "svgd_step")
+
+
+def csvgd_iteration(b: Batch, iteration: int, optimizer=PDS_OPT_ADAM, stream=None):
+    """One CSVGD iteration (Algorithm 1) over every job of the batch."""
+    sim_batch_adjoint(b, stream)
+    svgd_phi(b, stream)
+    svgd_step(b, optimizer, iteration, stream)
+
+
+def algorithmic_flops(model: int, n_dof: int):
+    """(forward step, reverse step per channel, sin/cos count) from the library's own counter."""
+    f, r, t = C.c_double(), C.c_double(), C.c_double()
+    rc = lib().pds_algorithmic_flops(int(model), int(n_dof), C.byref(f), C.byref(r), C.byref(t))
+    _check(rc, "pds_algorithmic_flops")
+    return f.value, r.value, t.value
+
+
+def timing_enable(on: bool = True):
+    _check(lib().pds_timing_enable(1 if on else 0), "pds_timing_enable")
+
+
+def timing_read(max_n: int = 4096):
+    buf = (C.c_float * max_n)()
+    n = lib().pds_timing_read(buf, max_n)
+    if n < 0:
+        _check(n, "pds_timing_read")
+    return np.array(buf[:n], dtype=np.float64)

@@ -1,0 +1,106 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+include/pds.h declares, the Python struct mirrors the C layout, and invalid
+arguments are rejected on the host before anything is queued."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2109_08815_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pds.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_five_calls():
+    names = declared_functions()
+    for n in ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
+              "pds_workspace_size", "pds_last_error", "pds_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    out = subprocess.check_output(["nm", "-D", "--defined-only", L.LIB_PATH]).decode()
+    for n in declared_functions():
+        assert re.search(r" T %s$" % n, out, flags=re.M), n
+    assert lib.pds_version() >= 100
+
+
+def test_struct_layout_matches_header():
+    """Compile a tiny C program against pds.h that prints offsetof/sizeof and
+    compare with the ctypes mirror."""
+    fields = [f[0] for f in L.PdsJob._fields_]
+    src = "#include <stdio.h>\n#include <stddef.h>\n#include \"pds.h\"\nint main(void){\n"
+    src += 'printf("%zu\\n", sizeof(pds_job));\n'
+    for f in fields:
+        src += 'printf("%%zu\\n", offsetof(pds_job, %s));\n' % f
+    src += "return 0;}\n"
+    d = os.path.join("/tmp", "pds_layout_%d" % os.getpid())
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "t.c"), "w") as fh:
+        fh.write(src)
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", os.path.join(d, "t"), os.path.join(d, "t.c")])
+    vals = [int(x) for x in subprocess.check_output([os.path.join(d, "t")]).split()]
+    assert vals[0] == C.sizeof(L.PdsJob)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(L.PdsJob, f).offset == off, f
+
+
+def _job(**kw):
+    j = L.PdsJob()
+    j.model, j.n_dof, j.M, j.d_x = L.PDS_MODEL_PLANAR, 2, 4, 2
+    j.N, j.K, j.T, j.n_s, j.h, j.combine = 8, 1, 20, 2, 10, 0
+    j.dt, j.sigma_def, j.c = 0.01, 0.1, 1.0
+    for k, v in kw.items():
+        setattr(j, k, v)
+    return j
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(T=21), -1), (dict(N=0), -1), (dict(dt=0.0), -1), (dict(sigma_def=-1.0), -1),
+    (dict(n_dof=6, M=12, d_x=6), -2), (dict(model=2), -2), (dict(model=7), -1), (dict(M=3), -1),
+    (dict(combine=5), -1),
+])
+def test_invalid_jobs_rejected_on_host(bad, code):
+    lib = L.lib()
+    arr = (L.PdsJob * 1)(_job(**bad))
+    fake_dev = C.c_void_p(4096)  # never dereferenced: validation fails first
+    for fn in (lib.sim_batch_forward, lib.loglik_multishoot, lib.sim_batch_adjoint):
+        rc = fn(arr, fake_dev, 1, None, 0, None)
+        assert rc == code
+        assert len(lib.pds_last_error()) > 0
+
+
+def test_null_buffers_and_batch_size_rejected():
+    lib = L.lib()
+    arr = (L.PdsJob * 1)(_job())
+    fake_dev = C.c_void_p(4096)
+    assert lib.sim_batch_forward(arr, fake_dev, 1, None, 0, None) == -1  # theta etc. NULL
+    assert b"NULL" in lib.pds_last_error()
+    assert lib.svgd_phi(arr, fake_dev, 0, None, 0, None) == -1
+    assert lib.svgd_step(arr, fake_dev, 1, 7, 1, None) == -1
+    assert lib.pds_workspace_size(arr, 0, 5) == 0
+
+
+def test_workspace_size_grows_with_problem():
+    lib = L.lib()
+    small = (L.PdsJob * 1)(_job())
+    big = (L.PdsJob * 1)(_job(N=1024, K=8, T=1000, n_s=20, h=50))
+    assert lib.pds_workspace_size(small, 1, L.PDS_CALL_FORWARD) == 0
+    a = lib.pds_workspace_size(small, 1, L.PDS_CALL_ADJOINT)
+    b = lib.pds_workspace_size(big, 1, L.PDS_CALL_ADJOINT)
+    assert 0 < a < b
+    assert b % 256 == 0

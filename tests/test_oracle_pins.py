@@ -351,8 +351,8 @@ def test_median_brute_force(orc):
         d = [math.sqrt(sum(((th[i, m] - th[j, m]) / rho[m]) ** 2 for m in range(3)))
              for i, j in itertools.combinations(range(N), 2)]
         ref = statistics.median(d)
-        assert abs(med - ref) <= 1e-15 * ref
-        assert abs(h - ref * ref / math.log(N)) <= 1e-15 * h
+        assert abs(med - ref) <= 1e-14 * ref
+        assert abs(h - ref * ref / math.log(N)) <= 1e-14 * h
 
 
 def test_phi_two_particles_hand_worked(orc):
