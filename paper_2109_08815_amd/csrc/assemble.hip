@@ -18,18 +18,15 @@
 namespace pds {
 namespace {
 
-__global__ void __launch_bounds__(256) assemble_logp_kernel(JobMap map, const pds_job* __restrict__ jobs) {
-  const int e = map_entry(map, blockIdx.x);
-  const pds_job& J = jobs[map.job[e]];
-  const int i = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
-  if (i >= J.N) return;
+// Combination over trajectories for particle i; writes logp and wk.
+__device__ inline void combine_particle(const pds_job& J, int i) {
   const int K = J.K, ns = J.n_s;
   const double* lw = J.ll_win + (size_t)i * K * ns;
   double mx = -INFINITY, lp = 0.0;
   for (int k = 0; k < K; ++k) {
     double a = 0.0;
     for (int j = 0; j < ns; ++j) a += lw[k * ns + j];
-    J.wk[(size_t)i * K + k] = a;  // temporarily hold l_k
+    J.wk[(size_t)i * K + k] = a;  // holds l_k until the weights are known
     mx = fmax(mx, a);
     lp += a;
   }
@@ -45,32 +42,44 @@ __global__ void __launch_bounds__(256) assemble_logp_kernel(JobMap map, const pd
   if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
 }
 
-// One thread per (particle, parameter).
-__global__ void __launch_bounds__(256) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                            char* __restrict__ ws) {
+// Forward-only path: one thread per particle.
+__global__ void __launch_bounds__(64) assemble_logp_kernel(JobMap map, const pds_job* __restrict__ jobs) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
-  if (t >= J.N * J.M) return;
-  const int i = t % J.N, m = t / J.N;
+  const int i = (blockIdx.x - map.begin[e]) * 64 + threadIdx.x;
+  if (i >= J.N) return;
+  combine_particle(J, i);
+}
+
+// Adjoint path: one thread per particle; combination, then both parameter
+// gradients (per-unit terms laid out [m][u], u = (k n_s + j) N + i).
+__global__ void __launch_bounds__(64) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                           char* __restrict__ ws) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int i = (blockIdx.x - map.begin[e]) * 64 + threadIdx.x;
+  if (i >= J.N) return;
+  combine_particle(J, i);
   const WsLayout L = ws_layout(J);
   const char* base = ws + map.ws_off[e];
   const size_t U = (size_t)J.N * J.K * J.n_s;
-  const double* go = reinterpret_cast<const double*>(base + L.gth_obs) + (size_t)m * U;
-  const double* gc = reinterpret_cast<const double*>(base + L.gth_con) + (size_t)m * U;
-  double so = 0.0, sc = 0.0;
-  for (int k = 0; k < J.K; ++k) {
-    double a = 0.0;
-    for (int j = 0; j < J.n_s; ++j) {
-      const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
-      a += go[u];
-      sc += gc[u];
-    }
-    so += J.wk[(size_t)i * J.K + k] * a;
-  }
   const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
-  J.g_obs[(size_t)i * J.M + m] = seed * so;
-  J.g_con[(size_t)i * J.M + m] = sc;
+  for (int m = 0; m < J.M; ++m) {
+    const double* go = reinterpret_cast<const double*>(base + L.gth_obs) + (size_t)m * U;
+    const double* gc = reinterpret_cast<const double*>(base + L.gth_con) + (size_t)m * U;
+    double so = 0.0, sc = 0.0;
+    for (int k = 0; k < J.K; ++k) {
+      double a = 0.0;
+      for (int j = 0; j < J.n_s; ++j) {
+        const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
+        a += go[u];
+        sc += gc[u];
+      }
+      so += J.wk[(size_t)i * J.K + k] * a;
+    }
+    J.g_obs[(size_t)i * J.M + m] = seed * so;
+    J.g_con[(size_t)i * J.M + m] = sc;
+  }
 }
 
 // One thread per shooting-state component (i, k, j >= 1, d).
@@ -113,12 +122,12 @@ __global__ void __launch_bounds__(256) assemble_sdot_kernel(JobMap map, const pd
 
 hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* /*ws*/, int grid, bool /*with_grad*/,
                            hipStream_t s) {
-  hipLaunchKernelGGL(assemble_logp_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs);
+  hipLaunchKernelGGL(assemble_logp_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs);
   return hipGetLastError();
 }
 
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(assemble_grad_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
+  hipLaunchKernelGGL(assemble_grad_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs, ws);
   return hipGetLastError();
 }
 

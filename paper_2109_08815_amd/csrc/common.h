@@ -35,8 +35,17 @@ struct WsLayout {
   size_t total;
 };
 
-constexpr int kPhiChunk = 128;   // particles j per phi partial
+constexpr int kPhiChunk = 32;    // particles j per phi partial
 constexpr int kRadixPasses = 8;  // 8-bit digits of a 64-bit key
+constexpr int kRadixJT = 16;     // particles j per radix-pass block (64 i per block)
+
+// Selection state of the bandwidth median, carried between radix passes.
+struct RadixState {
+  uint64_t pre[2];   // key prefix fixed so far, for both middle ranks
+  uint64_t rem[2];   // rank among keys sharing that prefix
+  uint32_t count[kRadixPasses];  // blocks finished per pass
+  uint32_t pad[kRadixPasses];
+};
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -49,7 +58,7 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   L.gth_con = o; o = align256(o + U * J.M * sizeof(double));
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
   L.gs_con = o;  o = align256(o + U * ds * sizeof(float));
-  L.hist = o;    o = align256(o + (size_t)kRadixPasses * 2 * 256 * sizeof(uint32_t));
+  L.hist = o;    o = align256(o + (size_t)kRadixPasses * 2 * 256 * sizeof(uint32_t) + sizeof(RadixState));
   const size_t chunks = ((size_t)J.N + kPhiChunk - 1) / kPhiChunk;
   L.phi_part = o; o = align256(o + chunks * (size_t)J.N * J.M * sizeof(float));
   L.total = o;
@@ -59,8 +68,8 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
 // Launchers implemented in the .hip files.  Each returns a hipError_t.
 hipError_t launch_planar_forward(const JobMap& map, int nb, const pds_job* d_jobs, int grid, bool with_ll,
                                  hipStream_t s);
-hipError_t launch_planar_adjoint(const JobMap& map, int nb, const pds_job* d_jobs, char* ws, int grid,
-                                 int seg_len, int n_seg, size_t lds_bytes, hipStream_t s);
+hipError_t launch_planar_adjoint(const JobMap& map, int nb, const pds_job* d_jobs, char* ws, int grid, bool split,
+                                 bool full, size_t lds_bytes, hipStream_t s);
 hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_grad,
                            hipStream_t s);
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);

@@ -200,7 +200,7 @@ int assemble_logp(const pds_job* h_jobs, const pds_job* d_jobs, int n, hipStream
   std::vector<uint64_t> off(n, 0);
   int grid = 0;
   JobMap m = make_map(
-      h_jobs, n, off, [](const pds_job&) { return true; }, [](const pds_job& J) { return div_up(J.N, 256); },
+      h_jobs, n, off, [](const pds_job&) { return true; }, [](const pds_job& J) { return div_up(J.N, 64); },
       &grid);
   return launch_rc(pds::launch_assemble(m, d_jobs, nullptr, grid, false, s), "assemble_logp");
 }
@@ -292,30 +292,48 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   int slot = -1;
   timing_begin(s, &slot);
   for (int nb = 1; nb <= 5; ++nb) {
+    // Launch shape: with few waves (less than one per SIMD) the two adjoint
+    // channels go to two lanes per unit and, if LDS allows every wave to be
+    // resident, whole windows stay in LDS; otherwise one lane per unit and
+    // sqrt(h) checkpointing.
+    auto pick = [&](const pds_job& J) { return J.n_dof == nb; };
+    long units = 0;
+    int hmax = 0;
+    for (int j = 0; j < n_jobs; ++j)
+      if (pick(h_jobs[j])) {
+        units += (long)h_jobs[j].N * h_jobs[j].K * h_jobs[j].n_s;
+        if (h_jobs[j].h > hmax) hmax = h_jobs[j].h;
+      }
+    if (units == 0) continue;
+    const int ds = 2 * nb;
+    const long kSimds = 256 * 4;
+    const size_t full_lds = (size_t)(hmax + 1) * ds * pds::kWave * sizeof(float);
+    const bool split = div_up(units, pds::kWave) < kSimds;
+    const long waves = split ? div_up(units, pds::kWave / 2) : div_up(units, pds::kWave);
+    const long resident_full = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
+    const bool full = waves <= resident_full;
     int grid = 0;
     size_t lds = 0;
     JobMap m = make_map(
-        h_jobs, n_jobs, off, [&](const pds_job& J) { return J.n_dof == nb; },
+        h_jobs, n_jobs, off, pick,
         [&](const pds_job& J) {
-          const int B = pds::planar_seg_len(J.h);
+          const int B = full ? J.h : pds::planar_seg_len(J.h);
           const int nseg = div_up(J.h, B);
-          const size_t b = (size_t)(nseg + B + 1) * (2 * nb) * pds::kWave * sizeof(float);
+          const size_t b = full ? (size_t)(J.h + 1) * ds * pds::kWave * sizeof(float)
+                                : (size_t)(nseg + B + 1) * ds * pds::kWave * sizeof(float);
           if (b > lds) lds = b;
-          return div_up((long)J.N * J.K * J.n_s, pds::kWave);
+          return div_up((long)J.N * J.K * J.n_s, split ? pds::kWave / 2 : pds::kWave);
         },
         &grid);
-    if (m.n == 0) continue;
     if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "window of h steps needs %zu bytes of LDS", lds);
-    rc = launch_rc(pds::launch_planar_adjoint(m, nb, d_jobs, w, grid, 0, 0, lds, s), "planar_adjoint");
+    rc = launch_rc(pds::launch_planar_adjoint(m, nb, d_jobs, w, grid, split, full, lds, s), "planar_adjoint");
     if (rc) return rc;
   }
   timing_end(s, slot);
-  rc = assemble_logp(h_jobs, d_jobs, n_jobs, s);
-  if (rc) return rc;
   int grid = 0;
   JobMap mg = make_map(
       h_jobs, n_jobs, off, [](const pds_job&) { return true; },
-      [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &grid);
+      [](const pds_job& J) { return div_up((long)J.N, 64); }, &grid);
   rc = launch_rc(pds::launch_assemble_grad(mg, d_jobs, w, grid, s), "assemble_grad");
   if (rc) return rc;
   JobMap ms = make_map(
@@ -343,16 +361,27 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   JobMap m1 = make_map(h_jobs, n_jobs, off, all, [](const pds_job&) { return 1; }, &grid);
   rc = launch_rc(pds::launch_hist_clear(m1, d_jobs, w, grid, s), "hist_clear");
   if (rc) return rc;
+  int rgrid0 = 0;
+  JobMap mrad = make_map(
+      h_jobs, n_jobs, off, [](const pds_job& J) { return J.N > 1; },
+      [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kRadixJT); }, &rgrid0);
+  if (mrad.n > 0) {
+    for (int p = 0; p < pds::kRadixPasses; ++p) {
+      rc = launch_rc(pds::launch_radix_pass(mrad, d_jobs, w, rgrid0, p, s), "radix_pass");
+      if (rc) return rc;
+    }
+  }
+  int sgrid = 0;
+  JobMap msingle = make_map(
+      h_jobs, n_jobs, off, [](const pds_job& J) { return J.N == 1; }, [](const pds_job&) { return 1; }, &sgrid);
+  if (msingle.n > 0) {
+    rc = launch_rc(pds::launch_radix_pass(msingle, d_jobs, w, sgrid, pds::kRadixPasses, s), "bandwidth");
+    if (rc) return rc;
+  }
   int pgrid = 0;
   JobMap mp = make_map(
       h_jobs, n_jobs, off, all,
       [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
-  for (int p = 0; p < pds::kRadixPasses; ++p) {
-    rc = launch_rc(pds::launch_radix_pass(mp, d_jobs, w, pgrid, p, s), "radix_pass");
-    if (rc) return rc;
-  }
-  rc = launch_rc(pds::launch_radix_pass(m1, d_jobs, w, grid, pds::kRadixPasses, s), "bandwidth");
-  if (rc) return rc;
   rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, s), "phi_partial");
   if (rc) return rc;
   int rgrid = 0;

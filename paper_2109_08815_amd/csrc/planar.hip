@@ -448,15 +448,25 @@ __host__ __device__ inline int seg_len_of(int h) {
   return B;
 }
 
-template <int NB>
+// Adjoint kernel.  SPLIT = false: a lane owns a unit and carries both
+// adjoint channels.  SPLIT = true (problems too small to fill the GPU): a
+// wave owns 32 units, lanes l and l + 32 share a unit, run the same primal
+// sweeps and each carries one channel (selected by data, so the two halves
+// execute the same instructions).  full = 1 keeps every state of the window
+// in LDS (no recomputation), full = 0 keeps checkpoints every B ~ sqrt(h)
+// steps and recomputes one segment at a time.
+template <int NB, bool SPLIT>
 __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                               char* __restrict__ ws) {
+                                                               char* __restrict__ ws, int full) {
   extern __shared__ float lds[];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int U = J.N * J.K * J.n_s;
   const int lane = threadIdx.x;
-  const int u = (blockIdx.x - map.begin[e]) * kWave + lane;
+  constexpr int UPW = SPLIT ? kWave / 2 : kWave;  // units per wave
+  const int u = (blockIdx.x - map.begin[e]) * UPW + (SPLIT ? (lane & (UPW - 1)) : lane);
+  // channel of this lane: 0 observation, 1 constraint (SPLIT only)
+  const int ch = SPLIT ? (lane >= UPW) : 0;
   if (u >= U) return;
   constexpr int DS = 2 * NB;
   const WsLayout L = ws_layout(J);
@@ -478,22 +488,25 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   for (int d = 0; d < NB; ++d) { q[d] = st[d]; qd[d] = st[NB + d]; }
   const float dt = J.dt;
   const int h = J.h;
-  const int B = seg_len_of(h);
+  const int B = full ? h : seg_len_of(h);
   const int nseg = (h + B - 1) / B;
+  // full: slots 0..h hold states 0..h.  Otherwise slots [0, nseg) hold
+  // checkpoints and [nseg, nseg + B + 1) the segment being reversed.
+  const int segbase = full ? 0 : nseg;
   const int t0 = w.j * h;
   const float* obs = J.obs + ((size_t)w.k * J.T + t0) * J.d_x;
   float wx[NB];
 #pragma unroll
   for (int d = 0; d < NB; ++d) wx[d] = J.w_x[d];
-  // LDS slots: [0, nseg) checkpoints, [nseg, nseg + B + 1) segment states
   auto slot = [&](int s, int d) -> float& { return lds[((size_t)s * DS + d) * kWave + lane]; };
 
-  // ---- forward sweep: log-likelihood, end state, checkpoints ----
+  // ---- forward sweep: log-likelihood, end state, stored states ----
   double ll = 0.0;
   for (int s = 0; s < h; ++s) {
-    if (s % B == 0) {
+    if (full || s % B == 0) {
+      const int sl = full ? s : s / B;
 #pragma unroll
-      for (int d = 0; d < NB; ++d) { slot(s / B, d) = q[d]; slot(s / B, NB + d) = qd[d]; }
+      for (int d = 0; d < NB; ++d) { slot(sl, d) = q[d]; slot(sl, NB + d) = qd[d]; }
     }
     step<NB>(P, dt, q, qd);
     float acc = 0.f;
@@ -504,20 +517,30 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     }
     ll -= 0.5 * (double)acc;
   }
+  if (full) {
+#pragma unroll
+    for (int d = 0; d < NB; ++d) { slot(h, d) = q[d]; slot(h, NB + d) = qd[d]; }
+  }
   ll += (double)h * log_norm_const(J);
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
-  float* es = J.end_states + iu * DS;
-#pragma unroll
-  for (int d = 0; d < NB; ++d) { es[d] = q[d]; es[NB + d] = qd[d]; }
-  J.ll_win[iu] = ll;
   bool bad = !isfinite(ll);
 #pragma unroll
   for (int d = 0; d < NB; ++d) bad |= !isfinite(q[d]) || !isfinite(qd[d]);
+  if (ch == 0) {
+    float* es = J.end_states + iu * DS;
+#pragma unroll
+    for (int d = 0; d < NB; ++d) { es[d] = q[d]; es[NB + d] = qd[d]; }
+    J.ll_win[iu] = ll;
+  }
 
   // ---- seeds ----
-  float qb_o[NB], qdb_o[NB], qb_c[NB], qdb_c[NB];
+  // channel variables: a (obs), c (con); with SPLIT a lane carries only
+  // its own channel in (qb_a, qdb_a) and the observation seed is scaled by
+  // obs_on (1 for the observation lane, 0 for the constraint lane).
+  float qb_a[NB], qdb_a[NB], qb_c[NB], qdb_c[NB];
 #pragma unroll
-  for (int d = 0; d < NB; ++d) { qb_o[d] = qdb_o[d] = qb_c[d] = qdb_c[d] = 0.f; }
+  for (int d = 0; d < NB; ++d) { qb_a[d] = qdb_a[d] = qb_c[d] = qdb_c[d] = 0.f; }
+  const float obs_on = (SPLIT && ch == 1) ? 0.f : 1.f;
   if (w.j + 1 < J.n_s) {
     const size_t id = ((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j;
     const float* sn = J.S + id * DS;
@@ -531,33 +554,46 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     }
     const double inv_s2 = 1.0 / ((double)J.sigma_def * J.sigma_def);
     g *= inv_s2;
-    J.gdef[id] = g;
+    if (ch == 0) J.gdef[id] = g;
     const double seed = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
     // d g / d s_end = -2 e u / sigma^2
     const float sc = (float)(-2.0 * seed * inv_s2);
+    if (SPLIT) {
+      const float con_on = 1.f - obs_on;
 #pragma unroll
-    for (int d = 0; d < NB; ++d) {
-      qb_c[d] = sc * e0[d] * J.u[d];
-      qdb_c[d] = sc * e1[d] * J.u[NB + d];
+      for (int d = 0; d < NB; ++d) {
+        qb_a[d] = con_on * sc * e0[d] * J.u[d];
+        qdb_a[d] = con_on * sc * e1[d] * J.u[NB + d];
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < NB; ++d) {
+        qb_c[d] = sc * e0[d] * J.u[d];
+        qdb_c[d] = sc * e1[d] * J.u[NB + d];
+      }
     }
   }
 
   // ---- reverse sweep over segments ----
-  double gm_o[2 * NB], gm_c[2 * NB];
+  double gm_a[2 * NB], gm_c[2 * NB];
 #pragma unroll
-  for (int m = 0; m < 2 * NB; ++m) { gm_o[m] = 0.0; gm_c[m] = 0.0; }
-  const int segbase = nseg;
+  for (int m = 0; m < 2 * NB; ++m) { gm_a[m] = 0.0; gm_c[m] = 0.0; }
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int a = sg * B;
     const int bnd = min(h, a + B);
+    if (!full) {
 #pragma unroll
-    for (int d = 0; d < NB; ++d) { q[d] = slot(sg, d); qd[d] = slot(sg, NB + d); }
+      for (int d = 0; d < NB; ++d) { q[d] = slot(sg, d); qd[d] = slot(sg, NB + d); }
 #pragma unroll
-    for (int d = 0; d < NB; ++d) { slot(segbase, d) = q[d]; slot(segbase, NB + d) = qd[d]; }
-    for (int s = a; s < bnd; ++s) {
-      step<NB>(P, dt, q, qd);
+      for (int d = 0; d < NB; ++d) { slot(segbase, d) = q[d]; slot(segbase, NB + d) = qd[d]; }
+      for (int s = a; s < bnd; ++s) {
+        step<NB>(P, dt, q, qd);
 #pragma unroll
-      for (int d = 0; d < NB; ++d) { slot(segbase + s - a + 1, d) = q[d]; slot(segbase + s - a + 1, NB + d) = qd[d]; }
+        for (int d = 0; d < NB; ++d) {
+          slot(segbase + s - a + 1, d) = q[d];
+          slot(segbase + s - a + 1, NB + d) = qd[d];
+        }
+      }
     }
     for (int s = bnd - 1; s >= a; --s) {
       // observation seed at the step's output state s+1
@@ -565,7 +601,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
       for (int d = 0; d < NB; ++d) {
         const float x = slot(segbase + s - a + 1, d);
         const float r = (obs[s * NB + d] - x) * wx[d];
-        qb_o[d] += r * wx[d];
+        qb_a[d] += obs_on * (r * wx[d]);
       }
       float qs[NB], qds[NB];
 #pragma unroll
@@ -575,29 +611,46 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
       float mb[NB], lb[NB];
 #pragma unroll
       for (int d = 0; d < NB; ++d) { mb[d] = 0.f; lb[d] = 0.f; }
-      step_rev<NB>(P, dt, qds, T, qb_o, qdb_o, mb, lb);
+      step_rev<NB>(P, dt, qds, T, qb_a, qdb_a, mb, lb);
 #pragma unroll
-      for (int d = 0; d < NB; ++d) { gm_o[d] += (double)mb[d]; gm_o[NB + d] += (double)lb[d]; }
+      for (int d = 0; d < NB; ++d) { gm_a[d] += (double)mb[d]; gm_a[NB + d] += (double)lb[d]; }
+      if (!SPLIT) {
 #pragma unroll
-      for (int d = 0; d < NB; ++d) { mb[d] = 0.f; lb[d] = 0.f; }
-      step_rev<NB>(P, dt, qds, T, qb_c, qdb_c, mb, lb);
+        for (int d = 0; d < NB; ++d) { mb[d] = 0.f; lb[d] = 0.f; }
+        step_rev<NB>(P, dt, qds, T, qb_c, qdb_c, mb, lb);
 #pragma unroll
-      for (int d = 0; d < NB; ++d) { gm_c[d] += (double)mb[d]; gm_c[NB + d] += (double)lb[d]; }
+        for (int d = 0; d < NB; ++d) { gm_c[d] += (double)mb[d]; gm_c[NB + d] += (double)lb[d]; }
+      }
     }
   }
   // ---- per-unit outputs ----
+  if (SPLIT) {
+    double* gth = ch == 0 ? gth_obs : gth_con;
+    float* gs = ch == 0 ? gs_obs : gs_con;
 #pragma unroll
-  for (int m = 0; m < 2 * NB; ++m) {
-    gth_obs[(size_t)m * U + u] = gm_o[m];
-    gth_con[(size_t)m * U + u] = gm_c[m];
-    bad |= !isfinite(gm_o[m]) || !isfinite(gm_c[m]);
-  }
+    for (int m = 0; m < 2 * NB; ++m) {
+      gth[(size_t)m * U + u] = gm_a[m];
+      bad |= !isfinite(gm_a[m]);
+    }
 #pragma unroll
-  for (int d = 0; d < NB; ++d) {
-    gs_obs[(size_t)d * U + u] = qb_o[d];
-    gs_obs[(size_t)(NB + d) * U + u] = qdb_o[d];
-    gs_con[(size_t)d * U + u] = qb_c[d];
-    gs_con[(size_t)(NB + d) * U + u] = qdb_c[d];
+    for (int d = 0; d < NB; ++d) {
+      gs[(size_t)d * U + u] = qb_a[d];
+      gs[(size_t)(NB + d) * U + u] = qdb_a[d];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 2 * NB; ++m) {
+      gth_obs[(size_t)m * U + u] = gm_a[m];
+      gth_con[(size_t)m * U + u] = gm_c[m];
+      bad |= !isfinite(gm_a[m]) || !isfinite(gm_c[m]);
+    }
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+      gs_obs[(size_t)d * U + u] = qb_a[d];
+      gs_obs[(size_t)(NB + d) * U + u] = qdb_a[d];
+      gs_con[(size_t)d * U + u] = qb_c[d];
+      gs_con[(size_t)(NB + d) * U + u] = qdb_c[d];
+    }
   }
   if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
 }
@@ -623,19 +676,25 @@ hipError_t launch_planar_forward(const JobMap& map, int nb, const pds_job* d_job
 }
 
 template <int NB>
-static hipError_t adj_nb(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(planar_adjoint_kernel<NB>, dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws);
+static hipError_t adj_nb(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, size_t lds, bool split,
+                         bool full, hipStream_t s) {
+  if (split)
+    hipLaunchKernelGGL((planar_adjoint_kernel<NB, true>), dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws,
+                       full ? 1 : 0);
+  else
+    hipLaunchKernelGGL((planar_adjoint_kernel<NB, false>), dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws,
+                       full ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_planar_adjoint(const JobMap& map, int nb, const pds_job* d_jobs, char* ws, int grid,
-                                 int /*seg_len*/, int /*n_seg*/, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_planar_adjoint(const JobMap& map, int nb, const pds_job* d_jobs, char* ws, int grid, bool split,
+                                 bool full, size_t lds_bytes, hipStream_t s) {
   switch (nb) {
-    case 1: return adj_nb<1>(map, d_jobs, ws, grid, lds_bytes, s);
-    case 2: return adj_nb<2>(map, d_jobs, ws, grid, lds_bytes, s);
-    case 3: return adj_nb<3>(map, d_jobs, ws, grid, lds_bytes, s);
-    case 4: return adj_nb<4>(map, d_jobs, ws, grid, lds_bytes, s);
-    case 5: return adj_nb<5>(map, d_jobs, ws, grid, lds_bytes, s);
+    case 1: return adj_nb<1>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 2: return adj_nb<2>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 3: return adj_nb<3>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 4: return adj_nb<4>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 5: return adj_nb<5>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -6,12 +6,14 @@
 // FP32 particles.  A non-negative IEEE double orders like its bit pattern
 // read as uint64, so the median is found by an exact most-significant-digit
 // radix select over the 64-bit patterns of the squared distances: eight
-// passes of 8 bits, each a per-block LDS histogram of the keys that still
-// match the prefix fixed by earlier passes, summed into a global histogram
-// with integer atomics (order-independent, hence deterministic).  Every
-// pass recomputes the distances instead of storing the N^2/2 keys.  Both
-// middle order statistics ((P-1)/2 and P/2 of P pairs) are selected at
-// once.
+// passes of 8 bits, each a per-block LDS histogram (wave-aggregated
+// increments) of the keys that still match the prefix fixed by earlier
+// passes, summed into a global histogram with integer atomics
+// (order-independent, hence deterministic).  The last block of a pass to
+// finish fixes that pass's digit, so the next pass only reads the carried
+// prefix.  Every pass recomputes the distances instead of storing the
+// N^2/2 keys.  Both middle order statistics ((P-1)/2 and P/2 of P pairs) are
+// selected at once.
 //
 // phi.  Blocks of 64 particles i against chunks of 128 particles j staged
 // in LDS; FP32 partial sums per chunk, reduced in chunk order.
@@ -29,31 +31,17 @@ __device__ inline uint32_t* hist_of(const pds_job& J, char* ws, uint64_t off) {
   return reinterpret_cast<uint32_t*>(ws + off + L.hist);
 }
 
+__device__ inline RadixState* state_of(uint32_t* hist) {
+  return reinterpret_cast<RadixState*>(hist + kRadixPasses * 2 * 256);
+}
+
 __global__ void __launch_bounds__(256) hist_clear_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                          char* __restrict__ ws) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   uint32_t* hist = hist_of(J, ws, map.ws_off[e]);
-  for (int t = threadIdx.x; t < kRadixPasses * 2 * 256; t += 256) hist[t] = 0u;
-}
-
-// Walks the histograms of passes 0..npass-1 to recover the prefix of the
-// rank-`rank` key (target tg) and its rank among keys with that prefix.
-__device__ inline void radix_prefix(const uint32_t* hist, int npass, int tg, uint64_t rank, uint64_t* prefix,
-                                    uint64_t* rem) {
-  uint64_t p = 0, r = rank;
-  for (int ps = 0; ps < npass; ++ps) {
-    const uint32_t* hh = hist + (ps * 2 + tg) * 256;
-    int b = 0;
-    for (; b < 255; ++b) {
-      const uint64_t c = hh[b];
-      if (r < c) break;
-      r -= c;
-    }
-    p |= (uint64_t)b << (56 - 8 * ps);
-  }
-  *prefix = p;
-  *rem = r;
+  const int n = kRadixPasses * 2 * 256 + (int)(sizeof(RadixState) / sizeof(uint32_t));
+  for (int t = threadIdx.x; t < n; t += 256) hist[t] = 0u;
 }
 
 // Squared scaled distance in FP64, summed in parameter order.
@@ -66,52 +54,68 @@ __device__ inline double pair_d2(const float* ti, const float* tj, const double*
   return s;
 }
 
+// Adds one count per valid lane to lh[bin]; the most common bin of the wave
+// (the first valid lane's) is added once with the wave's tally.
+__device__ inline void wave_hist_add(uint32_t* lh, bool valid, int bin) {
+  const unsigned long long m = __ballot(valid);
+  if (m == 0ull) return;
+  const int leader = __ffsll((long long)m) - 1;
+  const int lbin = __shfl(bin, leader);
+  const bool same = valid && bin == lbin;
+  const unsigned long long sm = __ballot(same);
+  if ((int)(threadIdx.x & 63) == leader) atomicAdd(&lh[lbin], (uint32_t)__popcll(sm));
+  if (valid && !same) atomicAdd(&lh[bin], 1u);
+}
+
 // One radix pass.  Block (ib, jc) covers particles i in [64 ib, 64 ib + 64)
-// against j in [128 jc, 128 jc + 128), pairs with i < j only.
+// against j in [16 jc, 16 jc + 16), pairs with i < j only.  The last block
+// of the job to finish fixes the pass's digit for both middle ranks (and,
+// after the last pass, computes the bandwidth).
 __global__ void __launch_bounds__(kPairBlock) radix_pass_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                 char* __restrict__ ws, int pass) {
   __shared__ uint32_t lh[2][256];
-  __shared__ float tj_s[kPhiChunk * PDS_MAX_M];
-  __shared__ uint64_t pre_s[2];
+  __shared__ float tj_s[kRadixJT * PDS_MAX_M];
+  __shared__ int last_s;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int N = J.N, M = J.M;
   const int nib = (N + kPairBlock - 1) / kPairBlock;
   const int local = blockIdx.x - map.begin[e];
+  const int nblocks = map.begin[e + 1] - map.begin[e];
   const int ib = local % nib, jc = local / nib;
   uint32_t* hist = hist_of(J, ws, map.ws_off[e]);
+  RadixState* st = state_of(hist);
   const uint64_t P = (uint64_t)N * (N - 1) / 2;
-  if (threadIdx.x < 2 && P > 0) {
-    const uint64_t rank = threadIdx.x == 0 ? (P - 1) / 2 : P / 2;
-    uint64_t pre, rem;
-    radix_prefix(hist, pass, threadIdx.x, rank, &pre, &rem);
-    pre_s[threadIdx.x] = pre;
+  uint64_t p0 = 0, p1 = 0;
+  if (pass > 0) {
+    p0 = st->pre[0];
+    p1 = st->pre[1];
   }
   for (int t = threadIdx.x; t < 512; t += kPairBlock) lh[t >> 8][t & 255] = 0u;
-  const int j0 = jc * kPhiChunk;
-  const int nj = min(kPhiChunk, N - j0);
+  const int j0 = jc * kRadixJT;
+  const int nj = max(0, min(kRadixJT, N - j0));
   for (int t = threadIdx.x; t < nj * M; t += kPairBlock) tj_s[t] = J.theta[(size_t)j0 * M + t];
   __syncthreads();
   const int i = ib * kPairBlock + threadIdx.x;
-  if (i < N && P > 0 && j0 + nj - 1 > ib * kPairBlock) {
+  const bool row = i < N;
+  if (nj > 0 && j0 + nj - 1 > ib * kPairBlock) {  // block touches the upper triangle
     double inv_rho[PDS_MAX_M];
     float ti[PDS_MAX_M];
     for (int m = 0; m < M; ++m) {
       inv_rho[m] = 1.0 / (double)J.rho[m];
-      ti[m] = J.theta[(size_t)i * M + m];
+      ti[m] = row ? J.theta[(size_t)i * M + m] : 0.f;
     }
     const int shift = 56 - 8 * pass;
-    const uint64_t p0 = pre_s[0], p1 = pre_s[1];
     for (int jj = 0; jj < nj; ++jj) {
       const int j = j0 + jj;
-      if (j <= i) continue;
+      const bool valid = row && j > i;
       const double d2 = pair_d2(ti, &tj_s[jj * M], inv_rho, M);
       const uint64_t key = (uint64_t)__double_as_longlong(d2);
       const int bin = (int)((key >> shift) & 255u);
-      const bool m0 = pass == 0 || (key >> (64 - 8 * pass)) == (p0 >> (64 - 8 * pass));
-      const bool m1 = pass == 0 || (key >> (64 - 8 * pass)) == (p1 >> (64 - 8 * pass));
-      if (m0) atomicAdd(&lh[0][bin], 1u);
-      if (m1) atomicAdd(&lh[1][bin], 1u);
+      const bool m0 = valid && (pass == 0 || (key >> (64 - 8 * pass)) == (p0 >> (64 - 8 * pass)));
+      const bool m1 = valid && (pass == 0 || (key >> (64 - 8 * pass)) == (p1 >> (64 - 8 * pass)));
+      wave_hist_add(lh[0], m0, bin);
+      wave_hist_add(lh[1], m1, bin);
     }
   }
   __syncthreads();
@@ -120,25 +124,51 @@ __global__ void __launch_bounds__(kPairBlock) radix_pass_kernel(JobMap map, cons
     const uint32_t c = lh[t >> 8][t & 255];
     if (c) atomicAdd(&gh[t], c);
   }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last_s = (atomicAdd(&st->count[pass], 1u) == (uint32_t)(nblocks - 1));
+  __syncthreads();
+  if (!last_s) return;
+  __threadfence();
+  // ---- last block: fix this pass's digit ----
+  for (int t = threadIdx.x; t < 512; t += kPairBlock)
+    lh[t >> 8][t & 255] = __hip_atomic_load(&gh[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int tg = threadIdx.x;
+    uint64_t pre = pass > 0 ? st->pre[tg] : 0ull;
+    uint64_t r = pass > 0 ? st->rem[tg] : (P == 0 ? 0ull : (tg == 0 ? (P - 1) / 2 : P / 2));
+    int b = 0;
+    for (; b < 255; ++b) {
+      const uint64_t c = lh[tg][b];
+      if (r < c) break;
+      r -= c;
+    }
+    pre |= (uint64_t)b << (56 - 8 * pass);
+    st->pre[tg] = pre;
+    st->rem[tg] = r;
+  }
+  if (pass == kRadixPasses - 1) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double h = 1.0;
+      if (P > 0) {
+        const double a = __longlong_as_double((long long)st->pre[0]);
+        const double c = __longlong_as_double((long long)st->pre[1]);
+        const double med = 0.5 * (sqrt(a) + sqrt(c));
+        const double lg = log((double)N);
+        if (med * med >= 1e-300 && lg > 0.0) h = med * med / lg;
+      }
+      J.bandwidth[0] = h;
+    }
+  }
 }
 
-// Final select: both middle keys from the eight histograms; h = med^2 / log N.
-__global__ void bandwidth_kernel(JobMap map, const pds_job* __restrict__ jobs, char* __restrict__ ws) {
+// Writes h = 1 for jobs with a single particle (no pairs, no radix passes).
+__global__ void bandwidth_single_kernel(JobMap map, const pds_job* __restrict__ jobs) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  if (threadIdx.x != 0) return;
-  const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
-  double h = 1.0;
-  if (P > 0) {
-    const uint32_t* hist = hist_of(J, ws, map.ws_off[e]);
-    uint64_t k0, k1, r;
-    radix_prefix(hist, kRadixPasses, 0, (P - 1) / 2, &k0, &r);
-    radix_prefix(hist, kRadixPasses, 1, P / 2, &k1, &r);
-    const double med = 0.5 * (sqrt(__longlong_as_double((long long)k0)) + sqrt(__longlong_as_double((long long)k1)));
-    const double lg = log((double)J.N);
-    if (med * med >= 1e-300 && lg > 0.0) h = med * med / lg;
-  }
-  J.bandwidth[0] = h;
+  if (threadIdx.x == 0) J.bandwidth[0] = 1.0;
 }
 
 // Partial phi of particles i (one per lane) over one chunk of j.
@@ -280,7 +310,7 @@ hipError_t launch_hist_clear(const JobMap& map, const pds_job* d_jobs, char* ws,
 hipError_t launch_radix_pass(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int pass,
                              hipStream_t s) {
   if (pass >= kRadixPasses) {
-    hipLaunchKernelGGL(bandwidth_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs, ws);
+    hipLaunchKernelGGL(bandwidth_single_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs);
   } else {
     hipLaunchKernelGGL(radix_pass_kernel, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws, pass);
   }

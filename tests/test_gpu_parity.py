@@ -82,6 +82,11 @@ CASES = [
     ("c2", dict(N=70, K=3)),                              # ragged: 70 particles span 2 waves
     ("c3", dict(N=70, K=2, T=200, n_s=4)),                # 5-link chain, reduced
     ("c2", dict(N=5, K=1, T=40, n_s=1)),                  # single shooting, tiny N
+    # launch-shape coverage of the adjoint: few units with long windows
+    # (two lanes per unit, checkpointed) and many units with short windows
+    # (one lane per unit, whole window in LDS)
+    ("c3", dict(N=64, K=1, T=400, n_s=2)),
+    ("c1", dict(N=2048, K=8, T=40, n_s=4)),
 ]
 
 
