@@ -42,7 +42,22 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="plain launches instead of graph replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 256 MiB (20 times): the reference for HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    n = 64 * 1024 * 1024  # float32 elements = 256 MiB
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 20}), flush=True)
 
 
 def cpu_baseline(pb, obs, theta, S, target_s):
@@ -79,6 +94,9 @@ def cpu_baseline(pb, obs, theta, S, target_s):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method's data-parallel path runs on a single device "
               "(see the sharding note in DESIGN.md); got --gpus %d" % args.gpus, file=sys.stderr)
@@ -102,8 +120,9 @@ def main():
         run.step()
     torch.cuda.synchronize()
     use_graph = not args.no_graph
+    per_graph = 10 if args.steps % 10 == 0 else 1
     if use_graph:
-        run.capture()
+        run.capture(per_graph)
         run.replay()
         torch.cuda.synchronize()
 
@@ -114,10 +133,11 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        if use_graph:
+    if use_graph:
+        for _ in range(args.steps // per_graph):
             run.replay()
-        else:
+    else:
+        for _ in range(args.steps):
             run.step()
     e1.record()
     torch.cuda.synchronize()
@@ -155,7 +175,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s N=%d M=%d K=%d T=%d dt=%g n_s=%d" % (
             args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain"}[args.config],
-            pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": "graph" if use_graph else "plain"},
+            pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain"},
         "iters_per_s": args.steps / elapsed,
         "roofline": {
             "bound": "alu",

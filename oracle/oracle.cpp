@@ -474,7 +474,8 @@ void orc_forward(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
 // M + d_s exceeds the compiled dual width.
 int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int* sel, double* end_states,
                  double* ll_win, double* gdef, double* logp, double* wk, double* g_obs, double* g_con,
-                 double* S_dot, double* dl_dth_unit /* [n_sel,K,n_s,M] or null */) {
+                 double* S_dot, double* dl_dth_unit /* [n_sel,K,n_s,M] or null */,
+                 double* dcon_dth_unit /* [n_sel,K,n_s,M] or null */) {
   const int ds = 2 * md->n_dof, K = pr->K, ns = pr->n_s, M = md->M;
   const int P = M + ds;
   if (P > 32 || M > 16 || ds > 16) return -1;
@@ -498,6 +499,8 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
     else window_grad<32>(*md, *pr, th, st, k, j, &ll_win[u], a0, a1, a2, a3, a4);
   }
   if (dl_dth_unit) std::memcpy(dl_dth_unit, dl_dth.data(), sizeof(double) * units * M);
+  if (dcon_dth_unit)
+    for (size_t t = 0; t < (size_t)units * M; ++t) dcon_dth_unit[t] = 0.0;
   const double inv_s2 = 1.0 / (pr->sigma_def * pr->sigma_def);
   for (int s = 0; s < n_sel; ++s) {
     const int i = sel[s];
@@ -538,6 +541,7 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
           double acc = 0.0;
           for (int d = 0; d < ds; ++d) acc += dg_dse[d] * dse_dth[(u * ds + d) * M + m];
           g_con[(size_t)s * M + m] += mult * acc;
+          if (dcon_dth_unit) dcon_dth_unit[u * M + m] = mult * acc;
         }
         // window j's start state is a variable only for j >= 1
         if (j >= 1) {

@@ -70,7 +70,7 @@ def lib():
             L.orc_rollout.argtypes = [C.POINTER(OrcModel), _D, _D, C.c_int, C.c_int, C.c_double, _D]
             L.orc_forward.argtypes = [C.POINTER(OrcModel), C.POINTER(OrcProblem), C.c_int, _I, _D, _D, _D, _D, _D, _D]
             L.orc_gradient.argtypes = [C.POINTER(OrcModel), C.POINTER(OrcProblem), C.c_int, _I, _D, _D, _D, _D, _D,
-                                       _D, _D, _D, _D]
+                                       _D, _D, _D, _D, _D]
             L.orc_gradient.restype = C.c_int
             L.orc_bandwidth.argtypes = [C.c_int, C.c_int, _D, _D, C.c_int, _D]
             L.orc_bandwidth.restype = C.c_double
@@ -231,15 +231,17 @@ def gradient(pb, obs, st: State, sel=None, per_unit=False):
     gc = np.zeros((n, M))
     sd = np.zeros((n, K, max(ns - 1, 1), ds))
     pu = np.zeros((n, K, ns, M)) if per_unit else None
+    pc = np.zeros((n, K, ns, M)) if per_unit else None
     m = model_struct(pb)
     rc = lib().orc_gradient(C.byref(m), C.byref(p), n, sel.ctypes.data_as(_I), _p(es), _p(ll), _p(gd), _p(lp),
-                            _p(wk), _p(go), _p(gc), _p(sd), _p(pu))
+                            _p(wk), _p(go), _p(gc), _p(sd), _p(pu), _p(pc))
     if rc != 0:
         raise ValueError("oracle: M + d_s exceeds the compiled dual width")
     out = dict(end_states=es, ll_win=ll, gdef=gd[:, :, : ns - 1], logp=lp, wk=wk, g_obs=go, g_con=gc,
                S_dot=sd[:, :, : ns - 1])
     if per_unit:
         out["dl_dtheta_unit"] = pu
+        out["dcon_dtheta_unit"] = pc
     return out
 
 

@@ -51,34 +51,59 @@ __global__ void __launch_bounds__(64) assemble_logp_kernel(JobMap map, const pds
   combine_particle(J, i);
 }
 
-// Adjoint path: one thread per particle; combination, then both parameter
-// gradients (per-unit terms laid out [m][u], u = (k n_s + j) N + i).
+// Adjoint path: one 64-lane block per particle.  Lanes first sum the window
+// log-likelihoods of one trajectory each, then lane 0 combines them; lanes
+// then sum the per-window parameter gradients of one (parameter,
+// trajectory) pair each (per-unit terms laid out [m][u], u = (k n_s + j) N +
+// i); finally lane m weights and sums over trajectories.  Every sum runs in
+// a fixed order.
+constexpr int kMaxKM = 256;  // (parameter, trajectory) pairs held in LDS per pass
+
 __global__ void __launch_bounds__(64) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                            char* __restrict__ ws) {
+  __shared__ double sa[kMaxKM], sc[kMaxKM];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  const int i = (blockIdx.x - map.begin[e]) * 64 + threadIdx.x;
+  const int i = blockIdx.x - map.begin[e];
   if (i >= J.N) return;
-  combine_particle(J, i);
+  const int K = J.K, ns = J.n_s, M = J.M;
+  const int t = threadIdx.x;
+  if (t == 0) combine_particle(J, i);
+  __syncthreads();
   const WsLayout L = ws_layout(J);
   const char* base = ws + map.ws_off[e];
-  const size_t U = (size_t)J.N * J.K * J.n_s;
+  const size_t U = (size_t)J.N * K * ns;
+  const double* go = reinterpret_cast<const double*>(base + L.gth_obs);
+  const double* gc = reinterpret_cast<const double*>(base + L.gth_con);
   const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
-  for (int m = 0; m < J.M; ++m) {
-    const double* go = reinterpret_cast<const double*>(base + L.gth_obs) + (size_t)m * U;
-    const double* gc = reinterpret_cast<const double*>(base + L.gth_con) + (size_t)m * U;
-    double so = 0.0, sc = 0.0;
-    for (int k = 0; k < J.K; ++k) {
-      double a = 0.0;
-      for (int j = 0; j < J.n_s; ++j) {
-        const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
-        a += go[u];
-        sc += gc[u];
+  // parameters in groups so that (parameter, trajectory) pairs fit in LDS
+  const int mg = K >= kMaxKM ? 1 : kMaxKM / K;
+  for (int m0 = 0; m0 < M; m0 += mg) {
+    const int m1 = min(M, m0 + mg);
+    const int npair = (m1 - m0) * K;
+    for (int p = t; p < npair; p += 64) {
+      const int m = m0 + p / K, k = p % K;
+      double a = 0.0, c = 0.0;
+      for (int j = 0; j < ns; ++j) {
+        const size_t u = ((size_t)k * ns + j) * J.N + i;
+        a += go[(size_t)m * U + u];
+        c += gc[(size_t)m * U + u];
       }
-      so += J.wk[(size_t)i * J.K + k] * a;
+      sa[p] = a;
+      sc[p] = c;
     }
-    J.g_obs[(size_t)i * J.M + m] = seed * so;
-    J.g_con[(size_t)i * J.M + m] = sc;
+    __syncthreads();
+    for (int m = m0 + t; m < m1; m += 64) {
+      double so = 0.0, scon = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const int p = (m - m0) * K + k;
+        so += J.wk[(size_t)i * K + k] * sa[p];
+        scon += sc[p];
+      }
+      J.g_obs[(size_t)i * M + m] = seed * so;
+      J.g_con[(size_t)i * M + m] = scon;
+    }
+    __syncthreads();
   }
 }
 

@@ -30,7 +30,9 @@ __device__ inline int map_entry(const JobMap& m, int block) {
 // Workspace layout of one job (byte offsets from the job's region start).
 struct WsLayout {
   size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients
-  size_t hist;                              // median radix histograms
+  size_t hist;                              // median radix histograms + state
+  size_t cand;                              // median candidate keys
+  size_t keys;                              // materialised pair keys (small problems)
   size_t phi_part;                          // phi partial sums
   size_t total;
 };
@@ -40,11 +42,19 @@ constexpr int kRadixPasses = 8;  // 8-bit digits of a 64-bit key
 constexpr int kRadixJT = 16;     // particles j per radix-pass block (64 i per block)
 
 // Selection state of the bandwidth median, carried between radix passes.
+constexpr int kCandCap = 8192;   // keys the compaction pass may collect
+// Up to this many pairs the median is one materialising kernel plus one
+// single-block selection; above it, multi-block radix passes.
+constexpr int kSmallPairs = 1 << 19;
+
 struct RadixState {
   uint64_t pre[2];   // key prefix fixed so far, for both middle ranks
   uint64_t rem[2];   // rank among keys sharing that prefix
   uint32_t count[kRadixPasses];  // blocks finished per pass
-  uint32_t pad[kRadixPasses];
+  uint32_t done;        // selection finished
+  uint32_t compact_at;  // 1 + pass that collects candidates, 0 = none yet
+  uint32_t ncand;       // candidates collected
+  uint32_t pad[kRadixPasses - 3];
 };
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -59,6 +69,9 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
   L.gs_con = o;  o = align256(o + U * ds * sizeof(float));
   L.hist = o;    o = align256(o + (size_t)kRadixPasses * 2 * 256 * sizeof(uint32_t) + sizeof(RadixState));
+  L.cand = o;    o = align256(o + (size_t)kCandCap * sizeof(uint64_t));
+  const size_t P = (size_t)J.N * (J.N - 1) / 2;
+  L.keys = o;    o = align256(o + (P <= (size_t)kSmallPairs ? P : 0) * sizeof(uint64_t));
   const size_t chunks = ((size_t)J.N + kPhiChunk - 1) / kPhiChunk;
   L.phi_part = o; o = align256(o + chunks * (size_t)J.N * J.M * sizeof(float));
   L.total = o;
@@ -74,12 +87,15 @@ hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* ws, i
                            hipStream_t s);
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_hist_clear(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_radix_pass(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int pass,
-                             hipStream_t s);
-hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
+hipError_t launch_median_small(const JobMap& map_keys, int grid_keys, const JobMap& map_sel, int grid_sel,
+                               const pds_job* d_jobs, char* ws, int mmax, hipStream_t s);
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
+hipError_t launch_hist_clear(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
+hipError_t launch_radix_pass(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int pass, int mmax,
+                             hipStream_t s);
+hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
+                              hipStream_t s);
+hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_step(const JobMap& map, const pds_job* d_jobs, int grid, int optimizer, int iter,
                        hipStream_t s);
 

@@ -333,7 +333,7 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   int grid = 0;
   JobMap mg = make_map(
       h_jobs, n_jobs, off, [](const pds_job&) { return true; },
-      [](const pds_job& J) { return div_up((long)J.N, 64); }, &grid);
+      [](const pds_job& J) { return J.N; }, &grid);
   rc = launch_rc(pds::launch_assemble_grad(mg, d_jobs, w, grid, s), "assemble_grad");
   if (rc) return rc;
   JobMap ms = make_map(
@@ -357,17 +357,37 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);
   auto all = [](const pds_job&) { return true; };
+  int mmax = 1;
+  for (int j = 0; j < n_jobs; ++j) mmax = h_jobs[j].M > mmax ? h_jobs[j].M : mmax;
+  auto npairs = [](const pds_job& J) { return (long)J.N * (J.N - 1) / 2; };
+  // small pair counts: materialised keys + one selecting block per job
+  int kgrid = 0, sgrid1 = 0;
+  JobMap mk = make_map(
+      h_jobs, n_jobs, off, [&](const pds_job& J) { return J.N > 1 && npairs(J) <= pds::kSmallPairs; },
+      [&](const pds_job& J) { return div_up(npairs(J), 256); }, &kgrid);
+  JobMap ms1 = make_map(
+      h_jobs, n_jobs, off, [&](const pds_job& J) { return J.N > 1 && npairs(J) <= pds::kSmallPairs; },
+      [](const pds_job&) { return 1; }, &sgrid1);
+  if (mk.n > 0) {
+    rc = launch_rc(pds::launch_median_small(mk, kgrid, ms1, sgrid1, d_jobs, w, mmax, s), "median_small");
+    if (rc) return rc;
+  }
+  // large pair counts: multi-block radix passes
   int grid = 0;
-  JobMap m1 = make_map(h_jobs, n_jobs, off, all, [](const pds_job&) { return 1; }, &grid);
-  rc = launch_rc(pds::launch_hist_clear(m1, d_jobs, w, grid, s), "hist_clear");
-  if (rc) return rc;
+  JobMap m1 = make_map(
+      h_jobs, n_jobs, off, [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; },
+      [](const pds_job&) { return 1; }, &grid);
+  if (m1.n > 0) {
+    rc = launch_rc(pds::launch_hist_clear(m1, d_jobs, w, grid, s), "hist_clear");
+    if (rc) return rc;
+  }
   int rgrid0 = 0;
   JobMap mrad = make_map(
-      h_jobs, n_jobs, off, [](const pds_job& J) { return J.N > 1; },
+      h_jobs, n_jobs, off, [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; },
       [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kRadixJT); }, &rgrid0);
   if (mrad.n > 0) {
     for (int p = 0; p < pds::kRadixPasses; ++p) {
-      rc = launch_rc(pds::launch_radix_pass(mrad, d_jobs, w, rgrid0, p, s), "radix_pass");
+      rc = launch_rc(pds::launch_radix_pass(mrad, d_jobs, w, rgrid0, p, mmax, s), "radix_pass");
       if (rc) return rc;
     }
   }
@@ -375,14 +395,14 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   JobMap msingle = make_map(
       h_jobs, n_jobs, off, [](const pds_job& J) { return J.N == 1; }, [](const pds_job&) { return 1; }, &sgrid);
   if (msingle.n > 0) {
-    rc = launch_rc(pds::launch_radix_pass(msingle, d_jobs, w, sgrid, pds::kRadixPasses, s), "bandwidth");
+    rc = launch_rc(pds::launch_radix_pass(msingle, d_jobs, w, sgrid, pds::kRadixPasses, mmax, s), "bandwidth");
     if (rc) return rc;
   }
   int pgrid = 0;
   JobMap mp = make_map(
       h_jobs, n_jobs, off, all,
       [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
-  rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, s), "phi_partial");
+  rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, mmax, s), "phi_partial");
   if (rc) return rc;
   int rgrid = 0;
   JobMap mr = make_map(h_jobs, n_jobs, off, all, [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &rgrid);

@@ -56,7 +56,7 @@ class CSVGD:
     def __init__(self, jobs, optimizer=L.PDS_OPT_ADAM):
         for j in jobs:
             if j.iter_dev is None:
-                j.iter_dev = torch.zeros(1, dtype=torch.int32, device=j.device)
+                j.iter_dev = torch.zeros(2, dtype=torch.int32, device=j.device)
         self.batch = L.Batch(jobs)
         self.optimizer = optimizer
         self.graph = None
@@ -66,13 +66,15 @@ class CSVGD:
         """One iteration with plain launches on the current stream."""
         L.csvgd_iteration(self.batch, 0, self.optimizer)
 
-    def capture(self):
-        """Capture one iteration into a graph (after one eager warm-up call)."""
+    def capture(self, iterations: int = 1):
+        """Capture `iterations` consecutive iterations into one graph."""
         self.stream = torch.cuda.Stream()
         self.stream.wait_stream(torch.cuda.current_stream())
         self.graph = torch.cuda.CUDAGraph()
+        self.graph_iterations = iterations
         with torch.cuda.graph(self.graph, stream=self.stream):
-            L.csvgd_iteration(self.batch, 0, self.optimizer)
+            for _ in range(iterations):
+                L.csvgd_iteration(self.batch, 0, self.optimizer)
         torch.cuda.current_stream().wait_stream(self.stream)
 
     def replay(self):

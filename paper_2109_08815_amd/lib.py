@@ -147,7 +147,7 @@ class Job:
         self.phi = torch.zeros((N, M), dtype=f32, device=dev)
         self.bandwidth = torch.zeros(1, dtype=f64, device=dev)
         self.flags = torch.zeros(N, dtype=torch.int32, device=dev)
-        self.iter_dev = torch.zeros(1, dtype=torch.int32, device=dev) if device_iter else None
+        self.iter_dev = torch.zeros(2, dtype=torch.int32, device=dev) if device_iter else None
         self.seed_logp = None if seed_logp is None else _dev(seed_logp, f64, dev)
         self.seed_gdef = None if seed_gdef is None else _dev(seed_gdef, f64, dev)
 
