@@ -31,6 +31,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "planar_adjoint_c2_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2109_08815_amd", "csrc", "planar.hip")
+
+
+def measured_traffic(config):
+    """HBM bytes per launch of the adjoint kernel from the committed PMC
+    summary, or None when it does not cover this workload or the kernel
+    source changed since the counters were taken."""
+    import hashlib
+
+    if config != "c2" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("source_sha256") != h or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -183,7 +204,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic(args.config),
             "kernel": "planar_adjoint_kernel<%d>" % pb.n_dof,
             "kernel_ms": k_ms,
             "flops_per_particle_step": fwd + 2 * rev,

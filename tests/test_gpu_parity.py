@@ -339,3 +339,27 @@ def test_graph_replays_match_eager(orc):
             np.testing.assert_array_equal(np64(getattr(job_a, name)), np64(getattr(job_b, name)), err_msg=name)
         assert np.isfinite(junk.item())
     assert int(np64(job_b.iter_dev)[0]) == 4
+
+
+def test_autograd_function_matches_oracle(orc):
+    """Backward of the autograd wrapper = oracle gradients of
+    sum_i log p_i - sum b * g_def (b random, c = 0)."""
+    from paper_2109_08815_amd.autograd import MultiShootingLikelihood
+
+    pb, obs, st, job, b = make_case(orc, "c2", perturb_S=0.01, N=70, K=3, c=0.0)
+    rng = np.random.default_rng(3)
+    bw = r32(rng.uniform(0.5, 2.0, (pb.N, pb.K, pb.n_s - 1)))
+    mod = MultiShootingLikelihood(pb, obs, pb.particles, st.S)
+    th = torch.tensor(pb.particles, dtype=torch.float32, device="cuda", requires_grad=True)
+    S = torch.tensor(st.S, dtype=torch.float32, device="cuda", requires_grad=True)
+    logp, gdef = mod(th, S)
+    loss = logp.sum() - (torch.as_tensor(bw, device="cuda") * gdef).sum()
+    loss.backward()
+    st_b = orc.State(pb, pb.particles, st.S, lam_def=bw)
+    ref = orc.gradient(pb, obs, st_b, per_unit=True)
+    np.testing.assert_allclose(np64(logp), ref["logp"], rtol=1e-4)
+    gt = ref["g_obs"] - ref["g_con"]
+    scale = (np.linalg.norm(ref["wk"][:, :, None, None] * ref["dl_dtheta_unit"], axis=3).sum(axis=(1, 2))
+             + np.linalg.norm(ref["dcon_dtheta_unit"], axis=3).sum(axis=(1, 2)))
+    assert np.all(np.linalg.norm(np64(th.grad) - gt, axis=1) <= 1e-3 * scale)
+    assert normwise(np64(S.grad), ref["S_dot"]).max() <= 1e-3
