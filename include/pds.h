@@ -68,8 +68,18 @@ extern "C" {
  * along the gravity direction; theta = (m_1..m_n, l_1..l_n), M = 2 n_dof;
  * observes x = q (d_x = n_dof); consts = [g_x, g_y, b_1..b_n] (gravity in
  * the plane, joint damping tau_i = -b_i qd_i).
- * ARM: reserved for the 7-joint arm with a hinged box (not in this build:
- * calls return PDS_EUNSUPPORTED). */
+ * ARM: 7 revolute arm joints about their local z axes after modified-DH
+ * placements (Rot_x(alpha) Trans_x(a) Trans_z(d)), PD-controlled towards
+ * q_d(t) = qc + amp sin(omega t + phase) (tau = kp (q_d - q) + kd (qd_d -
+ * qd)), then a passive hinge about the flange x axis (offset flange_d along
+ * the flange z axis, damping tau = -b_h qd) carrying a box and two equal
+ * point masses at (x_a, y_a, z_m), (x_b, y_b, z_m) in the box frame;
+ * n_dof = 8, theta = (x_a, y_a, x_b, y_b), M = 4, observes the hinge angle
+ * (d_x = 1); consts (126 floats) = gravity[3], then for each arm joint
+ * (a, alpha, d, m, c_x, c_y, c_z, I_xx, I_yy, I_zz, kp, kd, qc, amp,
+ * omega, phase) with the link inertia diagonal about its centre of mass,
+ * then flange_d, b_h, box m, box c[3], box I_xx, I_yy, I_zz, point-mass m,
+ * z_m.  Arm jobs need a workspace in every call that rolls out windows. */
 #define PDS_MODEL_PLANAR 1
 #define PDS_MODEL_ARM 2
 
@@ -145,7 +155,7 @@ typedef struct pds_job {
 /* Rolls out every window (a batched f_sim of Sec. II with the semi-implicit
  * Euler step of App. B-A eq. dynamics; forward dynamics by the Articulated
  * Body Algorithm).  Writes end_states and, where job.traj != NULL, every
- * visited state.  Needs no workspace. */
+ * visited state.  Needs a workspace only for arm jobs. */
 int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws,
                       size_t ws_bytes, void* stream);
 
@@ -153,7 +163,7 @@ int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
  * Gaussian observation terms of eq. combinedlikelihood summed in FP64 per
  * window (ll_win), the defects g_def of Sec. III-E, and the combination over
  * trajectories (logp, wk).  Writes end_states, ll_win, gdef, logp, wk.
- * Needs no workspace. */
+ * Needs a workspace only for arm jobs. */
 int loglik_multishoot(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws,
                       size_t ws_bytes, void* stream);
 

@@ -1,0 +1,790 @@
+// Window rollouts and their reverse-mode adjoint for the 7-joint arm that
+// carries a box on a passive hinge (8 bodies, 6D spatial algebra).
+//
+// Model.  Bodies 0..6 are the arm links, joint i revolute about its local z
+// axis after the fixed modified-DH placement (Rot_x(alpha), Trans_x(a),
+// Trans_z(d)); body 7 is the box on a hinge about the flange x axis, offset
+// by flange_d along the flange z axis.  Arm joints are PD-controlled
+// towards a sinusoid q_d(t) = qc + A sin(omega t + phase); the hinge has
+// viscous damping.  theta = (x_a, y_a, x_b, y_b), the in-plane positions of
+// two equal point masses in the box frame.  The observation is the hinge
+// angle.
+//
+// Forward dynamics: the Articulated Body Algorithm (App. B-A) in body
+// coordinates; articulated inertias are symmetric 6x6 matrices kept as
+// three 3x3 blocks [[A, B], [B^T, C]] (A, C symmetric).  A step is the
+// semi-implicit Euler update of eq. dynamics.
+//
+// Reverse step.  With F(q, qd, qdd, theta) = ID(q, qd, qdd; theta) -
+// tau(q, qd, t) = 0 defining qdd, the vector-Jacobian product of forward
+// dynamics with seed qdd_bar is x_bar = -(dF/dx)^T lambda with
+// lambda = H^{-1} qdd_bar.  lambda comes from an ABA solve (zero velocity,
+// no gravity) that reuses the articulated-body terms U, D of the forward
+// pass; dF/dx^T lambda is the reverse of the recursive Newton-Euler
+// inverse dynamics.  No articulated inertia is ever differentiated.
+//
+// Work layout as for planar chains: one lane per window unit, the window's
+// checkpoints and the segment being reversed in LDS [slot][component][lane].
+#include <cmath>
+
+#include "common.h"
+
+namespace pds {
+
+constexpr int kArmBodies = 8;
+constexpr int kArmDs = 16;
+
+// Per-job constants derived once per call from the caller's raw model
+// description (see pds.h for the raw layout).
+struct ArmConst {
+  float g[3];
+  float E[kArmBodies][9];   // tree rotation: parent coordinates -> joint frame (row-major)
+  float r[kArmBodies][3];   // tree translation (joint origin in parent coordinates)
+  float m[kArmBodies];      // link mass (body 7: the box alone)
+  float c[kArmBodies][3];   // centre of mass
+  float Ic[kArmBodies][6];  // inertia about the COM: xx, xy, xz, yy, yz, zz
+  float kp[7], kd[7], qc[7], amp[7], om[7], ph[7];
+  float bh;                 // hinge damping
+  float pm_m, pm_z;         // point masses: mass each, height in the box frame
+};
+
+namespace {
+
+struct V3 {
+  float x, y, z;
+};
+__host__ __device__ inline V3 v3(float a, float b, float c) { return V3{a, b, c}; }
+__host__ __device__ inline V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__host__ __device__ inline V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__host__ __device__ inline V3 operator-(V3 a) { return v3(-a.x, -a.y, -a.z); }
+__host__ __device__ inline V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+__host__ __device__ inline V3 cross(V3 a, V3 b) {
+  return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// Rotation E (row-major 3x3) applied to v and its transpose.
+__host__ __device__ inline V3 mulE(const float* E, V3 v) {
+  return v3(E[0] * v.x + E[1] * v.y + E[2] * v.z, E[3] * v.x + E[4] * v.y + E[5] * v.z,
+            E[6] * v.x + E[7] * v.y + E[8] * v.z);
+}
+__host__ __device__ inline V3 mulEt(const float* E, V3 v) {
+  return v3(E[0] * v.x + E[3] * v.y + E[6] * v.z, E[1] * v.x + E[4] * v.y + E[7] * v.z,
+            E[2] * v.x + E[5] * v.y + E[8] * v.z);
+}
+
+// Spatial vectors: motion (w; v), force (n; f).
+struct SV {
+  V3 a, l;
+};
+__host__ __device__ inline SV sv(V3 a, V3 l) { return SV{a, l}; }
+__host__ __device__ inline SV operator+(SV p, SV q) { return sv(p.a + q.a, p.l + q.l); }
+__host__ __device__ inline SV operator-(SV p, SV q) { return sv(p.a - q.a, p.l - q.l); }
+__host__ __device__ inline SV operator*(float s, SV p) { return sv(s * p.a, s * p.l); }
+__host__ __device__ inline float sdot(SV p, SV q) { return dot(p.a, q.a) + dot(p.l, q.l); }
+// v x m  and  v x* f
+__host__ __device__ inline SV crm(SV v, SV m) { return sv(cross(v.a, m.a), cross(v.a, m.l) + cross(v.l, m.a)); }
+__host__ __device__ inline SV crf(SV v, SV f) { return sv(cross(v.a, f.a) + cross(v.l, f.l), cross(v.a, f.l)); }
+
+// Plucker transform parent -> body: (E, r).  Motion: X m; force: X^T f.
+__host__ __device__ inline SV xm(const float* E, V3 r, SV m) { return sv(mulE(E, m.a), mulE(E, m.l - cross(r, m.a))); }
+__host__ __device__ inline SV xtf(const float* E, V3 r, SV f) {
+  const V3 fl = mulEt(E, f.l);
+  return sv(mulEt(E, f.a) + cross(r, fl), fl);
+}
+// Transpose of xm (maps a motion-space adjoint back to the parent): X^T y
+__host__ __device__ inline SV xtm(const float* E, V3 r, SV y) { return xtf(E, r, y); }
+// Transpose of xtf (maps a force adjoint to the body): X y
+__host__ __device__ inline SV xf(const float* E, V3 r, SV y) { return xm(E, r, y); }
+
+// Joint axis: bodies 0..6 about z, body 7 about x (unit vectors).
+__host__ __device__ inline int axis_of(int i) { return i == 7 ? 0 : 2; }
+__host__ __device__ inline float comp(V3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+__host__ __device__ inline V3 unit(int k) { return v3(k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f); }
+
+// Body rotation: joint rotation (about the axis, by q) after the tree rotation.
+__host__ __device__ inline void body_E(const ArmConst& K, int i, float cs, float sn, float* E) {
+  const float* T = K.E[i];
+  if (axis_of(i) == 2) {  // Rz(q)^T T
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      E[k] = cs * T[k] + sn * T[3 + k];
+      E[3 + k] = -sn * T[k] + cs * T[3 + k];
+      E[6 + k] = T[6 + k];
+    }
+  } else {  // Rx(q)^T T
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      E[k] = T[k];
+      E[3 + k] = cs * T[3 + k] + sn * T[6 + k];
+      E[6 + k] = -sn * T[3 + k] + cs * T[6 + k];
+    }
+  }
+}
+
+// Rigid-body inertia applied to a motion vector, from (m, c, Ic):
+// I [w; v] = [Ic w + c x p; p] with p = m (v - c x w).
+__host__ __device__ inline SV rbi_mul(float m, V3 c, const float* Ic, SV x) {
+  const V3 p = m * (x.l - cross(c, x.a));
+  const V3 Iw = v3(Ic[0] * x.a.x + Ic[1] * x.a.y + Ic[2] * x.a.z, Ic[1] * x.a.x + Ic[3] * x.a.y + Ic[4] * x.a.z,
+                   Ic[2] * x.a.x + Ic[4] * x.a.y + Ic[5] * x.a.z);
+  return sv(Iw + cross(c, p), p);
+}
+// Point mass m at c: I [w; v] = [c x p; p], p = m (v - c x w).
+__host__ __device__ inline SV pm_mul(float m, V3 c, SV x) {
+  const V3 p = m * (x.l - cross(c, x.a));
+  return sv(cross(c, p), p);
+}
+
+// Symmetric 6x6 as blocks A (sym 3: xx,xy,xz,yy,yz,zz), B (3x3 row-major), C (sym 3).
+struct Sym6 {
+  float A[6], B[9], C[6];
+};
+__host__ __device__ inline float s3(const float* S, int i, int j) {
+  const int a = i < j ? i : j, b = i < j ? j : i;
+  return a == 0 ? S[b] : (a == 1 ? S[2 + b] : S[5]);
+}
+
+// Adds the rigid inertia of (m, c, Ic) to I: [[Ic + m cx cx^T, m cx], [m cx^T, m 1]].
+__host__ __device__ inline void add_rbi(Sym6& I, float m, V3 c, const float* Ic) {
+  // cx cx^T = |c|^2 1 - c c^T
+  const float cc = dot(c, c);
+  I.A[0] += Ic[0] + m * (cc - c.x * c.x);
+  I.A[1] += Ic[1] - m * c.x * c.y;
+  I.A[2] += Ic[2] - m * c.x * c.z;
+  I.A[3] += Ic[3] + m * (cc - c.y * c.y);
+  I.A[4] += Ic[4] - m * c.y * c.z;
+  I.A[5] += Ic[5] + m * (cc - c.z * c.z);
+  // m skew(c)
+  I.B[0] += 0.f;      I.B[1] += -m * c.z; I.B[2] += m * c.y;
+  I.B[3] += m * c.z;  I.B[4] += 0.f;      I.B[5] += -m * c.x;
+  I.B[6] += -m * c.y; I.B[7] += m * c.x;  I.B[8] += 0.f;
+  I.C[0] += m; I.C[3] += m; I.C[5] += m;
+}
+
+__host__ __device__ inline SV sym6_mul(const Sym6& I, SV x) {
+  const V3 w = x.a, v = x.l;
+  const V3 Aw = v3(I.A[0] * w.x + I.A[1] * w.y + I.A[2] * w.z, I.A[1] * w.x + I.A[3] * w.y + I.A[4] * w.z,
+                   I.A[2] * w.x + I.A[4] * w.y + I.A[5] * w.z);
+  const V3 Bv = mulE(I.B, v);
+  const V3 Btw = mulEt(I.B, w);
+  const V3 Cv = v3(I.C[0] * v.x + I.C[1] * v.y + I.C[2] * v.z, I.C[1] * v.x + I.C[3] * v.y + I.C[4] * v.z,
+                   I.C[2] * v.x + I.C[4] * v.y + I.C[5] * v.z);
+  return sv(Aw + Bv, Btw + Cv);
+}
+
+// IA_parent += X^T Ia X for X = (E, r), R = skew(r):
+// with A' = E^T A E, B' = E^T B E, C' = E^T C E:
+// TL = A' - B' R + R B'^T - R C' R, TR = B' + R C', BR = C'.
+__host__ __device__ __forceinline__ void add_xtix(Sym6& P, const Sym6& I, const float* E, V3 r) {
+  float A[9], B[9], C[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float sa = 0.f, sb = 0.f, sc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          const float e = E[3 * k + i] * E[3 * l + j];
+          sa += e * s3(I.A, k, l);
+          sb += e * I.B[3 * k + l];
+          sc += e * s3(I.C, k, l);
+        }
+      A[3 * i + j] = sa;
+      B[3 * i + j] = sb;
+      C[3 * i + j] = sc;
+    }
+  // skew(r) rows
+  const float R[9] = {0.f, -r.z, r.y, r.z, 0.f, -r.x, -r.y, r.x, 0.f};
+  float BR[9], RC[9], RCR[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        s1 += B[3 * i + k] * R[3 * k + j];
+        s2 += R[3 * i + k] * C[3 * k + j];
+      }
+      BR[3 * i + j] = s1;
+      RC[3 * i + j] = s2;
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float s = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s += RC[3 * i + k] * R[3 * k + j];
+      RCR[3 * i + j] = s;
+    }
+  // TL(i,j) = A - BR - BR^T - RCR   (R B'^T = -(B' R)^T)
+  const int si[6] = {0, 0, 0, 1, 1, 2}, sj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int i = si[e], j = sj[e];
+    P.A[e] += A[3 * i + j] - BR[3 * i + j] - BR[3 * j + i] - RCR[3 * i + j];
+    P.C[e] += C[3 * i + j];
+  }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) P.B[e] += B[e] + RC[e];
+}
+
+// Joint torque at time `time` (PD on the arm, damping on the hinge).
+__host__ __device__ inline float arm_tau(const ArmConst& K, int i, float time, float q, float qd) {
+  if (i == 7) return -K.bh * qd;
+  float sn, cs;
+  sincosf(K.om[i] * time + K.ph[i], &sn, &cs);
+  const float qdes = K.qc[i] + K.amp[i] * sn;
+  const float qddes = K.amp[i] * K.om[i] * cs;
+  return K.kp[i] * (qdes - q) + K.kd[i] * (qddes - qd);
+}
+
+// Intermediates of one forward-dynamics evaluation kept for the reverse.
+struct ArmTape {
+  float cs[kArmBodies], sn[kArmBodies];
+  SV v[kArmBodies];   // body velocities
+  SV a[kArmBodies];   // body accelerations (incl. S qdd)
+  SV U[kArmBodies];   // IA S
+  float invD[kArmBodies];
+  float qdd[kArmBodies];
+};
+
+// Compiler-level memory barrier: the model constants are re-read (scalar
+// loads, cached) inside every step instead of being hoisted out of the step
+// loops into vector registers.
+__host__ __device__ __forceinline__ void keep_consts_in_memory() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" ::: "memory");
+#endif
+}
+
+// Articulated Body Algorithm (three passes over the chain).  The inward
+// pass carries only the child's contribution to the articulated inertia and
+// bias force; each body's rigid inertia is rebuilt on the fly.
+__host__ __device__ __forceinline__ void arm_aba(const ArmConst& K, const float* th, const float* q, const float* qd,
+                                        float time, ArmTape& T) {
+  float u[kArmBodies];
+  const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
+  const float z0[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < kArmBodies; ++i) {
+    keep_consts_in_memory();
+    sincosf(q[i], &T.sn[i], &T.cs[i]);
+    float E[9];
+    body_E(K, i, T.cs[i], T.sn[i], E);
+    const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+    const SV vj = sv(qd[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+    T.v[i] = (i == 0 ? sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f)) : xm(E, r, T.v[i - 1])) + vj;
+  }
+  Sym6 IAc;  // child's contribution X^T Ia X
+  SV pAc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+#pragma unroll
+  for (int e = 0; e < 6; ++e) { IAc.A[e] = 0.f; IAc.C[e] = 0.f; }
+#pragma unroll
+  for (int e = 0; e < 9; ++e) IAc.B[e] = 0.f;
+#pragma unroll
+  for (int i = kArmBodies - 1; i >= 0; --i) {
+    keep_consts_in_memory();
+    const int k = axis_of(i);
+    const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
+    Sym6 IA = IAc;
+    add_rbi(IA, K.m[i], cm, K.Ic[i]);
+    SV h = rbi_mul(K.m[i], cm, K.Ic[i], T.v[i]);
+    if (i == 7) {
+      add_rbi(IA, K.pm_m, ca, z0);
+      add_rbi(IA, K.pm_m, cb, z0);
+      h = h + pm_mul(K.pm_m, ca, T.v[i]) + pm_mul(K.pm_m, cb, T.v[i]);
+    }
+    const SV pA = crf(T.v[i], h) + pAc;
+    const SV U = sv(v3(s3(IA.A, 0, k), s3(IA.A, 1, k), s3(IA.A, 2, k)),
+                    v3(IA.B[3 * k], IA.B[3 * k + 1], IA.B[3 * k + 2]));
+    const float invD = 1.0f / comp(U.a, k);
+    u[i] = arm_tau(K, i, time, q[i], qd[i]) - comp(pA.a, k);
+    T.U[i] = U;
+    T.invD[i] = invD;
+    if (i > 0) {
+      Sym6 Ia = IA;
+      const float Uw[3] = {U.a.x, U.a.y, U.a.z}, Uv[3] = {U.l.x, U.l.y, U.l.z};
+      const int si[6] = {0, 0, 0, 1, 1, 2}, sj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        Ia.A[e] -= Uw[si[e]] * Uw[sj[e]] * invD;
+        Ia.C[e] -= Uv[si[e]] * Uv[sj[e]] * invD;
+      }
+#pragma unroll
+      for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < 3; ++b2) Ia.B[3 * a2 + b2] -= Uw[a2] * Uv[b2] * invD;
+      const SV ci = crm(T.v[i], sv(qd[i] * unit(k), v3(0.f, 0.f, 0.f)));
+      const SV pa = pA + sym6_mul(Ia, ci) + (u[i] * invD) * U;
+      float E[9];
+      body_E(K, i, T.cs[i], T.sn[i], E);
+      const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+#pragma unroll
+      for (int e = 0; e < 6; ++e) { IAc.A[e] = 0.f; IAc.C[e] = 0.f; }
+#pragma unroll
+      for (int e = 0; e < 9; ++e) IAc.B[e] = 0.f;
+      add_xtix(IAc, Ia, E, r);
+      pAc = xtf(E, r, pa);
+    }
+  }
+  SV ap = sv(v3(0.f, 0.f, 0.f), v3(-K.g[0], -K.g[1], -K.g[2]));
+#pragma unroll
+  for (int i = 0; i < kArmBodies; ++i) {
+    keep_consts_in_memory();
+    float E[9];
+    body_E(K, i, T.cs[i], T.sn[i], E);
+    const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+    const SV ci = crm(T.v[i], sv(qd[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f)));
+    const SV a1 = xm(E, r, ap) + ci;
+    const float qdd = (u[i] - sdot(T.U[i], a1)) * T.invD[i];
+    T.qdd[i] = qdd;
+    T.a[i] = a1 + sv(qdd * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+    ap = T.a[i];
+  }
+}
+
+__host__ __device__ __forceinline__ void arm_step(const ArmConst& K, const float* th, float time, float dt, float* q,
+                                         float* qd) {
+  keep_consts_in_memory();
+  ArmTape T;
+  arm_aba(K, th, q, qd, time, T);
+#pragma unroll
+  for (int i = 0; i < kArmBodies; ++i) {
+    keep_consts_in_memory();
+    qd[i] = qd[i] + dt * T.qdd[i];
+    q[i] = q[i] + dt * qd[i];
+  }
+}
+
+// Reverse of one Euler step.  (qb, qdb) enter as adjoints of the step's
+// outputs and leave as adjoints of its inputs; thb accumulates d/d theta.
+__host__ __device__ __forceinline__ void arm_step_rev(const ArmConst& K, const float* th, const float* q, const float* qd,
+                                             const ArmTape& T, float dt, float* qb, float* qdb, float* thb) {
+  keep_consts_in_memory();
+  // Euler: q' = q + dt qd', qd' = qd + dt qdd
+  float qddb[kArmBodies];
+  #pragma unroll
+  for (int i = 0; i < kArmBodies; ++i) {
+    keep_consts_in_memory();
+    qdb[i] += dt * qb[i];
+    qddb[i] = dt * qdb[i];
+  }
+  // lambda = H^{-1} qddb: ABA with zero velocity and gravity (the child's
+  // bias-force contribution is carried inward).
+  float lam[kArmBodies], us[kArmBodies];
+  {
+    SV pAc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+#pragma unroll
+    for (int i = kArmBodies - 1; i >= 0; --i) {
+      keep_consts_in_memory();
+      const int k = axis_of(i);
+      us[i] = qddb[i] - comp(pAc.a, k);
+      if (i > 0) {
+        float E[9];
+        body_E(K, i, T.cs[i], T.sn[i], E);
+        const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+        pAc = xtf(E, r, pAc + (us[i] * T.invD[i]) * T.U[i]);
+      }
+    }
+  }
+  {
+    SV ap = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+#pragma unroll
+    for (int i = 0; i < kArmBodies; ++i) {
+      keep_consts_in_memory();
+      float E[9];
+      body_E(K, i, T.cs[i], T.sn[i], E);
+      const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+      const SV a1 = xm(E, r, ap);
+      lam[i] = (us[i] - sdot(T.U[i], a1)) * T.invD[i];
+      ap = a1 + sv(lam[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+    }
+  }
+  // x_bar += -lambda^T dF/dx, F = ID - tau.  The tau part:
+  // d tau / d q = -kp, d tau / d qd = -kd (arm), -bh (hinge).
+  #pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    keep_consts_in_memory();
+    qb[i] += -K.kp[i] * lam[i];
+    qdb[i] += -K.kd[i] * lam[i];
+  }
+  qdb[7] += -K.bh * lam[7];
+  // ID part: reverse of RNEA with output seed mu = -lambda.  Total-force
+  // adjoints first (outward; they do not depend on the forces):
+  // ftb_i = S_i mu_i + X_i ftb_{i-1}.
+  const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
+  SV ftb[kArmBodies];
+#pragma unroll
+  for (int i = 0; i < kArmBodies; ++i) {
+    keep_consts_in_memory();
+    SV b = sv((-lam[i]) * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+    if (i > 0) {
+      float E[9];
+      body_E(K, i, T.cs[i], T.sn[i], E);
+      const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+      b = b + xf(E, r, ftb[i - 1]);
+    }
+    ftb[i] = b;
+  }
+  // Inward: total forces ft_i = f_i + X_{i+1}^T ft_{i+1} (carried), the
+  // q dependence of X_i^T ft_i, and the reverse of the outward pass
+  // (velocities, accelerations) with body-force adjoints ftb_i.
+  SV ftc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));  // X_{i+1}^T ft_{i+1}
+  SV abar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+  SV vbar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+#pragma unroll
+  for (int i = kArmBodies - 1; i >= 0; --i) {
+    keep_consts_in_memory();
+    const SV fb = ftb[i];
+    const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
+    const SV v = T.v[i], a = T.a[i];
+    const V3 ax = unit(axis_of(i));
+    const SV sax = sv(ax, v3(0.f, 0.f, 0.f));
+    // body force and total force
+    SV Ia = rbi_mul(K.m[i], cm, K.Ic[i], a);
+    SV h = rbi_mul(K.m[i], cm, K.Ic[i], v);
+    SV Ifb = rbi_mul(K.m[i], cm, K.Ic[i], fb);
+    const SV vxfb = crm(v, fb);
+    SV Ivxfb = rbi_mul(K.m[i], cm, K.Ic[i], vxfb);
+    if (i == 7) {
+      Ia = Ia + pm_mul(K.pm_m, ca, a) + pm_mul(K.pm_m, cb, a);
+      h = h + pm_mul(K.pm_m, ca, v) + pm_mul(K.pm_m, cb, v);
+      Ifb = Ifb + pm_mul(K.pm_m, ca, fb) + pm_mul(K.pm_m, cb, fb);
+      Ivxfb = Ivxfb + pm_mul(K.pm_m, ca, vxfb) + pm_mul(K.pm_m, cb, vxfb);
+      // theta: the point-mass positions (x, y) in f = I(c) a + v x* I(c) v.
+      // With g(c; x, y) = y . I(c) x = y_n . (c x p) + y_f . p and
+      // p = m (x_l - c x x_w):  dg/dc = p x y_n - m x_w x (y_n x c + y_f).
+      // fb . f = g(c; a, fb) + g(c; v, -v x fb)  (fb . (v x* h) = -(v x fb) . h).
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const V3 cp = w == 0 ? ca : cb;
+        const float mm = K.pm_m;
+        V3 gsum = v3(0.f, 0.f, 0.f);
+#pragma unroll
+        for (int term = 0; term < 2; ++term) {
+          const SV x = term == 0 ? a : v;
+          const SV y = term == 0 ? fb : sv(-vxfb.a, -vxfb.l);
+          const V3 p = mm * (x.l - cross(cp, x.a));
+          const V3 z = cross(y.a, cp) + y.l;
+          gsum = gsum + cross(p, y.a) - mm * cross(x.a, z);
+        }
+        thb[2 * w] += gsum.x;
+        thb[2 * w + 1] += gsum.y;
+      }
+    }
+    const SV ft = Ia + crf(v, h) + ftc;
+    float E[9];
+    body_E(K, i, T.cs[i], T.sn[i], E);
+    const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+    if (i > 0) {
+      // d/dq_i of ftb_{i-1} . X_i^T ft_i = (X_i ftb_{i-1}) . (S x* ft_i)
+      qb[i] += sdot(xf(E, r, ftb[i - 1]), crf(sax, ft));
+      ftc = xtf(E, r, ft);
+    }
+    // f = I a + v x* (I v):  a_bar += I fb;  v_bar += -crf(fb) h - I (v x fb)
+    abar = abar + Ifb;
+    vbar = vbar - crf(fb, h) - Ivxfb;
+    // a_i = X_i a_{i-1} + v_i x (S qd_i) + S qdd_i (qdd held fixed)
+    const SV sq = sv(qd[i] * ax, v3(0.f, 0.f, 0.f));
+    vbar = vbar + crf(sq, abar);
+    qdb[i] += -comp(crf(v, abar).a, axis_of(i));
+    // v_i = X_i v_{i-1} + S qd_i
+    qdb[i] += comp(vbar.a, axis_of(i));
+    if (i > 0) {
+      const SV ya = xm(E, r, T.a[i - 1]), yv = xm(E, r, T.v[i - 1]);
+      // d/dq (abar . X a_prev) = -abar . (S x y)
+      qb[i] += -sdot(abar, crm(sax, ya)) - sdot(vbar, crm(sax, yv));
+      abar = xtm(E, r, abar);
+      vbar = xtm(E, r, vbar);
+    } else {
+      // body 0: its parent is the fixed base (gravity as base acceleration)
+      const SV ya = xm(E, r, sv(v3(0.f, 0.f, 0.f), v3(-K.g[0], -K.g[1], -K.g[2])));
+      qb[0] += -sdot(abar, crm(sax, ya));
+    }
+  }
+}
+
+// Raw model description -> derived constants (the caller's consts array:
+// gravity[3]; per arm joint 7 x (a, alpha, d, m, cx, cy, cz, Ixx, Iyy, Izz,
+// kp, kd, qc, amp, omega, phase); flange_d, hinge damping, box m, box c[3],
+// box I[3] (diagonal), point-mass m, point-mass z).
+__host__ __device__ inline void arm_setup(const float* raw, ArmConst* K) {
+  for (int d = 0; d < 3; ++d) K->g[d] = raw[d];
+  for (int i = 0; i < 7; ++i) {
+    const float* j = raw + 3 + 16 * i;
+    const float a = j[0], al = j[1], d = j[2];
+    float sa, ca;
+    sincosf(al, &sa, &ca);
+    const float E[9] = {1.f, 0.f, 0.f, 0.f, ca, sa, 0.f, -sa, ca};  // Rot_x(alpha)^T
+    for (int e = 0; e < 9; ++e) K->E[i][e] = E[e];
+    K->r[i][0] = a;
+    K->r[i][1] = -d * sa;
+    K->r[i][2] = d * ca;
+    K->m[i] = j[3];
+    K->c[i][0] = j[4]; K->c[i][1] = j[5]; K->c[i][2] = j[6];
+    K->Ic[i][0] = j[7]; K->Ic[i][1] = 0.f; K->Ic[i][2] = 0.f;
+    K->Ic[i][3] = j[8]; K->Ic[i][4] = 0.f; K->Ic[i][5] = j[9];
+    K->kp[i] = j[10]; K->kd[i] = j[11]; K->qc[i] = j[12];
+    K->amp[i] = j[13]; K->om[i] = j[14]; K->ph[i] = j[15];
+  }
+  const float* h = raw + 3 + 16 * 7;
+  for (int e = 0; e < 9; ++e) K->E[7][e] = (e % 4 == 0) ? 1.f : 0.f;
+  K->r[7][0] = 0.f; K->r[7][1] = 0.f; K->r[7][2] = h[0];
+  K->bh = h[1];
+  K->m[7] = h[2];
+  K->c[7][0] = h[3]; K->c[7][1] = h[4]; K->c[7][2] = h[5];
+  K->Ic[7][0] = h[6]; K->Ic[7][1] = 0.f; K->Ic[7][2] = 0.f;
+  K->Ic[7][3] = h[7]; K->Ic[7][4] = 0.f; K->Ic[7][5] = h[8];
+  K->pm_m = h[9];
+  K->pm_z = h[10];
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+__device__ inline const ArmConst* arm_const_of(char* ws, uint64_t off) {
+  return reinterpret_cast<const ArmConst*>(ws + off);
+}
+
+__global__ void arm_setup_kernel(JobMap map, const pds_job* __restrict__ jobs, char* __restrict__ ws) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  if (threadIdx.x == 0) arm_setup(J.consts, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]));
+}
+
+struct AUnit {
+  int i, k, j;
+};
+__device__ inline AUnit aunit_of(const pds_job& J, int u) {
+  AUnit r;
+  r.i = u % J.N;
+  const int kj = u / J.N;
+  r.k = kj / J.n_s;
+  r.j = kj % J.n_s;
+  return r;
+}
+__device__ inline const float* astart_ptr(const pds_job& J, const AUnit& w) {
+  if (w.j == 0) return J.s0 + (size_t)w.k * kArmDs;
+  return J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + (w.j - 1)) * kArmDs;
+}
+
+__global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                            char* ws, int with_ll) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const ArmConst& K = *arm_const_of(ws, map.ws_off[e]);
+  const int U = J.N * J.K * J.n_s;
+  const int u = (blockIdx.x - map.begin[e]) * kWave + threadIdx.x;
+  if (u >= U) return;
+  const AUnit w = aunit_of(J, u);
+  float th[4];
+  for (int m = 0; m < 4; ++m) th[m] = J.theta[(size_t)w.i * 4 + m];
+  const float* st = astart_ptr(J, w);
+  float q[8], qd[8];
+  for (int d = 0; d < 8; ++d) { q[d] = st[d]; qd[d] = st[8 + d]; }
+  const float dt = J.dt;
+  const int t0 = w.j * J.h;
+  const float* obs = J.obs + ((size_t)w.k * J.T + t0);
+  float* traj = J.traj ? J.traj + (((size_t)w.i * J.K + w.k) * J.T + t0) * kArmDs : nullptr;
+  const float wx = J.w_x[0];
+  double ll = 0.0;
+  for (int s = 0; s < J.h; ++s) {
+    arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+    if (with_ll) {
+      const float r = (obs[s] - q[7]) * wx;
+      ll -= 0.5 * (double)(r * r);
+    }
+    if (traj)
+      for (int d = 0; d < 8; ++d) { traj[s * kArmDs + d] = q[d]; traj[s * kArmDs + 8 + d] = qd[d]; }
+  }
+  const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
+  float* es = J.end_states + iu * kArmDs;
+  bool bad = false;
+  for (int d = 0; d < 8; ++d) {
+    es[d] = q[d];
+    es[8 + d] = qd[d];
+    bad |= !isfinite(q[d]) || !isfinite(qd[d]);
+  }
+  if (with_ll) {
+    ll += (double)J.h * (log((double)wx) - 0.91893853320467274178);
+    J.ll_win[iu] = ll;
+    if (w.j + 1 < J.n_s) {
+      const float* sn = J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j) * kArmDs;
+      double g = 0.0;
+      for (int d = 0; d < 8; ++d) {
+        const float e0 = (sn[d] - q[d]) * J.u[d];
+        const float e1 = (sn[8 + d] - qd[d]) * J.u[8 + d];
+        g += (double)e0 * e0 + (double)e1 * e1;
+      }
+      J.gdef[((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j] = g / ((double)J.sigma_def * J.sigma_def);
+    }
+    bad |= !isfinite(ll);
+  }
+  if (bad && J.flags) atomicOr(&J.flags[w.i], 1);
+}
+
+__host__ __device__ inline int arm_seg_len(int h) {
+  int B = 1;
+  while (B * B < h) ++B;
+  return B;
+}
+
+// Adjoint kernel: one lane per unit, both adjoint channels; window states in
+// LDS (whole window when `full`, else sqrt(h) checkpoints plus the segment
+// being reversed).
+__global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                            char* ws, int full) {
+  extern __shared__ float lds[];
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const ArmConst& K = *arm_const_of(ws, map.ws_off[e]);
+  const int U = J.N * J.K * J.n_s;
+  const int lane = threadIdx.x;
+  const int u = (blockIdx.x - map.begin[e]) * kWave + lane;
+  if (u >= U) return;
+  const WsLayout L = ws_layout(J);
+  char* base = ws + map.ws_off[e];
+  double* gth_obs = reinterpret_cast<double*>(base + L.gth_obs);
+  double* gth_con = reinterpret_cast<double*>(base + L.gth_con);
+  float* gs_obs = reinterpret_cast<float*>(base + L.gs_obs);
+  float* gs_con = reinterpret_cast<float*>(base + L.gs_con);
+  const AUnit w = aunit_of(J, u);
+  float th[4];
+  for (int m = 0; m < 4; ++m) th[m] = J.theta[(size_t)w.i * 4 + m];
+  const float* st = astart_ptr(J, w);
+  float q[8], qd[8];
+  for (int d = 0; d < 8; ++d) { q[d] = st[d]; qd[d] = st[8 + d]; }
+  const float dt = J.dt;
+  const int h = J.h;
+  const int B = full ? h : arm_seg_len(h);
+  const int nseg = (h + B - 1) / B;
+  const int segbase = full ? 0 : nseg;
+  const int t0 = w.j * h;
+  const float* obs = J.obs + ((size_t)w.k * J.T + t0);
+  const float wx = J.w_x[0];
+  auto slot = [&](int s, int d) -> float& { return lds[((size_t)s * kArmDs + d) * kWave + lane]; };
+
+  double ll = 0.0;
+  for (int s = 0; s < h; ++s) {
+    if (full || s % B == 0) {
+      const int sl = full ? s : s / B;
+      for (int d = 0; d < 8; ++d) { slot(sl, d) = q[d]; slot(sl, 8 + d) = qd[d]; }
+    }
+    arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+    const float r = (obs[s] - q[7]) * wx;
+    ll -= 0.5 * (double)(r * r);
+  }
+  if (full)
+    for (int d = 0; d < 8; ++d) { slot(h, d) = q[d]; slot(h, 8 + d) = qd[d]; }
+  ll += (double)h * (log((double)wx) - 0.91893853320467274178);
+  const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
+  float* es = J.end_states + iu * kArmDs;
+  bool bad = !isfinite(ll);
+  for (int d = 0; d < 8; ++d) {
+    es[d] = q[d];
+    es[8 + d] = qd[d];
+    bad |= !isfinite(q[d]) || !isfinite(qd[d]);
+  }
+  J.ll_win[iu] = ll;
+
+  float qb_o[8], qdb_o[8], qb_c[8], qdb_c[8];
+  for (int d = 0; d < 8; ++d) { qb_o[d] = qdb_o[d] = qb_c[d] = qdb_c[d] = 0.f; }
+  if (w.j + 1 < J.n_s) {
+    const size_t id = ((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j;
+    const float* sn = J.S + id * kArmDs;
+    float e0[8], e1[8];
+    double g = 0.0;
+    for (int d = 0; d < 8; ++d) {
+      e0[d] = (sn[d] - q[d]) * J.u[d];
+      e1[d] = (sn[8 + d] - qd[d]) * J.u[8 + d];
+      g += (double)e0[d] * e0[d] + (double)e1[d] * e1[d];
+    }
+    const double inv_s2 = 1.0 / ((double)J.sigma_def * J.sigma_def);
+    g *= inv_s2;
+    J.gdef[id] = g;
+    const double seed = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
+    const float sc = (float)(-2.0 * seed * inv_s2);
+    for (int d = 0; d < 8; ++d) {
+      qb_c[d] = sc * e0[d] * J.u[d];
+      qdb_c[d] = sc * e1[d] * J.u[8 + d];
+    }
+  }
+  double gm_o[4] = {0.0, 0.0, 0.0, 0.0}, gm_c[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int a = sg * B;
+    const int bnd = min(h, a + B);
+    if (!full) {
+      for (int d = 0; d < 8; ++d) { q[d] = slot(sg, d); qd[d] = slot(sg, 8 + d); }
+      for (int d = 0; d < 8; ++d) { slot(segbase, d) = q[d]; slot(segbase, 8 + d) = qd[d]; }
+      for (int s = a; s < bnd; ++s) {
+        arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+        for (int d = 0; d < 8; ++d) {
+          slot(segbase + s - a + 1, d) = q[d];
+          slot(segbase + s - a + 1, 8 + d) = qd[d];
+        }
+      }
+    }
+    for (int s = bnd - 1; s >= a; --s) {
+      {
+        const float x = slot(segbase + s - a + 1, 7);
+        const float r = (obs[s] - x) * wx;
+        qb_o[7] += r * wx;
+      }
+      float qs[8], qds[8];
+      for (int d = 0; d < 8; ++d) { qs[d] = slot(segbase + s - a, d); qds[d] = slot(segbase + s - a, 8 + d); }
+      ArmTape T;
+      const float time = (float)(t0 + s) * dt;
+      keep_consts_in_memory();
+      arm_aba(K, th, qs, qds, time, T);
+      float tb[4] = {0.f, 0.f, 0.f, 0.f};
+      arm_step_rev(K, th, qs, qds, T, dt, qb_o, qdb_o, tb);
+      for (int m = 0; m < 4; ++m) gm_o[m] += (double)tb[m];
+      float tc[4] = {0.f, 0.f, 0.f, 0.f};
+      arm_step_rev(K, th, qs, qds, T, dt, qb_c, qdb_c, tc);
+      for (int m = 0; m < 4; ++m) gm_c[m] += (double)tc[m];
+    }
+  }
+  for (int m = 0; m < 4; ++m) {
+    gth_obs[(size_t)m * U + u] = gm_o[m];
+    gth_con[(size_t)m * U + u] = gm_c[m];
+    bad |= !isfinite(gm_o[m]) || !isfinite(gm_c[m]);
+  }
+  for (int d = 0; d < 8; ++d) {
+    gs_obs[(size_t)d * U + u] = qb_o[d];
+    gs_obs[(size_t)(8 + d) * U + u] = qdb_o[d];
+    gs_con[(size_t)d * U + u] = qb_c[d];
+    gs_con[(size_t)(8 + d) * U + u] = qdb_c[d];
+  }
+  if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
+}
+
+}  // namespace
+
+static_assert(sizeof(ArmConst) <= kArmConstBytes, "ArmConst must fit its workspace region");
+
+hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(arm_setup_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(arm_forward_kernel, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, with_ll ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool full,
+                              size_t lds_bytes, hipStream_t s) {
+  hipLaunchKernelGGL(arm_adjoint_kernel, dim3(grid), dim3(kWave), lds_bytes, s, map, d_jobs, ws, full ? 1 : 0);
+  return hipGetLastError();
+}
+
+int arm_seg_len_host(int h) { return arm_seg_len(h); }
+
+}  // namespace pds

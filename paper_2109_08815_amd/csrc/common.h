@@ -27,8 +27,13 @@ __device__ inline int map_entry(const JobMap& m, int block) {
   return e;
 }
 
+constexpr size_t kArmConstBytes = 2048;  // derived arm model constants per job
+
 // Workspace layout of one job (byte offsets from the job's region start).
+// The arm model's derived constants come first, so forward-only calls can
+// use a region of just that size.
 struct WsLayout {
+  size_t arm;                               // derived arm constants (arm jobs)
   size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients
   size_t hist;                              // median radix histograms + state
   size_t cand;                              // median candidate keys
@@ -64,6 +69,7 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   const size_t U = (size_t)J.N * J.K * J.n_s;
   const int ds = 2 * J.n_dof;
   size_t o = 0;
+  L.arm = o;     o = align256(o + (J.model == PDS_MODEL_ARM ? kArmConstBytes : 0));
   L.gth_obs = o; o = align256(o + U * J.M * sizeof(double));
   L.gth_con = o; o = align256(o + U * J.M * sizeof(double));
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
@@ -90,6 +96,12 @@ hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* 
 hipError_t launch_median_small(const JobMap& map_keys, int grid_keys, const JobMap& map_sel, int grid_sel,
                                const pds_job* d_jobs, char* ws, int mmax, hipStream_t s);
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
+hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
+hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
+                              hipStream_t s);
+hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool full,
+                              size_t lds_bytes, hipStream_t s);
+int arm_seg_len_host(int h);
 hipError_t launch_hist_clear(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_radix_pass(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int pass, int mmax,
                              hipStream_t s);

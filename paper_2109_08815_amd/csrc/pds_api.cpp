@@ -69,11 +69,17 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     if (!(J.ptr)) return fail(PDS_EINVAL, "job %d: " #ptr " is NULL", idx);                   \
     if (!aligned(J.ptr, al)) return fail(PDS_EINVAL, "job %d: " #ptr " is misaligned", idx);  \
   } while (0)
-  if (J.model == PDS_MODEL_ARM) return fail(PDS_EUNSUPPORTED, "job %d: the arm model is not built in this library", idx);
-  if (J.model != PDS_MODEL_PLANAR) return fail(PDS_EINVAL, "job %d: unknown model %d", idx, J.model);
-  if (J.n_dof < 1 || J.n_dof > 5) return fail(PDS_EUNSUPPORTED, "job %d: planar n_dof %d outside 1..5", idx, J.n_dof);
-  if (J.M != 2 * J.n_dof) return fail(PDS_EINVAL, "job %d: planar model needs M = 2 n_dof (got M=%d)", idx, J.M);
-  if (J.d_x != J.n_dof) return fail(PDS_EINVAL, "job %d: planar model observes q, d_x must be n_dof", idx);
+  if (J.model == PDS_MODEL_ARM) {
+    if (J.n_dof != 8 || J.M != 4 || J.d_x != 1)
+      return fail(PDS_EINVAL, "job %d: the arm model has n_dof = 8, M = 4, d_x = 1", idx);
+  } else if (J.model == PDS_MODEL_PLANAR) {
+    if (J.n_dof < 1 || J.n_dof > 5)
+      return fail(PDS_EUNSUPPORTED, "job %d: planar n_dof %d outside 1..5", idx, J.n_dof);
+    if (J.M != 2 * J.n_dof) return fail(PDS_EINVAL, "job %d: planar model needs M = 2 n_dof (got M=%d)", idx, J.M);
+    if (J.d_x != J.n_dof) return fail(PDS_EINVAL, "job %d: planar model observes q, d_x must be n_dof", idx);
+  } else {
+    return fail(PDS_EINVAL, "job %d: unknown model %d", idx, J.model);
+  }
   if (J.N < 1 || J.K < 1 || J.n_s < 1 || J.h < 1 || J.T != J.n_s * J.h)
     return fail(PDS_EINVAL, "job %d: need N, K, n_s, h >= 1 and T = n_s h (N=%d K=%d T=%d n_s=%d h=%d)", idx, J.N,
                 J.K, J.T, J.n_s, J.h);
@@ -124,7 +130,7 @@ size_t job_ws(const pds_job& J, int which) {
   const WsLayout L = pds::ws_layout(J);
   switch (which) {
     case PDS_CALL_FORWARD:
-    case PDS_CALL_LOGLIK:
+    case PDS_CALL_LOGLIK: return J.model == PDS_MODEL_ARM ? pds::align256(pds::kArmConstBytes) : 0;
     case PDS_CALL_STEP: return 0;
     default: return L.total;
   }
@@ -179,17 +185,44 @@ int launch_rc(hipError_t e, const char* what) {
 
 int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
-int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with_ll, hipStream_t s) {
-  std::vector<uint64_t> off(n, 0);
+int arm_setup_all(const pds_job* h_jobs, const pds_job* d_jobs, int n, const std::vector<uint64_t>& off, char* w,
+                  hipStream_t s) {
+  int grid = 0;
+  JobMap m = make_map(
+      h_jobs, n, off, [](const pds_job& J) { return J.model == PDS_MODEL_ARM; }, [](const pds_job&) { return 1; },
+      &grid);
+  if (m.n == 0) return PDS_OK;
+  return launch_rc(pds::launch_arm_setup(m, d_jobs, w, grid, s), "arm_setup");
+}
+
+int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with_ll, void* ws, size_t ws_bytes,
+                  hipStream_t s) {
+  size_t need = 0;
+  std::vector<uint64_t> off = ws_offsets(h_jobs, n, with_ll ? PDS_CALL_LOGLIK : PDS_CALL_FORWARD, &need);
+  int rc = check_ws(ws, ws_bytes, need);
+  if (rc) return rc;
+  char* w = static_cast<char*>(ws);
+  rc = arm_setup_all(h_jobs, d_jobs, n, off, w, s);
+  if (rc) return rc;
   int slot = -1;
   if (with_ll) timing_begin(s, &slot);
+  {
+    int grid = 0;
+    JobMap m = make_map(
+        h_jobs, n, off, [](const pds_job& J) { return J.model == PDS_MODEL_ARM; },
+        [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
+    if (m.n > 0) {
+      rc = launch_rc(pds::launch_arm_forward(m, d_jobs, w, grid, with_ll, s), "arm_forward");
+      if (rc) return rc;
+    }
+  }
   for (int nb = 1; nb <= 5; ++nb) {
     int grid = 0;
     JobMap m = make_map(
-        h_jobs, n, off, [&](const pds_job& J) { return J.n_dof == nb; },
+        h_jobs, n, off, [&](const pds_job& J) { return J.model == PDS_MODEL_PLANAR && J.n_dof == nb; },
         [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
     if (m.n == 0) continue;
-    int rc = launch_rc(pds::launch_planar_forward(m, nb, d_jobs, grid, with_ll, s), "planar_forward");
+    rc = launch_rc(pds::launch_planar_forward(m, nb, d_jobs, grid, with_ll, s), "planar_forward");
     if (rc) return rc;
   }
   timing_end(s, slot);
@@ -262,19 +295,19 @@ size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which) 
   return best;
 }
 
-int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* /*ws*/,
-                      size_t /*ws_bytes*/, void* stream) {
+int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                      void* stream) {
   int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_FWD);
   if (rc) return rc;
-  return rollout_calls(h_jobs, d_jobs, n_jobs, false, (hipStream_t)stream);
+  return rollout_calls(h_jobs, d_jobs, n_jobs, false, ws, ws_bytes, (hipStream_t)stream);
 }
 
-int loglik_multishoot(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* /*ws*/,
-                      size_t /*ws_bytes*/, void* stream) {
+int loglik_multishoot(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                      void* stream) {
   int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_FWD | NEED_LL);
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
-  rc = rollout_calls(h_jobs, d_jobs, n_jobs, true, s);
+  rc = rollout_calls(h_jobs, d_jobs, n_jobs, true, ws, ws_bytes, s);
   if (rc) return rc;
   return assemble_logp(h_jobs, d_jobs, n_jobs, s);
 }
@@ -289,14 +322,50 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);
+  rc = arm_setup_all(h_jobs, d_jobs, n_jobs, off, w, s);
+  if (rc) return rc;
   int slot = -1;
   timing_begin(s, &slot);
+  {
+    // arm: one lane per unit, both channels; whole window in LDS when every
+    // wave fits at once, else sqrt(h) checkpoints
+    auto pick = [](const pds_job& J) { return J.model == PDS_MODEL_ARM; };
+    long units = 0;
+    int hmax = 0;
+    for (int j = 0; j < n_jobs; ++j)
+      if (pick(h_jobs[j])) {
+        units += (long)h_jobs[j].N * h_jobs[j].K * h_jobs[j].n_s;
+        if (h_jobs[j].h > hmax) hmax = h_jobs[j].h;
+      }
+    if (units > 0) {
+      const size_t per_state = 16 * pds::kWave * sizeof(float);
+      const size_t full_lds = (size_t)(hmax + 1) * per_state;
+      const long waves = div_up(units, pds::kWave);
+      const long resident_full = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
+      const bool full = waves <= resident_full;
+      int grid = 0;
+      size_t lds = 0;
+      JobMap m = make_map(
+          h_jobs, n_jobs, off, pick,
+          [&](const pds_job& J) {
+            const int B = full ? J.h : pds::arm_seg_len_host(J.h);
+            const int nseg = div_up(J.h, B);
+            const size_t b = full ? (size_t)(J.h + 1) * per_state : (size_t)(nseg + B + 1) * per_state;
+            if (b > lds) lds = b;
+            return div_up((long)J.N * J.K * J.n_s, pds::kWave);
+          },
+          &grid);
+      if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "arm window of h steps needs %zu bytes of LDS", lds);
+      rc = launch_rc(pds::launch_arm_adjoint(m, d_jobs, w, grid, full, lds, s), "arm_adjoint");
+      if (rc) return rc;
+    }
+  }
   for (int nb = 1; nb <= 5; ++nb) {
     // Launch shape: with few waves (less than one per SIMD) the two adjoint
     // channels go to two lanes per unit and, if LDS allows every wave to be
     // resident, whole windows stay in LDS; otherwise one lane per unit and
     // sqrt(h) checkpointing.
-    auto pick = [&](const pds_job& J) { return J.n_dof == nb; };
+    auto pick = [&](const pds_job& J) { return J.model == PDS_MODEL_PLANAR && J.n_dof == nb; };
     long units = 0;
     int hmax = 0;
     for (int j = 0; j < n_jobs; ++j)

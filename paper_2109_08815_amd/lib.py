@@ -101,6 +101,21 @@ def _dev(a, dtype, device):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device)
 
 
+def model_consts(pb):
+    """(model kind, raw constants array) in the layout pds.h documents."""
+    if pb.kind == 1:
+        return PDS_MODEL_PLANAR, np.concatenate([pb.gravity[:2], pb.damping[: pb.n_dof]])
+    if pb.kind == 2:
+        a = pb.arm
+        out = list(pb.gravity)
+        for i in range(7):
+            out += [a["dh_a"][i], a["dh_alpha"][i], a["dh_d"][i], a["link_m"][i], *a["link_c"][i], *a["link_I"][i],
+                    a["kp"][i], a["kd"][i], a["qc"][i], a["amp"][i], a["omega"][i], a["phase"][i]]
+        out += [a["flange_d"], pb.damping[7], a["box_m"], *a["box_c"], *a["box_I"], a["pm_m"], a["pm_z"]]
+        return PDS_MODEL_ARM, np.asarray(out, dtype=np.float64)
+    raise PdsError("no GPU model for problem kind %d" % pb.kind)
+
+
 class Job:
     """Device buffers and the pds_job struct of one inference problem."""
 
@@ -115,12 +130,7 @@ class Job:
             theta = pb.particles
         N = theta.shape[0]
         self.N = N
-        if pb.kind == 1:
-            self.model = PDS_MODEL_PLANAR
-            consts = np.concatenate([pb.gravity[:2], pb.damping[: pb.n_dof]])
-        else:
-            self.model = PDS_MODEL_ARM
-            consts = np.zeros(1)
+        self.model, consts = model_consts(pb)
         self.consts = _dev(consts, f32, dev)
         self.lo, self.hi, self.rho = (_dev(pb.lo, f32, dev), _dev(pb.hi, f32, dev), _dev(pb.rho, f32, dev))
         self.w_x, self.u = _dev(pb.w_x, f32, dev), _dev(pb.u, f32, dev)

@@ -363,3 +363,32 @@ def test_autograd_function_matches_oracle(orc):
              + np.linalg.norm(ref["dcon_dtheta_unit"], axis=3).sum(axis=(1, 2)))
     assert np.all(np.linalg.norm(np64(th.grad) - gt, axis=1) <= 1e-3 * scale)
     assert normwise(np64(S.grad), ref["S_dot"]).max() <= 1e-3
+
+
+ARM_CASES = [
+    dict(N=70, K=1, T=100, n_s=2),      # two windows of 50 steps at dt = 1/240
+    dict(N=33, K=2, T=60, n_s=3),       # two trajectories, short windows (whole window in LDS)
+]
+
+
+@pytest.mark.parametrize("over", ARM_CASES)
+def test_arm_forward_states_and_loglik(orc, over):
+    pb, obs, st, job, b = make_case(orc, "c4", perturb_S=0.005, lam=True, with_traj=True, **over)
+    L.loglik_multishoot(b)
+    L.sim_batch_forward(b)
+    ref = orc.forward(pb, obs, st, traj=True)
+    check_states(pb, np64(job.traj), ref["traj"])
+    tol = ll_tolerance(pb, obs, ref["traj"], ref["ll_win"])
+    d = np.abs(np64(job.ll_win) - ref["ll_win"])
+    assert np.all(d <= tol), "ll_win worst ratio %.3g" % (d / tol).max()
+
+
+@pytest.mark.parametrize("over", ARM_CASES)
+def test_arm_adjoint_gradients(orc, over):
+    pb, obs, st, job, b = make_case(orc, "c4", perturb_S=0.005, lam=True, **over)
+    L.sim_batch_adjoint(b)
+    ref = orc.gradient(pb, obs, st, per_unit=True)
+    assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
+    assert grad_err(np64(job.g_con), ref, "con").max() <= 1e-3
+    assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
+    assert np.all(np64(job.flags) == 0)
