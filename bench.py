@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-graph", action="store_true", help="plain launches instead of graph replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -176,10 +176,14 @@ def main():
     steps_per_iter = pb.N * pb.K * pb.T
     value = steps_per_iter * args.steps / elapsed
 
-    fwd, rev, transc = L.algorithmic_flops(L.PDS_MODEL_PLANAR, pb.n_dof)
-    flops_per_launch = steps_per_iter * (fwd + 2 * rev)
     k_ms = float(np.mean(kt)) if len(kt) else float("nan")
-    achieved = flops_per_launch / (k_ms / 1e3) / 1e12
+    if pb.kind == 1:
+        fwd, rev, transc = L.algorithmic_flops(L.PDS_MODEL_PLANAR, pb.n_dof)
+        per_step = fwd + 2 * rev
+        achieved = steps_per_iter * per_step / (k_ms / 1e3) / 1e12
+    else:  # no algorithmic FLOP count for the arm model yet
+        per_step = None
+        achieved = None
     finite = bool(torch.isfinite(job.theta).all().item())
     out = {
         "metric": "particle-sim-steps/s (fwd+adjoint)",
@@ -195,7 +199,8 @@ def main():
         "dtype": "f32 (f64 accumulation and median)",
         "data": "synthetic",
         "config": {"workload": "%s: %s N=%d M=%d K=%d T=%d dt=%g n_s=%d" % (
-            args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain"}[args.config],
+            args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain",
+                          "c4": "7-joint arm with hinged box"}[args.config],
             pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain"},
         "iters_per_s": args.steps / elapsed,
         "roofline": {
@@ -203,11 +208,11 @@ def main():
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
+            "frac": None if achieved is None else achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(args.config),
-            "kernel": "planar_adjoint_kernel<%d>" % pb.n_dof,
+            "kernel": ("planar_adjoint_kernel<%d>" % pb.n_dof) if pb.kind == 1 else "arm_adjoint_kernel",
             "kernel_ms": k_ms,
-            "flops_per_particle_step": fwd + 2 * rev,
+            "flops_per_particle_step": per_step,
         },
         "finite": finite,
     }

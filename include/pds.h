@@ -62,6 +62,7 @@ extern "C" {
 #define PDS_MAX_JOBS 64
 #define PDS_MAX_M 16
 #define PDS_MAX_DOF 8
+#define PDS_MAX_N 32768  /* particles per job */
 
 /* Models.  PLANAR: chain of n_dof (1..5) revolute joints about z, link i a
  * massless rod of length l_i with a point mass m_i at its tip, q = 0 hanging
@@ -103,7 +104,7 @@ typedef struct pds_job {
   int32_t n_dof;
   int32_t M;          /* 1..PDS_MAX_M */
   int32_t d_x;
-  int32_t N;          /* particles, >= 1 */
+  int32_t N;          /* particles, 1..PDS_MAX_N */
   int32_t K;          /* trajectories, >= 1 */
   int32_t T;          /* steps per trajectory, T = n_s * h */
   int32_t n_s;        /* shooting windows, >= 1 */
@@ -180,7 +181,8 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
  * h = med^2 / log N (Sec. III-A), med the exact FP64 median of the
  * N (N - 1) / 2 scaled pair distances (mean of the two middle values for an
  * even count; h = 1 for N = 1).  Uses g_obs as the score.  Writes bandwidth
- * and phi. */
+ * and phi.  The workspace holds, per job, the selection state, one 8-byte
+ * slot per pair when N (N - 1) / 2 > 16384, and the phi partial sums. */
 int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
              void* stream);
 
@@ -197,6 +199,13 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
 /* Workspace bytes the call `which` (PDS_CALL_*) needs for this batch;
  * PDS_CALL_ALL gives the maximum over all calls.  0 on invalid input (see
  * pds_last_error). */
+/* Testing aid: moves the sampled median bracket of later svgd_phi calls by
+ * `ranks` sample positions (default 0), so tests can make it miss the
+ * middle ranks and exercise the exact recovery pass.  The bandwidth stays
+ * exact for every value; only the time changes.  Process-wide, not
+ * synchronised with calls in flight.  PDS_EINVAL if |ranks| > 1e6. */
+int pds_test_median_shift(int32_t ranks);
+
 size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which);
 
 /* Message for the last error on this thread ("" if none). */

@@ -29,38 +29,35 @@ __device__ inline int map_entry(const JobMap& m, int block) {
 
 constexpr size_t kArmConstBytes = 2048;  // derived arm model constants per job
 
+// Bandwidth median (see svgd.hip).  Up to kSmallPairs pairs one block
+// selects exactly; above, a sampled bracket plus a counting pass.
+constexpr int kSmallPairs = 32768;
+constexpr int kSampleKeys = 32768;
+constexpr int kMedThreads = 1024;
+constexpr int kSelBins = 2048;       // bins per selection level (2^11)
+constexpr int kMaxLevels = 8;        // selection levels never exceed 6
+constexpr int kCountTile = 64;       // pairs per count block: 64 x 64
+constexpr int kLastCap = 4096;       // keys the count kernel's last block holds in LDS
+
+struct MedianState {
+  uint64_t a, b;    // bracket keys from the sample
+  uint64_t packed;  // (keys inside [a, b] << 32) | keys below a, over all count blocks
+};
+
 // Workspace layout of one job (byte offsets from the job's region start).
 // The arm model's derived constants come first, so forward-only calls can
 // use a region of just that size.
 struct WsLayout {
   size_t arm;                               // derived arm constants (arm jobs)
   size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients
-  size_t hist;                              // median radix histograms + state
-  size_t cand;                              // median candidate keys
-  size_t keys;                              // materialised pair keys (small problems)
+  size_t med;                               // median selection state
+  size_t khi, klo;                          // median key words (all pairs, or a sample's high words)
+  size_t cand;                              // median candidate keys (one slot per pair)
   size_t phi_part;                          // phi partial sums
   size_t total;
 };
 
 constexpr int kPhiChunk = 32;    // particles j per phi partial
-constexpr int kRadixPasses = 8;  // 8-bit digits of a 64-bit key
-constexpr int kRadixJT = 16;     // particles j per radix-pass block (64 i per block)
-
-// Selection state of the bandwidth median, carried between radix passes.
-constexpr int kCandCap = 8192;   // keys the compaction pass may collect
-// Up to this many pairs the median is one materialising kernel plus one
-// single-block selection; above it, multi-block radix passes.
-constexpr int kSmallPairs = 1 << 19;
-
-struct RadixState {
-  uint64_t pre[2];   // key prefix fixed so far, for both middle ranks
-  uint64_t rem[2];   // rank among keys sharing that prefix
-  uint32_t count[kRadixPasses];  // blocks finished per pass
-  uint32_t done;        // selection finished
-  uint32_t compact_at;  // 1 + pass that collects candidates, 0 = none yet
-  uint32_t ncand;       // candidates collected
-  uint32_t pad[kRadixPasses - 3];
-};
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -74,10 +71,12 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   L.gth_con = o; o = align256(o + U * J.M * sizeof(double));
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
   L.gs_con = o;  o = align256(o + U * ds * sizeof(float));
-  L.hist = o;    o = align256(o + (size_t)kRadixPasses * 2 * 256 * sizeof(uint32_t) + sizeof(RadixState));
-  L.cand = o;    o = align256(o + (size_t)kCandCap * sizeof(uint64_t));
+  L.med = o;     o = align256(o + sizeof(MedianState));
   const size_t P = (size_t)J.N * (J.N - 1) / 2;
-  L.keys = o;    o = align256(o + (P <= (size_t)kSmallPairs ? P : 0) * sizeof(uint64_t));
+  const bool large = P > (size_t)kSmallPairs;
+  L.khi = o;     o = align256(o + (large ? (size_t)kSampleKeys : P) * sizeof(uint32_t));
+  L.klo = o;     o = align256(o + (large ? 0 : P) * sizeof(uint32_t));
+  L.cand = o;    o = align256(o + (large ? P : 0) * sizeof(uint64_t));
   const size_t chunks = ((size_t)J.N + kPhiChunk - 1) / kPhiChunk;
   L.phi_part = o; o = align256(o + chunks * (size_t)J.N * J.M * sizeof(float));
   L.total = o;
@@ -93,8 +92,12 @@ hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* ws, i
                            hipStream_t s);
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_median_small(const JobMap& map_keys, int grid_keys, const JobMap& map_sel, int grid_sel,
-                               const pds_job* d_jobs, char* ws, int mmax, hipStream_t s);
+struct MedianMaps {
+  JobMap keys, select, count, large;
+  int grid_keys, grid_select, grid_count, grid_large;
+};
+hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, int mmax, int rank_shift,
+                         hipStream_t s);
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
 hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
@@ -102,9 +105,6 @@ hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws
 hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool full,
                               size_t lds_bytes, hipStream_t s);
 int arm_seg_len_host(int h);
-hipError_t launch_hist_clear(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_radix_pass(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int pass, int mmax,
-                             hipStream_t s);
 hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
                               hipStream_t s);
 hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);

@@ -18,6 +18,8 @@ int planar_seg_len(int h);
 namespace {
 
 thread_local std::string g_err;
+// Offset, in sample positions, of the sampled median bracket (tests only).
+int g_median_rank_shift = 0;
 
 int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
@@ -84,8 +86,9 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     return fail(PDS_EINVAL, "job %d: need N, K, n_s, h >= 1 and T = n_s h (N=%d K=%d T=%d n_s=%d h=%d)", idx, J.N,
                 J.K, J.T, J.n_s, J.h);
   const double units = (double)J.N * J.K * J.n_s;
-  if (units > 2.0e9 || (double)J.N * J.K * (J.n_s) * (2 * J.n_dof) > 2.0e9 || (double)J.N * J.N > 4.0e12)
+  if (units > 2.0e9 || (double)J.N * J.K * (J.n_s) * (2 * J.n_dof) > 2.0e9)
     return fail(PDS_EUNSUPPORTED, "job %d: problem too large for 32-bit indexing", idx);
+  if (J.N > PDS_MAX_N) return fail(PDS_EUNSUPPORTED, "job %d: N=%d above %d particles", idx, J.N, PDS_MAX_N);
   if (!(J.dt > 0.f) || !std::isfinite(J.dt)) return fail(PDS_EINVAL, "job %d: dt must be > 0", idx);
   if (!(J.sigma_def > 0.f)) return fail(PDS_EINVAL, "job %d: sigma_def must be > 0", idx);
   if (!(J.c >= 0.f)) return fail(PDS_EINVAL, "job %d: c must be >= 0", idx);
@@ -415,6 +418,12 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   return PDS_OK;
 }
 
+int pds_test_median_shift(int32_t ranks) {
+  if (ranks < -1000000 || ranks > 1000000) return fail(PDS_EINVAL, "rank shift %d out of range", ranks);
+  g_median_rank_shift = ranks;
+  return PDS_OK;
+}
+
 int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
              void* stream) {
   int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_PHI);
@@ -429,44 +438,24 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   int mmax = 1;
   for (int j = 0; j < n_jobs; ++j) mmax = h_jobs[j].M > mmax ? h_jobs[j].M : mmax;
   auto npairs = [](const pds_job& J) { return (long)J.N * (J.N - 1) / 2; };
-  // small pair counts: materialised keys + one selecting block per job
-  int kgrid = 0, sgrid1 = 0;
-  JobMap mk = make_map(
-      h_jobs, n_jobs, off, [&](const pds_job& J) { return J.N > 1 && npairs(J) <= pds::kSmallPairs; },
-      [&](const pds_job& J) { return div_up(npairs(J), 256); }, &kgrid);
-  JobMap ms1 = make_map(
-      h_jobs, n_jobs, off, [&](const pds_job& J) { return J.N > 1 && npairs(J) <= pds::kSmallPairs; },
-      [](const pds_job&) { return 1; }, &sgrid1);
-  if (mk.n > 0) {
-    rc = launch_rc(pds::launch_median_small(mk, kgrid, ms1, sgrid1, d_jobs, w, mmax, s), "median_small");
-    if (rc) return rc;
-  }
-  // large pair counts: multi-block radix passes
-  int grid = 0;
-  JobMap m1 = make_map(
-      h_jobs, n_jobs, off, [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; },
-      [](const pds_job&) { return 1; }, &grid);
-  if (m1.n > 0) {
-    rc = launch_rc(pds::launch_hist_clear(m1, d_jobs, w, grid, s), "hist_clear");
-    if (rc) return rc;
-  }
-  int rgrid0 = 0;
-  JobMap mrad = make_map(
-      h_jobs, n_jobs, off, [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; },
-      [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kRadixJT); }, &rgrid0);
-  if (mrad.n > 0) {
-    for (int p = 0; p < pds::kRadixPasses; ++p) {
-      rc = launch_rc(pds::launch_radix_pass(mrad, d_jobs, w, rgrid0, p, mmax, s), "radix_pass");
-      if (rc) return rc;
-    }
-  }
-  int sgrid = 0;
-  JobMap msingle = make_map(
-      h_jobs, n_jobs, off, [](const pds_job& J) { return J.N == 1; }, [](const pds_job&) { return 1; }, &sgrid);
-  if (msingle.n > 0) {
-    rc = launch_rc(pds::launch_radix_pass(msingle, d_jobs, w, sgrid, pds::kRadixPasses, mmax, s), "bandwidth");
-    if (rc) return rc;
-  }
+  // bandwidth: keys (or a sample of them), one selecting block per job,
+  // then the count and final kernels for jobs above kSmallPairs pairs
+  auto large = [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; };
+  pds::MedianMaps mm;
+  mm.keys = make_map(
+      h_jobs, n_jobs, off, all,
+      [&](const pds_job& J) { return div_up(large(J) ? pds::kSampleKeys : npairs(J), 256); }, &mm.grid_keys);
+  mm.select = make_map(h_jobs, n_jobs, off, all, [](const pds_job&) { return 1; }, &mm.grid_select);
+  mm.count = make_map(
+      h_jobs, n_jobs, off, large,
+      [](const pds_job& J) {
+        const long nb = div_up(J.N, pds::kCountTile);
+        return nb * (nb + 1) / 2;
+      },
+      &mm.grid_count);
+  mm.large = make_map(h_jobs, n_jobs, off, large, [](const pds_job&) { return 1; }, &mm.grid_large);
+  rc = launch_rc(pds::launch_median(mm, d_jobs, w, mmax, g_median_rank_shift, s), "median");
+  if (rc) return rc;
   int pgrid = 0;
   JobMap mp = make_map(
       h_jobs, n_jobs, off, all,

@@ -4,16 +4,21 @@
 // Bandwidth.  h = med^2 / log N with med the exact median of the N (N-1)/2
 // pair distances ||(theta_i - theta_j) / rho||, computed in FP64 from the
 // FP32 particles.  A non-negative IEEE double orders like its bit pattern
-// read as uint64, so the median is found by an exact most-significant-digit
-// radix select over the 64-bit patterns of the squared distances: eight
-// passes of 8 bits, each a per-block LDS histogram (wave-aggregated
-// increments) of the keys that still match the prefix fixed by earlier
-// passes, summed into a global histogram with integer atomics
-// (order-independent, hence deterministic).  The last block of a pass to
-// finish fixes that pass's digit, so the next pass only reads the carried
-// prefix.  Every pass recomputes the distances instead of storing the
-// N^2/2 keys.  Both middle order statistics ((P-1)/2 and P/2 of P pairs) are
-// selected at once.
+// read as uint64, so selection works on the 64-bit patterns ("keys") of
+// the squared distances, and both middle order statistics ((P-1)/2 and P/2
+// of P pairs) are found together.  Two kernels:
+//  * bracket: one block per job.  Up to 16384 pairs it holds every key in
+//    LDS and selects exactly.  Otherwise it selects two order statistics of
+//    a fixed pseudo-random sample of 16384 keys that bracket the middle
+//    ranks with a margin of four binomial standard deviations.
+//  * count: every pair once, 32 x 32 pairs per block; keys below the
+//    bracket are counted and keys inside it appended to a candidate array;
+//    the last block selects exactly among the candidates (or, if the
+//    bracket missed, among all keys of the side that holds the ranks).
+// Selection narrows a key interval per rank by 2^11-bin histograms of
+// (key - lo) >> sh, so it needs at most seven passes over the keys it
+// holds whatever the distribution; counts are integers, so the result does
+// not depend on the order in which blocks finish.
 //
 // phi.  Blocks of 64 particles i against chunks of 128 particles j staged
 // in LDS; FP32 partial sums per chunk, reduced in chunk order.
@@ -26,26 +31,15 @@ namespace {
 
 constexpr int kPairBlock = 64;  // particles i per block
 
-__device__ inline uint32_t* hist_of(const pds_job& J, char* ws, uint64_t off) {
+__device__ inline MedianState* med_state(const pds_job& J, char* ws, uint64_t off) {
   const WsLayout L = ws_layout(J);
-  return reinterpret_cast<uint32_t*>(ws + off + L.hist);
-}
-
-__device__ inline RadixState* state_of(uint32_t* hist) {
-  return reinterpret_cast<RadixState*>(hist + kRadixPasses * 2 * 256);
-}
-
-__global__ void __launch_bounds__(256) hist_clear_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                         char* __restrict__ ws) {
-  const int e = map_entry(map, blockIdx.x);
-  const pds_job& J = jobs[map.job[e]];
-  uint32_t* hist = hist_of(J, ws, map.ws_off[e]);
-  const int n = kRadixPasses * 2 * 256 + (int)(sizeof(RadixState) / sizeof(uint32_t));
-  for (int t = threadIdx.x; t < n; t += 256) hist[t] = 0u;
+  return reinterpret_cast<MedianState*>(ws + off + L.med);
 }
 
 // Squared scaled distance in FP64, summed in parameter order.  MM is a
-// compile-time bound on M so per-lane arrays stay in registers.
+// compile-time bound on M so per-lane arrays stay in registers.  Every
+// kernel that forms keys calls this with the smaller particle index first,
+// so a pair's key is the same bit pattern wherever it is computed.
 template <int MM>
 __device__ inline double pair_d2(const float* ti, const float* tj, const double* inv_rho, int M) {
   double s = 0.0;
@@ -59,6 +53,22 @@ __device__ inline double pair_d2(const float* ti, const float* tj, const double*
   return s;
 }
 
+__device__ inline uint64_t key_of(double d2) { return (uint64_t)__double_as_longlong(d2); }
+
+template <int MM>
+__device__ inline void load_row(const pds_job& J, int i, float* t) {
+#pragma unroll
+  for (int m = 0; m < MM; ++m) t[m] = m < J.M ? J.theta[(size_t)i * J.M + m] : 0.f;
+}
+
+template <int MM>
+__device__ inline uint64_t pair_key(const pds_job& J, int i, int j, const double* inv_rho) {
+  float ti[MM], tj[MM];
+  load_row<MM>(J, i, ti);
+  load_row<MM>(J, j, tj);
+  return key_of(pair_d2<MM>(ti, tj, inv_rho, J.M));
+}
+
 // Inclusive scan over the 64 lanes of a wave (fixed order of additions).
 __device__ inline uint32_t wave_scan(uint32_t v) {
 #pragma unroll
@@ -69,57 +79,258 @@ __device__ inline uint32_t wave_scan(uint32_t v) {
   return v;
 }
 
-// Adds one count per valid lane to lh[bin]; the most common bin of the wave
-// (the first valid lane's) is added once with the wave's tally.
-__device__ inline void wave_hist_add(uint32_t* lh, bool valid, int bin) {
-  const unsigned long long m = __ballot(valid);
-  if (m == 0ull) return;
-  const int leader = __ffsll((long long)m) - 1;
-  const int lbin = __shfl(bin, leader);
-  const bool same = valid && bin == lbin;
-  const unsigned long long sm = __ballot(same);
-  if ((int)(threadIdx.x & 63) == leader) atomicAdd(&lh[lbin], (uint32_t)__popcll(sm));
-  if (valid && !same) atomicAdd(&lh[bin], 1u);
+__device__ inline int bit_len(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
+__device__ inline int bit_len(uint64_t x) { return x ? 64 - __clzll((long long)x) : 0; }
+
+// ---------------------------------------------------------------------------
+// Block-wide exact selection of two ranks among unsigned keys (32- or
+// 64-bit).  A target is a key interval [lo, hi] known to hold the wanted
+// key and that key's rank among the current keys inside the interval.
+// ---------------------------------------------------------------------------
+
+template <class KT>
+struct SelTarget {
+  KT lo, hi;
+  uint32_t t;
+};
+
+template <class KT>
+struct SelShared {
+  SelTarget<KT> tg[2];
+  uint32_t cnt[2];  // keys inside each target's interval after a level
+  uint32_t hist[2][kSelBins];
+  uint32_t wsum[16];
+  KT red[2][16];
+};
+
+// Exclusive prefix of v over the block's threads and the block total.
+template <int NT, class SS>
+__device__ inline uint32_t block_scan(uint32_t v, SS& S, uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_scan(v);
+  if (lane == 63) S.wsum[w] = inc;
+  __syncthreads();
+  uint32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) {
+    const uint32_t s = S.wsum[k];
+    base += k < w ? s : 0u;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + inc - v;
 }
 
-// Exact selection among the collected candidate keys, by the remaining
-// radix digits (from `pass` on), in one 64-lane block.
-__device__ void finish_from_candidates(const uint64_t* cand, uint32_t n, int pass, uint64_t pre[2],
-                                       uint64_t rem[2], uint32_t (*lh)[256]) {
-  for (int q = pass; q < kRadixPasses; ++q) {
-    for (int t = threadIdx.x; t < 512; t += 64) lh[t >> 8][t & 255] = 0u;
-    __syncthreads();
-    const int shift = 56 - 8 * q;
-    for (uint32_t c = threadIdx.x; c < n; c += 64) {
-      const uint64_t key = cand[c];
-      const int bin = (int)((key >> shift) & 255u);
-      const bool m0 = q == 0 || (key >> (64 - 8 * q)) == (pre[0] >> (64 - 8 * q));
-      const bool m1 = q == 0 || (key >> (64 - 8 * q)) == (pre[1] >> (64 - 8 * q));
-      if (m0) atomicAdd(&lh[0][bin], 1u);
-      if (m1) atomicAdd(&lh[1][bin], 1u);
-    }
-    __syncthreads();
-    for (int tg = 0; tg < 2; ++tg) {
-      const int l = threadIdx.x;
-      const uint32_t c0 = lh[tg][4 * l], c1 = lh[tg][4 * l + 1], c2 = lh[tg][4 * l + 2], c3 = lh[tg][4 * l + 3];
-      const uint32_t incl = wave_scan(c0 + c1 + c2 + c3);
-      const uint32_t excl = incl - (c0 + c1 + c2 + c3);
-      const uint64_t r = rem[tg];
-      const bool own = (uint64_t)excl <= r && r < (uint64_t)incl;
-      const unsigned long long bal = __ballot(own);
-      const int owner = bal ? __ffsll((long long)bal) - 1 : 63;
-      int b = 4 * l;
-      uint64_t rr = r - excl;
-      if (rr >= c0) { rr -= c0; ++b;
-        if (rr >= c1) { rr -= c1; ++b;
-          if (rr >= c2) { rr -= c2; ++b; } } }
-      const int bo = __shfl(b, owner);
-      const uint64_t ro = __shfl((long long)rr, owner);
-      pre[tg] |= (uint64_t)bo << shift;
-      rem[tg] = ro;
-    }
-    __syncthreads();
+template <int NT, class KT>
+__device__ inline void block_minmax(KT mn, KT mx, SelShared<KT>& S, KT* out_min, KT* out_max) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const KT a = (KT)__shfl_xor((unsigned long long)mn, o);
+    const KT b = (KT)__shfl_xor((unsigned long long)mx, o);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
   }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    S.red[0][w] = mn;
+    S.red[1][w] = mx;
+  }
+  __syncthreads();
+  mn = S.red[0][0];
+  mx = S.red[1][0];
+#pragma unroll
+  for (int k = 1; k < NT / 64; ++k) {
+    mn = S.red[0][k] < mn ? S.red[0][k] : mn;
+    mx = S.red[1][k] > mx ? S.red[1][k] : mx;
+  }
+  __syncthreads();
+  *out_min = mn;
+  *out_max = mx;
+}
+
+// Bins of one level: (key - lo) >> sh, with sh the smallest shift that puts
+// [lo, hi] into kSelBins = 2^11 bins.
+template <class KT>
+__device__ inline int sel_shift(KT span) {
+  const int bits = bit_len(span);
+  return bits > 11 ? bits - 11 : 0;
+}
+
+// Both targets count into hist[0] while their intervals coincide.
+template <class KT>
+__device__ inline bool sel_shared(const SelTarget<KT>* t, const bool* live) {
+  return live[0] && live[1] && t[0].lo == t[1].lo && t[0].hi == t[1].hi;
+}
+
+template <int NT, class KT>
+__device__ void sel_histogram(const KT* src, uint32_t n, SelShared<KT>& S, const SelTarget<KT>* t, const bool* live,
+                              const int* sh) {
+  for (int i = threadIdx.x; i < 2 * kSelBins; i += NT) (&S.hist[0][0])[i] = 0u;
+  __syncthreads();
+  const bool share = sel_shared(t, live);
+  const bool use1 = live[1] && !share;
+  constexpr int U = 8;
+  for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
+    KT key[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t c = c0 + u * NT + threadIdx.x;
+      key[u] = c < n ? src[c] : (KT)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = c0 + u * NT + threadIdx.x < n;
+      if (ok && live[0] && key[u] >= t[0].lo && key[u] <= t[0].hi)
+        atomicAdd(&S.hist[0][(uint32_t)((key[u] - t[0].lo) >> sh[0])], 1u);
+      if (ok && use1 && key[u] >= t[1].lo && key[u] <= t[1].hi)
+        atomicAdd(&S.hist[1][(uint32_t)((key[u] - t[1].lo) >> sh[1])], 1u);
+    }
+  }
+  __syncthreads();
+}
+
+// Narrows target k to the bin holding its rank: the thread whose bins
+// contain the rank rewrites the target.
+template <int NT, class KT>
+__device__ void sel_narrow(SelShared<KT>& S, int k, int hk, const SelTarget<KT> t, int sh) {
+  constexpr int BPT = kSelBins / NT;
+  const int b0 = threadIdx.x * BPT;
+  uint32_t c[BPT];
+  uint32_t local = 0;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    c[q] = S.hist[hk][b0 + q];
+    local += c[q];
+  }
+  uint32_t total;
+  const uint32_t base = block_scan<NT>(local, S, &total);
+  if (base <= t.t && t.t < base + local) {
+    uint32_t r = t.t - base;
+    int b = -1;
+    uint32_t cb = 0;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      if (b < 0) {
+        if (r < c[q]) {
+          b = b0 + q;
+          cb = c[q];
+        } else {
+          r -= c[q];
+        }
+      }
+    }
+    const KT span = t.hi - t.lo;
+    S.tg[k].lo = t.lo + ((KT)b << sh);
+    S.tg[k].hi = (KT)b == (KT)(span >> sh) ? t.hi : (KT)(t.lo + (((KT)b + 1) << sh) - 1);
+    S.tg[k].t = r;
+    S.cnt[k] = cb;
+  }
+  __syncthreads();
+}
+
+// Copies the keys inside either live target's interval from src to dst
+// (LDS, at most cap keys), in block-scan order.  Returns their number.
+template <int NT, class KT>
+__device__ uint32_t sel_compact(const KT* src, uint32_t n, KT* dst, uint32_t cap, SelShared<KT>& S) {
+  const SelTarget<KT> t0 = S.tg[0], t1 = S.tg[1];
+  const bool l0 = t0.lo != t0.hi, l1 = t1.lo != t1.hi;
+  constexpr int U = 8;
+  uint32_t base = 0;
+  for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
+    KT key[U];
+    bool keep[U];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t c = c0 + u * NT + threadIdx.x;
+      key[u] = c < n ? src[c] : (KT)0;
+      keep[u] = c < n && ((l0 && key[u] >= t0.lo && key[u] <= t0.hi) || (l1 && key[u] >= t1.lo && key[u] <= t1.hi));
+      cnt += keep[u] ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t o = base + block_scan<NT>(cnt, S, &total);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (keep[u]) {
+        if (o < cap) dst[o] = key[u];
+        ++o;
+      }
+    base += total;
+  }
+  __syncthreads();
+  return base < cap ? base : cap;
+}
+
+// Direct finish for n <= NT keys in LDS: the thread holding a key inside
+// a live target's interval counts the keys of that interval below it
+// (equal keys ordered by position); the one whose count is the target's
+// rank holds the answer.  Ends with a barrier.
+template <int NT, class KT>
+__device__ void sel_count_finish(const KT* src, uint32_t n, SelShared<KT>& S) {
+  const SelTarget<KT> t0 = S.tg[0], t1 = S.tg[1];
+  const bool l0 = t0.lo != t0.hi, l1 = t1.lo != t1.hi;
+  __syncthreads();
+  const uint32_t c = threadIdx.x;
+  const KT x = c < n ? src[c] : (KT)0;
+  const bool in0 = c < n && l0 && x >= t0.lo && x <= t0.hi;
+  const bool in1 = c < n && l1 && x >= t1.lo && x <= t1.hi;
+  uint32_t r0 = 0, r1 = 0;
+  for (uint32_t q = 0; q < n; ++q) {
+    const KT y = src[q];
+    const bool before = y < x || (y == x && q < c);
+    r0 += (before && y >= t0.lo && y <= t0.hi) ? 1u : 0u;
+    r1 += (before && y >= t1.lo && y <= t1.hi) ? 1u : 0u;
+  }
+  if (in0 && r0 == t0.t) S.tg[0] = SelTarget<KT>{x, x, 0u};
+  if (in1 && r1 == t1.t) S.tg[1] = SelTarget<KT>{x, x, 0u};
+  __syncthreads();
+}
+
+// Exact keys of both targets among the n keys src[0..n).  Each level
+// histograms the keys inside a live target's interval into 2^11 bins and
+// keeps the bin holding the rank, so an interval of b-bit span shrinks to
+// one below 2^(b-11): 32-bit keys need at most 3 levels, 64-bit keys 6.
+// Keys held in global memory move to `lds` as soon as the keys inside the
+// live intervals fit there; at most NT keys in LDS are finished by direct
+// counting.  On return S.tg[k].lo is the key; S.tg[k].t is its rank among
+// the keys equal to it only when the levels resolved it.
+template <int NT, class KT>
+__device__ void select_keys(const KT* src, uint32_t n, bool src_global, KT* lds, uint32_t lds_cap,
+                            SelShared<KT>& S, KT out[2], bool count_finish = true) {
+  for (int level = 0; level < kMaxLevels; ++level) {
+    SelTarget<KT> t[2] = {S.tg[0], S.tg[1]};
+    bool live[2];
+    int sh[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      live[k] = t[k].lo != t[k].hi;
+      sh[k] = sel_shift<KT>(t[k].hi - t[k].lo);
+    }
+    if (!live[0] && !live[1]) break;
+    if (count_finish && !src_global && n <= (uint32_t)NT) {
+      sel_count_finish<NT>(src, n, S);
+      break;
+    }
+    const bool share = sel_shared(t, live);
+    sel_histogram<NT>(src, n, S, t, live, sh);
+    if (live[0]) sel_narrow<NT>(S, 0, 0, t[0], sh[0]);
+    if (live[1]) sel_narrow<NT>(S, 1, share ? 0 : 1, t[1], sh[1]);
+    if (src_global) {
+      uint64_t need = 0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if (S.tg[k].lo != S.tg[k].hi) need += S.cnt[k];
+      if (need == 0) break;
+      if (need <= lds_cap) {
+        n = sel_compact<NT>(src, n, lds, lds_cap, S);
+        src = lds;
+        src_global = false;
+      }
+    }
+  }
+  out[0] = S.tg[0].lo;
+  out[1] = S.tg[1].lo;
 }
 
 __device__ inline void write_bandwidth(const pds_job& J, uint64_t k0, uint64_t k1) {
@@ -135,156 +346,7 @@ __device__ inline void write_bandwidth(const pds_job& J, uint64_t k0, uint64_t k
   J.bandwidth[0] = h;
 }
 
-// One radix pass.  Block (ib, jc) covers particles i in [64 ib, 64 ib + 64)
-// against j in [16 jc, 16 jc + 16), pairs with i < j only.  The last block
-// of the job to finish fixes the pass's digit for both middle ranks.  Once
-// both ranks lie among at most kCandCap keys, the next pass instead collects
-// those keys and its last block finishes the selection from them; the
-// passes after that return at once.
-template <int MM>
-__global__ void __launch_bounds__(kPairBlock) radix_pass_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                                char* __restrict__ ws, int pass) {
-  __shared__ uint32_t lh[2][256];
-  __shared__ float tj_s[kRadixJT * PDS_MAX_M];
-  __shared__ int last_s;
-  const int e = map_entry(map, blockIdx.x);
-  const pds_job& J = jobs[map.job[e]];
-  uint32_t* hist = hist_of(J, ws, map.ws_off[e]);
-  RadixState* st = state_of(hist);
-  if (st->done) return;
-  const int N = J.N, M = J.M;
-  const int nib = (N + kPairBlock - 1) / kPairBlock;
-  const int local = blockIdx.x - map.begin[e];
-  const int nblocks = map.begin[e + 1] - map.begin[e];
-  const int ib = local % nib, jc = local / nib;
-  const WsLayout L = ws_layout(J);
-  uint64_t* cand = reinterpret_cast<uint64_t*>(ws + map.ws_off[e] + L.cand);
-  const bool compact = st->compact_at == (uint32_t)(pass + 1);
-  const uint64_t P = (uint64_t)N * (N - 1) / 2;
-  uint64_t p0 = 0, p1 = 0;
-  if (pass > 0) {
-    p0 = st->pre[0];
-    p1 = st->pre[1];
-  }
-  for (int t = threadIdx.x; t < 512; t += kPairBlock) lh[t >> 8][t & 255] = 0u;
-  const int j0 = jc * kRadixJT;
-  const int nj = max(0, min(kRadixJT, N - j0));
-  for (int t = threadIdx.x; t < nj * M; t += kPairBlock) tj_s[t] = J.theta[(size_t)j0 * M + t];
-  __syncthreads();
-  const int i = ib * kPairBlock + threadIdx.x;
-  const bool row = i < N;
-  const int lane = threadIdx.x & 63;
-  if (nj > 0 && j0 + nj - 1 > ib * kPairBlock) {  // block touches the upper triangle
-    double inv_rho[MM];
-    float ti[MM];
-#pragma unroll
-    for (int m = 0; m < MM; ++m) {
-      inv_rho[m] = m < M ? 1.0 / (double)J.rho[m] : 0.0;
-      ti[m] = (row && m < M) ? J.theta[(size_t)i * M + m] : 0.f;
-    }
-    const int shift = 56 - 8 * pass;
-    for (int jj = 0; jj < nj; ++jj) {
-      const int j = j0 + jj;
-      const bool valid = row && j > i;
-      const double d2 = pair_d2<MM>(ti, &tj_s[jj * M], inv_rho, M);
-      const uint64_t key = (uint64_t)__double_as_longlong(d2);
-      const int bin = (int)((key >> shift) & 255u);
-      const bool m0 = valid && (pass == 0 || (key >> (64 - 8 * pass)) == (p0 >> (64 - 8 * pass)));
-      const bool m1 = valid && (pass == 0 || (key >> (64 - 8 * pass)) == (p1 >> (64 - 8 * pass)));
-      if (compact) {
-        const bool want = m0 || m1;
-        const unsigned long long bm = __ballot(want);
-        if (bm) {
-          const int leader = __ffsll((long long)bm) - 1;
-          uint32_t base = 0;
-          if (lane == leader) base = atomicAdd(&st->ncand, (uint32_t)__popcll(bm));
-          base = __shfl(base, leader);
-          const uint32_t off = (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
-          if (want && base + off < (uint32_t)kCandCap) cand[base + off] = key;
-        }
-      } else {
-        wave_hist_add(lh[0], m0, bin);
-        wave_hist_add(lh[1], m1, bin);
-      }
-    }
-  }
-  __syncthreads();
-  uint32_t* gh = hist + pass * 2 * 256;
-  if (!compact) {
-    for (int t = threadIdx.x; t < 512; t += kPairBlock) {
-      const uint32_t c = lh[t >> 8][t & 255];
-      if (c) atomicAdd(&gh[t], c);
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last_s = (atomicAdd(&st->count[pass], 1u) == (uint32_t)(nblocks - 1));
-  __syncthreads();
-  if (!last_s) return;
-  __threadfence();
-  // ---- last block ----
-  uint64_t pre[2], rem[2];
-  for (int tg = 0; tg < 2; ++tg) {
-    pre[tg] = pass > 0 ? st->pre[tg] : 0ull;
-    rem[tg] = pass > 0 ? st->rem[tg] : (P == 0 ? 0ull : (tg == 0 ? (P - 1) / 2 : P / 2));
-  }
-  if (compact) {
-    const uint32_t n = min(__hip_atomic_load(&st->ncand, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                           (uint32_t)kCandCap);
-    finish_from_candidates(cand, n, pass, pre, rem, lh);
-    if (threadIdx.x == 0) {
-      write_bandwidth(J, pre[0], pre[1]);
-      st->done = 1u;
-    }
-    return;
-  }
-  for (int t = threadIdx.x; t < 512; t += kPairBlock)
-    lh[t >> 8][t & 255] = __hip_atomic_load(&gh[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  // Each lane owns 4 consecutive bins; a wave scan locates the bin holding
-  // the wanted rank.
-  uint32_t chosen[2];
-  for (int tg = 0; tg < 2; ++tg) {
-    const int l = threadIdx.x;
-    const uint32_t c0 = lh[tg][4 * l], c1 = lh[tg][4 * l + 1], c2 = lh[tg][4 * l + 2], c3 = lh[tg][4 * l + 3];
-    const uint32_t incl = wave_scan(c0 + c1 + c2 + c3);
-    const uint32_t excl = incl - (c0 + c1 + c2 + c3);
-    const uint64_t r = rem[tg];
-    const bool own = (uint64_t)excl <= r && r < (uint64_t)incl;
-    const unsigned long long bal = __ballot(own);
-    const int owner = bal ? __ffsll((long long)bal) - 1 : 63;
-    int b = 4 * l;
-    uint64_t rr = r - excl;
-    if (rr >= c0) { rr -= c0; ++b;
-      if (rr >= c1) { rr -= c1; ++b;
-        if (rr >= c2) { rr -= c2; ++b; } } }
-    const int bo = __shfl(b, owner);
-    const uint64_t ro = __shfl((long long)rr, owner);
-    pre[tg] |= (uint64_t)bo << (56 - 8 * pass);
-    rem[tg] = ro;
-    chosen[tg] = lh[tg][bo];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    st->pre[0] = pre[0];
-    st->rem[0] = rem[0];
-    st->pre[1] = pre[1];
-    st->rem[1] = rem[1];
-    if (pass == kRadixPasses - 1) {
-      write_bandwidth(J, pre[0], pre[1]);
-      st->done = 1u;
-    } else if ((uint64_t)chosen[0] + chosen[1] <= (uint64_t)kCandCap) {
-      st->compact_at = (uint32_t)(pass + 2);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Median for up to kSmallPairs pairs: one kernel writes every pair's key,
-// one 1024-lane block per job selects both middle keys exactly.
-// ---------------------------------------------------------------------------
-
-// Row i of pair p in the row-major enumeration of pairs (i < j).
+// Row i and column j of pair p in the row-major enumeration of pairs i < j.
 __device__ inline void pair_of(uint64_t p, int N, int* pi, int* pj) {
   const double b = 2.0 * N - 1.0;
   int i = (int)floor((b - sqrt(b * b - 8.0 * (double)p)) * 0.5);
@@ -297,136 +359,324 @@ __device__ inline void pair_of(uint64_t p, int N, int* pi, int* pj) {
   *pj = (int)(p - off(i)) + i + 1;
 }
 
+// Tile (bi, bj), bi <= bj, of tile t in the row-major enumeration of the
+// upper triangle (diagonal included) of an nb x nb tile grid.
+__device__ inline void tile_of(int t, int nb, int* pbi, int* pbj) {
+  const double b = 2.0 * nb + 1.0;
+  int r = (int)floor((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+  auto off = [nb](long long q) -> long long { return q * nb - q * (q - 1) / 2; };
+  if (r < 0) r = 0;
+  if (r > nb - 1) r = nb - 1;
+  while (r > 0 && off(r) > t) --r;
+  while (r < nb - 1 && off(r + 1) <= t) ++r;
+  *pbi = r;
+  *pbj = (int)(t - off(r)) + r;
+}
+
+// Sample position k: a fixed 64-bit mix of k scaled onto [0, P).
+__device__ inline uint64_t sample_pair(uint64_t k, uint64_t P) {
+  uint64_t z = k * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return __umul64hi(z, P);
+}
+
+// Keys kernel, 256 pairs per block.  Jobs with at most kSmallPairs pairs:
+// every pair's key, split into high and low 32-bit words.  Larger jobs:
+// the high words of a fixed pseudo-random sample of kSampleKeys keys; their
+// first block also clears the count kernel's counter.
 template <int MM>
 __global__ void __launch_bounds__(256) median_keys_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                           char* __restrict__ ws) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  const int N = J.N, M = J.M;
-  const uint64_t P = (uint64_t)N * (N - 1) / 2;
-  const uint64_t p = (uint64_t)(blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
-  if (p >= P) return;
-  int i, j;
-  pair_of(p, N, &i, &j);
-  double inv_rho[MM];
-  float ti[MM], tj[MM];
-#pragma unroll
-  for (int m = 0; m < MM; ++m) {
-    inv_rho[m] = m < M ? 1.0 / (double)J.rho[m] : 0.0;
-    ti[m] = m < M ? J.theta[(size_t)i * M + m] : 0.f;
-    tj[m] = m < M ? J.theta[(size_t)j * M + m] : 0.f;
-  }
+  const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
+  const bool small = P <= (uint64_t)kSmallPairs;
+  const uint32_t k = (uint32_t)(blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
   const WsLayout L = ws_layout(J);
-  uint64_t* keys = reinterpret_cast<uint64_t*>(ws + map.ws_off[e] + L.keys);
-  keys[p] = (uint64_t)__double_as_longlong(pair_d2<MM>(ti, tj, inv_rho, M));
+  char* base = ws + map.ws_off[e];
+  if (!small && k == 0) med_state(J, ws, map.ws_off[e])->packed = 0ull;
+  if (small && k >= P) return;
+  double inv_rho[MM];
+#pragma unroll
+  for (int m = 0; m < MM; ++m) inv_rho[m] = m < J.M ? 1.0 / (double)J.rho[m] : 0.0;
+  int i, j;
+  pair_of(small ? (uint64_t)k : sample_pair(k, P), J.N, &i, &j);
+  const uint64_t key = pair_key<MM>(J, i, j, inv_rho);
+  reinterpret_cast<uint32_t*>(base + L.khi)[k] = (uint32_t)(key >> 32);
+  if (small) reinterpret_cast<uint32_t*>(base + L.klo)[k] = (uint32_t)key;
 }
 
-constexpr int kSelThreads = 1024;
-
-// Radix digit `q` of both targets from a 2 x 256 LDS histogram; wave 0
-// scans.  Updates pre/rem in LDS.  Returns after a block barrier.
-__device__ inline void select_digit(uint32_t (*lh)[256], int q, uint64_t* pre, uint64_t* rem, uint32_t* chosen) {
-  if (threadIdx.x < 64) {
-    for (int tg = 0; tg < 2; ++tg) {
-      const int l = threadIdx.x;
-      const uint32_t c0 = lh[tg][4 * l], c1 = lh[tg][4 * l + 1], c2 = lh[tg][4 * l + 2], c3 = lh[tg][4 * l + 3];
-      const uint32_t incl = wave_scan(c0 + c1 + c2 + c3);
-      const uint32_t excl = incl - (c0 + c1 + c2 + c3);
-      const uint64_t r = rem[tg];
-      const bool own = (uint64_t)excl <= r && r < (uint64_t)incl;
-      const unsigned long long bal = __ballot(own);
-      const int owner = bal ? __ffsll((long long)bal) - 1 : 63;
-      int b = 4 * l;
-      uint64_t rr = r - excl;
-      if (rr >= c0) { rr -= c0; ++b;
-        if (rr >= c1) { rr -= c1; ++b;
-          if (rr >= c2) { rr -= c2; ++b; } } }
-      const int bo = __shfl(b, owner);
-      const uint64_t ro = __shfl((long long)rr, owner);
-      if (threadIdx.x == 0) {
-        pre[tg] |= (uint64_t)bo << (56 - 8 * q);
-        rem[tg] = ro;
-        chosen[tg] = lh[tg][bo];
-      }
-    }
-  }
-  __syncthreads();
-}
-
-__global__ void __launch_bounds__(kSelThreads) median_select_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                                    char* __restrict__ ws) {
-  __shared__ uint32_t lh[2][256];
-  __shared__ uint64_t cand[kCandCap];
-  __shared__ uint64_t pre[2], rem[2];
-  __shared__ uint32_t chosen[2], ncand;
+// Select kernel, one block per job.  Loads the high words written by the
+// keys kernel into LDS (the first selection level, over [0, 2^32), is
+// histogrammed during the load) and selects two ranks among them: the
+// middle ranks of all pairs for small jobs, which then finish on the low
+// words of the keys sharing the selected high words; for larger jobs the
+// sample's order statistics at the middle ranks' sample positions widened
+// by four binomial standard deviations, stored as the bracket [a, b]
+// (whole high words) for the count kernel.
+__global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                                    char* __restrict__ ws, int rank_shift) {
+  __shared__ uint32_t hs[kSmallPairs];
+  __shared__ SelShared<uint32_t> S;
+  constexpr int NT = kMedThreads;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
+  if (P == 0) {
+    if (threadIdx.x == 0) write_bandwidth(J, 0ull, 0ull);
+    return;
+  }
+  const bool small = P <= (uint64_t)kSmallPairs;
+  const uint32_t n = small ? (uint32_t)P : (uint32_t)kSampleKeys;
   const WsLayout L = ws_layout(J);
-  const uint64_t* keys = reinterpret_cast<const uint64_t*>(ws + map.ws_off[e] + L.keys);
-  if (threadIdx.x == 0) {
-    pre[0] = pre[1] = 0ull;
-    rem[0] = (P - 1) / 2;
-    rem[1] = P / 2;
-    ncand = 0u;
-  }
-  bool in_lds = false;
-  uint32_t n = 0;
-  for (int q = 0; q < kRadixPasses; ++q) {
-    for (int t = threadIdx.x; t < 512; t += kSelThreads) lh[t >> 8][t & 255] = 0u;
-    __syncthreads();
-    const int shift = 56 - 8 * q;
-    const uint64_t p0 = pre[0], p1 = pre[1];
-    const uint64_t lim = in_lds ? (uint64_t)n : P;
-    for (uint64_t c = threadIdx.x; c < lim + ((kSelThreads - lim % kSelThreads) % kSelThreads); c += kSelThreads) {
-      const bool ok = c < lim;
-      const uint64_t key = ok ? (in_lds ? cand[c] : keys[c]) : 0ull;
-      const int bin = (int)((key >> shift) & 255u);
-      const bool m0 = ok && (q == 0 || (key >> (64 - 8 * q)) == (p0 >> (64 - 8 * q)));
-      const bool m1 = ok && (q == 0 || (key >> (64 - 8 * q)) == (p1 >> (64 - 8 * q)));
-      wave_hist_add(lh[0], m0, bin);
-      wave_hist_add(lh[1], m1, bin);
+  char* base = ws + map.ws_off[e];
+  const uint32_t* khi = reinterpret_cast<const uint32_t*>(base + L.khi);
+  for (int t = threadIdx.x; t < kSelBins; t += NT) S.hist[0][t] = 0u;
+  __syncthreads();
+  constexpr int kFirstShift = 21;  // 2^32 span -> 2^11 bins
+  constexpr int U = 8;
+  for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
+    uint32_t h[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t c = c0 + u * NT + threadIdx.x;
+      h[u] = c < n ? khi[c] : 0u;
     }
-    __syncthreads();
-    select_digit(lh, q, pre, rem, chosen);
-    // compact the surviving keys into LDS once they fit
-    if (!in_lds && q + 1 < kRadixPasses && (uint64_t)chosen[0] + chosen[1] <= (uint64_t)kCandCap) {
-      const int qs = 8 * (q + 1);
-      const uint64_t a0 = pre[0], a1 = pre[1];
-      for (uint64_t c = threadIdx.x; c < P; c += kSelThreads) {
-        const uint64_t key = keys[c];
-        if ((key >> (64 - qs)) == (a0 >> (64 - qs)) || (key >> (64 - qs)) == (a1 >> (64 - qs))) {
-          const uint32_t slot = atomicAdd(&ncand, 1u);
-          cand[slot] = key;
-        }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t c = c0 + u * NT + threadIdx.x;
+      if (c < n) {
+        hs[c] = h[u];
+        atomicAdd(&S.hist[0][h[u] >> kFirstShift], 1u);
       }
-      __syncthreads();
-      n = ncand;
-      in_lds = true;
     }
   }
-  if (threadIdx.x == 0) write_bandwidth(J, pre[0], pre[1]);
+  uint32_t t0, t1;
+  bool a_open = false, b_open = false;
+  if (small) {
+    t0 = (uint32_t)((P - 1) / 2);
+    t1 = (uint32_t)(P / 2);
+  } else {
+    const double d = 2.0 * sqrt((double)n) + 2.0;
+    const double c0 = (double)n * (double)((P - 1) / 2) / (double)P - d + rank_shift;
+    const double c1 = (double)n * (double)(P / 2 + 1) / (double)P + d + rank_shift;
+    a_open = c0 < 0.0;
+    b_open = c1 > (double)(n - 1);
+    t0 = a_open ? 0u : (uint32_t)fmin(floor(c0), (double)(n - 1));
+    t1 = b_open ? n - 1 : (uint32_t)fmax(ceil(c1), 0.0);
+  }
+  __syncthreads();
+  const SelTarget<uint32_t> full0{0u, ~0u, t0}, full1{0u, ~0u, t1};
+  sel_narrow<NT>(S, 0, 0, full0, kFirstShift);
+  sel_narrow<NT>(S, 1, 0, full1, kFirstShift);
+  uint32_t hsel[2];
+  select_keys<NT>(hs, n, false, (uint32_t*)nullptr, 0u, S, hsel, false);
+  if (!small) {
+    if (threadIdx.x == 0) {
+      MedianState* st = med_state(J, ws, map.ws_off[e]);
+      st->a = a_open ? 0ull : (uint64_t)hsel[0] << 32;
+      st->b = b_open ? ~0ull : (((uint64_t)hsel[1] << 32) | 0xffffffffull);
+    }
+    return;
+  }
+  const uint32_t rk0 = S.tg[0].t, rk1 = S.tg[1].t;
+  const bool same = hsel[0] == hsel[1];
+  // Low words of the keys whose high word is a selected one: list A for
+  // hsel[0], then list B for hsel[1] when it differs.
+  constexpr int kSteps = kSmallPairs / NT;
+  const uint32_t* klo = reinterpret_cast<const uint32_t*>(base + L.klo);
+  uint32_t mA = 0u, mB = 0u, cA = 0u, cB = 0u;
+#pragma unroll
+  for (int u = 0; u < kSteps; ++u) {
+    const uint32_t c = u * NT + threadIdx.x;
+    if (c < n) {
+      const uint32_t h = hs[c];
+      if (h == hsel[0]) {
+        mA |= 1u << u;
+        ++cA;
+      } else if (!same && h == hsel[1]) {
+        mB |= 1u << u;
+        ++cB;
+      }
+    }
+  }
+  uint32_t nA, nB;
+  uint32_t oA = block_scan<NT>(cA, S, &nA);  // its barriers end every read of hs[]
+  uint32_t oB = nA + block_scan<NT>(cB, S, &nB);
+#pragma unroll
+  for (int u = 0; u < kSteps; ++u) {
+    const uint32_t bit = 1u << u;
+    if (mA & bit) hs[oA++] = klo[u * NT + threadIdx.x];
+    if (mB & bit) hs[oB++] = klo[u * NT + threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    S.tg[0] = SelTarget<uint32_t>{0u, ~0u, rk0};
+    S.tg[1] = same ? SelTarget<uint32_t>{0u, ~0u, rk1} : SelTarget<uint32_t>{0u, 0u, 0u};
+  }
+  __syncthreads();
+  uint32_t lsel[2], tmp[2];
+  select_keys<NT>(hs, nA, false, (uint32_t*)nullptr, 0u, S, lsel);
+  if (!same) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      S.tg[0] = SelTarget<uint32_t>{0u, 0u, 0u};
+      S.tg[1] = SelTarget<uint32_t>{0u, ~0u, rk1};
+    }
+    __syncthreads();
+    select_keys<NT>(hs + nA, nB, false, (uint32_t*)nullptr, 0u, S, tmp);
+    lsel[1] = tmp[1];
+  }
+  if (threadIdx.x == 0)
+    write_bandwidth(J, ((uint64_t)hsel[0] << 32) | lsel[0], ((uint64_t)hsel[1] << 32) | lsel[1]);
 }
 
-hipError_t median_small_impl(const JobMap& mk, int gk, const JobMap& ms, int gs, const pds_job* d_jobs, char* ws,
-                             int mmax, hipStream_t s) {
-  if (mmax <= 4)
-    hipLaunchKernelGGL(median_keys_kernel<4>, dim3(gk), dim3(256), 0, s, mk, d_jobs, ws);
-  else if (mmax <= 8)
-    hipLaunchKernelGGL(median_keys_kernel<8>, dim3(gk), dim3(256), 0, s, mk, d_jobs, ws);
-  else
-    hipLaunchKernelGGL(median_keys_kernel<PDS_MAX_M>, dim3(gk), dim3(256), 0, s, mk, d_jobs, ws);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(median_select_kernel, dim3(gs), dim3(kSelThreads), 0, s, ms, d_jobs, ws);
-  return hipGetLastError();
+// Keys of every pair inside [lo, hi] into cand (block-scan order); one
+// block, used only when the sampled bracket missed a middle rank.
+template <int MM, int NT>
+__device__ uint32_t collect_pairs(const pds_job& J, const double* inv_rho, uint64_t lo, uint64_t hi, uint64_t* cand,
+                                  SelShared<uint64_t>& S) {
+  const uint32_t P = (uint32_t)((uint64_t)J.N * (J.N - 1) / 2);
+  constexpr int U = 4;
+  uint32_t base = 0;
+  for (uint32_t c0 = 0; c0 < P; c0 += NT * U) {
+    uint64_t key[U];
+    bool keep[U];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t p = c0 + u * NT + threadIdx.x;
+      keep[u] = false;
+      key[u] = 0ull;
+      if (p < P) {
+        int i, j;
+        pair_of(p, J.N, &i, &j);
+        key[u] = pair_key<MM>(J, i, j, inv_rho);
+        keep[u] = key[u] >= lo && key[u] <= hi;
+      }
+      cnt += keep[u] ? 1u : 0u;
+    }
+    uint32_t total;
+    uint32_t o = base + block_scan<NT>(cnt, S, &total);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (keep[u]) cand[o++] = key[u];
+    base += total;
+  }
+  return base;
 }
 
-// Writes h = 1 for jobs with a single particle (no pairs, no radix passes).
-__global__ void bandwidth_single_kernel(JobMap map, const pds_job* __restrict__ jobs) {
+// Count kernel over all pairs of the larger jobs, 64 x 64 pairs per block.
+// Each block adds its number of keys below a and its number of keys inside
+// [a, b] to one packed 64-bit counter and appends the latter to the job's
+// candidate array at the offset the addition returned.
+template <int MM>
+__global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                                   char* __restrict__ ws) {
+  __shared__ uint64_t lbuf[kCountTile * kCountTile];
+  __shared__ uint32_t wsum[16];
+  __shared__ float ti_s[kCountTile * PDS_MAX_M], tj_s[kCountTile * PDS_MAX_M];
+  __shared__ uint32_t less_s;
+  __shared__ uint32_t base_s;
+  constexpr int NT = kMedThreads;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  if (threadIdx.x == 0) J.bandwidth[0] = 1.0;
+  MedianState* st = med_state(J, ws, map.ws_off[e]);
+  const int N = J.N, M = J.M;
+  const int nb = (N + kCountTile - 1) / kCountTile;
+  int bi, bj;
+  tile_of(blockIdx.x - map.begin[e], nb, &bi, &bj);
+  const uint64_t a = st->a, b = st->b;
+  const int ri = bi * kCountTile, rj = bj * kCountTile;
+  const int ni = min(kCountTile, N - ri), nj = min(kCountTile, N - rj);
+  for (int t = threadIdx.x; t < ni * M; t += NT) ti_s[t] = J.theta[(size_t)ri * M + t];
+  for (int t = threadIdx.x; t < nj * M; t += NT) tj_s[t] = J.theta[(size_t)rj * M + t];
+  if (threadIdx.x == 0) less_s = 0u;
+  __syncthreads();
+  double inv_rho[MM];
+#pragma unroll
+  for (int m = 0; m < MM; ++m) inv_rho[m] = m < M ? 1.0 / (double)J.rho[m] : 0.0;
+  const int row = threadIdx.x & (kCountTile - 1);
+  const int cg = threadIdx.x / kCountTile;  // 16 groups of 4 columns
+  const int i = ri + row;
+  uint64_t key[4];
+  bool keep[4];
+  uint32_t nless = 0, nkeep = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int jl = cg * 4 + q;
+    const bool valid = row < ni && jl < nj && i < rj + jl;
+    key[q] = valid ? key_of(pair_d2<MM>(&ti_s[row * M], &tj_s[jl * M], inv_rho, M)) : 0ull;
+    nless += (valid && key[q] < a) ? 1u : 0u;
+    keep[q] = valid && key[q] >= a && key[q] <= b;
+    nkeep += keep[q] ? 1u : 0u;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nless += __shfl_xor(nless, o);
+  if ((threadIdx.x & 63) == 0 && nless) atomicAdd(&less_s, nless);
+  // block scan of nkeep (its barriers also publish less_s)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t inc = wave_scan(nkeep);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t o = inc - nkeep, total = 0;
+#pragma unroll
+  for (int k = 0; k < NT / 64; ++k) {
+    o += k < w ? wsum[k] : 0u;
+    total += wsum[k];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (keep[q]) lbuf[o++] = key[q];
+  if (threadIdx.x == 0 && (total | less_s)) {
+    const uint64_t old = atomicAdd((unsigned long long*)&st->packed,
+                                   (unsigned long long)(((uint64_t)total << 32) | (uint64_t)less_s));
+    base_s = (uint32_t)(old >> 32);
+  }
+  __syncthreads();
+  const WsLayout L = ws_layout(J);
+  uint64_t* cand = reinterpret_cast<uint64_t*>(ws + map.ws_off[e] + L.cand);
+  for (uint32_t c = threadIdx.x; c < total; c += NT) cand[base_s + c] = lbuf[c];
+}
+
+// Final kernel, one block per larger job: both middle keys exactly among
+// the candidates or, if the bracket missed a middle rank, among the keys of
+// the interval that holds both (recomputed from theta).
+template <int MM>
+__global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                                   char* __restrict__ ws) {
+  __shared__ uint64_t lbuf[kLastCap];
+  __shared__ SelShared<uint64_t> S;
+  constexpr int NT = kMedThreads;
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const MedianState* st = med_state(J, ws, map.ws_off[e]);
+  const uint32_t P = (uint32_t)((uint64_t)J.N * (J.N - 1) / 2);
+  const WsLayout L = ws_layout(J);
+  uint64_t* cand = reinterpret_cast<uint64_t*>(ws + map.ws_off[e] + L.cand);
+  const uint64_t a = st->a, b = st->b, packed = st->packed;
+  const uint32_t cl = (uint32_t)(packed & 0xffffffffull), nc = (uint32_t)(packed >> 32);
+  const uint32_t r0 = (P - 1) / 2, r1 = P / 2;
+  uint32_t n = nc, off = cl;
+  uint64_t lo = a, hi = b;
+  if (!(cl <= r0 && (uint64_t)r1 < (uint64_t)cl + nc)) {
+    double inv_rho[MM];
+#pragma unroll
+    for (int m = 0; m < MM; ++m) inv_rho[m] = m < J.M ? 1.0 / (double)J.rho[m] : 0.0;
+    lo = r0 < cl ? 0ull : a;
+    hi = (uint64_t)r1 >= (uint64_t)cl + nc ? ~0ull : b;
+    off = r0 < cl ? 0u : cl;
+    n = collect_pairs<MM, NT>(J, inv_rho, lo, hi, cand, S);
+  }
+  if (threadIdx.x == 0) {
+    S.tg[0] = SelTarget<uint64_t>{lo, hi, r0 - off};
+    S.tg[1] = SelTarget<uint64_t>{lo, hi, r1 - off};
+  }
+  __syncthreads();
+  uint64_t out[2];
+  select_keys<NT>((const uint64_t*)cand, n, true, lbuf, (uint32_t)kLastCap, S, out);
+  if (threadIdx.x == 0) write_bandwidth(J, out[0], out[1]);
 }
 
 // Partial phi of particles i (one per lane) over one chunk of j.
@@ -566,32 +816,36 @@ __global__ void iter_bump_kernel(JobMap map, const pds_job* __restrict__ jobs) {
 
 }  // namespace
 
-hipError_t launch_median_small(const JobMap& map_keys, int grid_keys, const JobMap& map_sel, int grid_sel,
-                               const pds_job* d_jobs, char* ws, int mmax, hipStream_t s) {
-  return median_small_impl(map_keys, grid_keys, map_sel, grid_sel, d_jobs, ws, mmax, s);
+#define PDS_MEDIAN_LAUNCH(kernel, grid, threads, map, ...)                                                  \
+  do {                                                                                                      \
+    if (mmax <= 4)                                                                                          \
+      hipLaunchKernelGGL(kernel<4>, dim3(grid), dim3(threads), 0, s, map, d_jobs, ws, ##__VA_ARGS__);         \
+    else if (mmax <= 8)                                                                                     \
+      hipLaunchKernelGGL(kernel<8>, dim3(grid), dim3(threads), 0, s, map, d_jobs, ws, ##__VA_ARGS__);         \
+    else                                                                                                    \
+      hipLaunchKernelGGL(kernel<PDS_MAX_M>, dim3(grid), dim3(threads), 0, s, map, d_jobs, ws, ##__VA_ARGS__); \
+  } while (0)
+
+hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, int mmax, int rank_shift,
+                         hipStream_t s) {
+  if (mm.keys.n > 0) {
+    PDS_MEDIAN_LAUNCH(median_keys_kernel, mm.grid_keys, 256, mm.keys);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(median_select_kernel, dim3(mm.grid_select), dim3(kMedThreads), 0, s, mm.select, d_jobs, ws,
+                     rank_shift);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess || mm.large.n == 0) return err;
+  PDS_MEDIAN_LAUNCH(median_count_kernel, mm.grid_count, kMedThreads, mm.count);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  PDS_MEDIAN_LAUNCH(median_final_kernel, mm.grid_large, kMedThreads, mm.large);
+  return hipGetLastError();
 }
 
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s) {
   hipLaunchKernelGGL(iter_bump_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs);
-  return hipGetLastError();
-}
-
-hipError_t launch_hist_clear(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(hist_clear_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
-  return hipGetLastError();
-}
-
-hipError_t launch_radix_pass(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int pass, int mmax,
-                             hipStream_t s) {
-  if (pass >= kRadixPasses) {
-    hipLaunchKernelGGL(bandwidth_single_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs);
-  } else if (mmax <= 4) {
-    hipLaunchKernelGGL(radix_pass_kernel<4>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws, pass);
-  } else if (mmax <= 8) {
-    hipLaunchKernelGGL(radix_pass_kernel<8>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws, pass);
-  } else {
-    hipLaunchKernelGGL(radix_pass_kernel<PDS_MAX_M>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws, pass);
-  }
   return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ _lock = threading.Lock()
 _lib = None
 EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
            "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_timing_enable",
-           "pds_timing_read")
+           "pds_timing_read", "pds_test_median_shift")
 
 
 def lib():
@@ -83,6 +83,8 @@ def lib():
             L.pds_timing_enable.restype = C.c_int
             L.pds_timing_read.argtypes = [C.c_void_p, C.c_int32]
             L.pds_timing_read.restype = C.c_int
+            L.pds_test_median_shift.argtypes = [C.c_int32]
+            L.pds_test_median_shift.restype = C.c_int
             _lib = L
     return _lib
 
@@ -254,6 +256,11 @@ def algorithmic_flops(model: int, n_dof: int):
 
 def timing_enable(on: bool = True):
     _check(lib().pds_timing_enable(1 if on else 0), "pds_timing_enable")
+
+
+def test_median_shift(ranks: int):
+    """Moves the sampled median bracket by `ranks` sample positions (tests only)."""
+    _check(lib().pds_test_median_shift(int(ranks)), "pds_test_median_shift")
 
 
 def timing_read(max_n: int = 4096):

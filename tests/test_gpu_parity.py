@@ -209,6 +209,53 @@ def test_bandwidth_exact_and_phi(orc, N):
     assert np.all(np.abs(ph - ph_ref) <= 1e-4 * scale + 1e-30)
 
 
+def _bandwidth_gpu(pb, theta):
+    obs = np.zeros((pb.K, pb.T, pb.d_x))
+    job = L.Job(pb, obs, theta=theta)
+    L.svgd_phi(L.Batch([job]))
+    return np64(job.bandwidth)[0]
+
+
+@pytest.mark.parametrize("config,N", [("c3", 1024), ("c2", 2048), ("c3", 181), ("c3", 182)])
+def test_bandwidth_exact_at_full_size(orc, config, N):
+    """Sampled bracket + counting pass (N > 181) and the all-in-LDS path
+    (N = 181, 16290 pairs) against the oracle's full sort."""
+    print_case("bandwidth", config, N)
+    pb = f32_problem(synth.make_problem(config, N=N, K=1, T=40, n_s=2))
+    theta = r32(pb.particles[:N]) if pb.particles.shape[0] >= N else r32(
+        pb.lo + np.random.default_rng(N).uniform(size=(N, pb.M)) * (pb.hi - pb.lo))
+    h_ref, _ = orc.bandwidth(theta, pb.rho)
+    assert abs(_bandwidth_gpu(pb, theta) - h_ref) <= 1e-15 * h_ref
+
+
+@pytest.mark.parametrize("shift", [400, -400, 20000, -20000])
+def test_bandwidth_exact_when_bracket_misses(orc, shift):
+    """A bracket moved off the middle ranks sends the count kernel's last
+    block through its recovery pass; the median stays exact."""
+    print_case("bandwidth-miss", shift)
+    pb = f32_problem(synth.make_problem("c2", N=600, K=1, T=40, n_s=2))
+    theta = r32(pb.lo + np.random.default_rng(7).uniform(size=(600, pb.M)) * (pb.hi - pb.lo))
+    h_ref, _ = orc.bandwidth(theta, pb.rho)
+    try:
+        L.test_median_shift(shift)
+        h = _bandwidth_gpu(pb, theta)
+    finally:
+        L.test_median_shift(0)
+    assert abs(h - h_ref) <= 1e-15 * h_ref
+
+
+@pytest.mark.parametrize("groups", [(300, 300), (150, 200, 250), (599, 1)])
+def test_bandwidth_exact_with_heavy_ties(orc, groups):
+    """Particles stacked on a few points: most pair distances are exactly
+    equal, so candidate sets far exceed the LDS capacity."""
+    print_case("bandwidth-ties", groups)
+    pb = f32_problem(synth.make_problem("c2", N=sum(groups), K=1, T=40, n_s=2))
+    pts = r32(pb.lo + np.random.default_rng(3).uniform(size=(len(groups), pb.M)) * (pb.hi - pb.lo))
+    theta = np.concatenate([np.repeat(pts[g:g + 1], n, axis=0) for g, n in enumerate(groups)])
+    h_ref, _ = orc.bandwidth(theta, pb.rho)
+    assert abs(_bandwidth_gpu(pb, theta) - h_ref) <= 1e-15 * h_ref
+
+
 @pytest.mark.parametrize("optimizer", [L.PDS_OPT_SGD, L.PDS_OPT_ADAM])
 def test_step_parity(orc, optimizer):
     print_case("step", optimizer)
