@@ -199,6 +199,14 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
 /* Workspace bytes the call `which` (PDS_CALL_*) needs for this batch;
  * PDS_CALL_ALL gives the maximum over all calls.  0 on invalid input (see
  * pds_last_error). */
+/* Device bytes one job occupies in a CSVGD iteration, for admission by
+ * HBM footprint: every buffer the pds_job fields point to at the sizes
+ * documented above (gdef and S_dot with at least one window, iter_dev with
+ * 2 entries; traj, seed_logp and seed_gdef only when non-NULL in *h_job)
+ * plus its workspace for all calls.  Reads only shapes and the three
+ * optional pointers; 0 on invalid shapes (see pds_last_error). */
+size_t pds_job_footprint(const pds_job* h_job);
+
 /* Testing aid: moves the sampled median bracket of later svgd_phi calls by
  * `ranks` sample positions (default 0), so tests can make it miss the
  * middle ranks and exercise the exact recovery pass.  The bandwidth stays

@@ -232,6 +232,47 @@ int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with
   return PDS_OK;
 }
 
+// Adjoint launch shape of one job, from its own size.  Planar: with fewer
+// waves than SIMDs the two adjoint channels go to two lanes per unit
+// (split); whole windows stay in LDS (full) when every wave of the job can
+// be resident at once, else sqrt(h) checkpoints.  Arm: one lane per unit,
+// full by the same rule.
+struct AdjShape {
+  bool split, full;
+  size_t lds;  // dynamic LDS bytes per block
+};
+
+AdjShape planar_shape(const pds_job& J) {
+  const long units = (long)J.N * J.K * J.n_s;
+  const int ds = 2 * J.n_dof;
+  const long kSimds = 256 * 4;
+  const size_t full_lds = (size_t)(J.h + 1) * ds * pds::kWave * sizeof(float);
+  AdjShape a;
+  a.split = div_up(units, pds::kWave) < kSimds;
+  const long waves = a.split ? div_up(units, pds::kWave / 2) : div_up(units, pds::kWave);
+  const long resident = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
+  a.full = waves <= resident;
+  const int B = a.full ? J.h : pds::planar_seg_len(J.h);
+  const int nseg = div_up(J.h, B);
+  a.lds = a.full ? full_lds : (size_t)(nseg + B + 1) * ds * pds::kWave * sizeof(float);
+  return a;
+}
+
+AdjShape arm_shape(const pds_job& J) {
+  const long units = (long)J.N * J.K * J.n_s;
+  const size_t per_state = 16 * pds::kWave * sizeof(float);
+  const size_t full_lds = (size_t)(J.h + 1) * per_state;
+  AdjShape a;
+  a.split = false;
+  const long waves = div_up(units, pds::kWave);
+  const long resident = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
+  a.full = waves <= resident;
+  const int B = a.full ? J.h : pds::arm_seg_len_host(J.h);
+  const int nseg = div_up(J.h, B);
+  a.lds = a.full ? full_lds : (size_t)(nseg + B + 1) * per_state;
+  return a;
+}
+
 int assemble_logp(const pds_job* h_jobs, const pds_job* d_jobs, int n, hipStream_t s) {
   std::vector<uint64_t> off(n, 0);
   int grid = 0;
@@ -298,6 +339,29 @@ size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which) 
   return best;
 }
 
+size_t pds_job_footprint(const pds_job* h_job) {
+  g_err.clear();
+  if (!h_job) {
+    fail(PDS_EINVAL, "pds_job_footprint: NULL job");
+    return 0;
+  }
+  const pds_job& J = *h_job;
+  if (validate_job(J, 0, 0)) return 0;
+  const size_t N = J.N, K = J.K, T = J.T, ns = J.n_s, M = J.M, ds = 2 * (size_t)J.n_dof, dx = J.d_x;
+  const size_t nsm = ns - 1, nsm1 = nsm > 0 ? nsm : 1;
+  size_t f32 = J.model == PDS_MODEL_ARM ? 126 : 2 + (size_t)J.n_dof;  // consts
+  f32 += 3 * M + dx + ds + M + ds + K * ds + K * T * dx;              // lo hi rho w_x u lr_theta lr_S s0 obs
+  f32 += N * M + N * K * nsm * ds + N * M + N * K * nsm;               // theta S lam_lim lam_def
+  f32 += 2 * N * (M + K * nsm * ds);                                   // adam_m adam_v
+  f32 += N * K * ns * ds + N * K * nsm1 * ds + N * M;                  // end_states S_dot phi
+  size_t f64 = N * K * ns + N * K * nsm1 + N + N * K + 2 * N * M + 1;  // ll_win gdef logp wk g_obs g_con bandwidth
+  const size_t i32 = N + 2;                                            // flags iter_dev
+  if (J.traj) f32 += N * K * T * ds;
+  if (J.seed_logp) f64 += N;
+  if (J.seed_gdef) f64 += N * K * nsm;
+  return 4 * f32 + 8 * f64 + 4 * i32 + job_ws(J, PDS_CALL_ALL);
+}
+
 int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
                       void* stream) {
   int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_FWD);
@@ -329,77 +393,49 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   if (rc) return rc;
   int slot = -1;
   timing_begin(s, &slot);
-  {
-    // arm: one lane per unit, both channels; whole window in LDS when every
-    // wave fits at once, else sqrt(h) checkpoints
-    auto pick = [](const pds_job& J) { return J.model == PDS_MODEL_ARM; };
-    long units = 0;
-    int hmax = 0;
-    for (int j = 0; j < n_jobs; ++j)
-      if (pick(h_jobs[j])) {
-        units += (long)h_jobs[j].N * h_jobs[j].K * h_jobs[j].n_s;
-        if (h_jobs[j].h > hmax) hmax = h_jobs[j].h;
-      }
-    if (units > 0) {
-      const size_t per_state = 16 * pds::kWave * sizeof(float);
-      const size_t full_lds = (size_t)(hmax + 1) * per_state;
-      const long waves = div_up(units, pds::kWave);
-      const long resident_full = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
-      const bool full = waves <= resident_full;
-      int grid = 0;
-      size_t lds = 0;
-      JobMap m = make_map(
-          h_jobs, n_jobs, off, pick,
-          [&](const pds_job& J) {
-            const int B = full ? J.h : pds::arm_seg_len_host(J.h);
-            const int nseg = div_up(J.h, B);
-            const size_t b = full ? (size_t)(J.h + 1) * per_state : (size_t)(nseg + B + 1) * per_state;
-            if (b > lds) lds = b;
-            return div_up((long)J.N * J.K * J.n_s, pds::kWave);
-          },
-          &grid);
-      if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "arm window of h steps needs %zu bytes of LDS", lds);
-      rc = launch_rc(pds::launch_arm_adjoint(m, d_jobs, w, grid, full, lds, s), "arm_adjoint");
-      if (rc) return rc;
-    }
-  }
-  for (int nb = 1; nb <= 5; ++nb) {
-    // Launch shape: with few waves (less than one per SIMD) the two adjoint
-    // channels go to two lanes per unit and, if LDS allows every wave to be
-    // resident, whole windows stay in LDS; otherwise one lane per unit and
-    // sqrt(h) checkpointing.
-    auto pick = [&](const pds_job& J) { return J.model == PDS_MODEL_PLANAR && J.n_dof == nb; };
-    long units = 0;
-    int hmax = 0;
-    for (int j = 0; j < n_jobs; ++j)
-      if (pick(h_jobs[j])) {
-        units += (long)h_jobs[j].N * h_jobs[j].K * h_jobs[j].n_s;
-        if (h_jobs[j].h > hmax) hmax = h_jobs[j].h;
-      }
-    if (units == 0) continue;
-    const int ds = 2 * nb;
-    const long kSimds = 256 * 4;
-    const size_t full_lds = (size_t)(hmax + 1) * ds * pds::kWave * sizeof(float);
-    const bool split = div_up(units, pds::kWave) < kSimds;
-    const long waves = split ? div_up(units, pds::kWave / 2) : div_up(units, pds::kWave);
-    const long resident_full = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
-    const bool full = waves <= resident_full;
+  // Launch shapes are chosen per job from its own size, never from the
+  // batch, so a job runs the same code path alone and in any mix; jobs
+  // sharing a shape share a launch.
+  for (int full = 0; full <= 1; ++full) {
+    auto pick = [&](const pds_job& J) { return J.model == PDS_MODEL_ARM && arm_shape(J).full == (full == 1); };
     int grid = 0;
     size_t lds = 0;
     JobMap m = make_map(
         h_jobs, n_jobs, off, pick,
         [&](const pds_job& J) {
-          const int B = full ? J.h : pds::planar_seg_len(J.h);
-          const int nseg = div_up(J.h, B);
-          const size_t b = full ? (size_t)(J.h + 1) * ds * pds::kWave * sizeof(float)
-                                : (size_t)(nseg + B + 1) * ds * pds::kWave * sizeof(float);
+          const size_t b = arm_shape(J).lds;
           if (b > lds) lds = b;
-          return div_up((long)J.N * J.K * J.n_s, split ? pds::kWave / 2 : pds::kWave);
+          return div_up((long)J.N * J.K * J.n_s, pds::kWave);
         },
         &grid);
-    if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "window of h steps needs %zu bytes of LDS", lds);
-    rc = launch_rc(pds::launch_planar_adjoint(m, nb, d_jobs, w, grid, split, full, lds, s), "planar_adjoint");
+    if (m.n == 0) continue;
+    if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "arm window of h steps needs %zu bytes of LDS", lds);
+    rc = launch_rc(pds::launch_arm_adjoint(m, d_jobs, w, grid, full == 1, lds, s), "arm_adjoint");
     if (rc) return rc;
+  }
+  for (int nb = 1; nb <= 5; ++nb) {
+    for (int mode = 0; mode < 4; ++mode) {
+      const bool split = (mode & 1) != 0, full = (mode & 2) != 0;
+      auto pick = [&](const pds_job& J) {
+        if (J.model != PDS_MODEL_PLANAR || J.n_dof != nb) return false;
+        const AdjShape a = planar_shape(J);
+        return a.split == split && a.full == full;
+      };
+      int grid = 0;
+      size_t lds = 0;
+      JobMap m = make_map(
+          h_jobs, n_jobs, off, pick,
+          [&](const pds_job& J) {
+            const size_t b = planar_shape(J).lds;
+            if (b > lds) lds = b;
+            return div_up((long)J.N * J.K * J.n_s, split ? pds::kWave / 2 : pds::kWave);
+          },
+          &grid);
+      if (m.n == 0) continue;
+      if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "window of h steps needs %zu bytes of LDS", lds);
+      rc = launch_rc(pds::launch_planar_adjoint(m, nb, d_jobs, w, grid, split, full, lds, s), "planar_adjoint");
+      if (rc) return rc;
+    }
   }
   timing_end(s, slot);
   int grid = 0;
@@ -456,12 +492,18 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   mm.large = make_map(h_jobs, n_jobs, off, large, [](const pds_job&) { return 1; }, &mm.grid_large);
   rc = launch_rc(pds::launch_median(mm, d_jobs, w, mmax, g_median_rank_shift, s), "median");
   if (rc) return rc;
-  int pgrid = 0;
-  JobMap mp = make_map(
-      h_jobs, n_jobs, off, all,
-      [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
-  rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, mmax, s), "phi_partial");
-  if (rc) return rc;
+  // phi partial sums, one launch per parameter-count class so a job's
+  // code path does not depend on the other jobs of the batch
+  for (int cls = 0; cls < 3; ++cls) {
+    const int lo_m = cls == 0 ? 1 : cls == 1 ? 5 : 9, hi_m = cls == 0 ? 4 : cls == 1 ? 8 : PDS_MAX_M;
+    int pgrid = 0;
+    JobMap mp = make_map(
+        h_jobs, n_jobs, off, [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; },
+        [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
+    if (mp.n == 0) continue;
+    rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, hi_m, s), "phi_partial");
+    if (rc) return rc;
+  }
   int rgrid = 0;
   JobMap mr = make_map(h_jobs, n_jobs, off, all, [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &rgrid);
   return launch_rc(pds::launch_phi_reduce(mr, d_jobs, w, rgrid, s), "phi_reduce");

@@ -23,13 +23,13 @@ def single_shooting(pb):
 
 
 def gpu_rollout(pb, theta, device="cuda"):
-    """Visited states [N, K, T, d_s] of every particle from every s0_k."""
+    """Visited states [N, K, T, d_s] of every particle from every s0_k (a
+    device tensor, ready in stream order on the current stream)."""
     ss = single_shooting(pb)
     obs = np.zeros((pb.K, pb.T, pb.d_x))
-    job = L.Job(ss, obs, theta=np.asarray(theta), device=device, with_traj=True)
+    job = L.Job(ss, obs, theta=theta, device=device, with_traj=True)
     b = L.Batch([job])
     L.sim_batch_forward(b)
-    torch.cuda.synchronize()
     return job.traj
 
 
@@ -41,13 +41,19 @@ def gpu_observations(pb, device="cuda"):
     return x.double().cpu().numpy() + pb.noise
 
 
-def gpu_shooting_init(pb, theta, device="cuda"):
-    """Shooting states [N, K, n_s-1, d_s] from each particle's own rollout."""
+def gpu_shooting_init_device(pb, theta, device="cuda"):
+    """Shooting states [N, K, n_s-1, d_s] (device tensor) from each
+    particle's own rollout: the state after step j h starts window j."""
     if pb.n_s == 1:
-        return np.zeros((theta.shape[0], pb.K, 0, pb.d_s))
+        return torch.zeros((theta.shape[0], pb.K, 0, pb.d_s), device=device)
     tr = gpu_rollout(pb, theta, device)
     idx = torch.arange(1, pb.n_s, device=tr.device) * pb.h - 1
-    return tr[:, :, idx].double().cpu().numpy()
+    return tr[:, :, idx].contiguous()
+
+
+def gpu_shooting_init(pb, theta, device="cuda"):
+    """Shooting states [N, K, n_s-1, d_s] as a host array."""
+    return gpu_shooting_init_device(pb, theta, device).double().cpu().numpy()
 
 
 class CSVGD:

@@ -55,7 +55,7 @@ _lock = threading.Lock()
 _lib = None
 EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
            "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_timing_enable",
-           "pds_timing_read", "pds_test_median_shift")
+           "pds_timing_read", "pds_test_median_shift", "pds_job_footprint")
 
 
 def lib():
@@ -83,6 +83,8 @@ def lib():
             L.pds_timing_enable.restype = C.c_int
             L.pds_timing_read.argtypes = [C.c_void_p, C.c_int32]
             L.pds_timing_read.restype = C.c_int
+            L.pds_job_footprint.argtypes = [P]
+            L.pds_job_footprint.restype = C.c_size_t
             L.pds_test_median_shift.argtypes = [C.c_int32]
             L.pds_test_median_shift.restype = C.c_int
             _lib = L
@@ -100,6 +102,8 @@ def _ptr(t):
 
 
 def _dev(a, dtype, device):
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).to(device)
 
 
@@ -256,6 +260,25 @@ def algorithmic_flops(model: int, n_dof: int):
 
 def timing_enable(on: bool = True):
     _check(lib().pds_timing_enable(1 if on else 0), "pds_timing_enable")
+
+
+def job_footprint(job_struct: PdsJob) -> int:
+    """Device bytes of one job (buffers + workspace) from the library's closed form."""
+    n = lib().pds_job_footprint(C.byref(job_struct))
+    if n == 0:
+        raise PdsError(lib().pds_last_error().decode())
+    return int(n)
+
+
+def shape_struct(pb, N=None) -> PdsJob:
+    """A pds_job carrying only the shapes of problem `pb` (no buffers)."""
+    j = PdsJob()
+    j.model, _ = model_consts(pb)
+    j.n_dof, j.M, j.d_x = pb.n_dof, pb.M, pb.d_x
+    j.N = pb.N if N is None else N
+    j.K, j.T, j.n_s, j.h, j.combine = pb.K, pb.T, pb.n_s, pb.h, pb.combine
+    j.dt, j.sigma_def, j.c, j.eps_lam = pb.dt, pb.sigma_def, pb.c, pb.eps_lam
+    return j
 
 
 def test_median_shift(ranks: int):

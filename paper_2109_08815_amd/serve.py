@@ -1,0 +1,388 @@
+"""Serving loop: continuous batching of CSVGD inference jobs on one GPU.
+
+Jobs arrive over time (a trace of seeded problems, `synth.serving_trace`).
+The scheduler admits a waiting job, first come first served, when a batch
+slot is free (at most PDS_MAX_JOBS jobs share one batch) and the job's
+device footprint fits the HBM budget still free.  The footprint is the
+library's closed form (`pds_job_footprint`: every buffer plus the job's
+workspace) plus the transient rollout buffer its set-up uses.  An admitted
+job is set up on the GPU: observed trajectories and default shooting
+states come from the library's own rollout.  Every engine tick then runs
+one CSVGD iteration (Algorithm 1) over all active jobs as one batch of the
+C-ABI calls, optionally as a captured HIP graph of several iterations
+while the batch does not change.  A job leaves the batch after its
+iteration count; its particles are copied to host memory, and its latency
+is the time from its arrival to its results being on the host.
+
+Every kernel reduces per job in a fixed order and per-job state (the Adam
+iteration counter included) lives in the job's own buffers, so a job's
+results are bitwise the same whichever jobs share its batches; the
+sequential mode (one job at a time, plain launches, same kernels) is the
+reference the batched mode is checked and timed against.
+
+Usage: python -m paper_2109_08815_amd.serve [--jobs 512] [--iterations 100]
+[--load 0.7 1.2] [--graph 10] prints one JSON line of latency and
+throughput figures.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import synth
+
+PDS_MAX_JOBS = 64
+
+
+# ---------------------------------------------------------------------------
+# Admission (host logic only)
+# ---------------------------------------------------------------------------
+
+class Scheduler:
+    """First-come-first-served admission by free slots and free HBM bytes.
+
+    `footprint(spec)` gives a job's device bytes.  A job larger than the
+    whole budget can never run and is rejected when it reaches the head of
+    the queue; otherwise the head waits until enough jobs have left (no
+    overtaking, so no job starves)."""
+
+    def __init__(self, budget_bytes: int, footprint, max_slots: int = PDS_MAX_JOBS):
+        if not 1 <= max_slots <= PDS_MAX_JOBS:
+            raise ValueError("max_slots must be in 1..%d" % PDS_MAX_JOBS)
+        self.budget = int(budget_bytes)
+        self.footprint = footprint
+        self.max_slots = max_slots
+        self.queue: collections.deque = collections.deque()
+        self.used = 0
+        self.active: dict[int, int] = {}  # job_id -> bytes held
+        self.rejected: list = []
+
+    def arrive(self, spec):
+        self.queue.append(spec)
+
+    def admit(self) -> list:
+        """Jobs to start now, in arrival order."""
+        out = []
+        while self.queue and len(self.active) < self.max_slots:
+            spec = self.queue[0]
+            need = int(self.footprint(spec))
+            if need > self.budget:
+                self.rejected.append(self.queue.popleft())
+                continue
+            if self.used + need > self.budget:
+                break
+            self.queue.popleft()
+            self.active[spec.job_id] = need
+            self.used += need
+            out.append(spec)
+        return out
+
+    def release(self, spec):
+        self.used -= self.active.pop(spec.job_id)
+
+
+# ---------------------------------------------------------------------------
+# GPU engine
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Record:
+    spec: synth.JobSpec
+    admitted: float = 0.0
+    done: float = 0.0
+    theta: np.ndarray | None = None
+    logp: np.ndarray | None = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.spec.arrival
+
+
+class _Active:
+    def __init__(self, spec, job):
+        self.spec = spec
+        self.job = job
+        self.iters = 0
+        self.event = None
+        self.host = None
+
+
+def setup_job(spec, device="cuda"):
+    """Device buffers of one job with observations and shooting states from
+    the library's rollout (all on the device)."""
+    import torch
+
+    from . import driver
+    from . import lib as L
+
+    pb = spec.problem()
+    dev = torch.device(device)
+    # observed trajectories: particle k rolled out from s0_k, plus the problem's noise
+    tr = driver.gpu_rollout(pb, pb.theta_true, dev)
+    k = torch.arange(pb.K, device=dev)
+    obs = tr[k, k][:, :, torch.as_tensor(pb.obs_index, device=dev)].double() + torch.as_tensor(pb.noise, device=dev)
+    del tr
+    S = driver.gpu_shooting_init_device(pb, pb.particles, dev)
+    job = L.Job(pb, obs, theta=pb.particles, S=S, device=device, device_iter=True)
+    return job
+
+
+def footprint(spec) -> int:
+    """Device bytes of a job: its buffers and workspace, plus the transient
+    single-shooting trajectory its set-up rolls out."""
+    from . import lib as L
+
+    pb = spec.problem()
+    steady = L.job_footprint(L.shape_struct(pb))
+    setup = 4 * pb.N * pb.K * pb.T * pb.d_s
+    return steady + setup
+
+
+class Engine:
+    """Runs a trace through the batched loop or one job at a time."""
+
+    def __init__(self, budget_bytes: int = 64 << 30, max_slots: int = PDS_MAX_JOBS, graph_iters: int = 0,
+                 device: str = "cuda", inflight: int = 2, footprint_fn=None):
+        self.budget = budget_bytes
+        self.max_slots = max_slots
+        self.graph_iters = graph_iters
+        self.device = device
+        self.inflight = inflight
+        self.footprint_fn = footprint_fn or _footprint_cached()
+
+    # -- batched ---------------------------------------------------------
+    def run_batched(self, trace, time_scale: float = 1.0) -> dict:
+        import torch
+
+        from . import lib as L
+
+        sched = Scheduler(self.budget, self.footprint_fn, self.max_slots)
+        pending = collections.deque(sorted(trace, key=lambda s: s.arrival))
+        records = {s.job_id: Record(s) for s in trace}
+        active: list[_Active] = []
+        finishing: list[_Active] = []
+        batch = None
+        graph = None
+        graph_n = 0
+        tick_events: collections.deque = collections.deque()
+        ticks = 0
+        t0 = time.perf_counter()
+
+        def now():
+            return (time.perf_counter() - t0) / time_scale
+
+        while pending or sched.queue or active or finishing:
+            # results whose copies have landed free their slots and bytes
+            for a in list(finishing):
+                if a.event.query():
+                    rec = records[a.spec.job_id]
+                    rec.done = now()
+                    rec.theta, rec.logp = a.host[0].numpy().copy(), a.host[1].numpy().copy()
+                    finishing.remove(a)
+                    sched.release(a.spec)
+            t = now()
+            while pending and pending[0].arrival <= t:
+                sched.arrive(pending.popleft())
+            started = sched.admit()
+            for spec in started:
+                records[spec.job_id].admitted = now()
+                active.append(_Active(spec, setup_job(spec, self.device)))
+            if started:
+                batch, graph = None, None
+            if not active:
+                if finishing:
+                    time.sleep(1e-4)
+                elif pending and not sched.queue:
+                    time.sleep(max(0.0, min(1e-3, pending[0].arrival - now())))
+                elif sched.queue and not sched.active:
+                    raise RuntimeError("job %d cannot be admitted" % sched.queue[0].job_id)
+                continue
+            if batch is None:
+                batch = L.Batch([a.job for a in active])
+            left = min(a.spec.iterations - a.iters for a in active)
+            # bound the work queued ahead of the GPU
+            while len(tick_events) >= self.inflight:
+                tick_events.popleft().synchronize()
+            if self.graph_iters > 1 and left >= self.graph_iters:
+                if graph is None:
+                    graph = _capture(batch, self.graph_iters)
+                    graph_n = self.graph_iters
+                graph.replay()
+                n_it = graph_n
+            else:
+                L.csvgd_iteration(batch, 0)
+                n_it = 1
+            ev = torch.cuda.Event()
+            ev.record()
+            tick_events.append(ev)
+            ticks += 1
+            for a in active:
+                a.iters += n_it
+            done = [a for a in active if a.iters >= a.spec.iterations]
+            if done:
+                for a in done:
+                    a.host = (_to_host(a.job.theta), _to_host(a.job.logp))
+                    a.event = torch.cuda.Event()
+                    a.event.record()
+                    a.job = None
+                    active.remove(a)
+                    finishing.append(a)
+                batch, graph = None, None
+        torch.cuda.synchronize()
+        wall = now()
+        return _summary(records, wall, ticks, sched.rejected)
+
+    # -- sequential reference --------------------------------------------
+    def run_sequential(self, trace, time_scale: float = 1.0) -> dict:
+        import torch
+
+        from . import lib as L
+
+        records = {s.job_id: Record(s) for s in trace}
+        t0 = time.perf_counter()
+
+        def now():
+            return (time.perf_counter() - t0) / time_scale
+
+        ticks = 0
+        for spec in sorted(trace, key=lambda s: s.arrival):
+            wait = spec.arrival - now()
+            if wait > 0:
+                time.sleep(wait * time_scale)
+            rec = records[spec.job_id]
+            rec.admitted = now()
+            job = setup_job(spec, self.device)
+            b = L.Batch([job])
+            for _ in range(spec.iterations):
+                L.csvgd_iteration(b, 0)
+                ticks += 1
+            rec.theta = job.theta.cpu().numpy()
+            rec.logp = job.logp.cpu().numpy()
+            rec.done = now()
+            del b, job
+        torch.cuda.synchronize()
+        return _summary(records, now(), ticks, [])
+
+
+def _to_host(t):
+    import torch
+
+    h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+    h.copy_(t, non_blocking=True)
+    return h
+
+
+def _capture(batch, iters):
+    import torch
+
+    from . import lib as L
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        for _ in range(iters):
+            L.csvgd_iteration(batch, 0)
+    torch.cuda.current_stream().wait_stream(s)
+    return g
+
+
+def _footprint_cached():
+    cache = {}
+
+    def f(spec):
+        key = (spec.family, spec.N, spec.K, spec.T)
+        if key not in cache:
+            cache[key] = footprint(spec)
+        return cache[key]
+
+    return f
+
+
+def _summary(records, wall, ticks, rejected):
+    recs = [r for r in records.values() if r.theta is not None]
+    lat = np.array([r.latency for r in recs]) if recs else np.zeros(0)
+    steps = sum(r.spec.N * r.spec.K * r.spec.T * r.spec.iterations for r in recs)
+    return {
+        "jobs": len(recs),
+        "rejected": [s.job_id for s in rejected],
+        "wall_s": wall,
+        "jobs_per_s": len(recs) / wall if wall > 0 else 0.0,
+        "particle_sim_steps_per_s": steps / wall if wall > 0 else 0.0,
+        "latency_p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+        "latency_p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+        "latency_mean_s": float(lat.mean()) if len(lat) else None,
+        "ticks": ticks,
+        "records": records,
+    }
+
+
+def same_results(a: dict, b: dict) -> tuple[int, int]:
+    """(jobs compared, jobs whose particles and log-likelihoods differ)."""
+    n = bad = 0
+    for jid, ra in a["records"].items():
+        rb = b["records"].get(jid)
+        if ra.theta is None or rb is None or rb.theta is None:
+            continue
+        n += 1
+        if not (np.array_equal(ra.theta, rb.theta) and np.array_equal(ra.logp, rb.logp, equal_nan=True)):
+            bad += 1
+    return n, bad
+
+
+def _strip(summary):
+    return {k: v for k, v in summary.items() if k != "records"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--jobs", type=int, default=64)
+    ap.add_argument("--iterations", type=int, default=20)
+    ap.add_argument("--load", type=float, nargs="*", default=[0.7, 1.2],
+                    help="arrival rates as fractions of the saturated batched throughput")
+    ap.add_argument("--graph", type=int, default=0, help="iterations per captured graph (0: plain launches)")
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--seed", type=int, default=5000)
+    ap.add_argument("--no-sequential", action="store_true")
+    args = ap.parse_args(argv)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    eng = Engine(budget_bytes=int(args.budget_gib * (1 << 30)), graph_iters=args.graph)
+    base = synth.serving_trace(args.jobs, seed=args.seed, iterations=args.iterations)
+    # warm-up: library load, kernels, allocator
+    eng.run_batched(base[:2])
+    closed = eng.run_batched(base)
+    sat = closed["jobs_per_s"]
+    print("closed loop: %.2f jobs/s over %d jobs" % (sat, closed["jobs"]), file=sys.stderr, flush=True)
+    out = {"workload": "serving trace: %d jobs, families c1/c2/c3, N 64..%d, K 1..8, T 200..1500, h %d, %d iterations"
+           % (args.jobs, 64 * 32, synth.SERVE_H, args.iterations),
+           "graph_iterations": args.graph, "closed_loop": _strip(closed), "load": {}}
+    for load in args.load:
+        tr = synth.serving_trace(args.jobs, seed=args.seed, iterations=args.iterations, rate=load * sat)
+        bat = eng.run_batched(tr)
+        entry = {"batched": _strip(bat)}
+        print("load %.2f batched: p50 %.3f s p99 %.3f s" % (load, bat["latency_p50_s"], bat["latency_p99_s"]),
+              file=sys.stderr, flush=True)
+        if not args.no_sequential:
+            seq = eng.run_sequential(tr)
+            n, bad = same_results(bat, seq)
+            entry["sequential"] = _strip(seq)
+            entry["compared_jobs"] = n
+            entry["jobs_differing"] = bad
+            print("load %.2f sequential: p50 %.3f s p99 %.3f s; %d/%d jobs bitwise equal" % (
+                load, seq["latency_p50_s"], seq["latency_p99_s"], n - bad, n), file=sys.stderr, flush=True)
+        out["load"][str(load)] = entry
+    print(json.dumps(out, default=float), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -223,3 +223,51 @@ def random_states(rng: np.random.Generator, n_dof: int, count: int, qmax: float 
 def perturb(rng: np.random.Generator, x: np.ndarray, scale: float) -> np.ndarray:
     """Additive Gaussian perturbation of an array (e.g. shooting states)."""
     return x + rng.normal(0.0, scale, x.shape)
+
+
+# ---------------------------------------------------------------------------
+# Serving trace
+# ---------------------------------------------------------------------------
+
+@dataclass
+class JobSpec:
+    """One inference job of a serving trace: a seeded problem plus when it
+    arrives (seconds from the start of the trace) and how many CSVGD
+    iterations it runs."""
+
+    job_id: int
+    family: str
+    N: int
+    K: int
+    T: int
+    seed: int
+    iterations: int
+    arrival: float = 0.0
+
+    def problem(self) -> "Problem":
+        return make_problem(self.family, seed=self.seed, N=self.N, K=self.K, T=self.T, n_s=self.T // SERVE_H)
+
+
+SERVE_H = 50  # window length of every serving job
+SERVE_T = (200, 400, 600, 800, 1000, 1200, 1500)
+
+
+def serving_trace(n_jobs: int = 512, seed: int = 5000, iterations: int = 100, rate: float | None = None,
+                  families=("c1", "c2", "c3"), max_log2_n: int = 5) -> list[JobSpec]:
+    """The mixed serving workload: family uniform over the planar problems,
+    N = 64 * 2^u with u uniform on 0..max_log2_n, T uniform over SERVE_T
+    (windows of SERVE_H steps), K uniform on 1..8.  With `rate` (jobs/s)
+    the arrivals are a Poisson process, else every job arrives at 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    t = 0.0
+    for j in range(n_jobs):
+        fam = families[int(rng.integers(len(families)))]
+        N = 64 * 2 ** int(rng.integers(max_log2_n + 1))
+        T = int(SERVE_T[int(rng.integers(len(SERVE_T)))])
+        K = int(rng.integers(1, 9))
+        if rate is not None:
+            t += float(rng.exponential(1.0 / rate))
+        out.append(JobSpec(j, fam, N, K, T, seed=seed * 1000 + j, iterations=iterations,
+                           arrival=t if rate is not None else 0.0))
+    return out
