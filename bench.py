@@ -177,13 +177,9 @@ def main():
     value = steps_per_iter * args.steps / elapsed
 
     k_ms = float(np.mean(kt)) if len(kt) else float("nan")
-    if pb.kind == 1:
-        fwd, rev, transc = L.algorithmic_flops(L.PDS_MODEL_PLANAR, pb.n_dof)
-        per_step = fwd + 2 * rev
-        achieved = steps_per_iter * per_step / (k_ms / 1e3) / 1e12
-    else:  # no algorithmic FLOP count for the arm model yet
-        per_step = None
-        achieved = None
+    fwd, rev, transc = L.algorithmic_flops(L.PDS_MODEL_PLANAR if pb.kind == 1 else L.PDS_MODEL_ARM, pb.n_dof)
+    per_step = fwd + 2 * rev  # forward step + reverse step of each of the two adjoint channels
+    achieved = steps_per_iter * per_step / (k_ms / 1e3) / 1e12
     finite = bool(torch.isfinite(job.theta).all().item())
     out = {
         "metric": "particle-sim-steps/s (fwd+adjoint)",
@@ -208,7 +204,7 @@ def main():
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": None if achieved is None else achieved / PEAK_FP32_TFLOPS,
+            "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(args.config),
             "kernel": ("planar_adjoint_kernel<%d>" % pb.n_dof) if pb.kind == 1 else "arm_adjoint_kernel",
             "kernel_ms": k_ms,

@@ -26,8 +26,10 @@
 // Work layout as for planar chains: one lane per window unit, the window's
 // checkpoints and the segment being reversed in LDS [slot][component][lane].
 #include <cmath>
+#include <vector>
 
 #include "common.h"
+#include "flop_count.h"
 
 namespace pds {
 
@@ -50,464 +52,472 @@ struct ArmConst {
 
 namespace {
 
-struct V3 {
-  float x, y, z;
-};
-__host__ __device__ inline V3 v3(float a, float b, float c) { return V3{a, b, c}; }
-__host__ __device__ inline V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
-__host__ __device__ inline V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
-__host__ __device__ inline V3 operator-(V3 a) { return v3(-a.x, -a.y, -a.z); }
-__host__ __device__ inline V3 operator*(float s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
-__host__ __device__ inline V3 cross(V3 a, V3 b) {
-  return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
-}
-__host__ __device__ inline float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincosf(x, sn, cs); }
 
-// Rotation E (row-major 3x3) applied to v and its transpose.
-__host__ __device__ inline V3 mulE(const float* E, V3 v) {
-  return v3(E[0] * v.x + E[1] * v.y + E[2] * v.z, E[3] * v.x + E[4] * v.y + E[5] * v.z,
-            E[6] * v.x + E[7] * v.y + E[8] * v.z);
-}
-__host__ __device__ inline V3 mulEt(const float* E, V3 v) {
-  return v3(E[0] * v.x + E[3] * v.y + E[6] * v.z, E[1] * v.x + E[4] * v.y + E[7] * v.z,
-            E[2] * v.x + E[5] * v.y + E[8] * v.z);
-}
-
-// Spatial vectors: motion (w; v), force (n; f).
-struct SV {
-  V3 a, l;
-};
-__host__ __device__ inline SV sv(V3 a, V3 l) { return SV{a, l}; }
-__host__ __device__ inline SV operator+(SV p, SV q) { return sv(p.a + q.a, p.l + q.l); }
-__host__ __device__ inline SV operator-(SV p, SV q) { return sv(p.a - q.a, p.l - q.l); }
-__host__ __device__ inline SV operator*(float s, SV p) { return sv(s * p.a, s * p.l); }
-__host__ __device__ inline float sdot(SV p, SV q) { return dot(p.a, q.a) + dot(p.l, q.l); }
-// v x m  and  v x* f
-__host__ __device__ inline SV crm(SV v, SV m) { return sv(cross(v.a, m.a), cross(v.a, m.l) + cross(v.l, m.a)); }
-__host__ __device__ inline SV crf(SV v, SV f) { return sv(cross(v.a, f.a) + cross(v.l, f.l), cross(v.a, f.l)); }
-
-// Plucker transform parent -> body: (E, r).  Motion: X m; force: X^T f.
-__host__ __device__ inline SV xm(const float* E, V3 r, SV m) { return sv(mulE(E, m.a), mulE(E, m.l - cross(r, m.a))); }
-__host__ __device__ inline SV xtf(const float* E, V3 r, SV f) {
-  const V3 fl = mulEt(E, f.l);
-  return sv(mulEt(E, f.a) + cross(r, fl), fl);
-}
-// Transpose of xm (maps a motion-space adjoint back to the parent): X^T y
-__host__ __device__ inline SV xtm(const float* E, V3 r, SV y) { return xtf(E, r, y); }
-// Transpose of xtf (maps a force adjoint to the body): X y
-__host__ __device__ inline SV xf(const float* E, V3 r, SV y) { return xm(E, r, y); }
-
-// Joint axis: bodies 0..6 about z, body 7 about x (unit vectors).
-__host__ __device__ inline int axis_of(int i) { return i == 7 ? 0 : 2; }
-__host__ __device__ inline float comp(V3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
-__host__ __device__ inline V3 unit(int k) { return v3(k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f); }
-
-// Body rotation: joint rotation (about the axis, by q) after the tree rotation.
-__host__ __device__ inline void body_E(const ArmConst& K, int i, float cs, float sn, float* E) {
-  const float* T = K.E[i];
-  if (axis_of(i) == 2) {  // Rz(q)^T T
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      E[k] = cs * T[k] + sn * T[3 + k];
-      E[3 + k] = -sn * T[k] + cs * T[3 + k];
-      E[6 + k] = T[6 + k];
-    }
-  } else {  // Rx(q)^T T
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      E[k] = T[k];
-      E[3 + k] = cs * T[3 + k] + sn * T[6 + k];
-      E[6 + k] = -sn * T[3 + k] + cs * T[6 + k];
-    }
+// The spatial algebra, forward dynamics and reverse step, generic over the
+// scalar type R: float on the device; a counting scalar on the host gives
+// the algorithmic FLOPs of one step.
+template <class R>
+struct ArmMath {
+  struct V3 {
+    R x, y, z;
+  };
+  __host__ __device__ static inline V3 v3(R a, R b, R c) { return V3{a, b, c}; }
+  __host__ __device__ friend inline V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+  __host__ __device__ friend inline V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+  __host__ __device__ friend inline V3 operator-(V3 a) { return v3(-a.x, -a.y, -a.z); }
+  __host__ __device__ friend inline V3 operator*(R s, V3 a) { return v3(s * a.x, s * a.y, s * a.z); }
+  __host__ __device__ static inline V3 cross(V3 a, V3 b) {
+    return v3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
   }
-}
+  __host__ __device__ static inline R dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
-// Rigid-body inertia applied to a motion vector, from (m, c, Ic):
-// I [w; v] = [Ic w + c x p; p] with p = m (v - c x w).
-__host__ __device__ inline SV rbi_mul(float m, V3 c, const float* Ic, SV x) {
-  const V3 p = m * (x.l - cross(c, x.a));
-  const V3 Iw = v3(Ic[0] * x.a.x + Ic[1] * x.a.y + Ic[2] * x.a.z, Ic[1] * x.a.x + Ic[3] * x.a.y + Ic[4] * x.a.z,
-                   Ic[2] * x.a.x + Ic[4] * x.a.y + Ic[5] * x.a.z);
-  return sv(Iw + cross(c, p), p);
-}
-// Point mass m at c: I [w; v] = [c x p; p], p = m (v - c x w).
-__host__ __device__ inline SV pm_mul(float m, V3 c, SV x) {
-  const V3 p = m * (x.l - cross(c, x.a));
-  return sv(cross(c, p), p);
-}
+  // Rotation E (row-major 3x3) applied to v and its transpose.
+  __host__ __device__ static inline V3 mulE(const R* E, V3 v) {
+    return v3(E[0] * v.x + E[1] * v.y + E[2] * v.z, E[3] * v.x + E[4] * v.y + E[5] * v.z,
+              E[6] * v.x + E[7] * v.y + E[8] * v.z);
+  }
+  __host__ __device__ static inline V3 mulEt(const R* E, V3 v) {
+    return v3(E[0] * v.x + E[3] * v.y + E[6] * v.z, E[1] * v.x + E[4] * v.y + E[7] * v.z,
+              E[2] * v.x + E[5] * v.y + E[8] * v.z);
+  }
 
-// Symmetric 6x6 as blocks A (sym 3: xx,xy,xz,yy,yz,zz), B (3x3 row-major), C (sym 3).
-struct Sym6 {
-  float A[6], B[9], C[6];
-};
-__host__ __device__ inline float s3(const float* S, int i, int j) {
-  const int a = i < j ? i : j, b = i < j ? j : i;
-  return a == 0 ? S[b] : (a == 1 ? S[2 + b] : S[5]);
-}
+  // Spatial vectors: motion (w; v), force (n; f).
+  struct SV {
+    V3 a, l;
+  };
+  __host__ __device__ static inline SV sv(V3 a, V3 l) { return SV{a, l}; }
+  __host__ __device__ friend inline SV operator+(SV p, SV q) { return sv(p.a + q.a, p.l + q.l); }
+  __host__ __device__ friend inline SV operator-(SV p, SV q) { return sv(p.a - q.a, p.l - q.l); }
+  __host__ __device__ friend inline SV operator*(R s, SV p) { return sv(s * p.a, s * p.l); }
+  __host__ __device__ static inline R sdot(SV p, SV q) { return dot(p.a, q.a) + dot(p.l, q.l); }
+  // v x m  and  v x* f
+  __host__ __device__ static inline SV crm(SV v, SV m) { return sv(cross(v.a, m.a), cross(v.a, m.l) + cross(v.l, m.a)); }
+  __host__ __device__ static inline SV crf(SV v, SV f) { return sv(cross(v.a, f.a) + cross(v.l, f.l), cross(v.a, f.l)); }
 
-// Adds the rigid inertia of (m, c, Ic) to I: [[Ic + m cx cx^T, m cx], [m cx^T, m 1]].
-__host__ __device__ inline void add_rbi(Sym6& I, float m, V3 c, const float* Ic) {
-  // cx cx^T = |c|^2 1 - c c^T
-  const float cc = dot(c, c);
-  I.A[0] += Ic[0] + m * (cc - c.x * c.x);
-  I.A[1] += Ic[1] - m * c.x * c.y;
-  I.A[2] += Ic[2] - m * c.x * c.z;
-  I.A[3] += Ic[3] + m * (cc - c.y * c.y);
-  I.A[4] += Ic[4] - m * c.y * c.z;
-  I.A[5] += Ic[5] + m * (cc - c.z * c.z);
-  // m skew(c)
-  I.B[0] += 0.f;      I.B[1] += -m * c.z; I.B[2] += m * c.y;
-  I.B[3] += m * c.z;  I.B[4] += 0.f;      I.B[5] += -m * c.x;
-  I.B[6] += -m * c.y; I.B[7] += m * c.x;  I.B[8] += 0.f;
-  I.C[0] += m; I.C[3] += m; I.C[5] += m;
-}
+  // Plucker transform parent -> body: (E, r).  Motion: X m; force: X^T f.
+  __host__ __device__ static inline SV xm(const R* E, V3 r, SV m) { return sv(mulE(E, m.a), mulE(E, m.l - cross(r, m.a))); }
+  __host__ __device__ static inline SV xtf(const R* E, V3 r, SV f) {
+    const V3 fl = mulEt(E, f.l);
+    return sv(mulEt(E, f.a) + cross(r, fl), fl);
+  }
+  // Transpose of xm (maps a motion-space adjoint back to the parent): X^T y
+  __host__ __device__ static inline SV xtm(const R* E, V3 r, SV y) { return xtf(E, r, y); }
+  // Transpose of xtf (maps a force adjoint to the body): X y
+  __host__ __device__ static inline SV xf(const R* E, V3 r, SV y) { return xm(E, r, y); }
 
-__host__ __device__ inline SV sym6_mul(const Sym6& I, SV x) {
-  const V3 w = x.a, v = x.l;
-  const V3 Aw = v3(I.A[0] * w.x + I.A[1] * w.y + I.A[2] * w.z, I.A[1] * w.x + I.A[3] * w.y + I.A[4] * w.z,
-                   I.A[2] * w.x + I.A[4] * w.y + I.A[5] * w.z);
-  const V3 Bv = mulE(I.B, v);
-  const V3 Btw = mulEt(I.B, w);
-  const V3 Cv = v3(I.C[0] * v.x + I.C[1] * v.y + I.C[2] * v.z, I.C[1] * v.x + I.C[3] * v.y + I.C[4] * v.z,
-                   I.C[2] * v.x + I.C[4] * v.y + I.C[5] * v.z);
-  return sv(Aw + Bv, Btw + Cv);
-}
+  // Joint axis: bodies 0..6 about z, body 7 about x (unit vectors).
+  __host__ __device__ static inline int axis_of(int i) { return i == 7 ? 0 : 2; }
+  __host__ __device__ static inline R comp(V3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+  __host__ __device__ static inline V3 unit(int k) { return v3(k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f); }
 
-// IA_parent += X^T Ia X for X = (E, r), R = skew(r):
-// with A' = E^T A E, B' = E^T B E, C' = E^T C E:
-// TL = A' - B' R + R B'^T - R C' R, TR = B' + R C', BR = C'.
-__host__ __device__ __forceinline__ void add_xtix(Sym6& P, const Sym6& I, const float* E, V3 r) {
-  float A[9], B[9], C[9];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      float sa = 0.f, sb = 0.f, sc = 0.f;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          const float e = E[3 * k + i] * E[3 * l + j];
-          sa += e * s3(I.A, k, l);
-          sb += e * I.B[3 * k + l];
-          sc += e * s3(I.C, k, l);
-        }
-      A[3 * i + j] = sa;
-      B[3 * i + j] = sb;
-      C[3 * i + j] = sc;
-    }
-  // skew(r) rows
-  const float R[9] = {0.f, -r.z, r.y, r.z, 0.f, -r.x, -r.y, r.x, 0.f};
-  float BR[9], RC[9], RCR[9];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      float s1 = 0.f, s2 = 0.f;
-#pragma unroll
+  // Body rotation: joint rotation (about the axis, by q) after the tree rotation.
+  __host__ __device__ static inline void body_E(const ArmConst& K, int i, R cs, R sn, R* E) {
+    const float* T = K.E[i];
+    if (axis_of(i) == 2) {  // Rz(q)^T T
+  #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        s1 += B[3 * i + k] * R[3 * k + j];
-        s2 += R[3 * i + k] * C[3 * k + j];
+        E[k] = cs * T[k] + sn * T[3 + k];
+        E[3 + k] = -sn * T[k] + cs * T[3 + k];
+        E[6 + k] = T[6 + k];
       }
-      BR[3 * i + j] = s1;
-      RC[3 * i + j] = s2;
-    }
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      float s = 0.f;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) s += RC[3 * i + k] * R[3 * k + j];
-      RCR[3 * i + j] = s;
-    }
-  // TL(i,j) = A - BR - BR^T - RCR   (R B'^T = -(B' R)^T)
-  const int si[6] = {0, 0, 0, 1, 1, 2}, sj[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-  for (int e = 0; e < 6; ++e) {
-    const int i = si[e], j = sj[e];
-    P.A[e] += A[3 * i + j] - BR[3 * i + j] - BR[3 * j + i] - RCR[3 * i + j];
-    P.C[e] += C[3 * i + j];
-  }
-#pragma unroll
-  for (int e = 0; e < 9; ++e) P.B[e] += B[e] + RC[e];
-}
-
-// Joint torque at time `time` (PD on the arm, damping on the hinge).
-__host__ __device__ inline float arm_tau(const ArmConst& K, int i, float time, float q, float qd) {
-  if (i == 7) return -K.bh * qd;
-  float sn, cs;
-  sincosf(K.om[i] * time + K.ph[i], &sn, &cs);
-  const float qdes = K.qc[i] + K.amp[i] * sn;
-  const float qddes = K.amp[i] * K.om[i] * cs;
-  return K.kp[i] * (qdes - q) + K.kd[i] * (qddes - qd);
-}
-
-// Intermediates of one forward-dynamics evaluation kept for the reverse.
-struct ArmTape {
-  float cs[kArmBodies], sn[kArmBodies];
-  SV v[kArmBodies];   // body velocities
-  SV a[kArmBodies];   // body accelerations (incl. S qdd)
-  SV U[kArmBodies];   // IA S
-  float invD[kArmBodies];
-  float qdd[kArmBodies];
-};
-
-// Compiler-level memory barrier: the model constants are re-read (scalar
-// loads, cached) inside every step instead of being hoisted out of the step
-// loops into vector registers.
-__host__ __device__ __forceinline__ void keep_consts_in_memory() {
-#if defined(__HIP_DEVICE_COMPILE__)
-  asm volatile("" ::: "memory");
-#endif
-}
-
-// Articulated Body Algorithm (three passes over the chain).  The inward
-// pass carries only the child's contribution to the articulated inertia and
-// bias force; each body's rigid inertia is rebuilt on the fly.
-__host__ __device__ __forceinline__ void arm_aba(const ArmConst& K, const float* th, const float* q, const float* qd,
-                                        float time, ArmTape& T) {
-  float u[kArmBodies];
-  const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
-  const float z0[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int i = 0; i < kArmBodies; ++i) {
-    keep_consts_in_memory();
-    sincosf(q[i], &T.sn[i], &T.cs[i]);
-    float E[9];
-    body_E(K, i, T.cs[i], T.sn[i], E);
-    const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
-    const SV vj = sv(qd[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
-    T.v[i] = (i == 0 ? sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f)) : xm(E, r, T.v[i - 1])) + vj;
-  }
-  Sym6 IAc;  // child's contribution X^T Ia X
-  SV pAc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
-#pragma unroll
-  for (int e = 0; e < 6; ++e) { IAc.A[e] = 0.f; IAc.C[e] = 0.f; }
-#pragma unroll
-  for (int e = 0; e < 9; ++e) IAc.B[e] = 0.f;
-#pragma unroll
-  for (int i = kArmBodies - 1; i >= 0; --i) {
-    keep_consts_in_memory();
-    const int k = axis_of(i);
-    const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
-    Sym6 IA = IAc;
-    add_rbi(IA, K.m[i], cm, K.Ic[i]);
-    SV h = rbi_mul(K.m[i], cm, K.Ic[i], T.v[i]);
-    if (i == 7) {
-      add_rbi(IA, K.pm_m, ca, z0);
-      add_rbi(IA, K.pm_m, cb, z0);
-      h = h + pm_mul(K.pm_m, ca, T.v[i]) + pm_mul(K.pm_m, cb, T.v[i]);
-    }
-    const SV pA = crf(T.v[i], h) + pAc;
-    const SV U = sv(v3(s3(IA.A, 0, k), s3(IA.A, 1, k), s3(IA.A, 2, k)),
-                    v3(IA.B[3 * k], IA.B[3 * k + 1], IA.B[3 * k + 2]));
-    const float invD = 1.0f / comp(U.a, k);
-    u[i] = arm_tau(K, i, time, q[i], qd[i]) - comp(pA.a, k);
-    T.U[i] = U;
-    T.invD[i] = invD;
-    if (i > 0) {
-      Sym6 Ia = IA;
-      const float Uw[3] = {U.a.x, U.a.y, U.a.z}, Uv[3] = {U.l.x, U.l.y, U.l.z};
-      const int si[6] = {0, 0, 0, 1, 1, 2}, sj[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-      for (int e = 0; e < 6; ++e) {
-        Ia.A[e] -= Uw[si[e]] * Uw[sj[e]] * invD;
-        Ia.C[e] -= Uv[si[e]] * Uv[sj[e]] * invD;
+    } else {  // Rx(q)^T T
+  #pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        E[k] = T[k];
+        E[3 + k] = cs * T[3 + k] + sn * T[6 + k];
+        E[6 + k] = -sn * T[3 + k] + cs * T[6 + k];
       }
-#pragma unroll
-      for (int a2 = 0; a2 < 3; ++a2)
-#pragma unroll
-        for (int b2 = 0; b2 < 3; ++b2) Ia.B[3 * a2 + b2] -= Uw[a2] * Uv[b2] * invD;
-      const SV ci = crm(T.v[i], sv(qd[i] * unit(k), v3(0.f, 0.f, 0.f)));
-      const SV pa = pA + sym6_mul(Ia, ci) + (u[i] * invD) * U;
-      float E[9];
+    }
+  }
+
+  // Rigid-body inertia applied to a motion vector, from (m, c, Ic):
+  // I [w; v] = [Ic w + c x p; p] with p = m (v - c x w).
+  __host__ __device__ static inline SV rbi_mul(float m, V3 c, const float* Ic, SV x) {
+    const V3 p = m * (x.l - cross(c, x.a));
+    const V3 Iw = v3(Ic[0] * x.a.x + Ic[1] * x.a.y + Ic[2] * x.a.z, Ic[1] * x.a.x + Ic[3] * x.a.y + Ic[4] * x.a.z,
+                     Ic[2] * x.a.x + Ic[4] * x.a.y + Ic[5] * x.a.z);
+    return sv(Iw + cross(c, p), p);
+  }
+  // Point mass m at c: I [w; v] = [c x p; p], p = m (v - c x w).
+  __host__ __device__ static inline SV pm_mul(float m, V3 c, SV x) {
+    const V3 p = m * (x.l - cross(c, x.a));
+    return sv(cross(c, p), p);
+  }
+
+  // Symmetric 6x6 as blocks A (sym 3: xx,xy,xz,yy,yz,zz), B (3x3 row-major), C (sym 3).
+  struct Sym6 {
+    R A[6], B[9], C[6];
+  };
+  __host__ __device__ static inline R s3(const R* S, int i, int j) {
+    const int a = i < j ? i : j, b = i < j ? j : i;
+    return a == 0 ? S[b] : (a == 1 ? S[2 + b] : S[5]);
+  }
+
+  // Adds the rigid inertia of (m, c, Ic) to I: [[Ic + m cx cx^T, m cx], [m cx^T, m 1]].
+  __host__ __device__ static inline void add_rbi(Sym6& I, float m, V3 c, const float* Ic) {
+    // cx cx^T = |c|^2 1 - c c^T
+    const R cc = dot(c, c);
+    I.A[0] += Ic[0] + m * (cc - c.x * c.x);
+    I.A[1] += Ic[1] - m * c.x * c.y;
+    I.A[2] += Ic[2] - m * c.x * c.z;
+    I.A[3] += Ic[3] + m * (cc - c.y * c.y);
+    I.A[4] += Ic[4] - m * c.y * c.z;
+    I.A[5] += Ic[5] + m * (cc - c.z * c.z);
+    // m skew(c)
+    I.B[1] += -m * c.z; I.B[2] += m * c.y;
+    I.B[3] += m * c.z;  I.B[5] += -m * c.x;
+    I.B[6] += -m * c.y; I.B[7] += m * c.x;
+    I.C[0] += m; I.C[3] += m; I.C[5] += m;
+  }
+
+  __host__ __device__ static inline SV sym6_mul(const Sym6& I, SV x) {
+    const V3 w = x.a, v = x.l;
+    const V3 Aw = v3(I.A[0] * w.x + I.A[1] * w.y + I.A[2] * w.z, I.A[1] * w.x + I.A[3] * w.y + I.A[4] * w.z,
+                     I.A[2] * w.x + I.A[4] * w.y + I.A[5] * w.z);
+    const V3 Bv = mulE(I.B, v);
+    const V3 Btw = mulEt(I.B, w);
+    const V3 Cv = v3(I.C[0] * v.x + I.C[1] * v.y + I.C[2] * v.z, I.C[1] * v.x + I.C[3] * v.y + I.C[4] * v.z,
+                     I.C[2] * v.x + I.C[4] * v.y + I.C[5] * v.z);
+    return sv(Aw + Bv, Btw + Cv);
+  }
+
+  // IA_parent += X^T Ia X for X = (E, r), R = skew(r):
+  // with A' = E^T A E, B' = E^T B E, C' = E^T C E:
+  // TL = A' - B' R + R B'^T - R C' R, TR = B' + R C', BR = C'.
+  __host__ __device__ static __forceinline__ void add_xtix(Sym6& P, const Sym6& I, const R* E, V3 r) {
+    R A[9], B[9], C[9];
+  #pragma unroll
+    for (int i = 0; i < 3; ++i)
+  #pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        R sa = 0.f, sb = 0.f, sc = 0.f;
+  #pragma unroll
+        for (int k = 0; k < 3; ++k)
+  #pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            const R e = E[3 * k + i] * E[3 * l + j];
+            sa += e * s3(I.A, k, l);
+            sb += e * I.B[3 * k + l];
+            sc += e * s3(I.C, k, l);
+          }
+        A[3 * i + j] = sa;
+        B[3 * i + j] = sb;
+        C[3 * i + j] = sc;
+      }
+    // skew(r) rows
+    const R Rs[9] = {0.f, -r.z, r.y, r.z, 0.f, -r.x, -r.y, r.x, 0.f};
+    R BR[9], RC[9], RCR[9];
+  #pragma unroll
+    for (int i = 0; i < 3; ++i)
+  #pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        R s1 = 0.f, s2 = 0.f;
+  #pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          s1 += B[3 * i + k] * Rs[3 * k + j];
+          s2 += Rs[3 * i + k] * C[3 * k + j];
+        }
+        BR[3 * i + j] = s1;
+        RC[3 * i + j] = s2;
+      }
+  #pragma unroll
+    for (int i = 0; i < 3; ++i)
+  #pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        R s = 0.f;
+  #pragma unroll
+        for (int k = 0; k < 3; ++k) s += RC[3 * i + k] * Rs[3 * k + j];
+        RCR[3 * i + j] = s;
+      }
+    // TL(i,j) = A - BR - BR^T - RCR   (R B'^T = -(B' R)^T)
+    const int si[6] = {0, 0, 0, 1, 1, 2}, sj[6] = {0, 1, 2, 1, 2, 2};
+  #pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int i = si[e], j = sj[e];
+      P.A[e] += A[3 * i + j] - BR[3 * i + j] - BR[3 * j + i] - RCR[3 * i + j];
+      P.C[e] += C[3 * i + j];
+    }
+  #pragma unroll
+    for (int e = 0; e < 9; ++e) P.B[e] += B[e] + RC[e];
+  }
+
+  // Joint torque at time `time` (PD on the arm, damping on the hinge).
+  __host__ __device__ static inline R arm_tau(const ArmConst& K, int i, R time, R q, R qd) {
+    if (i == 7) return -K.bh * qd;
+    R sn, cs;
+    sincos_r(K.om[i] * time + K.ph[i], &sn, &cs);
+    const R qdes = K.qc[i] + K.amp[i] * sn;
+    const R qddes = K.amp[i] * K.om[i] * cs;
+    return K.kp[i] * (qdes - q) + K.kd[i] * (qddes - qd);
+  }
+
+  // Intermediates of one forward-dynamics evaluation kept for the reverse.
+  struct ArmTape {
+    R cs[kArmBodies], sn[kArmBodies];
+    SV v[kArmBodies];   // body velocities
+    SV a[kArmBodies];   // body accelerations (incl. S qdd)
+    SV U[kArmBodies];   // IA S
+    R invD[kArmBodies];
+    R qdd[kArmBodies];
+  };
+
+  // Compiler-level memory barrier: the model constants are re-read (scalar
+  // loads, cached) inside every step instead of being hoisted out of the step
+  // loops into vector registers.
+  __host__ __device__ static __forceinline__ void keep_consts_in_memory() {
+  #if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" ::: "memory");
+  #endif
+  }
+
+  // Articulated Body Algorithm (three passes over the chain).  The inward
+  // pass carries only the child's contribution to the articulated inertia and
+  // bias force; each body's rigid inertia is rebuilt on the fly.
+  __host__ __device__ static __forceinline__ void arm_aba(const ArmConst& K, const R* th, const R* q, const R* qd,
+                                          R time, ArmTape& T) {
+    R u[kArmBodies];
+    const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
+    const float z0[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  #pragma unroll
+    for (int i = 0; i < kArmBodies; ++i) {
+      keep_consts_in_memory();
+      sincos_r(q[i], &T.sn[i], &T.cs[i]);
+      R E[9];
       body_E(K, i, T.cs[i], T.sn[i], E);
       const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
-#pragma unroll
-      for (int e = 0; e < 6; ++e) { IAc.A[e] = 0.f; IAc.C[e] = 0.f; }
-#pragma unroll
-      for (int e = 0; e < 9; ++e) IAc.B[e] = 0.f;
-      add_xtix(IAc, Ia, E, r);
-      pAc = xtf(E, r, pa);
+      const SV vj = sv(qd[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+      T.v[i] = (i == 0 ? sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f)) : xm(E, r, T.v[i - 1])) + vj;
     }
-  }
-  SV ap = sv(v3(0.f, 0.f, 0.f), v3(-K.g[0], -K.g[1], -K.g[2]));
-#pragma unroll
-  for (int i = 0; i < kArmBodies; ++i) {
-    keep_consts_in_memory();
-    float E[9];
-    body_E(K, i, T.cs[i], T.sn[i], E);
-    const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
-    const SV ci = crm(T.v[i], sv(qd[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f)));
-    const SV a1 = xm(E, r, ap) + ci;
-    const float qdd = (u[i] - sdot(T.U[i], a1)) * T.invD[i];
-    T.qdd[i] = qdd;
-    T.a[i] = a1 + sv(qdd * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
-    ap = T.a[i];
-  }
-}
-
-__host__ __device__ __forceinline__ void arm_step(const ArmConst& K, const float* th, float time, float dt, float* q,
-                                         float* qd) {
-  keep_consts_in_memory();
-  ArmTape T;
-  arm_aba(K, th, q, qd, time, T);
-#pragma unroll
-  for (int i = 0; i < kArmBodies; ++i) {
-    keep_consts_in_memory();
-    qd[i] = qd[i] + dt * T.qdd[i];
-    q[i] = q[i] + dt * qd[i];
-  }
-}
-
-// Reverse of one Euler step.  (qb, qdb) enter as adjoints of the step's
-// outputs and leave as adjoints of its inputs; thb accumulates d/d theta.
-__host__ __device__ __forceinline__ void arm_step_rev(const ArmConst& K, const float* th, const float* q, const float* qd,
-                                             const ArmTape& T, float dt, float* qb, float* qdb, float* thb) {
-  keep_consts_in_memory();
-  // Euler: q' = q + dt qd', qd' = qd + dt qdd
-  float qddb[kArmBodies];
-  #pragma unroll
-  for (int i = 0; i < kArmBodies; ++i) {
-    keep_consts_in_memory();
-    qdb[i] += dt * qb[i];
-    qddb[i] = dt * qdb[i];
-  }
-  // lambda = H^{-1} qddb: ABA with zero velocity and gravity (the child's
-  // bias-force contribution is carried inward).
-  float lam[kArmBodies], us[kArmBodies];
-  {
+    Sym6 IAc;  // child's contribution X^T Ia X
     SV pAc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
-#pragma unroll
+  #pragma unroll
+    for (int e = 0; e < 6; ++e) { IAc.A[e] = 0.f; IAc.C[e] = 0.f; }
+  #pragma unroll
+    for (int e = 0; e < 9; ++e) IAc.B[e] = 0.f;
+  #pragma unroll
     for (int i = kArmBodies - 1; i >= 0; --i) {
       keep_consts_in_memory();
       const int k = axis_of(i);
-      us[i] = qddb[i] - comp(pAc.a, k);
+      const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
+      Sym6 IA = IAc;
+      add_rbi(IA, K.m[i], cm, K.Ic[i]);
+      SV h = rbi_mul(K.m[i], cm, K.Ic[i], T.v[i]);
+      if (i == 7) {
+        add_rbi(IA, K.pm_m, ca, z0);
+        add_rbi(IA, K.pm_m, cb, z0);
+        h = h + pm_mul(K.pm_m, ca, T.v[i]) + pm_mul(K.pm_m, cb, T.v[i]);
+      }
+      const SV pA = crf(T.v[i], h) + pAc;
+      const SV U = sv(v3(s3(IA.A, 0, k), s3(IA.A, 1, k), s3(IA.A, 2, k)),
+                      v3(IA.B[3 * k], IA.B[3 * k + 1], IA.B[3 * k + 2]));
+      const R invD = 1.0f / comp(U.a, k);
+      u[i] = arm_tau(K, i, time, q[i], qd[i]) - comp(pA.a, k);
+      T.U[i] = U;
+      T.invD[i] = invD;
       if (i > 0) {
-        float E[9];
+        Sym6 Ia = IA;
+        const R Uw[3] = {U.a.x, U.a.y, U.a.z}, Uv[3] = {U.l.x, U.l.y, U.l.z};
+        const int si[6] = {0, 0, 0, 1, 1, 2}, sj[6] = {0, 1, 2, 1, 2, 2};
+  #pragma unroll
+        for (int e = 0; e < 6; ++e) {
+          Ia.A[e] -= Uw[si[e]] * Uw[sj[e]] * invD;
+          Ia.C[e] -= Uv[si[e]] * Uv[sj[e]] * invD;
+        }
+  #pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2)
+  #pragma unroll
+          for (int b2 = 0; b2 < 3; ++b2) Ia.B[3 * a2 + b2] -= Uw[a2] * Uv[b2] * invD;
+        const SV ci = crm(T.v[i], sv(qd[i] * unit(k), v3(0.f, 0.f, 0.f)));
+        const SV pa = pA + sym6_mul(Ia, ci) + (u[i] * invD) * U;
+        R E[9];
         body_E(K, i, T.cs[i], T.sn[i], E);
         const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
-        pAc = xtf(E, r, pAc + (us[i] * T.invD[i]) * T.U[i]);
+  #pragma unroll
+        for (int e = 0; e < 6; ++e) { IAc.A[e] = 0.f; IAc.C[e] = 0.f; }
+  #pragma unroll
+        for (int e = 0; e < 9; ++e) IAc.B[e] = 0.f;
+        add_xtix(IAc, Ia, E, r);
+        pAc = xtf(E, r, pa);
       }
     }
-  }
-  {
-    SV ap = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
-#pragma unroll
+    SV ap = sv(v3(0.f, 0.f, 0.f), v3(-K.g[0], -K.g[1], -K.g[2]));
+  #pragma unroll
     for (int i = 0; i < kArmBodies; ++i) {
       keep_consts_in_memory();
-      float E[9];
+      R E[9];
       body_E(K, i, T.cs[i], T.sn[i], E);
       const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
-      const SV a1 = xm(E, r, ap);
-      lam[i] = (us[i] - sdot(T.U[i], a1)) * T.invD[i];
-      ap = a1 + sv(lam[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+      const SV ci = crm(T.v[i], sv(qd[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f)));
+      const SV a1 = xm(E, r, ap) + ci;
+      const R qdd = (u[i] - sdot(T.U[i], a1)) * T.invD[i];
+      T.qdd[i] = qdd;
+      T.a[i] = a1 + sv(qdd * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+      ap = T.a[i];
     }
   }
-  // x_bar += -lambda^T dF/dx, F = ID - tau.  The tau part:
-  // d tau / d q = -kp, d tau / d qd = -kd (arm), -bh (hinge).
+
+  __host__ __device__ static __forceinline__ void arm_step(const ArmConst& K, const R* th, R time, R dt, R* q,
+                                           R* qd) {
+    keep_consts_in_memory();
+    ArmTape T;
+    arm_aba(K, th, q, qd, time, T);
   #pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    keep_consts_in_memory();
-    qb[i] += -K.kp[i] * lam[i];
-    qdb[i] += -K.kd[i] * lam[i];
-  }
-  qdb[7] += -K.bh * lam[7];
-  // ID part: reverse of RNEA with output seed mu = -lambda.  Total-force
-  // adjoints first (outward; they do not depend on the forces):
-  // ftb_i = S_i mu_i + X_i ftb_{i-1}.
-  const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
-  SV ftb[kArmBodies];
-#pragma unroll
-  for (int i = 0; i < kArmBodies; ++i) {
-    keep_consts_in_memory();
-    SV b = sv((-lam[i]) * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
-    if (i > 0) {
-      float E[9];
-      body_E(K, i, T.cs[i], T.sn[i], E);
-      const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
-      b = b + xf(E, r, ftb[i - 1]);
+    for (int i = 0; i < kArmBodies; ++i) {
+      keep_consts_in_memory();
+      qd[i] = qd[i] + dt * T.qdd[i];
+      q[i] = q[i] + dt * qd[i];
     }
-    ftb[i] = b;
   }
-  // Inward: total forces ft_i = f_i + X_{i+1}^T ft_{i+1} (carried), the
-  // q dependence of X_i^T ft_i, and the reverse of the outward pass
-  // (velocities, accelerations) with body-force adjoints ftb_i.
-  SV ftc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));  // X_{i+1}^T ft_{i+1}
-  SV abar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
-  SV vbar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
-#pragma unroll
-  for (int i = kArmBodies - 1; i >= 0; --i) {
+
+  // Reverse of one Euler step.  (qb, qdb) enter as adjoints of the step's
+  // outputs and leave as adjoints of its inputs; thb accumulates d/d theta.
+  __host__ __device__ static __forceinline__ void arm_step_rev(const ArmConst& K, const R* th, const R* q, const R* qd,
+                                               const ArmTape& T, R dt, R* qb, R* qdb, R* thb) {
     keep_consts_in_memory();
-    const SV fb = ftb[i];
-    const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
-    const SV v = T.v[i], a = T.a[i];
-    const V3 ax = unit(axis_of(i));
-    const SV sax = sv(ax, v3(0.f, 0.f, 0.f));
-    // body force and total force
-    SV Ia = rbi_mul(K.m[i], cm, K.Ic[i], a);
-    SV h = rbi_mul(K.m[i], cm, K.Ic[i], v);
-    SV Ifb = rbi_mul(K.m[i], cm, K.Ic[i], fb);
-    const SV vxfb = crm(v, fb);
-    SV Ivxfb = rbi_mul(K.m[i], cm, K.Ic[i], vxfb);
-    if (i == 7) {
-      Ia = Ia + pm_mul(K.pm_m, ca, a) + pm_mul(K.pm_m, cb, a);
-      h = h + pm_mul(K.pm_m, ca, v) + pm_mul(K.pm_m, cb, v);
-      Ifb = Ifb + pm_mul(K.pm_m, ca, fb) + pm_mul(K.pm_m, cb, fb);
-      Ivxfb = Ivxfb + pm_mul(K.pm_m, ca, vxfb) + pm_mul(K.pm_m, cb, vxfb);
-      // theta: the point-mass positions (x, y) in f = I(c) a + v x* I(c) v.
-      // With g(c; x, y) = y . I(c) x = y_n . (c x p) + y_f . p and
-      // p = m (x_l - c x x_w):  dg/dc = p x y_n - m x_w x (y_n x c + y_f).
-      // fb . f = g(c; a, fb) + g(c; v, -v x fb)  (fb . (v x* h) = -(v x fb) . h).
-#pragma unroll
-      for (int w = 0; w < 2; ++w) {
-        const V3 cp = w == 0 ? ca : cb;
-        const float mm = K.pm_m;
-        V3 gsum = v3(0.f, 0.f, 0.f);
-#pragma unroll
-        for (int term = 0; term < 2; ++term) {
-          const SV x = term == 0 ? a : v;
-          const SV y = term == 0 ? fb : sv(-vxfb.a, -vxfb.l);
-          const V3 p = mm * (x.l - cross(cp, x.a));
-          const V3 z = cross(y.a, cp) + y.l;
-          gsum = gsum + cross(p, y.a) - mm * cross(x.a, z);
+    // Euler: q' = q + dt qd', qd' = qd + dt qdd
+    R qddb[kArmBodies];
+    #pragma unroll
+    for (int i = 0; i < kArmBodies; ++i) {
+      keep_consts_in_memory();
+      qdb[i] += dt * qb[i];
+      qddb[i] = dt * qdb[i];
+    }
+    // lambda = H^{-1} qddb: ABA with zero velocity and gravity (the child's
+    // bias-force contribution is carried inward).
+    R lam[kArmBodies], us[kArmBodies];
+    {
+      SV pAc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+  #pragma unroll
+      for (int i = kArmBodies - 1; i >= 0; --i) {
+        keep_consts_in_memory();
+        const int k = axis_of(i);
+        us[i] = qddb[i] - comp(pAc.a, k);
+        if (i > 0) {
+          R E[9];
+          body_E(K, i, T.cs[i], T.sn[i], E);
+          const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+          pAc = xtf(E, r, pAc + (us[i] * T.invD[i]) * T.U[i]);
         }
-        thb[2 * w] += gsum.x;
-        thb[2 * w + 1] += gsum.y;
       }
     }
-    const SV ft = Ia + crf(v, h) + ftc;
-    float E[9];
-    body_E(K, i, T.cs[i], T.sn[i], E);
-    const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
-    if (i > 0) {
-      // d/dq_i of ftb_{i-1} . X_i^T ft_i = (X_i ftb_{i-1}) . (S x* ft_i)
-      qb[i] += sdot(xf(E, r, ftb[i - 1]), crf(sax, ft));
-      ftc = xtf(E, r, ft);
+    {
+      SV ap = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+  #pragma unroll
+      for (int i = 0; i < kArmBodies; ++i) {
+        keep_consts_in_memory();
+        R E[9];
+        body_E(K, i, T.cs[i], T.sn[i], E);
+        const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+        const SV a1 = xm(E, r, ap);
+        lam[i] = (us[i] - sdot(T.U[i], a1)) * T.invD[i];
+        ap = a1 + sv(lam[i] * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+      }
     }
-    // f = I a + v x* (I v):  a_bar += I fb;  v_bar += -crf(fb) h - I (v x fb)
-    abar = abar + Ifb;
-    vbar = vbar - crf(fb, h) - Ivxfb;
-    // a_i = X_i a_{i-1} + v_i x (S qd_i) + S qdd_i (qdd held fixed)
-    const SV sq = sv(qd[i] * ax, v3(0.f, 0.f, 0.f));
-    vbar = vbar + crf(sq, abar);
-    qdb[i] += -comp(crf(v, abar).a, axis_of(i));
-    // v_i = X_i v_{i-1} + S qd_i
-    qdb[i] += comp(vbar.a, axis_of(i));
-    if (i > 0) {
-      const SV ya = xm(E, r, T.a[i - 1]), yv = xm(E, r, T.v[i - 1]);
-      // d/dq (abar . X a_prev) = -abar . (S x y)
-      qb[i] += -sdot(abar, crm(sax, ya)) - sdot(vbar, crm(sax, yv));
-      abar = xtm(E, r, abar);
-      vbar = xtm(E, r, vbar);
-    } else {
-      // body 0: its parent is the fixed base (gravity as base acceleration)
-      const SV ya = xm(E, r, sv(v3(0.f, 0.f, 0.f), v3(-K.g[0], -K.g[1], -K.g[2])));
-      qb[0] += -sdot(abar, crm(sax, ya));
+    // x_bar += -lambda^T dF/dx, F = ID - tau.  The tau part:
+    // d tau / d q = -kp, d tau / d qd = -kd (arm), -bh (hinge).
+    #pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      keep_consts_in_memory();
+      qb[i] += -K.kp[i] * lam[i];
+      qdb[i] += -K.kd[i] * lam[i];
+    }
+    qdb[7] += -K.bh * lam[7];
+    // ID part: reverse of RNEA with output seed mu = -lambda.  Total-force
+    // adjoints first (outward; they do not depend on the forces):
+    // ftb_i = S_i mu_i + X_i ftb_{i-1}.
+    const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
+    SV ftb[kArmBodies];
+  #pragma unroll
+    for (int i = 0; i < kArmBodies; ++i) {
+      keep_consts_in_memory();
+      SV b = sv((-lam[i]) * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
+      if (i > 0) {
+        R E[9];
+        body_E(K, i, T.cs[i], T.sn[i], E);
+        const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+        b = b + xf(E, r, ftb[i - 1]);
+      }
+      ftb[i] = b;
+    }
+    // Inward: total forces ft_i = f_i + X_{i+1}^T ft_{i+1} (carried), the
+    // q dependence of X_i^T ft_i, and the reverse of the outward pass
+    // (velocities, accelerations) with body-force adjoints ftb_i.
+    SV ftc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));  // X_{i+1}^T ft_{i+1}
+    SV abar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+    SV vbar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
+  #pragma unroll
+    for (int i = kArmBodies - 1; i >= 0; --i) {
+      keep_consts_in_memory();
+      const SV fb = ftb[i];
+      const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
+      const SV v = T.v[i], a = T.a[i];
+      const V3 ax = unit(axis_of(i));
+      const SV sax = sv(ax, v3(0.f, 0.f, 0.f));
+      // body force and total force
+      SV Ia = rbi_mul(K.m[i], cm, K.Ic[i], a);
+      SV h = rbi_mul(K.m[i], cm, K.Ic[i], v);
+      SV Ifb = rbi_mul(K.m[i], cm, K.Ic[i], fb);
+      const SV vxfb = crm(v, fb);
+      SV Ivxfb = rbi_mul(K.m[i], cm, K.Ic[i], vxfb);
+      if (i == 7) {
+        Ia = Ia + pm_mul(K.pm_m, ca, a) + pm_mul(K.pm_m, cb, a);
+        h = h + pm_mul(K.pm_m, ca, v) + pm_mul(K.pm_m, cb, v);
+        Ifb = Ifb + pm_mul(K.pm_m, ca, fb) + pm_mul(K.pm_m, cb, fb);
+        Ivxfb = Ivxfb + pm_mul(K.pm_m, ca, vxfb) + pm_mul(K.pm_m, cb, vxfb);
+        // theta: the point-mass positions (x, y) in f = I(c) a + v x* I(c) v.
+        // With g(c; x, y) = y . I(c) x = y_n . (c x p) + y_f . p and
+        // p = m (x_l - c x x_w):  dg/dc = p x y_n - m x_w x (y_n x c + y_f).
+        // fb . f = g(c; a, fb) + g(c; v, -v x fb)  (fb . (v x* h) = -(v x fb) . h).
+  #pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          const V3 cp = w == 0 ? ca : cb;
+          const float mm = K.pm_m;
+          V3 gsum = v3(0.f, 0.f, 0.f);
+  #pragma unroll
+          for (int term = 0; term < 2; ++term) {
+            const SV x = term == 0 ? a : v;
+            const SV y = term == 0 ? fb : sv(-vxfb.a, -vxfb.l);
+            const V3 p = mm * (x.l - cross(cp, x.a));
+            const V3 z = cross(y.a, cp) + y.l;
+            gsum = gsum + cross(p, y.a) - mm * cross(x.a, z);
+          }
+          thb[2 * w] += gsum.x;
+          thb[2 * w + 1] += gsum.y;
+        }
+      }
+      const SV ft = Ia + crf(v, h) + ftc;
+      R E[9];
+      body_E(K, i, T.cs[i], T.sn[i], E);
+      const V3 r = v3(K.r[i][0], K.r[i][1], K.r[i][2]);
+      if (i > 0) {
+        // d/dq_i of ftb_{i-1} . X_i^T ft_i = (X_i ftb_{i-1}) . (S x* ft_i)
+        qb[i] += sdot(xf(E, r, ftb[i - 1]), crf(sax, ft));
+        ftc = xtf(E, r, ft);
+      }
+      // f = I a + v x* (I v):  a_bar += I fb;  v_bar += -crf(fb) h - I (v x fb)
+      abar = abar + Ifb;
+      vbar = vbar - crf(fb, h) - Ivxfb;
+      // a_i = X_i a_{i-1} + v_i x (S qd_i) + S qdd_i (qdd held fixed)
+      const SV sq = sv(qd[i] * ax, v3(0.f, 0.f, 0.f));
+      vbar = vbar + crf(sq, abar);
+      qdb[i] += -comp(crf(v, abar).a, axis_of(i));
+      // v_i = X_i v_{i-1} + S qd_i
+      qdb[i] += comp(vbar.a, axis_of(i));
+      if (i > 0) {
+        const SV ya = xm(E, r, T.a[i - 1]), yv = xm(E, r, T.v[i - 1]);
+        // d/dq (abar . X a_prev) = -abar . (S x y)
+        qb[i] += -sdot(abar, crm(sax, ya)) - sdot(vbar, crm(sax, yv));
+        abar = xtm(E, r, abar);
+        vbar = xtm(E, r, vbar);
+      } else {
+        // body 0: its parent is the fixed base (gravity as base acceleration)
+        const SV ya = xm(E, r, sv(v3(0.f, 0.f, 0.f), v3(-K.g[0], -K.g[1], -K.g[2])));
+        qb[0] += -sdot(abar, crm(sax, ya));
+      }
     }
   }
-}
+};
 
 // Raw model description -> derived constants (the caller's consts array:
 // gravity[3]; per arm joint 7 x (a, alpha, d, m, cx, cy, cz, Ixx, Iyy, Izz,
@@ -547,6 +557,8 @@ __host__ __device__ inline void arm_setup(const float* raw, ArmConst* K) {
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
+
+using AM = ArmMath<float>;
 
 __device__ inline const ArmConst* arm_const_of(char* ws, uint64_t off) {
   return reinterpret_cast<const ArmConst*>(ws + off);
@@ -595,7 +607,7 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   const float wx = J.w_x[0];
   double ll = 0.0;
   for (int s = 0; s < J.h; ++s) {
-    arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+    AM::arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
     if (with_ll) {
       const float r = (obs[s] - q[7]) * wx;
       ll -= 0.5 * (double)(r * r);
@@ -676,7 +688,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
       const int sl = full ? s : s / B;
       for (int d = 0; d < 8; ++d) { slot(sl, d) = q[d]; slot(sl, 8 + d) = qd[d]; }
     }
-    arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+    AM::arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
     const float r = (obs[s] - q[7]) * wx;
     ll -= 0.5 * (double)(r * r);
   }
@@ -723,7 +735,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
       for (int d = 0; d < 8; ++d) { q[d] = slot(sg, d); qd[d] = slot(sg, 8 + d); }
       for (int d = 0; d < 8; ++d) { slot(segbase, d) = q[d]; slot(segbase, 8 + d) = qd[d]; }
       for (int s = a; s < bnd; ++s) {
-        arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+        AM::arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
         for (int d = 0; d < 8; ++d) {
           slot(segbase + s - a + 1, d) = q[d];
           slot(segbase + s - a + 1, 8 + d) = qd[d];
@@ -738,15 +750,15 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
       }
       float qs[8], qds[8];
       for (int d = 0; d < 8; ++d) { qs[d] = slot(segbase + s - a, d); qds[d] = slot(segbase + s - a, 8 + d); }
-      ArmTape T;
+      AM::ArmTape T;
       const float time = (float)(t0 + s) * dt;
-      keep_consts_in_memory();
-      arm_aba(K, th, qs, qds, time, T);
+      AM::keep_consts_in_memory();
+      AM::arm_aba(K, th, qs, qds, time, T);
       float tb[4] = {0.f, 0.f, 0.f, 0.f};
-      arm_step_rev(K, th, qs, qds, T, dt, qb_o, qdb_o, tb);
+      AM::arm_step_rev(K, th, qs, qds, T, dt, qb_o, qdb_o, tb);
       for (int m = 0; m < 4; ++m) gm_o[m] += (double)tb[m];
       float tc[4] = {0.f, 0.f, 0.f, 0.f};
-      arm_step_rev(K, th, qs, qds, T, dt, qb_c, qdb_c, tc);
+      AM::arm_step_rev(K, th, qs, qds, T, dt, qb_c, qdb_c, tc);
       for (int m = 0; m < 4; ++m) gm_c[m] += (double)tc[m];
     }
   }
@@ -786,5 +798,40 @@ hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws
 }
 
 int arm_seg_len_host(int h) { return arm_seg_len(h); }
+
+// Algorithmic FLOPs of one arm time step: the forward step (ABA + Euler +
+// the observation residual and its FP64 accumulation) and the reverse step
+// of one adjoint channel (with its observation seed and the FP64
+// accumulation of the parameter adjoints), from the same step functions
+// the kernels run, instantiated with the counting scalar.
+void count_arm_flops(double* fwd, double* rev, double* transc) {
+  using CM = ArmMath<Counted>;
+  ArmConst K;
+  std::vector<float> raw(126, 0.5f);
+  raw[0] = 0.f;
+  raw[1] = 0.f;
+  raw[2] = -9.81f;
+  arm_setup(raw.data(), &K);
+  Counted th[4] = {0.05f, 0.02f, -0.04f, 0.03f};
+  Counted q[8], qd[8], qb[8], qdb[8], thb[4];
+  for (int i = 0; i < 8; ++i) {
+    q[i] = Counted(0.1f * i);
+    qd[i] = Counted(0.05f);
+    qb[i] = Counted(1.f);
+    qdb[i] = Counted(1.f);
+  }
+  g_tally = FlopTally();
+  CM::ArmTape T;
+  CM::arm_aba(K, th, q, qd, Counted(0.5f), T);
+  for (int i = 0; i < 8; ++i) {
+    qd[i] = qd[i] + Counted(0.004f) * T.qdd[i];
+    q[i] = q[i] + Counted(0.004f) * qd[i];
+  }
+  *fwd = g_tally.flops + 4.0;  // residual (x - q) w, its square, FP64 accumulate
+  *transc = g_tally.transc;
+  g_tally = FlopTally();
+  CM::arm_step_rev(K, th, q, qd, T, Counted(0.004f), qb, qdb, thb);
+  *rev = g_tally.flops + 2.0 + 4.0;  // observation seed r w; FP64 accumulation of 4 parameter adjoints
+}
 
 }  // namespace pds

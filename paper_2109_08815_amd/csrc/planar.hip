@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "flop_count.h"
 
 namespace pds {
 namespace {
@@ -707,38 +708,6 @@ int planar_seg_len(int h) { return seg_len_of(h); }
 // scalar (add, sub, mul, div each 1; negation 0; sin/cos tallied apart).
 // ---------------------------------------------------------------------------
 namespace {
-struct FlopTally {
-  double flops = 0, transc = 0;
-};
-FlopTally g_tally;
-
-struct Counted {
-  float v;
-  Counted() : v(0.f) {}
-  Counted(float x) : v(x) {}  // NOLINT: implicit from literals, like float
-};
-inline Counted operator+(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v + b.v); }
-inline Counted operator-(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v - b.v); }
-inline Counted operator*(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v * b.v); }
-inline Counted operator/(Counted a, Counted b) { g_tally.flops += 1; return Counted(a.v / b.v); }
-inline Counted operator-(Counted a) { return Counted(-a.v); }
-inline Counted operator+(float a, Counted b) { return Counted(a) + b; }
-inline Counted operator-(float a, Counted b) { return Counted(a) - b; }
-inline Counted operator*(float a, Counted b) { return Counted(a) * b; }
-inline Counted operator/(float a, Counted b) { return Counted(a) / b; }
-inline Counted operator+(Counted a, float b) { return a + Counted(b); }
-inline Counted operator-(Counted a, float b) { return a - Counted(b); }
-inline Counted operator*(Counted a, float b) { return a * Counted(b); }
-inline Counted& operator+=(Counted& a, Counted b) { a = a + b; return a; }
-inline Counted& operator-=(Counted& a, Counted b) { a = a - b; return a; }
-inline void sincos_r(Counted x, Counted* sn, Counted* cs) {
-  g_tally.transc += 2;
-  float s, c;
-  sincosf(x.v, &s, &c);
-  *sn = Counted(s);
-  *cs = Counted(c);
-}
-
 template <int NB>
 void count_planar(double* fwd, double* rev, double* transc) {
   Planar<NB, Counted> P;
@@ -767,7 +736,12 @@ void count_planar(double* fwd, double* rev, double* transc) {
 
 extern "C" int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_step, double* rev_step,
                                      double* transcendental) {
-  if (model != PDS_MODEL_PLANAR || !fwd_step || !rev_step || !transcendental) return PDS_EINVAL;
+  if (!fwd_step || !rev_step || !transcendental) return PDS_EINVAL;
+  if (model == PDS_MODEL_ARM) {
+    count_arm_flops(fwd_step, rev_step, transcendental);
+    return PDS_OK;
+  }
+  if (model != PDS_MODEL_PLANAR) return PDS_EINVAL;
   switch (n_dof) {
     case 1: count_planar<1>(fwd_step, rev_step, transcendental); break;
     case 2: count_planar<2>(fwd_step, rev_step, transcendental); break;

@@ -307,6 +307,7 @@ def _footprint_cached():
 
 def _summary(records, wall, ticks, rejected):
     recs = [r for r in records.values() if r.theta is not None]
+    nonfinite = sum(1 for r in recs if not np.isfinite(r.theta).all())
     lat = np.array([r.latency for r in recs]) if recs else np.zeros(0)
     steps = sum(r.spec.N * r.spec.K * r.spec.T * r.spec.iterations for r in recs)
     return {
@@ -319,21 +320,34 @@ def _summary(records, wall, ticks, rejected):
         "latency_p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
         "latency_mean_s": float(lat.mean()) if len(lat) else None,
         "ticks": ticks,
+        "jobs_with_nonfinite_particles": nonfinite,
+        "nonfinite_jobs": [dict(job=r.spec.job_id, family=r.spec.family, N=r.spec.N, K=r.spec.K, T=r.spec.T)
+                           for r in recs if not np.isfinite(r.theta).all()],
         "records": records,
     }
 
 
 def same_results(a: dict, b: dict) -> tuple[int, int]:
-    """(jobs compared, jobs whose particles and log-likelihoods differ)."""
-    n = bad = 0
+    """(jobs compared, jobs whose particles or log-likelihoods differ bitwise;
+    NaN matches NaN)."""
+    n, bad = 0, compare_results(a, b)
+    for jid, ra in a["records"].items():
+        rb = b["records"].get(jid)
+        if ra.theta is not None and rb is not None and rb.theta is not None:
+            n += 1
+    return n, len(bad)
+
+
+def compare_results(a: dict, b: dict) -> list:
+    """Ids of jobs present in both runs whose results differ bitwise."""
+    out = []
     for jid, ra in a["records"].items():
         rb = b["records"].get(jid)
         if ra.theta is None or rb is None or rb.theta is None:
             continue
-        n += 1
-        if not (np.array_equal(ra.theta, rb.theta) and np.array_equal(ra.logp, rb.logp, equal_nan=True)):
-            bad += 1
-    return n, bad
+        if not (np.array_equal(ra.theta, rb.theta, equal_nan=True) and np.array_equal(ra.logp, rb.logp, equal_nan=True)):
+            out.append(jid)
+    return out
 
 
 def _strip(summary):
@@ -378,6 +392,12 @@ def main(argv=None):
             entry["sequential"] = _strip(seq)
             entry["compared_jobs"] = n
             entry["jobs_differing"] = bad
+            diff = compare_results(bat, seq)
+            entry["differing"] = [dict(job=j, spec=dataclasses.asdict(bat["records"][j].spec),
+                                       nonfinite_theta=int((~np.isfinite(bat["records"][j].theta)).sum()),
+                                       max_abs_diff=float(np.nanmax(np.abs(bat["records"][j].theta
+                                                                           - seq["records"][j].theta))))
+                                  for j in diff]
             print("load %.2f sequential: p50 %.3f s p99 %.3f s; %d/%d jobs bitwise equal" % (
                 load, seq["latency_p50_s"], seq["latency_p99_s"], n - bad, n), file=sys.stderr, flush=True)
         out["load"][str(load)] = entry

@@ -104,3 +104,18 @@ def test_workspace_size_grows_with_problem():
     b = lib.pds_workspace_size(big, 1, L.PDS_CALL_ADJOINT)
     assert 0 < a < b
     assert b % 256 == 0
+
+
+def test_algorithmic_flop_counts():
+    """The counting scalar runs the library's own step functions: planar
+    counts grow linearly with the links; the arm step evaluates sin and cos
+    of its 8 joint angles and of the 7 desired-trajectory phases."""
+    planar = [L.algorithmic_flops(L.PDS_MODEL_PLANAR, n) for n in range(1, 6)]
+    fwd = np.array([p[0] for p in planar])
+    rev = np.array([p[1] for p in planar])
+    assert np.all(np.diff(fwd, 2) == 0) and np.all(np.diff(rev, 2) == 0)
+    assert [p[2] for p in planar] == [2.0 * n for n in range(1, 6)]
+    f, r, t = L.algorithmic_flops(L.PDS_MODEL_ARM, 8)
+    assert t == 2 * 8 + 2 * 7
+    assert f > 1000 and r > 1000
+    assert L.algorithmic_flops(L.PDS_MODEL_ARM, 8) == (f, r, t)
