@@ -641,18 +641,14 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   if (bad && J.flags) atomicOr(&J.flags[w.i], 1);
 }
 
-__host__ __device__ inline int arm_seg_len(int h) {
-  int B = 1;
-  while (B * B < h) ++B;
-  return B;
-}
 
-// Adjoint kernel: one lane per unit, both adjoint channels; window states in
-// LDS (whole window when `full`, else sqrt(h) checkpoints plus the segment
-// being reversed).
+// Adjoint kernel: one lane per unit, both adjoint channels.  The forward
+// pass stores every state of the window in the job's workspace (layout
+// [wave][step][component][lane], so each access is one coalesced row); the
+// reverse sweep reads them back and recomputes only the step's own ABA
+// intermediates.  No LDS: occupancy is set by registers alone.
 __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                            char* ws, int full) {
-  extern __shared__ float lds[];
+                                                            char* ws) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const ArmConst& K = *arm_const_of(ws, map.ws_off[e]);
@@ -674,26 +670,20 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   for (int d = 0; d < 8; ++d) { q[d] = st[d]; qd[d] = st[8 + d]; }
   const float dt = J.dt;
   const int h = J.h;
-  const int B = full ? h : arm_seg_len(h);
-  const int nseg = (h + B - 1) / B;
-  const int segbase = full ? 0 : nseg;
   const int t0 = w.j * h;
   const float* obs = J.obs + ((size_t)w.k * J.T + t0);
   const float wx = J.w_x[0];
-  auto slot = [&](int s, int d) -> float& { return lds[((size_t)s * kArmDs + d) * kWave + lane]; };
+  float* states = reinterpret_cast<float*>(base + L.arm_states) + (size_t)(u / kWave) * (h + 1) * kArmDs * kWave;
+  auto slot = [&](int s, int d) -> float& { return states[((size_t)s * kArmDs + d) * kWave + lane]; };
 
   double ll = 0.0;
   for (int s = 0; s < h; ++s) {
-    if (full || s % B == 0) {
-      const int sl = full ? s : s / B;
-      for (int d = 0; d < 8; ++d) { slot(sl, d) = q[d]; slot(sl, 8 + d) = qd[d]; }
-    }
+    for (int d = 0; d < 8; ++d) { slot(s, d) = q[d]; slot(s, 8 + d) = qd[d]; }
     AM::arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
     const float r = (obs[s] - q[7]) * wx;
     ll -= 0.5 * (double)(r * r);
   }
-  if (full)
-    for (int d = 0; d < 8; ++d) { slot(h, d) = q[d]; slot(h, 8 + d) = qd[d]; }
+  for (int d = 0; d < 8; ++d) { slot(h, d) = q[d]; slot(h, 8 + d) = qd[d]; }
   ll += (double)h * (log((double)wx) - 0.91893853320467274178);
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
   float* es = J.end_states + iu * kArmDs;
@@ -728,39 +718,24 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
     }
   }
   double gm_o[4] = {0.0, 0.0, 0.0, 0.0}, gm_c[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int sg = nseg - 1; sg >= 0; --sg) {
-    const int a = sg * B;
-    const int bnd = min(h, a + B);
-    if (!full) {
-      for (int d = 0; d < 8; ++d) { q[d] = slot(sg, d); qd[d] = slot(sg, 8 + d); }
-      for (int d = 0; d < 8; ++d) { slot(segbase, d) = q[d]; slot(segbase, 8 + d) = qd[d]; }
-      for (int s = a; s < bnd; ++s) {
-        AM::arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
-        for (int d = 0; d < 8; ++d) {
-          slot(segbase + s - a + 1, d) = q[d];
-          slot(segbase + s - a + 1, 8 + d) = qd[d];
-        }
-      }
+  for (int s = h - 1; s >= 0; --s) {
+    {
+      const float x = slot(s + 1, 7);
+      const float r = (obs[s] - x) * wx;
+      qb_o[7] += r * wx;
     }
-    for (int s = bnd - 1; s >= a; --s) {
-      {
-        const float x = slot(segbase + s - a + 1, 7);
-        const float r = (obs[s] - x) * wx;
-        qb_o[7] += r * wx;
-      }
-      float qs[8], qds[8];
-      for (int d = 0; d < 8; ++d) { qs[d] = slot(segbase + s - a, d); qds[d] = slot(segbase + s - a, 8 + d); }
-      AM::ArmTape T;
-      const float time = (float)(t0 + s) * dt;
-      AM::keep_consts_in_memory();
-      AM::arm_aba(K, th, qs, qds, time, T);
-      float tb[4] = {0.f, 0.f, 0.f, 0.f};
-      AM::arm_step_rev(K, th, qs, qds, T, dt, qb_o, qdb_o, tb);
-      for (int m = 0; m < 4; ++m) gm_o[m] += (double)tb[m];
-      float tc[4] = {0.f, 0.f, 0.f, 0.f};
-      AM::arm_step_rev(K, th, qs, qds, T, dt, qb_c, qdb_c, tc);
-      for (int m = 0; m < 4; ++m) gm_c[m] += (double)tc[m];
-    }
+    float qs[8], qds[8];
+    for (int d = 0; d < 8; ++d) { qs[d] = slot(s, d); qds[d] = slot(s, 8 + d); }
+    AM::ArmTape T;
+    const float time = (float)(t0 + s) * dt;
+    AM::keep_consts_in_memory();
+    AM::arm_aba(K, th, qs, qds, time, T);
+    float tb[4] = {0.f, 0.f, 0.f, 0.f};
+    AM::arm_step_rev(K, th, qs, qds, T, dt, qb_o, qdb_o, tb);
+    for (int m = 0; m < 4; ++m) gm_o[m] += (double)tb[m];
+    float tc[4] = {0.f, 0.f, 0.f, 0.f};
+    AM::arm_step_rev(K, th, qs, qds, T, dt, qb_c, qdb_c, tc);
+    for (int m = 0; m < 4; ++m) gm_c[m] += (double)tc[m];
   }
   for (int m = 0; m < 4; ++m) {
     gth_obs[(size_t)m * U + u] = gm_o[m];
@@ -791,13 +766,10 @@ hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws
   return hipGetLastError();
 }
 
-hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool full,
-                              size_t lds_bytes, hipStream_t s) {
-  hipLaunchKernelGGL(arm_adjoint_kernel, dim3(grid), dim3(kWave), lds_bytes, s, map, d_jobs, ws, full ? 1 : 0);
+hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(arm_adjoint_kernel, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws);
   return hipGetLastError();
 }
-
-int arm_seg_len_host(int h) { return arm_seg_len(h); }
 
 // Algorithmic FLOPs of one arm time step: the forward step (ABA + Euler +
 // the observation residual and its FP64 accumulation) and the reverse step

@@ -49,6 +49,7 @@ struct MedianState {
 // use a region of just that size.
 struct WsLayout {
   size_t arm;                               // derived arm constants (arm jobs)
+  size_t arm_states;                        // arm adjoint: every window state, [wave][step][16][lane]
   size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients
   size_t med;                               // median selection state
   size_t khi, klo;                          // median key words (all pairs, or a sample's high words)
@@ -67,6 +68,9 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   const int ds = 2 * J.n_dof;
   size_t o = 0;
   L.arm = o;     o = align256(o + (J.model == PDS_MODEL_ARM ? kArmConstBytes : 0));
+  const size_t lanes = (U + kWave - 1) / kWave * kWave;
+  L.arm_states = o;
+  o = align256(o + (J.model == PDS_MODEL_ARM ? lanes * (J.h + 1) * 16 * sizeof(float) : 0));
   L.gth_obs = o; o = align256(o + U * J.M * sizeof(double));
   L.gth_con = o; o = align256(o + U * J.M * sizeof(double));
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
@@ -102,9 +106,7 @@ hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, 
 hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
                               hipStream_t s);
-hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool full,
-                              size_t lds_bytes, hipStream_t s);
-int arm_seg_len_host(int h);
+hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
                               hipStream_t s);
 hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);

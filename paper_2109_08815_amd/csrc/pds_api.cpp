@@ -235,8 +235,8 @@ int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with
 // Adjoint launch shape of one job, from its own size.  Planar: with fewer
 // waves than SIMDs the two adjoint channels go to two lanes per unit
 // (split); whole windows stay in LDS (full) when every wave of the job can
-// be resident at once, else sqrt(h) checkpoints.  Arm: one lane per unit,
-// full by the same rule.
+// be resident at once, else sqrt(h) checkpoints.  (The arm adjoint keeps
+// its window states in the workspace and has one shape.)
 struct AdjShape {
   bool split, full;
   size_t lds;  // dynamic LDS bytes per block
@@ -255,21 +255,6 @@ AdjShape planar_shape(const pds_job& J) {
   const int B = a.full ? J.h : pds::planar_seg_len(J.h);
   const int nseg = div_up(J.h, B);
   a.lds = a.full ? full_lds : (size_t)(nseg + B + 1) * ds * pds::kWave * sizeof(float);
-  return a;
-}
-
-AdjShape arm_shape(const pds_job& J) {
-  const long units = (long)J.N * J.K * J.n_s;
-  const size_t per_state = 16 * pds::kWave * sizeof(float);
-  const size_t full_lds = (size_t)(J.h + 1) * per_state;
-  AdjShape a;
-  a.split = false;
-  const long waves = div_up(units, pds::kWave);
-  const long resident = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
-  a.full = waves <= resident;
-  const int B = a.full ? J.h : pds::arm_seg_len_host(J.h);
-  const int nseg = div_up(J.h, B);
-  a.lds = a.full ? full_lds : (size_t)(nseg + B + 1) * per_state;
   return a;
 }
 
@@ -396,22 +381,15 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   // Launch shapes are chosen per job from its own size, never from the
   // batch, so a job runs the same code path alone and in any mix; jobs
   // sharing a shape share a launch.
-  for (int full = 0; full <= 1; ++full) {
-    auto pick = [&](const pds_job& J) { return J.model == PDS_MODEL_ARM && arm_shape(J).full == (full == 1); };
+  {
     int grid = 0;
-    size_t lds = 0;
     JobMap m = make_map(
-        h_jobs, n_jobs, off, pick,
-        [&](const pds_job& J) {
-          const size_t b = arm_shape(J).lds;
-          if (b > lds) lds = b;
-          return div_up((long)J.N * J.K * J.n_s, pds::kWave);
-        },
-        &grid);
-    if (m.n == 0) continue;
-    if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "arm window of h steps needs %zu bytes of LDS", lds);
-    rc = launch_rc(pds::launch_arm_adjoint(m, d_jobs, w, grid, full == 1, lds, s), "arm_adjoint");
-    if (rc) return rc;
+        h_jobs, n_jobs, off, [](const pds_job& J) { return J.model == PDS_MODEL_ARM; },
+        [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
+    if (m.n > 0) {
+      rc = launch_rc(pds::launch_arm_adjoint(m, d_jobs, w, grid, s), "arm_adjoint");
+      if (rc) return rc;
+    }
   }
   for (int nb = 1; nb <= 5; ++nb) {
     for (int mode = 0; mode < 4; ++mode) {
