@@ -472,8 +472,8 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   if (rc) return rc;
   // phi partial sums, one launch per parameter-count class so a job's
   // code path does not depend on the other jobs of the batch
-  for (int cls = 0; cls < 3; ++cls) {
-    const int lo_m = cls == 0 ? 1 : cls == 1 ? 5 : 9, hi_m = cls == 0 ? 4 : cls == 1 ? 8 : PDS_MAX_M;
+  for (int cls = 0; cls < 4; ++cls) {
+    const int lo_m = 1 + 4 * cls, hi_m = cls == 3 ? PDS_MAX_M : 4 + 4 * cls;
     int pgrid = 0;
     JobMap mp = make_map(
         h_jobs, n_jobs, off, [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; },

@@ -37,28 +37,49 @@ __device__ inline MedianState* med_state(const pds_job& J, char* ws, uint64_t of
 }
 
 // Squared scaled distance in FP64, summed in parameter order.  MM is a
-// compile-time bound on M so per-lane arrays stay in registers.  Every
-// kernel that forms keys calls this with the smaller particle index first,
-// so a pair's key is the same bit pattern wherever it is computed.
+// compile-time bound on M; the rows and inv_rho are zero beyond M, so the
+// padded terms add +0 to a non-negative sum and the loop needs no
+// per-parameter branch (a branch per term would serialise the LDS reads).
+// Every kernel that forms keys calls this with the smaller particle index
+// first, so a pair's key is the same bit pattern wherever it is computed.
 template <int MM>
 __device__ inline double pair_d2(const float* ti, const float* tj, const double* inv_rho, int M) {
+  (void)M;
   double s = 0.0;
 #pragma unroll
   for (int m = 0; m < MM; ++m) {
-    if (m < M) {
-      const double z = ((double)ti[m] - (double)tj[m]) * inv_rho[m];
-      s = __dadd_rn(s, __dmul_rn(z, z));
-    }
+    const double z = ((double)ti[m] - (double)tj[m]) * inv_rho[m];
+    s = __dadd_rn(s, __dmul_rn(z, z));
   }
   return s;
 }
 
 __device__ inline uint64_t key_of(double d2) { return (uint64_t)__double_as_longlong(d2); }
 
+// Loads v[0..M) into out[0..MM), zero beyond M.  Every load is issued
+// unconditionally at an in-bounds index (clamped to M - 1) and the padding
+// is a select, so the loads need no branches and one wait.
+template <int MM>
+__device__ inline void load_padded(const float* v, int M, float* out) {
+  float t[MM];
+#pragma unroll
+  for (int m = 0; m < MM; ++m) t[m] = v[m < M ? m : M - 1];
+#pragma unroll
+  for (int m = 0; m < MM; ++m) out[m] = m < M ? t[m] : 0.f;
+}
+
+// 1 / rho in FP64, zero beyond M.
+template <int MM>
+__device__ inline void load_inv_rho(const pds_job& J, double* inv_rho) {
+  float r[MM];
+  load_padded<MM>(J.rho, J.M, r);
+#pragma unroll
+  for (int m = 0; m < MM; ++m) inv_rho[m] = m < J.M ? 1.0 / (double)r[m] : 0.0;
+}
+
 template <int MM>
 __device__ inline void load_row(const pds_job& J, int i, float* t) {
-#pragma unroll
-  for (int m = 0; m < MM; ++m) t[m] = m < J.M ? J.theta[(size_t)i * J.M + m] : 0.f;
+  load_padded<MM>(J.theta + (size_t)i * J.M, J.M, t);
 }
 
 template <int MM>
@@ -266,8 +287,8 @@ __device__ uint32_t sel_compact(const KT* src, uint32_t n, KT* dst, uint32_t cap
 // a live target's interval counts the keys of that interval below it
 // (equal keys ordered by position); the one whose count is the target's
 // rank holds the answer.  Ends with a barrier.
-template <int NT, class KT>
-__device__ void sel_count_finish(const KT* src, uint32_t n, SelShared<KT>& S) {
+template <int NT, class KT, class SS>
+__device__ void sel_count_finish(const KT* src, uint32_t n, SS& S) {
   const SelTarget<KT> t0 = S.tg[0], t1 = S.tg[1];
   const bool l0 = t0.lo != t0.hi, l1 = t1.lo != t1.hi;
   __syncthreads();
@@ -286,6 +307,12 @@ __device__ void sel_count_finish(const KT* src, uint32_t n, SelShared<KT>& S) {
   if (in1 && r1 == t1.t) S.tg[1] = SelTarget<KT>{x, x, 0u};
   __syncthreads();
 }
+
+// Two targets alone (the state of a direct finish).
+template <class KT>
+struct SelPair {
+  SelTarget<KT> tg[2];
+};
 
 // Exact keys of both targets among the n keys src[0..n).  Each level
 // histograms the keys inside a live target's interval into 2^11 bins and
@@ -399,8 +426,7 @@ __global__ void __launch_bounds__(256) median_keys_kernel(JobMap map, const pds_
   if (!small && k == 0) med_state(J, ws, map.ws_off[e])->packed = 0ull;
   if (small && k >= P) return;
   double inv_rho[MM];
-#pragma unroll
-  for (int m = 0; m < MM; ++m) inv_rho[m] = m < J.M ? 1.0 / (double)J.rho[m] : 0.0;
+  load_inv_rho<MM>(J, inv_rho);
   int i, j;
   pair_of(small ? (uint64_t)k : sample_pair(k, P), J.N, &i, &j);
   const uint64_t key = pair_key<MM>(J, i, j, inv_rho);
@@ -420,6 +446,8 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
                                                                     char* __restrict__ ws, int rank_shift) {
   __shared__ uint32_t hs[kSmallPairs];
   __shared__ SelShared<uint32_t> S;
+  __shared__ uint64_t cand[kMedThreads];
+  __shared__ SelPair<uint64_t> P64;
   constexpr int NT = kMedThreads;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
@@ -433,9 +461,7 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
   const WsLayout L = ws_layout(J);
   char* base = ws + map.ws_off[e];
   const uint32_t* khi = reinterpret_cast<const uint32_t*>(base + L.khi);
-  for (int t = threadIdx.x; t < kSelBins; t += NT) S.hist[0][t] = 0u;
-  __syncthreads();
-  constexpr int kFirstShift = 21;  // 2^32 span -> 2^11 bins
+  uint32_t mn = ~0u, mx = 0u;
   constexpr int U = 8;
   for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
     uint32_t h[U];
@@ -449,10 +475,13 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
       const uint32_t c = c0 + u * NT + threadIdx.x;
       if (c < n) {
         hs[c] = h[u];
-        atomicAdd(&S.hist[0][h[u] >> kFirstShift], 1u);
+        mn = h[u] < mn ? h[u] : mn;
+        mx = h[u] > mx ? h[u] : mx;
       }
     }
   }
+  uint32_t lo, hi;
+  block_minmax<NT>(mn, mx, S, &lo, &hi);  // its barriers also complete hs[]
   uint32_t t0, t1;
   bool a_open = false, b_open = false;
   if (small) {
@@ -467,10 +496,67 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
     t0 = a_open ? 0u : (uint32_t)fmin(floor(c0), (double)(n - 1));
     t1 = b_open ? n - 1 : (uint32_t)fmax(ceil(c1), 0.0);
   }
+  // first level over the keys' own range [lo, hi]
+  const SelTarget<uint32_t> full0{lo, hi, t0}, full1{lo, hi, t1};
+  const bool spread = lo != hi;
+  if (spread) {
+    const SelTarget<uint32_t> tt[2] = {full0, full1};
+    const bool live[2] = {true, true};
+    const int sh[2] = {sel_shift<uint32_t>(hi - lo), sel_shift<uint32_t>(hi - lo)};
+    sel_histogram<NT>(hs, n, S, tt, live, sh);
+    sel_narrow<NT>(S, 0, 0, full0, sh[0]);
+    sel_narrow<NT>(S, 1, 0, full1, sh[1]);
+  } else if (threadIdx.x == 0) {
+    S.tg[0] = full0;
+    S.tg[1] = full1;
+  }
   __syncthreads();
-  const SelTarget<uint32_t> full0{0u, ~0u, t0}, full1{0u, ~0u, t1};
-  sel_narrow<NT>(S, 0, 0, full0, kFirstShift);
-  sel_narrow<NT>(S, 1, 0, full1, kFirstShift);
+  const SelTarget<uint32_t> b0 = S.tg[0], b1 = S.tg[1];
+  const bool same_bin = b0.lo == b1.lo && b0.hi == b1.hi;
+  const uint32_t need = !spread ? n : (same_bin ? S.cnt[0] : S.cnt[0] + S.cnt[1]);
+  constexpr int kSteps = kSmallPairs / NT;
+  const uint32_t* klo = reinterpret_cast<const uint32_t*>(base + L.klo);
+  if (need <= (uint32_t)NT) {
+    // Direct finish: the (at most NT) keys in the two bins, as full 64-bit
+    // keys for small jobs, are ranked by counting.
+    uint32_t mask = 0u, cnt = 0u;
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u) {
+      const uint32_t c = u * NT + threadIdx.x;
+      if (c < n) {
+        const uint32_t h = hs[c];
+        if ((h >= b0.lo && h <= b0.hi) || (h >= b1.lo && h <= b1.hi)) {
+          mask |= 1u << u;
+          ++cnt;
+        }
+      }
+    }
+    uint32_t total;
+    uint32_t o = block_scan<NT>(cnt, S, &total);
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u)
+      if (mask & (1u << u)) {
+        const uint32_t c = u * NT + threadIdx.x;
+        cand[o++] = ((uint64_t)hs[c] << 32) | (small ? (uint64_t)klo[c] : 0ull);
+      }
+    if (threadIdx.x == 0) {
+      P64.tg[0] = SelTarget<uint64_t>{(uint64_t)b0.lo << 32, ((uint64_t)b0.hi << 32) | 0xffffffffull, b0.t};
+      P64.tg[1] = SelTarget<uint64_t>{(uint64_t)b1.lo << 32, ((uint64_t)b1.hi << 32) | 0xffffffffull, b1.t};
+    }
+    __syncthreads();
+    sel_count_finish<NT>(cand, total, P64);
+    if (threadIdx.x == 0) {
+      const uint64_t k0 = P64.tg[0].lo, k1 = P64.tg[1].lo;
+      if (small) {
+        write_bandwidth(J, k0, k1);
+      } else {
+        MedianState* st = med_state(J, ws, map.ws_off[e]);
+        st->a = a_open ? 0ull : (k0 >> 32) << 32;
+        st->b = b_open ? ~0ull : ((k1 >> 32) << 32) | 0xffffffffull;
+      }
+    }
+    return;
+  }
   uint32_t hsel[2];
   select_keys<NT>(hs, n, false, (uint32_t*)nullptr, 0u, S, hsel, false);
   if (!small) {
@@ -485,8 +571,6 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
   const bool same = hsel[0] == hsel[1];
   // Low words of the keys whose high word is a selected one: list A for
   // hsel[0], then list B for hsel[1] when it differs.
-  constexpr int kSteps = kSmallPairs / NT;
-  const uint32_t* klo = reinterpret_cast<const uint32_t*>(base + L.klo);
   uint32_t mA = 0u, mB = 0u, cA = 0u, cB = 0u;
 #pragma unroll
   for (int u = 0; u < kSteps; ++u) {
@@ -576,7 +660,7 @@ __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, c
                                                                    char* __restrict__ ws) {
   __shared__ uint64_t lbuf[kCountTile * kCountTile];
   __shared__ uint32_t wsum[16];
-  __shared__ float ti_s[kCountTile * PDS_MAX_M], tj_s[kCountTile * PDS_MAX_M];
+  __shared__ float ti_s[kCountTile * MM], tj_s[kCountTile * MM];
   __shared__ uint32_t less_s;
   __shared__ uint32_t base_s;
   constexpr int NT = kMedThreads;
@@ -590,13 +674,16 @@ __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, c
   const uint64_t a = st->a, b = st->b;
   const int ri = bi * kCountTile, rj = bj * kCountTile;
   const int ni = min(kCountTile, N - ri), nj = min(kCountTile, N - rj);
-  for (int t = threadIdx.x; t < ni * M; t += NT) ti_s[t] = J.theta[(size_t)ri * M + t];
-  for (int t = threadIdx.x; t < nj * M; t += NT) tj_s[t] = J.theta[(size_t)rj * M + t];
+  // tiles of theta rows, zero-padded to MM parameters
+  for (int t = threadIdx.x; t < kCountTile * MM; t += NT) {
+    const int r = t / MM, m = t % MM;
+    ti_s[t] = (r < ni && m < M) ? J.theta[(size_t)(ri + r) * M + m] : 0.f;
+    tj_s[t] = (r < nj && m < M) ? J.theta[(size_t)(rj + r) * M + m] : 0.f;
+  }
   if (threadIdx.x == 0) less_s = 0u;
   __syncthreads();
   double inv_rho[MM];
-#pragma unroll
-  for (int m = 0; m < MM; ++m) inv_rho[m] = m < M ? 1.0 / (double)J.rho[m] : 0.0;
+  load_inv_rho<MM>(J, inv_rho);
   const int row = threadIdx.x & (kCountTile - 1);
   const int cg = threadIdx.x / kCountTile;  // 16 groups of 4 columns
   const int i = ri + row;
@@ -607,7 +694,7 @@ __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, c
   for (int q = 0; q < 4; ++q) {
     const int jl = cg * 4 + q;
     const bool valid = row < ni && jl < nj && i < rj + jl;
-    key[q] = valid ? key_of(pair_d2<MM>(&ti_s[row * M], &tj_s[jl * M], inv_rho, M)) : 0ull;
+    key[q] = valid ? key_of(pair_d2<MM>(&ti_s[row * MM], &tj_s[jl * MM], inv_rho, M)) : 0ull;
     nless += (valid && key[q] < a) ? 1u : 0u;
     keep[q] = valid && key[q] >= a && key[q] <= b;
     nkeep += keep[q] ? 1u : 0u;
@@ -662,8 +749,7 @@ __global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, c
   uint64_t lo = a, hi = b;
   if (!(cl <= r0 && (uint64_t)r1 < (uint64_t)cl + nc)) {
     double inv_rho[MM];
-#pragma unroll
-    for (int m = 0; m < MM; ++m) inv_rho[m] = m < J.M ? 1.0 / (double)J.rho[m] : 0.0;
+    load_inv_rho<MM>(J, inv_rho);
     lo = r0 < cl ? 0ull : a;
     hi = (uint64_t)r1 >= (uint64_t)cl + nc ? ~0ull : b;
     off = r0 < cl ? 0u : cl;
@@ -679,12 +765,14 @@ __global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, c
   if (threadIdx.x == 0) write_bandwidth(J, out[0], out[1]);
 }
 
-// Partial phi of particles i (one per lane) over one chunk of j.
+// Partial phi of particles i (one per lane) over one chunk of j.  Chunk
+// rows sit in LDS with stride MM, zero beyond M, so the parameter loops
+// run unconditionally (padded terms contribute 0).
 template <int MM>
 __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                  char* __restrict__ ws) {
-  __shared__ float tj_s[kPhiChunk * PDS_MAX_M];
-  __shared__ float gj_s[kPhiChunk * PDS_MAX_M];
+  __shared__ float tj_s[kPhiChunk * MM];
+  __shared__ float gj_s[kPhiChunk * MM];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int N = J.N, M = J.M;
@@ -693,20 +781,23 @@ __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, con
   const int ib = local % nib, jc = local / nib;
   const int j0 = jc * kPhiChunk;
   const int nj = min(kPhiChunk, N - j0);
-  for (int t = threadIdx.x; t < nj * M; t += kPairBlock) {
-    tj_s[t] = J.theta[(size_t)j0 * M + t];
-    gj_s[t] = (float)J.g_obs[(size_t)j0 * M + t];
+  for (int t = threadIdx.x; t < kPhiChunk * MM; t += kPairBlock) {
+    const int r = t / MM, m = t % MM;
+    const bool in = r < nj && m < M;
+    tj_s[t] = in ? J.theta[(size_t)(j0 + r) * M + m] : 0.f;
+    gj_s[t] = in ? (float)J.g_obs[(size_t)(j0 + r) * M + m] : 0.f;
   }
   __syncthreads();
   const int i = ib * kPairBlock + threadIdx.x;
   if (i >= N) return;
   const float h = (float)J.bandwidth[0];
   const float inv_h = 1.0f / h;
-  float ti[MM], ir[MM], ir2[MM], acc[MM];
+  float ti[MM], rh[MM], ir[MM], ir2[MM], acc[MM];
+  load_padded<MM>(J.theta + (size_t)i * M, M, ti);
+  load_padded<MM>(J.rho, M, rh);
 #pragma unroll
   for (int m = 0; m < MM; ++m) {
-    ti[m] = m < M ? J.theta[(size_t)i * M + m] : 0.f;
-    ir[m] = m < M ? 1.0f / J.rho[m] : 0.f;
+    ir[m] = m < M ? 1.0f / rh[m] : 0.f;
     ir2[m] = ir[m] * ir[m];
     acc[m] = 0.f;
   }
@@ -714,16 +805,13 @@ __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, con
     float d2 = 0.f;
 #pragma unroll
     for (int m = 0; m < MM; ++m) {
-      if (m < M) {
-        const float z = (ti[m] - tj_s[jj * M + m]) * ir[m];
-        d2 += z * z;
-      }
+      const float z = (ti[m] - tj_s[jj * MM + m]) * ir[m];
+      d2 += z * z;
     }
     const float k = expf(-d2 * inv_h);
     const float k2h = 2.0f * k * inv_h;
 #pragma unroll
-    for (int m = 0; m < MM; ++m)
-      if (m < M) acc[m] += k * gj_s[jj * M + m] + k2h * (ti[m] - tj_s[jj * M + m]) * ir2[m];
+    for (int m = 0; m < MM; ++m) acc[m] += k * gj_s[jj * MM + m] + k2h * (ti[m] - tj_s[jj * MM + m]) * ir2[m];
   }
   const WsLayout L = ws_layout(J);
   float* part = reinterpret_cast<float*>(ws + map.ws_off[e] + L.phi_part);
@@ -855,6 +943,8 @@ hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws
     hipLaunchKernelGGL(phi_partial_kernel<4>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
   else if (mmax <= 8)
     hipLaunchKernelGGL(phi_partial_kernel<8>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+  else if (mmax <= 12)
+    hipLaunchKernelGGL(phi_partial_kernel<12>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
   else
     hipLaunchKernelGGL(phi_partial_kernel<PDS_MAX_M>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
   return hipGetLastError();
