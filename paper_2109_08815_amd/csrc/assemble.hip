@@ -18,14 +18,29 @@
 namespace pds {
 namespace {
 
+// sum_{j < n} p[j * stride], added in order j = 0, 1, ...; the loads are
+// issued eight at a time (clamped in-bounds indices) so they overlap.
+__device__ inline double sum_in_order(const double* p, size_t stride, int n) {
+  double a = 0.0;
+  constexpr int B = 8;
+  for (int j0 = 0; j0 < n; j0 += B) {
+    double v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[b] = p[(size_t)(j0 + b < n ? j0 + b : n - 1) * stride];
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      if (j0 + b < n) a += v[b];
+  }
+  return a;
+}
+
 // Combination over trajectories for particle i; writes logp and wk.
 __device__ inline void combine_particle(const pds_job& J, int i) {
   const int K = J.K, ns = J.n_s;
   const double* lw = J.ll_win + (size_t)i * K * ns;
   double mx = -INFINITY, lp = 0.0;
   for (int k = 0; k < K; ++k) {
-    double a = 0.0;
-    for (int j = 0; j < ns; ++j) a += lw[k * ns + j];
+    const double a = sum_in_order(lw + k * ns, 1, ns);
     J.wk[(size_t)i * K + k] = a;  // holds l_k until the weights are known
     mx = fmax(mx, a);
     lp += a;
@@ -83,14 +98,9 @@ __global__ void __launch_bounds__(64) assemble_grad_kernel(JobMap map, const pds
     const int npair = (m1 - m0) * K;
     for (int p = t; p < npair; p += 64) {
       const int m = m0 + p / K, k = p % K;
-      double a = 0.0, c = 0.0;
-      for (int j = 0; j < ns; ++j) {
-        const size_t u = ((size_t)k * ns + j) * J.N + i;
-        a += go[(size_t)m * U + u];
-        c += gc[(size_t)m * U + u];
-      }
-      sa[p] = a;
-      sc[p] = c;
+      const size_t u0 = (size_t)k * ns * J.N + i;  // unit of window 0; window j adds j N
+      sa[p] = sum_in_order(go + (size_t)m * U + u0, J.N, ns);
+      sc[p] = sum_in_order(gc + (size_t)m * U + u0, J.N, ns);
     }
     __syncthreads();
     for (int m = m0 + t; m < m1; m += 64) {

@@ -195,9 +195,9 @@ __device__ void sel_histogram(const KT* src, uint32_t n, SelShared<KT>& S, const
   for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
     KT key[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < U; ++u) {  // in-bounds index for every lane: no branch per load
       const uint32_t c = c0 + u * NT + threadIdx.x;
-      key[u] = c < n ? src[c] : (KT)0;
+      key[u] = src[c < n ? c : n - 1];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -265,7 +265,11 @@ __device__ uint32_t sel_compact(const KT* src, uint32_t n, KT* dst, uint32_t cap
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t c = c0 + u * NT + threadIdx.x;
-      key[u] = c < n ? src[c] : (KT)0;
+      key[u] = src[c < n ? c : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t c = c0 + u * NT + threadIdx.x;
       keep[u] = c < n && ((l0 && key[u] >= t0.lo && key[u] <= t0.hi) || (l1 && key[u] >= t1.lo && key[u] <= t1.hi));
       cnt += keep[u] ? 1u : 0u;
     }
@@ -293,15 +297,23 @@ __device__ void sel_count_finish(const KT* src, uint32_t n, SS& S) {
   const bool l0 = t0.lo != t0.hi, l1 = t1.lo != t1.hi;
   __syncthreads();
   const uint32_t c = threadIdx.x;
-  const KT x = c < n ? src[c] : (KT)0;
+  const KT x = n > 0 ? src[c < n ? c : n - 1] : (KT)0;
   const bool in0 = c < n && l0 && x >= t0.lo && x <= t0.hi;
   const bool in1 = c < n && l1 && x >= t1.lo && x <= t1.hi;
   uint32_t r0 = 0, r1 = 0;
-  for (uint32_t q = 0; q < n; ++q) {
-    const KT y = src[q];
-    const bool before = y < x || (y == x && q < c);
-    r0 += (before && y >= t0.lo && y <= t0.hi) ? 1u : 0u;
-    r1 += (before && y >= t1.lo && y <= t1.hi) ? 1u : 0u;
+  constexpr int U = 8;  // keys read per batch (one wait per batch)
+  // only threads holding a key count (waves past n skip the loop)
+  for (uint32_t q0 = 0; c < n && q0 < n; q0 += U) {
+    KT y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) y[u] = src[q0 + u < n ? q0 + u : n - 1];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t q = q0 + u;
+      const bool before = q < n && (y[u] < x || (y[u] == x && q < c));
+      r0 += (before && y[u] >= t0.lo && y[u] <= t0.hi) ? 1u : 0u;
+      r1 += (before && y[u] >= t1.lo && y[u] <= t1.hi) ? 1u : 0u;
+    }
   }
   if (in0 && r0 == t0.t) S.tg[0] = SelTarget<KT>{x, x, 0u};
   if (in1 && r1 == t1.t) S.tg[1] = SelTarget<KT>{x, x, 0u};
@@ -468,7 +480,7 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint32_t c = c0 + u * NT + threadIdx.x;
-      h[u] = c < n ? khi[c] : 0u;
+      h[u] = khi[c < n ? c : n - 1];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -520,15 +532,19 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
     // Direct finish: the (at most NT) keys in the two bins, as full 64-bit
     // keys for small jobs, are ranked by counting.
     uint32_t mask = 0u, cnt = 0u;
+    uint32_t hv[kSteps];
 #pragma unroll
     for (int u = 0; u < kSteps; ++u) {
       const uint32_t c = u * NT + threadIdx.x;
-      if (c < n) {
-        const uint32_t h = hs[c];
-        if ((h >= b0.lo && h <= b0.hi) || (h >= b1.lo && h <= b1.hi)) {
-          mask |= 1u << u;
-          ++cnt;
-        }
+      hv[u] = hs[c < n ? c : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kSteps; ++u) {
+      const uint32_t c = u * NT + threadIdx.x;
+      const uint32_t h = hv[u];
+      if (c < n && ((h >= b0.lo && h <= b0.hi) || (h >= b1.lo && h <= b1.hi))) {
+        mask |= 1u << u;
+        ++cnt;
       }
     }
     uint32_t total;
