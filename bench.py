@@ -31,24 +31,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "planar_adjoint_c2_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2109_08815_amd", "csrc", "planar.hip")
+# HBM traffic of the window-adjoint kernel per workload, from committed
+# rocprofv3 counter summaries; valid while the kernel's source file hashes
+# to the value recorded with the counters.
+TRAFFIC_PROFILES = {
+    "c2": ("planar_adjoint_c2_traffic.md", "planar.hip"),
+    "c3": ("planar_adjoint_c3_traffic.md", "planar.hip"),
+    "c4": ("arm_adjoint_c4_traffic.md", "arm.hip"),
+}
 
 
 def measured_traffic(config):
     """HBM bytes per launch of the adjoint kernel from the committed PMC
-    summary, or None when it does not cover this workload or the kernel
-    source changed since the counters were taken."""
+    summary, or None when none covers this workload or the kernel source
+    changed since the counters were taken."""
     import hashlib
 
-    if config != "c2" or not os.path.exists(TRAFFIC_PROFILE):
+    if config not in TRAFFIC_PROFILES:
+        return None
+    prof, src = TRAFFIC_PROFILES[config]
+    path = os.path.join(ROOT, "profiles", prof)
+    if not os.path.exists(path):
         return None
     fields = {}
-    for line in open(TRAFFIC_PROFILE):
+    for line in open(path):
         if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    h = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2109_08815_amd", "csrc", src), "rb").read()).hexdigest()
     if fields.get("source_sha256") != h or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])
@@ -83,34 +93,45 @@ def copy_calibration():
 
 def cpu_baseline(pb, obs, theta, S, target_s):
     """The FP64 oracle (forward-mode duals, OpenMP over window units) timed on
-    a bounded sample: full CSVGD iterations over a subset of particles."""
+    a bounded sample: full CSVGD iterations over a subset of particles, on
+    all host cores and, on a smaller sample, on one core."""
     from oracle import oracle as orc
 
     n_all = theta.shape[0]
-    sel_n = max(1, min(n_all, 16))
     st = orc.State(pb, theta, S)
-    sel = np.arange(sel_n, dtype=np.int32)
-    t0 = time.perf_counter()
-    orc.gradient(pb, obs, st, sel=sel)
-    t1 = time.perf_counter() - t0
-    per_particle = t1 / sel_n
+    lib = orc.lib()
+    cores = int(lib.orc_threads())
+
+    def timed(sel_n):
+        sel = np.arange(sel_n, dtype=np.int32)
+        t0 = time.perf_counter()
+        orc.gradient(pb, obs, st, sel=sel)
+        h, _ = orc.bandwidth(st.theta, pb.rho)
+        orc.phi(st.theta, np.zeros((n_all, pb.M)), pb.rho, h, sel=sel)
+        return time.perf_counter() - t0
+
+    probe = max(1, min(n_all, 16))
+    per_particle = timed(probe) / probe
     sel_n = int(max(1, min(n_all, target_s / max(per_particle, 1e-9))))
-    sel = np.arange(sel_n, dtype=np.int32)
-    t0 = time.perf_counter()
-    g = orc.gradient(pb, obs, st, sel=sel)
-    h, _ = orc.bandwidth(st.theta, pb.rho)
-    orc.phi(st.theta, np.zeros((n_all, pb.M)), pb.rho, h, sel=sel)
-    el = time.perf_counter() - t0
-    steps = sel_n * pb.K * pb.T
-    threads = orc.lib().orc_threads() if hasattr(orc.lib(), "orc_threads") else os.cpu_count()
-    return {
-        "value": steps / el,
+    el = timed(sel_n)
+    out = {
+        "value": sel_n * pb.K * pb.T / el,
         "unit": "particle-sim-steps/s",
-        "cores": int(threads),
+        "cores": cores,
         "kind": "oracle",
         "sample": "%d of %d particles, all %d trajectories x %d steps: forward-mode-dual gradient, bandwidth "
                   "and phi rows, one iteration, %.1f s" % (sel_n, n_all, pb.K, pb.T, el),
     }
+    # one core, on a quarter of the time budget
+    lib.orc_set_threads(1)
+    try:
+        one = max(1, min(n_all, int(0.25 * target_s / max(per_particle * cores, 1e-9))))
+        el1 = timed(one)
+        out["value_1_core"] = one * pb.K * pb.T / el1
+        out["sample_1_core"] = "%d particles, %.1f s" % (one, el1)
+    finally:
+        lib.orc_set_threads(cores)
+    return out
 
 
 def main():
@@ -154,8 +175,12 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record()
+    marks = []
     if use_graph:
         for _ in range(args.steps // per_graph):
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record()
+            marks.append(ev)
             run.replay()
     else:
         for _ in range(args.steps):
@@ -164,6 +189,8 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
+    # per-iteration time of each graph replay (events between replays)
+    per_iter = [a.elapsed_time(b) / per_graph for a, b in zip(marks, marks[1:] + [e1])] if marks else []
     if use_graph:
         # kernel timing: the same iteration with plain launches right after
         L.timing_enable(True)
@@ -199,6 +226,8 @@ def main():
                           "c4": "7-joint arm with hinged box"}[args.config],
             pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain"},
         "iters_per_s": args.steps / elapsed,
+        "iteration_ms": ({"p10": float(np.percentile(per_iter, 10)), "p50": float(np.percentile(per_iter, 50)),
+                          "p90": float(np.percentile(per_iter, 90)), "replays": len(per_iter)} if per_iter else None),
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

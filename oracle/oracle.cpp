@@ -404,6 +404,15 @@ int orc_threads(void) {
 #endif
 }
 
+// Sets the thread count of later OpenMP loops (timing on one core).
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 // Joint torques at time `time` (for tests of the controllers).
 void orc_tau(const OrcModel* md, const double* th, double time, const double* q, const double* qd, double* tau) {
   joint_torque<double>(*md, th, time, q, qd, tau);

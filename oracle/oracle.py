@@ -64,6 +64,7 @@ def lib():
             build()
             L = C.CDLL(_SO)
             L.orc_threads.restype = C.c_int
+            L.orc_set_threads.argtypes = [C.c_int]
             L.orc_aba.argtypes = [C.POINTER(OrcModel), _D, _D, _D, _D, _D]
             L.orc_crba_rnea.argtypes = [C.POINTER(OrcModel), _D, _D, _D, _D, _D]
             L.orc_tau.argtypes = [C.POINTER(OrcModel), _D, C.c_double, _D, _D, _D]

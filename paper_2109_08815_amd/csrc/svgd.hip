@@ -845,8 +845,17 @@ __global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_j
   const int chunks = (J.N + kPhiChunk - 1) / kPhiChunk;
   const WsLayout L = ws_layout(J);
   const float* part = reinterpret_cast<const float*>(ws + map.ws_off[e] + L.phi_part);
+  const size_t stride = (size_t)J.N * J.M;
   float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * J.N * J.M + t];
+  constexpr int B = 8;  // partials loaded per batch, added in chunk order
+  for (int c0 = 0; c0 < chunks; c0 += B) {
+    float v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[b] = part[(size_t)(c0 + b < chunks ? c0 + b : chunks - 1) * stride + t];
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      if (c0 + b < chunks) s += v[b];
+  }
   J.phi[t] = s / (float)J.N;
 }
 
