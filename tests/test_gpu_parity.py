@@ -461,3 +461,50 @@ def test_arm_adjoint_gradients(orc, over):
     assert grad_err(np64(job.g_con), ref, "con").max() <= 1e-3
     assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
     assert np.all(np64(job.flags) == 0)
+
+
+@pytest.mark.parametrize("cfg,over", [("c2", dict(N=16, K=2, T=40, n_s=2)), ("c3", dict(N=16, K=1, T=60, n_s=3)),
+                                      ("c4", dict(N=8, T=60, n_s=2))])
+def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
+    """The reverse-mode gradients against central differences of the GPU's
+    own forward (FP32 states, FP64 sums), along a random direction in theta
+    per particle: d log p / d theta (g_obs) and d Phi / d theta (g_con) with
+    Phi = sum_j lam_j g_j + (c / 2) g_j^2.  FP32 rounding noise limits the
+    differences, so the best of three step sizes must agree to 5e-3 of
+    |g| |v|."""
+    print_case("fd", cfg, over)
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01, lam=True, **over)
+    L.sim_batch_adjoint(b)
+    g_obs, g_con = np64(job.g_obs), np64(job.g_con)
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=g_obs.shape) * (pb.hi - pb.lo)
+    th0 = np64(job.theta)
+    lam = np64(job.lam_def)
+
+    def evaluate(theta):
+        set_tensor(job.theta, theta)
+        L.loglik_multishoot(b)
+        gd = np64(job.gdef)
+        phi_c = (lam * gd + 0.5 * pb.c * gd * gd).reshape(gd.shape[0], -1).sum(axis=1)
+        return np64(job.logp), phi_c
+
+    best_o = np.full(pb.N, np.inf)
+    best_c = np.full(pb.N, np.inf)
+    want_o = (g_obs * v).sum(axis=1)
+    want_c = (g_con * v).sum(axis=1)
+    # error of the directional derivative relative to |g| |v| (independent of
+    # how the random direction happens to align with the gradient)
+    norm_o = np.maximum(np.linalg.norm(g_obs, axis=1) * np.linalg.norm(v, axis=1), 1e-12)
+    norm_c = np.maximum(np.linalg.norm(g_con, axis=1) * np.linalg.norm(v, axis=1), 1e-12)
+    for rel in (1e-2, 3e-3, 1e-3):
+        lp_p, ph_p = evaluate(r32(th0 + rel * v))
+        lp_m, ph_m = evaluate(r32(th0 - rel * v))
+        step = (r32(th0 + rel * v) - r32(th0 - rel * v))  # the step actually taken in FP32
+        scale = (step * v).sum(axis=1) / (v * v).sum(axis=1)  # = 2 rel up to rounding
+        fd_o = (lp_p - lp_m) / scale
+        fd_c = (ph_p - ph_m) / scale
+        best_o = np.minimum(best_o, np.abs(fd_o - want_o) / norm_o)
+        best_c = np.minimum(best_c, np.abs(fd_c - want_c) / norm_c)
+    set_tensor(job.theta, th0)
+    assert best_o.max() <= 5e-3, best_o
+    assert best_c.max() <= 5e-3, best_c
