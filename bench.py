@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-graph", action="store_true", help="plain launches instead of graph replay")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="compute the kernel bandwidth after the adjoint instead of concurrently with it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -159,7 +161,7 @@ def main():
     obs = driver.gpu_observations(pb)
     S = driver.gpu_shooting_init(pb, pb.particles)
     job = L.Job(pb, obs, theta=pb.particles, S=S, device_iter=True)
-    run = driver.CSVGD([job])
+    run = driver.CSVGD([job], overlap=not args.no_overlap)
     for _ in range(max(1, args.warmup)):
         run.step()
     torch.cuda.synchronize()
@@ -226,7 +228,8 @@ def main():
         "config": {"workload": "%s: %s N=%d M=%d K=%d T=%d dt=%g n_s=%d" % (
             args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain",
                           "c4": "7-joint arm with hinged box"}[args.config],
-            pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain"},
+            pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain",
+            "bandwidth": "concurrent with the adjoint" if not args.no_overlap else "after the adjoint"},
         "iters_per_s": args.steps / elapsed,
         "iteration_ms": ({"p10": float(np.percentile(per_iter, 10)), "p50": float(np.percentile(per_iter, 50)),
                           "p90": float(np.percentile(per_iter, 90)), "replays": len(per_iter)} if per_iter else None),

@@ -186,6 +186,20 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
 int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
              void* stream);
 
+/* The two halves of svgd_phi, for callers that overlap the bandwidth with
+ * the adjoint: svgd_bandwidth writes `bandwidth` only (the median
+ * heuristic of Sec. III-A; reads theta and rho), svgd_phi_at_bandwidth
+ * writes phi from the `bandwidth` already in device memory (eq.
+ * svgd_update).  svgd_phi == svgd_bandwidth then svgd_phi_at_bandwidth on
+ * one stream.  The bandwidth depends on theta alone and uses workspace
+ * regions sim_batch_adjoint does not touch, so on a second stream it may
+ * run concurrently with sim_batch_adjoint of the same batch and workspace
+ * (nothing may write theta meanwhile). */
+int svgd_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                   void* stream);
+int svgd_phi_at_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                          void* stream);
+
 /* MDMM update of Sec. III-E / Algorithm 1, simultaneous for all variables:
  * theta_dot = phi - (lam_lim + c g_lim) dg_lim/dtheta - g_con with
  * g_lim = clamp(theta, lo, hi) - theta; S_dot as computed; lam_lim += eps_lam

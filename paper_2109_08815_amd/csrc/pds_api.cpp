@@ -62,6 +62,7 @@ enum : unsigned {
   NEED_LL = 2u,        // obs, w_x, u, ll_win, gdef, logp, wk
   NEED_ADJ = 4u,       // lam_def, g_obs, g_con, S_dot
   NEED_PHI = 8u,       // rho, g_obs, phi, bandwidth
+  NEED_BW = 32u,       // rho, theta, bandwidth
   NEED_STEP = 16u,     // lo, hi, lr_*, lam_lim, lam_def, adam, phi, g_con, S_dot, gdef
 };
 
@@ -108,6 +109,7 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     if (J.n_s > 1) { REQ(S_dot, 4); if (!J.seed_gdef) REQ(lam_def, 4); }
   }
   if (need & NEED_PHI) { REQ(rho, 4); REQ(g_obs, 8); REQ(phi, 4); REQ(bandwidth, 8); REQ(theta, 4); }
+  if (need & NEED_BW) { REQ(rho, 4); REQ(bandwidth, 8); REQ(theta, 4); }
   if (need & NEED_STEP) {
     REQ(theta, 4); REQ(lo, 4); REQ(hi, 4); REQ(lr_theta, 4); REQ(lam_lim, 4); REQ(phi, 4); REQ(g_con, 8);
     REQ(adam_m, 4); REQ(adam_v, 4);
@@ -265,6 +267,67 @@ int assemble_logp(const pds_job* h_jobs, const pds_job* d_jobs, int n, hipStream
       h_jobs, n, off, [](const pds_job&) { return true; }, [](const pds_job& J) { return div_up(J.N, 64); },
       &grid);
   return launch_rc(pds::launch_assemble(m, d_jobs, nullptr, grid, false, s), "assemble_logp");
+}
+
+// Shared prologue of the phi-family calls: validation, workspace offsets.
+int phi_prologue(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, unsigned need, void* ws,
+                 size_t ws_bytes, std::vector<uint64_t>* off, int* mmax) {
+  int rc = validate_batch(h_jobs, d_jobs, n_jobs, need);
+  if (rc) return rc;
+  size_t total = 0;
+  *off = ws_offsets(h_jobs, n_jobs, PDS_CALL_PHI, &total);
+  rc = check_ws(ws, ws_bytes, total);
+  if (rc) return rc;
+  *mmax = 1;
+  for (int j = 0; j < n_jobs; ++j) *mmax = h_jobs[j].M > *mmax ? h_jobs[j].M : *mmax;
+  return PDS_OK;
+}
+
+int bandwidth_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, const std::vector<uint64_t>& off,
+                    int mmax, char* w, hipStream_t s) {
+  int rc = PDS_OK;
+  auto all = [](const pds_job&) { return true; };
+  auto npairs = [](const pds_job& J) { return (long)J.N * (J.N - 1) / 2; };
+  // bandwidth: keys (or a sample of them), one selecting block per job,
+  // then the count and final kernels for jobs above kSmallPairs pairs
+  auto large = [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; };
+  pds::MedianMaps mm;
+  mm.keys = make_map(
+      h_jobs, n_jobs, off, all,
+      [&](const pds_job& J) { return div_up(large(J) ? pds::kSampleKeys : npairs(J), 256); }, &mm.grid_keys);
+  mm.select = make_map(h_jobs, n_jobs, off, all, [](const pds_job&) { return 1; }, &mm.grid_select);
+  mm.count = make_map(
+      h_jobs, n_jobs, off, large,
+      [](const pds_job& J) {
+        const long nb = div_up(J.N, pds::kCountTile);
+        return nb * (nb + 1) / 2;
+      },
+      &mm.grid_count);
+  mm.large = make_map(h_jobs, n_jobs, off, large, [](const pds_job&) { return 1; }, &mm.grid_large);
+  rc = launch_rc(pds::launch_median(mm, d_jobs, w, mmax, g_median_rank_shift, s), "median");
+  if (rc) return rc;
+  return PDS_OK;
+}
+
+int phi_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, const std::vector<uint64_t>& off,
+              char* w, hipStream_t s) {
+  int rc = PDS_OK;
+  auto all = [](const pds_job&) { return true; };
+  // phi partial sums, one launch per parameter-count class so a job's
+  // code path does not depend on the other jobs of the batch
+  for (int cls = 0; cls < 4; ++cls) {
+    const int lo_m = 1 + 4 * cls, hi_m = cls == 3 ? PDS_MAX_M : 4 + 4 * cls;
+    int pgrid = 0;
+    JobMap mp = make_map(
+        h_jobs, n_jobs, off, [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; },
+        [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
+    if (mp.n == 0) continue;
+    rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, hi_m, s), "phi_partial");
+    if (rc) return rc;
+  }
+  int rgrid = 0;
+  JobMap mr = make_map(h_jobs, n_jobs, off, all, [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &rgrid);
+  return launch_rc(pds::launch_phi_reduce(mr, d_jobs, w, rgrid, s), "phi_reduce");
 }
 
 }  // namespace
@@ -440,51 +503,31 @@ int pds_test_median_shift(int32_t ranks) {
 
 int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
              void* stream) {
-  int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_PHI);
-  if (rc) return rc;
-  size_t need = 0;
-  std::vector<uint64_t> off = ws_offsets(h_jobs, n_jobs, PDS_CALL_PHI, &need);
-  rc = check_ws(ws, ws_bytes, need);
-  if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  char* w = static_cast<char*>(ws);
-  auto all = [](const pds_job&) { return true; };
+  std::vector<uint64_t> off;
   int mmax = 1;
-  for (int j = 0; j < n_jobs; ++j) mmax = h_jobs[j].M > mmax ? h_jobs[j].M : mmax;
-  auto npairs = [](const pds_job& J) { return (long)J.N * (J.N - 1) / 2; };
-  // bandwidth: keys (or a sample of them), one selecting block per job,
-  // then the count and final kernels for jobs above kSmallPairs pairs
-  auto large = [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; };
-  pds::MedianMaps mm;
-  mm.keys = make_map(
-      h_jobs, n_jobs, off, all,
-      [&](const pds_job& J) { return div_up(large(J) ? pds::kSampleKeys : npairs(J), 256); }, &mm.grid_keys);
-  mm.select = make_map(h_jobs, n_jobs, off, all, [](const pds_job&) { return 1; }, &mm.grid_select);
-  mm.count = make_map(
-      h_jobs, n_jobs, off, large,
-      [](const pds_job& J) {
-        const long nb = div_up(J.N, pds::kCountTile);
-        return nb * (nb + 1) / 2;
-      },
-      &mm.grid_count);
-  mm.large = make_map(h_jobs, n_jobs, off, large, [](const pds_job&) { return 1; }, &mm.grid_large);
-  rc = launch_rc(pds::launch_median(mm, d_jobs, w, mmax, g_median_rank_shift, s), "median");
+  int rc = phi_prologue(h_jobs, d_jobs, n_jobs, NEED_PHI, ws, ws_bytes, &off, &mmax);
   if (rc) return rc;
-  // phi partial sums, one launch per parameter-count class so a job's
-  // code path does not depend on the other jobs of the batch
-  for (int cls = 0; cls < 4; ++cls) {
-    const int lo_m = 1 + 4 * cls, hi_m = cls == 3 ? PDS_MAX_M : 4 + 4 * cls;
-    int pgrid = 0;
-    JobMap mp = make_map(
-        h_jobs, n_jobs, off, [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; },
-        [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
-    if (mp.n == 0) continue;
-    rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, hi_m, s), "phi_partial");
-    if (rc) return rc;
-  }
-  int rgrid = 0;
-  JobMap mr = make_map(h_jobs, n_jobs, off, all, [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &rgrid);
-  return launch_rc(pds::launch_phi_reduce(mr, d_jobs, w, rgrid, s), "phi_reduce");
+  rc = bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, static_cast<char*>(ws), (hipStream_t)stream);
+  if (rc) return rc;
+  return phi_calls(h_jobs, d_jobs, n_jobs, off, static_cast<char*>(ws), (hipStream_t)stream);
+}
+
+int svgd_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                   void* stream) {
+  std::vector<uint64_t> off;
+  int mmax = 1;
+  int rc = phi_prologue(h_jobs, d_jobs, n_jobs, NEED_BW, ws, ws_bytes, &off, &mmax);
+  if (rc) return rc;
+  return bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, static_cast<char*>(ws), (hipStream_t)stream);
+}
+
+int svgd_phi_at_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
+                          void* stream) {
+  std::vector<uint64_t> off;
+  int mmax = 1;
+  int rc = phi_prologue(h_jobs, d_jobs, n_jobs, NEED_PHI, ws, ws_bytes, &off, &mmax);
+  if (rc) return rc;
+  return phi_calls(h_jobs, d_jobs, n_jobs, off, static_cast<char*>(ws), (hipStream_t)stream);
 }
 
 int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int32_t optimizer, int32_t iter,

@@ -4,8 +4,9 @@ Set-up uses the library's own rollout (sim_batch_forward) for the observed
 trajectories (rollout at the generating parameters plus the problem's noise
 draws) and for the default shooting states (each particle's own
 single-shooting state at the start of every window).  One iteration is
-Algorithm 1: sim_batch_adjoint -> svgd_phi -> svgd_step, optionally captured
-once into a HIP graph and replayed.
+Algorithm 1: sim_batch_adjoint -> svgd_phi -> svgd_step (optionally with the
+bandwidth on a second stream, concurrent with the adjoint), optionally
+captured once into a HIP graph and replayed.
 """
 from __future__ import annotations
 
@@ -59,18 +60,19 @@ def gpu_shooting_init(pb, theta, device="cuda"):
 class CSVGD:
     """Runs CSVGD iterations on a batch of jobs (plain launches or a replayed graph)."""
 
-    def __init__(self, jobs, optimizer=L.PDS_OPT_ADAM):
+    def __init__(self, jobs, optimizer=L.PDS_OPT_ADAM, overlap=False):
         for j in jobs:
             if j.iter_dev is None:
                 j.iter_dev = torch.zeros(2, dtype=torch.int32, device=j.device)
         self.batch = L.Batch(jobs)
         self.optimizer = optimizer
+        self.overlap = overlap
         self.graph = None
         self.stream = None
 
     def step(self):
         """One iteration with plain launches on the current stream."""
-        L.csvgd_iteration(self.batch, 0, self.optimizer)
+        L.csvgd_iteration(self.batch, 0, self.optimizer, overlap=self.overlap)
 
     def capture(self, iterations: int = 1):
         """Capture `iterations` consecutive iterations into one graph."""
@@ -80,7 +82,7 @@ class CSVGD:
         self.graph_iterations = iterations
         with torch.cuda.graph(self.graph, stream=self.stream):
             for _ in range(iterations):
-                L.csvgd_iteration(self.batch, 0, self.optimizer)
+                L.csvgd_iteration(self.batch, 0, self.optimizer, stream=self.stream, overlap=self.overlap)
         torch.cuda.current_stream().wait_stream(self.stream)
 
     def replay(self):

@@ -54,6 +54,7 @@ class PdsError(RuntimeError):
 _lock = threading.Lock()
 _lib = None
 EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
+           "svgd_bandwidth", "svgd_phi_at_bandwidth",
            "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_timing_enable",
            "pds_timing_read", "pds_test_median_shift", "pds_job_footprint")
 
@@ -67,7 +68,8 @@ def lib():
                 raise PdsError("libpds.so is missing: build it with `python -m paper_2109_08815_amd.build`")
             L = C.CDLL(LIB_PATH)
             P = C.POINTER(PdsJob)
-            for name in ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi"):
+            for name in ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_bandwidth",
+                         "svgd_phi_at_bandwidth"):
                 fn = getattr(L, name)
                 fn.argtypes = [P, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
                 fn.restype = C.c_int
@@ -209,6 +211,12 @@ class Batch:
     def n(self):
         return len(self.jobs)
 
+    def side_stream(self):
+        """A second stream of the batch's device (default priority)."""
+        if getattr(self, "_side", None) is None:
+            self._side = torch.cuda.Stream(device=self.device)
+        return self._side
+
 
 def _stream(stream):
     if stream is None:
@@ -238,16 +246,41 @@ def svgd_phi(b: Batch, stream=None):
     _call("svgd_phi", b, stream)
 
 
+def svgd_bandwidth(b: Batch, stream=None):
+    _call("svgd_bandwidth", b, stream)
+
+
+def svgd_phi_at_bandwidth(b: Batch, stream=None):
+    _call("svgd_phi_at_bandwidth", b, stream)
+
+
 def svgd_step(b: Batch, optimizer=PDS_OPT_ADAM, iteration=1, stream=None):
     rc = lib().svgd_step(b.h, C.c_void_p(b.d.data_ptr()), b.n, int(optimizer), int(iteration), _stream(stream))
     _check(rc, "svgd_step")
 
 
-def csvgd_iteration(b: Batch, iteration: int, optimizer=PDS_OPT_ADAM, stream=None):
-    """One CSVGD iteration (Algorithm 1) over every job of the batch."""
-    sim_batch_adjoint(b, stream)
-    svgd_phi(b, stream)
-    svgd_step(b, optimizer, iteration, stream)
+def csvgd_iteration(b: Batch, iteration: int, optimizer=PDS_OPT_ADAM, stream=None, overlap=False):
+    """One CSVGD iteration (Algorithm 1) over every job of the batch.
+
+    With `overlap` the kernel bandwidth (which depends on theta alone) runs
+    on the batch's side stream concurrently with the adjoint; both streams
+    join before phi.  `stream` (a torch stream, default the current one) is
+    the stream the iteration is ordered on."""
+    if not overlap:
+        sim_batch_adjoint(b, stream)
+        svgd_phi(b, stream)
+        svgd_step(b, optimizer, iteration, stream)
+        return
+    main = torch.cuda.current_stream() if stream is None else stream
+    side = b.side_stream()
+    side.wait_stream(main)
+    # (capture order matters for a graph: the branch enqueued first keeps
+    # the parent's queue; measured, the bandwidth first is the faster order)
+    svgd_bandwidth(b, side)
+    sim_batch_adjoint(b, main)
+    main.wait_stream(side)
+    svgd_phi_at_bandwidth(b, main)
+    svgd_step(b, optimizer, iteration, main)
 
 
 def algorithmic_flops(model: int, n_dof: int):

@@ -410,6 +410,34 @@ def test_graph_replays_match_eager(orc):
     assert int(np64(job_b.iter_dev)[0]) == 4
 
 
+@pytest.mark.parametrize("cfg,over", [("c2", dict(N=70, K=3)), ("c3", dict(N=300, K=2, T=100, n_s=2))])
+def test_overlapped_bandwidth_matches_serial_iterations(orc, cfg, over):
+    """The bandwidth on a second stream, concurrent with the adjoint, gives
+    bitwise the serial iteration's state, with plain launches and in a
+    replayed graph (the second case takes the large-problem median path)."""
+    from paper_2109_08815_amd import driver
+
+    print_case("overlap", cfg, over)
+    pb, obs, st, job_a, _ = make_case(orc, cfg, perturb_S=0.01, lam=True, **over)
+    jobs = [job_a] + [L.Job(pb, obs, theta=pb.particles, S=st.S) for _ in range(2)]
+    for j in jobs[1:]:
+        j.lam_def.copy_(torch.as_tensor(st.lam_def, dtype=torch.float32))
+    serial = driver.CSVGD([jobs[0]])
+    over_plain = driver.CSVGD([jobs[1]], overlap=True)
+    over_graph = driver.CSVGD([jobs[2]], overlap=True)
+    over_graph.capture(2)
+    for rep in range(3):
+        for _ in range(2):
+            serial.step()
+            over_plain.step()
+        over_graph.replay()
+        torch.cuda.synchronize()
+        for name in ("theta", "S", "lam_def", "adam_v", "phi", "g_obs", "bandwidth", "iter_dev"):
+            ref = np64(getattr(jobs[0], name))
+            np.testing.assert_array_equal(ref, np64(getattr(jobs[1], name)), err_msg=name)
+            np.testing.assert_array_equal(ref, np64(getattr(jobs[2], name)), err_msg=name)
+
+
 def test_autograd_function_matches_oracle(orc):
     """Backward of the autograd wrapper = oracle gradients of
     sum_i log p_i - sum b * g_def (b random, c = 0)."""
