@@ -66,12 +66,37 @@ __global__ void __launch_bounds__(64) assemble_logp_kernel(JobMap map, const pds
   combine_particle(J, i);
 }
 
-// Adjoint path: one 64-lane block per particle.  Lanes first sum the window
-// log-likelihoods of one trajectory each, then lane 0 combines them; lanes
-// then sum the per-window parameter gradients of one (parameter,
-// trajectory) pair each (per-unit terms laid out [m][u], u = (k n_s + j) N +
-// i); finally lane m weights and sums over trajectories.  Every sum runs in
-// a fixed order.
+// S_dot of shooting-state component r = ((k (n_s-1) + j-1) d_s + d) of
+// particle i (window j >= 1 starts from it).
+__device__ inline void sdot_element(const pds_job& J, int i, int r, size_t U, const float* gso, const float* gsc) {
+  const int ds = 2 * J.n_dof;
+  const int nS = J.K * (J.n_s - 1) * ds;
+  const int d = r % ds;
+  const int kj = r / ds;
+  const int k = kj / (J.n_s - 1);
+  const int j = kj % (J.n_s - 1) + 1;  // window started by this shooting state
+  const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
+  const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
+  double v = seed * J.wk[(size_t)i * J.K + k] * (double)gso[(size_t)d * U + u] - (double)gsc[(size_t)d * U + u];
+  // defect of window j-1, whose target is this shooting state
+  const size_t id = ((size_t)i * J.K + k) * (J.n_s - 1) + (j - 1);
+  const double g = J.gdef[id];
+  const double sg = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
+  const float s_next = J.S[id * ds + d];
+  const float s_end = J.end_states[(((size_t)i * J.K + k) * J.n_s + (j - 1)) * ds + d];
+  const double ud = J.u[d];
+  const double err = (double)(s_next - s_end) * ud;
+  v -= sg * 2.0 * err * ud / ((double)J.sigma_def * J.sigma_def);
+  J.S_dot[(size_t)i * nS + r] = (float)v;
+  if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], 2);
+}
+
+// Adjoint path: one 64-lane block per particle.  Lane 0 combines the
+// window log-likelihoods over trajectories; lanes then sum the per-window
+// parameter gradients of one (parameter, trajectory) pair each (per-unit
+// terms laid out [m][u], u = (k n_s + j) N + i); lane m weights and sums
+// over trajectories; finally the lanes write the particle's S_dot.  Every
+// sum runs in a fixed order.
 constexpr int kMaxKM = 256;  // (parameter, trajectory) pairs held in LDS per pass
 
 __global__ void __launch_bounds__(64) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
@@ -115,42 +140,28 @@ __global__ void __launch_bounds__(64) assemble_grad_kernel(JobMap map, const pds
     }
     __syncthreads();
   }
+  const int nS = K * (ns - 1) * 2 * J.n_dof;
+  if (ns > 1 && nS <= kSdotInline) {  // else assemble_sdot_kernel, one thread per component
+    const float* gso = reinterpret_cast<const float*>(base + L.gs_obs);
+    const float* gsc = reinterpret_cast<const float*>(base + L.gs_con);
+    for (int r = t; r < nS; r += 64) sdot_element(J, i, r, U, gso, gsc);
+  }
 }
 
-// One thread per shooting-state component (i, k, j >= 1, d).
+// S_dot with one thread per shooting-state component, for particles with
+// more than kSdotInline components.
 __global__ void __launch_bounds__(256) assemble_sdot_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                             char* __restrict__ ws) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  const int ds = 2 * J.n_dof;
-  const int nS = J.K * (J.n_s - 1) * ds;
+  const int nS = J.K * (J.n_s - 1) * 2 * J.n_dof;
   const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
   if (t >= J.N * nS) return;
-  const int i = t / nS;
-  const int r = t % nS;
-  const int d = r % ds;
-  const int kj = r / ds;
-  const int k = kj / (J.n_s - 1);
-  const int j = kj % (J.n_s - 1) + 1;  // window started by this shooting state
   const WsLayout L = ws_layout(J);
   const char* base = ws + map.ws_off[e];
   const size_t U = (size_t)J.N * J.K * J.n_s;
-  const float* gso = reinterpret_cast<const float*>(base + L.gs_obs);
-  const float* gsc = reinterpret_cast<const float*>(base + L.gs_con);
-  const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
-  const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
-  double v = seed * J.wk[(size_t)i * J.K + k] * (double)gso[(size_t)d * U + u] - (double)gsc[(size_t)d * U + u];
-  // defect of window j-1, whose target is this shooting state
-  const size_t id = ((size_t)i * J.K + k) * (J.n_s - 1) + (j - 1);
-  const double g = J.gdef[id];
-  const double sg = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
-  const float s_next = J.S[id * ds + d];
-  const float s_end = J.end_states[(((size_t)i * J.K + k) * J.n_s + (j - 1)) * ds + d];
-  const double ud = J.u[d];
-  const double err = (double)(s_next - s_end) * ud;
-  v -= sg * 2.0 * err * ud / ((double)J.sigma_def * J.sigma_def);
-  J.S_dot[(size_t)i * nS + r] = (float)v;
-  if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], 2);
+  sdot_element(J, t / nS, t % nS, U, reinterpret_cast<const float*>(base + L.gs_obs),
+               reinterpret_cast<const float*>(base + L.gs_con));
 }
 
 }  // namespace
@@ -161,14 +172,15 @@ hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* /*ws*
   return hipGetLastError();
 }
 
+hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(assemble_sdot_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
+  return hipGetLastError();
+}
+
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
   hipLaunchKernelGGL(assemble_grad_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs, ws);
   return hipGetLastError();
 }
 
-hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(assemble_sdot_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
-  return hipGetLastError();
-}
 
 }  // namespace pds

@@ -313,21 +313,21 @@ int phi_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, cons
               char* w, hipStream_t s) {
   int rc = PDS_OK;
   auto all = [](const pds_job&) { return true; };
-  // phi partial sums, one launch per parameter-count class so a job's
-  // code path does not depend on the other jobs of the batch
+  // one launch per parameter-count class, so a job's code path does not
+  // depend on the other jobs of the batch
+  (void)all;
+  (void)w;
   for (int cls = 0; cls < 4; ++cls) {
     const int lo_m = 1 + 4 * cls, hi_m = cls == 3 ? PDS_MAX_M : 4 + 4 * cls;
     int pgrid = 0;
     JobMap mp = make_map(
         h_jobs, n_jobs, off, [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; },
-        [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &pgrid);
+        [](const pds_job& J) { return div_up(J.N, pds::kWave); }, &pgrid);
     if (mp.n == 0) continue;
-    rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, pgrid, hi_m, s), "phi_partial");
+    rc = launch_rc(pds::launch_phi(mp, d_jobs, pgrid, hi_m, s), "phi");
     if (rc) return rc;
   }
-  int rgrid = 0;
-  JobMap mr = make_map(h_jobs, n_jobs, off, all, [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &rgrid);
-  return launch_rc(pds::launch_phi_reduce(mr, d_jobs, w, rgrid, s), "phi_reduce");
+  return PDS_OK;
 }
 
 }  // namespace
@@ -486,7 +486,8 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   rc = launch_rc(pds::launch_assemble_grad(mg, d_jobs, w, grid, s), "assemble_grad");
   if (rc) return rc;
   JobMap ms = make_map(
-      h_jobs, n_jobs, off, [](const pds_job& J) { return J.n_s > 1; },
+      h_jobs, n_jobs, off,
+      [](const pds_job& J) { return J.n_s > 1 && (long)J.K * (J.n_s - 1) * 2 * J.n_dof > pds::kSdotInline; },
       [](const pds_job& J) { return div_up((long)J.N * J.K * (J.n_s - 1) * 2 * J.n_dof, 256); }, &grid);
   if (ms.n > 0) {
     rc = launch_rc(pds::launch_assemble_sdot(ms, d_jobs, w, grid, s), "assemble_sdot");

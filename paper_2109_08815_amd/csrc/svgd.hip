@@ -20,8 +20,8 @@
 // holds whatever the distribution; counts are integers, so the result does
 // not depend on the order in which blocks finish.
 //
-// phi.  Blocks of 64 particles i against chunks of 128 particles j staged
-// in LDS; FP32 partial sums per chunk, reduced in chunk order.
+// phi.  One block per 64 particles i; its waves split the j range, stage
+// chunks of particles j in LDS and accumulate in FP32 in a fixed order.
 #include <cmath>
 
 #include "common.h"
@@ -781,35 +781,27 @@ __global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, c
   if (threadIdx.x == 0) write_bandwidth(J, out[0], out[1]);
 }
 
-// Partial phi of particles i (one per lane) over one chunk of j.  Chunk
-// rows sit in LDS with stride MM, zero beyond M, so the parameter loops
-// run unconditionally (padded terms contribute 0).
+// phi for 64 particles i per block (one per lane), the j range split over
+// kPhiWaves waves: each wave stages chunks of its j range in LDS (rows
+// padded with zeros to MM parameters, so the parameter loops run without
+// branches) and accumulates in j order; the waves' partial sums are then
+// added in wave order.  Every sum has a fixed order.
 template <int MM>
-__global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                                 char* __restrict__ ws) {
-  __shared__ float tj_s[kPhiChunk * MM];
-  __shared__ float gj_s[kPhiChunk * MM];
+__global__ void __launch_bounds__(kPhiWaves * kWave) phi_kernel(JobMap map, const pds_job* __restrict__ jobs) {
+  __shared__ float tj_s[kPhiWaves][kPhiChunk * MM];
+  __shared__ float gj_s[kPhiWaves][kPhiChunk * MM];
+  __shared__ float acc_s[kPhiWaves][kWave * MM];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int N = J.N, M = J.M;
-  const int nib = (N + kPairBlock - 1) / kPairBlock;
-  const int local = blockIdx.x - map.begin[e];
-  const int ib = local % nib, jc = local / nib;
-  const int j0 = jc * kPhiChunk;
-  const int nj = min(kPhiChunk, N - j0);
-  for (int t = threadIdx.x; t < kPhiChunk * MM; t += kPairBlock) {
-    const int r = t / MM, m = t % MM;
-    const bool in = r < nj && m < M;
-    tj_s[t] = in ? J.theta[(size_t)(j0 + r) * M + m] : 0.f;
-    gj_s[t] = in ? (float)J.g_obs[(size_t)(j0 + r) * M + m] : 0.f;
-  }
-  __syncthreads();
-  const int i = ib * kPairBlock + threadIdx.x;
-  if (i >= N) return;
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int i = (blockIdx.x - map.begin[e]) * kWave + lane;
+  const int per = (N + kPhiWaves - 1) / kPhiWaves;  // j per wave
+  const int ja = w * per, jb = min(N, ja + per);
   const float h = (float)J.bandwidth[0];
   const float inv_h = 1.0f / h;
   float ti[MM], rh[MM], ir[MM], ir2[MM], acc[MM];
-  load_padded<MM>(J.theta + (size_t)i * M, M, ti);
+  load_padded<MM>(J.theta + (size_t)min(i, N - 1) * M, M, ti);
   load_padded<MM>(J.rho, M, rh);
 #pragma unroll
   for (int m = 0; m < MM; ++m) {
@@ -817,46 +809,45 @@ __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, con
     ir2[m] = ir[m] * ir[m];
     acc[m] = 0.f;
   }
-  for (int jj = 0; jj < nj; ++jj) {
-    float d2 = 0.f;
+  const int nchunks = (per + kPhiChunk - 1) / kPhiChunk;  // equal for every wave
+  for (int c = 0; c < nchunks; ++c) {
+    const int j0 = ja + c * kPhiChunk;
+    const int nj = max(0, min(kPhiChunk, jb - j0));
+    for (int t = lane; t < kPhiChunk * MM; t += kWave) {
+      const int r = t / MM, m = t % MM;
+      const bool in = r < nj && m < M;
+      const size_t src = (size_t)(in ? j0 + r : 0) * M + (in ? m : 0);
+      tj_s[w][t] = in ? J.theta[src] : 0.f;
+      gj_s[w][t] = in ? (float)J.g_obs[src] : 0.f;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < nj; ++jj) {
+      float d2 = 0.f;
+#pragma unroll
+      for (int m = 0; m < MM; ++m) {
+        const float z = (ti[m] - tj_s[w][jj * MM + m]) * ir[m];
+        d2 += z * z;
+      }
+      const float k = expf(-d2 * inv_h);
+      const float k2h = 2.0f * k * inv_h;
+#pragma unroll
+      for (int m = 0; m < MM; ++m)
+        acc[m] += k * gj_s[w][jj * MM + m] + k2h * (ti[m] - tj_s[w][jj * MM + m]) * ir2[m];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < MM; ++m) acc_s[w][lane * MM + m] = acc[m];
+  __syncthreads();
+  if (w == 0 && i < N) {
 #pragma unroll
     for (int m = 0; m < MM; ++m) {
-      const float z = (ti[m] - tj_s[jj * MM + m]) * ir[m];
-      d2 += z * z;
+      float s = 0.f;
+#pragma unroll
+      for (int v = 0; v < kPhiWaves; ++v) s += acc_s[v][lane * MM + m];
+      if (m < M) J.phi[(size_t)i * M + m] = s / (float)N;
     }
-    const float k = expf(-d2 * inv_h);
-    const float k2h = 2.0f * k * inv_h;
-#pragma unroll
-    for (int m = 0; m < MM; ++m) acc[m] += k * gj_s[jj * MM + m] + k2h * (ti[m] - tj_s[jj * MM + m]) * ir2[m];
   }
-  const WsLayout L = ws_layout(J);
-  float* part = reinterpret_cast<float*>(ws + map.ws_off[e] + L.phi_part);
-#pragma unroll
-  for (int m = 0; m < MM; ++m)
-    if (m < M) part[((size_t)jc * N + i) * M + m] = acc[m];
-}
-
-__global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                         char* __restrict__ ws) {
-  const int e = map_entry(map, blockIdx.x);
-  const pds_job& J = jobs[map.job[e]];
-  const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
-  if (t >= J.N * J.M) return;
-  const int chunks = (J.N + kPhiChunk - 1) / kPhiChunk;
-  const WsLayout L = ws_layout(J);
-  const float* part = reinterpret_cast<const float*>(ws + map.ws_off[e] + L.phi_part);
-  const size_t stride = (size_t)J.N * J.M;
-  float s = 0.f;
-  constexpr int B = 8;  // partials loaded per batch, added in chunk order
-  for (int c0 = 0; c0 < chunks; c0 += B) {
-    float v[B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) v[b] = part[(size_t)(c0 + b < chunks ? c0 + b : chunks - 1) * stride + t];
-#pragma unroll
-    for (int b = 0; b < B; ++b)
-      if (c0 + b < chunks) s += v[b];
-  }
-  J.phi[t] = s / (float)J.N;
 }
 
 // MDMM + optimizer update.  Flat index over theta (N M), S (N K (n_s-1) d_s)
@@ -962,21 +953,16 @@ hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, 
   return hipGetLastError();
 }
 
-hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
-                              hipStream_t s) {
+hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, hipStream_t s) {
+  const dim3 blk(kPhiWaves * kWave);
   if (mmax <= 4)
-    hipLaunchKernelGGL(phi_partial_kernel<4>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+    hipLaunchKernelGGL(phi_kernel<4>, dim3(grid), blk, 0, s, map, d_jobs);
   else if (mmax <= 8)
-    hipLaunchKernelGGL(phi_partial_kernel<8>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+    hipLaunchKernelGGL(phi_kernel<8>, dim3(grid), blk, 0, s, map, d_jobs);
   else if (mmax <= 12)
-    hipLaunchKernelGGL(phi_partial_kernel<12>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+    hipLaunchKernelGGL(phi_kernel<12>, dim3(grid), blk, 0, s, map, d_jobs);
   else
-    hipLaunchKernelGGL(phi_partial_kernel<PDS_MAX_M>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
-  return hipGetLastError();
-}
-
-hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(phi_reduce_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
+    hipLaunchKernelGGL(phi_kernel<PDS_MAX_M>, dim3(grid), blk, 0, s, map, d_jobs);
   return hipGetLastError();
 }
 
