@@ -54,11 +54,13 @@ struct WsLayout {
   size_t med;                               // median selection state
   size_t khi, klo;                          // median key words (all pairs, or a sample's high words)
   size_t cand;                              // median candidate keys (one slot per pair)
+  size_t phi_part;                          // phi partial sums (jobs above kPhiFusedMaxN particles)
   size_t total;
 };
 
 constexpr int kPhiChunk = 32;    // particles j per LDS chunk in phi
 constexpr int kPhiWaves = 16;    // waves per phi block, splitting the j range
+constexpr int kPhiFusedMaxN = 512;  // larger jobs use partial sums and a reduction
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -81,6 +83,8 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   L.khi = o;     o = align256(o + (large ? (size_t)kSampleKeys : P) * sizeof(uint32_t));
   L.klo = o;     o = align256(o + (large ? 0 : P) * sizeof(uint32_t));
   L.cand = o;    o = align256(o + (large ? P : 0) * sizeof(uint64_t));
+  const size_t chunks = J.N > kPhiFusedMaxN ? ((size_t)J.N + kPhiChunk - 1) / kPhiChunk : 0;
+  L.phi_part = o; o = align256(o + chunks * (size_t)J.N * J.M * sizeof(float));
   L.total = o;
   return L;
 }
@@ -109,6 +113,9 @@ hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws
                               hipStream_t s);
 hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, hipStream_t s);
+hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
+                              hipStream_t s);
+hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_step(const JobMap& map, const pds_job* d_jobs, int grid, int optimizer, int iter,
                        hipStream_t s);
 

@@ -312,21 +312,32 @@ int bandwidth_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs
 int phi_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, const std::vector<uint64_t>& off,
               char* w, hipStream_t s) {
   int rc = PDS_OK;
-  auto all = [](const pds_job&) { return true; };
-  // one launch per parameter-count class, so a job's code path does not
-  // depend on the other jobs of the batch
-  (void)all;
-  (void)w;
+  // one launch per parameter-count class and per phi scheme (chosen from
+  // the job's own N), so a job's code path does not depend on the batch
   for (int cls = 0; cls < 4; ++cls) {
     const int lo_m = 1 + 4 * cls, hi_m = cls == 3 ? PDS_MAX_M : 4 + 4 * cls;
-    int pgrid = 0;
+    auto in_cls = [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; };
+    int grid = 0;
+    JobMap mf = make_map(
+        h_jobs, n_jobs, off, [&](const pds_job& J) { return in_cls(J) && J.N <= pds::kPhiFusedMaxN; },
+        [](const pds_job& J) { return div_up(J.N, pds::kWave); }, &grid);
+    if (mf.n > 0) {
+      rc = launch_rc(pds::launch_phi(mf, d_jobs, grid, hi_m, s), "phi");
+      if (rc) return rc;
+    }
     JobMap mp = make_map(
-        h_jobs, n_jobs, off, [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; },
-        [](const pds_job& J) { return div_up(J.N, pds::kWave); }, &pgrid);
-    if (mp.n == 0) continue;
-    rc = launch_rc(pds::launch_phi(mp, d_jobs, pgrid, hi_m, s), "phi");
-    if (rc) return rc;
+        h_jobs, n_jobs, off, [&](const pds_job& J) { return in_cls(J) && J.N > pds::kPhiFusedMaxN; },
+        [](const pds_job& J) { return div_up(J.N, 64) * div_up(J.N, pds::kPhiChunk); }, &grid);
+    if (mp.n > 0) {
+      rc = launch_rc(pds::launch_phi_partial(mp, d_jobs, w, grid, hi_m, s), "phi_partial");
+      if (rc) return rc;
+    }
   }
+  int rgrid = 0;
+  JobMap mr = make_map(
+      h_jobs, n_jobs, off, [](const pds_job& J) { return J.N > pds::kPhiFusedMaxN; },
+      [](const pds_job& J) { return div_up((long)J.N * J.M, 256); }, &rgrid);
+  if (mr.n > 0) return launch_rc(pds::launch_phi_reduce(mr, d_jobs, w, rgrid, s), "phi_reduce");
   return PDS_OK;
 }
 

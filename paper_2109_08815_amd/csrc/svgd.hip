@@ -20,8 +20,10 @@
 // holds whatever the distribution; counts are integers, so the result does
 // not depend on the order in which blocks finish.
 //
-// phi.  One block per 64 particles i; its waves split the j range, stage
-// chunks of particles j in LDS and accumulate in FP32 in a fixed order.
+// phi.  Up to kPhiFusedMaxN particles: one block per 64 particles i whose
+// waves split the j range.  Larger jobs: blocks of 64 particles i against
+// chunks of 32 particles j (enough blocks to fill the chip), then a
+// reduction over chunks.  Both accumulate in FP32 in a fixed order.
 #include <cmath>
 
 #include "common.h"
@@ -781,7 +783,87 @@ __global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, c
   if (threadIdx.x == 0) write_bandwidth(J, out[0], out[1]);
 }
 
-// phi for 64 particles i per block (one per lane), the j range split over
+// Larger jobs: partial phi of particles i (one per lane) over one chunk
+// of j (many blocks), then a reduction over the chunks in chunk order.  Chunk
+// rows sit in LDS with stride MM, zero beyond M, so the parameter loops
+// run unconditionally (padded terms contribute 0).
+template <int MM>
+__global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                                 char* __restrict__ ws) {
+  __shared__ float tj_s[kPhiChunk * MM];
+  __shared__ float gj_s[kPhiChunk * MM];
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int N = J.N, M = J.M;
+  const int nib = (N + kPairBlock - 1) / kPairBlock;
+  const int local = blockIdx.x - map.begin[e];
+  const int ib = local % nib, jc = local / nib;
+  const int j0 = jc * kPhiChunk;
+  const int nj = min(kPhiChunk, N - j0);
+  for (int t = threadIdx.x; t < kPhiChunk * MM; t += kPairBlock) {
+    const int r = t / MM, m = t % MM;
+    const bool in = r < nj && m < M;
+    tj_s[t] = in ? J.theta[(size_t)(j0 + r) * M + m] : 0.f;
+    gj_s[t] = in ? (float)J.g_obs[(size_t)(j0 + r) * M + m] : 0.f;
+  }
+  __syncthreads();
+  const int i = ib * kPairBlock + threadIdx.x;
+  if (i >= N) return;
+  const float h = (float)J.bandwidth[0];
+  const float inv_h = 1.0f / h;
+  float ti[MM], rh[MM], ir[MM], ir2[MM], acc[MM];
+  load_padded<MM>(J.theta + (size_t)i * M, M, ti);
+  load_padded<MM>(J.rho, M, rh);
+#pragma unroll
+  for (int m = 0; m < MM; ++m) {
+    ir[m] = m < M ? 1.0f / rh[m] : 0.f;
+    ir2[m] = ir[m] * ir[m];
+    acc[m] = 0.f;
+  }
+  for (int jj = 0; jj < nj; ++jj) {
+    float d2 = 0.f;
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+      const float z = (ti[m] - tj_s[jj * MM + m]) * ir[m];
+      d2 += z * z;
+    }
+    const float k = expf(-d2 * inv_h);
+    const float k2h = 2.0f * k * inv_h;
+#pragma unroll
+    for (int m = 0; m < MM; ++m) acc[m] += k * gj_s[jj * MM + m] + k2h * (ti[m] - tj_s[jj * MM + m]) * ir2[m];
+  }
+  const WsLayout L = ws_layout(J);
+  float* part = reinterpret_cast<float*>(ws + map.ws_off[e] + L.phi_part);
+#pragma unroll
+  for (int m = 0; m < MM; ++m)
+    if (m < M) part[((size_t)jc * N + i) * M + m] = acc[m];
+}
+
+__global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                         char* __restrict__ ws) {
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
+  if (t >= J.N * J.M) return;
+  const int chunks = (J.N + kPhiChunk - 1) / kPhiChunk;
+  const WsLayout L = ws_layout(J);
+  const float* part = reinterpret_cast<const float*>(ws + map.ws_off[e] + L.phi_part);
+  const size_t stride = (size_t)J.N * J.M;
+  float s = 0.f;
+  constexpr int B = 8;  // partials loaded per batch, added in chunk order
+  for (int c0 = 0; c0 < chunks; c0 += B) {
+    float v[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) v[b] = part[(size_t)(c0 + b < chunks ? c0 + b : chunks - 1) * stride + t];
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      if (c0 + b < chunks) s += v[b];
+  }
+  J.phi[t] = s / (float)J.N;
+}
+
+// Jobs up to kPhiFusedMaxN particles: phi for 64 particles i per block (one
+// per lane), the j range split over
 // kPhiWaves waves: each wave stages chunks of its j range in LDS (rows
 // padded with zeros to MM parameters, so the parameter loops run without
 // branches) and accumulates in j order; the waves' partial sums are then
@@ -950,6 +1032,24 @@ hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, 
 
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s) {
   hipLaunchKernelGGL(iter_bump_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
+                              hipStream_t s) {
+  if (mmax <= 4)
+    hipLaunchKernelGGL(phi_partial_kernel<4>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+  else if (mmax <= 8)
+    hipLaunchKernelGGL(phi_partial_kernel<8>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+  else if (mmax <= 12)
+    hipLaunchKernelGGL(phi_partial_kernel<12>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+  else
+    hipLaunchKernelGGL(phi_partial_kernel<PDS_MAX_M>, dim3(grid), dim3(kPairBlock), 0, s, map, d_jobs, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(phi_reduce_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, ws);
   return hipGetLastError();
 }
 

@@ -17,8 +17,9 @@ is the time from its arrival to its results being on the host.
 Every kernel reduces per job in a fixed order and per-job state (the Adam
 iteration counter included) lives in the job's own buffers, so a job's
 results are bitwise the same whichever jobs share its batches; the
-sequential mode (one job at a time, plain launches, same kernels) is the
-reference the batched mode is checked and timed against.
+sequential mode (one job at a time, plain launches, same kernels, the
+bandwidth after the adjoint) is the reference the batched mode (bandwidth
+concurrent with the adjoint by default) is checked and timed against.
 
 Usage: python -m paper_2109_08815_amd.serve [--jobs 512] [--iterations 100]
 [--load 0.7 1.2] [--graph 10] prints one JSON line of latency and
@@ -148,7 +149,8 @@ class Engine:
     """Runs a trace through the batched loop or one job at a time."""
 
     def __init__(self, budget_bytes: int = 64 << 30, max_slots: int = PDS_MAX_JOBS, graph_iters: int = 0,
-                 device: str = "cuda", inflight: int = 2, footprint_fn=None):
+                 device: str = "cuda", inflight: int = 2, footprint_fn=None, overlap: bool = True):
+        self.overlap = overlap
         self.budget = budget_bytes
         self.max_slots = max_slots
         self.graph_iters = graph_iters
@@ -211,12 +213,12 @@ class Engine:
                 tick_events.popleft().synchronize()
             if self.graph_iters > 1 and left >= self.graph_iters:
                 if graph is None:
-                    graph = _capture(batch, self.graph_iters)
+                    graph = _capture(batch, self.graph_iters, self.overlap)
                     graph_n = self.graph_iters
                 graph.replay()
                 n_it = graph_n
             else:
-                L.csvgd_iteration(batch, 0)
+                L.csvgd_iteration(batch, 0, overlap=self.overlap)
                 n_it = 1
             ev = torch.cuda.Event()
             ev.record()
@@ -278,7 +280,7 @@ def _to_host(t):
     return h
 
 
-def _capture(batch, iters):
+def _capture(batch, iters, overlap=True):
     import torch
 
     from . import lib as L
@@ -288,7 +290,7 @@ def _capture(batch, iters):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         for _ in range(iters):
-            L.csvgd_iteration(batch, 0)
+            L.csvgd_iteration(batch, 0, stream=s, overlap=overlap)
     torch.cuda.current_stream().wait_stream(s)
     return g
 

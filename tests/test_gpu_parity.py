@@ -183,7 +183,7 @@ def set_tensor(t, a):
     t.copy_(torch.as_tensor(np.asarray(a), dtype=t.dtype))
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 64, 65, 200, 300])
+@pytest.mark.parametrize("N", [1, 2, 3, 64, 65, 200, 300, 512, 700])
 def test_bandwidth_exact_and_phi(orc, N):
     print_case("phi", N)
     pb = f32_problem(synth.make_problem("c2", N=N, K=1, T=40, n_s=2))
