@@ -147,10 +147,13 @@ typedef struct pds_job {
   float* phi;         /* [N, M] SVGD direction */
   double* bandwidth;  /* [1] kernel bandwidth h used by phi */
   int32_t* flags;     /* [N] per-particle status bits */
-  int32_t* iter_dev;  /* [1] Adam iteration counter in device memory, or NULL:
-                         when set, svgd_step uses *iter_dev + 1 (ignoring its
-                         `iter` argument) and then increments *iter_dev, so a
-                         captured graph can be replayed without new arguments */
+  int32_t* iter_dev;  /* [2] Adam iteration counter in device memory, or NULL:
+                         when set, svgd_step uses iter_dev[0] + 1 (ignoring
+                         its `iter` argument) and then increments iter_dev[0],
+                         so a captured graph can be replayed without new
+                         arguments.  iter_dev[1] is the step's block count,
+                         zero before and after every call: allocate both
+                         zeroed, and never run two steps of one job at once */
 } pds_job;
 
 /* Rolls out every window (a batched f_sim of Sec. II with the semi-implicit

@@ -738,15 +738,15 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
     for (int m = 0; m < 4; ++m) gm_c[m] += (double)tc[m];
   }
   for (int m = 0; m < 4; ++m) {
-    gth_obs[(size_t)m * U + u] = gm_o[m];
-    gth_con[(size_t)m * U + u] = gm_c[m];
+    gth_obs[iu * 4 + m] = gm_o[m];
+    gth_con[iu * 4 + m] = gm_c[m];
     bad |= !isfinite(gm_o[m]) || !isfinite(gm_c[m]);
   }
   for (int d = 0; d < 8; ++d) {
-    gs_obs[(size_t)d * U + u] = qb_o[d];
-    gs_obs[(size_t)(8 + d) * U + u] = qdb_o[d];
-    gs_con[(size_t)d * U + u] = qb_c[d];
-    gs_con[(size_t)(8 + d) * U + u] = qdb_c[d];
+    gs_obs[iu * kArmDs + d] = qb_o[d];
+    gs_obs[iu * kArmDs + 8 + d] = qdb_o[d];
+    gs_con[iu * kArmDs + d] = qb_c[d];
+    gs_con[iu * kArmDs + 8 + d] = qdb_c[d];
   }
   if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
 }

@@ -66,85 +66,157 @@ __global__ void __launch_bounds__(64) assemble_logp_kernel(JobMap map, const pds
   combine_particle(J, i);
 }
 
+// Per-unit adjoint outputs are laid out with the unit index in particle
+// order, iu = (i K + k) n_s + j: parameter terms as [iu][m], shooting-state
+// terms as [iu][d].  One particle's terms are therefore contiguous.
+
 // S_dot of shooting-state component r = ((k (n_s-1) + j-1) d_s + d) of
-// particle i (window j >= 1 starts from it).
-__device__ inline void sdot_element(const pds_job& J, int i, int r, size_t U, const float* gso, const float* gsc) {
+// particle i (window j >= 1 starts from it), split into the parts known
+// before the trajectory weights: S_dot = seed w_k a - b - c.
+struct SdotPart {
+  double a, b, c;
+  int k;
+};
+
+__device__ inline SdotPart sdot_part(const pds_job& J, int i, int r, const float* gso, const float* gsc) {
   const int ds = 2 * J.n_dof;
-  const int nS = J.K * (J.n_s - 1) * ds;
   const int d = r % ds;
   const int kj = r / ds;
   const int k = kj / (J.n_s - 1);
   const int j = kj % (J.n_s - 1) + 1;  // window started by this shooting state
-  const size_t u = ((size_t)k * J.n_s + j) * J.N + i;
-  const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
-  double v = seed * J.wk[(size_t)i * J.K + k] * (double)gso[(size_t)d * U + u] - (double)gsc[(size_t)d * U + u];
+  const size_t iu = ((size_t)i * J.K + k) * J.n_s + j;
+  SdotPart p;
+  p.k = k;
+  p.a = (double)gso[iu * ds + d];
+  p.b = (double)gsc[iu * ds + d];
   // defect of window j-1, whose target is this shooting state
   const size_t id = ((size_t)i * J.K + k) * (J.n_s - 1) + (j - 1);
   const double g = J.gdef[id];
   const double sg = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
   const float s_next = J.S[id * ds + d];
-  const float s_end = J.end_states[(((size_t)i * J.K + k) * J.n_s + (j - 1)) * ds + d];
+  const float s_end = J.end_states[(iu - 1) * ds + d];
   const double ud = J.u[d];
   const double err = (double)(s_next - s_end) * ud;
-  v -= sg * 2.0 * err * ud / ((double)J.sigma_def * J.sigma_def);
+  p.c = sg * 2.0 * err * ud / ((double)J.sigma_def * J.sigma_def);
+  return p;
+}
+
+__device__ inline void sdot_finish(const pds_job& J, int i, int r, const SdotPart& p, double seed, double w) {
+  const int nS = J.K * (J.n_s - 1) * 2 * J.n_dof;
+  double v = seed * w * p.a - p.b;
+  v -= p.c;
   J.S_dot[(size_t)i * nS + r] = (float)v;
   if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], 2);
 }
 
-// Adjoint path: one 64-lane block per particle.  Lane 0 combines the
-// window log-likelihoods over trajectories; lanes then sum the per-window
-// parameter gradients of one (parameter, trajectory) pair each (per-unit
-// terms laid out [m][u], u = (k n_s + j) N + i); lane m weights and sums
-// over trajectories; finally the lanes write the particle's S_dot.  Every
-// sum runs in a fixed order.
-constexpr int kMaxKM = 256;  // (parameter, trajectory) pairs held in LDS per pass
+// Trajectory combination for particle i from l_k already held in wk.
+__device__ inline void combine_sums(const pds_job& J, int i) {
+  const int K = J.K;
+  double* wk = J.wk + (size_t)i * K;
+  double mx = -INFINITY, lp = 0.0;
+  for (int k = 0; k < K; ++k) {
+    mx = fmax(mx, wk[k]);
+    lp += wk[k];
+  }
+  if (J.combine == PDS_COMBINE_PROD) {
+    for (int k = 0; k < K; ++k) wk[k] = 1.0;
+  } else {
+    double z = 0.0;
+    for (int k = 0; k < K; ++k) z += exp(wk[k] - mx);
+    for (int k = 0; k < K; ++k) wk[k] = exp(wk[k] - mx) / z;
+    lp = mx + log(z) - log((double)K);
+  }
+  J.logp[i] = lp;
+  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+}
 
-__global__ void __launch_bounds__(64) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                           char* __restrict__ ws) {
-  __shared__ double sa[kMaxKM], sc[kMaxKM];
+// Adjoint path: one block per particle.  Every global load of the particle
+// is issued up front, spread over the block's threads: the trajectory sums
+// l_k = sum_j l_kj, the (parameter, trajectory) window sums of both
+// channels (contiguous rows of n_s terms) and the particle's S_dot inputs.
+// Thread 0 then combines over trajectories; threads m weight and sum the
+// parameter rows over k; S_dot takes its trajectory weight last.  Every
+// sum runs in a fixed order.
+constexpr int kAsmThreads = 256;
+constexpr int kAsmCap = 512;  // (parameter, trajectory) sums per channel held in LDS per pass
+
+__global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                                    char* __restrict__ ws) {
+  __shared__ double sa[kAsmCap], sc[kAsmCap], sw[kAsmCap];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int i = blockIdx.x - map.begin[e];
   if (i >= J.N) return;
   const int K = J.K, ns = J.n_s, M = J.M;
   const int t = threadIdx.x;
-  if (t == 0) combine_particle(J, i);
-  __syncthreads();
   const WsLayout L = ws_layout(J);
   const char* base = ws + map.ws_off[e];
-  const size_t U = (size_t)J.N * K * ns;
+  const size_t pu = (size_t)i * K * ns;  // first unit of particle i
   const double* go = reinterpret_cast<const double*>(base + L.gth_obs);
   const double* gc = reinterpret_cast<const double*>(base + L.gth_con);
   const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
-  // parameters in groups so that (parameter, trajectory) pairs fit in LDS
-  const int mg = K >= kMaxKM ? 1 : kMaxKM / K;
-  for (int m0 = 0; m0 < M; m0 += mg) {
-    const int m1 = min(M, m0 + mg);
-    const int npair = (m1 - m0) * K;
-    for (int p = t; p < npair; p += 64) {
-      const int m = m0 + p / K, k = p % K;
-      const size_t u0 = (size_t)k * ns * J.N + i;  // unit of window 0; window j adds j N
-      sa[p] = sum_in_order(go + (size_t)m * U + u0, J.N, ns);
-      sc[p] = sum_in_order(gc + (size_t)m * U + u0, J.N, ns);
-    }
-    __syncthreads();
-    for (int m = m0 + t; m < m1; m += 64) {
-      double so = 0.0, scon = 0.0;
-      for (int k = 0; k < K; ++k) {
-        const int p = (m - m0) * K + k;
-        so += J.wk[(size_t)i * K + k] * sa[p];
-        scon += sc[p];
-      }
-      J.g_obs[(size_t)i * M + m] = seed * so;
-      J.g_con[(size_t)i * M + m] = scon;
-    }
-    __syncthreads();
-  }
   const int nS = K * (ns - 1) * 2 * J.n_dof;
-  if (ns > 1 && nS <= kSdotInline) {  // else assemble_sdot_kernel, one thread per component
+  const bool inl = ns > 1 && nS <= kSdotInline;  // else assemble_sdot_kernel
+  SdotPart sp[2];
+  if (inl) {
     const float* gso = reinterpret_cast<const float*>(base + L.gs_obs);
     const float* gsc = reinterpret_cast<const float*>(base + L.gs_con);
-    for (int r = t; r < nS; r += 64) sdot_element(J, i, r, U, gso, gsc);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = t + q * kAsmThreads;
+      if (r < nS) sp[q] = sdot_part(J, i, r, gso, gsc);
+    }
+  }
+  const int kc = K < kAsmCap ? K : kAsmCap;  // trajectories per chunk
+  const int mg = kAsmCap / kc;               // parameters per pass
+  bool first = true;
+  for (int m0 = 0; m0 < M; m0 += mg) {
+    const int m1 = min(M, m0 + mg);
+    double so = 0.0, scon = 0.0;  // thread t < m1 - m0 owns parameter m0 + t
+    for (int k0 = 0; k0 < K; k0 += kc) {
+      const int nk = min(K, k0 + kc) - k0;
+      const int np = (m1 - m0) * nk;
+      const int lead = first ? K : 0;  // the first pass also sums the window log-likelihoods
+      for (int r = t; r < lead + 2 * np; r += kAsmThreads) {
+        if (r < lead) {
+          J.wk[(size_t)i * K + r] = sum_in_order(J.ll_win + pu + (size_t)r * ns, 1, ns);  // l_k for now
+        } else {
+          // row p = (k - k0) (m1 - m0) + (m - m0): neighbouring threads read
+          // neighbouring parameters of one unit
+          const bool con = r - lead >= np;
+          const int p = con ? r - lead - np : r - lead;
+          const int m = m0 + p % (m1 - m0), k = k0 + p / (m1 - m0);
+          const double v = sum_in_order((con ? gc : go) + (pu + (size_t)k * ns) * M + m, M, ns);
+          if (con) sc[p] = v; else sa[p] = v;
+        }
+      }
+      __syncthreads();
+      if (first) {
+        if (t == 0) combine_sums(J, i);
+        first = false;
+        __syncthreads();
+      }
+      for (int k = t; k < nk; k += kAsmThreads) sw[k] = J.wk[(size_t)i * K + k0 + k];
+      __syncthreads();
+      if (t < m1 - m0) {
+        for (int k = 0; k < nk; ++k) {
+          so += sw[k] * sa[k * (m1 - m0) + t];
+          scon += sc[k * (m1 - m0) + t];
+        }
+      }
+      __syncthreads();
+    }
+    if (t < m1 - m0) {
+      J.g_obs[(size_t)i * M + m0 + t] = seed * so;
+      J.g_con[(size_t)i * M + m0 + t] = scon;
+    }
+  }
+  if (inl) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = t + q * kAsmThreads;
+      if (r < nS) sdot_finish(J, i, r, sp[q], seed, J.wk[(size_t)i * K + sp[q].k]);
+    }
   }
 }
 
@@ -159,9 +231,11 @@ __global__ void __launch_bounds__(256) assemble_sdot_kernel(JobMap map, const pd
   if (t >= J.N * nS) return;
   const WsLayout L = ws_layout(J);
   const char* base = ws + map.ws_off[e];
-  const size_t U = (size_t)J.N * J.K * J.n_s;
-  sdot_element(J, t / nS, t % nS, U, reinterpret_cast<const float*>(base + L.gs_obs),
-               reinterpret_cast<const float*>(base + L.gs_con));
+  const int i = t / nS, r = t % nS;
+  const SdotPart p = sdot_part(J, i, r, reinterpret_cast<const float*>(base + L.gs_obs),
+                               reinterpret_cast<const float*>(base + L.gs_con));
+  const double seed = J.seed_logp ? J.seed_logp[i] : 1.0;
+  sdot_finish(J, i, r, p, seed, J.wk[(size_t)i * J.K + p.k]);
 }
 
 }  // namespace
@@ -178,7 +252,7 @@ hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* 
 }
 
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(assemble_grad_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs, ws);
+  hipLaunchKernelGGL(assemble_grad_kernel, dim3(grid), dim3(kAsmThreads), 0, s, map, d_jobs, ws);
   return hipGetLastError();
 }
 

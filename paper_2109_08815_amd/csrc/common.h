@@ -27,6 +27,22 @@ __device__ inline int map_entry(const JobMap& m, int block) {
   return e;
 }
 
+// Per-unit adjoint rows: N consecutive values from registers to memory with
+// 16-byte (double) or 8-byte (float) vector stores.  p must be aligned to
+// that width and N even.
+template <int N>
+__device__ inline void store_row(double* p, const double* v) {
+  static_assert(N % 2 == 0, "even rows only");
+#pragma unroll
+  for (int c = 0; c < N / 2; ++c) reinterpret_cast<double2*>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
+}
+template <int N>
+__device__ inline void store_row(float* p, const float* v) {
+  static_assert(N % 2 == 0, "even rows only");
+#pragma unroll
+  for (int c = 0; c < N / 2; ++c) reinterpret_cast<float2*>(p)[c] = make_float2(v[2 * c], v[2 * c + 1]);
+}
+
 constexpr size_t kArmConstBytes = 2048;  // derived arm model constants per job
 
 // Bandwidth median (see svgd.hip).  Up to kSmallPairs pairs one block
@@ -34,6 +50,7 @@ constexpr size_t kArmConstBytes = 2048;  // derived arm model constants per job
 constexpr int kSmallPairs = 32768;
 constexpr int kSampleKeys = 32768;
 constexpr int kMedThreads = 1024;
+constexpr int kDirectMax = 512;      // keys a selection finishes on by direct counting
 constexpr int kSelBins = 2048;       // bins per selection level (2^11)
 constexpr int kMaxLevels = 8;        // selection levels never exceed 6
 constexpr int kCountTile = 64;       // pairs per count block: 64 x 64
@@ -50,7 +67,8 @@ struct MedianState {
 struct WsLayout {
   size_t arm;                               // derived arm constants (arm jobs)
   size_t arm_states;                        // arm adjoint: every window state, [wave][step][16][lane]
-  size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients
+  size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients: [iu][m], [iu][d] with
+                                            // iu = (i K + k) n_s + j (one particle's units adjacent)
   size_t med;                               // median selection state
   size_t khi, klo;                          // median key words (all pairs, or a sample's high words)
   size_t cand;                              // median candidate keys (one slot per pair)
@@ -59,7 +77,8 @@ struct WsLayout {
 };
 
 constexpr int kPhiChunk = 32;    // particles j per LDS chunk in phi
-constexpr int kPhiWaves = 16;    // waves per phi block, splitting the j range
+constexpr int kPhiThreads = 1024;  // threads per block of the one-kernel phi
+constexpr int kPhiTI = 16;         // particles i per block of the one-kernel phi
 constexpr int kPhiFusedMaxN = 512;  // larger jobs use partial sums and a reduction
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -99,14 +118,19 @@ hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* ws, i
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_assemble_sdot(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 // Particles with at most this many shooting-state components get S_dot from
-// their assembly block; larger ones from a one-thread-per-component kernel.
-constexpr int kSdotInline = 256;
+// their assembly block (two per thread); larger ones from a
+// one-thread-per-component kernel.
+constexpr int kSdotInline = 512;
 struct MedianMaps {
   JobMap keys, select, count, large;
   int grid_keys, grid_select, grid_count, grid_large;
 };
 hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, int mmax, int rank_shift,
                          hipStream_t s);
+// Step launches of at most this many blocks per job advance the device
+// iteration counter themselves (a completion count); larger ones are
+// followed by iter_bump.
+constexpr int kStepCountBlocks = 256;
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
 hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,

@@ -114,6 +114,7 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     REQ(theta, 4); REQ(lo, 4); REQ(hi, 4); REQ(lr_theta, 4); REQ(lam_lim, 4); REQ(phi, 4); REQ(g_con, 8);
     REQ(adam_m, 4); REQ(adam_v, 4);
     if (J.n_s > 1) { REQ(S, 4); REQ(S_dot, 4); REQ(lam_def, 4); REQ(gdef, 8); REQ(lr_S, 4); }
+    if (J.iter_dev && !aligned(J.iter_dev, 8)) return fail(PDS_EINVAL, "job %d: iter_dev is misaligned", idx);
   }
 #undef REQ
   return PDS_OK;
@@ -320,7 +321,7 @@ int phi_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, cons
     int grid = 0;
     JobMap mf = make_map(
         h_jobs, n_jobs, off, [&](const pds_job& J) { return in_cls(J) && J.N <= pds::kPhiFusedMaxN; },
-        [](const pds_job& J) { return div_up(J.N, pds::kWave); }, &grid);
+        [](const pds_job& J) { return div_up(J.N, pds::kPhiTI); }, &grid);
     if (mf.n > 0) {
       rc = launch_rc(pds::launch_phi(mf, d_jobs, grid, hi_m, s), "phi");
       if (rc) return rc;
@@ -551,21 +552,20 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
     if (optimizer == PDS_OPT_ADAM && iter < 1 && !h_jobs[j].iter_dev)
       return fail(PDS_EINVAL, "Adam needs iter >= 1 or a device iteration counter");
   std::vector<uint64_t> off(n_jobs, 0);
+  auto blocks = [](const pds_job& J) {
+    const long ds = 2 * J.n_dof;
+    const long n = (long)J.N * J.M + (long)J.N * J.K * (J.n_s - 1) * ds + (long)J.N * J.K * (J.n_s - 1);
+    return div_up(n, 256);
+  };
   int grid = 0;
-  JobMap m = make_map(
-      h_jobs, n_jobs, off, [](const pds_job&) { return true; },
-      [](const pds_job& J) {
-        const long ds = 2 * J.n_dof;
-        const long n = (long)J.N * J.M + (long)J.N * J.K * (J.n_s - 1) * ds + (long)J.N * J.K * (J.n_s - 1);
-        return div_up(n, 256);
-      },
-      &grid);
+  JobMap m = make_map(h_jobs, n_jobs, off, [](const pds_job&) { return true; }, blocks, &grid);
   rc = launch_rc(pds::launch_step(m, d_jobs, grid, optimizer, iter, (hipStream_t)stream), "step");
   if (rc) return rc;
   int bgrid = 0;
   JobMap mb = make_map(
-      h_jobs, n_jobs, off, [](const pds_job& J) { return J.iter_dev != nullptr; }, [](const pds_job&) { return 1; },
-      &bgrid);
+      h_jobs, n_jobs, off,
+      [&](const pds_job& J) { return J.iter_dev != nullptr && blocks(J) > pds::kStepCountBlocks; },
+      [](const pds_job&) { return 1; }, &bgrid);
   if (mb.n == 0) return PDS_OK;
   return launch_rc(pds::launch_iter_bump(mb, d_jobs, bgrid, (hipStream_t)stream), "iter_bump");
 }

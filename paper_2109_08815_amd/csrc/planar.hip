@@ -629,29 +629,27 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     double* gth = ch == 0 ? gth_obs : gth_con;
     float* gs = ch == 0 ? gs_obs : gs_con;
 #pragma unroll
-    for (int m = 0; m < 2 * NB; ++m) {
-      gth[(size_t)m * U + u] = gm_a[m];
-      bad |= !isfinite(gm_a[m]);
-    }
+    for (int m = 0; m < 2 * NB; ++m) bad |= !isfinite(gm_a[m]);
+    store_row<2 * NB>(gth + iu * (2 * NB), gm_a);
+    float row[DS];
 #pragma unroll
-    for (int d = 0; d < NB; ++d) {
-      gs[(size_t)d * U + u] = qb_a[d];
-      gs[(size_t)(NB + d) * U + u] = qdb_a[d];
-    }
+    for (int d = 0; d < NB; ++d) { row[d] = qb_a[d]; row[NB + d] = qdb_a[d]; }
+    store_row<DS>(gs + iu * DS, row);
   } else {
 #pragma unroll
-    for (int m = 0; m < 2 * NB; ++m) {
-      gth_obs[(size_t)m * U + u] = gm_a[m];
-      gth_con[(size_t)m * U + u] = gm_c[m];
-      bad |= !isfinite(gm_a[m]) || !isfinite(gm_c[m]);
-    }
+    for (int m = 0; m < 2 * NB; ++m) bad |= !isfinite(gm_a[m]) || !isfinite(gm_c[m]);
+    store_row<2 * NB>(gth_obs + iu * (2 * NB), gm_a);
+    store_row<2 * NB>(gth_con + iu * (2 * NB), gm_c);
+    float ra[DS], rc[DS];
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
-      gs_obs[(size_t)d * U + u] = qb_a[d];
-      gs_obs[(size_t)(NB + d) * U + u] = qdb_a[d];
-      gs_con[(size_t)d * U + u] = qb_c[d];
-      gs_con[(size_t)(NB + d) * U + u] = qdb_c[d];
+      ra[d] = qb_a[d];
+      ra[NB + d] = qdb_a[d];
+      rc[d] = qb_c[d];
+      rc[NB + d] = qdb_c[d];
     }
+    store_row<DS>(gs_obs + iu * DS, ra);
+    store_row<DS>(gs_con + iu * DS, rc);
   }
   if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
 }

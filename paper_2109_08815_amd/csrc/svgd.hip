@@ -6,22 +6,27 @@
 // FP32 particles.  A non-negative IEEE double orders like its bit pattern
 // read as uint64, so selection works on the 64-bit patterns ("keys") of
 // the squared distances, and both middle order statistics ((P-1)/2 and P/2
-// of P pairs) are found together.  Two kernels:
-//  * bracket: one block per job.  Up to 16384 pairs it holds every key in
-//    LDS and selects exactly.  Otherwise it selects two order statistics of
-//    a fixed pseudo-random sample of 16384 keys that bracket the middle
-//    ranks with a margin of four binomial standard deviations.
-//  * count: every pair once, 32 x 32 pairs per block; keys below the
-//    bracket are counted and keys inside it appended to a candidate array;
-//    the last block selects exactly among the candidates (or, if the
-//    bracket missed, among all keys of the side that holds the ranks).
-// Selection narrows a key interval per rank by 2^11-bin histograms of
-// (key - lo) >> sh, so it needs at most seven passes over the keys it
-// holds whatever the distribution; counts are integers, so the result does
-// not depend on the order in which blocks finish.
+// of P pairs) are found together.  Kernels:
+//  * keys: up to kSmallPairs pairs, every pair's key (high and low words);
+//    above, the high words of a fixed pseudo-random sample of kSampleKeys
+//    pairs.
+//  * select: one block per job, the high words in registers.  A histogram
+//    of 2^11 bins over [min, max] narrows both middle ranks; the keys of
+//    the two bins are then ranked by direct counting (further levels when
+//    the bins hold more than kDirectMax keys).  Small jobs get the exact
+//    median; larger ones a bracket [a, b] on the sample's order statistics
+//    widened by four binomial standard deviations.
+//  * count (larger jobs): every pair once, 64 x 64 pairs per block; keys
+//    below a are counted and keys inside [a, b] appended to a candidate
+//    array, both with one atomic add per block.
+//  * final (larger jobs): one block selects exactly among the candidates,
+//    or, if the bracket missed a middle rank, among all keys of the side
+//    that holds it.
+// Counts are integers, so the result does not depend on the order in which
+// blocks finish.
 //
-// phi.  Up to kPhiFusedMaxN particles: one block per 64 particles i whose
-// waves split the j range.  Larger jobs: blocks of 64 particles i against
+// phi.  Up to kPhiFusedMaxN particles: one block per 16 particles i with
+// every particle's row in LDS and 64 slices of the j range.  Larger jobs: blocks of 64 particles i against
 // chunks of 32 particles j (enough blocks to fill the chip), then a
 // reduction over chunks.  Both accumulate in FP32 in a fixed order.
 #include <cmath>
@@ -322,6 +327,46 @@ __device__ void sel_count_finish(const KT* src, uint32_t n, SS& S) {
   __syncthreads();
 }
 
+// Direct finish with g = min(64, NT / 2^ceil(log2 n)) consecutive threads
+// per key, each counting over its share of the n keys; the shares are
+// summed across the g lanes.  Same ranks and result as sel_count_finish.
+template <int NT, class KT, class SS>
+__device__ void sel_count_finish_split(const KT* src, uint32_t n, SS& S) {
+  __syncthreads();
+  const SelTarget<KT> t0 = S.tg[0], t1 = S.tg[1];
+  const bool l0 = t0.lo != t0.hi, l1 = t1.lo != t1.hi;
+  uint32_t np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  const uint32_t g = NT / np2 < 64 ? NT / np2 : 64;  // n <= NT, so g >= 1
+  const uint32_t c = threadIdx.x / g, part = threadIdx.x % g;
+  const uint32_t per = (n + g - 1) / g;
+  const uint32_t q0 = part * per, q1 = q0 + per < n ? q0 + per : n;
+  const KT x = n > 0 ? src[c < n ? c : n - 1] : (KT)0;
+  uint32_t r0 = 0, r1 = 0;
+  constexpr int U = 8;
+  for (uint32_t qb = q0; c < n && qb < q1; qb += U) {
+    KT y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) y[u] = src[qb + u < q1 ? qb + u : q1 - 1];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t q = qb + u;
+      const bool before = q < q1 && (y[u] < x || (y[u] == x && q < c));
+      r0 += (before && y[u] >= t0.lo && y[u] <= t0.hi) ? 1u : 0u;
+      r1 += (before && y[u] >= t1.lo && y[u] <= t1.hi) ? 1u : 0u;
+    }
+  }
+  for (uint32_t o = 1; o < g; o <<= 1) {
+    r0 += __shfl_xor(r0, (int)o);
+    r1 += __shfl_xor(r1, (int)o);
+  }
+  if (part == 0 && c < n) {
+    if (l0 && x >= t0.lo && x <= t0.hi && r0 == t0.t) S.tg[0] = SelTarget<KT>{x, x, 0u};
+    if (l1 && x >= t1.lo && x <= t1.hi && r1 == t1.t) S.tg[1] = SelTarget<KT>{x, x, 0u};
+  }
+  __syncthreads();
+}
+
 // Two targets alone (the state of a direct finish).
 template <class KT>
 struct SelPair {
@@ -448,138 +493,20 @@ __global__ void __launch_bounds__(256) median_keys_kernel(JobMap map, const pds_
   if (small) reinterpret_cast<uint32_t*>(base + L.klo)[k] = (uint32_t)key;
 }
 
-// Select kernel, one block per job.  Loads the high words written by the
-// keys kernel into LDS (the first selection level, over [0, 2^32), is
-// histogrammed during the load) and selects two ranks among them: the
-// middle ranks of all pairs for small jobs, which then finish on the low
-// words of the keys sharing the selected high words; for larger jobs the
-// sample's order statistics at the middle ranks' sample positions widened
-// by four binomial standard deviations, stored as the bracket [a, b]
-// (whole high words) for the count kernel.
-__global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                                    char* __restrict__ ws, int rank_shift) {
-  __shared__ uint32_t hs[kSmallPairs];
-  __shared__ SelShared<uint32_t> S;
-  __shared__ uint64_t cand[kMedThreads];
-  __shared__ SelPair<uint64_t> P64;
-  constexpr int NT = kMedThreads;
-  const int e = map_entry(map, blockIdx.x);
-  const pds_job& J = jobs[map.job[e]];
-  const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
-  if (P == 0) {
-    if (threadIdx.x == 0) write_bandwidth(J, 0ull, 0ull);
-    return;
-  }
-  const bool small = P <= (uint64_t)kSmallPairs;
-  const uint32_t n = small ? (uint32_t)P : (uint32_t)kSampleKeys;
-  const WsLayout L = ws_layout(J);
-  char* base = ws + map.ws_off[e];
-  const uint32_t* khi = reinterpret_cast<const uint32_t*>(base + L.khi);
-  uint32_t mn = ~0u, mx = 0u;
-  constexpr int U = 8;
-  for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
-    uint32_t h[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t c = c0 + u * NT + threadIdx.x;
-      h[u] = khi[c < n ? c : n - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const uint32_t c = c0 + u * NT + threadIdx.x;
-      if (c < n) {
-        hs[c] = h[u];
-        mn = h[u] < mn ? h[u] : mn;
-        mx = h[u] > mx ? h[u] : mx;
-      }
-    }
-  }
-  uint32_t lo, hi;
-  block_minmax<NT>(mn, mx, S, &lo, &hi);  // its barriers also complete hs[]
-  uint32_t t0, t1;
-  bool a_open = false, b_open = false;
-  if (small) {
-    t0 = (uint32_t)((P - 1) / 2);
-    t1 = (uint32_t)(P / 2);
-  } else {
-    const double d = 2.0 * sqrt((double)n) + 2.0;
-    const double c0 = (double)n * (double)((P - 1) / 2) / (double)P - d + rank_shift;
-    const double c1 = (double)n * (double)(P / 2 + 1) / (double)P + d + rank_shift;
-    a_open = c0 < 0.0;
-    b_open = c1 > (double)(n - 1);
-    t0 = a_open ? 0u : (uint32_t)fmin(floor(c0), (double)(n - 1));
-    t1 = b_open ? n - 1 : (uint32_t)fmax(ceil(c1), 0.0);
-  }
-  // first level over the keys' own range [lo, hi]
-  const SelTarget<uint32_t> full0{lo, hi, t0}, full1{lo, hi, t1};
-  const bool spread = lo != hi;
-  if (spread) {
-    const SelTarget<uint32_t> tt[2] = {full0, full1};
-    const bool live[2] = {true, true};
-    const int sh[2] = {sel_shift<uint32_t>(hi - lo), sel_shift<uint32_t>(hi - lo)};
-    sel_histogram<NT>(hs, n, S, tt, live, sh);
-    sel_narrow<NT>(S, 0, 0, full0, sh[0]);
-    sel_narrow<NT>(S, 1, 0, full1, sh[1]);
-  } else if (threadIdx.x == 0) {
-    S.tg[0] = full0;
-    S.tg[1] = full1;
-  }
-  __syncthreads();
-  const SelTarget<uint32_t> b0 = S.tg[0], b1 = S.tg[1];
-  const bool same_bin = b0.lo == b1.lo && b0.hi == b1.hi;
-  const uint32_t need = !spread ? n : (same_bin ? S.cnt[0] : S.cnt[0] + S.cnt[1]);
+// More than kDirectMax keys in the middle bins of the first level:
+// further levels over the high words in LDS, then (small jobs) over the low
+// words of the keys whose high word is a selected one.  Out of line, so its
+// registers stay out of the common path.
+template <int NT>
+__device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws, uint64_t ws_off, uint32_t* hs,
+                                                      SelShared<uint32_t>& S, const uint32_t* klo, uint32_t n,
+                                                      bool small, bool a_open, bool b_open) {
   constexpr int kSteps = kSmallPairs / NT;
-  const uint32_t* klo = reinterpret_cast<const uint32_t*>(base + L.klo);
-  if (need <= (uint32_t)NT) {
-    // Direct finish: the (at most NT) keys in the two bins, as full 64-bit
-    // keys for small jobs, are ranked by counting.
-    uint32_t mask = 0u, cnt = 0u;
-    uint32_t hv[kSteps];
-#pragma unroll
-    for (int u = 0; u < kSteps; ++u) {
-      const uint32_t c = u * NT + threadIdx.x;
-      hv[u] = hs[c < n ? c : n - 1];
-    }
-#pragma unroll
-    for (int u = 0; u < kSteps; ++u) {
-      const uint32_t c = u * NT + threadIdx.x;
-      const uint32_t h = hv[u];
-      if (c < n && ((h >= b0.lo && h <= b0.hi) || (h >= b1.lo && h <= b1.hi))) {
-        mask |= 1u << u;
-        ++cnt;
-      }
-    }
-    uint32_t total;
-    uint32_t o = block_scan<NT>(cnt, S, &total);
-#pragma unroll
-    for (int u = 0; u < kSteps; ++u)
-      if (mask & (1u << u)) {
-        const uint32_t c = u * NT + threadIdx.x;
-        cand[o++] = ((uint64_t)hs[c] << 32) | (small ? (uint64_t)klo[c] : 0ull);
-      }
-    if (threadIdx.x == 0) {
-      P64.tg[0] = SelTarget<uint64_t>{(uint64_t)b0.lo << 32, ((uint64_t)b0.hi << 32) | 0xffffffffull, b0.t};
-      P64.tg[1] = SelTarget<uint64_t>{(uint64_t)b1.lo << 32, ((uint64_t)b1.hi << 32) | 0xffffffffull, b1.t};
-    }
-    __syncthreads();
-    sel_count_finish<NT>(cand, total, P64);
-    if (threadIdx.x == 0) {
-      const uint64_t k0 = P64.tg[0].lo, k1 = P64.tg[1].lo;
-      if (small) {
-        write_bandwidth(J, k0, k1);
-      } else {
-        MedianState* st = med_state(J, ws, map.ws_off[e]);
-        st->a = a_open ? 0ull : (k0 >> 32) << 32;
-        st->b = b_open ? ~0ull : ((k1 >> 32) << 32) | 0xffffffffull;
-      }
-    }
-    return;
-  }
   uint32_t hsel[2];
   select_keys<NT>(hs, n, false, (uint32_t*)nullptr, 0u, S, hsel, false);
   if (!small) {
     if (threadIdx.x == 0) {
-      MedianState* st = med_state(J, ws, map.ws_off[e]);
+      MedianState* st = med_state(J, ws, ws_off);
       st->a = a_open ? 0ull : (uint64_t)hsel[0] << 32;
       st->b = b_open ? ~0ull : (((uint64_t)hsel[1] << 32) | 0xffffffffull);
     }
@@ -632,6 +559,198 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
   }
   if (threadIdx.x == 0)
     write_bandwidth(J, ((uint64_t)hsel[0] << 32) | lsel[0], ((uint64_t)hsel[1] << 32) | lsel[1]);
+}
+
+// Select kernel, one block per job.  Loads the high words written by the
+// keys kernel into LDS (the first selection level, over [0, 2^32), is
+// histogrammed during the load) and selects two ranks among them: the
+// middle ranks of all pairs for small jobs, which then finish on the low
+// words of the keys sharing the selected high words; for larger jobs the
+// sample's order statistics at the middle ranks' sample positions widened
+// by four binomial standard deviations, stored as the bracket [a, b]
+// (whole high words) for the count kernel.
+__global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                                    char* __restrict__ ws, int rank_shift) {
+  __shared__ __align__(16) uint32_t hs[kSmallPairs];  // used by select_rest only
+  __shared__ SelShared<uint32_t> S;
+  __shared__ uint64_t cand[kDirectMax];
+  __shared__ uint32_t cidx[kDirectMax];
+  __shared__ SelPair<uint64_t> P64;
+  __shared__ uint32_t s_lo, s_hi, s_cnt;
+  constexpr int NT = kMedThreads;
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
+  if (P == 0) {
+    if (threadIdx.x == 0) write_bandwidth(J, 0ull, 0ull);
+    return;
+  }
+  const bool small = P <= (uint64_t)kSmallPairs;
+  const uint32_t n = small ? (uint32_t)P : (uint32_t)kSampleKeys;
+  const WsLayout L = ws_layout(J);
+  char* base = ws + map.ws_off[e];
+  const uint32_t* khi = reinterpret_cast<const uint32_t*>(base + L.khi);
+  const uint32_t* klo = reinterpret_cast<const uint32_t*>(base + L.klo);
+  // Every key's high word in registers: thread element k = 4 v + c is key
+  // 4 (v NT + thread) + c, loaded 16 bytes at a time, all loads in flight
+  // together (the last vector may extend past n into the region's 256-byte
+  // padding).  Elements past n hold kNoKey, above every key's high word
+  // (the sign bit is clear), so each later test is a compare on the value
+  // itself, made where it is used.
+  constexpr int V = kSmallPairs / (4 * NT);
+  constexpr uint32_t kNoKey = 0xffffffffu;
+  static_assert(kSampleKeys <= kSmallPairs, "register layout holds the sample");
+  static_assert(kSelBins == 2 * NT, "two histogram bins per thread");
+  uint32_t hv[4 * V];
+  const uint32_t n4 = (n + 3) / 4;
+  uint4 q[V];
+  {
+    const uint4* k4 = reinterpret_cast<const uint4*>(khi);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const uint32_t idx = v * NT + threadIdx.x;
+      q[v] = k4[idx < n4 ? idx : n4 - 1];
+    }
+  }
+  auto key_at = [&](int k) { return 4u * ((k >> 2) * NT + threadIdx.x) + (k & 3); };
+  // while the loads are in flight: clear the histogram and the block's
+  // min / max / candidate count
+  for (int b = threadIdx.x; b < kSelBins; b += NT) S.hist[0][b] = 0u;
+  if (threadIdx.x == 0) {
+    s_lo = kNoKey;
+    s_hi = 0u;
+    s_cnt = 0u;
+  }
+  __syncthreads();
+  uint32_t mn = kNoKey, mx = 0u;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t w4[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint32_t h = key_at(4 * v + c) < n ? w4[c] : kNoKey;
+      hv[4 * v + c] = h;
+      mn = h < mn ? h : mn;
+      mx = (h != kNoKey && h > mx) ? h : mx;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t a = (uint32_t)__shfl_xor((int)mn, o), b = (uint32_t)__shfl_xor((int)mx, o);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&s_lo, mn);
+    atomicMax(&s_hi, mx);
+  }
+  __syncthreads();
+  const uint32_t lo = s_lo, hi = s_hi;
+  uint32_t t0, t1;
+  bool a_open = false, b_open = false;
+  if (small) {
+    t0 = (uint32_t)((P - 1) / 2);
+    t1 = (uint32_t)(P / 2);
+  } else {
+    const double d = 2.0 * sqrt((double)n) + 2.0;
+    const double c0 = (double)n * (double)((P - 1) / 2) / (double)P - d + rank_shift;
+    const double c1 = (double)n * (double)(P / 2 + 1) / (double)P + d + rank_shift;
+    a_open = c0 < 0.0;
+    b_open = c1 > (double)(n - 1);
+    t0 = a_open ? 0u : (uint32_t)fmin(floor(c0), (double)(n - 1));
+    t1 = b_open ? n - 1 : (uint32_t)fmax(ceil(c1), 0.0);
+  }
+  // First level over the keys' own range [lo, hi]: one histogram for both
+  // targets and one block scan over it narrows both.
+  if (lo != hi) {
+    const uint32_t span = hi - lo;
+    const int sh = sel_shift<uint32_t>(span);
+#pragma unroll
+    for (int k = 0; k < 4 * V; ++k) {
+      const uint32_t d = hv[k] - lo;
+      if (d <= span) atomicAdd(&S.hist[0][d >> sh], 1u);
+    }
+    __syncthreads();
+    const int b0 = 2 * threadIdx.x;
+    const uint32_t c0 = S.hist[0][b0], c1 = S.hist[0][b0 + 1];
+    const uint32_t local = c0 + c1;
+    const uint32_t inc = wave_scan(local);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) S.wsum[w] = inc;
+    __syncthreads();
+    uint32_t below = inc - local;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) below += k < w ? S.wsum[k] : 0u;
+    const uint32_t tt[2] = {t0, t1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (below <= tt[k] && tt[k] < below + local) {
+        const bool first = tt[k] - below < c0;
+        const uint32_t b = first ? b0 : b0 + 1;
+        S.tg[k].lo = lo + (b << sh);
+        S.tg[k].hi = b == (span >> sh) ? hi : lo + ((b + 1) << sh) - 1;
+        S.tg[k].t = first ? tt[k] - below : tt[k] - below - c0;
+        S.cnt[k] = first ? c0 : c1;
+      }
+    }
+  } else if (threadIdx.x == 0) {
+    S.tg[0] = SelTarget<uint32_t>{lo, hi, t0};
+    S.tg[1] = SelTarget<uint32_t>{lo, hi, t1};
+  }
+  __syncthreads();
+  const SelTarget<uint32_t> g0 = S.tg[0], g1 = S.tg[1];
+  const bool same_bin = g0.lo == g1.lo && g0.hi == g1.hi;
+  const uint32_t need = lo == hi ? n : (same_bin ? S.cnt[0] : S.cnt[0] + S.cnt[1]);
+  if (need <= (uint32_t)kDirectMax) {
+    // Direct finish: the indices of the keys in the two bins go to cidx
+    // (order immaterial: the ranking below orders by value, then by
+    // position), their full 64-bit keys are fetched with one pair of loads
+    // per thread, and the two ranks are found by counting.
+    uint32_t mask = 0u;
+#pragma unroll
+    for (int k = 0; k < 4 * V; ++k) {
+      const uint32_t h = hv[k];
+      const bool in = h - g0.lo <= g0.hi - g0.lo || h - g1.lo <= g1.hi - g1.lo;  // kNoKey is in neither
+      mask |= (in ? 1u : 0u) << k;
+    }
+    if (mask) {
+      uint32_t o = atomicAdd(&s_cnt, (uint32_t)__popc(mask));
+#pragma unroll
+      for (int k = 0; k < 4 * V; ++k)
+        if ((mask >> k) & 1u) cidx[o++] = key_at(k);
+    }
+    if (threadIdx.x == 0) {
+      P64.tg[0] = SelTarget<uint64_t>{(uint64_t)g0.lo << 32, ((uint64_t)g0.hi << 32) | 0xffffffffull, g0.t};
+      P64.tg[1] = SelTarget<uint64_t>{(uint64_t)g1.lo << 32, ((uint64_t)g1.hi << 32) | 0xffffffffull, g1.t};
+    }
+    __syncthreads();
+    const uint32_t total = s_cnt;
+    if (threadIdx.x < total) {
+      const uint32_t k = cidx[threadIdx.x];
+      cand[threadIdx.x] = ((uint64_t)khi[k] << 32) | (small ? (uint64_t)klo[k] : 0ull);
+    }
+    sel_count_finish_split<NT>(cand, total, P64);
+    if (threadIdx.x == 0) {
+      const uint64_t k0 = P64.tg[0].lo, k1 = P64.tg[1].lo;
+      if (small) {
+        write_bandwidth(J, k0, k1);
+      } else {
+        MedianState* st = med_state(J, ws, map.ws_off[e]);
+        st->a = a_open ? 0ull : (k0 >> 32) << 32;
+        st->b = b_open ? ~0ull : ((k1 >> 32) << 32) | 0xffffffffull;
+      }
+    }
+    return;
+  }
+  // More than kDirectMax keys in the middle bins: further levels over the
+  // high words, held in LDS from here on.
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    if (v * NT + threadIdx.x < n4)
+      reinterpret_cast<uint4*>(hs)[v * NT + threadIdx.x] =
+          make_uint4(hv[4 * v], hv[4 * v + 1], hv[4 * v + 2], hv[4 * v + 3]);
+  __syncthreads();
+  select_rest<NT>(J, ws, map.ws_off[e], hs, S, klo, n, small, a_open, b_open);
 }
 
 // Keys of every pair inside [lo, hi] into cand (block-scan order); one
@@ -862,24 +981,35 @@ __global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_j
   J.phi[t] = s / (float)J.N;
 }
 
-// Jobs up to kPhiFusedMaxN particles: phi for 64 particles i per block (one
-// per lane), the j range split over
-// kPhiWaves waves: each wave stages chunks of its j range in LDS (rows
-// padded with zeros to MM parameters, so the parameter loops run without
-// branches) and accumulates in j order; the waves' partial sums are then
-// added in wave order.  Every sum has a fixed order.
+// Jobs up to kPhiFusedMaxN particles: phi for kPhiTI particles i per block,
+// so even small jobs spread over many compute units.  The block stages
+// every particle's row and driving term in LDS (rows padded with zeros to
+// MM parameters, so the parameter loops run without branches); thread
+// (il, js) accumulates particle i0 + il over j = js, js + 64, ... in that
+// order; the four slices of a wave that share il are added by a fixed
+// shuffle tree, then the 16 waves' sums in wave order.  Every sum has a
+// fixed order that depends on N alone.
 template <int MM>
-__global__ void __launch_bounds__(kPhiWaves * kWave) phi_kernel(JobMap map, const pds_job* __restrict__ jobs) {
-  __shared__ float tj_s[kPhiWaves][kPhiChunk * MM];
-  __shared__ float gj_s[kPhiWaves][kPhiChunk * MM];
-  __shared__ float acc_s[kPhiWaves][kWave * MM];
+__global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_job* __restrict__ jobs) {
+  __shared__ float tj_s[kPhiFusedMaxN * MM];
+  __shared__ float gj_s[kPhiFusedMaxN * MM];
+  __shared__ float red[kPhiThreads / kWave][kPhiTI * MM];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int N = J.N, M = J.M;
-  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int i = (blockIdx.x - map.begin[e]) * kWave + lane;
-  const int per = (N + kPhiWaves - 1) / kPhiWaves;  // j per wave
-  const int ja = w * per, jb = min(N, ja + per);
+  const int il = threadIdx.x % kPhiTI, js = threadIdx.x / kPhiTI;
+  const int w = threadIdx.x / kWave;
+  const int i = (blockIdx.x - map.begin[e]) * kPhiTI + il;
+  constexpr int kSlices = kPhiThreads / kPhiTI;  // j stride
+  // every row into LDS, zero-padded to MM parameters
+  for (int t = threadIdx.x; t < N * MM; t += kPhiThreads) {
+    const int r = t / MM, m = t % MM;
+    const size_t src = (size_t)r * M + (m < M ? m : M - 1);
+    const float th = J.theta[src];
+    const double g = J.g_obs[src];
+    tj_s[t] = m < M ? th : 0.f;
+    gj_s[t] = m < M ? (float)g : 0.f;
+  }
   const float h = (float)J.bandwidth[0];
   const float inv_h = 1.0f / h;
   float ti[MM], rh[MM], ir[MM], ir2[MM], acc[MM];
@@ -891,44 +1021,37 @@ __global__ void __launch_bounds__(kPhiWaves * kWave) phi_kernel(JobMap map, cons
     ir2[m] = ir[m] * ir[m];
     acc[m] = 0.f;
   }
-  const int nchunks = (per + kPhiChunk - 1) / kPhiChunk;  // equal for every wave
-  for (int c = 0; c < nchunks; ++c) {
-    const int j0 = ja + c * kPhiChunk;
-    const int nj = max(0, min(kPhiChunk, jb - j0));
-    for (int t = lane; t < kPhiChunk * MM; t += kWave) {
-      const int r = t / MM, m = t % MM;
-      const bool in = r < nj && m < M;
-      const size_t src = (size_t)(in ? j0 + r : 0) * M + (in ? m : 0);
-      tj_s[w][t] = in ? J.theta[src] : 0.f;
-      gj_s[w][t] = in ? (float)J.g_obs[src] : 0.f;
-    }
-    __syncthreads();
-    for (int jj = 0; jj < nj; ++jj) {
-      float d2 = 0.f;
-#pragma unroll
-      for (int m = 0; m < MM; ++m) {
-        const float z = (ti[m] - tj_s[w][jj * MM + m]) * ir[m];
-        d2 += z * z;
-      }
-      const float k = expf(-d2 * inv_h);
-      const float k2h = 2.0f * k * inv_h;
-#pragma unroll
-      for (int m = 0; m < MM; ++m)
-        acc[m] += k * gj_s[w][jj * MM + m] + k2h * (ti[m] - tj_s[w][jj * MM + m]) * ir2[m];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int m = 0; m < MM; ++m) acc_s[w][lane * MM + m] = acc[m];
   __syncthreads();
-  if (w == 0 && i < N) {
+  for (int j = js; j < N; j += kSlices) {
+    float d2 = 0.f;
 #pragma unroll
     for (int m = 0; m < MM; ++m) {
-      float s = 0.f;
-#pragma unroll
-      for (int v = 0; v < kPhiWaves; ++v) s += acc_s[v][lane * MM + m];
-      if (m < M) J.phi[(size_t)i * M + m] = s / (float)N;
+      const float z = (ti[m] - tj_s[j * MM + m]) * ir[m];
+      d2 += z * z;
     }
+    const float k = expf(-d2 * inv_h);
+    const float k2h = 2.0f * k * inv_h;
+#pragma unroll
+    for (int m = 0; m < MM; ++m) acc[m] += k * gj_s[j * MM + m] + k2h * (ti[m] - tj_s[j * MM + m]) * ir2[m];
+  }
+  // lanes il, il + 16, il + 32, il + 48 of a wave hold the same particle
+#pragma unroll
+  for (int m = 0; m < MM; ++m) {
+    acc[m] += __shfl_xor(acc[m], kPhiTI);
+    acc[m] += __shfl_xor(acc[m], 2 * kPhiTI);
+  }
+  if ((threadIdx.x % kWave) < kPhiTI) {
+#pragma unroll
+    for (int m = 0; m < MM; ++m) red[w][il * MM + m] = acc[m];
+  }
+  __syncthreads();
+  if (threadIdx.x < kPhiTI * MM) {
+    const int r = threadIdx.x / MM, m = threadIdx.x % MM;
+    const int ir_ = (blockIdx.x - map.begin[e]) * kPhiTI + r;
+    float s = 0.f;
+#pragma unroll
+    for (int v = 0; v < kPhiThreads / kWave; ++v) s += red[v][r * MM + m];
+    if (ir_ < N && m < M) J.phi[(size_t)ir_ * M + m] = s / (float)N;
   }
 }
 
@@ -989,11 +1112,26 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
     const int r = t - nT - nS;
     J.lam_def[r] += J.eps_lam * (float)J.gdef[r];
   }
+  const int nb = map.begin[e + 1] - map.begin[e];
+  if (J.iter_dev && nb <= kStepCountBlocks) {
+    // Advance the device counter once every block of the job is past its
+    // use of it: each thread's stores above depend on the value it read,
+    // so after the barrier every read of this block has returned.  Blocks
+    // count themselves in iter_dev[1] with device-scope atomics; the last
+    // one bumps the counter and leaves the count at zero for the next call.
+    // (Same-address atomics serialise: larger jobs use iter_bump_kernel.)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (atomicAdd(&J.iter_dev[1], 1) == nb - 1) {
+        atomicExch(&J.iter_dev[1], 0);
+        atomicAdd(&J.iter_dev[0], 1);
+      }
+    }
+  }
 }
 
-// Advances the device iteration counter after the step kernel (a separate
-// launch: the step's blocks all read the counter, and a cross-block
-// completion count would cost more than this kernel).
+// Advances the device counter after the step kernel of a job with more
+// than kStepCountBlocks blocks.
 __global__ void iter_bump_kernel(JobMap map, const pds_job* __restrict__ jobs) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
@@ -1054,7 +1192,7 @@ hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws,
 }
 
 hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, hipStream_t s) {
-  const dim3 blk(kPhiWaves * kWave);
+  const dim3 blk(kPhiThreads);
   if (mmax <= 4)
     hipLaunchKernelGGL(phi_kernel<4>, dim3(grid), blk, 0, s, map, d_jobs);
   else if (mmax <= 8)

@@ -275,9 +275,9 @@ def csvgd_iteration(b: Batch, iteration: int, optimizer=PDS_OPT_ADAM, stream=Non
     side = b.side_stream()
     side.wait_stream(main)
     # (capture order matters for a graph: the branch enqueued first keeps
-    # the parent's queue; measured, the bandwidth first is the faster order)
-    svgd_bandwidth(b, side)
+    # the parent's queue, so the adjoint, the longer branch, goes first)
     sim_batch_adjoint(b, main)
+    svgd_bandwidth(b, side)
     main.wait_stream(side)
     svgd_phi_at_bandwidth(b, main)
     svgd_step(b, optimizer, iteration, main)

@@ -72,7 +72,7 @@ def _job(**kw):
 @pytest.mark.parametrize("bad,code", [
     (dict(T=21), -1), (dict(N=0), -1), (dict(dt=0.0), -1), (dict(sigma_def=-1.0), -1),
     (dict(n_dof=6, M=12, d_x=6), -2), (dict(model=2), -1), (dict(model=7), -1), (dict(M=3), -1),
-    (dict(combine=5), -1),
+    (dict(combine=5), -1), (dict(N=32769), -2),
 ])
 def test_invalid_jobs_rejected_on_host(bad, code):
     lib = L.lib()

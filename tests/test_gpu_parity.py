@@ -244,10 +244,13 @@ def test_bandwidth_exact_when_bracket_misses(orc, shift):
     assert abs(h - h_ref) <= 1e-15 * h_ref
 
 
-@pytest.mark.parametrize("groups", [(300, 300), (150, 200, 250), (599, 1)])
+@pytest.mark.parametrize("groups", [(300, 300), (150, 200, 250), (599, 1), (100, 100), (150, 50), (199, 1),
+                                    (64, 64, 72)])
 def test_bandwidth_exact_with_heavy_ties(orc, groups):
     """Particles stacked on a few points: most pair distances are exactly
-    equal, so candidate sets far exceed the LDS capacity."""
+    equal, so candidate sets far exceed the LDS capacity (jobs of up to 200
+    particles take the all-pairs selection, larger ones the sampled
+    bracket)."""
     print_case("bandwidth-ties", groups)
     pb = f32_problem(synth.make_problem("c2", N=sum(groups), K=1, T=40, n_s=2))
     pts = r32(pb.lo + np.random.default_rng(3).uniform(size=(len(groups), pb.M)) * (pb.hi - pb.lo))
