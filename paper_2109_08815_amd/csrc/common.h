@@ -51,6 +51,11 @@ constexpr int kSmallPairs = 32768;
 constexpr int kSampleKeys = 32768;
 constexpr int kMedThreads = 1024;
 constexpr int kDirectMax = 512;      // keys a selection finishes on by direct counting
+constexpr int kSelLdsCap = 8192;     // keys the select kernel's tie path stages in LDS
+// The select kernel is held to the registers of this many waves per SIMD
+// (and to a small LDS footprint) so that its block fits on a compute unit
+// beside an adjoint block and runs concurrently with it.
+constexpr int kSelWavesPerSimd = 5;
 constexpr int kSelBins = 2048;       // bins per selection level (2^11)
 constexpr int kMaxLevels = 8;        // selection levels never exceed 6
 constexpr int kCountTile = 64;       // pairs per count block: 64 x 64
@@ -71,7 +76,8 @@ struct WsLayout {
                                             // iu = (i K + k) n_s + j (one particle's units adjacent)
   size_t med;                               // median selection state
   size_t khi, klo;                          // median key words (all pairs, or a sample's high words)
-  size_t cand;                              // median candidate keys (one slot per pair)
+  size_t cand;                              // median candidates: 64-bit keys of larger jobs, or the
+                                            // low-word lists of small jobs (one slot per pair)
   size_t phi_part;                          // phi partial sums (jobs above kPhiFusedMaxN particles)
   size_t total;
 };
@@ -101,7 +107,7 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   const bool large = P > (size_t)kSmallPairs;
   L.khi = o;     o = align256(o + (large ? (size_t)kSampleKeys : P) * sizeof(uint32_t));
   L.klo = o;     o = align256(o + (large ? 0 : P) * sizeof(uint32_t));
-  L.cand = o;    o = align256(o + (large ? P : 0) * sizeof(uint64_t));
+  L.cand = o;    o = align256(o + P * (large ? sizeof(uint64_t) : sizeof(uint32_t)));
   const size_t chunks = J.N > kPhiFusedMaxN ? ((size_t)J.N + kPhiChunk - 1) / kPhiChunk : 0;
   L.phi_part = o; o = align256(o + chunks * (size_t)J.N * J.M * sizeof(float));
   L.total = o;

@@ -493,17 +493,19 @@ __global__ void __launch_bounds__(256) median_keys_kernel(JobMap map, const pds_
   if (small) reinterpret_cast<uint32_t*>(base + L.klo)[k] = (uint32_t)key;
 }
 
-// More than kDirectMax keys in the middle bins of the first level:
-// further levels over the high words in LDS, then (small jobs) over the low
-// words of the keys whose high word is a selected one.  Out of line, so its
-// registers stay out of the common path.
+// More than kDirectMax keys in the middle bins of the first level (heavy
+// ties): further levels over the high words in global memory (moved to the
+// LDS buffer lbuf once the live keys fit), then, for small jobs, over the
+// low words of the keys whose high word is a selected one, compacted into
+// the job's list region.  Out of line, so its registers stay out of the
+// common path.
 template <int NT>
-__device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws, uint64_t ws_off, uint32_t* hs,
-                                                      SelShared<uint32_t>& S, const uint32_t* klo, uint32_t n,
-                                                      bool small, bool a_open, bool b_open) {
-  constexpr int kSteps = kSmallPairs / NT;
+__device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws, uint64_t ws_off, uint32_t* lbuf,
+                                                      SelShared<uint32_t>& S, const uint32_t* khi,
+                                                      const uint32_t* klo, uint32_t* lists, uint32_t n, bool small,
+                                                      bool a_open, bool b_open) {
   uint32_t hsel[2];
-  select_keys<NT>(hs, n, false, (uint32_t*)nullptr, 0u, S, hsel, false);
+  select_keys<NT>(khi, n, true, lbuf, (uint32_t)kSelLdsCap, S, hsel, false);
   if (!small) {
     if (threadIdx.x == 0) {
       MedianState* st = med_state(J, ws, ws_off);
@@ -516,37 +518,27 @@ __device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws
   const bool same = hsel[0] == hsel[1];
   // Low words of the keys whose high word is a selected one: list A for
   // hsel[0], then list B for hsel[1] when it differs.
-  uint32_t mA = 0u, mB = 0u, cA = 0u, cB = 0u;
-#pragma unroll
-  for (int u = 0; u < kSteps; ++u) {
-    const uint32_t c = u * NT + threadIdx.x;
-    if (c < n) {
-      const uint32_t h = hs[c];
-      if (h == hsel[0]) {
-        mA |= 1u << u;
-        ++cA;
-      } else if (!same && h == hsel[1]) {
-        mB |= 1u << u;
-        ++cB;
-      }
-    }
+  uint32_t cA = 0u, cB = 0u;
+  for (uint32_t c = threadIdx.x; c < n; c += NT) {
+    const uint32_t h = khi[c];
+    cA += h == hsel[0] ? 1u : 0u;
+    cB += (!same && h == hsel[1]) ? 1u : 0u;
   }
   uint32_t nA, nB;
-  uint32_t oA = block_scan<NT>(cA, S, &nA);  // its barriers end every read of hs[]
+  uint32_t oA = block_scan<NT>(cA, S, &nA);
   uint32_t oB = nA + block_scan<NT>(cB, S, &nB);
-#pragma unroll
-  for (int u = 0; u < kSteps; ++u) {
-    const uint32_t bit = 1u << u;
-    if (mA & bit) hs[oA++] = klo[u * NT + threadIdx.x];
-    if (mB & bit) hs[oB++] = klo[u * NT + threadIdx.x];
+  for (uint32_t c = threadIdx.x; c < n; c += NT) {
+    const uint32_t h = khi[c];
+    if (h == hsel[0]) lists[oA++] = klo[c];
+    else if (!same && h == hsel[1]) lists[oB++] = klo[c];
   }
   if (threadIdx.x == 0) {
     S.tg[0] = SelTarget<uint32_t>{0u, ~0u, rk0};
     S.tg[1] = same ? SelTarget<uint32_t>{0u, ~0u, rk1} : SelTarget<uint32_t>{0u, 0u, 0u};
   }
-  __syncthreads();
+  __syncthreads();  // the lists are complete and visible to the block
   uint32_t lsel[2], tmp[2];
-  select_keys<NT>(hs, nA, false, (uint32_t*)nullptr, 0u, S, lsel);
+  select_keys<NT>(lists, nA, true, lbuf, (uint32_t)kSelLdsCap, S, lsel);
   if (!same) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -554,7 +546,7 @@ __device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws
       S.tg[1] = SelTarget<uint32_t>{0u, ~0u, rk1};
     }
     __syncthreads();
-    select_keys<NT>(hs + nA, nB, false, (uint32_t*)nullptr, 0u, S, tmp);
+    select_keys<NT>(lists + nA, nB, true, lbuf, (uint32_t)kSelLdsCap, S, tmp);
     lsel[1] = tmp[1];
   }
   if (threadIdx.x == 0)
@@ -569,9 +561,9 @@ __device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws
 // sample's order statistics at the middle ranks' sample positions widened
 // by four binomial standard deviations, stored as the bracket [a, b]
 // (whole high words) for the count kernel.
-__global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                                    char* __restrict__ ws, int rank_shift) {
-  __shared__ __align__(16) uint32_t hs[kSmallPairs];  // used by select_rest only
+__global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_kernel(
+    JobMap map, const pds_job* __restrict__ jobs, char* __restrict__ ws, int rank_shift) {
+  __shared__ uint32_t lbuf[kSelLdsCap];  // used by select_rest only
   __shared__ SelShared<uint32_t> S;
   __shared__ uint64_t cand[kDirectMax];
   __shared__ uint32_t cidx[kDirectMax];
@@ -742,15 +734,8 @@ __global__ void __launch_bounds__(kMedThreads) median_select_kernel(JobMap map, 
     }
     return;
   }
-  // More than kDirectMax keys in the middle bins: further levels over the
-  // high words, held in LDS from here on.
-#pragma unroll
-  for (int v = 0; v < V; ++v)
-    if (v * NT + threadIdx.x < n4)
-      reinterpret_cast<uint4*>(hs)[v * NT + threadIdx.x] =
-          make_uint4(hv[4 * v], hv[4 * v + 1], hv[4 * v + 2], hv[4 * v + 3]);
-  __syncthreads();
-  select_rest<NT>(J, ws, map.ws_off[e], hs, S, klo, n, small, a_open, b_open);
+  select_rest<NT>(J, ws, map.ws_off[e], lbuf, S, khi, klo, reinterpret_cast<uint32_t*>(base + L.cand), n, small,
+                  a_open, b_open);
 }
 
 // Keys of every pair inside [lo, hi] into cand (block-scan order); one
