@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "common.h"
+#include "sincos.h"
 #include "flop_count.h"
 
 namespace pds {
@@ -52,7 +53,7 @@ struct ArmConst {
 
 namespace {
 
-__host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincosf(x, sn, cs); }
+__host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincos_fast(x, sn, cs); }
 
 // The spatial algebra, forward dynamics and reverse step, generic over the
 // scalar type R: float on the device; a counting scalar on the host gives

@@ -19,10 +19,10 @@ namespace pds {
 namespace {
 
 // sum_{j < n} p[j * stride], added in order j = 0, 1, ...; the loads are
-// issued eight at a time (clamped in-bounds indices) so they overlap.
+// issued B at a time (clamped in-bounds indices) so they overlap.
+template <int B = 8>
 __device__ inline double sum_in_order(const double* p, size_t stride, int n) {
   double a = 0.0;
-  constexpr int B = 8;
   for (int j0 = 0; j0 < n; j0 += B) {
     double v[B];
 #pragma unroll
@@ -109,6 +109,29 @@ __device__ inline void sdot_finish(const pds_job& J, int i, int r, const SdotPar
   if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], 2);
 }
 
+// Trajectory combination for particle i from l_k in LDS (K <= kAsmCap):
+// weights to w (LDS) and wk, log p to logp.  Same operations as
+// combine_sums.
+__device__ inline void combine_lds(const pds_job& J, int i, const double* l, double* w) {
+  const int K = J.K;
+  double mx = -INFINITY, lp = 0.0;
+  for (int k = 0; k < K; ++k) {
+    mx = fmax(mx, l[k]);
+    lp += l[k];
+  }
+  if (J.combine == PDS_COMBINE_PROD) {
+    for (int k = 0; k < K; ++k) w[k] = 1.0;
+  } else {
+    double z = 0.0;
+    for (int k = 0; k < K; ++k) z += exp(l[k] - mx);
+    for (int k = 0; k < K; ++k) w[k] = exp(l[k] - mx) / z;
+    lp = mx + log(z) - log((double)K);
+  }
+  for (int k = 0; k < K; ++k) J.wk[(size_t)i * K + k] = w[k];
+  J.logp[i] = lp;
+  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+}
+
 // Trajectory combination for particle i from l_k already held in wk.
 __device__ inline void combine_sums(const pds_job& J, int i) {
   const int K = J.K;
@@ -142,7 +165,7 @@ constexpr int kAsmCap = 512;  // (parameter, trajectory) sums per channel held i
 
 __global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                     char* __restrict__ ws) {
-  __shared__ double sa[kAsmCap], sc[kAsmCap], sw[kAsmCap];
+  __shared__ double sa[kAsmCap], sc[kAsmCap], sw[kAsmCap], sl[kAsmCap];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int i = blockIdx.x - map.begin[e];
@@ -169,6 +192,8 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, 
   }
   const int kc = K < kAsmCap ? K : kAsmCap;  // trajectories per chunk
   const int mg = kAsmCap / kc;               // parameters per pass
+  // up to kAsmCap trajectories: l_k and the weights stay in LDS (one chunk)
+  const bool in_lds = K <= kAsmCap;
   bool first = true;
   for (int m0 = 0; m0 < M; m0 += mg) {
     const int m1 = min(M, m0 + mg);
@@ -179,25 +204,32 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, 
       const int lead = first ? K : 0;  // the first pass also sums the window log-likelihoods
       for (int r = t; r < lead + 2 * np; r += kAsmThreads) {
         if (r < lead) {
-          J.wk[(size_t)i * K + r] = sum_in_order(J.ll_win + pu + (size_t)r * ns, 1, ns);  // l_k for now
+          const double l = sum_in_order<16>(J.ll_win + pu + (size_t)r * ns, 1, ns);
+          if (in_lds) sl[r] = l;
+          else J.wk[(size_t)i * K + r] = l;  // l_k for now
         } else {
           // row p = (k - k0) (m1 - m0) + (m - m0): neighbouring threads read
           // neighbouring parameters of one unit
           const bool con = r - lead >= np;
           const int p = con ? r - lead - np : r - lead;
           const int m = m0 + p % (m1 - m0), k = k0 + p / (m1 - m0);
-          const double v = sum_in_order((con ? gc : go) + (pu + (size_t)k * ns) * M + m, M, ns);
+          const double v = sum_in_order<16>((con ? gc : go) + (pu + (size_t)k * ns) * M + m, M, ns);
           if (con) sc[p] = v; else sa[p] = v;
         }
       }
       __syncthreads();
       if (first) {
-        if (t == 0) combine_sums(J, i);
+        if (t == 0) {
+          if (in_lds) combine_lds(J, i, sl, sw);
+          else combine_sums(J, i);
+        }
         first = false;
         __syncthreads();
       }
-      for (int k = t; k < nk; k += kAsmThreads) sw[k] = J.wk[(size_t)i * K + k0 + k];
-      __syncthreads();
+      if (!in_lds) {
+        for (int k = t; k < nk; k += kAsmThreads) sw[k] = J.wk[(size_t)i * K + k0 + k];
+        __syncthreads();
+      }
       if (t < m1 - m0) {
         for (int k = 0; k < nk; ++k) {
           so += sw[k] * sa[k * (m1 - m0) + t];
@@ -215,7 +247,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, 
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int r = t + q * kAsmThreads;
-      if (r < nS) sdot_finish(J, i, r, sp[q], seed, J.wk[(size_t)i * K + sp[q].k]);
+      if (r < nS) sdot_finish(J, i, r, sp[q], seed, in_lds ? sw[sp[q].k] : J.wk[(size_t)i * K + sp[q].k]);
     }
   }
 }

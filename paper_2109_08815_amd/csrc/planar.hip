@@ -26,12 +26,13 @@
 #include <cmath>
 
 #include "common.h"
+#include "sincos.h"
 #include "flop_count.h"
 
 namespace pds {
 namespace {
 
-__host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincosf(x, sn, cs); }
+__host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincos_fast(x, sn, cs); }
 
 template <int NB, class R = float>
 struct Planar {
