@@ -312,7 +312,7 @@ struct ArmMath {
       const SV pA = crf(T.v[i], h) + pAc;
       const SV U = sv(v3(s3(IA.A, 0, k), s3(IA.A, 1, k), s3(IA.A, 2, k)),
                       v3(IA.B[3 * k], IA.B[3 * k + 1], IA.B[3 * k + 2]));
-      const R invD = 1.0f / comp(U.a, k);
+      const R invD = recip(comp(U.a, k));
       u[i] = arm_tau(K, i, time, q[i], qd[i]) - comp(pA.a, k);
       T.U[i] = U;
       T.invD[i] = invD;

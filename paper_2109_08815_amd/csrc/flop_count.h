@@ -31,6 +31,7 @@ inline Counted operator-(Counted a, float b) { return a - Counted(b); }
 inline Counted operator*(Counted a, float b) { return a * Counted(b); }
 inline Counted& operator+=(Counted& a, Counted b) { a = a + b; return a; }
 inline Counted& operator-=(Counted& a, Counted b) { a = a - b; return a; }
+inline Counted recip(Counted x) { return 1.0f / x; }
 inline void sincos_r(Counted x, Counted* sn, Counted* cs) {
   g_tally.transc += 2;
   float s, c;

@@ -80,7 +80,7 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
   }
 #pragma unroll
   for (int i = NB - 1; i >= 0; --i) {
-    const R invD = 1.0f / T.IA[i][0];
+    const R invD = recip(T.IA[i][0]);
     const R U1 = T.IA[i][1], U2 = T.IA[i][2];
     const R u = -P.b[i] * qd[i] - T.pA[i][0];
     T.invD[i] = invD;

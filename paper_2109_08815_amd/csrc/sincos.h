@@ -1,4 +1,4 @@
-// Single-precision sine and cosine for the dynamics kernels.
+// Single-precision sine, cosine and reciprocal for the dynamics kernels.
 //
 // x = k pi/2 + r with k = rint(2x/pi) and r reduced by a three-part
 // splitting of pi/2 (Cody and Waite), each part subtracted with one fused
@@ -46,6 +46,18 @@ __host__ __device__ inline void sincos_fast(float x, float* sn, float* cs) {
   if ((q + 1) & 2) c = -c;
   *sn = s;
   *cs = c;
+}
+
+// 1 / x: the hardware reciprocal estimate refined by one Newton step
+// r' = r + r (1 - x r) (two fused multiply-adds), within about half a unit
+// in the last place for normal x; host builds divide.
+__host__ __device__ inline float recip(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const float r = __builtin_amdgcn_rcpf(x);
+  return std::fma(std::fma(-x, r, 1.0f), r, r);
+#else
+  return 1.0f / x;
+#endif
 }
 
 }  // namespace pds
