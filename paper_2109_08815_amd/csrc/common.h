@@ -84,8 +84,14 @@ struct WsLayout {
 
 constexpr int kPhiChunk = 32;    // particles j per LDS chunk in phi
 constexpr int kPhiThreads = 1024;  // threads per block of the one-kernel phi
-constexpr int kPhiTI = 16;         // particles i per block of the one-kernel phi
-constexpr int kPhiFusedMaxN = 512;  // larger jobs use partial sums and a reduction
+// particles i per block of the one-kernel phi: kPhiTISmall up to
+// kPhiTIMaxN particles, kPhiTILarge above
+constexpr int kPhiTISmall = 16;
+constexpr int kPhiTILarge = 4;
+constexpr int kPhiTIMaxN = 512;
+inline int phi_ti(int N) { return N <= kPhiTIMaxN ? kPhiTISmall : kPhiTILarge; }
+constexpr int kPhiRows = 512;       // particle rows per LDS chunk of the one-kernel phi
+constexpr int kPhiFusedMaxN = 4096;  // larger jobs use partial sums and a reduction
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -142,7 +148,7 @@ hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, 
 hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
                               hipStream_t s);
 hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, hipStream_t s);
+hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, int ti, hipStream_t s);
 hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
                               hipStream_t s);
 hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);

@@ -319,12 +319,15 @@ int phi_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, cons
     const int lo_m = 1 + 4 * cls, hi_m = cls == 3 ? PDS_MAX_M : 4 + 4 * cls;
     auto in_cls = [&](const pds_job& J) { return J.M >= lo_m && J.M <= hi_m; };
     int grid = 0;
-    JobMap mf = make_map(
-        h_jobs, n_jobs, off, [&](const pds_job& J) { return in_cls(J) && J.N <= pds::kPhiFusedMaxN; },
-        [](const pds_job& J) { return div_up(J.N, pds::kPhiTI); }, &grid);
-    if (mf.n > 0) {
-      rc = launch_rc(pds::launch_phi(mf, d_jobs, grid, hi_m, s), "phi");
-      if (rc) return rc;
+    for (int ti : {pds::kPhiTISmall, pds::kPhiTILarge}) {
+      JobMap mf = make_map(
+          h_jobs, n_jobs, off,
+          [&](const pds_job& J) { return in_cls(J) && J.N <= pds::kPhiFusedMaxN && pds::phi_ti(J.N) == ti; },
+          [&](const pds_job& J) { return div_up(J.N, ti); }, &grid);
+      if (mf.n > 0) {
+        rc = launch_rc(pds::launch_phi(mf, d_jobs, grid, hi_m, ti, s), "phi");
+        if (rc) return rc;
+      }
     }
     JobMap mp = make_map(
         h_jobs, n_jobs, off, [&](const pds_job& J) { return in_cls(J) && J.N > pds::kPhiFusedMaxN; },

@@ -966,18 +966,21 @@ __global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_j
   J.phi[t] = s / (float)J.N;
 }
 
-// Jobs up to kPhiFusedMaxN particles: phi for kPhiTI particles i per block,
-// so even small jobs spread over many compute units.  The block stages
-// every particle's row and driving term in LDS (rows padded with zeros to
-// MM parameters, so the parameter loops run without branches); thread
-// (il, js) accumulates particle i0 + il over j = js, js + 64, ... in that
-// order; the four slices of a wave that share il are added by a fixed
-// shuffle tree, then the 16 waves' sums in wave order.  Every sum has a
-// fixed order that depends on N alone.
-template <int MM>
+// Jobs up to kPhiFusedMaxN particles: phi for TI particles i per block
+// (16 up to 512 particles, 4 above: enough blocks to fill the chip).  The block stages the
+// particles' rows and driving terms in LDS kPhiRows at a time (rows padded
+// with zeros to MM parameters, so the parameter loops run without
+// branches); thread (il, js) accumulates particle i0 + il over j = js,
+// js + 1024 / TI, ... in that order; the slices of a wave that share il
+// are added by a fixed shuffle tree, then the 16 waves' sums in wave
+// order.  Every sum has a fixed order that depends on N alone.
+template <int MM, int TI>
 __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_job* __restrict__ jobs) {
-  __shared__ float tj_s[kPhiFusedMaxN * MM];
-  __shared__ float gj_s[kPhiFusedMaxN * MM];
+  constexpr int kPhiTI = TI;
+  static_assert(kPhiRows % (kPhiThreads / kPhiTI) == 0, "chunks keep each slice's j order");
+  static_assert(kWave % kPhiTI == 0, "a wave holds whole groups of slices");
+  __shared__ float tj_s[kPhiRows * MM];
+  __shared__ float gj_s[kPhiRows * MM];
   __shared__ float red[kPhiThreads / kWave][kPhiTI * MM];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
@@ -986,15 +989,6 @@ __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_
   const int w = threadIdx.x / kWave;
   const int i = (blockIdx.x - map.begin[e]) * kPhiTI + il;
   constexpr int kSlices = kPhiThreads / kPhiTI;  // j stride
-  // every row into LDS, zero-padded to MM parameters
-  for (int t = threadIdx.x; t < N * MM; t += kPhiThreads) {
-    const int r = t / MM, m = t % MM;
-    const size_t src = (size_t)r * M + (m < M ? m : M - 1);
-    const float th = J.theta[src];
-    const double g = J.g_obs[src];
-    tj_s[t] = m < M ? th : 0.f;
-    gj_s[t] = m < M ? (float)g : 0.f;
-  }
   const float h = (float)J.bandwidth[0];
   const float inv_h = 1.0f / h;
   float ti[MM], rh[MM], ir[MM], ir2[MM], acc[MM];
@@ -1006,24 +1000,36 @@ __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_
     ir2[m] = ir[m] * ir[m];
     acc[m] = 0.f;
   }
-  __syncthreads();
-  for (int j = js; j < N; j += kSlices) {
-    float d2 = 0.f;
-#pragma unroll
-    for (int m = 0; m < MM; ++m) {
-      const float z = (ti[m] - tj_s[j * MM + m]) * ir[m];
-      d2 += z * z;
+  for (int j0 = 0; j0 < N; j0 += kPhiRows) {
+    const int nr = min(kPhiRows, N - j0);
+    if (j0 > 0) __syncthreads();  // the previous chunk is consumed
+    for (int t = threadIdx.x; t < nr * MM; t += kPhiThreads) {
+      const int r = t / MM, m = t % MM;
+      const size_t src = (size_t)(j0 + r) * M + (m < M ? m : M - 1);
+      const float th = J.theta[src];
+      const double g = J.g_obs[src];
+      tj_s[t] = m < M ? th : 0.f;
+      gj_s[t] = m < M ? (float)g : 0.f;
     }
-    const float k = expf(-d2 * inv_h);
-    const float k2h = 2.0f * k * inv_h;
+    __syncthreads();
+    for (int jl = js; jl < nr; jl += kSlices) {
+      float d2 = 0.f;
 #pragma unroll
-    for (int m = 0; m < MM; ++m) acc[m] += k * gj_s[j * MM + m] + k2h * (ti[m] - tj_s[j * MM + m]) * ir2[m];
+      for (int m = 0; m < MM; ++m) {
+        const float z = (ti[m] - tj_s[jl * MM + m]) * ir[m];
+        d2 += z * z;
+      }
+      const float k = expf(-d2 * inv_h);
+      const float k2h = 2.0f * k * inv_h;
+#pragma unroll
+      for (int m = 0; m < MM; ++m) acc[m] += k * gj_s[jl * MM + m] + k2h * (ti[m] - tj_s[jl * MM + m]) * ir2[m];
+    }
   }
-  // lanes il, il + 16, il + 32, il + 48 of a wave hold the same particle
+  // lanes il, il + TI, il + 2 TI, ... of a wave hold the same particle
 #pragma unroll
-  for (int m = 0; m < MM; ++m) {
-    acc[m] += __shfl_xor(acc[m], kPhiTI);
-    acc[m] += __shfl_xor(acc[m], 2 * kPhiTI);
+  for (int o = kPhiTI; o < kWave; o <<= 1) {
+#pragma unroll
+    for (int m = 0; m < MM; ++m) acc[m] += __shfl_xor(acc[m], o);
   }
   if ((threadIdx.x % kWave) < kPhiTI) {
 #pragma unroll
@@ -1053,8 +1059,15 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
   const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
   const int stride = J.M + nSp;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  const int it = J.iter_dev ? J.iter_dev[0] + 1 : iter;
-  const float bc1 = 1.0f - powf(b1, (float)it), bc2 = 1.0f - powf(b2, (float)it);
+  // Adam bias corrections, once per block (thread 0 reads the counter)
+  __shared__ float s_bc[2];
+  if (threadIdx.x == 0) {
+    const int it = J.iter_dev ? J.iter_dev[0] + 1 : iter;
+    s_bc[0] = 1.0f - powf(b1, (float)it);
+    s_bc[1] = 1.0f - powf(b2, (float)it);
+  }
+  __syncthreads();
+  const float bc1 = s_bc[0], bc2 = s_bc[1];
   if (t < nT) {
     const int i = t / J.M, m = t % J.M;
     const float x = J.theta[t];
@@ -1100,12 +1113,11 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
   const int nb = map.begin[e + 1] - map.begin[e];
   if (J.iter_dev && nb <= kStepCountBlocks) {
     // Advance the device counter once every block of the job is past its
-    // use of it: each thread's stores above depend on the value it read,
-    // so after the barrier every read of this block has returned.  Blocks
-    // count themselves in iter_dev[1] with device-scope atomics; the last
-    // one bumps the counter and leaves the count at zero for the next call.
-    // (Same-address atomics serialise: larger jobs use iter_bump_kernel.)
-    __syncthreads();
+    // use of it.  Only thread 0 reads it, and that read has returned (the
+    // bias corrections it wrote derive from it).  Blocks count themselves
+    // in iter_dev[1] with device-scope atomics; the last one bumps the
+    // counter and leaves the count at zero for the next call.  (Same-address
+    // atomics serialise: larger jobs use iter_bump_kernel.)
     if (threadIdx.x == 0) {
       if (atomicAdd(&J.iter_dev[1], 1) == nb - 1) {
         atomicExch(&J.iter_dev[1], 0);
@@ -1176,16 +1188,24 @@ hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws,
   return hipGetLastError();
 }
 
-hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, hipStream_t s) {
+template <int TI>
+static void launch_phi_ti(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, hipStream_t s) {
   const dim3 blk(kPhiThreads);
   if (mmax <= 4)
-    hipLaunchKernelGGL(phi_kernel<4>, dim3(grid), blk, 0, s, map, d_jobs);
+    hipLaunchKernelGGL((phi_kernel<4, TI>), dim3(grid), blk, 0, s, map, d_jobs);
   else if (mmax <= 8)
-    hipLaunchKernelGGL(phi_kernel<8>, dim3(grid), blk, 0, s, map, d_jobs);
+    hipLaunchKernelGGL((phi_kernel<8, TI>), dim3(grid), blk, 0, s, map, d_jobs);
   else if (mmax <= 12)
-    hipLaunchKernelGGL(phi_kernel<12>, dim3(grid), blk, 0, s, map, d_jobs);
+    hipLaunchKernelGGL((phi_kernel<12, TI>), dim3(grid), blk, 0, s, map, d_jobs);
   else
-    hipLaunchKernelGGL(phi_kernel<PDS_MAX_M>, dim3(grid), blk, 0, s, map, d_jobs);
+    hipLaunchKernelGGL((phi_kernel<PDS_MAX_M, TI>), dim3(grid), blk, 0, s, map, d_jobs);
+}
+
+hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, int ti, hipStream_t s) {
+  if (ti == kPhiTISmall)
+    launch_phi_ti<kPhiTISmall>(map, d_jobs, grid, mmax, s);
+  else
+    launch_phi_ti<kPhiTILarge>(map, d_jobs, grid, mmax, s);
   return hipGetLastError();
 }
 

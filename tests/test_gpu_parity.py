@@ -209,6 +209,30 @@ def test_bandwidth_exact_and_phi(orc, N):
     assert np.all(np.abs(ph - ph_ref) <= 1e-4 * scale + 1e-30)
 
 
+@pytest.mark.parametrize("N,M", [(4500, 4), (4200, 10)])
+def test_phi_partial_scheme_sampled_rows(orc, N, M):
+    """Jobs above 4096 particles take the partial-sum phi and its reduction;
+    sampled rows against the oracle's rows at the oracle's bandwidth."""
+    print_case("phi-partial", N, M)
+    pb = f32_problem(synth.make_problem("c2" if M == 4 else "c3", N=N, K=1, T=40, n_s=2))
+    rng = np.random.default_rng(N + M)
+    theta = r32(pb.lo + rng.uniform(size=(N, pb.M)) * (pb.hi - pb.lo))
+    G = rng.normal(scale=1e4, size=(N, pb.M))
+    job = L.Job(pb, np.zeros((pb.K, pb.T, pb.d_x)), theta=theta)
+    set_tensor(job.g_obs, G)
+    L.svgd_phi(L.Batch([job]))
+    h_ref, _ = orc.bandwidth(theta, pb.rho)
+    assert abs(np64(job.bandwidth)[0] - h_ref) <= 1e-15 * h_ref
+    sel = np.sort(rng.choice(N, size=48, replace=False)).astype(np.int32)
+    ph_ref = orc.phi(theta, r32(G), pb.rho, h_ref, sel=sel)
+    ph = np64(job.phi)[sel]
+    d = (theta[sel][:, None, :] - theta[None, :, :]) / pb.rho
+    k = np.exp(-(d ** 2).sum(-1) / h_ref)
+    gk = k[:, :, None] * 2.0 / h_ref * np.abs(d) / pb.rho
+    scale = (k[:, :, None] * np.abs(G)[None, :, :] + gk).mean(axis=1)
+    assert np.all(np.abs(ph - ph_ref) <= 1e-4 * scale + 1e-30)
+
+
 def _bandwidth_gpu(pb, theta):
     obs = np.zeros((pb.K, pb.T, pb.d_x))
     job = L.Job(pb, obs, theta=theta)
