@@ -126,6 +126,22 @@ def cpu_baseline(pb, obs, theta, S, target_s):
         "sample": "%d of %d particles, all %d trajectories x %d steps: forward-mode-dual gradient, bandwidth "
                   "and phi rows, %d iteration(s), %.1f s" % (sel_n, n_all, pb.K, pb.T, reps, el),
     }
+    # fairer floor: the oracle's forward-only rollout (likelihood and
+    # defects, no derivatives) on the same cores, a quarter of the budget
+    probe_f = max(1, min(n_all, 16))
+    selp = np.arange(probe_f, dtype=np.int32)
+    t0 = time.perf_counter()
+    orc.forward(pb, obs, st, sel=selp)
+    per_f = (time.perf_counter() - t0) / probe_f
+    nf = int(max(1, min(n_all, 0.25 * target_s / max(per_f, 1e-9))))
+    repf = max(1, int(0.25 * target_s / max(per_f * n_all, 1e-9))) if nf == n_all else 1
+    t0 = time.perf_counter()
+    for _ in range(repf):
+        orc.forward(pb, obs, st, sel=np.arange(nf, dtype=np.int32))
+    elf = time.perf_counter() - t0
+    out["forward_only_value"] = repf * nf * pb.K * pb.T / elf
+    out["forward_only_sample"] = "%d of %d particles, forward rollout and likelihood only, %d pass(es), %.1f s" % (
+        nf, n_all, repf, elf)
     # one core, on a quarter of the time budget
     lib.orc_set_threads(1)
     try:
