@@ -87,6 +87,21 @@ extern "C" {
 #define PDS_COMBINE_SUM 0   /* equally weighted mixture over trajectories, eq. traj_likelihood */
 #define PDS_COMBINE_PROD 1  /* product over trajectories, App. A-B eq. traj_likelihood_prod */
 
+/* How the shooting defects enter (eq. likelihood-defect, eq. ms_likelihood).
+ * MDMM: as equality constraints of Sec. III-E (CSVGD): the window
+ *   log-likelihoods hold the observation terms only, the constraint
+ *   channel carries (lam_def + c g_def) d g_def, and svgd_step ascends
+ *   lam_def.
+ * DEFECT: as Gaussian factors inside p_ms (eq. ms_likelihood, the form the
+ *   paper gives its sampling baselines): window j < n_s-1 adds
+ *   log N(S_{j+1} | s_end, sigma_def^2 / u^2) = -g_def / 2 + sum_d
+ *   log(u_d / (sigma_def sqrt(2 pi))) to its log-likelihood, the defect
+ *   gradients ride in the observation channel with the trajectory
+ *   weights, the constraint channel's default defect seed is 0 (explicit
+ *   seed_gdef still applies) and svgd_step leaves lam_def unchanged. */
+#define PDS_LIK_MDMM 0
+#define PDS_LIK_DEFECT 1
+
 #define PDS_OPT_SGD 0
 #define PDS_OPT_ADAM 1
 
@@ -110,6 +125,7 @@ typedef struct pds_job {
   int32_t n_s;        /* shooting windows, >= 1 */
   int32_t h;          /* steps per window, >= 1 */
   int32_t combine;    /* PDS_COMBINE_* */
+  int32_t lik;        /* PDS_LIK_* */
   float dt;           /* > 0 */
   float sigma_def;    /* > 0, defect scale of eq. likelihood-defect */
   float c;            /* >= 0, MDMM damping constant of eq. mdmm-loss */
@@ -137,7 +153,8 @@ typedef struct pds_job {
   /* ---- outputs ---- */
   float* end_states;  /* [N, K, n_s, d_s] last state of each window */
   float* traj;        /* [N, K, T, d_s] visited states, or NULL (sim_batch_forward only) */
-  double* ll_win;     /* [N, K, n_s] window log-likelihoods (with Gaussian constants) */
+  double* ll_win;     /* [N, K, n_s] window log-likelihoods (with Gaussian constants; with
+                         PDS_LIK_DEFECT window j < n_s-1 includes its defect's log density) */
   double* gdef;       /* [N, K, n_s-1] defects ||(S_{j+1} - s_end) u||^2 / sigma_def^2 */
   double* logp;       /* [N] log p_obs per particle */
   double* wk;         /* [N, K] d log p / d l_k (mixture responsibilities, or 1) */

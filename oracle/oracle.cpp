@@ -71,6 +71,7 @@ typedef struct {
 
 typedef struct {
   int32_t N, K, T, n_s, h, combine;  // combine: 0 sum (GMM), 1 product
+  int32_t lik;  // 0: defects as MDMM constraints; 1: defect densities inside p_ms
   double dt, sigma_def, c;
   const double* w_x;      // [d_x]   observation weights (1 / sigma_obs)
   const double* u;        // [d_s]   defect state scales
@@ -351,6 +352,15 @@ double defect(const OrcProblem& pr, int ds, const double* S_next, const double* 
   return g / (pr.sigma_def * pr.sigma_def);
 }
 
+// Log density of defect g (eq. "likelihood-defect"): the shooting state
+// S ~ N(s_end, sigma_def^2 / u_d^2) per state dimension, i.e.
+// -g / 2 + sum_d log(u_d / (sigma_def sqrt(2 pi))).
+double defect_log_density(const OrcProblem& pr, int ds, double g) {
+  double lp = -0.5 * g;
+  for (int d = 0; d < ds; ++d) lp += std::log(pr.u[d] / (pr.sigma_def * std::sqrt(2.0 * kPi)));
+  return lp;
+}
+
 // Combination over trajectories: eq. "traj_likelihood" (equally weighted
 // mixture, evaluated in log space with the 1/K weight) or App. A-B
 // eq. "traj_likelihood_prod".  Returns log p and writes the weights
@@ -463,12 +473,16 @@ void orc_forward(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
     const int i = sel[s];
     std::vector<double> lk(K);
     for (int k = 0; k < K; ++k) {
+      for (int j = 0; j + 1 < ns; ++j) {
+        const size_t u = ((size_t)s * K + k) * ns + j;
+        const double g = defect(*pr, ds, start_state(*pr, ds, i, k, j + 1), end_states + u * ds);
+        gdef[((size_t)s * K + k) * (ns - 1) + j] = g;
+        // eq. "ms_likelihood": the defect density is a factor of p_ms
+        if (pr->lik == 1) ll_win[u] += defect_log_density(*pr, ds, g);
+      }
       double acc = 0.0;
       for (int j = 0; j < ns; ++j) acc += ll_win[((size_t)s * K + k) * ns + j];
       lk[k] = acc;
-      for (int j = 0; j + 1 < ns; ++j)
-        gdef[((size_t)s * K + k) * (ns - 1) + j] =
-            defect(*pr, ds, start_state(*pr, ds, i, k, j + 1), end_states + (((size_t)s * K + k) * ns + j) * ds);
     }
     logp[s] = combine(*pr, lk.data(), wk + (size_t)s * K);
   }
@@ -479,6 +493,9 @@ void orc_forward(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
 //   g_obs[i]  = d log p_obs / d theta                (enters phi)
 //   g_con[i]  = sum_{k,j} (lam_def + c g_def) d g_def / d theta
 //   S_dot     = w_ik d l_ikj / d S_j - d Phi / d S_j  (Phi = lam g + c/2 g^2)
+// With lik = 1 the defect densities are factors of p_ms (eq. "ms_likelihood"):
+// l_ikj gains log p_def of window j's defect, g_obs and S_dot carry its
+// derivatives with the trajectory weights, and g_con is zero.
 // Also returns the forward quantities of orc_forward.  Returns 0, or -1 if
 // M + d_s exceeds the compiled dual width.
 int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int* sel, double* end_states,
@@ -507,12 +524,42 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
     else if (P <= 20) window_grad<20>(*md, *pr, th, st, k, j, &ll_win[u], a0, a1, a2, a3, a4);
     else window_grad<32>(*md, *pr, th, st, k, j, &ll_win[u], a0, a1, a2, a3, a4);
   }
-  if (dl_dth_unit) std::memcpy(dl_dth_unit, dl_dth.data(), sizeof(double) * units * M);
   if (dcon_dth_unit)
     for (size_t t = 0; t < (size_t)units * M; ++t) dcon_dth_unit[t] = 0.0;
   const double inv_s2 = 1.0 / (pr->sigma_def * pr->sigma_def);
+  const bool in_lik = pr->lik == 1;
   for (int s = 0; s < n_sel; ++s) {
     const int i = sel[s];
+    // defects first: with the densities inside p_ms (eq. "ms_likelihood")
+    // their log densities join the window terms, and d log p_def / d s_end
+    // = -(1/2) d g / d s_end joins the window's theta gradient through
+    // d s_end / d theta
+    for (int k = 0; k < K; ++k)
+      for (int j = 0; j + 1 < ns; ++j) {
+        const size_t u = ((size_t)s * K + k) * ns + j;
+        const double* Snext = start_state(*pr, ds, i, k, j + 1);
+        const double* se = end_states + u * ds;
+        const double g = defect(*pr, ds, Snext, se);
+        gdef[((size_t)s * K + k) * (ns - 1) + j] = g;
+        if (!in_lik) continue;
+        ll_win[u] += defect_log_density(*pr, ds, g);
+        for (int m = 0; m < M; ++m) {
+          double acc = 0.0;
+          for (int d = 0; d < ds; ++d) {
+            const double e = (Snext[d] - se[d]) * pr->u[d];
+            acc += (e * pr->u[d] * inv_s2) * dse_dth[(u * ds + d) * M + m];  // -(1/2) d g / d s_end = e u / sigma^2
+          }
+          dl_dth[u * M + m] += acc;
+        }
+        for (int c = 0; c < ds; ++c) {
+          double acc = 0.0;
+          for (int d = 0; d < ds; ++d) {
+            const double e = (Snext[d] - se[d]) * pr->u[d];
+            acc += (e * pr->u[d] * inv_s2) * dse_ds[(u * ds + d) * ds + c];
+          }
+          dl_ds[u * ds + c] += acc;
+        }
+      }
     std::vector<double> lk(K);
     for (int k = 0; k < K; ++k) {
       double acc = 0.0;
@@ -536,8 +583,17 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
         const size_t u = ((size_t)s * K + k) * ns + j;
         const double* Snext = start_state(*pr, ds, i, k, j + 1);
         const double* se = end_states + u * ds;
-        const double g = defect(*pr, ds, Snext, se);
-        gdef[((size_t)s * K + k) * (ns - 1) + j] = g;
+        double* sn = S_dot + (((size_t)s * K + k) * (ns - 1) + j) * ds;
+        if (in_lik) {
+          // direct dependence of the defect density on its target S_{j+1}:
+          // d log p_def / d S_next = -e u / sigma^2, weighted like the window
+          for (int d = 0; d < ds; ++d) {
+            const double e = (Snext[d] - se[d]) * pr->u[d];
+            sn[d] += w[k] * (-e * pr->u[d] * inv_s2);
+          }
+          continue;
+        }
+        const double g = gdef[((size_t)s * K + k) * (ns - 1) + j];
         const double lam = pr->lam_def[((size_t)i * K + k) * (ns - 1) + j];
         const double mult = lam + pr->c * g;  // d Phi / d g
         // d g / d s_end = -2 e u / sigma^2 with e = (S_next - s_end) u
@@ -562,11 +618,11 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
           }
         }
         // direct dependence of defect j on its target S_{j+1}: d g / d S_next = +2 e u / sigma^2
-        double* sn = S_dot + (((size_t)s * K + k) * (ns - 1) + j) * ds;
         for (int d = 0; d < ds; ++d) sn[d] -= mult * (-dg_dse[d]);
       }
     }
   }
+  if (dl_dth_unit) std::memcpy(dl_dth_unit, dl_dth.data(), sizeof(double) * units * M);
   return 0;
 }
 

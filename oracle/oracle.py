@@ -41,7 +41,8 @@ class OrcModel(C.Structure):
 class OrcProblem(C.Structure):
     _fields_ = [
         ("N", C.c_int32), ("K", C.c_int32), ("T", C.c_int32), ("n_s", C.c_int32), ("h", C.c_int32),
-        ("combine", C.c_int32), ("dt", C.c_double), ("sigma_def", C.c_double), ("c", C.c_double),
+        ("combine", C.c_int32), ("lik", C.c_int32), ("dt", C.c_double), ("sigma_def", C.c_double),
+        ("c", C.c_double),
         ("w_x", _D), ("u", _D), ("s0", _D), ("obs", _D), ("theta", _D), ("S", _D), ("lam_def", _D),
     ]
 
@@ -134,6 +135,7 @@ def _problem(pb, obs, st: State, keep):
     keep.extend([_f64(pb.w_x), _f64(pb.u), _f64(pb.s0), _f64(obs), st.theta, st.S, st.lam_def])
     p = OrcProblem()
     p.N, p.K, p.T, p.n_s, p.h, p.combine = st.theta.shape[0], pb.K, pb.T, pb.n_s, pb.h, pb.combine
+    p.lik = int(getattr(pb, "lik", 0))
     p.dt, p.sigma_def, p.c = pb.dt, pb.sigma_def, pb.c
     p.w_x, p.u, p.s0, p.obs, p.theta, p.S, p.lam_def = [_p(a) for a in keep[-7:]]
     return p
@@ -270,7 +272,8 @@ def mdmm_step(pb, st: State, phi_, g_con, S_dot, gdef, optimizer, it, lr_theta=N
     lrs = _f64(pb.lr_S if lr_S is None else lr_S)
     el = pb.eps_lam if eps_lam is None else eps_lam
     Sd = _f64(S_dot).reshape(N, pb.K, pb.n_s - 1, pb.d_s) if pb.n_s > 1 else np.zeros((N, pb.K, 1, pb.d_s))
-    gd = _f64(gdef) if pb.n_s > 1 else np.zeros((N, pb.K, 1))
+    # defects inside p_ms (lik = 1) are no constraints: lam_def stays put
+    gd = _f64(gdef) if pb.n_s > 1 and getattr(pb, "lik", 0) == 0 else np.zeros((N, pb.K, max(pb.n_s - 1, 1)))
     lib().orc_mdmm_step(N, pb.M, pb.K, pb.n_s, pb.d_s, float(pb.c), _p(_f64(pb.lo)), _p(_f64(pb.hi)),
                         _p(_f64(phi_)), _p(_f64(g_con)), _p(np.ascontiguousarray(Sd)), _p(np.ascontiguousarray(gd)),
                         _p(lrt), _p(lrs), float(el), int(optimizer), int(it), _p(st.theta), _p(st.S), _p(st.lam_lim),

@@ -626,7 +626,6 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   }
   if (with_ll) {
     ll += (double)J.h * (log((double)wx) - 0.91893853320467274178);
-    J.ll_win[iu] = ll;
     if (w.j + 1 < J.n_s) {
       const float* sn = J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j) * kArmDs;
       double g = 0.0;
@@ -635,8 +634,11 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
         const float e1 = (sn[8 + d] - qd[d]) * J.u[8 + d];
         g += (double)e0 * e0 + (double)e1 * e1;
       }
-      J.gdef[((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j] = g / ((double)J.sigma_def * J.sigma_def);
+      g /= (double)J.sigma_def * J.sigma_def;
+      J.gdef[((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j] = g;
+      if (J.lik == PDS_LIK_DEFECT) ll += -0.5 * g + defect_log_norm(J);
     }
+    J.ll_win[iu] = ll;
     bad |= !isfinite(ll);
   }
   if (bad && J.flags) atomicOr(&J.flags[w.i], 1);
@@ -688,13 +690,12 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   ll += (double)h * (log((double)wx) - 0.91893853320467274178);
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
   float* es = J.end_states + iu * kArmDs;
-  bool bad = !isfinite(ll);
+  bool bad = false;
   for (int d = 0; d < 8; ++d) {
     es[d] = q[d];
     es[8 + d] = qd[d];
     bad |= !isfinite(q[d]) || !isfinite(qd[d]);
   }
-  J.ll_win[iu] = ll;
 
   float qb_o[8], qdb_o[8], qb_c[8], qdb_c[8];
   for (int d = 0; d < 8; ++d) { qb_o[d] = qdb_o[d] = qb_c[d] = qdb_c[d] = 0.f; }
@@ -711,13 +712,22 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
     const double inv_s2 = 1.0 / ((double)J.sigma_def * J.sigma_def);
     g *= inv_s2;
     J.gdef[id] = g;
-    const double seed = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
+    const bool in_lik = J.lik == PDS_LIK_DEFECT;
+    if (in_lik) ll += -0.5 * g + defect_log_norm(J);
+    const double seed =
+        J.seed_gdef ? J.seed_gdef[id] : (in_lik ? 0.0 : (double)J.lam_def[id] + (double)J.c * g);
+    // d g / d s_end = -2 e u / sigma^2; in the likelihood, d(-g/2) / d s_end = e u / sigma^2
     const float sc = (float)(-2.0 * seed * inv_s2);
+    const float so = in_lik ? (float)inv_s2 : 0.f;
     for (int d = 0; d < 8; ++d) {
+      qb_o[d] = so * e0[d] * J.u[d];
+      qdb_o[d] = so * e1[d] * J.u[8 + d];
       qb_c[d] = sc * e0[d] * J.u[d];
       qdb_c[d] = sc * e1[d] * J.u[8 + d];
     }
   }
+  bad |= !isfinite(ll);
+  J.ll_win[iu] = ll;
   double gm_o[4] = {0.0, 0.0, 0.0, 0.0}, gm_c[4] = {0.0, 0.0, 0.0, 0.0};
   for (int s = h - 1; s >= 0; --s) {
     {

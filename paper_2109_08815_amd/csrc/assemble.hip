@@ -72,7 +72,8 @@ __global__ void __launch_bounds__(64) assemble_logp_kernel(JobMap map, const pds
 
 // S_dot of shooting-state component r = ((k (n_s-1) + j-1) d_s + d) of
 // particle i (window j >= 1 starts from it), split into the parts known
-// before the trajectory weights: S_dot = seed w_k a - b - c.
+// before the trajectory weights: S_dot = seed w_k a - b - c (with
+// PDS_LIK_DEFECT, a includes the defect's direct term).
 struct SdotPart {
   double a, b, c;
   int k;
@@ -92,12 +93,16 @@ __device__ inline SdotPart sdot_part(const pds_job& J, int i, int r, const float
   // defect of window j-1, whose target is this shooting state
   const size_t id = ((size_t)i * J.K + k) * (J.n_s - 1) + (j - 1);
   const double g = J.gdef[id];
-  const double sg = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
+  const bool in_lik = J.lik == PDS_LIK_DEFECT;
+  const double sg = J.seed_gdef ? J.seed_gdef[id] : (in_lik ? 0.0 : (double)J.lam_def[id] + (double)J.c * g);
   const float s_next = J.S[id * ds + d];
   const float s_end = J.end_states[(iu - 1) * ds + d];
   const double ud = J.u[d];
   const double err = (double)(s_next - s_end) * ud;
   p.c = sg * 2.0 * err * ud / ((double)J.sigma_def * J.sigma_def);
+  // in the likelihood the defect's log density depends on its target
+  // directly: d(-g/2) / d S = -e u / sigma^2, weighted like the window terms
+  if (in_lik) p.a -= err * ud / ((double)J.sigma_def * J.sigma_def);
   return p;
 }
 

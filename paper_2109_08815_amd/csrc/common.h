@@ -43,6 +43,16 @@ __device__ inline void store_row(float* p, const float* v) {
   for (int c = 0; c < N / 2; ++c) reinterpret_cast<float2*>(p)[c] = make_float2(v[2 * c], v[2 * c + 1]);
 }
 
+// Normalising constant of the defect density of eq. likelihood-defect,
+// N(S | s_end, sigma_def^2 / u^2): sum_d log(u_d / (sigma_def sqrt(2 pi))),
+// so log p_def = -g_def / 2 + defect_log_norm (PDS_LIK_DEFECT).
+__device__ inline double defect_log_norm(const pds_job& J) {
+  const int ds = 2 * J.n_dof;
+  double c = 0.0;
+  for (int d = 0; d < ds; ++d) c += log((double)J.u[d]) - log((double)J.sigma_def) - 0.91893853320467274178;
+  return c;
+}
+
 constexpr size_t kArmConstBytes = 2048;  // derived arm model constants per job
 
 // Bandwidth median (see svgd.hip).  Up to kSmallPairs pairs one block

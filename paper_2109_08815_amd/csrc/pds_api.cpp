@@ -95,6 +95,8 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
   if (!(J.c >= 0.f)) return fail(PDS_EINVAL, "job %d: c must be >= 0", idx);
   if (J.combine != PDS_COMBINE_SUM && J.combine != PDS_COMBINE_PROD)
     return fail(PDS_EINVAL, "job %d: unknown combine %d", idx, J.combine);
+  if (J.lik != PDS_LIK_MDMM && J.lik != PDS_LIK_DEFECT)
+    return fail(PDS_EINVAL, "job %d: unknown likelihood mode %d", idx, J.lik);
   if (need & (NEED_FWD | NEED_LL | NEED_ADJ)) {
     REQ(consts, 4); REQ(theta, 4); REQ(s0, 4); REQ(end_states, 4);
     if (J.n_s > 1) REQ(S, 4);

@@ -426,7 +426,6 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
   for (int d = 0; d < NB; ++d) bad |= !isfinite(q[d]) || !isfinite(qd[d]);
   if (with_ll) {
     ll += (double)J.h * log_norm_const(J);
-    J.ll_win[iu] = ll;
     if (w.j + 1 < J.n_s) {
       const float* sn = J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j) * DS;
       double g = 0.0;
@@ -436,8 +435,11 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
         const float e1 = (sn[NB + d] - qd[d]) * J.u[NB + d];
         g += (double)e0 * e0 + (double)e1 * e1;
       }
-      J.gdef[((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j] = g / ((double)J.sigma_def * J.sigma_def);
+      g /= (double)J.sigma_def * J.sigma_def;
+      J.gdef[((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j] = g;
+      if (J.lik == PDS_LIK_DEFECT) ll += -0.5 * g + defect_log_norm(J);
     }
+    J.ll_win[iu] = ll;
     bad |= !isfinite(ll);
   }
   if (bad && J.flags) atomicOr(&J.flags[w.i], 1);
@@ -525,14 +527,13 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   }
   ll += (double)h * log_norm_const(J);
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
-  bool bad = !isfinite(ll);
+  bool bad = false;
 #pragma unroll
   for (int d = 0; d < NB; ++d) bad |= !isfinite(q[d]) || !isfinite(qd[d]);
   if (ch == 0) {
     float* es = J.end_states + iu * DS;
 #pragma unroll
     for (int d = 0; d < NB; ++d) { es[d] = q[d]; es[NB + d] = qd[d]; }
-    J.ll_win[iu] = ll;
   }
 
   // ---- seeds ----
@@ -557,24 +558,33 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     const double inv_s2 = 1.0 / ((double)J.sigma_def * J.sigma_def);
     g *= inv_s2;
     if (ch == 0) J.gdef[id] = g;
-    const double seed = J.seed_gdef ? J.seed_gdef[id] : (double)J.lam_def[id] + (double)J.c * g;
-    // d g / d s_end = -2 e u / sigma^2
+    const bool in_lik = J.lik == PDS_LIK_DEFECT;
+    if (in_lik) ll += -0.5 * g + defect_log_norm(J);
+    const double seed =
+        J.seed_gdef ? J.seed_gdef[id] : (in_lik ? 0.0 : (double)J.lam_def[id] + (double)J.c * g);
+    // d g / d s_end = -2 e u / sigma^2; in the likelihood, d(-g/2) / d s_end = e u / sigma^2
     const float sc = (float)(-2.0 * seed * inv_s2);
+    const float so = in_lik ? (float)inv_s2 : 0.f;
     if (SPLIT) {
       const float con_on = 1.f - obs_on;
+      const float sa = obs_on * so + con_on * sc;
 #pragma unroll
       for (int d = 0; d < NB; ++d) {
-        qb_a[d] = con_on * sc * e0[d] * J.u[d];
-        qdb_a[d] = con_on * sc * e1[d] * J.u[NB + d];
+        qb_a[d] = sa * e0[d] * J.u[d];
+        qdb_a[d] = sa * e1[d] * J.u[NB + d];
       }
     } else {
 #pragma unroll
       for (int d = 0; d < NB; ++d) {
+        qb_a[d] = so * e0[d] * J.u[d];
+        qdb_a[d] = so * e1[d] * J.u[NB + d];
         qb_c[d] = sc * e0[d] * J.u[d];
         qdb_c[d] = sc * e1[d] * J.u[NB + d];
       }
     }
   }
+  bad |= !isfinite(ll);
+  if (ch == 0) J.ll_win[iu] = ll;
 
   // ---- reverse sweep over segments ----
   double gm_a[2 * NB], gm_c[2 * NB];

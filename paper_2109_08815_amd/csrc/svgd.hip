@@ -1106,7 +1106,7 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
       J.adam_v[a] = vv;
       J.S[r] -= J.lr_S[d] * (mm / bc1) / (sqrtf(vv / bc2) + eps);
     }
-  } else if (t < nT + nS + nL) {
+  } else if (t < nT + nS + nL && J.lik != PDS_LIK_DEFECT) {
     const int r = t - nT - nS;
     J.lam_def[r] += J.eps_lam * (float)J.gdef[r];
   }

@@ -40,6 +40,8 @@ KIND_TOY = 3
 
 COMBINE_SUM = 0
 COMBINE_PROD = 1
+LIK_MDMM = 0    # defects as MDMM equality constraints (CSVGD)
+LIK_DEFECT = 1  # defects as Gaussian factors inside the multiple-shooting likelihood
 
 
 @dataclass
@@ -78,6 +80,7 @@ class Problem:
     lr_S: np.ndarray              # [d_s]
     eps_lam: float
     seed: int
+    lik: int = 0                  # LIK_MDMM or LIK_DEFECT (how the defects enter)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -135,7 +138,7 @@ def _arm_constants(rng: np.random.Generator) -> dict:
 
 def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem:
     """Build a seeded problem.  ``over`` overrides N, K, T, n_s, dt, sigma_obs,
-    sigma_def, c, combine, n_dof (planar families), M (toy)."""
+    sigma_def, c, combine, lik, n_dof (planar families), M (toy)."""
     base = dict(CONFIGS.get(config, {}))
     if config == "toy":
         base = dict(family="toy", N=256, K=1, T=50, n_s=1, dt=0.1, sigma_obs=0.5)
@@ -209,6 +212,7 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         combine=int(over.get("combine", COMBINE_SUM)), lo=lo, hi=hi, theta_true=theta_true,
         s0=s0, noise=noise, particles=particles, w_x=np.full(d_x, 1.0 / sigma_obs), u=u,
         rho=hi - lo, lr_theta=1e-2 * (hi - lo), lr_S=lr_S, eps_lam=1e-2, seed=seed,
+        lik=int(over.get("lik", LIK_MDMM)),
     )
 
 

@@ -108,6 +108,11 @@ CASES = [
     ("c3", dict(N=64, K=1, T=300, n_s=4)),
     ("c1", dict(N=64, K=1, T=800, n_s=2)),
     ("c1", dict(N=2048, K=8, T=40, n_s=4)),
+    # product over trajectories (App. A-B) and defect densities inside p_ms
+    # (eq. ms_likelihood), alone and together
+    ("c2", dict(N=40, K=3, T=80, n_s=4, combine=synth.COMBINE_PROD)),
+    ("c2", dict(N=70, K=3, T=80, n_s=4, lik=synth.LIK_DEFECT)),
+    ("c3", dict(N=64, K=2, T=150, n_s=3, lik=synth.LIK_DEFECT, combine=synth.COMBINE_PROD)),
 ]
 
 
@@ -283,10 +288,11 @@ def test_bandwidth_exact_with_heavy_ties(orc, groups):
     assert abs(_bandwidth_gpu(pb, theta) - h_ref) <= 1e-15 * h_ref
 
 
-@pytest.mark.parametrize("optimizer", [L.PDS_OPT_SGD, L.PDS_OPT_ADAM])
-def test_step_parity(orc, optimizer):
-    print_case("step", optimizer)
-    pb = f32_problem(synth.make_problem("c2", N=70, K=2, T=80, n_s=4))
+@pytest.mark.parametrize("optimizer,lik", [(L.PDS_OPT_SGD, synth.LIK_MDMM), (L.PDS_OPT_ADAM, synth.LIK_MDMM),
+                                           (L.PDS_OPT_ADAM, synth.LIK_DEFECT)])
+def test_step_parity(orc, optimizer, lik):
+    print_case("step", optimizer, lik)
+    pb = f32_problem(synth.make_problem("c2", N=70, K=2, T=80, n_s=4, lik=lik))
     rng = np.random.default_rng(5)
     N, K, ns, ds, M = pb.N, pb.K, pb.n_s, pb.d_s, pb.M
     theta = r32(pb.lo - 0.2 + rng.uniform(size=(N, M)) * (pb.hi - pb.lo + 0.4))  # some outside the limits
@@ -316,9 +322,11 @@ def test_step_parity(orc, optimizer):
     assert np.all(((fl & 4) != 0) == outside)
 
 
-def test_csvgd_iteration_sgd(orc):
-    """One full iteration (adjoint -> phi -> step) from identical inputs."""
-    pb, obs, st, job, b = make_case(orc, "c2", perturb_S=0.01, lam=True, N=70, K=3)
+@pytest.mark.parametrize("lik", [synth.LIK_MDMM, synth.LIK_DEFECT])
+def test_csvgd_iteration_sgd(orc, lik):
+    """One full iteration (adjoint -> phi -> step) from identical inputs,
+    with the defects as constraints (CSVGD) or inside p_ms."""
+    pb, obs, st, job, b = make_case(orc, "c2", perturb_S=0.01, lam=True, N=70, K=3, lik=lik)
     th0 = st.theta.copy()
     S0 = st.S.copy()
     L.csvgd_iteration(b, 1, L.PDS_OPT_SGD)
@@ -492,6 +500,8 @@ def test_autograd_function_matches_oracle(orc):
 ARM_CASES = [
     dict(N=70, K=1, T=100, n_s=2),      # two windows of 50 steps at dt = 1/240
     dict(N=33, K=2, T=60, n_s=3),       # two trajectories, short windows (whole window in LDS)
+    dict(N=24, K=2, T=60, n_s=3, lik=synth.LIK_DEFECT),
+    dict(N=20, K=2, T=60, n_s=2, combine=synth.COMBINE_PROD),
 ]
 
 
@@ -519,7 +529,9 @@ def test_arm_adjoint_gradients(orc, over):
 
 
 @pytest.mark.parametrize("cfg,over", [("c2", dict(N=16, K=2, T=40, n_s=2)), ("c3", dict(N=16, K=1, T=60, n_s=3)),
-                                      ("c4", dict(N=8, T=60, n_s=2))])
+                                      ("c4", dict(N=8, T=60, n_s=2)),
+                                      ("c2", dict(N=16, K=2, T=40, n_s=3, lik=synth.LIK_DEFECT)),
+                                      ("c4", dict(N=8, K=2, T=60, n_s=2, lik=synth.LIK_DEFECT))])
 def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
     """The reverse-mode gradients against central differences of the GPU's
     own forward (FP32 states, FP64 sums), along a random direction in theta
@@ -541,6 +553,8 @@ def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
         L.loglik_multishoot(b)
         gd = np64(job.gdef)
         phi_c = (lam * gd + 0.5 * pb.c * gd * gd).reshape(gd.shape[0], -1).sum(axis=1)
+        if pb.lik == synth.LIK_DEFECT:  # no constraints: the defects are inside log p
+            phi_c = np.zeros_like(phi_c)
         return np64(job.logp), phi_c
 
     best_o = np.full(pb.N, np.inf)

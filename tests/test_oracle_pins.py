@@ -308,6 +308,64 @@ def test_dual_gradients_match_finite_differences(orc, cfg):
         assert np.linalg.norm(g["S_dot"][i] - sd) <= 1e-6 * np.linalg.norm(sd)
 
 
+@pytest.mark.parametrize("cfg", ["c2", "c4"])
+def test_defect_density_in_likelihood_gradients_match_finite_differences(orc, cfg):
+    """Defects inside p_ms (eq. ms_likelihood): g_obs = d log p_ms / d theta
+    and S_dot = d log p_ms / d S by central differences through the whole
+    forward pipeline, with no constraint part (g_con = 0)."""
+    rng = np.random.default_rng(23)
+    pb, obs, st = _setup(orc, cfg, N=2, K=2, T=30, n_s=3, lik=synth.LIK_DEFECT)
+    st.S = synth.perturb(rng, st.S, 0.02)
+    st.lam_def = rng.uniform(0.0, 2.0, st.lam_def.shape)  # must not matter
+    st.theta = pb.lo + rng.uniform(0.2, 0.8, st.theta.shape) * (pb.hi - pb.lo)
+    g = orc.gradient(pb, obs, st)
+    assert np.all(g["g_con"] == 0.0)
+
+    def F(theta=None, S=None):
+        s2 = orc.State(pb, st.theta if theta is None else theta, st.S if S is None else S, lam_def=st.lam_def)
+        return orc.forward(pb, obs, s2)["logp"]
+
+    for i in range(2):
+        go = np.zeros(pb.M)
+        for m in range(pb.M):
+            e = 1e-6 * max(1.0, abs(st.theta[i, m]))
+            tp, tm = st.theta.copy(), st.theta.copy()
+            tp[i, m] += e
+            tm[i, m] -= e
+            go[m] = (F(theta=tp)[i] - F(theta=tm)[i]) / (2 * e)
+        assert np.linalg.norm(g["g_obs"][i] - go) <= 1e-6 * np.linalg.norm(go)
+        sd = np.zeros_like(st.S[i])
+        for idx in np.ndindex(*st.S[i].shape):
+            e = 1e-6 * max(1.0, abs(st.S[i][idx]))
+            Sp, Sm = st.S.copy(), st.S.copy()
+            Sp[(i,) + idx] += e
+            Sm[(i,) + idx] -= e
+            sd[idx] = (F(S=Sp)[i] - F(S=Sm)[i]) / (2 * e)
+        assert np.linalg.norm(g["S_dot"][i] - sd) <= 1e-6 * np.linalg.norm(sd)
+
+
+@pytest.mark.parametrize("combine", [synth.COMBINE_SUM, synth.COMBINE_PROD])
+def test_defect_density_constant_on_continuous_trajectories(orc, combine):
+    """Shooting states taken from each particle's own rollout close every
+    defect exactly (g_def = 0), so each density factor is its Gaussian
+    normalising constant: log p_ms exceeds the observation-only log p by
+    (n_s - 1) sum_d log(u_d / (sigma_def sqrt(2 pi))) per trajectory (times K
+    for the product over trajectories)."""
+    K, ns = 3, 4
+    pb0, obs, st0 = _setup(orc, "c2", N=3, K=K, T=40, n_s=ns, combine=combine)
+    pb1 = synth.make_problem("c2", N=3, K=K, T=40, n_s=ns, combine=combine, lik=synth.LIK_DEFECT)
+    pb1.u = np.array([1.0, 2.0, 0.5, 0.25])
+    pb0.u = pb1.u.copy()
+    st0.S = orc.shooting_init(pb0, st0.theta)
+    f0 = orc.forward(pb0, obs, st0)
+    f1 = orc.forward(pb1, obs, orc.State(pb1, st0.theta, st0.S))
+    assert np.all(f1["gdef"] == 0.0)
+    per_traj = (ns - 1) * np.sum(np.log(pb1.u / (pb1.sigma_def * np.sqrt(2.0 * np.pi))))
+    expect = per_traj * (K if combine == synth.COMBINE_PROD else 1)
+    np.testing.assert_allclose(f1["logp"] - f0["logp"], expect, rtol=0, atol=1e-9 * np.abs(f0["logp"]).max())
+    np.testing.assert_allclose(f1["wk"], f0["wk"], rtol=1e-12, atol=1e-15)
+
+
 def test_mass_scale_invariance(orc):
     """Without damping the planar dynamics are degree-0 homogeneous in the
     masses: single pendulum d l / d m = 0, double pendulum sum m_i d l/d m_i
