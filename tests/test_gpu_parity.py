@@ -530,7 +530,7 @@ def test_arm_adjoint_gradients(orc, over):
 
 @pytest.mark.parametrize("cfg,over", [("c2", dict(N=16, K=2, T=40, n_s=2)), ("c3", dict(N=16, K=1, T=60, n_s=3)),
                                       ("c4", dict(N=8, T=60, n_s=2)),
-                                      ("c2", dict(N=16, K=2, T=40, n_s=3, lik=synth.LIK_DEFECT)),
+                                      ("c2", dict(N=16, K=2, T=60, n_s=3, lik=synth.LIK_DEFECT)),
                                       ("c4", dict(N=8, K=2, T=60, n_s=2, lik=synth.LIK_DEFECT))])
 def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
     """The reverse-mode gradients against central differences of the GPU's
