@@ -114,27 +114,46 @@ __device__ inline void sdot_finish(const pds_job& J, int i, int r, const SdotPar
   if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], 2);
 }
 
-// Trajectory combination for particle i from l_k in LDS (K <= kAsmCap):
-// weights to w (LDS) and wk, log p to logp.  Same operations as
-// combine_sums.
-__device__ inline void combine_lds(const pds_job& J, int i, const double* l, double* w) {
-  const int K = J.K;
-  double mx = -INFINITY, lp = 0.0;
-  for (int k = 0; k < K; ++k) {
+// Wave sum over the 64 lanes by a fixed xor tree (every lane gets the sum).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Trajectory combination for particle i from l_k in LDS (K <= kAsmCap),
+// by the block's first wave: lane t handles k = t, t + 64, ... (in order),
+// lanes meet by fixed shuffle trees.  Weights to w (LDS) and wk, log p to
+// logp.
+__device__ inline void combine_wave(const pds_job& J, int i, const double* l, double* w) {
+  const int K = J.K, lane = threadIdx.x;
+  double mx = -INFINITY, ls = 0.0;
+  for (int k = lane; k < K; k += kWave) {
     mx = fmax(mx, l[k]);
-    lp += l[k];
+    ls += l[k];
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  double lp;
   if (J.combine == PDS_COMBINE_PROD) {
-    for (int k = 0; k < K; ++k) w[k] = 1.0;
+    for (int k = lane; k < K; k += kWave) w[k] = 1.0;
+    lp = wave_sum(ls);
   } else {
     double z = 0.0;
-    for (int k = 0; k < K; ++k) z += exp(l[k] - mx);
-    for (int k = 0; k < K; ++k) w[k] = exp(l[k] - mx) / z;
+    for (int k = lane; k < K; k += kWave) {
+      const double ek = exp(l[k] - mx);
+      w[k] = ek;
+      z += ek;
+    }
+    z = wave_sum(z);
+    for (int k = lane; k < K; k += kWave) w[k] /= z;
     lp = mx + log(z) - log((double)K);
   }
-  for (int k = 0; k < K; ++k) J.wk[(size_t)i * K + k] = w[k];
-  J.logp[i] = lp;
-  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+  for (int k = lane; k < K; k += kWave) J.wk[(size_t)i * K + k] = w[k];
+  if (lane == 0) {
+    J.logp[i] = lp;
+    if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+  }
 }
 
 // Trajectory combination for particle i from l_k already held in wk.
@@ -224,9 +243,10 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, 
       }
       __syncthreads();
       if (first) {
-        if (t == 0) {
-          if (in_lds) combine_lds(J, i, sl, sw);
-          else combine_sums(J, i);
+        if (in_lds) {
+          if (t < kWave) combine_wave(J, i, sl, sw);
+        } else if (t == 0) {
+          combine_sums(J, i);
         }
         first = false;
         __syncthreads();

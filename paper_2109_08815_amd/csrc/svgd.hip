@@ -1059,15 +1059,10 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
   const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
   const int stride = J.M + nSp;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  // Adam bias corrections, once per block (thread 0 reads the counter)
-  __shared__ float s_bc[2];
-  if (threadIdx.x == 0) {
-    const int it = J.iter_dev ? J.iter_dev[0] + 1 : iter;
-    s_bc[0] = 1.0f - powf(b1, (float)it);
-    s_bc[1] = 1.0f - powf(b2, (float)it);
-  }
-  __syncthreads();
-  const float bc1 = s_bc[0], bc2 = s_bc[1];
+  // Adam bias corrections 1 - b^it per thread, b^it = 2^(it log2 b): no
+  // block-wide wait before the element loads
+  const int it = J.iter_dev ? J.iter_dev[0] + 1 : iter;
+  const float bc1 = 1.0f - exp2f((float)it * log2f(b1)), bc2 = 1.0f - exp2f((float)it * log2f(b2));
   if (t < nT) {
     const int i = t / J.M, m = t % J.M;
     const float x = J.theta[t];
@@ -1113,11 +1108,12 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
   const int nb = map.begin[e + 1] - map.begin[e];
   if (J.iter_dev && nb <= kStepCountBlocks) {
     // Advance the device counter once every block of the job is past its
-    // use of it.  Only thread 0 reads it, and that read has returned (the
-    // bias corrections it wrote derive from it).  Blocks count themselves
-    // in iter_dev[1] with device-scope atomics; the last one bumps the
-    // counter and leaves the count at zero for the next call.  (Same-address
-    // atomics serialise: larger jobs use iter_bump_kernel.)
+    // use of it: each thread's stores above depend on the value it read,
+    // so after the barrier every read of this block has returned.  Blocks
+    // count themselves in iter_dev[1] with device-scope atomics; the last
+    // one bumps the counter and leaves the count at zero for the next call.
+    // (Same-address atomics serialise: larger jobs use iter_bump_kernel.)
+    __syncthreads();
     if (threadIdx.x == 0) {
       if (atomicAdd(&J.iter_dev[1], 1) == nb - 1) {
         atomicExch(&J.iter_dev[1], 0);
