@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "rigid2"])
     ap.add_argument("--no-graph", action="store_true", help="plain launches instead of graph replay")
     ap.add_argument("--no-overlap", action="store_true",
                     help="compute the kernel bandwidth after the adjoint instead of concurrently with it")
@@ -224,7 +224,8 @@ def main():
     value = steps_per_iter * args.steps / elapsed
 
     k_ms = float(np.mean(kt)) if len(kt) else float("nan")
-    fwd, rev, transc = L.algorithmic_flops(L.PDS_MODEL_PLANAR if pb.kind == 1 else L.PDS_MODEL_ARM, pb.n_dof)
+    model = L.model_consts(pb)[0]
+    fwd, rev, transc = L.algorithmic_flops(model, pb.n_dof)
     per_step = fwd + 2 * rev  # forward step + reverse step of each of the two adjoint channels
     achieved = steps_per_iter * per_step / (k_ms / 1e3) / 1e12
     finite = bool(torch.isfinite(job.theta).all().item())
@@ -243,7 +244,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s N=%d M=%d K=%d T=%d dt=%g n_s=%d" % (
             args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain",
-                          "c4": "7-joint arm with hinged box"}[args.config],
+                          "c4": "7-joint arm with hinged box",
+                          "rigid2": "rigid-link double pendulum"}[args.config],
             pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain",
             "bandwidth": "concurrent with the adjoint" if not args.no_overlap else "after the adjoint"},
         "iters_per_s": args.steps / elapsed,
@@ -256,7 +258,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(args.config),
-            "kernel": ("planar_adjoint_kernel<%d>" % pb.n_dof) if pb.kind == 1 else "arm_adjoint_kernel",
+            "kernel": "arm_adjoint_kernel" if model == L.PDS_MODEL_ARM else "planar_adjoint_kernel<%d, %s links>" % (
+                pb.n_dof, "rigid" if model == L.PDS_MODEL_PLANAR_RIGID else "point-mass"),
             "kernel_ms": k_ms,
             "flops_per_particle_step": per_step,
         },

@@ -67,8 +67,9 @@ extern "C" {
 /* Models.  PLANAR: chain of n_dof (1..5) revolute joints about z, link i a
  * massless rod of length l_i with a point mass m_i at its tip, q = 0 hanging
  * along the gravity direction; theta = (m_1..m_n, l_1..l_n), M = 2 n_dof;
- * observes x = q (d_x = n_dof); consts = [g_x, g_y, b_1..b_n] (gravity in
- * the plane, joint damping tau_i = -b_i qd_i).
+ * observes x = q (d_x = n_dof) or the whole state x = (q, qd) (d_x =
+ * 2 n_dof, one weight w_x per component); consts = [g_x, g_y, b_1..b_n]
+ * (gravity in the plane, joint damping tau_i = -b_i qd_i).
  * ARM: 7 revolute arm joints about their local z axes after modified-DH
  * placements (Rot_x(alpha) Trans_x(a) Trans_z(d)), PD-controlled towards
  * q_d(t) = qc + amp sin(omega t + phase) (tau = kp (q_d - q) + kd (qd_d -
@@ -81,8 +82,19 @@ extern "C" {
  * omega, phase) with the link inertia diagonal about its centre of mass,
  * then flange_d, b_h, box m, box c[3], box I_xx, I_yy, I_zz, point-mass m,
  * z_m.  Arm jobs need a workspace in every call that rolls out windows. */
+/* PLANAR_RIGID: the planar chain with rigid links, the parameterisation of
+ * the paper's physical double pendulum (Sec. IV-B table of estimated
+ * parameters): n_dof 1..2 revolute joints about z; link i has mass m_i,
+ * rotational inertia I_i (> 0) about its centre of mass at (cx_i, cy_i) in
+ * the link frame, joint friction tau_i = -b_i qd_i, and joint i sits at
+ * (0, -L_i) in link i-1's frame; theta = (m_1, I_1, cx_1, cy_1, b_1, then
+ * per further link L_i, m_i, I_i, cx_i, cy_i, b_i), M = 6 n_dof - 1 (11 for
+ * the double pendulum); observes q or (q, qd) as PLANAR does (the
+ * paper's pendulum experiment observes the whole state); consts = [g_x,
+ * g_y]. */
 #define PDS_MODEL_PLANAR 1
 #define PDS_MODEL_ARM 2
+#define PDS_MODEL_PLANAR_RIGID 3
 
 #define PDS_COMBINE_SUM 0   /* equally weighted mixture over trajectories, eq. traj_likelihood */
 #define PDS_COMBINE_PROD 1  /* product over trajectories, App. A-B eq. traj_likelihood_prod */
@@ -101,6 +113,16 @@ extern "C" {
  *   seed_gdef still applies) and svgd_step leaves lam_def unchanged. */
 #define PDS_LIK_MDMM 0
 #define PDS_LIK_DEFECT 1
+
+/* How svgd_step keeps theta inside [lo, hi] (Sec. III-D, III-E).
+ * SOFT: only through the MDMM limit constraint g_lim = clamp(theta) -
+ *   theta and its multiplier lam_lim, as the paper does; a particle may
+ *   leave the box for a while.
+ * PROJECT: additionally clamps every updated theta into [lo, hi], for
+ *   models whose simulation is undefined outside the box (the rigid links'
+ *   masses and inertias must stay positive); g_lim then stays 0. */
+#define PDS_LIMITS_SOFT 0
+#define PDS_LIMITS_PROJECT 1
 
 #define PDS_OPT_SGD 0
 #define PDS_OPT_ADAM 1
@@ -126,6 +148,7 @@ typedef struct pds_job {
   int32_t h;          /* steps per window, >= 1 */
   int32_t combine;    /* PDS_COMBINE_* */
   int32_t lik;        /* PDS_LIK_* */
+  int32_t limits;     /* PDS_LIMITS_* */
   float dt;           /* > 0 */
   float sigma_def;    /* > 0, defect scale of eq. likelihood-defect */
   float c;            /* >= 0, MDMM damping constant of eq. mdmm-loss */

@@ -52,13 +52,18 @@ extern "C" {
 // Model description.  kind: 1 planar chain of point masses on massless rods
 // (joints about z, q = 0 hangs along -y), 2 seven-joint arm (modified DH)
 // carrying a box on a passive hinge about the flange x axis, 3 linear toy
-// (one prismatic unit mass, no gravity, force theta0 + theta1 * time).
+// (one prismatic unit mass, no gravity, force theta0 + theta1 * time),
+// 4 planar chain of rigid links (joints about z) parameterised as the
+// physical double pendulum of Sec. IV-B: per link mass, rotational inertia
+// about the centre of mass, centre of mass (x, y) in the link frame and
+// joint friction, and the offset of every further joint along -y of its
+// parent (the link length).
 typedef struct {
   int32_t kind;
   int32_t n_dof;
   int32_t M;
   int32_t d_x;
-  int32_t obs_index[8];
+  int32_t obs_index[16];
   double gravity[3];
   double damping[8];
   double dh_a[7], dh_alpha[7], dh_d[7];
@@ -106,8 +111,14 @@ M3<S> diag3(const S& a, const S& b, const S& c) {
   return m;
 }
 
+// Parameter slots of the rigid planar chain (kind 4): link 0 holds (m, I,
+// cx, cy, b); every further link i holds (L, m, I, cx, cy, b), L being the
+// distance from joint i-1 to joint i.
+inline int rigid_base(int i) { return i == 0 ? 0 : 5 + 6 * (i - 1); }
+inline int rigid_slot(int i, int f) { return rigid_base(i) + (i > 0 ? 1 : 0) + f; }  // f: 0 m, 1 I, 2 cx, 3 cy, 4 b
+
 // Builds the articulated chain for parameters theta.  Planar chain: theta =
-// (m_1..m_n, l_1..l_n).  Arm: theta = (x_a, y_a, x_b, y_b), the in-plane
+// (m_1..m_n, l_1..l_n).  Rigid planar chain: see rigid_slot().  Arm: theta = (x_a, y_a, x_b, y_b), the in-plane
 // positions of the two point masses in the hinge frame.  Toy: theta drives
 // the force only.
 template <class S>
@@ -122,6 +133,18 @@ Chain<S> build_chain(const OrcModel& md, const S* th) {
       ch.jtype[i] = 0;
       ch.axis[i][0] = 0.0; ch.axis[i][1] = 0.0; ch.axis[i][2] = 1.0;
       ch.I[i] = rbi<S>(th[i], v3<S>(S(0.0), -th[n + i], S(0.0)), diag3<S>(S(0.0), S(0.0), S(0.0)));
+    }
+  } else if (md.kind == 4) {
+    for (int i = 0; i < md.n_dof; ++i) {
+      ch.Xtree[i].E = m3ident<S>();
+      ch.Xtree[i].r = (i == 0) ? v3zero<S>() : v3<S>(S(0.0), -th[rigid_base(i)], S(0.0));
+      ch.jtype[i] = 0;
+      ch.axis[i][0] = 0.0; ch.axis[i][1] = 0.0; ch.axis[i][2] = 1.0;
+      // Only the inertia about the joint axis acts in planar motion; the
+      // other two principal moments are set equal to it.
+      const S Iz = th[rigid_slot(i, 1)];
+      ch.I[i] = rbi<S>(th[rigid_slot(i, 0)], v3<S>(th[rigid_slot(i, 2)], th[rigid_slot(i, 3)], S(0.0)),
+                       diag3<S>(Iz, Iz, Iz));
     }
   } else if (md.kind == 2) {
     for (int i = 0; i < 7; ++i) {
@@ -164,6 +187,8 @@ template <class S>
 void joint_torque(const OrcModel& md, const S* th, double time, const S* q, const S* qd, S* tau) {
   if (md.kind == 1) {
     for (int i = 0; i < md.n_dof; ++i) tau[i] = -(md.damping[i] * qd[i]);
+  } else if (md.kind == 4) {
+    for (int i = 0; i < md.n_dof; ++i) tau[i] = -(th[rigid_slot(i, 4)] * qd[i]);
   } else if (md.kind == 2) {
     for (int i = 0; i < 7; ++i) {
       const double ph = md.omega[i] * time + md.phase[i];

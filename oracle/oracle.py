@@ -28,7 +28,7 @@ _I = C.POINTER(C.c_int)
 class OrcModel(C.Structure):
     _fields_ = [
         ("kind", C.c_int32), ("n_dof", C.c_int32), ("M", C.c_int32), ("d_x", C.c_int32),
-        ("obs_index", C.c_int32 * 8), ("gravity", C.c_double * 3), ("damping", C.c_double * 8),
+        ("obs_index", C.c_int32 * 16), ("gravity", C.c_double * 3), ("damping", C.c_double * 8),
         ("dh_a", C.c_double * 7), ("dh_alpha", C.c_double * 7), ("dh_d", C.c_double * 7),
         ("link_m", C.c_double * 7), ("link_c", (C.c_double * 3) * 7), ("link_I", (C.c_double * 3) * 7),
         ("kp", C.c_double * 7), ("kd", C.c_double * 7), ("qc", C.c_double * 7), ("amp", C.c_double * 7),
@@ -278,6 +278,8 @@ def mdmm_step(pb, st: State, phi_, g_con, S_dot, gdef, optimizer, it, lr_theta=N
                         _p(_f64(phi_)), _p(_f64(g_con)), _p(np.ascontiguousarray(Sd)), _p(np.ascontiguousarray(gd)),
                         _p(lrt), _p(lrs), float(el), int(optimizer), int(it), _p(st.theta), _p(st.S), _p(st.lam_lim),
                         _p(st.lam_def), _p(st.adam_m), _p(st.adam_v))
+    if getattr(pb, "limits", 0) == 1:  # projected limits: clamp the updated theta into the box
+        np.clip(st.theta, pb.lo, pb.hi, out=st.theta)
 
 
 def csvgd_iteration(pb, obs, st: State, it, optimizer=1, variant=0):

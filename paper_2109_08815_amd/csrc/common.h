@@ -29,12 +29,17 @@ __device__ inline int map_entry(const JobMap& m, int block) {
 
 // Per-unit adjoint rows: N consecutive values from registers to memory with
 // 16-byte (double) or 8-byte (float) vector stores.  p must be aligned to
-// that width and N even.
+// that width and N even; odd-length double rows (rows of odd length start at
+// any 8-byte boundary) are stored element by element.
 template <int N>
 __device__ inline void store_row(double* p, const double* v) {
-  static_assert(N % 2 == 0, "even rows only");
+  if constexpr (N % 2 == 0) {
 #pragma unroll
-  for (int c = 0; c < N / 2; ++c) reinterpret_cast<double2*>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
+    for (int c = 0; c < N / 2; ++c) reinterpret_cast<double2*>(p)[c] = make_double2(v[2 * c], v[2 * c + 1]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < N; ++c) p[c] = v[c];
+  }
 }
 template <int N>
 __device__ inline void store_row(float* p, const float* v) {
@@ -131,10 +136,10 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
 }
 
 // Launchers implemented in the .hip files.  Each returns a hipError_t.
-hipError_t launch_planar_forward(const JobMap& map, int nb, const pds_job* d_jobs, int grid, bool with_ll,
-                                 hipStream_t s);
-hipError_t launch_planar_adjoint(const JobMap& map, int nb, const pds_job* d_jobs, char* ws, int grid, bool split,
-                                 bool full, size_t lds_bytes, hipStream_t s);
+hipError_t launch_planar_forward(const JobMap& map, int nb, bool rigid, const pds_job* d_jobs, int grid,
+                                 bool with_ll, hipStream_t s);
+hipError_t launch_planar_adjoint(const JobMap& map, int nb, bool rigid, const pds_job* d_jobs, char* ws, int grid,
+                                 bool split, bool full, size_t lds_bytes, hipStream_t s);
 hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_grad,
                            hipStream_t s);
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);

@@ -79,7 +79,15 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     if (J.n_dof < 1 || J.n_dof > 5)
       return fail(PDS_EUNSUPPORTED, "job %d: planar n_dof %d outside 1..5", idx, J.n_dof);
     if (J.M != 2 * J.n_dof) return fail(PDS_EINVAL, "job %d: planar model needs M = 2 n_dof (got M=%d)", idx, J.M);
-    if (J.d_x != J.n_dof) return fail(PDS_EINVAL, "job %d: planar model observes q, d_x must be n_dof", idx);
+    if (J.d_x != J.n_dof && J.d_x != 2 * J.n_dof)
+      return fail(PDS_EINVAL, "job %d: planar models observe q (d_x = n_dof) or (q, qd) (d_x = 2 n_dof)", idx);
+  } else if (J.model == PDS_MODEL_PLANAR_RIGID) {
+    if (J.n_dof < 1 || J.n_dof > 2)
+      return fail(PDS_EUNSUPPORTED, "job %d: rigid planar n_dof %d outside 1..2", idx, J.n_dof);
+    if (J.M != 6 * J.n_dof - 1)
+      return fail(PDS_EINVAL, "job %d: rigid planar model needs M = 6 n_dof - 1 (got M=%d)", idx, J.M);
+    if (J.d_x != J.n_dof && J.d_x != 2 * J.n_dof)
+      return fail(PDS_EINVAL, "job %d: planar models observe q (d_x = n_dof) or (q, qd) (d_x = 2 n_dof)", idx);
   } else {
     return fail(PDS_EINVAL, "job %d: unknown model %d", idx, J.model);
   }
@@ -97,6 +105,8 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     return fail(PDS_EINVAL, "job %d: unknown combine %d", idx, J.combine);
   if (J.lik != PDS_LIK_MDMM && J.lik != PDS_LIK_DEFECT)
     return fail(PDS_EINVAL, "job %d: unknown likelihood mode %d", idx, J.lik);
+  if (J.limits != PDS_LIMITS_SOFT && J.limits != PDS_LIMITS_PROJECT)
+    return fail(PDS_EINVAL, "job %d: unknown limits mode %d", idx, J.limits);
   if (need & (NEED_FWD | NEED_LL | NEED_ADJ)) {
     REQ(consts, 4); REQ(theta, 4); REQ(s0, 4); REQ(end_states, 4);
     if (J.n_s > 1) REQ(S, 4);
@@ -224,15 +234,17 @@ int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with
       if (rc) return rc;
     }
   }
-  for (int nb = 1; nb <= 5; ++nb) {
-    int grid = 0;
-    JobMap m = make_map(
-        h_jobs, n, off, [&](const pds_job& J) { return J.model == PDS_MODEL_PLANAR && J.n_dof == nb; },
-        [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
-    if (m.n == 0) continue;
-    rc = launch_rc(pds::launch_planar_forward(m, nb, d_jobs, grid, with_ll, s), "planar_forward");
-    if (rc) return rc;
-  }
+  for (int model : {PDS_MODEL_PLANAR, PDS_MODEL_PLANAR_RIGID})
+    for (int nb = 1; nb <= 5; ++nb) {
+      int grid = 0;
+      JobMap m = make_map(
+          h_jobs, n, off, [&](const pds_job& J) { return J.model == model && J.n_dof == nb; },
+          [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
+      if (m.n == 0) continue;
+      rc = launch_rc(pds::launch_planar_forward(m, nb, model == PDS_MODEL_PLANAR_RIGID, d_jobs, grid, with_ll, s),
+                     "planar_forward");
+      if (rc) return rc;
+    }
   timing_end(s, slot);
   return PDS_OK;
 }
@@ -471,11 +483,12 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
       if (rc) return rc;
     }
   }
+  for (int model : {PDS_MODEL_PLANAR, PDS_MODEL_PLANAR_RIGID})
   for (int nb = 1; nb <= 5; ++nb) {
     for (int mode = 0; mode < 4; ++mode) {
       const bool split = (mode & 1) != 0, full = (mode & 2) != 0;
       auto pick = [&](const pds_job& J) {
-        if (J.model != PDS_MODEL_PLANAR || J.n_dof != nb) return false;
+        if (J.model != model || J.n_dof != nb) return false;
         const AdjShape a = planar_shape(J);
         return a.split == split && a.full == full;
       };
@@ -491,7 +504,9 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
           &grid);
       if (m.n == 0) continue;
       if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "window of h steps needs %zu bytes of LDS", lds);
-      rc = launch_rc(pds::launch_planar_adjoint(m, nb, d_jobs, w, grid, split, full, lds, s), "planar_adjoint");
+      rc = launch_rc(pds::launch_planar_adjoint(m, nb, model == PDS_MODEL_PLANAR_RIGID, d_jobs, w, grid, split, full,
+                                                lds, s),
+                     "planar_adjoint");
       if (rc) return rc;
     }
   }

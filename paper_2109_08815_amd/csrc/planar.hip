@@ -34,11 +34,41 @@ namespace {
 
 __host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincos_fast(x, sn, cs); }
 
+// Link parameters.  Point-mass chain (PDS_MODEL_PLANAR): mass m_i at the
+// tip of a massless rod of length l_i, joint i+1 at that tip.  Rigid chain
+// (PDS_MODEL_PLANAR_RIGID, RIGID = true): link i has mass m_i, rotational
+// inertia I_i about its centre of mass at (cx_i, cy_i) in the link frame,
+// joint friction b_i, and joint i sits at (0, -L_i) in the frame of link
+// i-1 (L_0 unused); the point-mass chain is the rigid one with c = (0, -l),
+// I = 0 and L_i = l_{i-1}.
 template <int NB, class R = float>
 struct Planar {
   R m[NB], l[NB], b[NB];
+  R I[NB], cx[NB], cy[NB], L[NB];  // rigid chain only
   R gx, gy;
 };
+
+// theta layout.  Point masses: (m_1..m_n, l_1..l_n).  Rigid chain: link 1
+// (m, I, cx, cy, b), then per further link (L, m, I, cx, cy, b): 6 n - 1.
+template <int NB, bool RIGID>
+struct PlanarParams {
+  static constexpr int M = RIGID ? 6 * NB - 1 : 2 * NB;
+  __host__ __device__ static constexpr int base(int i) { return i == 0 ? 0 : 5 + 6 * (i - 1); }
+  __host__ __device__ static constexpr int L(int i) { return base(i); }  // i >= 1
+  __host__ __device__ static constexpr int m(int i) { return RIGID ? base(i) + (i > 0) : i; }
+  __host__ __device__ static constexpr int l(int i) { return NB + i; }  // point masses
+  __host__ __device__ static constexpr int I(int i) { return base(i) + (i > 0) + 1; }
+  __host__ __device__ static constexpr int cx(int i) { return base(i) + (i > 0) + 2; }
+  __host__ __device__ static constexpr int cy(int i) { return base(i) + (i > 0) + 3; }
+  __host__ __device__ static constexpr int b(int i) { return base(i) + (i > 0) + 4; }
+};
+
+// Offset of joint i (i >= 1) along the parent's -y axis.
+template <int NB, bool RIGID, class R>
+__host__ __device__ __forceinline__ R joint_offset(const Planar<NB, R>& P, int i) {
+  if constexpr (RIGID) return P.L[i];
+  else return P.l[i - 1];
+}
 
 // Intermediates of one ABA evaluation needed by its reverse.
 template <int NB, class R = float>
@@ -53,7 +83,7 @@ struct Tape {
 };
 
 // Articulated Body Algorithm, planar form.  Fills the tape; qdd in T.qdd.
-template <int NB, class R = float>
+template <int NB, class R = float, bool RIGID = false>
 __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q, const R* qd, Tape<NB, R>& T) {
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
@@ -62,7 +92,7 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
     if (i == 0) {
       v0 = qd[0]; v1 = 0.f; v2 = 0.f;
     } else {
-      const R L = P.l[i - 1];
+      const R L = joint_offset<NB, RIGID>(P, i);
       const R w = T.v[i - 1][0];
       const R tx = T.v[i - 1][1] + w * L, ty = T.v[i - 1][2];
       v0 = w + qd[i];
@@ -70,13 +100,24 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
       v2 = -T.sn[i] * tx + T.cs[i] * ty;
     }
     T.v[i][0] = v0; T.v[i][1] = v1; T.v[i][2] = v2;
-    const R m = P.m[i], l = P.l[i];
-    const R h1 = m * (l * v0 + v1), h2 = m * v2;
+    const R m = P.m[i];
+    R h1, h2;  // linear momentum of the link, m (v + w x c)
+    if constexpr (RIGID) {
+      const R cx = P.cx[i], cy = P.cy[i];
+      h1 = m * (v1 - cy * v0);
+      h2 = m * (v2 + cx * v0);
+      T.IA[i][0] = P.I[i] + m * (cx * cx + cy * cy); T.IA[i][1] = -m * cy; T.IA[i][2] = m * cx;
+      T.IA[i][3] = m;                                T.IA[i][4] = 0.f;     T.IA[i][5] = m;
+    } else {
+      const R l = P.l[i];
+      h1 = m * (l * v0 + v1);
+      h2 = m * v2;
+      T.IA[i][0] = m * l * l; T.IA[i][1] = m * l; T.IA[i][2] = 0.f;
+      T.IA[i][3] = m;         T.IA[i][4] = 0.f;   T.IA[i][5] = m;
+    }
     T.pA[i][0] = v1 * h2 - v2 * h1;
     T.pA[i][1] = -v0 * h2;
     T.pA[i][2] = v0 * h1;
-    T.IA[i][0] = m * l * l; T.IA[i][1] = m * l; T.IA[i][2] = 0.f;
-    T.IA[i][3] = m;         T.IA[i][4] = 0.f;   T.IA[i][5] = m;
   }
 #pragma unroll
   for (int i = NB - 1; i >= 0; --i) {
@@ -94,7 +135,7 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
       const R pa0 = T.pA[i][0] + u;
       const R pa1 = T.pA[i][1] + a * c1 + bb * c2 + U1 * k;
       const R pa2 = T.pA[i][2] + bb * c1 + d * c2 + U2 * k;
-      const R cs = T.cs[i], sn = T.sn[i], L = P.l[i - 1];
+      const R cs = T.cs[i], sn = T.sn[i], L = joint_offset<NB, RIGID>(P, i);
       const R A00 = a * cs * cs - 2.f * bb * cs * sn + d * sn * sn;
       const R A01 = (a - d) * cs * sn + bb * (cs * cs - sn * sn);
       const R A11 = a * sn * sn + 2.f * bb * cs * sn + d * cs * cs;
@@ -113,7 +154,7 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
   R a0 = 0.f, a1 = -P.gx, a2 = -P.gy;  // base acceleration = -gravity
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const R L = (i == 0) ? 0.f : P.l[i - 1];
+    const R L = (i == 0) ? R(0.f) : joint_offset<NB, RIGID>(P, i);
     const R tx = a1 + a0 * L, ty = a2;
     const R c1 = T.v[i][2] * qd[i], c2 = -T.v[i][1] * qd[i];
     const R ap0 = a0;
@@ -127,10 +168,11 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
 }
 
 // Reverse of aba(): given qddb = d L / d qdd, accumulates d L / d q, d L / d qd
-// and d L / d (m, l).
-template <int NB, class R = float>
+// and d L / d theta into thb (layout of PlanarParams).
+template <int NB, class R = float, bool RIGID = false>
 __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R* qd, const Tape<NB, R>& T,
-                                        const R* qddb_in, R* qb, R* qdb, R* mb, R* lb) {
+                                        const R* qddb_in, R* qb, R* qdb, R* thb) {
+  using PP = PlanarParams<NB, RIGID>;
   R csb[NB], snb[NB], Lb[NB], taub[NB];
   R IAb[NB][6], pAb[NB][3], vb[NB][3], cb1[NB], cb2[NB];
   R ub[NB], Db[NB], U1b[NB], U2b[NB], invDb[NB];
@@ -167,7 +209,8 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
     if (i == 0) {
       x0 = 0.f; x1 = -P.gx; x2 = -P.gy; L = 0.f;
     } else {
-      x0 = T.ap[i - 1][0] + T.qdd[i - 1]; x1 = T.ap[i - 1][1]; x2 = T.ap[i - 1][2]; L = P.l[i - 1];
+      x0 = T.ap[i - 1][0] + T.qdd[i - 1]; x1 = T.ap[i - 1][1]; x2 = T.ap[i - 1][2];
+      L = joint_offset<NB, RIGID>(P, i);
     }
     const R cs = T.cs[i], sn = T.sn[i];
     const R tx = x1 + x0 * L, ty = x2;
@@ -192,7 +235,7 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
       const R k = u * invD;
       const R pa1 = T.pA[i][1] + a * c1 + bb * c2 + U1 * k;
       const R pa2 = T.pA[i][2] + bb * c1 + d * c2 + U2 * k;
-      const R cs = T.cs[i], sn = T.sn[i], L = P.l[p];
+      const R cs = T.cs[i], sn = T.sn[i], L = joint_offset<NB, RIGID>(P, i);
       const R A00 = a * cs * cs - 2.f * bb * cs * sn + d * sn * sn;
       const R A01 = (a - d) * cs * sn + bb * (cs * cs - sn * sn);
       const R f1 = cs * pa1 - sn * pa2;
@@ -257,17 +300,34 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
     IAb[i][0] += Db[i];
     IAb[i][1] += U1b[i];
     IAb[i][2] += U2b[i];
-    // rigid inertia of a point mass at (0, -l): m [l^2, l, 0, 1, 0, 1]
-    const R m = P.m[i], l = P.l[i];
-    mb[i] += l * l * IAb[i][0] + l * IAb[i][1] + IAb[i][3] + IAb[i][5];
-    lb[i] += 2.f * m * l * IAb[i][0] + m * IAb[i][1];
+    const R m = P.m[i];
+    if constexpr (RIGID) {
+      // rigid inertia [I + m |c|^2, -m cy, m cx, m, 0, m]
+      const R cx = P.cx[i], cy = P.cy[i];
+      thb[PP::m(i)] += (cx * cx + cy * cy) * IAb[i][0] - cy * IAb[i][1] + cx * IAb[i][2] + IAb[i][3] + IAb[i][5];
+      thb[PP::I(i)] += IAb[i][0];
+      thb[PP::cx(i)] += 2.f * m * cx * IAb[i][0] + m * IAb[i][2];
+      thb[PP::cy(i)] += 2.f * m * cy * IAb[i][0] - m * IAb[i][1];
+    } else {
+      // rigid inertia of a point mass at (0, -l): m [l^2, l, 0, 1, 0, 1]
+      const R l = P.l[i];
+      thb[PP::m(i)] += l * l * IAb[i][0] + l * IAb[i][1] + IAb[i][3] + IAb[i][5];
+      thb[PP::l(i)] += 2.f * m * l * IAb[i][0] + m * IAb[i][1];
+    }
   }
   // ---- pass 1 (outward velocities and bias forces), reversed ----
 #pragma unroll
   for (int i = NB - 1; i >= 0; --i) {
     const R v0 = T.v[i][0], v1 = T.v[i][1], v2 = T.v[i][2];
-    const R m = P.m[i], l = P.l[i];
-    const R h1 = m * (l * v0 + v1), h2 = m * v2;
+    const R m = P.m[i];
+    R h1, h2;
+    if constexpr (RIGID) {
+      h1 = m * (v1 - P.cy[i] * v0);
+      h2 = m * (v2 + P.cx[i] * v0);
+    } else {
+      h1 = m * (P.l[i] * v0 + v1);
+      h2 = m * v2;
+    }
     R vb0 = vb[i][0], vb1 = vb[i][1], vb2 = vb[i][2];
     const R pb0 = pAb[i][0], pb1 = pAb[i][1], pb2 = pAb[i][2];
     vb1 += pb0 * h2;
@@ -278,11 +338,22 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
     h2b -= pb1 * v0;
     vb0 += pb2 * h1;
     h1b += pb2 * v0;
-    vb0 += m * l * h1b;
-    vb1 += m * h1b;
-    mb[i] += (l * v0 + v1) * h1b + v2 * h2b;
-    lb[i] += m * v0 * h1b;
-    vb2 += m * h2b;
+    if constexpr (RIGID) {
+      const R cx = P.cx[i], cy = P.cy[i];
+      vb0 += -m * cy * h1b + m * cx * h2b;
+      vb1 += m * h1b;
+      vb2 += m * h2b;
+      thb[PP::m(i)] += (v1 - cy * v0) * h1b + (v2 + cx * v0) * h2b;
+      thb[PP::cy(i)] += -m * v0 * h1b;
+      thb[PP::cx(i)] += m * v0 * h2b;
+    } else {
+      const R l = P.l[i];
+      vb0 += m * l * h1b;
+      vb1 += m * h1b;
+      thb[PP::m(i)] += (l * v0 + v1) * h1b + v2 * h2b;
+      thb[PP::l(i)] += m * v0 * h1b;
+      vb2 += m * h2b;
+    }
     // c = (0, v2 qd, -v1 qd)
     vb2 += cb1[i] * qd[i];
     qdb[i] += cb1[i] * v2;
@@ -292,7 +363,7 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
     qdb[i] += vb0;
     if (i > 0) {
       const R x0 = T.v[i - 1][0], x1 = T.v[i - 1][1], x2 = T.v[i - 1][2];
-      const R L = P.l[i - 1], cs = T.cs[i], sn = T.sn[i];
+      const R L = joint_offset<NB, RIGID>(P, i), cs = T.cs[i], sn = T.sn[i];
       const R tx = x1 + x0 * L, ty = x2;
       const R txb = cs * vb1 - sn * vb2, tyb = sn * vb1 + cs * vb2;
       csb[i] += vb1 * tx + vb2 * ty;
@@ -307,15 +378,20 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
   for (int i = 0; i < NB; ++i) {
     qb[i] += -T.sn[i] * csb[i] + T.cs[i] * snb[i];
     qdb[i] += -P.b[i] * taub[i];
-    if (i > 0) lb[i - 1] += Lb[i];
+    if constexpr (RIGID) {
+      thb[PP::b(i)] += -qd[i] * taub[i];  // tau_i = -b_i qd_i
+      if (i > 0) thb[PP::L(i)] += Lb[i];
+    } else {
+      if (i > 0) thb[PP::l(i - 1)] += Lb[i];
+    }
   }
 }
 
 // Semi-implicit Euler: qd' = qd + dt qdd, q' = q + dt qd'.
-template <int NB, class R = float>
+template <int NB, class R = float, bool RIGID = false>
 __host__ __device__ __forceinline__ void step(const Planar<NB, R>& P, R dt, R* q, R* qd) {
   Tape<NB, R> T;
-  aba<NB, R>(P, q, qd, T);
+  aba<NB, R, RIGID>(P, q, qd, T);
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     qd[i] = qd[i] + dt * T.qdd[i];
@@ -325,25 +401,34 @@ __host__ __device__ __forceinline__ void step(const Planar<NB, R>& P, R dt, R* q
 
 // Reverse of one Euler step given the tape at its input state.  On entry
 // (qb, qdb) are the adjoints of the step's outputs; on exit of its inputs.
-template <int NB, class R = float>
+template <int NB, class R = float, bool RIGID = false>
 __host__ __device__ __forceinline__ void step_rev(const Planar<NB, R>& P, R dt, const R* qd, const Tape<NB, R>& T,
-                                         R* qb, R* qdb, R* mb, R* lb) {
+                                         R* qb, R* qdb, R* thb) {
   R qddb[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     qdb[i] = qdb[i] + dt * qb[i];
     qddb[i] = dt * qdb[i];
   }
-  aba_rev<NB, R>(P, qd, T, qddb, qb, qdb, mb, lb);
+  aba_rev<NB, R, RIGID>(P, qd, T, qddb, qb, qdb, thb);
 }
 
-template <int NB>
+template <int NB, bool RIGID>
 __device__ __forceinline__ void load_model(const pds_job& J, const float* th, Planar<NB>& P) {
+  using PP = PlanarParams<NB, RIGID>;
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    P.m[i] = th[i];
-    P.l[i] = th[NB + i];
-    P.b[i] = J.consts[2 + i];
+    P.m[i] = th[PP::m(i)];
+    if constexpr (RIGID) {
+      P.I[i] = th[PP::I(i)];
+      P.cx[i] = th[PP::cx(i)];
+      P.cy[i] = th[PP::cy(i)];
+      P.b[i] = th[PP::b(i)];
+      P.L[i] = i > 0 ? th[PP::L(i)] : 0.f;
+    } else {
+      P.l[i] = th[PP::l(i)];
+      P.b[i] = J.consts[2 + i];
+    }
   }
   P.gx = J.consts[0];
   P.gy = J.consts[1];
@@ -374,9 +459,10 @@ __device__ inline double log_norm_const(const pds_job& J) {
   return c;
 }
 
-template <int NB>
+template <int NB, bool RIGID>
 __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                int with_ll) {
+  constexpr int MP = PlanarParams<NB, RIGID>::M;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int U = J.N * J.K * J.n_s;
@@ -385,10 +471,10 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
   constexpr int DS = 2 * NB;
   const Unit w = unit_of(J, u);
   Planar<NB> P;
-  float th[2 * NB];
+  float th[MP];
 #pragma unroll
-  for (int m = 0; m < 2 * NB; ++m) th[m] = J.theta[(size_t)w.i * J.M + m];
-  load_model<NB>(J, th, P);
+  for (int m = 0; m < MP; ++m) th[m] = J.theta[(size_t)w.i * J.M + m];
+  load_model<NB, RIGID>(J, th, P);
   const float* st = start_ptr(J, w, DS);
   float q[NB], qd[NB];
 #pragma unroll
@@ -397,18 +483,28 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
   const int t0 = w.j * J.h;
   const float* obs = J.obs + ((size_t)w.k * J.T + t0) * J.d_x;
   float* traj = J.traj ? J.traj + (((size_t)w.i * J.K + w.k) * J.T + t0) * DS : nullptr;
-  float wx[NB];
+  // d_x = NB observes q; d_x = 2 NB the whole state (q, qd)
+  const bool obs_v = J.d_x == DS;
+  const int DX = obs_v ? DS : NB;
+  float wx[DS];
 #pragma unroll
-  for (int d = 0; d < NB; ++d) wx[d] = J.w_x[d];
+  for (int d = 0; d < DS; ++d) wx[d] = (d < NB || obs_v) ? J.w_x[d] : 0.f;
   double ll = 0.0;
   for (int s = 0; s < J.h; ++s) {
-    step<NB>(P, dt, q, qd);
+    step<NB, float, RIGID>(P, dt, q, qd);
     if (with_ll) {
       float acc = 0.f;
 #pragma unroll
       for (int d = 0; d < NB; ++d) {
-        const float r = (obs[s * NB + d] - q[d]) * wx[d];
+        const float r = (obs[s * DX + d] - q[d]) * wx[d];
         acc += r * r;
+      }
+      if (obs_v) {
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+          const float r = (obs[s * DX + NB + d] - qd[d]) * wx[NB + d];
+          acc += r * r;
+        }
       }
       ll -= 0.5 * (double)acc;
     }
@@ -459,9 +555,10 @@ __host__ __device__ inline int seg_len_of(int h) {
 // execute the same instructions).  full = 1 keeps every state of the window
 // in LDS (no recomputation), full = 0 keeps checkpoints every B ~ sqrt(h)
 // steps and recomputes one segment at a time.
-template <int NB, bool SPLIT>
+template <int NB, bool SPLIT, bool RIGID>
 __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                char* __restrict__ ws, int full) {
+  constexpr int MP = PlanarParams<NB, RIGID>::M;
   extern __shared__ float lds[];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
@@ -482,10 +579,10 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 
   const Unit w = unit_of(J, u);
   Planar<NB> P;
-  float th[2 * NB];
+  float th[MP];
 #pragma unroll
-  for (int m = 0; m < 2 * NB; ++m) th[m] = J.theta[(size_t)w.i * J.M + m];
-  load_model<NB>(J, th, P);
+  for (int m = 0; m < MP; ++m) th[m] = J.theta[(size_t)w.i * J.M + m];
+  load_model<NB, RIGID>(J, th, P);
   const float* st = start_ptr(J, w, DS);
   float q[NB], qd[NB];
 #pragma unroll
@@ -499,9 +596,11 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   const int segbase = full ? 0 : nseg;
   const int t0 = w.j * h;
   const float* obs = J.obs + ((size_t)w.k * J.T + t0) * J.d_x;
-  float wx[NB];
+  const bool obs_v = J.d_x == DS;  // observes (q, qd), else q
+  const int DX = obs_v ? DS : NB;
+  float wx[DS];
 #pragma unroll
-  for (int d = 0; d < NB; ++d) wx[d] = J.w_x[d];
+  for (int d = 0; d < DS; ++d) wx[d] = (d < NB || obs_v) ? J.w_x[d] : 0.f;
   auto slot = [&](int s, int d) -> float& { return lds[((size_t)s * DS + d) * kWave + lane]; };
 
   // ---- forward sweep: log-likelihood, end state, stored states ----
@@ -512,12 +611,19 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 #pragma unroll
       for (int d = 0; d < NB; ++d) { slot(sl, d) = q[d]; slot(sl, NB + d) = qd[d]; }
     }
-    step<NB>(P, dt, q, qd);
+    step<NB, float, RIGID>(P, dt, q, qd);
     float acc = 0.f;
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
-      const float r = (obs[s * NB + d] - q[d]) * wx[d];
+      const float r = (obs[s * DX + d] - q[d]) * wx[d];
       acc += r * r;
+    }
+    if (obs_v) {
+#pragma unroll
+      for (int d = 0; d < NB; ++d) {
+        const float r = (obs[s * DX + NB + d] - qd[d]) * wx[NB + d];
+        acc += r * r;
+      }
     }
     ll -= 0.5 * (double)acc;
   }
@@ -587,9 +693,9 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   if (ch == 0) J.ll_win[iu] = ll;
 
   // ---- reverse sweep over segments ----
-  double gm_a[2 * NB], gm_c[2 * NB];
+  double gm_a[MP], gm_c[MP];
 #pragma unroll
-  for (int m = 0; m < 2 * NB; ++m) { gm_a[m] = 0.0; gm_c[m] = 0.0; }
+  for (int m = 0; m < MP; ++m) { gm_a[m] = 0.0; gm_c[m] = 0.0; }
   for (int sg = nseg - 1; sg >= 0; --sg) {
     const int a = sg * B;
     const int bnd = min(h, a + B);
@@ -599,7 +705,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 #pragma unroll
       for (int d = 0; d < NB; ++d) { slot(segbase, d) = q[d]; slot(segbase, NB + d) = qd[d]; }
       for (int s = a; s < bnd; ++s) {
-        step<NB>(P, dt, q, qd);
+        step<NB, float, RIGID>(P, dt, q, qd);
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
           slot(segbase + s - a + 1, d) = q[d];
@@ -612,26 +718,34 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 #pragma unroll
       for (int d = 0; d < NB; ++d) {
         const float x = slot(segbase + s - a + 1, d);
-        const float r = (obs[s * NB + d] - x) * wx[d];
+        const float r = (obs[s * DX + d] - x) * wx[d];
         qb_a[d] += obs_on * (r * wx[d]);
+      }
+      if (obs_v) {
+#pragma unroll
+        for (int d = 0; d < NB; ++d) {
+          const float x = slot(segbase + s - a + 1, NB + d);
+          const float r = (obs[s * DX + NB + d] - x) * wx[NB + d];
+          qdb_a[d] += obs_on * (r * wx[NB + d]);
+        }
       }
       float qs[NB], qds[NB];
 #pragma unroll
       for (int d = 0; d < NB; ++d) { qs[d] = slot(segbase + s - a, d); qds[d] = slot(segbase + s - a, NB + d); }
       Tape<NB> T;
-      aba<NB>(P, qs, qds, T);
-      float mb[NB], lb[NB];
+      aba<NB, float, RIGID>(P, qs, qds, T);
+      float thb[MP];
 #pragma unroll
-      for (int d = 0; d < NB; ++d) { mb[d] = 0.f; lb[d] = 0.f; }
-      step_rev<NB>(P, dt, qds, T, qb_a, qdb_a, mb, lb);
+      for (int m = 0; m < MP; ++m) thb[m] = 0.f;
+      step_rev<NB, float, RIGID>(P, dt, qds, T, qb_a, qdb_a, thb);
 #pragma unroll
-      for (int d = 0; d < NB; ++d) { gm_a[d] += (double)mb[d]; gm_a[NB + d] += (double)lb[d]; }
+      for (int m = 0; m < MP; ++m) gm_a[m] += (double)thb[m];
       if (!SPLIT) {
 #pragma unroll
-        for (int d = 0; d < NB; ++d) { mb[d] = 0.f; lb[d] = 0.f; }
-        step_rev<NB>(P, dt, qds, T, qb_c, qdb_c, mb, lb);
+        for (int m = 0; m < MP; ++m) thb[m] = 0.f;
+        step_rev<NB, float, RIGID>(P, dt, qds, T, qb_c, qdb_c, thb);
 #pragma unroll
-        for (int d = 0; d < NB; ++d) { gm_c[d] += (double)mb[d]; gm_c[NB + d] += (double)lb[d]; }
+        for (int m = 0; m < MP; ++m) gm_c[m] += (double)thb[m];
       }
     }
   }
@@ -640,17 +754,17 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     double* gth = ch == 0 ? gth_obs : gth_con;
     float* gs = ch == 0 ? gs_obs : gs_con;
 #pragma unroll
-    for (int m = 0; m < 2 * NB; ++m) bad |= !isfinite(gm_a[m]);
-    store_row<2 * NB>(gth + iu * (2 * NB), gm_a);
+    for (int m = 0; m < MP; ++m) bad |= !isfinite(gm_a[m]);
+    store_row<MP>(gth + iu * MP, gm_a);
     float row[DS];
 #pragma unroll
     for (int d = 0; d < NB; ++d) { row[d] = qb_a[d]; row[NB + d] = qdb_a[d]; }
     store_row<DS>(gs + iu * DS, row);
   } else {
 #pragma unroll
-    for (int m = 0; m < 2 * NB; ++m) bad |= !isfinite(gm_a[m]) || !isfinite(gm_c[m]);
-    store_row<2 * NB>(gth_obs + iu * (2 * NB), gm_a);
-    store_row<2 * NB>(gth_con + iu * (2 * NB), gm_c);
+    for (int m = 0; m < MP; ++m) bad |= !isfinite(gm_a[m]) || !isfinite(gm_c[m]);
+    store_row<MP>(gth_obs + iu * MP, gm_a);
+    store_row<MP>(gth_con + iu * MP, gm_c);
     float ra[DS], rc[DS];
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
@@ -667,44 +781,59 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 
 }  // namespace
 
-template <int NB>
+template <int NB, bool RIGID>
 static hipError_t fwd_nb(const JobMap& map, const pds_job* d_jobs, int grid, bool with_ll, hipStream_t s) {
-  hipLaunchKernelGGL(planar_forward_kernel<NB>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, with_ll ? 1 : 0);
+  hipLaunchKernelGGL((planar_forward_kernel<NB, RIGID>), dim3(grid), dim3(kWave), 0, s, map, d_jobs,
+                     with_ll ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_planar_forward(const JobMap& map, int nb, const pds_job* d_jobs, int grid, bool with_ll,
-                                 hipStream_t s) {
+hipError_t launch_planar_forward(const JobMap& map, int nb, bool rigid, const pds_job* d_jobs, int grid,
+                                 bool with_ll, hipStream_t s) {
+  if (rigid) {
+    switch (nb) {
+      case 1: return fwd_nb<1, true>(map, d_jobs, grid, with_ll, s);
+      case 2: return fwd_nb<2, true>(map, d_jobs, grid, with_ll, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (nb) {
-    case 1: return fwd_nb<1>(map, d_jobs, grid, with_ll, s);
-    case 2: return fwd_nb<2>(map, d_jobs, grid, with_ll, s);
-    case 3: return fwd_nb<3>(map, d_jobs, grid, with_ll, s);
-    case 4: return fwd_nb<4>(map, d_jobs, grid, with_ll, s);
-    case 5: return fwd_nb<5>(map, d_jobs, grid, with_ll, s);
+    case 1: return fwd_nb<1, false>(map, d_jobs, grid, with_ll, s);
+    case 2: return fwd_nb<2, false>(map, d_jobs, grid, with_ll, s);
+    case 3: return fwd_nb<3, false>(map, d_jobs, grid, with_ll, s);
+    case 4: return fwd_nb<4, false>(map, d_jobs, grid, with_ll, s);
+    case 5: return fwd_nb<5, false>(map, d_jobs, grid, with_ll, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int NB>
+template <int NB, bool RIGID>
 static hipError_t adj_nb(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, size_t lds, bool split,
                          bool full, hipStream_t s) {
   if (split)
-    hipLaunchKernelGGL((planar_adjoint_kernel<NB, true>), dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws,
+    hipLaunchKernelGGL((planar_adjoint_kernel<NB, true, RIGID>), dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws,
                        full ? 1 : 0);
   else
-    hipLaunchKernelGGL((planar_adjoint_kernel<NB, false>), dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws,
-                       full ? 1 : 0);
+    hipLaunchKernelGGL((planar_adjoint_kernel<NB, false, RIGID>), dim3(grid), dim3(kWave), lds, s, map, d_jobs,
+                       ws, full ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_planar_adjoint(const JobMap& map, int nb, const pds_job* d_jobs, char* ws, int grid, bool split,
-                                 bool full, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_planar_adjoint(const JobMap& map, int nb, bool rigid, const pds_job* d_jobs, char* ws, int grid,
+                                 bool split, bool full, size_t lds_bytes, hipStream_t s) {
+  if (rigid) {
+    switch (nb) {
+      case 1: return adj_nb<1, true>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+      case 2: return adj_nb<2, true>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (nb) {
-    case 1: return adj_nb<1>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 2: return adj_nb<2>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 3: return adj_nb<3>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 4: return adj_nb<4>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 5: return adj_nb<5>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 1: return adj_nb<1, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 2: return adj_nb<2, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 3: return adj_nb<3, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 4: return adj_nb<4, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 5: return adj_nb<5, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -717,18 +846,20 @@ int planar_seg_len(int h) { return seg_len_of(h); }
 // scalar (add, sub, mul, div each 1; negation 0; sin/cos tallied apart).
 // ---------------------------------------------------------------------------
 namespace {
-template <int NB>
+template <int NB, bool RIGID>
 void count_planar(double* fwd, double* rev, double* transc) {
+  constexpr int MP = PlanarParams<NB, RIGID>::M;
   Planar<NB, Counted> P;
-  Counted q[NB], qd[NB], qb[NB], qdb[NB], mb[NB], lb[NB];
+  Counted q[NB], qd[NB], qb[NB], qdb[NB], thb[MP];
   for (int i = 0; i < NB; ++i) {
     P.m[i] = Counted(1.0f); P.l[i] = Counted(1.0f); P.b[i] = Counted(0.05f);
+    P.I[i] = Counted(0.01f); P.cx[i] = Counted(0.02f); P.cy[i] = Counted(-0.1f); P.L[i] = Counted(0.2f);
     q[i] = Counted(0.3f); qd[i] = Counted(0.1f); qb[i] = Counted(1.f); qdb[i] = Counted(1.f);
   }
   P.gx = Counted(0.f); P.gy = Counted(-9.81f);
   g_tally = FlopTally();
   Tape<NB, Counted> T;
-  aba<NB, Counted>(P, q, qd, T);
+  aba<NB, Counted, RIGID>(P, q, qd, T);
   for (int i = 0; i < NB; ++i) {  // Euler update
     qd[i] = qd[i] + Counted(0.01f) * T.qdd[i];
     q[i] = q[i] + Counted(0.01f) * qd[i];
@@ -737,9 +868,9 @@ void count_planar(double* fwd, double* rev, double* transc) {
   *fwd = g_tally.flops + 4.0 * NB + 1.0;
   *transc = g_tally.transc;
   g_tally = FlopTally();
-  step_rev<NB, Counted>(P, Counted(0.01f), qd, T, qb, qdb, mb, lb);
+  step_rev<NB, Counted, RIGID>(P, Counted(0.01f), qd, T, qb, qdb, thb);
   // observation seed r w per component; FP64 accumulation of the M parameter adjoints
-  *rev = g_tally.flops + 4.0 * NB + 2.0 * NB;
+  *rev = g_tally.flops + 4.0 * NB + (double)MP;
 }
 }  // namespace
 
@@ -750,13 +881,21 @@ extern "C" int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_s
     count_arm_flops(fwd_step, rev_step, transcendental);
     return PDS_OK;
   }
+  if (model == PDS_MODEL_PLANAR_RIGID) {
+    switch (n_dof) {
+      case 1: count_planar<1, true>(fwd_step, rev_step, transcendental); break;
+      case 2: count_planar<2, true>(fwd_step, rev_step, transcendental); break;
+      default: return PDS_EUNSUPPORTED;
+    }
+    return PDS_OK;
+  }
   if (model != PDS_MODEL_PLANAR) return PDS_EINVAL;
   switch (n_dof) {
-    case 1: count_planar<1>(fwd_step, rev_step, transcendental); break;
-    case 2: count_planar<2>(fwd_step, rev_step, transcendental); break;
-    case 3: count_planar<3>(fwd_step, rev_step, transcendental); break;
-    case 4: count_planar<4>(fwd_step, rev_step, transcendental); break;
-    case 5: count_planar<5>(fwd_step, rev_step, transcendental); break;
+    case 1: count_planar<1, false>(fwd_step, rev_step, transcendental); break;
+    case 2: count_planar<2, false>(fwd_step, rev_step, transcendental); break;
+    case 3: count_planar<3, false>(fwd_step, rev_step, transcendental); break;
+    case 4: count_planar<4, false>(fwd_step, rev_step, transcendental); break;
+    case 5: count_planar<5, false>(fwd_step, rev_step, transcendental); break;
     default: return PDS_EUNSUPPORTED;
   }
   return PDS_OK;

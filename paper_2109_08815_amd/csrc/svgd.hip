@@ -1082,6 +1082,7 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
       J.adam_v[a] = vv;
       xn = x - J.lr_theta[m] * (mm / bc1) / (sqrtf(vv / bc2) + eps);
     }
+    if (J.limits == PDS_LIMITS_PROJECT) xn = fminf(fmaxf(xn, lo), hi);
     J.theta[t] = xn;
     J.lam_lim[t] += J.eps_lam * g;
     if ((xn < lo || xn > hi) && J.flags) atomicOr(&J.flags[i], 4);

@@ -20,10 +20,13 @@ LIB_PATH = os.path.join(_HERE, "libpds.so")
 PDS_OK = 0
 PDS_MODEL_PLANAR = 1
 PDS_MODEL_ARM = 2
+PDS_MODEL_PLANAR_RIGID = 3
 PDS_COMBINE_SUM = 0
 PDS_COMBINE_PROD = 1
 PDS_LIK_MDMM = 0
 PDS_LIK_DEFECT = 1
+PDS_LIMITS_SOFT = 0
+PDS_LIMITS_PROJECT = 1
 PDS_OPT_SGD = 0
 PDS_OPT_ADAM = 1
 PDS_CALL_FORWARD, PDS_CALL_LOGLIK, PDS_CALL_ADJOINT, PDS_CALL_PHI, PDS_CALL_STEP, PDS_CALL_ALL = range(6)
@@ -38,7 +41,8 @@ class PdsJob(C.Structure):
     _fields_ = [
         ("model", C.c_int32), ("n_dof", C.c_int32), ("M", C.c_int32), ("d_x", C.c_int32),
         ("N", C.c_int32), ("K", C.c_int32), ("T", C.c_int32), ("n_s", C.c_int32), ("h", C.c_int32),
-        ("combine", C.c_int32), ("lik", C.c_int32), ("dt", C.c_float), ("sigma_def", C.c_float), ("c", C.c_float),
+        ("combine", C.c_int32), ("lik", C.c_int32), ("limits", C.c_int32),
+        ("dt", C.c_float), ("sigma_def", C.c_float), ("c", C.c_float),
         ("eps_lam", C.c_float),
         ("consts", _f), ("lo", _f), ("hi", _f), ("rho", _f), ("w_x", _f), ("u", _f), ("lr_theta", _f),
         ("lr_S", _f), ("s0", _f), ("obs", _f), ("seed_logp", _f), ("seed_gdef", _f),
@@ -123,6 +127,8 @@ def model_consts(pb):
                     a["kp"][i], a["kd"][i], a["qc"][i], a["amp"][i], a["omega"][i], a["phase"][i]]
         out += [a["flange_d"], pb.damping[7], a["box_m"], *a["box_c"], *a["box_I"], a["pm_m"], a["pm_z"]]
         return PDS_MODEL_ARM, np.asarray(out, dtype=np.float64)
+    if pb.kind == 4:
+        return PDS_MODEL_PLANAR_RIGID, np.asarray(pb.gravity[:2], dtype=np.float64)
     raise PdsError("no GPU model for problem kind %d" % pb.kind)
 
 
@@ -177,6 +183,7 @@ class Job:
         j.model, j.n_dof, j.M, j.d_x = self.model, pb.n_dof, pb.M, pb.d_x
         j.N, j.K, j.T, j.n_s, j.h, j.combine = self.N, pb.K, pb.T, pb.n_s, pb.h, pb.combine
         j.lik = int(getattr(pb, "lik", PDS_LIK_MDMM))
+        j.limits = int(getattr(pb, "limits", PDS_LIMITS_SOFT))
         j.dt, j.sigma_def, j.c, j.eps_lam = pb.dt, pb.sigma_def, pb.c, pb.eps_lam
         for name in ("consts", "lo", "hi", "rho", "w_x", "u", "lr_theta", "lr_S", "s0", "obs", "seed_logp",
                      "seed_gdef", "theta", "S", "lam_lim", "lam_def", "adam_m", "adam_v", "end_states", "traj",
@@ -314,6 +321,7 @@ def shape_struct(pb, N=None) -> PdsJob:
     j.N = pb.N if N is None else N
     j.K, j.T, j.n_s, j.h, j.combine = pb.K, pb.T, pb.n_s, pb.h, pb.combine
     j.lik = int(getattr(pb, "lik", PDS_LIK_MDMM))
+    j.limits = int(getattr(pb, "limits", PDS_LIMITS_SOFT))
     j.dt, j.sigma_def, j.c, j.eps_lam = pb.dt, pb.sigma_def, pb.c, pb.eps_lam
     return j
 

@@ -19,6 +19,11 @@ synthetic stand-ins for the recordings the paper used, Sec. IV):
   hinge that holds two 0.2 kg point masses at unknown in-plane positions
   theta = (x_a, y_a, x_b, y_b)                                     (M = 4);
   the synthetic analogue of the arm-and-box experiment of Sec. IV-C
+* ``rigid2`` double pendulum with rigid links, the 11 parameters of the
+  paper's physical double pendulum (Sec. IV-B): per link mass, inertia
+  about the centre of mass, centre of mass (x, y) and joint friction, plus
+  the length of link 2, inside that table's bounds; observes the whole
+  state (q, qd) as that experiment does                             (M = 11)
 * ``toy`` one prismatic unit mass driven by force theta0 (+ theta1 * time),
   the linear-Gaussian check problem                                 (M = 1, 2)
 
@@ -37,11 +42,14 @@ import numpy as np
 KIND_PLANAR = 1
 KIND_ARM = 2
 KIND_TOY = 3
+KIND_PLANAR_RIGID = 4
 
 COMBINE_SUM = 0
 COMBINE_PROD = 1
 LIK_MDMM = 0    # defects as MDMM equality constraints (CSVGD)
 LIK_DEFECT = 1  # defects as Gaussian factors inside the multiple-shooting likelihood
+LIMITS_SOFT = 0     # parameter limits through MDMM only
+LIMITS_PROJECT = 1  # ... and theta clamped into [lo, hi] after every step
 
 
 @dataclass
@@ -81,6 +89,7 @@ class Problem:
     eps_lam: float
     seed: int
     lik: int = 0                  # LIK_MDMM or LIK_DEFECT (how the defects enter)
+    limits: int = 0               # LIMITS_SOFT or LIMITS_PROJECT
     extra: dict = field(default_factory=dict)
 
     @property
@@ -93,6 +102,7 @@ CONFIGS = {
     "c1": dict(family="pendulum", N=32, K=1, T=200, n_s=4, dt=0.01, sigma_obs=0.01),
     "c2": dict(family="double", N=256, K=4, T=400, n_s=10, dt=0.005, sigma_obs=0.01),
     "c3": dict(family="chain5", N=1024, K=8, T=1000, n_s=20, dt=0.002, sigma_obs=0.02),
+    "rigid2": dict(family="rigid", N=256, K=4, T=400, n_s=10, dt=0.005, sigma_obs=0.01),
     "c4": dict(family="arm", N=2048, K=1, T=1500, n_s=30, dt=1.0 / 240.0, sigma_obs=0.01),
 }
 
@@ -138,13 +148,14 @@ def _arm_constants(rng: np.random.Generator) -> dict:
 
 def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem:
     """Build a seeded problem.  ``over`` overrides N, K, T, n_s, dt, sigma_obs,
-    sigma_def, c, combine, lik, n_dof (planar families), M (toy)."""
+    sigma_def, c, combine, lik, limits, n_dof (planar families), full_state (planar
+    families: observe (q, qd) instead of q), M (toy)."""
     base = dict(CONFIGS.get(config, {}))
     if config == "toy":
         base = dict(family="toy", N=256, K=1, T=50, n_s=1, dt=0.1, sigma_obs=0.5)
     base.update({k: v for k, v in over.items() if k in ("N", "K", "T", "n_s", "dt", "sigma_obs")})
     fam = base["family"]
-    idx = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "toy": 9}.get(config, 7)
+    idx = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "rigid2": 5, "toy": 9}.get(config, 7)
     if seed is None:
         seed = 1000 * idx
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -163,11 +174,28 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         if fam == "chain5" or over.get("damped", False):
             damping[:n] = rng.uniform(0.0, 0.1, n)
         gravity = np.array([0.0, -9.81, 0.0])
-        d_x = n
-        obs_index = np.arange(n)
+        d_x = 2 * n if over.get("full_state", False) else n
+        obs_index = np.arange(d_x)
         qmax = np.pi if fam == "double" else np.pi / 2
         s0 = np.zeros((K, 2 * n))
         s0[:, :n] = rng.uniform(-qmax, qmax, (K, n))
+    elif fam == "rigid":
+        kind = KIND_PLANAR_RIGID
+        n = int(over.get("n_dof", 2))
+        if n not in (1, 2):
+            raise ValueError("the rigid planar family has 1 or 2 links")
+        M = 6 * n - 1
+        # Bounds of the Sec. IV-B table: mass, inertia, COM x, COM y, friction
+        # per link, the length of link 2 ahead of its block.
+        link_lo, link_hi = [0.05, 0.002, -0.2, -0.2, 0.0], [0.5, 1.0, 0.2, 0.2, 0.5]
+        lo = np.array(link_lo + ([0.08] + link_lo) * (n - 1))
+        hi = np.array(link_hi + ([0.3] + link_hi) * (n - 1))
+        gravity = np.array([0.0, -9.81, 0.0])
+        # the whole state is observed, as in the paper's pendulum experiment
+        d_x = 2 * n if over.get("full_state", True) else n
+        obs_index = np.arange(d_x)
+        s0 = np.zeros((K, 2 * n))
+        s0[:, :n] = rng.uniform(-np.pi / 2, np.pi / 2, (K, n))
     elif fam == "arm":
         kind = KIND_ARM
         n = 8
@@ -201,6 +229,11 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
     if over.get("same_theta", True) and fam != "toy":
         theta_true = np.tile(theta_true[:1], (K, 1))
     noise = rng.normal(0.0, sigma_obs, (K, T, d_x))
+    # Adam moves every coordinate by about lr per iteration whatever the
+    # gradient's size, and the limits act only softly (MDMM); the rigid
+    # links' inertias sit near their lower bound (0.002 of a 1.0 range), so
+    # that family takes smaller steps to keep them positive.
+    lr_frac = 1e-3 if fam == "rigid" else 1e-2
     particles = sobol_particles(N, lo, hi)
     d_s = 2 * n
     u = np.ones(d_s)
@@ -211,8 +244,11 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         sigma_def=float(over.get("sigma_def", 0.1)), c=float(over.get("c", 1.0)),
         combine=int(over.get("combine", COMBINE_SUM)), lo=lo, hi=hi, theta_true=theta_true,
         s0=s0, noise=noise, particles=particles, w_x=np.full(d_x, 1.0 / sigma_obs), u=u,
-        rho=hi - lo, lr_theta=1e-2 * (hi - lo), lr_S=lr_S, eps_lam=1e-2, seed=seed,
+        rho=hi - lo, lr_theta=lr_frac * (hi - lo), lr_S=lr_S, eps_lam=1e-2, seed=seed,
         lik=int(over.get("lik", LIK_MDMM)),
+        # rigid links: masses and inertias must stay positive, and their
+        # lower limits sit within one Adam step of zero
+        limits=int(over.get("limits", LIMITS_PROJECT if fam == "rigid" else LIMITS_SOFT)),
     )
 
 

@@ -73,6 +73,7 @@ def _job(**kw):
     (dict(T=21), -1), (dict(N=0), -1), (dict(dt=0.0), -1), (dict(sigma_def=-1.0), -1),
     (dict(n_dof=6, M=12, d_x=6), -2), (dict(model=2), -1), (dict(model=7), -1), (dict(M=3), -1),
     (dict(combine=5), -1), (dict(N=32769), -2),
+    (dict(model=3), -1), (dict(model=3, n_dof=3, M=17, d_x=3), -2), (dict(d_x=3), -1), (dict(limits=2), -1),
 ])
 def test_invalid_jobs_rejected_on_host(bad, code):
     lib = L.lib()
@@ -119,3 +120,8 @@ def test_algorithmic_flop_counts():
     assert t == 2 * 8 + 2 * 7
     assert f > 1000 and r > 1000
     assert L.algorithmic_flops(L.PDS_MODEL_ARM, 8) == (f, r, t)
+    # rigid links: the same sin/cos per joint, more work per link than point masses
+    for n in (1, 2):
+        rf, rr, rt = L.algorithmic_flops(L.PDS_MODEL_PLANAR_RIGID, n)
+        assert rt == 2.0 * n
+        assert rf > planar[n - 1][0] and rr > planar[n - 1][1]

@@ -11,7 +11,12 @@ Tolerances (FP32 arithmetic on the GPU, FP64 in the oracle):
   (w_k d l_kj / d theta for g_obs, seed_kj d g_kj / d theta for g_con); for
   a gradient without cancellation this is ||g_ref||_2, and near an optimum,
   where the window terms cancel, it is the error FP32 rounding of each term
-  implies.  S_dot: per particle ||dS_gpu - dS_ref|| / ||dS_ref|| <= 1e-3;
+  implies.  A g_con term is linear in its defect vector e = (S - s_end) u
+  twice (through d g_def and through lam + c g_def), so the relative error
+  the GPU's FP32 end state leaves in e (measured per unit, delta_kj) enters
+  it up to three times: term_kj is weighted by 1 + 3 delta_kj / 1e-3.  This
+  matters where a defect is small against the state it is the difference
+  of.  S_dot: per particle ||dS_gpu - dS_ref|| / ||dS_ref|| <= 1e-3;
 * window log-likelihoods: the error the state tolerance implies,
   sum_t,d |r| w * 1e-4 * max(||x||_inf, 1e-6), plus 1e-9 |l| for the FP64
   sums (r = residual, w = 1/sigma_obs);
@@ -82,15 +87,31 @@ def normwise(a, b):
     return np.linalg.norm(a - b, axis=1) / den
 
 
-def grad_err(g_gpu, ref, kind):
-    """Per-particle error ratio against the summed per-window term norms."""
+def defect_rel_err(pb, job, ref, S, sel=None):
+    """Relative error of each defect vector (S - s_end) u that the GPU's
+    FP32 end states leave, per (particle, trajectory, window)."""
+    es = np64(job.end_states)
+    if sel is not None:
+        es, S = es[sel], S[sel]
+    e_g = (S - es[:, :, : pb.n_s - 1]) * pb.u
+    e_r = (S - ref["end_states"][:, :, : pb.n_s - 1]) * pb.u
+    return np.linalg.norm(e_g - e_r, axis=3) / np.maximum(np.linalg.norm(e_r, axis=3), 1e-30)
+
+
+def grad_err(g_gpu, ref, kind, defect_err=None):
+    """Per-particle error ratio against the summed per-window term norms
+    (con terms weighted by their defects' measured relative error)."""
     if kind == "obs":
         terms = ref["wk"][:, :, None, None] * ref["dl_dtheta_unit"]
         g_ref = ref["g_obs"]
     else:
         terms = ref["dcon_dtheta_unit"]
         g_ref = ref["g_con"]
-    scale = np.linalg.norm(terms, axis=3).sum(axis=(1, 2))
+    tn = np.linalg.norm(terms, axis=3)
+    if kind == "con" and defect_err is not None:
+        tn = tn.copy()
+        tn[:, :, : defect_err.shape[2]] *= 1.0 + 3.0 * defect_err / 1e-3
+    scale = tn.sum(axis=(1, 2))
     err = np.linalg.norm(g_gpu - g_ref, axis=1)
     return err / np.maximum(scale, 1e-30)
 
@@ -113,6 +134,16 @@ CASES = [
     ("c2", dict(N=40, K=3, T=80, n_s=4, combine=synth.COMBINE_PROD)),
     ("c2", dict(N=70, K=3, T=80, n_s=4, lik=synth.LIK_DEFECT)),
     ("c3", dict(N=64, K=2, T=150, n_s=3, lik=synth.LIK_DEFECT, combine=synth.COMBINE_PROD)),
+    # rigid links with the 11 parameters of the physical double pendulum
+    # (Sec. IV-B), whole state observed, ragged; one rigid link with long
+    # windows (two lanes per unit); defect densities inside p_ms
+    ("rigid2", dict(N=70, K=3, T=80, n_s=4)),
+    ("rigid2", dict(n_dof=1, N=64, K=1, T=800, n_s=2)),
+    ("rigid2", dict(N=40, K=2, T=120, n_s=3, lik=synth.LIK_DEFECT)),
+    # point masses observed in the whole state (q, qd); rigid links
+    # observed in q only
+    ("c2", dict(N=70, K=2, T=80, n_s=4, full_state=True)),
+    ("rigid2", dict(N=33, K=2, T=80, n_s=2, full_state=False)),
 ]
 
 
@@ -146,21 +177,23 @@ def test_adjoint_gradients(orc, cfg, over):
     ref = orc.gradient(pb, obs, st, per_unit=True)
     assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
     if pb.n_s > 1:
-        assert grad_err(np64(job.g_con), ref, "con").max() <= 1e-3
+        assert grad_err(np64(job.g_con), ref, "con", defect_rel_err(pb, job, ref, st.S)).max() <= 1e-3
         assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
     assert np.all(np64(job.flags) == 0)
 
 
-def test_adjoint_full_c2_sampled(orc):
+@pytest.mark.parametrize("cfg", ["c2", "rigid2"])
+def test_adjoint_full_c2_sampled(orc, cfg):
     """Headline double-pendulum size (N=256, K=4, T=400, 10 windows), the
-    launch the benchmark times; every particle's forward quantities and a
-    sample of particles' gradients against the oracle."""
-    pb, obs, st, job, b = make_case(orc, "c2", perturb_S=0.01, lam=True)
+    launch the benchmark times (point-mass links), and the rigid-link model
+    at the same size; every particle's forward quantities and a sample of
+    particles' gradients against the oracle."""
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01, lam=True)
     L.sim_batch_adjoint(b)
     sel = np.arange(0, pb.N, 17)
     ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
     assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
-    assert grad_err(np64(job.g_con)[sel], ref, "con").max() <= 1e-3
+    assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
     assert normwise(np64(job.S_dot)[sel], ref["S_dot"]).max() <= 1e-3
     fwd = orc.forward(pb, obs, st, traj=True)
     tol = ll_tolerance(pb, obs, fwd["traj"], fwd["ll_win"])
@@ -176,7 +209,7 @@ def test_full_c3_sampled(orc):
     sel = np.array([0, 1, 63, 64, 511, 1000, 1023])
     ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
     assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
-    assert grad_err(np64(job.g_con)[sel], ref, "con").max() <= 1e-3
+    assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
     assert normwise(np64(job.S_dot)[sel], ref["S_dot"]).max() <= 1e-3
     es_ref = ref["end_states"]
     es = np64(job.end_states)[sel]
@@ -288,11 +321,13 @@ def test_bandwidth_exact_with_heavy_ties(orc, groups):
     assert abs(_bandwidth_gpu(pb, theta) - h_ref) <= 1e-15 * h_ref
 
 
-@pytest.mark.parametrize("optimizer,lik", [(L.PDS_OPT_SGD, synth.LIK_MDMM), (L.PDS_OPT_ADAM, synth.LIK_MDMM),
-                                           (L.PDS_OPT_ADAM, synth.LIK_DEFECT)])
-def test_step_parity(orc, optimizer, lik):
-    print_case("step", optimizer, lik)
-    pb = f32_problem(synth.make_problem("c2", N=70, K=2, T=80, n_s=4, lik=lik))
+@pytest.mark.parametrize("optimizer,lik,limits", [(L.PDS_OPT_SGD, synth.LIK_MDMM, synth.LIMITS_SOFT),
+                                                  (L.PDS_OPT_ADAM, synth.LIK_MDMM, synth.LIMITS_SOFT),
+                                                  (L.PDS_OPT_ADAM, synth.LIK_DEFECT, synth.LIMITS_SOFT),
+                                                  (L.PDS_OPT_ADAM, synth.LIK_MDMM, synth.LIMITS_PROJECT)])
+def test_step_parity(orc, optimizer, lik, limits):
+    print_case("step", optimizer, lik, limits)
+    pb = f32_problem(synth.make_problem("c2", N=70, K=2, T=80, n_s=4, lik=lik, limits=limits))
     rng = np.random.default_rng(5)
     N, K, ns, ds, M = pb.N, pb.K, pb.n_s, pb.d_s, pb.M
     theta = r32(pb.lo - 0.2 + rng.uniform(size=(N, M)) * (pb.hi - pb.lo + 0.4))  # some outside the limits
@@ -320,13 +355,17 @@ def test_step_parity(orc, optimizer, lik):
     fl = np64(job.flags).astype(int)
     outside = ((st.theta < pb.lo) | (st.theta > pb.hi)).any(axis=1)
     assert np.all(((fl & 4) != 0) == outside)
+    if limits == synth.LIMITS_PROJECT:
+        got = np64(job.theta).reshape(st.theta.shape)
+        assert np.all((got >= pb.lo) & (got <= pb.hi)) and not outside.any()
 
 
-@pytest.mark.parametrize("lik", [synth.LIK_MDMM, synth.LIK_DEFECT])
-def test_csvgd_iteration_sgd(orc, lik):
+@pytest.mark.parametrize("cfg,lik", [("c2", synth.LIK_MDMM), ("c2", synth.LIK_DEFECT), ("rigid2", synth.LIK_MDMM)])
+def test_csvgd_iteration_sgd(orc, cfg, lik):
     """One full iteration (adjoint -> phi -> step) from identical inputs,
-    with the defects as constraints (CSVGD) or inside p_ms."""
-    pb, obs, st, job, b = make_case(orc, "c2", perturb_S=0.01, lam=True, N=70, K=3, lik=lik)
+    with the defects as constraints (CSVGD) or inside p_ms; point-mass and
+    rigid links (M = 11)."""
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01, lam=True, N=70, K=3, lik=lik)
     th0 = st.theta.copy()
     S0 = st.S.copy()
     L.csvgd_iteration(b, 1, L.PDS_OPT_SGD)
@@ -341,7 +380,8 @@ def test_batch_matches_single_jobs_bitwise(orc):
     gives alone (fixed-order per-job reductions)."""
     cases = [make_case(orc, "c2", perturb_S=0.01, lam=True, N=70, K=3),
              make_case(orc, "c1", perturb_S=0.01, lam=True, N=40),
-             make_case(orc, "c3", perturb_S=0.01, lam=True, N=33, K=2, T=100, n_s=2)]
+             make_case(orc, "c3", perturb_S=0.01, lam=True, N=33, K=2, T=100, n_s=2),
+             make_case(orc, "rigid2", perturb_S=0.01, lam=True, N=50, K=2, T=80, n_s=2)]
     solo = []
     for pb, obs, st, job, b in cases:
         L.csvgd_iteration(b, 1)
@@ -523,7 +563,7 @@ def test_arm_adjoint_gradients(orc, over):
     L.sim_batch_adjoint(b)
     ref = orc.gradient(pb, obs, st, per_unit=True)
     assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
-    assert grad_err(np64(job.g_con), ref, "con").max() <= 1e-3
+    assert grad_err(np64(job.g_con), ref, "con", defect_rel_err(pb, job, ref, st.S)).max() <= 1e-3
     assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
     assert np.all(np64(job.flags) == 0)
 
@@ -531,14 +571,15 @@ def test_arm_adjoint_gradients(orc, over):
 @pytest.mark.parametrize("cfg,over", [("c2", dict(N=16, K=2, T=40, n_s=2)), ("c3", dict(N=16, K=1, T=60, n_s=3)),
                                       ("c4", dict(N=8, T=60, n_s=2)),
                                       ("c2", dict(N=16, K=2, T=60, n_s=3, lik=synth.LIK_DEFECT)),
-                                      ("c4", dict(N=8, K=2, T=60, n_s=2, lik=synth.LIK_DEFECT))])
+                                      ("c4", dict(N=8, K=2, T=60, n_s=2, lik=synth.LIK_DEFECT)),
+                                      ("rigid2", dict(N=16, K=2, T=40, n_s=2))])
 def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
     """The reverse-mode gradients against central differences of the GPU's
     own forward (FP32 states, FP64 sums), along a random direction in theta
     per particle: d log p / d theta (g_obs) and d Phi / d theta (g_con) with
     Phi = sum_j lam_j g_j + (c / 2) g_j^2.  FP32 rounding noise limits the
-    differences, so the best of three step sizes must agree to 5e-3 of
-    |g| |v|."""
+    differences from below and curvature (Phi is quartic in the defect) from
+    above, so the best of five step sizes must agree to 5e-3 of |g| |v|."""
     print_case("fd", cfg, over)
     pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01, lam=True, **over)
     L.sim_batch_adjoint(b)
@@ -565,7 +606,7 @@ def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
     # how the random direction happens to align with the gradient)
     norm_o = np.maximum(np.linalg.norm(g_obs, axis=1) * np.linalg.norm(v, axis=1), 1e-12)
     norm_c = np.maximum(np.linalg.norm(g_con, axis=1) * np.linalg.norm(v, axis=1), 1e-12)
-    for rel in (1e-2, 3e-3, 1e-3):
+    for rel in (1e-2, 3e-3, 1e-3, 3e-4, 1e-4):
         lp_p, ph_p = evaluate(r32(th0 + rel * v))
         lp_m, ph_m = evaluate(r32(th0 - rel * v))
         step = (r32(th0 + rel * v) - r32(th0 - rel * v))  # the step actually taken in FP32

@@ -24,7 +24,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # Dynamics (App. B-A: ABA forward dynamics + semi-implicit Euler)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "toy"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "toy"])
 def test_aba_equals_crba_rnea(orc, cfg):
     """ABA's q_dd equals H^{-1}(tau - C) from CRBA + RNEA (independent algorithms)."""
     pb = synth.make_problem(cfg, N=4, K=1, T=10, n_s=1)
@@ -77,6 +77,91 @@ def test_double_pendulum_lagrangian(orc):
         ref = np.array([a1, a2 - a1])
         qdd = orc.aba(pb, [m1, m2, l1, l2], q, qd, [0.0, 0.0])
         assert np.max(np.abs(qdd - ref)) <= 1e-11 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_rigid_link_compound_pendulum(orc):
+    """One rigid link with its centre of mass at (cx, cy) in the link frame:
+    (I + m |c|^2) q_dd = -m g (cx cos q - cy sin q) - b q_d (potential
+    m g y_com with y_com = cx sin q + cy cos q)."""
+    pb = synth.make_problem("rigid2", n_dof=1, N=4, K=1, T=10, n_s=1)
+    assert pb.M == 5
+    rng = np.random.default_rng(13)
+    g = 9.81
+    for _ in range(20):
+        th = pb.lo + rng.uniform(size=5) * (pb.hi - pb.lo)
+        m, I, cx, cy, b = th
+        q, qd = rng.uniform(-3, 3), rng.uniform(-3, 3)
+        tau = orc.tau(pb, th, 0.0, [q], [qd])
+        qdd = orc.aba(pb, th, [q], [qd], tau)[0]
+        ref = (-m * g * (cx * math.cos(q) - cy * math.sin(q)) - b * qd) / (I + m * (cx * cx + cy * cy))
+        assert abs(qdd - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def _rigid_double_lagrange():
+    """Euler-Lagrange equations of two rigid planar links, derived
+    symbolically from their kinetic and potential energy: returns
+    f(q, qd, theta) -> q_dd with joint friction as the generalised force."""
+    sp = pytest.importorskip("sympy")
+    q1, q2, w1, w2 = sp.symbols("q1 q2 w1 w2")
+    m1, I1, cx1, cy1, b1, L2, m2, I2, cx2, cy2, b2 = sp.symbols("m1 I1 cx1 cy1 b1 L2 m2 I2 cx2 cy2 b2")
+    g = sp.Rational(981, 100)
+
+    def rot(a, v):
+        return sp.Matrix([sp.cos(a) * v[0] - sp.sin(a) * v[1], sp.sin(a) * v[0] + sp.cos(a) * v[1]])
+
+    q, w = sp.Matrix([q1, q2]), sp.Matrix([w1, w2])
+    p1 = rot(q1, (cx1, cy1))
+    p2 = rot(q1, (0, -L2)) + rot(q1 + q2, (cx2, cy2))
+    v1, v2 = p1.jacobian(q) * w, p2.jacobian(q) * w
+    Tk = (m1 * v1.dot(v1) + I1 * w1 ** 2 + m2 * v2.dot(v2) + I2 * (w1 + w2) ** 2) / 2
+    V = g * (m1 * p1[1] + m2 * p2[1])
+    Lg = Tk - V
+    dL_dw = sp.Matrix([sp.diff(Lg, x) for x in (w1, w2)])
+    H = dL_dw.jacobian(w)
+    h = dL_dw.jacobian(q) * w - sp.Matrix([sp.diff(Lg, x) for x in (q1, q2)])
+    fric = sp.Matrix([-b1 * w1, -b2 * w2])
+    args = (q1, q2, w1, w2, m1, I1, cx1, cy1, b1, L2, m2, I2, cx2, cy2, b2)
+    fH, fr = sp.lambdify(args, H.tolist(), "math"), sp.lambdify(args, (fric - h).tolist(), "math")
+
+    def f(qv, qdv, th):
+        a = tuple(qv) + tuple(qdv) + tuple(th)
+        return np.linalg.solve(np.array(fH(*a), dtype=float), np.array(fr(*a), dtype=float).ravel())
+
+    return f
+
+
+def test_rigid_double_pendulum_lagrangian(orc):
+    """Rigid-link double pendulum (11 parameters of Sec. IV-B): ABA with the
+    friction torques equals the Euler-Lagrange equations derived
+    symbolically from the links' energies."""
+    f = _rigid_double_lagrange()
+    pb = synth.make_problem("rigid2", N=4, K=1, T=10, n_s=1)
+    assert pb.M == 11
+    rng = np.random.default_rng(19)
+    for _ in range(20):
+        th = pb.lo + rng.uniform(size=11) * (pb.hi - pb.lo)
+        q, qd = rng.uniform(-3, 3, 2), rng.uniform(-3, 3, 2)
+        tau = orc.tau(pb, th, 0.0, q, qd)
+        qdd = orc.aba(pb, th, q, qd, tau)
+        ref = f(q, qd, th)
+        assert np.max(np.abs(qdd - ref)) <= 1e-10 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_rigid_chain_reduces_to_point_masses(orc):
+    """With zero inertia, the centre of mass at (0, -l_i) and joint 2 at
+    the tip of link 1, the rigid chain is the point-mass chain."""
+    rig = synth.make_problem("rigid2", N=4, K=1, T=10, n_s=1)
+    pm = synth.make_problem("c2", damped=True, N=4, K=1, T=10, n_s=1)
+    b = pm.damping[:2]
+    rng = np.random.default_rng(23)
+    for _ in range(10):
+        m1, m2, l1, l2 = rng.uniform(0.5, 2.0, 4)
+        th_pm = [m1, m2, l1, l2]
+        th_rig = [m1, 0.0, 0.0, -l1, b[0], l1, m2, 0.0, 0.0, -l2, b[1]]
+        q, qd = rng.uniform(-3, 3, 2), rng.uniform(-3, 3, 2)
+        a = orc.aba(pm, th_pm, q, qd, orc.tau(pm, th_pm, 0.0, q, qd))
+        r = orc.aba(rig, th_rig, q, qd, orc.tau(rig, th_rig, 0.0, q, qd))
+        assert np.max(np.abs(a - r)) <= 1e-12 * max(1.0, np.max(np.abs(a)))
 
 
 def _pendulum(orc, dt, l=1.0):
@@ -198,7 +283,7 @@ def _setup(orc, cfg, **kw):
     return pb, obs, st
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2"])
 def test_multiple_shooting_on_trajectory_equals_single(orc, cfg):
     """Shooting states taken from the single-shooting rollout give zero
     defects, and the window log-likelihoods sum to the single-shooting one."""
@@ -267,7 +352,7 @@ def _total_phi(pb, f, lam_def):
     return np.sum(lam_def * g + 0.5 * pb.c * g * g, axis=(1, 2))
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2"])
 def test_dual_gradients_match_finite_differences(orc, cfg):
     """g_obs = d log p / d theta, g_con = d Phi / d theta and S_dot =
     d (log p - Phi) / d S, with Phi = sum (lam g + c/2 g^2), by central
@@ -308,7 +393,7 @@ def test_dual_gradients_match_finite_differences(orc, cfg):
         assert np.linalg.norm(g["S_dot"][i] - sd) <= 1e-6 * np.linalg.norm(sd)
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c4"])
+@pytest.mark.parametrize("cfg", ["c2", "c4", "rigid2"])
 def test_defect_density_in_likelihood_gradients_match_finite_differences(orc, cfg):
     """Defects inside p_ms (eq. ms_likelihood): g_obs = d log p_ms / d theta
     and S_dot = d log p_ms / d S by central differences through the whole
