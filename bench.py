@@ -38,6 +38,7 @@ TRAFFIC_PROFILES = {
     "c2": ("planar_adjoint_c2_traffic.md", "planar.hip"),
     "c3": ("planar_adjoint_c3_traffic.md", "planar.hip"),
     "c4": ("arm_adjoint_c4_traffic.md", "arm.hip"),
+    "rigid2": ("planar_adjoint_rigid2_traffic.md", "planar.hip"),
 }
 
 
