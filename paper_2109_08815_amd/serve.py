@@ -366,14 +366,17 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--seed", type=int, default=5000)
     ap.add_argument("--no-sequential", action="store_true")
+    ap.add_argument("--limits", choices=["soft", "project"], default="soft",
+                    help="parameter limits: MDMM only (the paper's), or also clamped into the box each step")
     args = ap.parse_args(argv)
+    limits = synth.LIMITS_PROJECT if args.limits == "project" else synth.LIMITS_SOFT
     import torch
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     eng = Engine(budget_bytes=int(args.budget_gib * (1 << 30)), graph_iters=args.graph)
-    base = synth.serving_trace(args.jobs, seed=args.seed, iterations=args.iterations)
+    base = synth.serving_trace(args.jobs, seed=args.seed, iterations=args.iterations, limits=limits)
     # warm-up: library load, kernels, allocator
     eng.run_batched(base[:2])
     closed = eng.run_batched(base)
@@ -381,9 +384,10 @@ def main(argv=None):
     print("closed loop: %.2f jobs/s over %d jobs" % (sat, closed["jobs"]), file=sys.stderr, flush=True)
     out = {"workload": "serving trace: %d jobs, families c1/c2/c3, N 64..%d, K 1..8, T 200..1500, h %d, %d iterations"
            % (args.jobs, 64 * 32, synth.SERVE_H, args.iterations),
-           "graph_iterations": args.graph, "closed_loop": _strip(closed), "load": {}}
+           "graph_iterations": args.graph, "limits": args.limits, "closed_loop": _strip(closed), "load": {}}
     for load in args.load:
-        tr = synth.serving_trace(args.jobs, seed=args.seed, iterations=args.iterations, rate=load * sat)
+        tr = synth.serving_trace(args.jobs, seed=args.seed, iterations=args.iterations, rate=load * sat,
+                                 limits=limits)
         bat = eng.run_batched(tr)
         entry = {"batched": _strip(bat)}
         print("load %.2f batched: p50 %.3f s p99 %.3f s" % (load, bat["latency_p50_s"], bat["latency_p99_s"]),

@@ -283,9 +283,12 @@ class JobSpec:
     seed: int
     iterations: int
     arrival: float = 0.0
+    limits: int | None = None  # LIMITS_SOFT / LIMITS_PROJECT, None: the family's default
 
     def problem(self) -> "Problem":
-        return make_problem(self.family, seed=self.seed, N=self.N, K=self.K, T=self.T, n_s=self.T // SERVE_H)
+        over = {} if self.limits is None else {"limits": self.limits}
+        return make_problem(self.family, seed=self.seed, N=self.N, K=self.K, T=self.T, n_s=self.T // SERVE_H,
+                            **over)
 
 
 SERVE_H = 50  # window length of every serving job
@@ -293,11 +296,12 @@ SERVE_T = (200, 400, 600, 800, 1000, 1200, 1500)
 
 
 def serving_trace(n_jobs: int = 512, seed: int = 5000, iterations: int = 100, rate: float | None = None,
-                  families=("c1", "c2", "c3"), max_log2_n: int = 5) -> list[JobSpec]:
+                  families=("c1", "c2", "c3"), max_log2_n: int = 5, limits: int | None = None) -> list[JobSpec]:
     """The mixed serving workload: family uniform over the planar problems,
     N = 64 * 2^u with u uniform on 0..max_log2_n, T uniform over SERVE_T
     (windows of SERVE_H steps), K uniform on 1..8.  With `rate` (jobs/s)
-    the arrivals are a Poisson process, else every job arrives at 0."""
+    the arrivals are a Poisson process, else every job arrives at 0.
+    `limits` sets every job's limits mode (None: each family's default)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     t = 0.0
@@ -309,5 +313,5 @@ def serving_trace(n_jobs: int = 512, seed: int = 5000, iterations: int = 100, ra
         if rate is not None:
             t += float(rng.exponential(1.0 / rate))
         out.append(JobSpec(j, fam, N, K, T, seed=seed * 1000 + j, iterations=iterations,
-                           arrival=t if rate is not None else 0.0))
+                           arrival=t if rate is not None else 0.0, limits=limits))
     return out
