@@ -39,6 +39,7 @@ TRAFFIC_PROFILES = {
     "c3": ("planar_adjoint_c3_traffic.md", "planar.hip"),
     "c4": ("arm_adjoint_c4_traffic.md", "arm.hip"),
     "rigid2": ("planar_adjoint_rigid2_traffic.md", "planar.hip"),
+    "metrics_c3": ("metric_dist_c3_traffic.md", "metrics.hip"),
 }
 
 
@@ -70,7 +71,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "rigid2"])
+    ap.add_argument("--config", default=None, choices=["c1", "c2", "c3", "c4", "rigid2"],
+                    help="workload (default c2; c3 with --metrics)")
+    ap.add_argument("--metrics", action="store_true",
+                    help="time the posterior-consistency metrics (KNN-KL both ways + MMD) between the particles' "
+                         "rollouts and 10 held-out trajectories instead of the CSVGD iteration")
     ap.add_argument("--no-graph", action="store_true", help="plain launches instead of graph replay")
     ap.add_argument("--no-overlap", action="store_true",
                     help="compute the kernel bandwidth after the adjoint instead of concurrently with it")
@@ -155,6 +160,103 @@ def cpu_baseline(pb, obs, theta, S, target_s):
     return out
 
 
+METRIC_HELD_OUT = 10
+
+
+def run_metrics(args):
+    """Posterior-consistency metrics (Sec. III-F, App. A-D) between the N
+    particles' rollouts from the first trajectory's start state and
+    METRIC_HELD_OUT held-out trajectories (the generating parameters'
+    rollout plus fresh observation noise), each row the observed joint
+    angles of all T steps.  A step is one pds_traj_metrics call."""
+    import torch
+
+    from paper_2109_08815_amd import driver, synth
+    from paper_2109_08815_amd import lib as L
+
+    pb = synth.make_problem(args.config)
+    dev = torch.device("cuda")
+    idx = torch.as_tensor(pb.obs_index, device=dev)
+    tr = driver.gpu_rollout(pb, pb.particles, dev)  # [N, K, T, d_s]
+    P = tr[:, 0][:, :, idx].reshape(pb.N, -1).float().contiguous()
+    del tr
+    tt = driver.gpu_rollout(pb, pb.theta_true[:1], dev)[0, 0][:, idx].reshape(1, -1).double()
+    rng = np.random.Generator(np.random.PCG64(pb.seed + 77))
+    noise = rng.normal(0.0, pb.sigma_obs, (METRIC_HELD_OUT, tt.shape[1]))
+    Q = (tt + torch.as_tensor(noise, device=dev)).float().contiguous()
+    n, d = P.shape
+    m = Q.shape[0]
+    R = n + m
+    ws = torch.empty(L.traj_metrics_workspace(n, m, d), dtype=torch.uint8, device=dev)
+    for _ in range(max(1, args.warmup)):
+        out = L.traj_metrics(P, Q, ws=ws)
+    torch.cuda.synchronize()
+    L.timing_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        out = L.traj_metrics(P, Q, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    elapsed = max(e0.elapsed_time(e1) / 1e3, 1e-12)
+    kt = L.timing_read()
+    L.timing_enable(False)
+    k_ms = float(np.mean(kt)) if len(kt) else float("nan")
+    pairs = R * (R - 1) // 2
+    flops = 3.0 * pairs * d  # difference, multiply, add per pair and coordinate
+    res = out.cpu().numpy()
+    line = {
+        "metric": "trajectory-pair-coordinates/s (KNN-KL both ways + MMD)",
+        "value": pairs * d * args.steps / elapsed,
+        "unit": "pair-coordinates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 sums, logs, kernel values and median)",
+        "data": "synthetic",
+        "config": {"workload": "%s rollouts: %d particle rollouts vs %d held-out trajectories, d = T x d_x = %d x %d"
+                               % (args.config, n, m, pb.T, pb.d_x), "k": 3, "l": 3},
+        "outputs": {"kl_sim_real": float(res[0]), "kl_real_sim": float(res[1]), "mmd2": float(res[2]),
+                    "sigma": float(res[3])},
+        "wall_s": wall,
+        "roofline": {
+            "bound": "alu",
+            "achieved": flops / (k_ms / 1e3) / 1e12,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": flops / (k_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS,
+            "traffic": measured_traffic("metrics_" + args.config),
+            "kernel": "metric_dist_kernel (+ metric_dist_reduce_kernel of the coordinate splits)",
+            "kernel_ms": k_ms,
+            "flops_per_launch": flops,
+        },
+    }
+    if not args.no_cpu_baseline:
+        from oracle import metrics as om
+
+        Ph, Qh = P.cpu().numpy().astype(np.float64), Q.cpu().numpy().astype(np.float64)
+        ns, t = 32, 0.0
+        while True:
+            t0 = time.perf_counter()
+            om.metrics(Ph[:ns], Qh)
+            t = time.perf_counter() - t0
+            if t > 0.25 * args.cpu_seconds or ns >= n:
+                break
+            ns = min(n, ns * 2)
+        rs = ns + m
+        line["cpu_baseline"] = {"value": rs * (rs - 1) // 2 * d / t, "unit": "pair-coordinates/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": "the oracle's metrics (explicit FP64 differences, numpy) on the first %d "
+                                          "rollouts and the %d held-out trajectories, %.1f s" % (ns, m, t)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -173,6 +275,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     L.lib()
+    if args.metrics:
+        args.config = args.config or "c3"
+        run_metrics(args)
+        return
+    args.config = args.config or "c2"
     pb = synth.make_problem(args.config)
     print("setup %s N=%d K=%d T=%d n_s=%d" % (args.config, pb.N, pb.K, pb.T, pb.n_s), file=sys.stderr, flush=True)
     obs = driver.gpu_observations(pb)

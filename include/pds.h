@@ -273,6 +273,39 @@ int pds_test_median_shift(int32_t ranks);
 
 size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which);
 
+/* ---- Posterior-consistency metrics (Sec. III-F, App. A-D) ----
+ * Compares two sets of trajectories, each row one trajectory's
+ * observations flattened to d floats (e.g. rollouts of the particles
+ * against held-out trajectories):
+ *   out[0] = d_KL(P || Q) by the k-nearest-neighbour estimate of eq. knn-kl,
+ *            d/n sum_i log(nu_k(i) / rho_l(i)) + psi(l) - psi(k)
+ *            + log(m / (n - 1)), nu_k(i) the Euclidean distance from P_i to
+ *            its k-th nearest row of Q, rho_l(i) to its l-th nearest row of
+ *            P other than itself (the paper takes k = l = 3);
+ *   out[1] = d_KL(Q || P), the same with the roles swapped;
+ *   out[2] = squared MMD (Sec. III-F), unbiased estimate with the Gaussian
+ *            kernel exp(-||x - y||^2 / (2 sigma^2));
+ *   out[3] = the sigma used: `sigma` if > 0, else the median Euclidean
+ *            distance over all distinct pairs of P u Q (mean of the two
+ *            middle ones for an even count; 1 if that median is 0).
+ * P [n, d], Q [m, d]: row-major device floats; w [d] device floats
+ * scaling each coordinate before the distances, or NULL for 1.  Rows must
+ * be finite; a zero nearest-neighbour distance gives an infinite estimate,
+ * as the formula does.  rows: NULL, or device doubles [n + m, 3] receiving
+ * per pooled row r (P rows first) d/2 (log nu^2 - log rho^2) with nu over
+ * the other set and rho over its own set, and the kernel sums over its own
+ * set (j != r) and over the other set.  out: device doubles [4].  ws:
+ * caller-owned device workspace of pds_traj_metrics_workspace(n, m, d)
+ * bytes, 256-byte aligned.  Limits: 1 <= k, l <= PDS_METRICS_MAX_K,
+ * n, m >= max(k, l + 1, 2), n + m <= PDS_METRICS_MAX_ROWS, d >= 1.
+ * Returns PDS_OK or a negative code before anything is queued; the outputs
+ * are ready when the stream reaches them.  The library allocates nothing. */
+#define PDS_METRICS_MAX_K 8
+#define PDS_METRICS_MAX_ROWS 16384
+size_t pds_traj_metrics_workspace(int32_t n, int32_t m, int32_t d);
+int pds_traj_metrics(const float* P, int32_t n, const float* Q, int32_t m, int32_t d, const float* w, int32_t k,
+                     int32_t l, double sigma, double* out, double* rows, void* ws, size_t ws_bytes, void* stream);
+
 /* Message for the last error on this thread ("" if none). */
 const char* pds_last_error(void);
 

@@ -25,8 +25,9 @@ trajectory's observations, flattened to d numbers):
 * ``row_terms``: the per-row quantities both sums are made of, for checks at
   sizes where the full oracle would be slow.
 
-Distances are explicit differences, squared and summed in FP64; the
-nearest neighbours come from a full sort of each row.  Optional per-column
+Distances are explicit differences, squared and summed in FP64 (for the
+median of very large sets optionally norms plus an FP64 matrix product);
+the nearest neighbours come from a full sort of each row.  Optional per-column
 weights w scale each coordinate before the distances (w = 1 / sigma_obs
 turns observations into standardised residual space).
 """
@@ -92,10 +93,19 @@ def knn_kl(P, Q, k=3, l=3, w=None):
     return s / n + (harmonic(l - 1) - harmonic(k - 1)) + math.log(m / (n - 1))
 
 
-def median_distance(P, Q, w=None):
+def sq_dists_gram(X, Y):
+    """The same squared distances as ||x||^2 + ||y||^2 - 2 x.y with an FP64
+    matrix product (for sets too large for explicit differences; the FP64
+    cancellation stays far below the GPU's FP32 tolerance)."""
+    nx = (X * X).sum(axis=1)
+    ny = (Y * Y).sum(axis=1)
+    return np.maximum(nx[:, None] + ny[None, :] - 2.0 * (X @ Y.T), 0.0)
+
+
+def median_distance(P, Q, w=None, gram=False):
     """Median of the Euclidean distances over all distinct pairs of P u Q."""
     Z = np.concatenate([_rows(P, w), _rows(Q, w)])
-    D2 = sq_dists(Z, Z)
+    D2 = sq_dists_gram(Z, Z) if gram else sq_dists(Z, Z)
     iu = np.triu_indices(Z.shape[0], 1)
     return float(np.median(np.sqrt(D2[iu])))
 

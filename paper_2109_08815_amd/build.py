@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpds.so")
-SOURCES = ["pds_api.cpp", "planar.hip", "arm.hip", "assemble.hip", "svgd.hip"]
+SOURCES = ["pds_api.cpp", "planar.hip", "arm.hip", "assemble.hip", "svgd.hip", "metrics.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

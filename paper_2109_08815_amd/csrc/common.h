@@ -170,4 +170,18 @@ hipError_t launch_phi_reduce(const JobMap& map, const pds_job* d_jobs, char* ws,
 hipError_t launch_step(const JobMap& map, const pds_job* d_jobs, int grid, int optimizer, int iter,
                        hipStream_t s);
 
+// Posterior-consistency metrics (metrics.hip): launch shape and workspace
+// layout for n + m rows of d floats.
+struct MetricsPlan {
+  int R = 0;       // pooled rows n + m
+  int tiles = 0;   // 64 x 64 pair tiles on and above the diagonal
+  int splits = 1;  // blocks that share one tile's coordinate range
+  size_t off_dist = 0, off_part = 0, off_rows = 0, off_sel = 0, bytes = 0;
+};
+MetricsPlan metrics_plan(int n, int m, int d);
+hipError_t launch_metric_dist(const MetricsPlan& p, const float* P, const float* Q, int n, int m, int d,
+                              const float* w, char* ws, hipStream_t s);
+hipError_t launch_metric_rest(const MetricsPlan& p, int n, int m, int d, int k, int l, double sigma, double* out,
+                              double* rows_out, char* ws, hipStream_t s);
+
 }  // namespace pds

@@ -2,6 +2,7 @@
 // job maps, workspace carving and the launch sequence of each call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -588,6 +589,44 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
       [](const pds_job&) { return 1; }, &bgrid);
   if (mb.n == 0) return PDS_OK;
   return launch_rc(pds::launch_iter_bump(mb, d_jobs, bgrid, (hipStream_t)stream), "iter_bump");
+}
+
+size_t pds_traj_metrics_workspace(int32_t n, int32_t m, int32_t d) {
+  g_err.clear();
+  if (n < 2 || m < 2 || d < 1 || (long)n + m > PDS_METRICS_MAX_ROWS) {
+    fail(PDS_EINVAL, "pds_traj_metrics_workspace: need n, m >= 2, d >= 1, n + m <= %d", PDS_METRICS_MAX_ROWS);
+    return 0;
+  }
+  return pds::metrics_plan(n, m, d).bytes;
+}
+
+int pds_traj_metrics(const float* P, int32_t n, const float* Q, int32_t m, int32_t d, const float* w, int32_t k,
+                     int32_t l, double sigma, double* out, double* rows, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!P || !Q || !out || !ws) return fail(PDS_EINVAL, "pds_traj_metrics: P, Q, out and ws must be non-NULL");
+  if (!aligned(P, 4) || !aligned(Q, 4) || (w && !aligned(w, 4)) || !aligned(out, 8) || (rows && !aligned(rows, 8)) ||
+      !aligned(ws, 256))
+    return fail(PDS_EINVAL, "pds_traj_metrics: misaligned buffer (floats 4, doubles 8, workspace 256 bytes)");
+  if (k < 1 || l < 1 || k > PDS_METRICS_MAX_K || l > PDS_METRICS_MAX_K)
+    return fail(PDS_EUNSUPPORTED, "pds_traj_metrics: k = %d, l = %d outside 1..%d", k, l, PDS_METRICS_MAX_K);
+  const int need = std::max(std::max(k, l + 1), 2);
+  if (n < need || m < need)
+    return fail(PDS_EINVAL, "pds_traj_metrics: each set needs at least %d rows (n = %d, m = %d)", need, n, m);
+  if (d < 1) return fail(PDS_EINVAL, "pds_traj_metrics: d = %d", d);
+  if ((long)n + m > PDS_METRICS_MAX_ROWS)
+    return fail(PDS_EUNSUPPORTED, "pds_traj_metrics: n + m = %ld above %d", (long)n + m, PDS_METRICS_MAX_ROWS);
+  if (!std::isfinite(sigma)) return fail(PDS_EINVAL, "pds_traj_metrics: sigma must be finite (<= 0: median)");
+  const pds::MetricsPlan plan = pds::metrics_plan(n, m, d);
+  if (ws_bytes < plan.bytes)
+    return fail(PDS_EINVAL, "pds_traj_metrics: workspace of %zu bytes, %zu needed", ws_bytes, plan.bytes);
+  hipStream_t s = (hipStream_t)stream;
+  char* w8 = static_cast<char*>(ws);
+  int slot;
+  timing_begin(s, &slot);
+  int rc = launch_rc(pds::launch_metric_dist(plan, P, Q, n, m, d, w, w8, s), "metric_dist");
+  timing_end(s, slot);
+  if (rc != PDS_OK) return rc;
+  return launch_rc(pds::launch_metric_rest(plan, n, m, d, k, l, sigma, out, rows, w8, s), "metric_rest");
 }
 
 }  // extern "C"

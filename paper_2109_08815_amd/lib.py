@@ -95,6 +95,12 @@ def lib():
             L.pds_job_footprint.restype = C.c_size_t
             L.pds_test_median_shift.argtypes = [C.c_int32]
             L.pds_test_median_shift.restype = C.c_int
+            L.pds_traj_metrics_workspace.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+            L.pds_traj_metrics_workspace.restype = C.c_size_t
+            L.pds_traj_metrics.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                           C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_size_t, C.c_void_p]
+            L.pds_traj_metrics.restype = C.c_int
             _lib = L
     return _lib
 
@@ -337,3 +343,44 @@ def timing_read(max_n: int = 4096):
     if n < 0:
         _check(n, "pds_timing_read")
     return np.array(buf[:n], dtype=np.float64)
+
+
+def traj_metrics_workspace(n: int, m: int, d: int) -> int:
+    nb = lib().pds_traj_metrics_workspace(int(n), int(m), int(d))
+    if nb == 0:
+        raise PdsError(lib().pds_last_error().decode())
+    return nb
+
+
+def traj_metrics(P, Q, w=None, k: int = 3, l: int = 3, sigma: float | None = None, rows: bool = False,
+                 ws=None, stream=None):
+    """Posterior-consistency metrics of two trajectory sets on the GPU
+    (pds_traj_metrics): P [n, d] and Q [m, d] float32 CUDA tensors, one
+    trajectory per row.  Returns a float64 CUDA tensor (KL(P||Q), KL(Q||P),
+    MMD^2, sigma), and with rows=True also the [n + m, 3] per-row terms.
+    `ws` may be a preallocated uint8 CUDA tensor of at least
+    traj_metrics_workspace(n, m, d) bytes."""
+    if P.dtype != torch.float32 or Q.dtype != torch.float32 or not P.is_cuda or not Q.is_cuda:
+        raise PdsError("traj_metrics: P and Q must be float32 CUDA tensors")
+    P, Q = P.contiguous(), Q.contiguous()
+    n, d = P.shape
+    m, d2 = Q.shape
+    if d2 != d:
+        raise PdsError("traj_metrics: P and Q rows differ in length")
+    if w is not None:
+        w = w.to(device=P.device, dtype=torch.float32).contiguous()
+        if w.numel() != d:
+            raise PdsError("traj_metrics: w needs d entries")
+    nb = traj_metrics_workspace(n, m, d)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=P.device)
+    out = torch.empty(4, dtype=torch.float64, device=P.device)
+    rws = torch.empty((n + m, 3), dtype=torch.float64, device=P.device) if rows else None
+    rc = lib().pds_traj_metrics(C.c_void_p(P.data_ptr()), n, C.c_void_p(Q.data_ptr()), m, d,
+                                C.c_void_p(w.data_ptr()) if w is not None else None, int(k), int(l),
+                                float(sigma) if sigma is not None else 0.0, C.c_void_p(out.data_ptr()),
+                                C.c_void_p(rws.data_ptr()) if rows else None, C.c_void_p(ws.data_ptr()),
+                                ws.numel(), _stream(stream))
+    _check(rc, "pds_traj_metrics")
+    return (out, rws) if rows else out
+

@@ -315,3 +315,17 @@ def serving_trace(n_jobs: int = 512, seed: int = 5000, iterations: int = 100, ra
         out.append(JobSpec(j, fam, N, K, T, seed=seed * 1000 + j, iterations=iterations,
                            arrival=t if rate is not None else 0.0, limits=limits))
     return out
+
+
+def metric_sets(seed: int, n: int, m: int, d: int, spread: float = 1.0, shift: float = 0.3):
+    """Two seeded sets of trajectory-like rows for the consistency metrics
+    (float32, [n, d] and [m, d]): a shared random-walk path, plus per-row
+    random walks (step 0.05 * spread for P, 0.05 for Q) and, for Q, a
+    constant offset `shift`.  Neighbouring rows are close, as rollouts of
+    nearby particles are."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = np.cumsum(rng.normal(0.0, 0.1, (1, d)), axis=1)
+    P = base + np.cumsum(rng.normal(0.0, 0.05 * spread, (n, d)), axis=1)
+    Q = base + shift + np.cumsum(rng.normal(0.0, 0.05, (m, d)), axis=1)
+    return P.astype(np.float32), Q.astype(np.float32)
+

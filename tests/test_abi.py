@@ -125,3 +125,29 @@ def test_algorithmic_flop_counts():
         rf, rr, rt = L.algorithmic_flops(L.PDS_MODEL_PLANAR_RIGID, n)
         assert rt == 2.0 * n
         assert rf > planar[n - 1][0] and rr > planar[n - 1][1]
+
+
+def test_metrics_arguments_rejected_on_host():
+    """pds_traj_metrics validates before queueing anything (the fake device
+    addresses are never dereferenced)."""
+    lib = L.lib()
+    dev = C.c_void_p(4096)
+    ws = C.c_void_p(1 << 20)
+    nb = lib.pds_traj_metrics_workspace(100, 20, 64)
+    assert nb > 0 and nb % 256 == 0
+    assert lib.pds_traj_metrics_workspace(1, 20, 64) == 0 and len(lib.pds_last_error()) > 0
+
+    def call(n=100, m=20, d=64, k=3, l=3, sigma=0.0, P=dev, Q=dev, out=dev, w=None, ws_=ws, nbytes=nb):
+        return lib.pds_traj_metrics(P, n, Q, m, d, w, k, l, sigma, out, None, ws_, nbytes, None)
+
+    assert call(P=None) == -1
+    assert call(k=9) == -2
+    assert call(l=0) == -2
+    assert call(n=3) == -1          # l + 1 = 4 rows needed
+    assert call(m=3, k=4, l=2) == -1
+    assert call(d=0) == -1
+    assert call(n=16000, m=1000) == -2
+    assert call(ws_=C.c_void_p((1 << 20) + 64)) == -1  # misaligned workspace
+    assert call(nbytes=nb - 1) == -1
+    assert call(sigma=float("nan")) == -1
+    assert lib.pds_traj_metrics_workspace(1000, 40, 5000) > lib.pds_traj_metrics_workspace(100, 20, 64)
