@@ -12,7 +12,8 @@
 //   metric_sel_*            exact median of the n+m choose 2 squared
 //                           distances: radix select on the FP64 bit
 //                           patterns, 8 bits per pass, both middle ranks at
-//                           once
+//                           once, each pass deriving its digit prefix from
+//                           the previous pass's histogram
 //   metric_rows_kernel      one wave per row: k-th / l-th nearest squared
 //                           distance in the other / own set, and the
 //                           kernel sums over both sets
@@ -70,27 +71,46 @@ __global__ void __launch_bounds__(256) metric_dist_kernel(const float* __restric
   __shared__ float Ws[kMC];
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   const int i0 = ti * kMT, j0 = tj * kMT;
+  // This thread stages coordinate lc of rows lr + 8 q (q = 0..7) of both
+  // row blocks; row pointers are fixed for the whole coordinate range.
+  constexpr int kRowsPerThread = kMT * kMC / 256;
+  const int lc = threadIdx.x % kMC, lr = threadIdx.x / kMC;
+  const float* pa[kRowsPerThread];
+  const float* pb[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int ra = i0 + lr + 8 * q, rb = j0 + lr + 8 * q;
+    pa[q] = ra < R ? zrow(P, Q, n, d, ra) + lc : nullptr;
+    pb[q] = rb < R ? zrow(P, Q, n, d, rb) + lc : nullptr;
+  }
+  float na[kRowsPerThread], nb[kRowsPerThread];
+  float nw = 0.f;
+  auto fetch = [&](int ch) {
+    const int col = ch * kMC;
+    const bool in = col + lc < d;
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      na[q] = (in && pa[q]) ? pa[q][col] : 0.f;
+      nb[q] = (in && pb[q]) ? pb[q][col] : 0.f;
+    }
+    if (HAS_W) nw = in ? w[col + lc] : 0.f;
+  };
   double acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+  if (cb < ce) fetch(cb);
   for (int ch = cb; ch < ce; ++ch) {
-    const int c0 = ch * kMC;
     __syncthreads();  // the previous chunk is consumed
-    for (int e = threadIdx.x; e < kMT * kMC; e += 256) {
-      const int r = e / kMC, c = e % kMC;
-      const int col = c0 + c;
-      float a = 0.f, bb = 0.f;
-      if (col < d) {
-        if (i0 + r < R) a = zrow(P, Q, n, d, i0 + r)[col];
-        if (j0 + r < R) bb = zrow(P, Q, n, d, j0 + r)[col];
-      }
-      As[c][r] = a;
-      Bs[c][r] = bb;
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) {
+      As[lc][lr + 8 * q] = na[q];
+      Bs[lc][lr + 8 * q] = nb[q];
     }
-    if (HAS_W && threadIdx.x < kMC) Ws[threadIdx.x] = (c0 + (int)threadIdx.x < d) ? w[c0 + threadIdx.x] : 0.f;
+    if (HAS_W && lr == 0) Ws[lc] = nw;
     __syncthreads();
+    if (ch + 1 < ce) fetch(ch + 1);  // in flight while this chunk is computed
     float sacc[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -149,85 +169,123 @@ __global__ void __launch_bounds__(256) metric_dist_reduce_kernel(const double* _
 // ---- exact median of the squared distances over pairs i < j ----
 // Non-negative doubles order like their bit patterns read as unsigned
 // integers, so a most-significant-digit radix select on the bits is exact.
+// Pass p (p = 0..7) histograms digit p (bits 56 - 8p and up) of the keys
+// that match prefix[p] on the digits above; each of its blocks first
+// derives prefix[p] and rank[p] from pass p-1's histogram, so no separate
+// digit kernel runs between passes.  Both middle ranks travel together.
+constexpr int kSelPasses = 8;
+
 struct SelState {
-  unsigned long long prefix[2];
-  unsigned long long rank[2];
-  unsigned int hist[2][256];
+  unsigned long long prefix[kSelPasses + 1][2];
+  unsigned long long rank[kSelPasses + 1][2];
+  unsigned int hist[kSelPasses][2][256];
   double sigma;
 };
 
 __global__ void __launch_bounds__(256) metric_sel_init_kernel(SelState* st, int R) {
   const unsigned long long C = (unsigned long long)R * (R - 1) / 2;
   if (threadIdx.x == 0) {
-    st->prefix[0] = st->prefix[1] = 0ULL;
-    st->rank[0] = (C % 2) ? (C - 1) / 2 : C / 2 - 1;
-    st->rank[1] = (C % 2) ? (C - 1) / 2 : C / 2;
+    st->prefix[0][0] = st->prefix[0][1] = 0ULL;
+    st->rank[0][0] = (C % 2) ? (C - 1) / 2 : C / 2 - 1;
+    st->rank[0][1] = (C % 2) ? (C - 1) / 2 : C / 2;
   }
-  st->hist[0][threadIdx.x] = 0u;
-  st->hist[1][threadIdx.x] = 0u;
+  for (int p = 0; p < kSelPasses; ++p) {
+    st->hist[p][0][threadIdx.x] = 0u;
+    st->hist[p][1][threadIdx.x] = 0u;
+  }
 }
 
-// Histogram of the digit at `shift` over the keys that match each target's
-// prefix above that digit.
+// Block-wide: digit of pass p-1 for both targets from its histogram, giving
+// (prefix, rank) for pass p in pre[] / rk[] (LDS).  256 threads.
+__device__ inline void sel_advance(const SelState* st, int p, unsigned long long* pre, unsigned long long* rk,
+                                   unsigned int (*scan)[256]) {
+  const int t = threadIdx.x;
+  const int shift_prev = 56 - 8 * (p - 1);
+  for (int g = 0; g < 2; ++g) scan[g][t] = st->hist[p - 1][g][t];
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {  // inclusive scan (Hillis-Steele)
+    unsigned int v0 = 0u, v1 = 0u;
+    if (t >= o) {
+      v0 = scan[0][t - o];
+      v1 = scan[1][t - o];
+    }
+    __syncthreads();
+    scan[0][t] += v0;
+    scan[1][t] += v1;
+    __syncthreads();
+  }
+  for (int g = 0; g < 2; ++g) {
+    const unsigned long long incl = scan[g][t];
+    const unsigned long long excl = t ? scan[g][t - 1] : 0ULL;
+    const unsigned long long r = st->rank[p - 1][g];
+    if (r >= excl && r < incl) {
+      pre[g] = st->prefix[p - 1][g] | ((unsigned long long)t << shift_prev);
+      rk[g] = r - excl;
+    }
+  }
+  __syncthreads();
+}
+
+// Pass p: histogram of digit p over the keys matching prefix[p] above it.
+// Blocks walk rows i of the upper triangle (pairs j > i).
 __global__ void __launch_bounds__(256) metric_sel_hist_kernel(const double* __restrict__ dist, int R, SelState* st,
-                                                              int shift) {
+                                                              int p) {
   __shared__ unsigned int h[2][256];
+  __shared__ unsigned int scan[2][256];
+  __shared__ unsigned long long pre[2], rk[2];
+  if (p == 0) {
+    if (threadIdx.x < 2) {
+      pre[threadIdx.x] = st->prefix[0][threadIdx.x];
+      rk[threadIdx.x] = st->rank[0][threadIdx.x];
+    }
+  } else {
+    sel_advance(st, p, pre, rk, scan);
+  }
   h[0][threadIdx.x] = 0u;
   h[1][threadIdx.x] = 0u;
   __syncthreads();
-  const unsigned long long hi_mask = (shift == 56) ? 0ULL : (~0ULL << (shift + 8));
-  const unsigned long long p0 = st->prefix[0] & hi_mask, p1 = st->prefix[1] & hi_mask;
-  const size_t RR = (size_t)R * R;
-  for (size_t f = (size_t)blockIdx.x * 256 + threadIdx.x; f < RR; f += (size_t)gridDim.x * 256) {
-    const int i = (int)(f / R), j = (int)(f % R);
-    if (j <= i) continue;
-    const unsigned long long key = (unsigned long long)__double_as_longlong(dist[f]);
-    const unsigned int dg = (unsigned int)(key >> shift) & 255u;
-    if ((key & hi_mask) == p0) atomicAdd(&h[0][dg], 1u);
-    if ((key & hi_mask) == p1) atomicAdd(&h[1][dg], 1u);
+  if (blockIdx.x == 0 && threadIdx.x < 2) {
+    st->prefix[p][threadIdx.x] = pre[threadIdx.x];
+    st->rank[p][threadIdx.x] = rk[threadIdx.x];
   }
-  __syncthreads();
-  for (int t = 0; t < 2; ++t)
-    if (h[t][threadIdx.x]) atomicAdd(&st->hist[t][threadIdx.x], h[t][threadIdx.x]);
-}
-
-// Picks each target's digit from its histogram and clears the histograms.
-__global__ void __launch_bounds__(256) metric_sel_digit_kernel(SelState* st, int shift) {
-  if (threadIdx.x < 2) {
-    const int t = threadIdx.x;
-    unsigned long long cum = 0;
-    int dg = 255;
-    for (int b = 0; b < 256; ++b) {
-      const unsigned long long c = st->hist[t][b];
-      if (st->rank[t] < cum + c) {
-        dg = b;
-        break;
-      }
-      cum += c;
+  const int shift = 56 - 8 * p;
+  const unsigned long long hi_mask = (p == 0) ? 0ULL : (~0ULL << (shift + 8));
+  const unsigned long long p0 = pre[0] & hi_mask, p1 = pre[1] & hi_mask;
+  for (int i = blockIdx.x; i < R - 1; i += gridDim.x) {
+    const double* row = dist + (size_t)i * R;
+    for (int j = i + 1 + threadIdx.x; j < R; j += 256) {
+      const unsigned long long key = (unsigned long long)__double_as_longlong(row[j]);
+      const unsigned int dg = (unsigned int)(key >> shift) & 255u;
+      if ((key & hi_mask) == p0) atomicAdd(&h[0][dg], 1u);
+      if ((key & hi_mask) == p1) atomicAdd(&h[1][dg], 1u);
     }
-    st->prefix[t] |= (unsigned long long)dg << shift;
-    st->rank[t] -= cum;
   }
   __syncthreads();
-  st->hist[0][threadIdx.x] = 0u;
-  st->hist[1][threadIdx.x] = 0u;
+  for (int g = 0; g < 2; ++g)
+    if (h[g][threadIdx.x]) atomicAdd(&st->hist[p][g][threadIdx.x], h[g][threadIdx.x]);
 }
 
-// sigma = median distance (mean of the two middle distances for an even
-// pair count), 1 when that median is 0; or the caller's value.
-__global__ void metric_sigma_kernel(SelState* st, int R, double given) {
-  if (threadIdx.x != 0) return;
-  double s;
-  if (given > 0.0) {
-    s = given;
-  } else {
+// Last digit, then sigma = median distance (mean of the two middle
+// distances for an even pair count), 1 when that median is 0.
+__global__ void __launch_bounds__(256) metric_sel_final_kernel(SelState* st, int R) {
+  __shared__ unsigned int scan[2][256];
+  __shared__ unsigned long long pre[2], rk[2];
+  sel_advance(st, kSelPasses, pre, rk, scan);
+  if (threadIdx.x == 0) {
+    st->prefix[kSelPasses][0] = pre[0];
+    st->prefix[kSelPasses][1] = pre[1];
     const unsigned long long C = (unsigned long long)R * (R - 1) / 2;
-    const double a = sqrt(__longlong_as_double((long long)st->prefix[0]));
-    const double b = sqrt(__longlong_as_double((long long)st->prefix[1]));
-    s = (C % 2) ? a : 0.5 * (a + b);
-    if (s * s < 1e-300) s = 1.0;
+    const double a = sqrt(__longlong_as_double((long long)pre[0]));
+    const double b = sqrt(__longlong_as_double((long long)pre[1]));
+    double sg = (C % 2) ? a : 0.5 * (a + b);
+    if (sg * sg < 1e-300) sg = 1.0;
+    st->sigma = sg;
   }
-  st->sigma = s;
+}
+
+// The caller's sigma.
+__global__ void metric_sigma_given_kernel(SelState* st, double given) {
+  if (threadIdx.x == 0) st->sigma = given;
 }
 
 __device__ inline double wave_min(double v) {
@@ -411,15 +469,14 @@ hipError_t launch_metric_rest(const MetricsPlan& p, int n, int m, int d, int k, 
   SelState* st = reinterpret_cast<SelState*>(ws + p.off_sel);
   const int R = p.R;
   if (!(sigma > 0.0)) {
-    const size_t RR = (size_t)R * R;
-    const int grid = (int)std::min<size_t>((RR + 255) / 256, 2048);
+    const int grid = std::min(R - 1, 512);
     hipLaunchKernelGGL(metric_sel_init_kernel, dim3(1), dim3(256), 0, s, st, R);
-    for (int shift = 56; shift >= 0; shift -= 8) {
-      hipLaunchKernelGGL(metric_sel_hist_kernel, dim3(grid), dim3(256), 0, s, dist, R, st, shift);
-      hipLaunchKernelGGL(metric_sel_digit_kernel, dim3(1), dim3(256), 0, s, st, shift);
-    }
+    for (int p = 0; p < kSelPasses; ++p)
+      hipLaunchKernelGGL(metric_sel_hist_kernel, dim3(grid), dim3(256), 0, s, dist, R, st, p);
+    hipLaunchKernelGGL(metric_sel_final_kernel, dim3(1), dim3(256), 0, s, st, R);
+  } else {
+    hipLaunchKernelGGL(metric_sigma_given_kernel, dim3(1), dim3(64), 0, s, st, sigma);
   }
-  hipLaunchKernelGGL(metric_sigma_kernel, dim3(1), dim3(64), 0, s, st, R, sigma);
   hipLaunchKernelGGL(metric_rows_kernel, dim3((R + 3) / 4), dim3(256), 0, s, dist, n, m, d, k, l, st, rows);
   hipLaunchKernelGGL(metric_final_kernel, dim3(1), dim3(256), 0, s, rows, n, m, k, l, st, out);
   return hipGetLastError();
