@@ -57,7 +57,13 @@ extern "C" {
 // physical double pendulum of Sec. IV-B: per link mass, rotational inertia
 // about the centre of mass, centre of mass (x, y) in the link frame and
 // joint friction, and the offset of every further joint along -y of its
-// parent (the link length).
+// parent (the link length), 5 the seven-joint arm of kind 2 carrying the box
+// on a passive universal joint (Sec. IV-C and its appendix, phase I): a
+// massless ring turning about the flange x axis, then the box about the
+// ring's y axis; theta = the box's inertia about its centre of mass (xx,
+// yy, zz, xy, xz, yz), its centre of mass and the viscous friction of the
+// two joint axes; the observation is the box frame (origin and the points
+// 1 m along its x, y, z axes, in world coordinates).
 typedef struct {
   int32_t kind;
   int32_t n_dof;
@@ -92,14 +98,15 @@ typedef struct {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxB = 10;  // bodies of the longest chain (the U-joint arm has 9)
 
 template <class S>
 struct Chain {
   int n;
-  Xform<S> Xtree[8];
-  int jtype[8];  // 0 revolute, 1 prismatic
-  double axis[8][3];
-  M6<S> I[8];
+  Xform<S> Xtree[kMaxB];
+  int jtype[kMaxB];  // 0 revolute, 1 prismatic
+  double axis[kMaxB][3];
+  M6<S> I[kMaxB];
 };
 
 template <class S>
@@ -146,7 +153,7 @@ Chain<S> build_chain(const OrcModel& md, const S* th) {
       ch.I[i] = rbi<S>(th[rigid_slot(i, 0)], v3<S>(th[rigid_slot(i, 2)], th[rigid_slot(i, 3)], S(0.0)),
                        diag3<S>(Iz, Iz, Iz));
     }
-  } else if (md.kind == 2) {
+  } else if (md.kind == 2 || md.kind == 5) {
     for (int i = 0; i < 7; ++i) {
       const double ca = std::cos(md.dh_alpha[i]), sa = std::sin(md.dh_alpha[i]);
       // Rot_x(alpha) as an active rotation; the coordinate transform is its transpose.
@@ -166,6 +173,21 @@ Chain<S> build_chain(const OrcModel& md, const S* th) {
     ch.jtype[7] = 0;
     ch.axis[7][0] = 1.0; ch.axis[7][1] = 0.0; ch.axis[7][2] = 0.0;
     const M3<S> zero3 = diag3<S>(S(0.0), S(0.0), S(0.0));
+    if (md.kind == 5) {
+      // massless ring, then the box about the ring's y axis at the same point
+      ch.I[7] = rbi<S>(S(0.0), v3zero<S>(), zero3);
+      ch.Xtree[8].E = m3ident<S>();
+      ch.Xtree[8].r = v3zero<S>();
+      ch.jtype[8] = 0;
+      ch.axis[8][0] = 0.0; ch.axis[8][1] = 1.0; ch.axis[8][2] = 0.0;
+      M3<S> Ic;
+      Ic.a[0][0] = th[0]; Ic.a[1][1] = th[1]; Ic.a[2][2] = th[2];
+      Ic.a[0][1] = Ic.a[1][0] = th[3];
+      Ic.a[0][2] = Ic.a[2][0] = th[4];
+      Ic.a[1][2] = Ic.a[2][1] = th[5];
+      ch.I[8] = rbi<S>(S(md.box_m), v3<S>(th[6], th[7], th[8]), Ic);
+      return ch;
+    }
     M6<S> Ib = rbi<S>(S(md.box_m), v3<S>(S(md.box_c[0]), S(md.box_c[1]), S(md.box_c[2])),
                       diag3<S>(S(md.box_I[0]), S(md.box_I[1]), S(md.box_I[2])));
     M6<S> Ia = rbi<S>(S(md.pm_m), v3<S>(th[0], th[1], S(md.pm_z)), zero3);
@@ -189,14 +211,19 @@ void joint_torque(const OrcModel& md, const S* th, double time, const S* q, cons
     for (int i = 0; i < md.n_dof; ++i) tau[i] = -(md.damping[i] * qd[i]);
   } else if (md.kind == 4) {
     for (int i = 0; i < md.n_dof; ++i) tau[i] = -(th[rigid_slot(i, 4)] * qd[i]);
-  } else if (md.kind == 2) {
+  } else if (md.kind == 2 || md.kind == 5) {
     for (int i = 0; i < 7; ++i) {
       const double ph = md.omega[i] * time + md.phase[i];
       const double qdes = md.qc[i] + md.amp[i] * std::sin(ph);
       const double qddes = md.amp[i] * md.omega[i] * std::cos(ph);
       tau[i] = md.kp[i] * (qdes - q[i]) + md.kd[i] * (qddes - qd[i]);
     }
-    tau[7] = -(md.damping[7] * qd[7]);
+    if (md.kind == 2) {
+      tau[7] = -(md.damping[7] * qd[7]);
+    } else {
+      tau[7] = -(th[9] * qd[7]);
+      tau[8] = -(th[10] * qd[8]);
+    }
   } else {
     tau[0] = th[0];
     if (md.M >= 2) tau[0] = tau[0] + th[1] * time;
@@ -239,10 +266,10 @@ M6<S> m6v_outer_div(const SV<S>& Uv, const S& D) {
 template <class S>
 void aba(const Chain<S>& ch, const double g[3], const S* q, const S* qd, const S* tau, S* qdd) {
   const int n = ch.n;
-  Xform<S> X[8];
-  SV<S> Sj[8], v[8], c[8], pA[8], U[8], a[8];
-  M6<S> IA[8];
-  S D[8], uu[8];
+  Xform<S> X[kMaxB];
+  SV<S> Sj[kMaxB], v[kMaxB], c[kMaxB], pA[kMaxB], U[kMaxB], a[kMaxB];
+  M6<S> IA[kMaxB];
+  S D[kMaxB], uu[kMaxB];
   for (int i = 0; i < n; ++i) {
     X[i] = xcompose(joint_xform(ch, i, q[i]), ch.Xtree[i]);
     Sj[i] = motion_subspace(ch, i);
@@ -282,8 +309,8 @@ void aba(const Chain<S>& ch, const double g[3], const S* q, const S* qd, const S
 void crba_rnea(const Chain<double>& ch, const double g[3], const double* q, const double* qd,
                double* H, double* C) {
   const int n = ch.n;
-  Xform<double> X[8];
-  SV<double> Sj[8], v[8], a[8], f[8];
+  Xform<double> X[kMaxB];
+  SV<double> Sj[kMaxB], v[kMaxB], a[kMaxB], f[kMaxB];
   SV<double> a0 = svzero<double>();
   for (int d = 0; d < 3; ++d) a0.a[3 + d] = -g[d];
   for (int i = 0; i < n; ++i) {
@@ -300,7 +327,7 @@ void crba_rnea(const Chain<double>& ch, const double g[3], const double* q, cons
     C[i] = svdot(Sj[i], f[i]);
     if (i > 0) f[i - 1] = svadd(f[i - 1], m6v(m6T(xmat(X[i])), f[i]));
   }
-  M6<double> IC[8];
+  M6<double> IC[kMaxB];
   for (int i = 0; i < n; ++i) IC[i] = ch.I[i];
   for (int i = n - 1; i >= 0; --i)
     if (i > 0) IC[i - 1] = m6add(IC[i - 1], m6mul(m6T(xmat(X[i])), m6mul(IC[i], xmat(X[i]))));
@@ -322,11 +349,45 @@ void crba_rnea(const Chain<double>& ch, const double g[3], const double* q, cons
 // velocity updates the position.
 template <class S>
 void step(const OrcModel& md, const Chain<S>& ch, const S* th, double time, double dt, S* q, S* qd) {
-  S tau[8], qdd[8];
+  S tau[kMaxB], qdd[kMaxB];
   joint_torque<S>(md, th, time, q, qd, tau);
   aba<S>(ch, md.gravity, q, qd, tau, qdd);
   for (int i = 0; i < md.n_dof; ++i) qd[i] = qd[i] + dt * qdd[i];
   for (int i = 0; i < md.n_dof; ++i) q[i] = q[i] + dt * qd[i];
+}
+
+// World-frame points of the last body's frame: its origin, then the points
+// 1 m along its x, y and z axes (12 numbers).  Each transform X = (E, r)
+// holds the rotation from parent to body coordinates and the body origin in
+// parent coordinates, so the body-to-world rotation is R_parent E^T and the
+// origin o_parent + R_parent r.
+template <class S>
+void frame_points(const Chain<S>& ch, const S* q, S* x) {
+  M3<S> R = m3ident<S>();
+  V3<S> o = v3zero<S>();
+  for (int i = 0; i < ch.n; ++i) {
+    const Xform<S> X = xcompose(joint_xform(ch, i, q[i]), ch.Xtree[i]);
+    o = add(o, m3v(R, X.r));
+    R = m3mul(R, m3T(X.E));
+  }
+  for (int d = 0; d < 3; ++d) {
+    x[d] = o.x[d];
+    for (int a = 0; a < 3; ++a) x[3 + 3 * a + d] = o.x[d] + R.a[d][a];
+  }
+}
+
+// The observed quantities of a state: the box-frame points for kind 5,
+// otherwise the state components listed in obs_index.
+template <class S>
+void observe(const OrcModel& md, const Chain<S>& ch, const S* q, const S* qd, S* x) {
+  if (md.kind == 5) {
+    frame_points<S>(ch, q, x);
+    return;
+  }
+  for (int d = 0; d < md.d_x; ++d) {
+    const int si = md.obs_index[d];
+    x[d] = (si < md.n_dof) ? q[si] : qd[si - md.n_dof];
+  }
 }
 
 // One multiple-shooting window (Sec. III-C): start at state `start` at step
@@ -338,7 +399,7 @@ S window(const OrcModel& md, const OrcProblem& pr, const S* th, const S* start, 
          S* end_state, double* traj /* [h, d_s] or null */) {
   const int n = md.n_dof, ds = 2 * n;
   const Chain<S> ch = build_chain<S>(md, th);
-  S q[8], qd[8];
+  S q[kMaxB], qd[kMaxB];
   for (int i = 0; i < n; ++i) { q[i] = start[i]; qd[i] = start[n + i]; }
   const double log_sqrt_2pi = 0.5 * std::log(2.0 * kPi);
   S ll(0.0);
@@ -346,10 +407,10 @@ S window(const OrcModel& md, const OrcProblem& pr, const S* th, const S* start, 
     const int t = j * pr.h + s;  // index of the state the step starts from
     step<S>(md, ch, th, t * pr.dt, pr.dt, q, qd);
     const double* x_real = pr.obs + ((size_t)k * pr.T + t) * md.d_x;  // observes state t+1
+    S xs[16];
+    observe<S>(md, ch, q, qd, xs);
     for (int d = 0; d < md.d_x; ++d) {
-      const int si = md.obs_index[d];
-      const S x_sim = (si < n) ? q[si] : qd[si - n];
-      const S r = (x_real[d] - x_sim) * pr.w_x[d];
+      const S r = (x_real[d] - xs[d]) * pr.w_x[d];
       ll = ll - 0.5 * (r * r) - (log_sqrt_2pi - std::log(pr.w_x[d]));
     }
     if (traj)
@@ -410,7 +471,7 @@ void window_grad(const OrcModel& md, const OrcProblem& pr, const double* th, con
                  int k, int j, double* ll, double* dl_dth, double* dl_ds, double* send,
                  double* dsend_dth /* [d_s][M] */, double* dsend_ds /* [d_s][d_s] */) {
   const int M = md.M, ds = 2 * md.n_dof;
-  Dual<P> thd[16], sd[16], ed[16];
+  Dual<P> thd[16], sd[2 * kMaxB], ed[2 * kMaxB];
   for (int m = 0; m < M; ++m) { thd[m] = Dual<P>(th[m]); thd[m].d[m] = 1.0; }
   for (int d = 0; d < ds; ++d) { sd[d] = Dual<P>(start[d]); sd[d].d[M + d] = 1.0; }
   const Dual<P> l = window<Dual<P>>(md, pr, thd, sd, k, j, ed, nullptr);
@@ -467,11 +528,17 @@ void orc_crba_rnea(const OrcModel* md, const double* th, const double* q, const 
 
 // Single-shooting rollout of n_steps from state s0 at step index t0:
 // f_sim of Sec. II, writing states t0+1 .. t0+n_steps.
+// Observed quantities (d_x numbers) of the states (q, qd) under parameters th.
+void orc_observe(const OrcModel* md, const double* th, const double* q, const double* qd, double* x) {
+  const Chain<double> ch = build_chain<double>(*md, th);
+  observe<double>(*md, ch, q, qd, x);
+}
+
 void orc_rollout(const OrcModel* md, const double* th, const double* s0, int t0, int n_steps, double dt,
                  double* traj) {
   const int n = md->n_dof, ds = 2 * n;
   const Chain<double> ch = build_chain<double>(*md, th);
-  double q[8], qd[8];
+  double q[kMaxB], qd[kMaxB];
   for (int i = 0; i < n; ++i) { q[i] = s0[i]; qd[i] = s0[n + i]; }
   for (int s = 0; s < n_steps; ++s) {
     step<double>(*md, ch, th, (t0 + s) * dt, dt, q, qd);
@@ -529,7 +596,7 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
                  double* dcon_dth_unit /* [n_sel,K,n_s,M] or null */) {
   const int ds = 2 * md->n_dof, K = pr->K, ns = pr->n_s, M = md->M;
   const int P = M + ds;
-  if (P > 32 || M > 16 || ds > 16) return -1;
+  if (P > 32 || M > 16 || ds > 2 * kMaxB) return -1;
   const int units = n_sel * K * ns;
   std::vector<double> dl_dth((size_t)units * M), dl_ds((size_t)units * ds);
   std::vector<double> dse_dth((size_t)units * ds * M), dse_ds((size_t)units * ds * ds);
@@ -622,7 +689,7 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
         const double lam = pr->lam_def[((size_t)i * K + k) * (ns - 1) + j];
         const double mult = lam + pr->c * g;  // d Phi / d g
         // d g / d s_end = -2 e u / sigma^2 with e = (S_next - s_end) u
-        double dg_dse[16];
+        double dg_dse[2 * kMaxB];
         for (int d = 0; d < ds; ++d) {
           const double e = (Snext[d] - se[d]) * pr->u[d];
           dg_dse[d] = -2.0 * e * pr->u[d] * inv_s2;

@@ -70,6 +70,7 @@ def lib():
             L.orc_crba_rnea.argtypes = [C.POINTER(OrcModel), _D, _D, _D, _D, _D]
             L.orc_tau.argtypes = [C.POINTER(OrcModel), _D, C.c_double, _D, _D, _D]
             L.orc_rollout.argtypes = [C.POINTER(OrcModel), _D, _D, C.c_int, C.c_int, C.c_double, _D]
+            L.orc_observe.argtypes = [C.POINTER(OrcModel), _D, _D, _D, _D]
             L.orc_forward.argtypes = [C.POINTER(OrcModel), C.POINTER(OrcProblem), C.c_int, _I, _D, _D, _D, _D, _D, _D]
             L.orc_gradient.argtypes = [C.POINTER(OrcModel), C.POINTER(OrcProblem), C.c_int, _I, _D, _D, _D, _D, _D,
                                        _D, _D, _D, _D, _D]
@@ -179,8 +180,25 @@ def observations(pb, theta_true=None):
     obs = np.zeros((pb.K, pb.T, pb.d_x))
     for k in range(pb.K):
         tr = rollout(pb, tt[k], pb.s0[k], pb.T)
-        obs[k] = tr[:, pb.obs_index] + pb.noise[k]
+        obs[k] = observe(pb, tt[k], tr) + pb.noise[k]
     return obs
+
+
+def observe(pb, theta, states):
+    """Observed quantities [n, d_x] of states [n, d_s] (the listed state
+    components, or the box-frame points of the universal-joint arm)."""
+    states = np.atleast_2d(states)
+    if pb.kind != 5:
+        return states[:, pb.obs_index]
+    m = model_struct(pb)
+    th = _f64(theta)
+    n = pb.n_dof
+    out = np.zeros((states.shape[0], pb.d_x))
+    x = np.zeros(pb.d_x)
+    for t in range(states.shape[0]):
+        lib().orc_observe(C.byref(m), _p(th), _p(_f64(states[t, :n])), _p(_f64(states[t, n:])), _p(x))
+        out[t] = x
+    return out
 
 
 def shooting_init(pb, theta, obs=None):

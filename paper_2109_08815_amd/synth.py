@@ -24,6 +24,12 @@ synthetic stand-ins for the recordings the paper used, Sec. IV):
   about the centre of mass, centre of mass (x, y) and joint friction, plus
   the length of link 2, inside that table's bounds; observes the whole
   state (q, qd) as that experiment does                             (M = 11)
+* ``box1`` the 7-joint arm carrying the box on a passive universal joint
+  (Sec. IV-C and its appendix, phase I): the box's inertia about its
+  centre of mass (xx, yy, zz, xy, xz, yz), its centre of mass and the
+  viscous friction of the two joint axes, inside the phase-I table's
+  bounds; box mass 0.92 kg known; observes the box frame (origin and the
+  points 1 m along its axes, 12 numbers)                           (M = 11)
 * ``toy`` one prismatic unit mass driven by force theta0 (+ theta1 * time),
   the linear-Gaussian check problem                                 (M = 1, 2)
 
@@ -43,6 +49,7 @@ KIND_PLANAR = 1
 KIND_ARM = 2
 KIND_TOY = 3
 KIND_PLANAR_RIGID = 4
+KIND_ARM_UJOINT = 5
 
 COMBINE_SUM = 0
 COMBINE_PROD = 1
@@ -103,6 +110,7 @@ CONFIGS = {
     "c2": dict(family="double", N=256, K=4, T=400, n_s=10, dt=0.005, sigma_obs=0.01),
     "c3": dict(family="chain5", N=1024, K=8, T=1000, n_s=20, dt=0.002, sigma_obs=0.02),
     "rigid2": dict(family="rigid", N=256, K=4, T=400, n_s=10, dt=0.005, sigma_obs=0.01),
+    "box1": dict(family="ujoint", N=1024, K=1, T=1200, n_s=24, dt=1.0 / 240.0, sigma_obs=0.01),
     "c4": dict(family="arm", N=2048, K=1, T=1500, n_s=30, dt=1.0 / 240.0, sigma_obs=0.01),
 }
 
@@ -155,7 +163,7 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         base = dict(family="toy", N=256, K=1, T=50, n_s=1, dt=0.1, sigma_obs=0.5)
     base.update({k: v for k, v in over.items() if k in ("N", "K", "T", "n_s", "dt", "sigma_obs")})
     fam = base["family"]
-    idx = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "rigid2": 5, "toy": 9}.get(config, 7)
+    idx = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "rigid2": 5, "box1": 6, "toy": 9}.get(config, 7)
     if seed is None:
         seed = 1000 * idx
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -210,6 +218,21 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         s0 = np.zeros((K, 16))
         s0[:, :7] = arm["qc"] + arm["amp"] * np.sin(arm["phase"])
         s0[:, 8:15] = arm["amp"] * arm["omega"] * np.cos(arm["phase"])
+    elif fam == "ujoint":
+        kind = KIND_ARM_UJOINT
+        n = 9
+        M = 11
+        # phase-I table: inertia diagonal, products of inertia, COM, joint friction
+        lo = np.array([0.05, 0.05, 0.05, -0.01, -0.01, -0.01, -0.005, -0.005, 0.1, 0.0, 0.0])
+        hi = np.array([0.1, 0.1, 0.1, 0.01, 0.01, 0.01, 0.005, 0.005, 0.4, 0.15, 0.15])
+        arm = _arm_constants(rng)
+        arm["box_m"] = 0.92
+        gravity = np.array([0.0, 0.0, -9.81])
+        d_x = 12
+        obs_index = np.arange(12)
+        s0 = np.zeros((K, 18))
+        s0[:, :7] = arm["qc"] + arm["amp"] * np.sin(arm["phase"])
+        s0[:, 9:16] = arm["amp"] * arm["omega"] * np.cos(arm["phase"])
     elif fam == "toy":
         kind = KIND_TOY
         n = 1
@@ -247,8 +270,9 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         rho=hi - lo, lr_theta=lr_frac * (hi - lo), lr_S=lr_S, eps_lam=1e-2, seed=seed,
         lik=int(over.get("lik", LIK_MDMM)),
         # rigid links: masses and inertias must stay positive, and their
-        # lower limits sit within one Adam step of zero
-        limits=int(over.get("limits", LIMITS_PROJECT if fam == "rigid" else LIMITS_SOFT)),
+        # lower limits sit within one Adam step of zero; the box's inertia
+        # must stay positive definite
+        limits=int(over.get("limits", LIMITS_PROJECT if fam in ("rigid", "ujoint") else LIMITS_SOFT)),
     )
 
 

@@ -24,7 +24,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # Dynamics (App. B-A: ABA forward dynamics + semi-implicit Euler)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "toy"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1", "toy"])
 def test_aba_equals_crba_rnea(orc, cfg):
     """ABA's q_dd equals H^{-1}(tau - C) from CRBA + RNEA (independent algorithms)."""
     pb = synth.make_problem(cfg, N=4, K=1, T=10, n_s=1)
@@ -271,6 +271,67 @@ def test_hinge_inertia_parallel_axis(orc):
         assert abs(H[7, 7] - Ih) <= 1e-13 * Ih
 
 
+def _box_frame_by_homogeneous_matrices(a, q):
+    """Box-frame points from 4x4 homogeneous matrices: per arm joint the
+    modified-DH placement Rot_x(alpha) Trans_x(a) then Rot_z(q) Trans_z(d),
+    then Trans_z(flange_d) Rot_x(q_7) Rot_y(q_8)."""
+    def rx(t):
+        c, s = math.cos(t), math.sin(t)
+        return np.array([[1, 0, 0, 0], [0, c, -s, 0], [0, s, c, 0], [0, 0, 0, 1.0]])
+
+    def ry(t):
+        c, s = math.cos(t), math.sin(t)
+        return np.array([[c, 0, s, 0], [0, 1, 0, 0], [-s, 0, c, 0], [0, 0, 0, 1.0]])
+
+    def rz(t):
+        c, s = math.cos(t), math.sin(t)
+        return np.array([[c, -s, 0, 0], [s, c, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1.0]])
+
+    def tr(x, y, z):
+        T = np.eye(4)
+        T[:3, 3] = (x, y, z)
+        return T
+
+    T = np.eye(4)
+    for i in range(7):
+        T = T @ rx(a["dh_alpha"][i]) @ tr(a["dh_a"][i], 0, 0) @ rz(q[i]) @ tr(0, 0, a["dh_d"][i])
+    T = T @ tr(0, 0, a["flange_d"]) @ rx(q[7]) @ ry(q[8])
+    pts = [T @ np.array(v) for v in ([0, 0, 0, 1.0], [1, 0, 0, 1.0], [0, 1, 0, 1.0], [0, 0, 1, 1.0])]
+    return np.concatenate([p[:3] for p in pts])
+
+
+def test_universal_joint_box_frame_points(orc):
+    """The observed box frame equals forward kinematics written with
+    homogeneous matrices from the DH table (an independent formulation)."""
+    pb = synth.make_problem("box1", N=4, T=24, n_s=1)
+    rng = np.random.default_rng(21)
+    for _ in range(10):
+        th = pb.lo + rng.uniform(size=pb.M) * (pb.hi - pb.lo)
+        s = rng.uniform(-1.5, 1.5, 18)
+        got = orc.observe(pb, th, s[None])[0]
+        ref = _box_frame_by_homogeneous_matrices(pb.arm, s[:9])
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13)
+
+
+def test_universal_joint_inertia_parallel_axis(orc):
+    """With q_8 = 0 the joint-space inertia of the two passive axes is the
+    box's inertia about the joint point (parallel axis): H_77 = I_xx +
+    m (c_y^2 + c_z^2), H_88 = I_yy + m (c_x^2 + c_z^2), H_78 = I_xy -
+    m c_x c_y (the ring is massless)."""
+    pb = synth.make_problem("box1", N=4, T=24, n_s=1)
+    m = pb.arm["box_m"]
+    rng = np.random.default_rng(22)
+    for _ in range(5):
+        th = pb.lo + rng.uniform(size=pb.M) * (pb.hi - pb.lo)
+        s = rng.uniform(-1.0, 1.0, 18)
+        s[8] = 0.0
+        H, _ = orc.crba_rnea(pb, th, s[:9], s[9:])
+        cx, cy, cz = th[6:9]
+        assert abs(H[7, 7] - (th[0] + m * (cy * cy + cz * cz))) <= 1e-14
+        assert abs(H[8, 8] - (th[1] + m * (cx * cx + cz * cz))) <= 1e-14
+        assert abs(H[7, 8] - (th[3] - m * cx * cy)) <= 1e-14
+
+
 # --------------------------------------------------------------------------
 # Likelihood, multiple shooting, combination (Sec. III-B, III-C, App. A-B)
 # --------------------------------------------------------------------------
@@ -283,7 +344,7 @@ def _setup(orc, cfg, **kw):
     return pb, obs, st
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1"])
 def test_multiple_shooting_on_trajectory_equals_single(orc, cfg):
     """Shooting states taken from the single-shooting rollout give zero
     defects, and the window log-likelihoods sum to the single-shooting one."""
@@ -352,7 +413,7 @@ def _total_phi(pb, f, lam_def):
     return np.sum(lam_def * g + 0.5 * pb.c * g * g, axis=(1, 2))
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1"])
 def test_dual_gradients_match_finite_differences(orc, cfg):
     """g_obs = d log p / d theta, g_con = d Phi / d theta and S_dot =
     d (log p - Phi) / d S, with Phi = sum (lam g + c/2 g^2), by central
