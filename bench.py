@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default=None, choices=["c1", "c2", "c3", "c4", "rigid2"],
+    ap.add_argument("--config", default=None, choices=["c1", "c2", "c3", "c4", "rigid2", "box1"],
                     help="workload (default c2; c3 with --metrics)")
     ap.add_argument("--metrics", action="store_true",
                     help="time the posterior-consistency metrics (KNN-KL both ways + MMD) between the particles' "
@@ -353,7 +353,8 @@ def main():
         "config": {"workload": "%s: %s N=%d M=%d K=%d T=%d dt=%g n_s=%d" % (
             args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain",
                           "c4": "7-joint arm with hinged box",
-                          "rigid2": "rigid-link double pendulum"}[args.config],
+                          "rigid2": "rigid-link double pendulum",
+                          "box1": "7-joint arm with the box on a universal joint"}[args.config],
             pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain",
             "bandwidth": "concurrent with the adjoint" if not args.no_overlap else "after the adjoint"},
         "iters_per_s": args.steps / elapsed,
@@ -366,7 +367,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(args.config),
-            "kernel": "arm_adjoint_kernel" if model == L.PDS_MODEL_ARM else "planar_adjoint_kernel<%d, %s links>" % (
+            "kernel": ("arm_adjoint_kernel<%s>" % ("universal joint" if model == L.PDS_MODEL_ARM_UJOINT else "hinge"))
+            if model in (L.PDS_MODEL_ARM, L.PDS_MODEL_ARM_UJOINT) else "planar_adjoint_kernel<%d, %s links>" % (
                 pb.n_dof, "rigid" if model == L.PDS_MODEL_PLANAR_RIGID else "point-mass"),
             "kernel_ms": k_ms,
             "flops_per_particle_step": per_step,

@@ -95,6 +95,18 @@ extern "C" {
 #define PDS_MODEL_PLANAR 1
 #define PDS_MODEL_ARM 2
 #define PDS_MODEL_PLANAR_RIGID 3
+/* ARM_UJOINT: the ARM model's 7 PD-controlled joints with the box on a
+ * passive universal joint instead of the hinge, the mount of the paper's
+ * Panda experiment (Sec. IV-C and its appendix, phase I): a massless ring
+ * turns about the flange x axis (offset flange_d along the flange z axis),
+ * the box about the ring's y axis through the same point; n_dof = 9;
+ * theta = the box's inertia about its centre of mass (I_xx, I_yy, I_zz,
+ * I_xy, I_xz, I_yz), its centre of mass (x, y, z) in the box frame and the
+ * viscous friction of the two axes (tau = -b qd), M = 11; observes the box
+ * frame, i.e. its origin and the points 1 m along its x, y and z axes in
+ * world coordinates (d_x = 12, in that order); consts (117 floats) =
+ * gravity[3], the 7 x 16 arm-joint table of ARM, flange_d, box mass. */
+#define PDS_MODEL_ARM_UJOINT 4
 
 #define PDS_COMBINE_SUM 0   /* equally weighted mixture over trajectories, eq. traj_likelihood */
 #define PDS_COMBINE_PROD 1  /* product over trajectories, App. A-B eq. traj_likelihood_prod */

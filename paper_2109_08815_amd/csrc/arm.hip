@@ -34,18 +34,33 @@
 
 namespace pds {
 
-constexpr int kArmBodies = 8;
-constexpr int kArmDs = 16;
+// How the box hangs from the flange: on a hinge about the flange x axis
+// (8 bodies; theta = the in-plane positions of two point masses in the
+// box; observes the hinge angle), or on a universal joint, a massless ring
+// about the flange x axis and then the box about the ring's y axis (9
+// bodies; theta = the box's inertia about its centre of mass (xx, yy, zz,
+// xy, xz, yz), its centre of mass and the viscous friction of both axes;
+// observes the box frame: its origin and the points 1 m along its x, y, z
+// axes in world coordinates, 12 numbers).
+enum ArmBox { kHinge = 0, kUJoint = 1 };
+template <int BOX>
+struct ArmShape {
+  static constexpr int NB = BOX == kUJoint ? 9 : 8;   // bodies = joints
+  static constexpr int DS = 2 * NB;                  // state (q, qd)
+  static constexpr int M = BOX == kUJoint ? 11 : 4;  // parameters
+  static constexpr int DX = BOX == kUJoint ? 12 : 1; // observed numbers per step
+};
+constexpr int kArmMaxBodies = 9;
 
 // Per-job constants derived once per call from the caller's raw model
 // description (see pds.h for the raw layout).
 struct ArmConst {
   float g[3];
-  float E[kArmBodies][9];   // tree rotation: parent coordinates -> joint frame (row-major)
-  float r[kArmBodies][3];   // tree translation (joint origin in parent coordinates)
-  float m[kArmBodies];      // link mass (body 7: the box alone)
-  float c[kArmBodies][3];   // centre of mass
-  float Ic[kArmBodies][6];  // inertia about the COM: xx, xy, xz, yy, yz, zz
+  float E[kArmMaxBodies][9];   // tree rotation: parent coordinates -> joint frame (row-major)
+  float r[kArmMaxBodies][3];   // tree translation (joint origin in parent coordinates)
+  float m[kArmMaxBodies];      // link mass (hinge: body 7 the box alone; joint: body 8 the box)
+  float c[kArmMaxBodies][3];   // centre of mass
+  float Ic[kArmMaxBodies][6];  // inertia about the COM: xx, xy, xz, yy, yz, zz
   float kp[7], kd[7], qc[7], amp[7], om[7], ph[7];
   float bh;                 // hinge damping
   float pm_m, pm_z;         // point masses: mass each, height in the box frame
@@ -58,8 +73,9 @@ __host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincos
 // The spatial algebra, forward dynamics and reverse step, generic over the
 // scalar type R: float on the device; a counting scalar on the host gives
 // the algorithmic FLOPs of one step.
-template <class R>
+template <class R, int BOX>
 struct ArmMath {
+  static constexpr int NB = ArmShape<BOX>::NB;
   struct V3 {
     R x, y, z;
   };
@@ -107,8 +123,8 @@ struct ArmMath {
   // Transpose of xtf (maps a force adjoint to the body): X y
   __host__ __device__ static inline SV xf(const R* E, V3 r, SV y) { return xm(E, r, y); }
 
-  // Joint axis: bodies 0..6 about z, body 7 about x (unit vectors).
-  __host__ __device__ static inline int axis_of(int i) { return i == 7 ? 0 : 2; }
+  // Joint axis: bodies 0..6 about z, body 7 about x, body 8 about y.
+  __host__ __device__ static inline int axis_of(int i) { return i == 7 ? 0 : (i == 8 ? 1 : 2); }
   __host__ __device__ static inline R comp(V3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
   __host__ __device__ static inline V3 unit(int k) { return v3(k == 0 ? 1.f : 0.f, k == 1 ? 1.f : 0.f, k == 2 ? 1.f : 0.f); }
 
@@ -122,19 +138,27 @@ struct ArmMath {
         E[3 + k] = -sn * T[k] + cs * T[3 + k];
         E[6 + k] = T[6 + k];
       }
-    } else {  // Rx(q)^T T
+    } else if (axis_of(i) == 0) {  // Rx(q)^T T
   #pragma unroll
       for (int k = 0; k < 3; ++k) {
         E[k] = T[k];
         E[3 + k] = cs * T[3 + k] + sn * T[6 + k];
         E[6 + k] = -sn * T[3 + k] + cs * T[6 + k];
       }
+    } else {  // Ry(q)^T T
+  #pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        E[k] = cs * T[k] - sn * T[6 + k];
+        E[3 + k] = T[3 + k];
+        E[6 + k] = sn * T[k] + cs * T[6 + k];
+      }
     }
   }
 
   // Rigid-body inertia applied to a motion vector, from (m, c, Ic):
   // I [w; v] = [Ic w + c x p; p] with p = m (v - c x w).
-  __host__ __device__ static inline SV rbi_mul(float m, V3 c, const float* Ic, SV x) {
+  template <class T>
+  __host__ __device__ static inline SV rbi_mul(float m, V3 c, const T* Ic, SV x) {
     const V3 p = m * (x.l - cross(c, x.a));
     const V3 Iw = v3(Ic[0] * x.a.x + Ic[1] * x.a.y + Ic[2] * x.a.z, Ic[1] * x.a.x + Ic[3] * x.a.y + Ic[4] * x.a.z,
                      Ic[2] * x.a.x + Ic[4] * x.a.y + Ic[5] * x.a.z);
@@ -156,7 +180,8 @@ struct ArmMath {
   }
 
   // Adds the rigid inertia of (m, c, Ic) to I: [[Ic + m cx cx^T, m cx], [m cx^T, m 1]].
-  __host__ __device__ static inline void add_rbi(Sym6& I, float m, V3 c, const float* Ic) {
+  template <class T>
+  __host__ __device__ static inline void add_rbi(Sym6& I, float m, V3 c, const T* Ic) {
     // cx cx^T = |c|^2 1 - c c^T
     const R cc = dot(c, c);
     I.A[0] += Ic[0] + m * (cc - c.x * c.x);
@@ -243,9 +268,19 @@ struct ArmMath {
     for (int e = 0; e < 9; ++e) P.B[e] += B[e] + RC[e];
   }
 
-  // Joint torque at time `time` (PD on the arm, damping on the hinge).
-  __host__ __device__ static inline R arm_tau(const ArmConst& K, int i, R time, R q, R qd) {
-    if (i == 7) return -K.bh * qd;
+  // The box's centre of mass and inertia about it from theta (universal
+  // joint): Ic in the order xx, xy, xz, yy, yz, zz.
+  __host__ __device__ static inline void box_from_theta(const R* th, V3* c, R* Ic) {
+    *c = v3(th[6], th[7], th[8]);
+    Ic[0] = th[0]; Ic[1] = th[3]; Ic[2] = th[4];
+    Ic[3] = th[1]; Ic[4] = th[5]; Ic[5] = th[2];
+  }
+
+  // Joint torque at time `time` (PD on the arm, viscous damping on the
+  // passive axes).
+  __host__ __device__ static inline R arm_tau(const ArmConst& K, const R* th, int i, R time, R q, R qd) {
+    if (BOX == kHinge && i == 7) return -K.bh * qd;
+    if (BOX == kUJoint && i >= 7) return -th[i + 2] * qd;
     R sn, cs;
     sincos_r(K.om[i] * time + K.ph[i], &sn, &cs);
     const R qdes = K.qc[i] + K.amp[i] * sn;
@@ -255,12 +290,12 @@ struct ArmMath {
 
   // Intermediates of one forward-dynamics evaluation kept for the reverse.
   struct ArmTape {
-    R cs[kArmBodies], sn[kArmBodies];
-    SV v[kArmBodies];   // body velocities
-    SV a[kArmBodies];   // body accelerations (incl. S qdd)
-    SV U[kArmBodies];   // IA S
-    R invD[kArmBodies];
-    R qdd[kArmBodies];
+    R cs[NB], sn[NB];
+    SV v[NB];   // body velocities
+    SV a[NB];   // body accelerations (incl. S qdd)
+    SV U[NB];   // IA S
+    R invD[NB];
+    R qdd[NB];
   };
 
   // Compiler-level memory barrier: the model constants are re-read (scalar
@@ -277,11 +312,11 @@ struct ArmMath {
   // bias force; each body's rigid inertia is rebuilt on the fly.
   __host__ __device__ static __forceinline__ void arm_aba(const ArmConst& K, const R* th, const R* q, const R* qd,
                                           R time, ArmTape& T) {
-    R u[kArmBodies];
-    const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
+    R u[NB];
+    const V3 ca = v3(th[0], th[1], K.pm_z), cb = BOX == kHinge ? v3(th[2], th[3], K.pm_z) : v3(0.f, 0.f, 0.f);
     const float z0[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   #pragma unroll
-    for (int i = 0; i < kArmBodies; ++i) {
+    for (int i = 0; i < NB; ++i) {
       keep_consts_in_memory();
       sincos_r(q[i], &T.sn[i], &T.cs[i]);
       R E[9];
@@ -297,14 +332,23 @@ struct ArmMath {
   #pragma unroll
     for (int e = 0; e < 9; ++e) IAc.B[e] = 0.f;
   #pragma unroll
-    for (int i = kArmBodies - 1; i >= 0; --i) {
+    for (int i = NB - 1; i >= 0; --i) {
       keep_consts_in_memory();
       const int k = axis_of(i);
-      const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
       Sym6 IA = IAc;
-      add_rbi(IA, K.m[i], cm, K.Ic[i]);
-      SV h = rbi_mul(K.m[i], cm, K.Ic[i], T.v[i]);
-      if (i == 7) {
+      SV h;
+      if (BOX == kUJoint && i == 8) {
+        V3 cm;
+        R Icb[6];
+        box_from_theta(th, &cm, Icb);
+        add_rbi(IA, K.m[i], cm, Icb);
+        h = rbi_mul(K.m[i], cm, Icb, T.v[i]);
+      } else {
+        const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
+        add_rbi(IA, K.m[i], cm, K.Ic[i]);
+        h = rbi_mul(K.m[i], cm, K.Ic[i], T.v[i]);
+      }
+      if (BOX == kHinge && i == 7) {
         add_rbi(IA, K.pm_m, ca, z0);
         add_rbi(IA, K.pm_m, cb, z0);
         h = h + pm_mul(K.pm_m, ca, T.v[i]) + pm_mul(K.pm_m, cb, T.v[i]);
@@ -313,7 +357,7 @@ struct ArmMath {
       const SV U = sv(v3(s3(IA.A, 0, k), s3(IA.A, 1, k), s3(IA.A, 2, k)),
                       v3(IA.B[3 * k], IA.B[3 * k + 1], IA.B[3 * k + 2]));
       const R invD = recip(comp(U.a, k));
-      u[i] = arm_tau(K, i, time, q[i], qd[i]) - comp(pA.a, k);
+      u[i] = arm_tau(K, th, i, time, q[i], qd[i]) - comp(pA.a, k);
       T.U[i] = U;
       T.invD[i] = invD;
       if (i > 0) {
@@ -344,7 +388,7 @@ struct ArmMath {
     }
     SV ap = sv(v3(0.f, 0.f, 0.f), v3(-K.g[0], -K.g[1], -K.g[2]));
   #pragma unroll
-    for (int i = 0; i < kArmBodies; ++i) {
+    for (int i = 0; i < NB; ++i) {
       keep_consts_in_memory();
       R E[9];
       body_E(K, i, T.cs[i], T.sn[i], E);
@@ -364,7 +408,7 @@ struct ArmMath {
     ArmTape T;
     arm_aba(K, th, q, qd, time, T);
   #pragma unroll
-    for (int i = 0; i < kArmBodies; ++i) {
+    for (int i = 0; i < NB; ++i) {
       keep_consts_in_memory();
       qd[i] = qd[i] + dt * T.qdd[i];
       q[i] = q[i] + dt * qd[i];
@@ -377,20 +421,20 @@ struct ArmMath {
                                                const ArmTape& T, R dt, R* qb, R* qdb, R* thb) {
     keep_consts_in_memory();
     // Euler: q' = q + dt qd', qd' = qd + dt qdd
-    R qddb[kArmBodies];
+    R qddb[NB];
     #pragma unroll
-    for (int i = 0; i < kArmBodies; ++i) {
+    for (int i = 0; i < NB; ++i) {
       keep_consts_in_memory();
       qdb[i] += dt * qb[i];
       qddb[i] = dt * qdb[i];
     }
     // lambda = H^{-1} qddb: ABA with zero velocity and gravity (the child's
     // bias-force contribution is carried inward).
-    R lam[kArmBodies], us[kArmBodies];
+    R lam[NB], us[NB];
     {
       SV pAc = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
   #pragma unroll
-      for (int i = kArmBodies - 1; i >= 0; --i) {
+      for (int i = NB - 1; i >= 0; --i) {
         keep_consts_in_memory();
         const int k = axis_of(i);
         us[i] = qddb[i] - comp(pAc.a, k);
@@ -405,7 +449,7 @@ struct ArmMath {
     {
       SV ap = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
   #pragma unroll
-      for (int i = 0; i < kArmBodies; ++i) {
+      for (int i = 0; i < NB; ++i) {
         keep_consts_in_memory();
         R E[9];
         body_E(K, i, T.cs[i], T.sn[i], E);
@@ -416,21 +460,30 @@ struct ArmMath {
       }
     }
     // x_bar += -lambda^T dF/dx, F = ID - tau.  The tau part:
-    // d tau / d q = -kp, d tau / d qd = -kd (arm), -bh (hinge).
+    // d tau / d q = -kp, d tau / d qd = -kd (arm), -b (passive axes), and
+    // for the joint's friction coefficients d tau / d b = -qd.
     #pragma unroll
     for (int i = 0; i < 7; ++i) {
       keep_consts_in_memory();
       qb[i] += -K.kp[i] * lam[i];
       qdb[i] += -K.kd[i] * lam[i];
     }
-    qdb[7] += -K.bh * lam[7];
+    if (BOX == kHinge) {
+      qdb[7] += -K.bh * lam[7];
+    } else {
+  #pragma unroll
+      for (int i = 7; i < NB; ++i) {
+        qdb[i] += -th[i + 2] * lam[i];
+        thb[i + 2] += -lam[i] * qd[i];
+      }
+    }
     // ID part: reverse of RNEA with output seed mu = -lambda.  Total-force
     // adjoints first (outward; they do not depend on the forces):
     // ftb_i = S_i mu_i + X_i ftb_{i-1}.
-    const V3 ca = v3(th[0], th[1], K.pm_z), cb = v3(th[2], th[3], K.pm_z);
-    SV ftb[kArmBodies];
+    const V3 ca = v3(th[0], th[1], K.pm_z), cb = BOX == kHinge ? v3(th[2], th[3], K.pm_z) : v3(0.f, 0.f, 0.f);
+    SV ftb[NB];
   #pragma unroll
-    for (int i = 0; i < kArmBodies; ++i) {
+    for (int i = 0; i < NB; ++i) {
       keep_consts_in_memory();
       SV b = sv((-lam[i]) * unit(axis_of(i)), v3(0.f, 0.f, 0.f));
       if (i > 0) {
@@ -448,20 +501,52 @@ struct ArmMath {
     SV abar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
     SV vbar = sv(v3(0.f, 0.f, 0.f), v3(0.f, 0.f, 0.f));
   #pragma unroll
-    for (int i = kArmBodies - 1; i >= 0; --i) {
+    for (int i = NB - 1; i >= 0; --i) {
       keep_consts_in_memory();
       const SV fb = ftb[i];
-      const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
       const SV v = T.v[i], a = T.a[i];
       const V3 ax = unit(axis_of(i));
       const SV sax = sv(ax, v3(0.f, 0.f, 0.f));
       // body force and total force
-      SV Ia = rbi_mul(K.m[i], cm, K.Ic[i], a);
-      SV h = rbi_mul(K.m[i], cm, K.Ic[i], v);
-      SV Ifb = rbi_mul(K.m[i], cm, K.Ic[i], fb);
       const SV vxfb = crm(v, fb);
-      SV Ivxfb = rbi_mul(K.m[i], cm, K.Ic[i], vxfb);
-      if (i == 7) {
+      SV Ia, h, Ifb, Ivxfb;
+      if (BOX == kUJoint && i == 8) {
+        V3 cm;
+        R Icb[6];
+        box_from_theta(th, &cm, Icb);
+        Ia = rbi_mul(K.m[i], cm, Icb, a);
+        h = rbi_mul(K.m[i], cm, Icb, v);
+        Ifb = rbi_mul(K.m[i], cm, Icb, fb);
+        Ivxfb = rbi_mul(K.m[i], cm, Icb, vxfb);
+        // theta: fb . f = g(a, fb) + g(v, -v x fb) with g(x, y) = y . I x,
+        // I x = [Ic x_w + c x p; p], p = m (x_l - c x x_w).  d g / d Ic is
+        // the symmetric outer product of y_n and x_w; d g / d c as for the
+        // hinge's point masses.
+  #pragma unroll
+        for (int term = 0; term < 2; ++term) {
+          const SV x = term == 0 ? a : v;
+          const SV y = term == 0 ? fb : sv(-vxfb.a, -vxfb.l);
+          thb[0] += y.a.x * x.a.x;
+          thb[1] += y.a.y * x.a.y;
+          thb[2] += y.a.z * x.a.z;
+          thb[3] += y.a.x * x.a.y + y.a.y * x.a.x;
+          thb[4] += y.a.x * x.a.z + y.a.z * x.a.x;
+          thb[5] += y.a.y * x.a.z + y.a.z * x.a.y;
+          const V3 p = K.m[i] * (x.l - cross(cm, x.a));
+          const V3 z = cross(y.a, cm) + y.l;
+          const V3 gc = cross(p, y.a) - K.m[i] * cross(x.a, z);
+          thb[6] += gc.x;
+          thb[7] += gc.y;
+          thb[8] += gc.z;
+        }
+      } else {
+        const V3 cm = v3(K.c[i][0], K.c[i][1], K.c[i][2]);
+        Ia = rbi_mul(K.m[i], cm, K.Ic[i], a);
+        h = rbi_mul(K.m[i], cm, K.Ic[i], v);
+        Ifb = rbi_mul(K.m[i], cm, K.Ic[i], fb);
+        Ivxfb = rbi_mul(K.m[i], cm, K.Ic[i], vxfb);
+      }
+      if (BOX == kHinge && i == 7) {
         Ia = Ia + pm_mul(K.pm_m, ca, a) + pm_mul(K.pm_m, cb, a);
         h = h + pm_mul(K.pm_m, ca, v) + pm_mul(K.pm_m, cb, v);
         Ifb = Ifb + pm_mul(K.pm_m, ca, fb) + pm_mul(K.pm_m, cb, fb);
@@ -518,13 +603,92 @@ struct ArmMath {
       }
     }
   }
+
+  // Forward kinematics of the last body's frame (universal joint: the box):
+  // body-to-world rotation R_i = R_{i-1} E_i^T and origin o_i = o_{i-1} +
+  // R_{i-1} r_i.  Writes its origin and the points 1 m along its x, y, z
+  // axes (12 numbers).
+  __host__ __device__ static __forceinline__ void box_frame(const ArmConst& K, const R* q, R* x) {
+    R Rw[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    V3 o = v3(0.f, 0.f, 0.f);
+  #pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      keep_consts_in_memory();
+      R sn, cs;
+      sincos_r(q[i], &sn, &cs);
+      R E[9];
+      body_E(K, i, cs, sn, E);
+      o = o + mulE(Rw, v3(K.r[i][0], K.r[i][1], K.r[i][2]));
+      R Rn[9];
+  #pragma unroll
+      for (int a = 0; a < 3; ++a)
+  #pragma unroll
+        for (int b = 0; b < 3; ++b) Rn[3 * a + b] = Rw[3 * a] * E[3 * b] + Rw[3 * a + 1] * E[3 * b + 1] + Rw[3 * a + 2] * E[3 * b + 2];
+  #pragma unroll
+      for (int e = 0; e < 9; ++e) Rw[e] = Rn[e];
+    }
+    x[0] = o.x; x[1] = o.y; x[2] = o.z;
+  #pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      x[3 + 3 * a] = o.x + Rw[a];
+      x[4 + 3 * a] = o.y + Rw[3 + a];
+      x[5 + 3 * a] = o.z + Rw[6 + a];
+    }
+  }
+
+  // Observation term of one state (universal joint): returns
+  // sum_c ((obs_c - x_c) w_c)^2 and adds d/dq of -1/2 of it to qb.  Every
+  // observed point p sits on the box, so dp/dq_j = z_j x (p - o_j) with z_j
+  // and o_j joint j's world axis and origin; with rt_p = w^2 (obs - p)
+  // summed as A = sum p x rt_p and B = sum rt_p, the adjoint of q_j is
+  // z_j . (A - o_j x B).
+  __host__ __device__ static __forceinline__ R box_obs(const ArmConst& K, const R* q, const float* obs, const float* w,
+                                                       R* qb) {
+    R x[12];
+    box_frame(K, q, x);
+    R ss = 0.f;
+    V3 A = v3(0.f, 0.f, 0.f), B = v3(0.f, 0.f, 0.f);
+  #pragma unroll
+    for (int pnt = 0; pnt < 4; ++pnt) {
+      const int c0 = 3 * pnt;
+      const R r0 = (obs[c0] - x[c0]) * w[c0], r1 = (obs[c0 + 1] - x[c0 + 1]) * w[c0 + 1],
+              r2 = (obs[c0 + 2] - x[c0 + 2]) * w[c0 + 2];
+      ss += r0 * r0 + r1 * r1 + r2 * r2;
+      const V3 rt = v3(r0 * w[c0], r1 * w[c0 + 1], r2 * w[c0 + 2]);
+      A = A + cross(v3(x[c0], x[c0 + 1], x[c0 + 2]), rt);
+      B = B + rt;
+    }
+    R Rw[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    V3 o = v3(0.f, 0.f, 0.f);
+  #pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      keep_consts_in_memory();
+      R sn, cs;
+      sincos_r(q[i], &sn, &cs);
+      R E[9];
+      body_E(K, i, cs, sn, E);
+      o = o + mulE(Rw, v3(K.r[i][0], K.r[i][1], K.r[i][2]));
+      R Rn[9];
+  #pragma unroll
+      for (int a = 0; a < 3; ++a)
+  #pragma unroll
+        for (int b = 0; b < 3; ++b) Rn[3 * a + b] = Rw[3 * a] * E[3 * b] + Rw[3 * a + 1] * E[3 * b + 1] + Rw[3 * a + 2] * E[3 * b + 2];
+  #pragma unroll
+      for (int e = 0; e < 9; ++e) Rw[e] = Rn[e];
+      const int k = axis_of(i);
+      const V3 z = v3(Rw[k], Rw[3 + k], Rw[6 + k]);
+      qb[i] += dot(z, A - cross(o, B));
+    }
+    return ss;
+  }
 };
 
-// Raw model description -> derived constants (the caller's consts array:
+// Raw model description -> derived constants.  The caller's consts array:
 // gravity[3]; per arm joint 7 x (a, alpha, d, m, cx, cy, cz, Ixx, Iyy, Izz,
-// kp, kd, qc, amp, omega, phase); flange_d, hinge damping, box m, box c[3],
-// box I[3] (diagonal), point-mass m, point-mass z).
-__host__ __device__ inline void arm_setup(const float* raw, ArmConst* K) {
+// kp, kd, qc, amp, omega, phase); then for the hinge flange_d, hinge
+// damping, box m, box c[3], box I[3] (diagonal), point-mass m, point-mass
+// z; for the universal joint flange_d, box m.
+__host__ __device__ inline void arm_setup(const float* raw, ArmConst* K, bool ujoint) {
   for (int d = 0; d < 3; ++d) K->g[d] = raw[d];
   for (int i = 0; i < 7; ++i) {
     const float* j = raw + 3 + 16 * i;
@@ -544,8 +708,18 @@ __host__ __device__ inline void arm_setup(const float* raw, ArmConst* K) {
     K->amp[i] = j[13]; K->om[i] = j[14]; K->ph[i] = j[15];
   }
   const float* h = raw + 3 + 16 * 7;
-  for (int e = 0; e < 9; ++e) K->E[7][e] = (e % 4 == 0) ? 1.f : 0.f;
-  K->r[7][0] = 0.f; K->r[7][1] = 0.f; K->r[7][2] = h[0];
+  for (int b = 7; b < kArmMaxBodies; ++b) {
+    for (int e = 0; e < 9; ++e) K->E[b][e] = (e % 4 == 0) ? 1.f : 0.f;
+    for (int d = 0; d < 3; ++d) K->r[b][d] = K->c[b][d] = 0.f;
+    for (int e = 0; e < 6; ++e) K->Ic[b][e] = 0.f;
+    K->m[b] = 0.f;
+  }
+  K->r[7][2] = h[0];
+  K->bh = K->pm_m = K->pm_z = 0.f;
+  if (ujoint) {
+    K->m[8] = h[1];  // the box; its centre of mass and inertia come from theta
+    return;
+  }
   K->bh = h[1];
   K->m[7] = h[2];
   K->c[7][0] = h[3]; K->c[7][1] = h[4]; K->c[7][2] = h[5];
@@ -559,8 +733,6 @@ __host__ __device__ inline void arm_setup(const float* raw, ArmConst* K) {
 // Kernels
 // ---------------------------------------------------------------------------
 
-using AM = ArmMath<float>;
-
 __device__ inline const ArmConst* arm_const_of(char* ws, uint64_t off) {
   return reinterpret_cast<const ArmConst*>(ws + off);
 }
@@ -568,7 +740,8 @@ __device__ inline const ArmConst* arm_const_of(char* ws, uint64_t off) {
 __global__ void arm_setup_kernel(JobMap map, const pds_job* __restrict__ jobs, char* __restrict__ ws) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  if (threadIdx.x == 0) arm_setup(J.consts, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]));
+  if (threadIdx.x == 0)
+    arm_setup(J.consts, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]), J.model == PDS_MODEL_ARM_UJOINT);
 }
 
 struct AUnit {
@@ -582,13 +755,43 @@ __device__ inline AUnit aunit_of(const pds_job& J, int u) {
   r.j = kj % J.n_s;
   return r;
 }
+template <int DS>
 __device__ inline const float* astart_ptr(const pds_job& J, const AUnit& w) {
-  if (w.j == 0) return J.s0 + (size_t)w.k * kArmDs;
-  return J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + (w.j - 1)) * kArmDs;
+  if (w.j == 0) return J.s0 + (size_t)w.k * DS;
+  return J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + (w.j - 1)) * DS;
 }
 
+// Observation term of the state after a step: -1/2 sum ((obs - x) w)^2
+// without the constant; with qb non-null, its q-adjoint is added there.
+template <int BOX>
+__device__ __forceinline__ float arm_obs_term(const ArmConst& K, const float* q, const float* obs_row,
+                                              const float* w, float* qb) {
+  if (BOX == kHinge) {
+    const float r = (obs_row[0] - q[7]) * w[0];
+    if (qb) qb[7] += r * w[0];
+    return r * r;
+  }
+  float tmp[ArmShape<BOX>::NB];
+  float* acc = qb;
+  if (!qb) {
+    for (int i = 0; i < ArmShape<BOX>::NB; ++i) tmp[i] = 0.f;
+    acc = tmp;
+  }
+  return ArmMath<float, BOX>::box_obs(K, q, obs_row, w, acc);
+}
+
+template <int BOX>
+__device__ inline double arm_obs_log_norm(const pds_job& J) {
+  double c = 0.0;
+  for (int d = 0; d < ArmShape<BOX>::DX; ++d) c += log((double)J.w_x[d]) - 0.91893853320467274178;
+  return c;
+}
+
+template <int BOX>
 __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                             char* ws, int with_ll) {
+  using AM = ArmMath<float, BOX>;
+  constexpr int NB = ArmShape<BOX>::NB, DS = ArmShape<BOX>::DS, M = ArmShape<BOX>::M, DX = ArmShape<BOX>::DX;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const ArmConst& K = *arm_const_of(ws, map.ws_off[e]);
@@ -596,42 +799,40 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   const int u = (blockIdx.x - map.begin[e]) * kWave + threadIdx.x;
   if (u >= U) return;
   const AUnit w = aunit_of(J, u);
-  float th[4];
-  for (int m = 0; m < 4; ++m) th[m] = J.theta[(size_t)w.i * 4 + m];
-  const float* st = astart_ptr(J, w);
-  float q[8], qd[8];
-  for (int d = 0; d < 8; ++d) { q[d] = st[d]; qd[d] = st[8 + d]; }
+  float th[M];
+  for (int m = 0; m < M; ++m) th[m] = J.theta[(size_t)w.i * M + m];
+  const float* st = astart_ptr<DS>(J, w);
+  float q[NB], qd[NB];
+  for (int d = 0; d < NB; ++d) { q[d] = st[d]; qd[d] = st[NB + d]; }
   const float dt = J.dt;
   const int t0 = w.j * J.h;
-  const float* obs = J.obs + ((size_t)w.k * J.T + t0);
-  float* traj = J.traj ? J.traj + (((size_t)w.i * J.K + w.k) * J.T + t0) * kArmDs : nullptr;
-  const float wx = J.w_x[0];
+  const float* obs = J.obs + ((size_t)w.k * J.T + t0) * DX;
+  float* traj = J.traj ? J.traj + (((size_t)w.i * J.K + w.k) * J.T + t0) * DS : nullptr;
+  float wx[DX];
+  for (int d = 0; d < DX; ++d) wx[d] = J.w_x[d];
   double ll = 0.0;
   for (int s = 0; s < J.h; ++s) {
     AM::arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
-    if (with_ll) {
-      const float r = (obs[s] - q[7]) * wx;
-      ll -= 0.5 * (double)(r * r);
-    }
+    if (with_ll) ll -= 0.5 * (double)arm_obs_term<BOX>(K, q, obs + (size_t)s * DX, wx, nullptr);
     if (traj)
-      for (int d = 0; d < 8; ++d) { traj[s * kArmDs + d] = q[d]; traj[s * kArmDs + 8 + d] = qd[d]; }
+      for (int d = 0; d < NB; ++d) { traj[s * DS + d] = q[d]; traj[s * DS + NB + d] = qd[d]; }
   }
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
-  float* es = J.end_states + iu * kArmDs;
+  float* es = J.end_states + iu * DS;
   bool bad = false;
-  for (int d = 0; d < 8; ++d) {
+  for (int d = 0; d < NB; ++d) {
     es[d] = q[d];
-    es[8 + d] = qd[d];
+    es[NB + d] = qd[d];
     bad |= !isfinite(q[d]) || !isfinite(qd[d]);
   }
   if (with_ll) {
-    ll += (double)J.h * (log((double)wx) - 0.91893853320467274178);
+    ll += (double)J.h * arm_obs_log_norm<BOX>(J);
     if (w.j + 1 < J.n_s) {
-      const float* sn = J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j) * kArmDs;
+      const float* sn = J.S + (((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j) * DS;
       double g = 0.0;
-      for (int d = 0; d < 8; ++d) {
+      for (int d = 0; d < NB; ++d) {
         const float e0 = (sn[d] - q[d]) * J.u[d];
-        const float e1 = (sn[8 + d] - qd[d]) * J.u[8 + d];
+        const float e1 = (sn[NB + d] - qd[d]) * J.u[NB + d];
         g += (double)e0 * e0 + (double)e1 * e1;
       }
       g /= (double)J.sigma_def * J.sigma_def;
@@ -650,8 +851,11 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
 // [wave][step][component][lane], so each access is one coalesced row); the
 // reverse sweep reads them back and recomputes only the step's own ABA
 // intermediates.  No LDS: occupancy is set by registers alone.
+template <int BOX>
 __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                             char* ws) {
+  using AM = ArmMath<float, BOX>;
+  constexpr int NB = ArmShape<BOX>::NB, DS = ArmShape<BOX>::DS, M = ArmShape<BOX>::M, DX = ArmShape<BOX>::DX;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const ArmConst& K = *arm_const_of(ws, map.ws_off[e]);
@@ -666,47 +870,47 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   float* gs_obs = reinterpret_cast<float*>(base + L.gs_obs);
   float* gs_con = reinterpret_cast<float*>(base + L.gs_con);
   const AUnit w = aunit_of(J, u);
-  float th[4];
-  for (int m = 0; m < 4; ++m) th[m] = J.theta[(size_t)w.i * 4 + m];
-  const float* st = astart_ptr(J, w);
-  float q[8], qd[8];
-  for (int d = 0; d < 8; ++d) { q[d] = st[d]; qd[d] = st[8 + d]; }
+  float th[M];
+  for (int m = 0; m < M; ++m) th[m] = J.theta[(size_t)w.i * M + m];
+  const float* st = astart_ptr<DS>(J, w);
+  float q[NB], qd[NB];
+  for (int d = 0; d < NB; ++d) { q[d] = st[d]; qd[d] = st[NB + d]; }
   const float dt = J.dt;
   const int h = J.h;
   const int t0 = w.j * h;
-  const float* obs = J.obs + ((size_t)w.k * J.T + t0);
-  const float wx = J.w_x[0];
-  float* states = reinterpret_cast<float*>(base + L.arm_states) + (size_t)(u / kWave) * (h + 1) * kArmDs * kWave;
-  auto slot = [&](int s, int d) -> float& { return states[((size_t)s * kArmDs + d) * kWave + lane]; };
+  const float* obs = J.obs + ((size_t)w.k * J.T + t0) * DX;
+  float wx[DX];
+  for (int d = 0; d < DX; ++d) wx[d] = J.w_x[d];
+  float* states = reinterpret_cast<float*>(base + L.arm_states) + (size_t)(u / kWave) * (h + 1) * DS * kWave;
+  auto slot = [&](int s, int d) -> float& { return states[((size_t)s * DS + d) * kWave + lane]; };
 
   double ll = 0.0;
   for (int s = 0; s < h; ++s) {
-    for (int d = 0; d < 8; ++d) { slot(s, d) = q[d]; slot(s, 8 + d) = qd[d]; }
+    for (int d = 0; d < NB; ++d) { slot(s, d) = q[d]; slot(s, NB + d) = qd[d]; }
     AM::arm_step(K, th, (float)(t0 + s) * dt, dt, q, qd);
-    const float r = (obs[s] - q[7]) * wx;
-    ll -= 0.5 * (double)(r * r);
+    ll -= 0.5 * (double)arm_obs_term<BOX>(K, q, obs + (size_t)s * DX, wx, nullptr);
   }
-  for (int d = 0; d < 8; ++d) { slot(h, d) = q[d]; slot(h, 8 + d) = qd[d]; }
-  ll += (double)h * (log((double)wx) - 0.91893853320467274178);
+  for (int d = 0; d < NB; ++d) { slot(h, d) = q[d]; slot(h, NB + d) = qd[d]; }
+  ll += (double)h * arm_obs_log_norm<BOX>(J);
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
-  float* es = J.end_states + iu * kArmDs;
+  float* es = J.end_states + iu * DS;
   bool bad = false;
-  for (int d = 0; d < 8; ++d) {
+  for (int d = 0; d < NB; ++d) {
     es[d] = q[d];
-    es[8 + d] = qd[d];
+    es[NB + d] = qd[d];
     bad |= !isfinite(q[d]) || !isfinite(qd[d]);
   }
 
-  float qb_o[8], qdb_o[8], qb_c[8], qdb_c[8];
-  for (int d = 0; d < 8; ++d) { qb_o[d] = qdb_o[d] = qb_c[d] = qdb_c[d] = 0.f; }
+  float qb_o[NB], qdb_o[NB], qb_c[NB], qdb_c[NB];
+  for (int d = 0; d < NB; ++d) { qb_o[d] = qdb_o[d] = qb_c[d] = qdb_c[d] = 0.f; }
   if (w.j + 1 < J.n_s) {
     const size_t id = ((size_t)w.i * J.K + w.k) * (J.n_s - 1) + w.j;
-    const float* sn = J.S + id * kArmDs;
-    float e0[8], e1[8];
+    const float* sn = J.S + id * DS;
+    float e0[NB], e1[NB];
     double g = 0.0;
-    for (int d = 0; d < 8; ++d) {
+    for (int d = 0; d < NB; ++d) {
       e0[d] = (sn[d] - q[d]) * J.u[d];
-      e1[d] = (sn[8 + d] - qd[d]) * J.u[8 + d];
+      e1[d] = (sn[NB + d] - qd[d]) * J.u[NB + d];
       g += (double)e0[d] * e0[d] + (double)e1[d] * e1[d];
     }
     const double inv_s2 = 1.0 / ((double)J.sigma_def * J.sigma_def);
@@ -719,45 +923,47 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
     // d g / d s_end = -2 e u / sigma^2; in the likelihood, d(-g/2) / d s_end = e u / sigma^2
     const float sc = (float)(-2.0 * seed * inv_s2);
     const float so = in_lik ? (float)inv_s2 : 0.f;
-    for (int d = 0; d < 8; ++d) {
+    for (int d = 0; d < NB; ++d) {
       qb_o[d] = so * e0[d] * J.u[d];
-      qdb_o[d] = so * e1[d] * J.u[8 + d];
+      qdb_o[d] = so * e1[d] * J.u[NB + d];
       qb_c[d] = sc * e0[d] * J.u[d];
-      qdb_c[d] = sc * e1[d] * J.u[8 + d];
+      qdb_c[d] = sc * e1[d] * J.u[NB + d];
     }
   }
   bad |= !isfinite(ll);
   J.ll_win[iu] = ll;
-  double gm_o[4] = {0.0, 0.0, 0.0, 0.0}, gm_c[4] = {0.0, 0.0, 0.0, 0.0};
+  double gm_o[M], gm_c[M];
+  for (int m = 0; m < M; ++m) gm_o[m] = gm_c[m] = 0.0;
   for (int s = h - 1; s >= 0; --s) {
     {
-      const float x = slot(s + 1, 7);
-      const float r = (obs[s] - x) * wx;
-      qb_o[7] += r * wx;
+      float qn[NB];
+      for (int d = 0; d < NB; ++d) qn[d] = slot(s + 1, d);
+      arm_obs_term<BOX>(K, qn, obs + (size_t)s * DX, wx, qb_o);
     }
-    float qs[8], qds[8];
-    for (int d = 0; d < 8; ++d) { qs[d] = slot(s, d); qds[d] = slot(s, 8 + d); }
-    AM::ArmTape T;
+    float qs[NB], qds[NB];
+    for (int d = 0; d < NB; ++d) { qs[d] = slot(s, d); qds[d] = slot(s, NB + d); }
+    typename AM::ArmTape T;
     const float time = (float)(t0 + s) * dt;
     AM::keep_consts_in_memory();
     AM::arm_aba(K, th, qs, qds, time, T);
-    float tb[4] = {0.f, 0.f, 0.f, 0.f};
+    float tb[M];
+    for (int m = 0; m < M; ++m) tb[m] = 0.f;
     AM::arm_step_rev(K, th, qs, qds, T, dt, qb_o, qdb_o, tb);
-    for (int m = 0; m < 4; ++m) gm_o[m] += (double)tb[m];
-    float tc[4] = {0.f, 0.f, 0.f, 0.f};
-    AM::arm_step_rev(K, th, qs, qds, T, dt, qb_c, qdb_c, tc);
-    for (int m = 0; m < 4; ++m) gm_c[m] += (double)tc[m];
+    for (int m = 0; m < M; ++m) gm_o[m] += (double)tb[m];
+    for (int m = 0; m < M; ++m) tb[m] = 0.f;
+    AM::arm_step_rev(K, th, qs, qds, T, dt, qb_c, qdb_c, tb);
+    for (int m = 0; m < M; ++m) gm_c[m] += (double)tb[m];
   }
-  for (int m = 0; m < 4; ++m) {
-    gth_obs[iu * 4 + m] = gm_o[m];
-    gth_con[iu * 4 + m] = gm_c[m];
+  for (int m = 0; m < M; ++m) {
+    gth_obs[iu * M + m] = gm_o[m];
+    gth_con[iu * M + m] = gm_c[m];
     bad |= !isfinite(gm_o[m]) || !isfinite(gm_c[m]);
   }
-  for (int d = 0; d < 8; ++d) {
-    gs_obs[iu * kArmDs + d] = qb_o[d];
-    gs_obs[iu * kArmDs + 8 + d] = qdb_o[d];
-    gs_con[iu * kArmDs + d] = qb_c[d];
-    gs_con[iu * kArmDs + 8 + d] = qdb_c[d];
+  for (int d = 0; d < NB; ++d) {
+    gs_obs[iu * DS + d] = qb_o[d];
+    gs_obs[iu * DS + NB + d] = qdb_o[d];
+    gs_con[iu * DS + d] = qb_c[d];
+    gs_con[iu * DS + NB + d] = qdb_c[d];
   }
   if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
 }
@@ -771,50 +977,83 @@ hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, 
   return hipGetLastError();
 }
 
-hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(arm_forward_kernel, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, with_ll ? 1 : 0);
+hipError_t launch_arm_forward(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid,
+                              bool with_ll, hipStream_t s) {
+  if (ujoint)
+    hipLaunchKernelGGL(arm_forward_kernel<kUJoint>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, with_ll ? 1 : 0);
+  else
+    hipLaunchKernelGGL(arm_forward_kernel<kHinge>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, with_ll ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(arm_adjoint_kernel, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws);
+hipError_t launch_arm_adjoint(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid,
+                              hipStream_t s) {
+  if (ujoint)
+    hipLaunchKernelGGL(arm_adjoint_kernel<kUJoint>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws);
+  else
+    hipLaunchKernelGGL(arm_adjoint_kernel<kHinge>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws);
   return hipGetLastError();
 }
 
 // Algorithmic FLOPs of one arm time step: the forward step (ABA + Euler +
-// the observation residual and its FP64 accumulation) and the reverse step
-// of one adjoint channel (with its observation seed and the FP64
+// the observation residuals and their FP64 accumulation) and the reverse
+// step of one adjoint channel (with its observation seed and the FP64
 // accumulation of the parameter adjoints), from the same step functions
 // the kernels run, instantiated with the counting scalar.
-void count_arm_flops(double* fwd, double* rev, double* transc) {
-  using CM = ArmMath<Counted>;
+template <int BOX>
+static void count_arm(double* fwd, double* rev, double* transc) {
+  using CM = ArmMath<Counted, BOX>;
+  constexpr int NB = ArmShape<BOX>::NB, M = ArmShape<BOX>::M;
   ArmConst K;
   std::vector<float> raw(126, 0.5f);
   raw[0] = 0.f;
   raw[1] = 0.f;
   raw[2] = -9.81f;
-  arm_setup(raw.data(), &K);
-  Counted th[4] = {0.05f, 0.02f, -0.04f, 0.03f};
-  Counted q[8], qd[8], qb[8], qdb[8], thb[4];
-  for (int i = 0; i < 8; ++i) {
+  arm_setup(raw.data(), &K, BOX == kUJoint);
+  Counted th[11];
+  for (int m = 0; m < 11; ++m) th[m] = Counted(0.01f * (m + 1));
+  Counted q[NB], qd[NB], qb[NB], qdb[NB], thb[M];
+  for (int i = 0; i < NB; ++i) {
     q[i] = Counted(0.1f * i);
     qd[i] = Counted(0.05f);
     qb[i] = Counted(1.f);
     qdb[i] = Counted(1.f);
   }
+  const float obs[12] = {0.1f, 0.2f, 0.3f, 1.f, 0.2f, 0.3f, 0.1f, 1.f, 0.3f, 0.1f, 0.2f, 1.f};
+  const float w[12] = {100.f, 100.f, 100.f, 100.f, 100.f, 100.f, 100.f, 100.f, 100.f, 100.f, 100.f, 100.f};
   g_tally = FlopTally();
-  CM::ArmTape T;
+  typename CM::ArmTape T;
   CM::arm_aba(K, th, q, qd, Counted(0.5f), T);
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < NB; ++i) {
     qd[i] = qd[i] + Counted(0.004f) * T.qdd[i];
     q[i] = q[i] + Counted(0.004f) * qd[i];
   }
-  *fwd = g_tally.flops + 4.0;  // residual (x - q) w, its square, FP64 accumulate
+  if (BOX == kUJoint) {
+    Counted x[12];
+    CM::box_frame(K, q, x);  // the kinematics of the observation, sin/cos included
+  }
+  // + the residuals (x - obs) w, their squares and the FP64 accumulation
+  *fwd = g_tally.flops + (BOX == kUJoint ? 12 * 4 + 2 : 4.0);
   *transc = g_tally.transc;
   g_tally = FlopTally();
   CM::arm_step_rev(K, th, q, qd, T, Counted(0.004f), qb, qdb, thb);
-  *rev = g_tally.flops + 2.0 + 4.0;  // observation seed r w; FP64 accumulation of 4 parameter adjoints
+  const double rev_step = g_tally.flops;
+  double obs_rev = 2.0;  // hinge: the observation seed r w
+  if (BOX == kUJoint) {
+    g_tally = FlopTally();
+    Counted qb2[NB];
+    for (int i = 0; i < NB; ++i) qb2[i] = Counted(0.f);
+    CM::box_obs(K, q, obs, w, qb2);
+    obs_rev = g_tally.flops;
+  }
+  *rev = rev_step + obs_rev + M;  // + the FP64 accumulation of the M parameter adjoints
+}
+
+void count_arm_flops(bool ujoint, double* fwd, double* rev, double* transc) {
+  if (ujoint)
+    count_arm<kUJoint>(fwd, rev, transc);
+  else
+    count_arm<kHinge>(fwd, rev, transc);
 }
 
 }  // namespace pds

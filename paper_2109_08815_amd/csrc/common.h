@@ -86,7 +86,7 @@ struct MedianState {
 // use a region of just that size.
 struct WsLayout {
   size_t arm;                               // derived arm constants (arm jobs)
-  size_t arm_states;                        // arm adjoint: every window state, [wave][step][16][lane]
+  size_t arm_states;                        // arm adjoint: every window state, [wave][step][2 n_dof][lane]
   size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients: [iu][m], [iu][d] with
                                             // iu = (i K + k) n_s + j (one particle's units adjacent)
   size_t med;                               // median selection state
@@ -115,10 +115,11 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   const size_t U = (size_t)J.N * J.K * J.n_s;
   const int ds = 2 * J.n_dof;
   size_t o = 0;
-  L.arm = o;     o = align256(o + (J.model == PDS_MODEL_ARM ? kArmConstBytes : 0));
+  const bool arm = J.model == PDS_MODEL_ARM || J.model == PDS_MODEL_ARM_UJOINT;
+  L.arm = o;     o = align256(o + (arm ? kArmConstBytes : 0));
   const size_t lanes = (U + kWave - 1) / kWave * kWave;
   L.arm_states = o;
-  o = align256(o + (J.model == PDS_MODEL_ARM ? lanes * (J.h + 1) * 16 * sizeof(float) : 0));
+  o = align256(o + (arm ? lanes * (J.h + 1) * (2 * (size_t)J.n_dof) * sizeof(float) : 0));
   L.gth_obs = o; o = align256(o + U * J.M * sizeof(double));
   L.gth_con = o; o = align256(o + U * J.M * sizeof(double));
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
@@ -160,9 +161,10 @@ hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, 
 constexpr int kStepCountBlocks = 256;
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
 hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_arm_forward(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
+hipError_t launch_arm_forward(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
                               hipStream_t s);
-hipError_t launch_arm_adjoint(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
+hipError_t launch_arm_adjoint(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid,
+                              hipStream_t s);
 hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, int ti, hipStream_t s);
 hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
                               hipStream_t s);

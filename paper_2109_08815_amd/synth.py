@@ -110,7 +110,7 @@ CONFIGS = {
     "c2": dict(family="double", N=256, K=4, T=400, n_s=10, dt=0.005, sigma_obs=0.01),
     "c3": dict(family="chain5", N=1024, K=8, T=1000, n_s=20, dt=0.002, sigma_obs=0.02),
     "rigid2": dict(family="rigid", N=256, K=4, T=400, n_s=10, dt=0.005, sigma_obs=0.01),
-    "box1": dict(family="ujoint", N=1024, K=1, T=1200, n_s=24, dt=1.0 / 240.0, sigma_obs=0.01),
+    "box1": dict(family="ujoint", N=2048, K=1, T=1500, n_s=30, dt=1.0 / 240.0, sigma_obs=0.01),
     "c4": dict(family="arm", N=2048, K=1, T=1500, n_s=30, dt=1.0 / 240.0, sigma_obs=0.01),
 }
 

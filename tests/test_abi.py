@@ -74,6 +74,7 @@ def _job(**kw):
     (dict(n_dof=6, M=12, d_x=6), -2), (dict(model=2), -1), (dict(model=7), -1), (dict(M=3), -1),
     (dict(combine=5), -1), (dict(N=32769), -2),
     (dict(model=3), -1), (dict(model=3, n_dof=3, M=17, d_x=3), -2), (dict(d_x=3), -1), (dict(limits=2), -1),
+    (dict(model=4, n_dof=9, M=11, d_x=1), -1),
 ])
 def test_invalid_jobs_rejected_on_host(bad, code):
     lib = L.lib()
@@ -120,6 +121,9 @@ def test_algorithmic_flop_counts():
     assert t == 2 * 8 + 2 * 7
     assert f > 1000 and r > 1000
     assert L.algorithmic_flops(L.PDS_MODEL_ARM, 8) == (f, r, t)
+    # universal joint: a ninth body, the box-frame kinematics and its adjoint
+    uf, ur, ut = L.algorithmic_flops(L.PDS_MODEL_ARM_UJOINT, 9)
+    assert uf > f and ur > r and ut > t
     # rigid links: the same sin/cos per joint, more work per link than point masses
     for n in (1, 2):
         rf, rr, rt = L.algorithmic_flops(L.PDS_MODEL_PLANAR_RIGID, n)

@@ -568,11 +568,64 @@ def test_arm_adjoint_gradients(orc, over):
     assert np.all(np64(job.flags) == 0)
 
 
+BOX_CASES = [
+    dict(N=70, K=1, T=96, n_s=2),       # two windows of 48 steps at dt = 1/240
+    dict(N=33, K=2, T=60, n_s=3),
+    dict(N=24, K=1, T=60, n_s=3, lik=synth.LIK_DEFECT),
+]
+
+
+def box_ll_tolerance(orc, pb, obs, traj_ref, ll_ref):
+    """The window log-likelihood error the state tolerance implies for the
+    box-frame observation: each observed point moves by at most the sum
+    over the 9 joints of |dq| times its distance from the joint (< 2.5 m),
+    with |dq| <= 1e-4 max|x| of the window, plus FP32 rounding of the
+    point itself."""
+    N, K = traj_ref.shape[:2]
+    tr = traj_ref.reshape(N, K, pb.n_s, pb.h, pb.d_s)
+    scale = np.maximum(np.abs(tr).max(axis=(3, 4)), 1e-6)
+    per = np.zeros((N, K, pb.n_s))
+    for i in range(N):
+        for k in range(K):
+            x = orc.observe(pb, pb.particles[i], traj_ref[i, k])
+            r = np.abs((obs[k] - x) * pb.w_x) * pb.w_x
+            dx = 9 * 2.5 * 1e-4 * scale[i, k][:, None] + 1e-6 * np.abs(x).reshape(pb.n_s, pb.h, -1).max(axis=(1, 2))[:, None]
+            per[i, k] = (r.reshape(pb.n_s, pb.h, -1).sum(axis=1) * dx).sum(axis=1)
+    return per + 1e-9 * np.abs(ll_ref)
+
+
+@pytest.mark.parametrize("over", BOX_CASES)
+def test_box_universal_joint_forward_and_loglik(orc, over):
+    """The arm with the box on a universal joint (phase I parameters,
+    box-frame observation): window states, log-likelihoods and defects."""
+    pb, obs, st, job, b = make_case(orc, "box1", perturb_S=0.005, lam=True, with_traj=True, **over)
+    L.loglik_multishoot(b)
+    L.sim_batch_forward(b)
+    ref = orc.forward(pb, obs, st, traj=True)
+    check_states(pb, np64(job.traj), ref["traj"])
+    tol = box_ll_tolerance(orc, pb, obs, ref["traj"], ref["ll_win"])
+    d = np.abs(np64(job.ll_win) - ref["ll_win"])
+    assert np.all(d <= tol), "ll_win worst ratio %.3g" % (d / tol).max()
+
+
+@pytest.mark.parametrize("over", BOX_CASES)
+def test_box_universal_joint_adjoint_gradients(orc, over):
+    pb, obs, st, job, b = make_case(orc, "box1", perturb_S=0.005, lam=True, **over)
+    L.sim_batch_adjoint(b)
+    ref = orc.gradient(pb, obs, st, per_unit=True)
+    assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
+    if pb.n_s > 1:
+        assert grad_err(np64(job.g_con), ref, "con", defect_rel_err(pb, job, ref, st.S)).max() <= 1e-3
+        assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
+    assert np.all(np64(job.flags) == 0)
+
+
 @pytest.mark.parametrize("cfg,over", [("c2", dict(N=16, K=2, T=40, n_s=2)), ("c3", dict(N=16, K=1, T=60, n_s=3)),
                                       ("c4", dict(N=8, T=60, n_s=2)),
                                       ("c2", dict(N=16, K=2, T=60, n_s=3, lik=synth.LIK_DEFECT)),
                                       ("c4", dict(N=8, K=2, T=60, n_s=2, lik=synth.LIK_DEFECT)),
-                                      ("rigid2", dict(N=16, K=2, T=40, n_s=2))])
+                                      ("rigid2", dict(N=16, K=2, T=40, n_s=2)),
+                                      ("box1", dict(N=8, T=48, n_s=2))])
 def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
     """The reverse-mode gradients against central differences of the GPU's
     own forward (FP32 states, FP64 sums), along a random direction in theta
