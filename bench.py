@@ -71,7 +71,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default=None, choices=["c1", "c2", "c3", "c4", "rigid2", "box1"],
+    ap.add_argument("--config", default=None, choices=["c1", "c2", "c3", "c4", "rigid2", "box1", "box2"],
                     help="workload (default c2; c3 with --metrics)")
     ap.add_argument("--metrics", action="store_true",
                     help="time the posterior-consistency metrics (KNN-KL both ways + MMD) between the particles' "
@@ -354,7 +354,8 @@ def main():
             args.config, {"c1": "pendulum", "c2": "double pendulum", "c3": "5-link chain",
                           "c4": "7-joint arm with hinged box",
                           "rigid2": "rigid-link double pendulum",
-                          "box1": "7-joint arm with the box on a universal joint"}[args.config],
+                          "box1": "7-joint arm with the box on a universal joint",
+                          "box2": "7-joint arm with two weights in the box on a universal joint"}[args.config],
             pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain",
             "bandwidth": "concurrent with the adjoint" if not args.no_overlap else "after the adjoint"},
         "iters_per_s": args.steps / elapsed,
@@ -367,8 +368,9 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(args.config),
-            "kernel": ("arm_adjoint_kernel<%s>" % ("universal joint" if model == L.PDS_MODEL_ARM_UJOINT else "hinge"))
-            if model in (L.PDS_MODEL_ARM, L.PDS_MODEL_ARM_UJOINT) else "planar_adjoint_kernel<%d, %s links>" % (
+            "kernel": ("arm_adjoint_kernel<%s>" % {L.PDS_MODEL_ARM: "hinge", L.PDS_MODEL_ARM_UJOINT: "universal joint",
+                                                   L.PDS_MODEL_ARM_UJOINT_WEIGHTS: "universal joint, weights"}[model])
+            if model in (L.PDS_MODEL_ARM, L.PDS_MODEL_ARM_UJOINT, L.PDS_MODEL_ARM_UJOINT_WEIGHTS) else "planar_adjoint_kernel<%d, %s links>" % (
                 pb.n_dof, "rigid" if model == L.PDS_MODEL_PLANAR_RIGID else "point-mass"),
             "kernel_ms": k_ms,
             "flops_per_particle_step": per_step,

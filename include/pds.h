@@ -107,6 +107,16 @@ extern "C" {
  * world coordinates (d_x = 12, in that order); consts (117 floats) =
  * gravity[3], the 7 x 16 arm-joint table of ARM, flange_d, box mass. */
 #define PDS_MODEL_ARM_UJOINT 4
+/* ARM_UJOINT_WEIGHTS: the same universal-joint mount with the box's
+ * phase-I values known and two equal point masses on the box floor to be
+ * found (phase II of the paper's Panda experiment): theta = (x_a, y_a, x_b,
+ * y_b), the in-plane positions of the masses at height z_m in the box
+ * frame, M = 4; n_dof = 9; observes the box frame as ARM_UJOINT (d_x =
+ * 12); consts (130 floats) = gravity[3], the 7 x 16 arm-joint table,
+ * flange_d, box m, box c[3], box inertia about its centre of mass (I_xx,
+ * I_yy, I_zz, I_xy, I_xz, I_yz), the damping of the two axes, point-mass
+ * m, z_m. */
+#define PDS_MODEL_ARM_UJOINT_WEIGHTS 5
 
 #define PDS_COMBINE_SUM 0   /* equally weighted mixture over trajectories, eq. traj_likelihood */
 #define PDS_COMBINE_PROD 1  /* product over trajectories, App. A-B eq. traj_likelihood_prod */

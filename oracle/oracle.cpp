@@ -63,7 +63,9 @@ extern "C" {
 // ring's y axis; theta = the box's inertia about its centre of mass (xx,
 // yy, zz, xy, xz, yz), its centre of mass and the viscous friction of the
 // two joint axes; the observation is the box frame (origin and the points
-// 1 m along its x, y, z axes, in world coordinates).
+// 1 m along its x, y, z axes, in world coordinates), 6 the same mount
+// with the box's inertia and the joints' friction known and theta the
+// in-plane positions of two point masses on the box floor (phase II).
 typedef struct {
   int32_t kind;
   int32_t n_dof;
@@ -78,6 +80,8 @@ typedef struct {
   double flange_d;
   double box_m, box_c[3], box_I[3];
   double pm_m, pm_z;
+  double box_Ioff[3];  // kind 6: the box's products of inertia xy, xz, yz
+  double ujoint_b[2];  // kind 6: viscous friction of the two joint axes
 } OrcModel;
 
 typedef struct {
@@ -153,7 +157,7 @@ Chain<S> build_chain(const OrcModel& md, const S* th) {
       ch.I[i] = rbi<S>(th[rigid_slot(i, 0)], v3<S>(th[rigid_slot(i, 2)], th[rigid_slot(i, 3)], S(0.0)),
                        diag3<S>(Iz, Iz, Iz));
     }
-  } else if (md.kind == 2 || md.kind == 5) {
+  } else if (md.kind == 2 || md.kind == 5 || md.kind == 6) {
     for (int i = 0; i < 7; ++i) {
       const double ca = std::cos(md.dh_alpha[i]), sa = std::sin(md.dh_alpha[i]);
       // Rot_x(alpha) as an active rotation; the coordinate transform is its transpose.
@@ -173,7 +177,7 @@ Chain<S> build_chain(const OrcModel& md, const S* th) {
     ch.jtype[7] = 0;
     ch.axis[7][0] = 1.0; ch.axis[7][1] = 0.0; ch.axis[7][2] = 0.0;
     const M3<S> zero3 = diag3<S>(S(0.0), S(0.0), S(0.0));
-    if (md.kind == 5) {
+    if (md.kind == 5 || md.kind == 6) {
       // massless ring, then the box about the ring's y axis at the same point
       ch.I[7] = rbi<S>(S(0.0), v3zero<S>(), zero3);
       ch.Xtree[8].E = m3ident<S>();
@@ -181,6 +185,17 @@ Chain<S> build_chain(const OrcModel& md, const S* th) {
       ch.jtype[8] = 0;
       ch.axis[8][0] = 0.0; ch.axis[8][1] = 1.0; ch.axis[8][2] = 0.0;
       M3<S> Ic;
+      if (md.kind == 6) {
+        Ic.a[0][0] = S(md.box_I[0]); Ic.a[1][1] = S(md.box_I[1]); Ic.a[2][2] = S(md.box_I[2]);
+        Ic.a[0][1] = Ic.a[1][0] = S(md.box_Ioff[0]);
+        Ic.a[0][2] = Ic.a[2][0] = S(md.box_Ioff[1]);
+        Ic.a[1][2] = Ic.a[2][1] = S(md.box_Ioff[2]);
+        const M6<S> Ib = rbi<S>(S(md.box_m), v3<S>(S(md.box_c[0]), S(md.box_c[1]), S(md.box_c[2])), Ic);
+        const M6<S> Ia = rbi<S>(S(md.pm_m), v3<S>(th[0], th[1], S(md.pm_z)), zero3);
+        const M6<S> Ibb = rbi<S>(S(md.pm_m), v3<S>(th[2], th[3], S(md.pm_z)), zero3);
+        ch.I[8] = m6add(m6add(Ib, Ia), Ibb);
+        return ch;
+      }
       Ic.a[0][0] = th[0]; Ic.a[1][1] = th[1]; Ic.a[2][2] = th[2];
       Ic.a[0][1] = Ic.a[1][0] = th[3];
       Ic.a[0][2] = Ic.a[2][0] = th[4];
@@ -211,7 +226,7 @@ void joint_torque(const OrcModel& md, const S* th, double time, const S* q, cons
     for (int i = 0; i < md.n_dof; ++i) tau[i] = -(md.damping[i] * qd[i]);
   } else if (md.kind == 4) {
     for (int i = 0; i < md.n_dof; ++i) tau[i] = -(th[rigid_slot(i, 4)] * qd[i]);
-  } else if (md.kind == 2 || md.kind == 5) {
+  } else if (md.kind == 2 || md.kind == 5 || md.kind == 6) {
     for (int i = 0; i < 7; ++i) {
       const double ph = md.omega[i] * time + md.phase[i];
       const double qdes = md.qc[i] + md.amp[i] * std::sin(ph);
@@ -220,6 +235,9 @@ void joint_torque(const OrcModel& md, const S* th, double time, const S* q, cons
     }
     if (md.kind == 2) {
       tau[7] = -(md.damping[7] * qd[7]);
+    } else if (md.kind == 6) {
+      tau[7] = -(md.ujoint_b[0] * qd[7]);
+      tau[8] = -(md.ujoint_b[1] * qd[8]);
     } else {
       tau[7] = -(th[9] * qd[7]);
       tau[8] = -(th[10] * qd[8]);
@@ -380,7 +398,7 @@ void frame_points(const Chain<S>& ch, const S* q, S* x) {
 // otherwise the state components listed in obs_index.
 template <class S>
 void observe(const OrcModel& md, const Chain<S>& ch, const S* q, const S* qd, S* x) {
-  if (md.kind == 5) {
+  if (md.kind == 5 || md.kind == 6) {
     frame_points<S>(ch, q, x);
     return;
   }

@@ -34,7 +34,7 @@ class OrcModel(C.Structure):
         ("kp", C.c_double * 7), ("kd", C.c_double * 7), ("qc", C.c_double * 7), ("amp", C.c_double * 7),
         ("omega", C.c_double * 7), ("phase", C.c_double * 7), ("flange_d", C.c_double),
         ("box_m", C.c_double), ("box_c", C.c_double * 3), ("box_I", C.c_double * 3),
-        ("pm_m", C.c_double), ("pm_z", C.c_double),
+        ("pm_m", C.c_double), ("pm_z", C.c_double), ("box_Ioff", C.c_double * 3), ("ujoint_b", C.c_double * 2),
     ]
 
 
@@ -115,6 +115,9 @@ def model_struct(pb) -> OrcModel:
         for d in range(3):
             m.box_c[d] = a["box_c"][d]
             m.box_I[d] = a["box_I"][d]
+            m.box_Ioff[d] = a.get("box_Ioff", np.zeros(3))[d]
+        for d in range(2):
+            m.ujoint_b[d] = a.get("ujoint_b", np.zeros(2))[d]
     return m
 
 
@@ -188,7 +191,7 @@ def observe(pb, theta, states):
     """Observed quantities [n, d_x] of states [n, d_s] (the listed state
     components, or the box-frame points of the universal-joint arm)."""
     states = np.atleast_2d(states)
-    if pb.kind != 5:
+    if pb.kind not in (5, 6):
         return states[:, pb.obs_index]
     m = model_struct(pb)
     th = _f64(theta)

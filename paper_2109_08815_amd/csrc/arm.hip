@@ -41,14 +41,18 @@ namespace pds {
 // bodies; theta = the box's inertia about its centre of mass (xx, yy, zz,
 // xy, xz, yz), its centre of mass and the viscous friction of both axes;
 // observes the box frame: its origin and the points 1 m along its x, y, z
-// axes in world coordinates, 12 numbers).
-enum ArmBox { kHinge = 0, kUJoint = 1 };
+// axes in world coordinates, 12 numbers), or on the universal joint with
+// the box's inertia and the joints' friction known and theta the in-plane
+// positions of two point masses on the box floor (observes the box frame).
+enum ArmBox { kHinge = 0, kUJoint = 1, kUJointWeights = 2 };
 template <int BOX>
 struct ArmShape {
-  static constexpr int NB = BOX == kUJoint ? 9 : 8;   // bodies = joints
+  static constexpr int NB = BOX == kHinge ? 8 : 9;    // bodies = joints
   static constexpr int DS = 2 * NB;                  // state (q, qd)
   static constexpr int M = BOX == kUJoint ? 11 : 4;  // parameters
-  static constexpr int DX = BOX == kUJoint ? 12 : 1; // observed numbers per step
+  static constexpr int DX = BOX == kHinge ? 1 : 12;  // observed numbers per step
+  static constexpr int BOXB = BOX == kHinge ? 7 : 8;  // the box's body
+  static constexpr bool PM = BOX != kUJoint;         // point masses in the box (theta)
 };
 constexpr int kArmMaxBodies = 9;
 
@@ -62,7 +66,8 @@ struct ArmConst {
   float c[kArmMaxBodies][3];   // centre of mass
   float Ic[kArmMaxBodies][6];  // inertia about the COM: xx, xy, xz, yy, yz, zz
   float kp[7], kd[7], qc[7], amp[7], om[7], ph[7];
-  float bh;                 // hinge damping
+  float bh;                 // hinge damping (universal joint with weights: first axis)
+  float b8;                 // universal joint with weights: damping of the second axis
   float pm_m, pm_z;         // point masses: mass each, height in the box frame
 };
 
@@ -76,6 +81,8 @@ __host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincos
 template <class R, int BOX>
 struct ArmMath {
   static constexpr int NB = ArmShape<BOX>::NB;
+  static constexpr int BOXB = ArmShape<BOX>::BOXB;
+  static constexpr bool PM = ArmShape<BOX>::PM;
   struct V3 {
     R x, y, z;
   };
@@ -281,6 +288,8 @@ struct ArmMath {
   __host__ __device__ static inline R arm_tau(const ArmConst& K, const R* th, int i, R time, R q, R qd) {
     if (BOX == kHinge && i == 7) return -K.bh * qd;
     if (BOX == kUJoint && i >= 7) return -th[i + 2] * qd;
+    if (BOX == kUJointWeights && i == 7) return -K.bh * qd;
+    if (BOX == kUJointWeights && i == 8) return -K.b8 * qd;
     R sn, cs;
     sincos_r(K.om[i] * time + K.ph[i], &sn, &cs);
     const R qdes = K.qc[i] + K.amp[i] * sn;
@@ -313,7 +322,7 @@ struct ArmMath {
   __host__ __device__ static __forceinline__ void arm_aba(const ArmConst& K, const R* th, const R* q, const R* qd,
                                           R time, ArmTape& T) {
     R u[NB];
-    const V3 ca = v3(th[0], th[1], K.pm_z), cb = BOX == kHinge ? v3(th[2], th[3], K.pm_z) : v3(0.f, 0.f, 0.f);
+    const V3 ca = v3(th[0], th[1], K.pm_z), cb = PM ? v3(th[2], th[3], K.pm_z) : v3(0.f, 0.f, 0.f);
     const float z0[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -348,7 +357,7 @@ struct ArmMath {
         add_rbi(IA, K.m[i], cm, K.Ic[i]);
         h = rbi_mul(K.m[i], cm, K.Ic[i], T.v[i]);
       }
-      if (BOX == kHinge && i == 7) {
+      if (PM && i == BOXB) {
         add_rbi(IA, K.pm_m, ca, z0);
         add_rbi(IA, K.pm_m, cb, z0);
         h = h + pm_mul(K.pm_m, ca, T.v[i]) + pm_mul(K.pm_m, cb, T.v[i]);
@@ -470,6 +479,9 @@ struct ArmMath {
     }
     if (BOX == kHinge) {
       qdb[7] += -K.bh * lam[7];
+    } else if (BOX == kUJointWeights) {
+      qdb[7] += -K.bh * lam[7];
+      qdb[8] += -K.b8 * lam[8];
     } else {
   #pragma unroll
       for (int i = 7; i < NB; ++i) {
@@ -480,7 +492,7 @@ struct ArmMath {
     // ID part: reverse of RNEA with output seed mu = -lambda.  Total-force
     // adjoints first (outward; they do not depend on the forces):
     // ftb_i = S_i mu_i + X_i ftb_{i-1}.
-    const V3 ca = v3(th[0], th[1], K.pm_z), cb = BOX == kHinge ? v3(th[2], th[3], K.pm_z) : v3(0.f, 0.f, 0.f);
+    const V3 ca = v3(th[0], th[1], K.pm_z), cb = PM ? v3(th[2], th[3], K.pm_z) : v3(0.f, 0.f, 0.f);
     SV ftb[NB];
   #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -546,7 +558,7 @@ struct ArmMath {
         Ifb = rbi_mul(K.m[i], cm, K.Ic[i], fb);
         Ivxfb = rbi_mul(K.m[i], cm, K.Ic[i], vxfb);
       }
-      if (BOX == kHinge && i == 7) {
+      if (PM && i == BOXB) {
         Ia = Ia + pm_mul(K.pm_m, ca, a) + pm_mul(K.pm_m, cb, a);
         h = h + pm_mul(K.pm_m, ca, v) + pm_mul(K.pm_m, cb, v);
         Ifb = Ifb + pm_mul(K.pm_m, ca, fb) + pm_mul(K.pm_m, cb, fb);
@@ -687,8 +699,10 @@ struct ArmMath {
 // gravity[3]; per arm joint 7 x (a, alpha, d, m, cx, cy, cz, Ixx, Iyy, Izz,
 // kp, kd, qc, amp, omega, phase); then for the hinge flange_d, hinge
 // damping, box m, box c[3], box I[3] (diagonal), point-mass m, point-mass
-// z; for the universal joint flange_d, box m.
-__host__ __device__ inline void arm_setup(const float* raw, ArmConst* K, bool ujoint) {
+// z; for the universal joint flange_d, box m; for the universal joint with
+// weights flange_d, box m, box c[3], box I (xx, yy, zz, xy, xz, yz), the
+// damping of both axes, point-mass m, point-mass z.
+__host__ __device__ inline void arm_setup(const float* raw, ArmConst* K, int mount) {
   for (int d = 0; d < 3; ++d) K->g[d] = raw[d];
   for (int i = 0; i < 7; ++i) {
     const float* j = raw + 3 + 16 * i;
@@ -715,9 +729,20 @@ __host__ __device__ inline void arm_setup(const float* raw, ArmConst* K, bool uj
     K->m[b] = 0.f;
   }
   K->r[7][2] = h[0];
-  K->bh = K->pm_m = K->pm_z = 0.f;
-  if (ujoint) {
+  K->bh = K->b8 = K->pm_m = K->pm_z = 0.f;
+  if (mount == kUJoint) {
     K->m[8] = h[1];  // the box; its centre of mass and inertia come from theta
+    return;
+  }
+  if (mount == kUJointWeights) {
+    K->m[8] = h[1];
+    K->c[8][0] = h[2]; K->c[8][1] = h[3]; K->c[8][2] = h[4];
+    K->Ic[8][0] = h[5]; K->Ic[8][1] = h[8]; K->Ic[8][2] = h[9];
+    K->Ic[8][3] = h[6]; K->Ic[8][4] = h[10]; K->Ic[8][5] = h[7];
+    K->bh = h[11];
+    K->b8 = h[12];
+    K->pm_m = h[13];
+    K->pm_z = h[14];
     return;
   }
   K->bh = h[1];
@@ -741,7 +766,8 @@ __global__ void arm_setup_kernel(JobMap map, const pds_job* __restrict__ jobs, c
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   if (threadIdx.x == 0)
-    arm_setup(J.consts, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]), J.model == PDS_MODEL_ARM_UJOINT);
+    arm_setup(J.consts, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]),
+              J.model == PDS_MODEL_ARM_UJOINT ? kUJoint : (J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? kUJointWeights : kHinge));
 }
 
 struct AUnit {
@@ -977,19 +1003,24 @@ hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, 
   return hipGetLastError();
 }
 
-hipError_t launch_arm_forward(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid,
+hipError_t launch_arm_forward(const JobMap& map, int mount, const pds_job* d_jobs, char* ws, int grid,
                               bool with_ll, hipStream_t s) {
-  if (ujoint)
-    hipLaunchKernelGGL(arm_forward_kernel<kUJoint>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, with_ll ? 1 : 0);
+  const int ll = with_ll ? 1 : 0;
+  if (mount == kUJoint)
+    hipLaunchKernelGGL(arm_forward_kernel<kUJoint>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, ll);
+  else if (mount == kUJointWeights)
+    hipLaunchKernelGGL(arm_forward_kernel<kUJointWeights>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, ll);
   else
-    hipLaunchKernelGGL(arm_forward_kernel<kHinge>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, with_ll ? 1 : 0);
+    hipLaunchKernelGGL(arm_forward_kernel<kHinge>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws, ll);
   return hipGetLastError();
 }
 
-hipError_t launch_arm_adjoint(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid,
+hipError_t launch_arm_adjoint(const JobMap& map, int mount, const pds_job* d_jobs, char* ws, int grid,
                               hipStream_t s) {
-  if (ujoint)
+  if (mount == kUJoint)
     hipLaunchKernelGGL(arm_adjoint_kernel<kUJoint>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws);
+  else if (mount == kUJointWeights)
+    hipLaunchKernelGGL(arm_adjoint_kernel<kUJointWeights>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws);
   else
     hipLaunchKernelGGL(arm_adjoint_kernel<kHinge>, dim3(grid), dim3(kWave), 0, s, map, d_jobs, ws);
   return hipGetLastError();
@@ -1005,11 +1036,11 @@ static void count_arm(double* fwd, double* rev, double* transc) {
   using CM = ArmMath<Counted, BOX>;
   constexpr int NB = ArmShape<BOX>::NB, M = ArmShape<BOX>::M;
   ArmConst K;
-  std::vector<float> raw(126, 0.5f);
+  std::vector<float> raw(130, 0.5f);  // the longest consts layout
   raw[0] = 0.f;
   raw[1] = 0.f;
   raw[2] = -9.81f;
-  arm_setup(raw.data(), &K, BOX == kUJoint);
+  arm_setup(raw.data(), &K, BOX);
   Counted th[11];
   for (int m = 0; m < 11; ++m) th[m] = Counted(0.01f * (m + 1));
   Counted q[NB], qd[NB], qb[NB], qdb[NB], thb[M];
@@ -1028,18 +1059,18 @@ static void count_arm(double* fwd, double* rev, double* transc) {
     qd[i] = qd[i] + Counted(0.004f) * T.qdd[i];
     q[i] = q[i] + Counted(0.004f) * qd[i];
   }
-  if (BOX == kUJoint) {
+  if (BOX != kHinge) {
     Counted x[12];
     CM::box_frame(K, q, x);  // the kinematics of the observation, sin/cos included
   }
   // + the residuals (x - obs) w, their squares and the FP64 accumulation
-  *fwd = g_tally.flops + (BOX == kUJoint ? 12 * 4 + 2 : 4.0);
+  *fwd = g_tally.flops + (BOX != kHinge ? 12 * 4 + 2 : 4.0);
   *transc = g_tally.transc;
   g_tally = FlopTally();
   CM::arm_step_rev(K, th, q, qd, T, Counted(0.004f), qb, qdb, thb);
   const double rev_step = g_tally.flops;
   double obs_rev = 2.0;  // hinge: the observation seed r w
-  if (BOX == kUJoint) {
+  if (BOX != kHinge) {
     g_tally = FlopTally();
     Counted qb2[NB];
     for (int i = 0; i < NB; ++i) qb2[i] = Counted(0.f);
@@ -1049,9 +1080,11 @@ static void count_arm(double* fwd, double* rev, double* transc) {
   *rev = rev_step + obs_rev + M;  // + the FP64 accumulation of the M parameter adjoints
 }
 
-void count_arm_flops(bool ujoint, double* fwd, double* rev, double* transc) {
-  if (ujoint)
+void count_arm_flops(int mount, double* fwd, double* rev, double* transc) {
+  if (mount == kUJoint)
     count_arm<kUJoint>(fwd, rev, transc);
+  else if (mount == kUJointWeights)
+    count_arm<kUJointWeights>(fwd, rev, transc);
   else
     count_arm<kHinge>(fwd, rev, transc);
 }

@@ -115,7 +115,7 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   const size_t U = (size_t)J.N * J.K * J.n_s;
   const int ds = 2 * J.n_dof;
   size_t o = 0;
-  const bool arm = J.model == PDS_MODEL_ARM || J.model == PDS_MODEL_ARM_UJOINT;
+  const bool arm = J.model == PDS_MODEL_ARM || J.model == PDS_MODEL_ARM_UJOINT || J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS;
   L.arm = o;     o = align256(o + (arm ? kArmConstBytes : 0));
   const size_t lanes = (U + kWave - 1) / kWave * kWave;
   L.arm_states = o;
@@ -160,10 +160,16 @@ hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, 
 // followed by iter_bump.
 constexpr int kStepCountBlocks = 256;
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
+// Arm box mounts (the kernels' template argument): 0 hinge, 1 universal
+// joint with the box's parameters in theta, 2 universal joint with two
+// point masses in theta.
+inline int arm_mount(int model) {
+  return model == PDS_MODEL_ARM_UJOINT ? 1 : (model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? 2 : 0);
+}
 hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
-hipError_t launch_arm_forward(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
+hipError_t launch_arm_forward(const JobMap& map, int mount, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
                               hipStream_t s);
-hipError_t launch_arm_adjoint(const JobMap& map, bool ujoint, const pds_job* d_jobs, char* ws, int grid,
+hipError_t launch_arm_adjoint(const JobMap& map, int mount, const pds_job* d_jobs, char* ws, int grid,
                               hipStream_t s);
 hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, int ti, hipStream_t s);
 hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,

@@ -42,6 +42,6 @@ inline void sincos_r(Counted x, Counted* sn, Counted* cs) {
 
 // Arm model: forward step, reverse step of one adjoint channel, sin/cos
 // per step (implemented in arm.hip).
-void count_arm_flops(bool ujoint, double* fwd, double* rev, double* transc);
+void count_arm_flops(int mount, double* fwd, double* rev, double* transc);
 
 }  // namespace pds

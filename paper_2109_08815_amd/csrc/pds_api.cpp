@@ -79,6 +79,9 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
   } else if (J.model == PDS_MODEL_ARM_UJOINT) {
     if (J.n_dof != 9 || J.M != 11 || J.d_x != 12)
       return fail(PDS_EINVAL, "job %d: the universal-joint arm model has n_dof = 9, M = 11, d_x = 12", idx);
+  } else if (J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS) {
+    if (J.n_dof != 9 || J.M != 4 || J.d_x != 12)
+      return fail(PDS_EINVAL, "job %d: the universal-joint arm with weights has n_dof = 9, M = 4, d_x = 12", idx);
   } else if (J.model == PDS_MODEL_PLANAR) {
     if (J.n_dof < 1 || J.n_dof > 5)
       return fail(PDS_EUNSUPPORTED, "job %d: planar n_dof %d outside 1..5", idx, J.n_dof);
@@ -148,7 +151,9 @@ int validate_batch(const pds_job* h_jobs, const pds_job* d_jobs, int n_jobs, uns
   return PDS_OK;
 }
 
-bool is_arm(const pds_job& J) { return J.model == PDS_MODEL_ARM || J.model == PDS_MODEL_ARM_UJOINT; }
+bool is_arm(const pds_job& J) {
+  return J.model == PDS_MODEL_ARM || J.model == PDS_MODEL_ARM_UJOINT || J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS;
+}
 
 size_t job_ws(const pds_job& J, int which) {
   const WsLayout L = pds::ws_layout(J);
@@ -229,14 +234,13 @@ int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with
   if (rc) return rc;
   int slot = -1;
   if (with_ll) timing_begin(s, &slot);
-  for (int model : {PDS_MODEL_ARM, PDS_MODEL_ARM_UJOINT}) {
+  for (int model : {PDS_MODEL_ARM, PDS_MODEL_ARM_UJOINT, PDS_MODEL_ARM_UJOINT_WEIGHTS}) {
     int grid = 0;
     JobMap m = make_map(
         h_jobs, n, off, [&](const pds_job& J) { return J.model == model; },
         [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
     if (m.n > 0) {
-      rc = launch_rc(pds::launch_arm_forward(m, model == PDS_MODEL_ARM_UJOINT, d_jobs, w, grid, with_ll, s),
-                     "arm_forward");
+      rc = launch_rc(pds::launch_arm_forward(m, pds::arm_mount(model), d_jobs, w, grid, with_ll, s), "arm_forward");
       if (rc) return rc;
     }
   }
@@ -432,7 +436,10 @@ size_t pds_job_footprint(const pds_job* h_job) {
   if (validate_job(J, 0, 0)) return 0;
   const size_t N = J.N, K = J.K, T = J.T, ns = J.n_s, M = J.M, ds = 2 * (size_t)J.n_dof, dx = J.d_x;
   const size_t nsm = ns - 1, nsm1 = nsm > 0 ? nsm : 1;
-  size_t f32 = J.model == PDS_MODEL_ARM ? 126 : (J.model == PDS_MODEL_ARM_UJOINT ? 117 : 2 + (size_t)J.n_dof);  // consts
+  size_t f32 = J.model == PDS_MODEL_ARM ? 126
+               : J.model == PDS_MODEL_ARM_UJOINT ? 117
+               : J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? 130
+                                                    : 2 + (size_t)J.n_dof;  // consts
   f32 += 3 * M + dx + ds + M + ds + K * ds + K * T * dx;              // lo hi rho w_x u lr_theta lr_S s0 obs
   f32 += N * M + N * K * nsm * ds + N * M + N * K * nsm;               // theta S lam_lim lam_def
   f32 += 2 * N * (M + K * nsm * ds);                                   // adam_m adam_v
@@ -479,13 +486,13 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   // Launch shapes are chosen per job from its own size, never from the
   // batch, so a job runs the same code path alone and in any mix; jobs
   // sharing a shape share a launch.
-  for (int model : {PDS_MODEL_ARM, PDS_MODEL_ARM_UJOINT}) {
+  for (int model : {PDS_MODEL_ARM, PDS_MODEL_ARM_UJOINT, PDS_MODEL_ARM_UJOINT_WEIGHTS}) {
     int grid = 0;
     JobMap m = make_map(
         h_jobs, n_jobs, off, [&](const pds_job& J) { return J.model == model; },
         [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
     if (m.n > 0) {
-      rc = launch_rc(pds::launch_arm_adjoint(m, model == PDS_MODEL_ARM_UJOINT, d_jobs, w, grid, s), "arm_adjoint");
+      rc = launch_rc(pds::launch_arm_adjoint(m, pds::arm_mount(model), d_jobs, w, grid, s), "arm_adjoint");
       if (rc) return rc;
     }
   }

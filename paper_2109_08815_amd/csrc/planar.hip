@@ -877,8 +877,8 @@ void count_planar(double* fwd, double* rev, double* transc) {
 extern "C" int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_step, double* rev_step,
                                      double* transcendental) {
   if (!fwd_step || !rev_step || !transcendental) return PDS_EINVAL;
-  if (model == PDS_MODEL_ARM || model == PDS_MODEL_ARM_UJOINT) {
-    count_arm_flops(model == PDS_MODEL_ARM_UJOINT, fwd_step, rev_step, transcendental);
+  if (model == PDS_MODEL_ARM || model == PDS_MODEL_ARM_UJOINT || model == PDS_MODEL_ARM_UJOINT_WEIGHTS) {
+    count_arm_flops(pds::arm_mount(model), fwd_step, rev_step, transcendental);
     return PDS_OK;
   }
   if (model == PDS_MODEL_PLANAR_RIGID) {

@@ -73,7 +73,7 @@ def gpu_observations(pb, device="cuda"):
     """Observed trajectories [K, T, d_x]: trajectory k rolled out at theta_true[k] from s0[k] plus noise."""
     tr = gpu_rollout(pb, pb.theta_true, device)
     k = torch.arange(pb.K, device=tr.device)
-    if pb.kind == synth.KIND_ARM_UJOINT:
+    if pb.kind in (synth.KIND_ARM_UJOINT, synth.KIND_ARM_UJOINT_WEIGHTS):
         q = tr[k, k][:, :, : pb.n_dof].double().cpu().numpy()
         x = np.stack([box_frame_points(pb, q[j]) for j in range(pb.K)])
         return x + pb.noise

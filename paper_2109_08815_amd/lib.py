@@ -22,6 +22,7 @@ PDS_MODEL_PLANAR = 1
 PDS_MODEL_ARM = 2
 PDS_MODEL_PLANAR_RIGID = 3
 PDS_MODEL_ARM_UJOINT = 4
+PDS_MODEL_ARM_UJOINT_WEIGHTS = 5
 PDS_COMBINE_SUM = 0
 PDS_COMBINE_PROD = 1
 PDS_LIK_MDMM = 0
@@ -144,6 +145,15 @@ def model_consts(pb):
                     a["kp"][i], a["kd"][i], a["qc"][i], a["amp"][i], a["omega"][i], a["phase"][i]]
         out += [a["flange_d"], a["box_m"]]
         return PDS_MODEL_ARM_UJOINT, np.asarray(out, dtype=np.float64)
+    if pb.kind == 6:
+        a = pb.arm
+        out = list(pb.gravity[:3])
+        for i in range(7):
+            out += [a["dh_a"][i], a["dh_alpha"][i], a["dh_d"][i], a["link_m"][i], *a["link_c"][i], *a["link_I"][i],
+                    a["kp"][i], a["kd"][i], a["qc"][i], a["amp"][i], a["omega"][i], a["phase"][i]]
+        out += [a["flange_d"], a["box_m"], *a["box_c"], *a["box_I"], *a["box_Ioff"], *a["ujoint_b"], a["pm_m"],
+                a["pm_z"]]
+        return PDS_MODEL_ARM_UJOINT_WEIGHTS, np.asarray(out, dtype=np.float64)
     raise PdsError("no GPU model for problem kind %d" % pb.kind)
 
 

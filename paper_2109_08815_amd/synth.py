@@ -30,6 +30,10 @@ synthetic stand-ins for the recordings the paper used, Sec. IV):
   viscous friction of the two joint axes, inside the phase-I table's
   bounds; box mass 0.92 kg known; observes the box frame (origin and the
   points 1 m along its axes, 12 numbers)                           (M = 11)
+* ``box2`` the same universal-joint mount with the box's phase-I values
+  known and two 0.5 kg weights on the box floor (phase II): theta = their
+  in-plane positions inside the phase-II table's bounds; observes the box
+  frame                                                            (M = 4)
 * ``toy`` one prismatic unit mass driven by force theta0 (+ theta1 * time),
   the linear-Gaussian check problem                                 (M = 1, 2)
 
@@ -50,6 +54,7 @@ KIND_ARM = 2
 KIND_TOY = 3
 KIND_PLANAR_RIGID = 4
 KIND_ARM_UJOINT = 5
+KIND_ARM_UJOINT_WEIGHTS = 6
 
 COMBINE_SUM = 0
 COMBINE_PROD = 1
@@ -111,6 +116,7 @@ CONFIGS = {
     "c3": dict(family="chain5", N=1024, K=8, T=1000, n_s=20, dt=0.002, sigma_obs=0.02),
     "rigid2": dict(family="rigid", N=256, K=4, T=400, n_s=10, dt=0.005, sigma_obs=0.01),
     "box1": dict(family="ujoint", N=2048, K=1, T=1500, n_s=30, dt=1.0 / 240.0, sigma_obs=0.01),
+    "box2": dict(family="ujoint_weights", N=2048, K=1, T=1500, n_s=30, dt=1.0 / 240.0, sigma_obs=0.01),
     "c4": dict(family="arm", N=2048, K=1, T=1500, n_s=30, dt=1.0 / 240.0, sigma_obs=0.01),
 }
 
@@ -163,7 +169,7 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         base = dict(family="toy", N=256, K=1, T=50, n_s=1, dt=0.1, sigma_obs=0.5)
     base.update({k: v for k, v in over.items() if k in ("N", "K", "T", "n_s", "dt", "sigma_obs")})
     fam = base["family"]
-    idx = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "rigid2": 5, "box1": 6, "toy": 9}.get(config, 7)
+    idx = {"c1": 1, "c2": 2, "c3": 3, "c4": 4, "rigid2": 5, "box1": 6, "box2": 8, "toy": 9}.get(config, 7)
     if seed is None:
         seed = 1000 * idx
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -227,6 +233,28 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         hi = np.array([0.1, 0.1, 0.1, 0.01, 0.01, 0.01, 0.005, 0.005, 0.4, 0.15, 0.15])
         arm = _arm_constants(rng)
         arm["box_m"] = 0.92
+        gravity = np.array([0.0, 0.0, -9.81])
+        d_x = 12
+        obs_index = np.arange(12)
+        s0 = np.zeros((K, 18))
+        s0[:, :7] = arm["qc"] + arm["amp"] * np.sin(arm["phase"])
+        s0[:, 9:16] = arm["amp"] * arm["omega"] * np.cos(arm["phase"])
+    elif fam == "ujoint_weights":
+        kind = KIND_ARM_UJOINT_WEIGHTS
+        n = 9
+        M = 4
+        lo = np.array([-0.14, -0.08, -0.14, -0.08])
+        hi = np.array([0.14, 0.08, 0.14, 0.08])
+        arm = _arm_constants(rng)
+        # the empty box as phase I would have found it (seeded, inside that
+        # table's bounds), two 0.5 kg weights on its floor
+        arm["box_m"] = 0.92
+        arm["box_c"] = np.array([rng.uniform(-0.005, 0.005), rng.uniform(-0.005, 0.005), rng.uniform(0.1, 0.4)])
+        arm["box_I"] = rng.uniform(0.05, 0.1, 3)
+        arm["box_Ioff"] = rng.uniform(-0.01, 0.01, 3)
+        arm["ujoint_b"] = rng.uniform(0.0, 0.15, 2)
+        arm["pm_m"] = 0.5
+        arm["pm_z"] = 0.4
         gravity = np.array([0.0, 0.0, -9.81])
         d_x = 12
         obs_index = np.arange(12)

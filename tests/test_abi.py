@@ -124,6 +124,8 @@ def test_algorithmic_flop_counts():
     # universal joint: a ninth body, the box-frame kinematics and its adjoint
     uf, ur, ut = L.algorithmic_flops(L.PDS_MODEL_ARM_UJOINT, 9)
     assert uf > f and ur > r and ut > t
+    wf, wr, wt = L.algorithmic_flops(L.PDS_MODEL_ARM_UJOINT_WEIGHTS, 9)
+    assert wf > f and wr > r and wt == ut
     # rigid links: the same sin/cos per joint, more work per link than point masses
     for n in (1, 2):
         rf, rr, rt = L.algorithmic_flops(L.PDS_MODEL_PLANAR_RIGID, n)

@@ -594,11 +594,13 @@ def box_ll_tolerance(orc, pb, obs, traj_ref, ll_ref):
     return per + 1e-9 * np.abs(ll_ref)
 
 
+@pytest.mark.parametrize("cfg", ["box1", "box2"])
 @pytest.mark.parametrize("over", BOX_CASES)
-def test_box_universal_joint_forward_and_loglik(orc, over):
-    """The arm with the box on a universal joint (phase I parameters,
-    box-frame observation): window states, log-likelihoods and defects."""
-    pb, obs, st, job, b = make_case(orc, "box1", perturb_S=0.005, lam=True, with_traj=True, **over)
+def test_box_universal_joint_forward_and_loglik(orc, cfg, over):
+    """The arm with the box on a universal joint (phase I: the box's
+    parameters; phase II: two weights in the box), box-frame observation:
+    window states, log-likelihoods and defects."""
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.005, lam=True, with_traj=True, **over)
     L.loglik_multishoot(b)
     L.sim_batch_forward(b)
     ref = orc.forward(pb, obs, st, traj=True)
@@ -608,9 +610,10 @@ def test_box_universal_joint_forward_and_loglik(orc, over):
     assert np.all(d <= tol), "ll_win worst ratio %.3g" % (d / tol).max()
 
 
+@pytest.mark.parametrize("cfg", ["box1", "box2"])
 @pytest.mark.parametrize("over", BOX_CASES)
-def test_box_universal_joint_adjoint_gradients(orc, over):
-    pb, obs, st, job, b = make_case(orc, "box1", perturb_S=0.005, lam=True, **over)
+def test_box_universal_joint_adjoint_gradients(orc, cfg, over):
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.005, lam=True, **over)
     L.sim_batch_adjoint(b)
     ref = orc.gradient(pb, obs, st, per_unit=True)
     assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
@@ -625,7 +628,7 @@ def test_box_universal_joint_adjoint_gradients(orc, over):
                                       ("c2", dict(N=16, K=2, T=60, n_s=3, lik=synth.LIK_DEFECT)),
                                       ("c4", dict(N=8, K=2, T=60, n_s=2, lik=synth.LIK_DEFECT)),
                                       ("rigid2", dict(N=16, K=2, T=40, n_s=2)),
-                                      ("box1", dict(N=8, T=48, n_s=2))])
+                                      ("box1", dict(N=8, T=48, n_s=2)), ("box2", dict(N=8, T=48, n_s=2))])
 def test_adjoint_matches_central_differences_of_gpu_likelihood(orc, cfg, over):
     """The reverse-mode gradients against central differences of the GPU's
     own forward (FP32 states, FP64 sums), along a random direction in theta

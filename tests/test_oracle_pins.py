@@ -24,7 +24,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # Dynamics (App. B-A: ABA forward dynamics + semi-implicit Euler)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1", "toy"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1", "box2", "toy"])
 def test_aba_equals_crba_rnea(orc, cfg):
     """ABA's q_dd equals H^{-1}(tau - C) from CRBA + RNEA (independent algorithms)."""
     pb = synth.make_problem(cfg, N=4, K=1, T=10, n_s=1)
@@ -300,10 +300,11 @@ def _box_frame_by_homogeneous_matrices(a, q):
     return np.concatenate([p[:3] for p in pts])
 
 
-def test_universal_joint_box_frame_points(orc):
+@pytest.mark.parametrize("cfg", ["box1", "box2"])
+def test_universal_joint_box_frame_points(orc, cfg):
     """The observed box frame equals forward kinematics written with
     homogeneous matrices from the DH table (an independent formulation)."""
-    pb = synth.make_problem("box1", N=4, T=24, n_s=1)
+    pb = synth.make_problem(cfg, N=4, T=24, n_s=1)
     rng = np.random.default_rng(21)
     for _ in range(10):
         th = pb.lo + rng.uniform(size=pb.M) * (pb.hi - pb.lo)
@@ -332,6 +333,25 @@ def test_universal_joint_inertia_parallel_axis(orc):
         assert abs(H[7, 8] - (th[3] - m * cx * cy)) <= 1e-14
 
 
+def test_universal_joint_weights_inertia_parallel_axis(orc):
+    """Phase II: with q_8 = 0 the two passive axes see the box (parallel
+    axis) plus the two point masses at (x_w, y_w, z_m): H_77 = I_xx +
+    m (c_y^2 + c_z^2) + m_w sum (y_w^2 + z_m^2), H_88 = I_yy + m (c_x^2 +
+    c_z^2) + m_w sum (x_w^2 + z_m^2)."""
+    pb = synth.make_problem("box2", N=4, T=24, n_s=1)
+    a = pb.arm
+    m, c, I, mw, zm = a["box_m"], a["box_c"], a["box_I"], a["pm_m"], a["pm_z"]
+    rng = np.random.default_rng(23)
+    for _ in range(5):
+        th = pb.lo + rng.uniform(size=4) * (pb.hi - pb.lo)
+        s = rng.uniform(-1.0, 1.0, 18)
+        s[8] = 0.0
+        H, _ = orc.crba_rnea(pb, th, s[:9], s[9:])
+        h77 = I[0] + m * (c[1] ** 2 + c[2] ** 2) + mw * (th[1] ** 2 + th[3] ** 2 + 2 * zm * zm)
+        h88 = I[1] + m * (c[0] ** 2 + c[2] ** 2) + mw * (th[0] ** 2 + th[2] ** 2 + 2 * zm * zm)
+        assert abs(H[7, 7] - h77) <= 1e-13 and abs(H[8, 8] - h88) <= 1e-13
+
+
 # --------------------------------------------------------------------------
 # Likelihood, multiple shooting, combination (Sec. III-B, III-C, App. A-B)
 # --------------------------------------------------------------------------
@@ -344,7 +364,7 @@ def _setup(orc, cfg, **kw):
     return pb, obs, st
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1", "box2"])
 def test_multiple_shooting_on_trajectory_equals_single(orc, cfg):
     """Shooting states taken from the single-shooting rollout give zero
     defects, and the window log-likelihoods sum to the single-shooting one."""
@@ -413,7 +433,7 @@ def _total_phi(pb, f, lam_def):
     return np.sum(lam_def * g + 0.5 * pb.c * g * g, axis=(1, 2))
 
 
-@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1"])
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3", "c4", "rigid2", "box1", "box2"])
 def test_dual_gradients_match_finite_differences(orc, cfg):
     """g_obs = d log p / d theta, g_con = d Phi / d theta and S_dot =
     d (log p - Phi) / d S, with Phi = sum (lam g + c/2 g^2), by central
@@ -527,10 +547,11 @@ def test_mass_scale_invariance(orc):
     assert np.all(np.abs(lhs) > 1e-6 * np.linalg.norm(g, axis=1))
 
 
-def test_arm_weight_swap_symmetry(orc):
+@pytest.mark.parametrize("cfg", ["c4", "box2"])
+def test_arm_weight_swap_symmetry(orc, cfg):
     """Equal point masses: swapping their positions leaves log p unchanged
     and permutes the gradient (the symmetry reported in Sec. IV-C)."""
-    pb, obs, st = _setup(orc, "c4", N=3, K=1, T=100, n_s=2)
+    pb, obs, st = _setup(orc, cfg, N=3, K=1, T=100, n_s=2)
     sw = st.theta[:, [2, 3, 0, 1]]
     st2 = orc.State(pb, sw, st.S)
     g1 = orc.gradient(pb, obs, st)
