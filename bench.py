@@ -39,6 +39,8 @@ TRAFFIC_PROFILES = {
     "c3": ("planar_adjoint_c3_traffic.md", "planar.hip"),
     "c4": ("arm_adjoint_c4_traffic.md", "arm.hip"),
     "rigid2": ("planar_adjoint_rigid2_traffic.md", "planar.hip"),
+    "box1": ("arm_adjoint_box1_traffic.md", "arm.hip"),
+    "box2": ("arm_adjoint_box2_traffic.md", "arm.hip"),
     "metrics_c3": ("metric_dist_c3_traffic.md", "metrics.hip"),
 }
 
