@@ -33,6 +33,20 @@ namespace pds {
 namespace {
 
 __host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincos_fast(x, sn, cs); }
+// FP64 versions for host-side checks of the step functions.
+__host__ __device__ inline void sincos_r(double x, double* sn, double* cs) {
+  *sn = sin(x);
+  *cs = cos(x);
+}
+
+// A load through a global-memory pointer.  The job's arrays reach the
+// kernels as generic pointers, whose loads also count against the LDS wait
+// counter; typed as global they count only against the vector-memory one,
+// in order, so a load issued a step ahead is not waited for by the next LDS
+// access or by older loads.
+__device__ __forceinline__ float ldg(const float* p) {
+  return *(const __attribute__((address_space(1))) float*)p;
+}
 
 // Link parameters.  Point-mass chain (PDS_MODEL_PLANAR): mass m_i at the
 // tip of a massless rod of length l_i, joint i+1 at that tip.  Rigid chain
@@ -82,9 +96,84 @@ struct Tape {
   R qdd[NB];
 };
 
+// Two point-mass links in closed form.  The forward dynamics of the chain
+// are unique, so for n_dof = 2 they can be written out in joint
+// coordinates instead of running the ABA passes: with phi_1 = q_1,
+// phi_2 = q_1 + q_2, a = (m_1 + m_2) l_1^2, b = m_2 l_2^2,
+// c = m_2 l_1 l_2 cos q_2 and s~ = m_2 l_1 l_2 sin q_2 the joint-space
+// inertia is H = [[a + b + 2c, b + c], [b + c, b]], and H qdd = r with
+//   r_1 = -b_1 qd_1 + s~ (2 qd_1 qd_2 + qd_2^2) + (m_1 + m_2) l_1 e_1 + m_2 l_2 e_2
+//   r_2 = -b_2 qd_2 - s~ qd_1^2 + m_2 l_2 e_2,
+// e_i = g . (cos phi_i, sin phi_i) (Coriolis and centripetal terms,
+// gravity, joint damping).  A quarter of the ABA's arithmetic.  The tape
+// keeps sin/cos of q_1, q_2, qdd and 1 / det H.
+template <class R>
+__host__ __device__ __forceinline__ void dp2_forward(const Planar<2, R>& P, const R* q, const R* qd, Tape<2, R>& T) {
+  sincos_r(q[0], &T.sn[0], &T.cs[0]);
+  sincos_r(q[1], &T.sn[1], &T.cs[1]);
+  const R s1 = T.sn[0], c1 = T.cs[0], s2 = T.sn[1], c2 = T.cs[1];
+  const R s12 = s1 * c2 + c1 * s2, c12 = c1 * c2 - s1 * s2;
+  const R m1 = P.m[0], m2 = P.m[1], l1 = P.l[0], l2 = P.l[1];
+  const R k = m2 * l1 * l2;
+  const R cc = k * c2, st = k * s2;
+  const R a = (m1 + m2) * l1 * l1, bb = m2 * l2 * l2;
+  const R H11 = a + bb + 2.f * cc, H12 = bb + cc, H22 = bb;
+  const R e1 = P.gx * c1 + P.gy * s1, e2 = P.gx * c12 + P.gy * s12;
+  const R g2 = m2 * l2 * e2;
+  const R r1 = -P.b[0] * qd[0] + st * (2.f * qd[0] * qd[1] + qd[1] * qd[1]) + (m1 + m2) * l1 * e1 + g2;
+  const R r2 = -P.b[1] * qd[1] - st * qd[0] * qd[0] + g2;
+  const R idet = recip(H11 * H22 - H12 * H12);
+  T.invD[0] = idet;
+  T.qdd[0] = (H22 * r1 - H12 * r2) * idet;
+  T.qdd[1] = (H11 * r2 - H12 * r1) * idet;
+}
+
+// Reverse of dp2_forward: qdd = H^{-1} r, so with lambda = H^{-1} qddb
+// (H is symmetric) every input x gets lambda . (dr/dx - (dH/dx) qdd).
+template <class R>
+__host__ __device__ __forceinline__ void dp2_reverse(const Planar<2, R>& P, const R* qd, const Tape<2, R>& T,
+                                                     const R* qddb, R* qb, R* qdb, R* thb) {
+  const R s1 = T.sn[0], c1 = T.cs[0], s2 = T.sn[1], c2 = T.cs[1];
+  const R s12 = s1 * c2 + c1 * s2, c12 = c1 * c2 - s1 * s2;
+  const R m1 = P.m[0], m2 = P.m[1], l1 = P.l[0], l2 = P.l[1];
+  const R k = m2 * l1 * l2;
+  const R cc = k * c2, st = k * s2;
+  const R bb = m2 * l2 * l2;
+  const R H11 = (m1 + m2) * l1 * l1 + bb + 2.f * cc, H12 = bb + cc, H22 = bb;
+  const R idet = T.invD[0];
+  const R lam1 = (H22 * qddb[0] - H12 * qddb[1]) * idet;
+  const R lam2 = (H11 * qddb[1] - H12 * qddb[0]) * idet;
+  const R x1 = T.qdd[0], x2 = T.qdd[1];
+  // lambda^T (dH/dx) qdd = mu11 dH11 + mu12 dH12 + mu22 dH22
+  const R mu11 = lam1 * x1, mu12 = lam1 * x2 + lam2 * x1, mu22 = lam2 * x2;
+  const R e1 = P.gx * c1 + P.gy * s1, e2 = P.gx * c12 + P.gy * s12;
+  const R f1 = P.gy * c1 - P.gx * s1, f2 = P.gy * c12 - P.gx * s12;  // d e_i / d phi_i
+  const R w1 = qd[0], w2 = qd[1];
+  const R cor = 2.f * w1 * w2 + w2 * w2;  // r_1's factor of s~
+  const R lsum = lam1 + lam2;
+  // joint angles
+  qb[0] += lam1 * (m1 + m2) * l1 * f1 + lsum * m2 * l2 * f2;
+  qb[1] += lam1 * cc * cor - lam2 * cc * w1 * w1 + lsum * m2 * l2 * f2 + st * (2.f * mu11 + mu12);
+  // joint velocities
+  qdb[0] += lam1 * (-P.b[0] + 2.f * st * w2) - lam2 * 2.f * st * w1;
+  qdb[1] += lam1 * 2.f * st * (w1 + w2) - lam2 * P.b[1];
+  // theta = (m_1, m_2, l_1, l_2)
+  const R hl = l1 * l2;
+  thb[0] += lam1 * l1 * e1 - mu11 * l1 * l1;
+  thb[1] += lam1 * (hl * s2 * cor + l1 * e1 + l2 * e2) + lam2 * (l2 * e2 - hl * s2 * w1 * w1) -
+            (mu11 * (l1 * l1 + l2 * l2 + 2.f * hl * c2) + mu12 * (l2 * l2 + hl * c2) + mu22 * l2 * l2);
+  thb[2] += lam1 * (m2 * l2 * s2 * cor + (m1 + m2) * e1) - lam2 * m2 * l2 * s2 * w1 * w1 -
+            (mu11 * (2.f * (m1 + m2) * l1 + 2.f * m2 * l2 * c2) + mu12 * m2 * l2 * c2);
+  thb[3] += lam1 * (m2 * l1 * s2 * cor + m2 * e2) + lam2 * (m2 * e2 - m2 * l1 * s2 * w1 * w1) -
+            (mu11 * (2.f * m2 * l2 + 2.f * m2 * l1 * c2) + mu12 * (2.f * m2 * l2 + m2 * l1 * c2) + mu22 * 2.f * m2 * l2);
+}
+
 // Articulated Body Algorithm, planar form.  Fills the tape; qdd in T.qdd.
 template <int NB, class R = float, bool RIGID = false>
 __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q, const R* qd, Tape<NB, R>& T) {
+  if constexpr (NB == 2 && !RIGID) {
+    dp2_forward<R>(P, q, qd, T);
+  } else {
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     sincos_r(q[i], &T.sn[i], &T.cs[i]);
@@ -165,6 +254,7 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
     T.qdd[i] = qdd;
     a0 = ap0 + qdd; a1 = ap1; a2 = ap2;
   }
+  }
 }
 
 // Reverse of aba(): given qddb = d L / d qdd, accumulates d L / d q, d L / d qd
@@ -172,6 +262,9 @@ __host__ __device__ __forceinline__ void aba(const Planar<NB, R>& P, const R* q,
 template <int NB, class R = float, bool RIGID = false>
 __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R* qd, const Tape<NB, R>& T,
                                         const R* qddb_in, R* qb, R* qdb, R* thb) {
+  if constexpr (NB == 2 && !RIGID) {
+    dp2_reverse<R>(P, qd, T, qddb_in, qb, qdb, thb);
+  } else {
   using PP = PlanarParams<NB, RIGID>;
   R csb[NB], snb[NB], Lb[NB], taub[NB];
   R IAb[NB][6], pAb[NB][3], vb[NB][3], cb1[NB], cb2[NB];
@@ -385,6 +478,7 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
       if (i > 0) thb[PP::l(i - 1)] += Lb[i];
     }
   }
+  }
 }
 
 // Semi-implicit Euler: qd' = qd + dt qdd, q' = q + dt qd'.
@@ -478,7 +572,7 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
   const float* st = start_ptr(J, w, DS);
   float q[NB], qd[NB];
 #pragma unroll
-  for (int d = 0; d < NB; ++d) { q[d] = st[d]; qd[d] = st[NB + d]; }
+  for (int d = 0; d < NB; ++d) { q[d] = ldg(st + d); qd[d] = ldg(st + NB + d); }
   const float dt = J.dt;
   const int t0 = w.j * J.h;
   const float* obs = J.obs + ((size_t)w.k * J.T + t0) * J.d_x;
@@ -489,6 +583,24 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
   float wx[DS];
 #pragma unroll
   for (int d = 0; d < DS; ++d) wx[d] = (d < NB || obs_v) ? J.w_x[d] : 0.f;
+  constexpr bool kAhead = NB <= 2;
+  // Short chains (kAhead) read observation rows one step ahead, so each
+  // load's latency hides behind a step of arithmetic instead of stalling the
+  // wave; longer chains have enough arithmetic per step to hide a load made
+  // at its use, and the extra live registers would cost them more.
+  // load_row is unconditional and in bounds (no branch the compiler must
+  // merge): when only q is observed the velocity half reads a value of the
+  // same row, which is never used.
+  auto load_row = [&](int s, float* o) {
+    const float* row = obs + (size_t)s * DX;
+#pragma unroll
+    for (int d = 0; d < NB; ++d) o[d] = ldg(row + d);
+#pragma unroll
+    for (int d = 0; d < NB; ++d) o[NB + d] = ldg(row + min(NB + d, DX - 1));
+  };
+  float ob[DS] = {};
+  auto obs_at = [&](int s, int d) -> float { return kAhead ? ob[d] : obs[s * DX + d]; };
+  if (kAhead && with_ll && J.h > 0) load_row(0, ob);
   double ll = 0.0;
   for (int s = 0; s < J.h; ++s) {
     step<NB, float, RIGID>(P, dt, q, qd);
@@ -496,17 +608,18 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
       float acc = 0.f;
 #pragma unroll
       for (int d = 0; d < NB; ++d) {
-        const float r = (obs[s * DX + d] - q[d]) * wx[d];
+        const float r = (obs_at(s, d) - q[d]) * wx[d];
         acc += r * r;
       }
       if (obs_v) {
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
-          const float r = (obs[s * DX + NB + d] - qd[d]) * wx[NB + d];
+          const float r = (obs_at(s, NB + d) - qd[d]) * wx[NB + d];
           acc += r * r;
         }
       }
       ll -= 0.5 * (double)acc;
+      if (kAhead) load_row(min(s + 1, J.h - 1), ob);  // in flight during the next step
     }
     if (traj) {
 #pragma unroll
@@ -586,7 +699,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   const float* st = start_ptr(J, w, DS);
   float q[NB], qd[NB];
 #pragma unroll
-  for (int d = 0; d < NB; ++d) { q[d] = st[d]; qd[d] = st[NB + d]; }
+  for (int d = 0; d < NB; ++d) { q[d] = ldg(st + d); qd[d] = ldg(st + NB + d); }
   const float dt = J.dt;
   const int h = J.h;
   const int B = full ? h : seg_len_of(h);
@@ -603,10 +716,35 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   for (int d = 0; d < DS; ++d) wx[d] = (d < NB || obs_v) ? J.w_x[d] : 0.f;
   auto slot = [&](int s, int d) -> float& { return lds[((size_t)s * DS + d) * kWave + lane]; };
 
+  constexpr bool kAhead = NB <= 2;
+  // Short chains (kAhead) read observation rows one step ahead in both
+  // sweeps, so each load's latency hides behind a step of arithmetic; longer
+  // chains load at the use (enough arithmetic per step to hide it, fewer
+  // live registers).  load_row is unconditional and in bounds (no branch the
+  // compiler must merge): when only q is observed the velocity half reads a
+  // value of the same row, which is never used.
+  auto load_row = [&](int s, float* o) {
+    const float* row = obs + (size_t)s * DX;
+#pragma unroll
+    for (int d = 0; d < NB; ++d) o[d] = ldg(row + d);
+#pragma unroll
+    for (int d = 0; d < NB; ++d) o[NB + d] = ldg(row + min(NB + d, DX - 1));
+  };
+  float ob[DS] = {};
+  auto obs_at = [&](int s, int d) -> float { return kAhead ? ob[d] : obs[s * DX + d]; };
+
   // ---- forward sweep: log-likelihood, end state, stored states ----
+  // Short chains store state 0 first: its slot is the start state in both
+  // storage modes, and storing it here completes the start-state loads
+  // before the loop, so the loop never waits on them.
+  if (kAhead) {
+#pragma unroll
+    for (int d = 0; d < NB; ++d) { slot(0, d) = q[d]; slot(0, NB + d) = qd[d]; }
+    load_row(0, ob);
+  }
   double ll = 0.0;
   for (int s = 0; s < h; ++s) {
-    if (full || s % B == 0) {
+    if ((!kAhead || s > 0) && (full || s % B == 0)) {
       const int sl = full ? s : s / B;
 #pragma unroll
       for (int d = 0; d < NB; ++d) { slot(sl, d) = q[d]; slot(sl, NB + d) = qd[d]; }
@@ -615,17 +753,18 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     float acc = 0.f;
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
-      const float r = (obs[s * DX + d] - q[d]) * wx[d];
+      const float r = (obs_at(s, d) - q[d]) * wx[d];
       acc += r * r;
     }
     if (obs_v) {
 #pragma unroll
       for (int d = 0; d < NB; ++d) {
-        const float r = (obs[s * DX + NB + d] - qd[d]) * wx[NB + d];
+        const float r = (obs_at(s, NB + d) - qd[d]) * wx[NB + d];
         acc += r * r;
       }
     }
     ll -= 0.5 * (double)acc;
+    if (kAhead) load_row(min(s + 1, h - 1), ob);  // in flight during the next step
   }
   if (full) {
 #pragma unroll
@@ -692,7 +831,8 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   bad |= !isfinite(ll);
   if (ch == 0) J.ll_win[iu] = ll;
 
-  // ---- reverse sweep over segments ----
+  // ---- reverse sweep over segments (steps h-1 .. 0 in one descending order) ----
+  if (kAhead) load_row(h - 1, ob);
   double gm_a[MP], gm_c[MP];
 #pragma unroll
   for (int m = 0; m < MP; ++m) { gm_a[m] = 0.0; gm_c[m] = 0.0; }
@@ -718,17 +858,18 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 #pragma unroll
       for (int d = 0; d < NB; ++d) {
         const float x = slot(segbase + s - a + 1, d);
-        const float r = (obs[s * DX + d] - x) * wx[d];
+        const float r = (obs_at(s, d) - x) * wx[d];
         qb_a[d] += obs_on * (r * wx[d]);
       }
       if (obs_v) {
 #pragma unroll
         for (int d = 0; d < NB; ++d) {
           const float x = slot(segbase + s - a + 1, NB + d);
-          const float r = (obs[s * DX + NB + d] - x) * wx[NB + d];
+          const float r = (obs_at(s, NB + d) - x) * wx[NB + d];
           qdb_a[d] += obs_on * (r * wx[NB + d]);
         }
       }
+      if (kAhead) load_row(max(s - 1, 0), ob);  // in flight during this step's reverse
       float qs[NB], qds[NB];
 #pragma unroll
       for (int d = 0; d < NB; ++d) { qs[d] = slot(segbase + s - a, d); qds[d] = slot(segbase + s - a, NB + d); }

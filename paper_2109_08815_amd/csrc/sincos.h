@@ -60,4 +60,10 @@ __host__ __device__ inline float recip(float x) {
 #endif
 }
 
+// FP64 overload for host-side checks of the step functions.  It lives beside
+// the float one: declared in a nested namespace it would hide the float
+// version from unqualified calls there, and float arguments would be divided
+// in full precision instead.
+__host__ __device__ inline double recip(double x) { return 1.0 / x; }
+
 }  // namespace pds

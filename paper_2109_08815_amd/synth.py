@@ -163,7 +163,8 @@ def _arm_constants(rng: np.random.Generator) -> dict:
 def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem:
     """Build a seeded problem.  ``over`` overrides N, K, T, n_s, dt, sigma_obs,
     sigma_def, c, combine, lik, limits, n_dof (planar families), full_state (planar
-    families: observe (q, qd) instead of q), M (toy)."""
+    families: observe (q, qd) instead of q), damped, gravity_x (point-mass
+    planar families: joint damping, a gravity component along x), M (toy)."""
     base = dict(CONFIGS.get(config, {}))
     if config == "toy":
         base = dict(family="toy", N=256, K=1, T=50, n_s=1, dt=0.1, sigma_obs=0.5)
@@ -187,7 +188,7 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
         hi = np.array([2.0] * n + [1.5] * n)
         if fam == "chain5" or over.get("damped", False):
             damping[:n] = rng.uniform(0.0, 0.1, n)
-        gravity = np.array([0.0, -9.81, 0.0])
+        gravity = np.array([float(over.get("gravity_x", 0.0)), -9.81, 0.0])
         d_x = 2 * n if over.get("full_state", False) else n
         obs_index = np.arange(d_x)
         qmax = np.pi if fam == "double" else np.pi / 2

@@ -115,7 +115,11 @@ def test_algorithmic_flop_counts():
     planar = [L.algorithmic_flops(L.PDS_MODEL_PLANAR, n) for n in range(1, 6)]
     fwd = np.array([p[0] for p in planar])
     rev = np.array([p[1] for p in planar])
-    assert np.all(np.diff(fwd, 2) == 0) and np.all(np.diff(rev, 2) == 0)
+    # the ABA's passes grow linearly with the links (1, 3, 4, 5); two links
+    # run in closed form with less work than the ABA would need there
+    assert fwd[3] - fwd[2] == fwd[4] - fwd[3] == (fwd[2] - fwd[0]) / 2
+    assert rev[3] - rev[2] == rev[4] - rev[3] == (rev[2] - rev[0]) / 2
+    assert fwd[1] < (fwd[0] + fwd[2]) / 2 and rev[1] < (rev[0] + rev[2]) / 2
     assert [p[2] for p in planar] == [2.0 * n for n in range(1, 6)]
     f, r, t = L.algorithmic_flops(L.PDS_MODEL_ARM, 8)
     assert t == 2 * 8 + 2 * 7

@@ -143,6 +143,9 @@ CASES = [
     # point masses observed in the whole state (q, qd); rigid links
     # observed in q only
     ("c2", dict(N=70, K=2, T=80, n_s=4, full_state=True)),
+    # the double pendulum's closed-form dynamics with joint damping and a
+    # gravity component along x
+    ("c2", dict(N=70, K=2, T=80, n_s=4, damped=True, gravity_x=2.5)),
     ("rigid2", dict(N=33, K=2, T=80, n_s=2, full_state=False)),
 ]
 
