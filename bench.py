@@ -34,6 +34,11 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
 # HBM traffic of the window-adjoint kernel per workload, from committed
 # rocprofv3 counter summaries; valid while the kernel's source file hashes
 # to the value recorded with the counters.
+# Back-to-back launches of the window kernel per event pair when its
+# duration is measured after the graph replays: an event pair adds the
+# kernel's dispatch latency (a few microseconds) to what it brackets.
+KERNEL_REPS = 8
+
 TRAFFIC_PROFILES = {
     "c2": ("planar_adjoint_c2_traffic.md", "planar.hip"),
     "c3": ("planar_adjoint_c3_traffic.md", "planar.hip"),
@@ -322,8 +327,9 @@ def main():
     # per-iteration time of each graph replay (events between replays)
     per_iter = [a.elapsed_time(b) / per_graph for a, b in zip(marks, marks[1:] + [e1])] if marks else []
     if use_graph:
-        # kernel timing: the same iteration with plain launches right after
-        L.timing_enable(True)
+        # kernel timing: the same iteration with plain launches right after,
+        # each window-kernel launch repeated back to back inside its event pair
+        L.timing_enable(True, reps=KERNEL_REPS)
         for _ in range(min(args.steps, 200)):
             run.step()
         torch.cuda.synchronize()
@@ -375,6 +381,9 @@ def main():
             if model in (L.PDS_MODEL_ARM, L.PDS_MODEL_ARM_UJOINT, L.PDS_MODEL_ARM_UJOINT_WEIGHTS) else "planar_adjoint_kernel<%d, %s links>" % (
                 pb.n_dof, "rigid" if model == L.PDS_MODEL_PLANAR_RIGID else "point-mass"),
             "kernel_ms": k_ms,
+            "kernel_timing": ("HIP events on the kernel's stream, %d back-to-back launches per pair, plain launches "
+                              "after the timed replays" % KERNEL_REPS) if use_graph else
+                             "HIP events on the kernel's stream around each launch in the timed region",
             "flops_per_particle_step": per_step,
         },
         "finite": finite,

@@ -346,12 +346,17 @@ int32_t pds_version(void);
 int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_step, double* rev_step,
                           double* transcendental);
 
-/* Kernel timing for benchmarks.  While enabled, every sim_batch_adjoint and
- * loglik_multishoot call records a pair of HIP events on its stream around
- * its window-kernel launches (a ring of 4096 pairs).  pds_timing_enable(1)
- * clears the ring; pds_timing_read waits for the recorded events and writes
- * up to max_n elapsed times in milliseconds, returning how many it wrote
- * (or a negative error code). */
+/* Kernel timing for benchmarks.  While enabled, every sim_batch_adjoint,
+ * loglik_multishoot and traj_metrics call records a pair of HIP events on its
+ * stream around its window-kernel (distance-kernel) launches (a ring of 4096
+ * pairs).  pds_timing_enable(r), 1 <= r <= 64, clears the ring and turns
+ * timing on with r back-to-back launches of those kernels inside each pair
+ * (they rewrite the same outputs from the same inputs, so results are
+ * unchanged): the dispatch latency an event pair adds is then paid once per
+ * r launches.  pds_timing_enable(0) turns timing off; other values give
+ * PDS_EINVAL.  pds_timing_read waits for the recorded events and writes up
+ * to max_n times in milliseconds, each a pair's elapsed time divided by its
+ * r, returning how many it wrote (or a negative error code). */
 int pds_timing_enable(int32_t enable);
 int pds_timing_read(float* ms, int32_t max_n);
 

@@ -326,8 +326,10 @@ def algorithmic_flops(model: int, n_dof: int):
     return f.value, r.value, t.value
 
 
-def timing_enable(on: bool = True):
-    _check(lib().pds_timing_enable(1 if on else 0), "pds_timing_enable")
+def timing_enable(on: bool = True, reps: int = 1):
+    """Turn kernel timing on (each timed call launches its kernels `reps`
+    times back to back between one event pair) or off."""
+    _check(lib().pds_timing_enable(int(reps) if on else 0), "pds_timing_enable")
 
 
 def job_footprint(job_struct: PdsJob) -> int:

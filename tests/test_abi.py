@@ -161,3 +161,12 @@ def test_metrics_arguments_rejected_on_host():
     assert call(nbytes=nb - 1) == -1
     assert call(sigma=float("nan")) == -1
     assert lib.pds_traj_metrics_workspace(1000, 40, 5000) > lib.pds_traj_metrics_workspace(100, 20, 64)
+
+
+def test_timing_repeat_count_validated_on_host():
+    """pds_timing_enable takes 0 (off) or 1..64 launches per timed call;
+    anything else is rejected before any event is created."""
+    lib = L.lib()
+    assert lib.pds_timing_enable(-1) == -1 and b"64" in lib.pds_last_error()
+    assert lib.pds_timing_enable(65) == -1
+    assert lib.pds_timing_enable(0) == 0

@@ -432,6 +432,33 @@ def test_repeatable_bitwise(orc):
         np.testing.assert_array_equal(a, c)
 
 
+@pytest.mark.parametrize("cfg,over", [("c2", dict(N=70, K=3)), ("c4", dict(N=40, T=300, n_s=6))])
+def test_timed_repeated_launches_leave_results_bitwise(orc, cfg, over):
+    """With kernel timing on, each timed call launches its window kernels
+    several times back to back; they rewrite the same outputs from the same
+    inputs, so the iteration's results are bitwise those of an untimed
+    run, and every recorded time is positive."""
+    print_case("timing repeats", cfg, over)
+    outs = []
+    for reps in (0, 4):
+        pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01, lam=True, **over)
+        if reps:
+            L.timing_enable(True, reps=reps)
+        try:
+            for it in range(1, 3):
+                L.loglik_multishoot(b)
+                L.csvgd_iteration(b, it)
+            torch.cuda.synchronize()
+            if reps:
+                kt = L.timing_read()
+                assert len(kt) == 4 and np.all(kt > 0)
+        finally:
+            L.timing_enable(False)
+        outs.append([np64(t) for t in (job.theta, job.S, job.logp, job.g_obs, job.g_con, job.lam_def)])
+    for a, c in zip(*outs):
+        np.testing.assert_array_equal(a, c)
+
+
 def test_nonfinite_flags(orc):
     """A NaN parameter and an exploding time step are flagged, not errors."""
     pb, obs, st, job, b = make_case(orc, "c2", N=70, K=1, T=40, n_s=2)
