@@ -477,9 +477,9 @@ struct ArmMath {
       qb[i] += -K.kp[i] * lam[i];
       qdb[i] += -K.kd[i] * lam[i];
     }
-    if (BOX == kHinge) {
+    if constexpr (BOX == kHinge) {
       qdb[7] += -K.bh * lam[7];
-    } else if (BOX == kUJointWeights) {
+    } else if constexpr (BOX == kUJointWeights) {
       qdb[7] += -K.bh * lam[7];
       qdb[8] += -K.b8 * lam[8];
     } else {

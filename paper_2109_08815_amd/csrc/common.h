@@ -140,7 +140,7 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
 hipError_t launch_planar_forward(const JobMap& map, int nb, bool rigid, const pds_job* d_jobs, int grid,
                                  bool with_ll, hipStream_t s);
 hipError_t launch_planar_adjoint(const JobMap& map, int nb, bool rigid, const pds_job* d_jobs, char* ws, int grid,
-                                 bool split, bool full, size_t lds_bytes, hipStream_t s);
+                                 bool split, bool full, bool tape, size_t lds_bytes, hipStream_t s);
 hipError_t launch_assemble(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, bool with_grad,
                            hipStream_t s);
 hipError_t launch_assemble_grad(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);

@@ -14,6 +14,7 @@
 
 namespace pds {
 int planar_seg_len(int h);
+size_t planar_tape_bytes(int h);
 }
 
 namespace {
@@ -277,9 +278,13 @@ int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with
 // be resident at once, else sqrt(h) checkpoints.  (The arm adjoint keeps
 // its window states in the workspace and has one shape.)
 struct AdjShape {
-  bool split, full;
+  bool split, full, tape;
   size_t lds;  // dynamic LDS bytes per block
 };
+
+// Blocks of `lds` bytes that fit on the chip at once (256 CUs, 160 KiB
+// each), 0 when one does not fit a CU.
+long resident_blocks(size_t lds) { return lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / lds) : 0L; }
 
 AdjShape planar_shape(const pds_job& J) {
   const long units = (long)J.N * J.K * J.n_s;
@@ -289,11 +294,14 @@ AdjShape planar_shape(const pds_job& J) {
   AdjShape a;
   a.split = div_up(units, pds::kWave) < kSimds;
   const long waves = a.split ? div_up(units, pds::kWave / 2) : div_up(units, pds::kWave);
-  const long resident = full_lds <= 160 * 1024 ? 256L * (long)((160 * 1024) / full_lds) : 0L;
-  a.full = waves <= resident;
+  a.full = waves <= resident_blocks(full_lds);
+  // The closed-form double pendulum keeps its dynamics tape beside the
+  // window when every wave of the job still fits on the chip at once.
+  const size_t tape_lds = full_lds + pds::planar_tape_bytes(J.h);
+  a.tape = a.split && a.full && J.model == PDS_MODEL_PLANAR && J.n_dof == 2 && waves <= resident_blocks(tape_lds);
   const int B = a.full ? J.h : pds::planar_seg_len(J.h);
   const int nseg = div_up(J.h, B);
-  a.lds = a.full ? full_lds : (size_t)(nseg + B + 1) * ds * pds::kWave * sizeof(float);
+  a.lds = a.tape ? tape_lds : a.full ? full_lds : (size_t)(nseg + B + 1) * ds * pds::kWave * sizeof(float);
   return a;
 }
 
@@ -515,12 +523,12 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   }
   for (int model : {PDS_MODEL_PLANAR, PDS_MODEL_PLANAR_RIGID})
   for (int nb = 1; nb <= 5; ++nb) {
-    for (int mode = 0; mode < 4; ++mode) {
-      const bool split = (mode & 1) != 0, full = (mode & 2) != 0;
+    for (int mode = 0; mode < 8; ++mode) {
+      const bool split = (mode & 1) != 0, full = (mode & 2) != 0, tape = (mode & 4) != 0;
       auto pick = [&](const pds_job& J) {
         if (J.model != model || J.n_dof != nb) return false;
         const AdjShape a = planar_shape(J);
-        return a.split == split && a.full == full;
+        return a.split == split && a.full == full && a.tape == tape;
       };
       int grid = 0;
       size_t lds = 0;
@@ -535,7 +543,7 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
       if (m.n == 0) continue;
       if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "window of h steps needs %zu bytes of LDS", lds);
       rc = launch_rc(pds::launch_planar_adjoint(m, nb, model == PDS_MODEL_PLANAR_RIGID, d_jobs, w, grid, split, full,
-                                                lds, s),
+                                                tape, lds, s),
                      "planar_adjoint");
       if (rc) return rc;
     }

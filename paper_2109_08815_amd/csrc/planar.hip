@@ -482,15 +482,20 @@ __host__ __device__ __forceinline__ void aba_rev(const Planar<NB, R>& P, const R
 }
 
 // Semi-implicit Euler: qd' = qd + dt qdd, q' = q + dt qd'.
-template <int NB, class R = float, bool RIGID = false>
-__host__ __device__ __forceinline__ void step(const Planar<NB, R>& P, R dt, R* q, R* qd) {
-  Tape<NB, R> T;
-  aba<NB, R, RIGID>(P, q, qd, T);
+template <int NB, class R = float>
+__host__ __device__ __forceinline__ void euler(R dt, const Tape<NB, R>& T, R* q, R* qd) {
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     qd[i] = qd[i] + dt * T.qdd[i];
     q[i] = q[i] + dt * qd[i];
   }
+}
+
+template <int NB, class R = float, bool RIGID = false>
+__host__ __device__ __forceinline__ void step(const Planar<NB, R>& P, R dt, R* q, R* qd) {
+  Tape<NB, R> T;
+  aba<NB, R, RIGID>(P, q, qd, T);
+  euler<NB, R>(dt, T, q, qd);
 }
 
 // Reverse of one Euler step given the tape at its input state.  On entry
@@ -667,10 +672,16 @@ __host__ __device__ inline int seg_len_of(int h) {
 // sweeps and each carries one channel (selected by data, so the two halves
 // execute the same instructions).  full = 1 keeps every state of the window
 // in LDS (no recomputation), full = 0 keeps checkpoints every B ~ sqrt(h)
-// steps and recomputes one segment at a time.
-template <int NB, bool SPLIT, bool RIGID>
+// steps and recomputes one segment at a time.  TAPE (two point-mass links,
+// SPLIT, full = 1): the forward sweep also keeps each step's dynamics tape
+// (sin/cos of both angles, qdd, 1 / det H) in LDS after the states, one
+// copy per unit, and the reverse sweep reads it instead of evaluating the
+// dynamics again (the reverse then uses exactly the forward sweep's values;
+// a re-evaluation, compiled in another context, may round differently).
+template <int NB, bool SPLIT, bool RIGID, bool TAPE = false>
 __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                char* __restrict__ ws, int full) {
+  static_assert(!TAPE || (NB == 2 && SPLIT && !RIGID), "the tape holds the closed-form two-link dynamics");
   constexpr int MP = PlanarParams<NB, RIGID>::M;
   extern __shared__ float lds[];
   const int e = map_entry(map, blockIdx.x);
@@ -715,6 +726,13 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 #pragma unroll
   for (int d = 0; d < DS; ++d) wx[d] = (d < NB || obs_v) ? J.w_x[d] : 0.f;
   auto slot = [&](int s, int d) -> float& { return lds[((size_t)s * DS + d) * kWave + lane]; };
+  // Tape of step s, [step][entry][unit of the wave]: both lanes of a unit
+  // write the same values to the same word, so each lane reads back what it
+  // wrote itself.
+  constexpr int kTapeW = 7;
+  float* const tape = lds + (size_t)(h + 1) * DS * kWave;
+  const int ul = lane & (UPW - 1);
+  auto tp = [&](int s, int t) -> float& { return tape[((size_t)s * kTapeW + t) * UPW + ul]; };
 
   constexpr bool kAhead = NB <= 2;
   // Short chains (kAhead) read observation rows one step ahead in both
@@ -749,7 +767,17 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 #pragma unroll
       for (int d = 0; d < NB; ++d) { slot(sl, d) = q[d]; slot(sl, NB + d) = qd[d]; }
     }
-    step<NB, float, RIGID>(P, dt, q, qd);
+    if constexpr (TAPE) {
+      Tape<NB> T;
+      aba<NB, float, RIGID>(P, q, qd, T);
+      tp(s, 0) = T.sn[0]; tp(s, 1) = T.sn[1];
+      tp(s, 2) = T.cs[0]; tp(s, 3) = T.cs[1];
+      tp(s, 4) = T.qdd[0]; tp(s, 5) = T.qdd[1];
+      tp(s, 6) = T.invD[0];
+      euler<NB>(dt, T, q, qd);
+    } else {
+      step<NB, float, RIGID>(P, dt, q, qd);
+    }
     float acc = 0.f;
 #pragma unroll
     for (int d = 0; d < NB; ++d) {
@@ -874,7 +902,14 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
 #pragma unroll
       for (int d = 0; d < NB; ++d) { qs[d] = slot(segbase + s - a, d); qds[d] = slot(segbase + s - a, NB + d); }
       Tape<NB> T;
-      aba<NB, float, RIGID>(P, qs, qds, T);
+      if constexpr (TAPE) {
+        T.sn[0] = tp(s, 0); T.sn[1] = tp(s, 1);
+        T.cs[0] = tp(s, 2); T.cs[1] = tp(s, 3);
+        T.qdd[0] = tp(s, 4); T.qdd[1] = tp(s, 5);
+        T.invD[0] = tp(s, 6);
+      } else {
+        aba<NB, float, RIGID>(P, qs, qds, T);
+      }
       float thb[MP];
 #pragma unroll
       for (int m = 0; m < MP; ++m) thb[m] = 0.f;
@@ -950,7 +985,17 @@ hipError_t launch_planar_forward(const JobMap& map, int nb, bool rigid, const pd
 
 template <int NB, bool RIGID>
 static hipError_t adj_nb(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, size_t lds, bool split,
-                         bool full, hipStream_t s) {
+                         bool full, bool tape, hipStream_t s) {
+  if constexpr (NB == 2 && !RIGID) {
+    if (tape) {
+      if (!split || !full) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((planar_adjoint_kernel<2, true, false, true>), dim3(grid), dim3(kWave), lds, s, map, d_jobs,
+                         ws, 1);
+      return hipGetLastError();
+    }
+  } else {
+    if (tape) return hipErrorInvalidValue;
+  }
   if (split)
     hipLaunchKernelGGL((planar_adjoint_kernel<NB, true, RIGID>), dim3(grid), dim3(kWave), lds, s, map, d_jobs, ws,
                        full ? 1 : 0);
@@ -961,23 +1006,25 @@ static hipError_t adj_nb(const JobMap& map, const pds_job* d_jobs, char* ws, int
 }
 
 hipError_t launch_planar_adjoint(const JobMap& map, int nb, bool rigid, const pds_job* d_jobs, char* ws, int grid,
-                                 bool split, bool full, size_t lds_bytes, hipStream_t s) {
+                                 bool split, bool full, bool tape, size_t lds_bytes, hipStream_t s) {
   if (rigid) {
     switch (nb) {
-      case 1: return adj_nb<1, true>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-      case 2: return adj_nb<2, true>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+      case 1: return adj_nb<1, true>(map, d_jobs, ws, grid, lds_bytes, split, full, tape, s);
+      case 2: return adj_nb<2, true>(map, d_jobs, ws, grid, lds_bytes, split, full, tape, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (nb) {
-    case 1: return adj_nb<1, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 2: return adj_nb<2, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 3: return adj_nb<3, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 4: return adj_nb<4, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
-    case 5: return adj_nb<5, false>(map, d_jobs, ws, grid, lds_bytes, split, full, s);
+    case 1: return adj_nb<1, false>(map, d_jobs, ws, grid, lds_bytes, split, full, tape, s);
+    case 2: return adj_nb<2, false>(map, d_jobs, ws, grid, lds_bytes, split, full, tape, s);
+    case 3: return adj_nb<3, false>(map, d_jobs, ws, grid, lds_bytes, split, full, tape, s);
+    case 4: return adj_nb<4, false>(map, d_jobs, ws, grid, lds_bytes, split, full, tape, s);
+    case 5: return adj_nb<5, false>(map, d_jobs, ws, grid, lds_bytes, split, full, tape, s);
     default: return hipErrorInvalidValue;
   }
 }
+
+size_t planar_tape_bytes(int h) { return (size_t)h * 7 * (kWave / 2) * sizeof(float); }
 
 int planar_seg_len(int h) { return seg_len_of(h); }
 

@@ -203,6 +203,42 @@ def test_adjoint_full_c2_sampled(orc, cfg):
     assert np.all(np.abs(np64(job.ll_win) - fwd["ll_win"]) <= tol)
 
 
+def test_taped_and_reevaluated_double_pendulum_adjoints(orc):
+    """The double pendulum's adjoint keeps each step's dynamics tape in LDS
+    when all of the job's waves still fit on the chip with it (N = 256:
+    320 waves of 76 KiB), and evaluates the dynamics again in the reverse
+    sweep otherwise (N = 600: 750 waves, only 512 fit with the tape).  The
+    first 256 particles of the larger job carry the smaller job's
+    parameters, shooting states and multipliers; their outputs depend on
+    their own windows alone.  The forward sweep is the same code on both
+    paths (bitwise equal outputs).  The reverse sweep's re-evaluation may
+    round differently from the forward sweep's evaluation (the compiler
+    fuses multiply-adds per context), so the gradients agree to FP32
+    rounding: 1e-4 of each particle's gradient norm, and both paths meet
+    the oracle's bar."""
+    import dataclasses
+
+    pb, obs, st, big, b = make_case(orc, "c2", perturb_S=0.01, lam=True, N=600)
+    n = 256
+    pb_s = dataclasses.replace(pb, N=n, particles=pb.particles[:n].copy())
+    small = L.Job(pb_s, obs, theta=pb_s.particles, S=st.S[:n])
+    small.lam_def.copy_(torch.as_tensor(st.lam_def[:n], dtype=torch.float32))
+    L.sim_batch_adjoint(b)
+    L.sim_batch_adjoint(L.Batch([small]))
+    for name in ("ll_win", "gdef", "logp", "wk"):
+        np.testing.assert_array_equal(np64(getattr(big, name))[:n], np64(getattr(small, name)), err_msg=name)
+    for name in ("g_obs", "g_con", "S_dot"):
+        a = np64(getattr(big, name))[:n].reshape(n, -1)
+        c = np64(getattr(small, name)).reshape(n, -1)
+        assert np.all(np.linalg.norm(a - c, axis=1) <= 1e-4 * np.linalg.norm(c, axis=1)), name
+    # both paths' sampled gradients against the oracle
+    sel = np.arange(0, n, 37)
+    ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
+    for job in (big, small):
+        assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
+        assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
+
+
 @pytest.mark.slow
 def test_full_c3_sampled(orc):
     """5-link chain at its full size (N=1024, K=8, T=1000, 20 windows): all
