@@ -147,6 +147,11 @@ CASES = [
     # gravity component along x
     ("c2", dict(N=70, K=2, T=80, n_s=4, damped=True, gravity_x=2.5)),
     ("rigid2", dict(N=33, K=2, T=80, n_s=2, full_state=False)),
+    # one-step windows (a tape of one step).  The whole window without the
+    # tape is covered at 40-step windows by the 600-particle comparison
+    # below; at small N it needs windows of 85 steps or more, over which
+    # FP32 rounding in this chaotic system alone drifts past 1e-3.
+    ("c2", dict(N=40, K=2, T=12, n_s=12)),
 ]
 
 
@@ -237,6 +242,20 @@ def test_taped_and_reevaluated_double_pendulum_adjoints(orc):
     for job in (big, small):
         assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
         assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
+
+
+def test_double_pendulum_checkpointed_adjoint_sampled(orc):
+    """Split double-pendulum job whose whole windows do not all fit in LDS at
+    once (N = 256, K = 8, 10 windows of 60 steps: 640 waves of 61 KiB, 512
+    fit), so the adjoint keeps checkpoints and re-evaluates each segment:
+    sampled particles against the oracle."""
+    pb, obs, st, job, b = make_case(orc, "c2", perturb_S=0.01, lam=True, K=8, T=600, n_s=10)
+    L.sim_batch_adjoint(b)
+    sel = np.arange(0, pb.N, 51)
+    ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
+    assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
+    assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
+    assert normwise(np64(job.S_dot)[sel], ref["S_dot"]).max() <= 1e-3
 
 
 @pytest.mark.slow
