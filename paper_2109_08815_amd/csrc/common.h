@@ -103,7 +103,7 @@ constexpr int kPhiThreads = 1024;  // threads per block of the one-kernel phi
 // kPhiTIMaxN particles, kPhiTILarge above
 constexpr int kPhiTISmall = 16;
 constexpr int kPhiTILarge = 4;
-constexpr int kPhiTIMaxN = 512;
+constexpr int kPhiTIMaxN = 128;
 inline int phi_ti(int N) { return N <= kPhiTIMaxN ? kPhiTISmall : kPhiTILarge; }
 constexpr int kPhiRows = 512;       // particle rows per LDS chunk of the one-kernel phi
 constexpr int kPhiFusedMaxN = 4096;  // larger jobs use partial sums and a reduction

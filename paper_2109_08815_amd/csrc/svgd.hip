@@ -25,8 +25,9 @@
 // Counts are integers, so the result does not depend on the order in which
 // blocks finish.
 //
-// phi.  Up to kPhiFusedMaxN particles: one block per 16 particles i with
-// every particle's row in LDS and 64 slices of the j range.  Larger jobs: blocks of 64 particles i against
+// phi.  Up to kPhiFusedMaxN particles: one block per 16 particles i (4
+// above 128 particles) with every particle's row in LDS and 1024 / 16 (or
+// 1024 / 4) slices of the j range.  Larger jobs: blocks of 64 particles i against
 // chunks of 32 particles j (enough blocks to fill the chip), then a
 // reduction over chunks.  Both accumulate in FP32 in a fixed order.
 #include <cmath>
@@ -967,7 +968,7 @@ __global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_j
 }
 
 // Jobs up to kPhiFusedMaxN particles: phi for TI particles i per block
-// (16 up to 512 particles, 4 above: enough blocks to fill the chip).  The block stages the
+// (16 up to 128 particles, 4 above: more blocks, each with less work).  The block stages the
 // particles' rows and driving terms in LDS kPhiRows at a time (rows padded
 // with zeros to MM parameters, so the parameter loops run without
 // branches); thread (il, js) accumulates particle i0 + il over j = js,
