@@ -159,6 +159,7 @@ hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, 
 // iteration counter themselves (a completion count); larger ones are
 // followed by iter_bump.
 constexpr int kStepCountBlocks = 256;
+constexpr int kStepThreads = 1024;  // threads (one element each) per step-kernel block
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
 // Arm box mounts (the kernels' template argument): 0 hinge, 1 universal
 // joint with the box's parameters in theta, 2 universal joint with two

@@ -614,7 +614,7 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
   auto blocks = [](const pds_job& J) {
     const long ds = 2 * J.n_dof;
     const long n = (long)J.N * J.M + (long)J.N * J.K * (J.n_s - 1) * ds + (long)J.N * J.K * (J.n_s - 1);
-    return div_up(n, 256);
+    return div_up(n, pds::kStepThreads);
   };
   int grid = 0;
   JobMap m = make_map(h_jobs, n_jobs, off, [](const pds_job&) { return true; }, blocks, &grid);

@@ -1049,7 +1049,7 @@ __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_
 
 // MDMM + optimizer update.  Flat index over theta (N M), S (N K (n_s-1) d_s)
 // and lam_def (N K (n_s-1)).
-__global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __restrict__ jobs, int optimizer,
+__global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pds_job* __restrict__ jobs, int optimizer,
                                                    int iter) {
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
@@ -1057,7 +1057,7 @@ __global__ void __launch_bounds__(256) step_kernel(JobMap map, const pds_job* __
   const int nSp = J.K * (J.n_s - 1) * ds;  // shooting floats per particle
   const int nLp = J.K * (J.n_s - 1);
   const int nT = J.N * J.M, nS = J.N * nSp, nL = J.N * nLp;
-  const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
+  const int t = (blockIdx.x - map.begin[e]) * kStepThreads + threadIdx.x;
   const int stride = J.M + nSp;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   // Adam bias corrections 1 - b^it per thread, b^it = 2^(it log2 b): no
@@ -1209,7 +1209,7 @@ hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mm
 
 hipError_t launch_step(const JobMap& map, const pds_job* d_jobs, int grid, int optimizer, int iter,
                        hipStream_t s) {
-  hipLaunchKernelGGL(step_kernel, dim3(grid), dim3(256), 0, s, map, d_jobs, optimizer, iter);
+  hipLaunchKernelGGL(step_kernel, dim3(grid), dim3(kStepThreads), 0, s, map, d_jobs, optimizer, iter);
   return hipGetLastError();
 }
 
