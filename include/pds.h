@@ -293,6 +293,16 @@ size_t pds_job_footprint(const pds_job* h_job);
  * synchronised with calls in flight.  PDS_EINVAL if |ranks| > 1e6. */
 int pds_test_median_shift(int32_t ranks);
 
+/* Test hook (host logic only, no device access): the launch shape
+ * sim_batch_adjoint gives a planar job (PDS_MODEL_PLANAR or
+ * PDS_MODEL_PLANAR_RIGID), read from the shape fields of *h_job (model,
+ * n_dof, N, K, n_s, h).  Returns bit 0 = two lanes per window unit (the job
+ * has fewer waves than the chip has SIMDs), bit 1 = the whole window in LDS
+ * (else sqrt(h) checkpoints), bit 2 = the dynamics tape in LDS as well (two
+ * point-mass links); writes the block's dynamic LDS bytes to *lds_bytes.
+ * PDS_EINVAL for a null argument, another model or a non-positive size. */
+int pds_test_adjoint_shape(const pds_job* h_job, size_t* lds_bytes);
+
 size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which);
 
 /* ---- Posterior-consistency metrics (Sec. III-F, App. A-D) ----

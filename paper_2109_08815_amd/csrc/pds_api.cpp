@@ -567,6 +567,19 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   return PDS_OK;
 }
 
+int pds_test_adjoint_shape(const pds_job* h_job, size_t* lds_bytes) {
+  g_err.clear();
+  if (!h_job || !lds_bytes) return fail(PDS_EINVAL, "pds_test_adjoint_shape: null argument");
+  const pds_job& J = *h_job;
+  if (J.model != PDS_MODEL_PLANAR && J.model != PDS_MODEL_PLANAR_RIGID)
+    return fail(PDS_EINVAL, "pds_test_adjoint_shape: not a planar model (%d)", J.model);
+  if (J.N < 1 || J.K < 1 || J.n_s < 1 || J.h < 1 || J.n_dof < 1)
+    return fail(PDS_EINVAL, "pds_test_adjoint_shape: sizes must be positive");
+  const AdjShape a = planar_shape(J);
+  *lds_bytes = a.lds;
+  return (a.split ? 1 : 0) | (a.full ? 2 : 0) | (a.tape ? 4 : 0);
+}
+
 int pds_test_median_shift(int32_t ranks) {
   if (ranks < -1000000 || ranks > 1000000) return fail(PDS_EINVAL, "rank shift %d out of range", ranks);
   g_median_rank_shift = ranks;

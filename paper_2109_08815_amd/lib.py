@@ -64,7 +64,7 @@ _lib = None
 EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
            "svgd_bandwidth", "svgd_phi_at_bandwidth",
            "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_timing_enable",
-           "pds_timing_read", "pds_test_median_shift", "pds_job_footprint")
+           "pds_timing_read", "pds_test_median_shift", "pds_test_adjoint_shape", "pds_job_footprint")
 
 
 def lib():
@@ -97,6 +97,8 @@ def lib():
             L.pds_job_footprint.restype = C.c_size_t
             L.pds_test_median_shift.argtypes = [C.c_int32]
             L.pds_test_median_shift.restype = C.c_int
+            L.pds_test_adjoint_shape.argtypes = [P, C.POINTER(C.c_size_t)]
+            L.pds_test_adjoint_shape.restype = C.c_int
             L.pds_traj_metrics_workspace.argtypes = [C.c_int32, C.c_int32, C.c_int32]
             L.pds_traj_metrics_workspace.restype = C.c_size_t
             L.pds_traj_metrics.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
@@ -351,6 +353,15 @@ def shape_struct(pb, N=None) -> PdsJob:
     j.limits = int(getattr(pb, "limits", PDS_LIMITS_SOFT))
     j.dt, j.sigma_def, j.c, j.eps_lam = pb.dt, pb.sigma_def, pb.c, pb.eps_lam
     return j
+
+
+def adjoint_shape(job_struct: PdsJob):
+    """(two lanes per unit, whole window in LDS, tape in LDS, LDS bytes) the
+    library chooses for a planar job's adjoint (host logic only)."""
+    nb = C.c_size_t()
+    r = lib().pds_test_adjoint_shape(C.byref(job_struct), C.byref(nb))
+    _check(r if r < 0 else 0, "pds_test_adjoint_shape")
+    return bool(r & 1), bool(r & 2), bool(r & 4), int(nb.value)
 
 
 def test_median_shift(ranks: int):

@@ -170,3 +170,46 @@ def test_timing_repeat_count_validated_on_host():
     assert lib.pds_timing_enable(-1) == -1 and b"64" in lib.pds_last_error()
     assert lib.pds_timing_enable(65) == -1
     assert lib.pds_timing_enable(0) == 0
+
+
+def _shape(cfg, **over):
+    from paper_2109_08815_amd import synth
+    pb = synth.make_problem(cfg, **over)
+    return L.adjoint_shape(L.shape_struct(pb))
+
+
+def test_adjoint_launch_shape_boundaries():
+    """The host's choice of adjoint storage at its boundaries.  A split job
+    has fewer than 1024 waves of 64 units; the whole window ((h + 1) states
+    of 2 n_dof floats per lane) stays in LDS when all of the job's waves fit
+    on the 256 CUs at once (160 KiB each); the double pendulum's tape (7
+    floats per step and unit, 32 units per wave) joins it on the same
+    condition with the larger footprint."""
+    full2 = lambda h: (h + 1) * 4 * 64 * 4
+    tape2 = lambda h: full2(h) + h * 7 * 32 * 4
+    # the benchmark's double pendulum: 320 waves, two 76 KiB waves per CU
+    assert _shape("c2") == (True, True, True, tape2(40)) and tape2(40) == 77824
+    # 512 waves still fit with the tape, 513 do not (K = 1, 16 windows)
+    assert _shape("c2", N=1024, K=1, T=640, n_s=16) == (True, True, True, tape2(40))
+    assert _shape("c2", N=1025, K=1, T=640, n_s=16) == (True, True, False, full2(40))
+    # 750 waves: the window alone fits three per CU
+    assert _shape("c2", N=600) == (True, True, False, full2(40))
+    # one wave per CU with the tape up to h = 84, none at 85
+    assert _shape("c2", N=40, K=1, T=168, n_s=2) == (True, True, True, tape2(84))
+    assert _shape("c2", N=40, K=1, T=170, n_s=2) == (True, True, False, full2(85))
+    # rigid links keep the re-evaluation
+    assert _shape("rigid2")[:3] == (True, True, False)
+    # the 5-link chain: 2560 waves, one lane per unit, sqrt(h) = 8-step segments
+    # (7 checkpoints + 9 segment states of 10 floats per lane)
+    assert _shape("c3") == (False, False, False, (7 + 8 + 1) * 10 * 64 * 4)
+
+
+def test_adjoint_shape_rejects_other_models():
+    from paper_2109_08815_amd import synth
+    j = L.shape_struct(synth.make_problem("c4"))
+    with pytest.raises(L.PdsError):
+        L.adjoint_shape(j)
+    j = L.shape_struct(synth.make_problem("c2"))
+    j.h = 0
+    with pytest.raises(L.PdsError):
+        L.adjoint_shape(j)
