@@ -741,8 +741,7 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
 // full; the
 // median (mean of the two middle values for an even count) gives
 // h = med^2 / log N.  N = 1 or a vanishing median gives h = 1.
-// variant 1 uses log(N+1).
-double orc_bandwidth(int N, int M, const double* theta, const double* rho, int variant, double* med_out) {
+double orc_bandwidth(int N, int M, const double* theta, const double* rho, double* med_out) {
   std::vector<double> d2;
   d2.reserve((size_t)N * (N - 1) / 2);
   for (int i = 0; i < N; ++i)
@@ -761,9 +760,8 @@ double orc_bandwidth(int N, int M, const double* theta, const double* rho, int v
     med = 0.5 * (std::sqrt(d2[(P - 1) / 2]) + std::sqrt(d2[P / 2]));
   }
   if (med_out) *med_out = med;
-  const double lg = (variant == 1) ? std::log((double)N + 1.0) : std::log((double)N);
-  if (N <= 1 || med * med < 1e-300 || lg <= 0.0) return 1.0;
-  return med * med / lg;
+  if (N <= 1 || med * med < 1e-300) return 1.0;
+  return med * med / std::log((double)N);
 }
 
 // SVGD direction of eq. "svgd_update" with k(a, b) = exp(-||(a - b)/rho||^2 / h):

@@ -75,7 +75,7 @@ def lib():
             L.orc_gradient.argtypes = [C.POINTER(OrcModel), C.POINTER(OrcProblem), C.c_int, _I, _D, _D, _D, _D, _D,
                                        _D, _D, _D, _D, _D]
             L.orc_gradient.restype = C.c_int
-            L.orc_bandwidth.argtypes = [C.c_int, C.c_int, _D, _D, C.c_int, _D]
+            L.orc_bandwidth.argtypes = [C.c_int, C.c_int, _D, _D, _D]
             L.orc_bandwidth.restype = C.c_double
             L.orc_phi.argtypes = [C.c_int, C.c_int, _D, _D, _D, C.c_double, C.c_int, _I, _D]
             L.orc_mdmm_step.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _D, _D, _D, _D,
@@ -269,11 +269,11 @@ def gradient(pb, obs, st: State, sel=None, per_unit=False):
     return out
 
 
-def bandwidth(theta, rho, variant=0):
+def bandwidth(theta, rho):
     th = _f64(theta)
     N, M = th.shape
     med = C.c_double(0.0)
-    h = lib().orc_bandwidth(N, M, _p(th), _p(_f64(rho)), int(variant), C.byref(med))
+    h = lib().orc_bandwidth(N, M, _p(th), _p(_f64(rho)), C.byref(med))
     return h, med.value
 
 
@@ -303,10 +303,10 @@ def mdmm_step(pb, st: State, phi_, g_con, S_dot, gdef, optimizer, it, lr_theta=N
         np.clip(st.theta, pb.lo, pb.hi, out=st.theta)
 
 
-def csvgd_iteration(pb, obs, st: State, it, optimizer=1, variant=0):
+def csvgd_iteration(pb, obs, st: State, it, optimizer=1):
     """One CSVGD iteration (Algorithm 1) on FP64 state; returns intermediates."""
     g = gradient(pb, obs, st)
-    h, med = bandwidth(st.theta, pb.rho, variant)
+    h, med = bandwidth(st.theta, pb.rho)
     ph = phi(st.theta, g["g_obs"], pb.rho, h)
     mdmm_step(pb, st, ph, g["g_con"], g["S_dot"], g["gdef"], optimizer, it)
     g.update(bandwidth=h, median=med, phi=ph)

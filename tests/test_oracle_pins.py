@@ -692,3 +692,123 @@ def test_linear_gaussian_posterior(orc, M):
     std = st.theta.std(axis=0)
     assert np.all(np.abs(mean - mu) <= 0.05 * sd)
     assert np.all(np.abs(std / sd - 1) <= 0.1)
+
+
+def test_adam_hand_worked(orc):
+    """Three Adam steps of theta, the shooting states and the defect
+    multiplier against tests/golden/adam_three_steps.json (Kingma and Ba's
+    rule with -x_dot as the gradient, bias corrections at t = 1, 2, 3)."""
+    gd = json.load(open(os.path.join(GOLDEN, "adam_three_steps.json")))
+    pb = synth.make_problem("toy", N=1, M=1, T=50, n_s=2)
+    pb.lo[:] = gd["lo"]
+    pb.hi[:] = gd["hi"]
+    st = orc.State(pb, np.array([[gd["theta0"]]]), np.full((1, 1, 1, pb.d_s), gd["S0"]))
+    nA = pb.M + pb.d_s
+    for it in range(3):
+        orc.mdmm_step(pb, st, np.array([[gd["phi"][it]]]), np.array([[gd["g_con"][it]]]),
+                      np.full((1, 1, 1, pb.d_s), gd["S_dot"][it]), np.array([[[gd["g_def"][it]]]]), 1, it + 1,
+                      lr_theta=np.array([gd["lr_theta"]]), lr_S=np.full(pb.d_s, gd["lr_S"]),
+                      eps_lam=gd["eps_lambda"])
+        assert abs(st.theta[0, 0] - float(gd["theta"][it])) <= 1e-15
+        assert abs(st.adam_m[0, 0] - gd["adam_m_theta"][it]) <= 1e-16
+        assert abs(st.adam_v[0, 0] - gd["adam_v_theta"][it]) <= 1e-17
+        np.testing.assert_allclose(st.S.reshape(-1), float(gd["S"][it]), rtol=0, atol=1e-15)
+        np.testing.assert_allclose(st.adam_m[0, 1:nA], gd["adam_m_S"][it], rtol=0, atol=1e-15)
+        np.testing.assert_allclose(st.adam_v[0, 1:nA], gd["adam_v_S"][it], rtol=0, atol=1e-16)
+        assert abs(st.lam_def[0, 0, 0] - gd["lam_def"][it]) <= 1e-15
+        assert st.lam_lim[0, 0] == 0.0
+
+
+def test_adam_matches_torch_adam(orc):
+    """The oracle's Adam branch (theta and shooting states, per-coordinate
+    step sizes, iterations 1..5) against torch.optim.Adam in float64 fed
+    -x_dot as the gradient, every parameter inside its limits so that
+    x_dot = phi - g_con for theta and S_dot for S."""
+    import torch
+
+    rng = np.random.default_rng(31)
+    pb = synth.make_problem("c2", N=3, K=2, T=40, n_s=4)
+    N, M, K, ns, ds = 3, pb.M, pb.K, pb.n_s, pb.d_s
+    th0 = pb.lo + rng.uniform(0.3, 0.7, (N, M)) * (pb.hi - pb.lo)
+    S0 = rng.normal(size=(N, K, ns - 1, ds))
+    st = orc.State(pb, th0, S0)
+    # one torch tensor per step-size group: theta column m, S component d
+    tcols = [torch.tensor(th0[:, m].copy(), dtype=torch.float64, requires_grad=True) for m in range(M)]
+    scols = [torch.tensor(S0[..., d].copy(), dtype=torch.float64, requires_grad=True) for d in range(ds)]
+    groups = [{"params": [t], "lr": float(pb.lr_theta[m])} for m, t in enumerate(tcols)]
+    groups += [{"params": [s], "lr": float(pb.lr_S[d])} for d, s in enumerate(scols)]
+    opt = torch.optim.Adam(groups, betas=(0.9, 0.999), eps=1e-8, foreach=False)
+    for it in range(1, 6):
+        ph = rng.normal(size=(N, M)) * 1e3
+        gc = rng.normal(size=(N, M)) * 1e3
+        sd = rng.normal(size=(N, K, ns - 1, ds)) * 10.0
+        gdef = rng.uniform(0, 1, (N, K, ns - 1))
+        orc.mdmm_step(pb, st, ph, gc, sd, gdef, 1, it)
+        for m, t in enumerate(tcols):
+            t.grad = torch.tensor(-(ph[:, m] - gc[:, m]), dtype=torch.float64)
+        for d, s in enumerate(scols):
+            s.grad = torch.tensor(-sd[..., d], dtype=torch.float64)
+        opt.step()
+        for m, t in enumerate(tcols):
+            np.testing.assert_allclose(st.theta[:, m], t.detach().numpy(), rtol=1e-14, atol=1e-15)
+            np.testing.assert_allclose(st.adam_m[:, m], opt.state[t]["exp_avg"].numpy(), rtol=1e-13)
+            np.testing.assert_allclose(st.adam_v[:, m], opt.state[t]["exp_avg_sq"].numpy(), rtol=1e-13)
+        for d, s in enumerate(scols):
+            np.testing.assert_allclose(st.S[..., d], s.detach().numpy(), rtol=1e-14, atol=1e-15)
+        assert np.all(st.lam_lim == 0.0)
+
+
+@pytest.mark.parametrize("cfg", ["c4", "box1", "box2"])
+def test_arm_pd_torque(orc, cfg):
+    """The arm's joint torques (the controls of App. B-A's f_step): PD
+    tracking of the prescribed sinusoid q_d(t) = qc + A sin(omega t + phase)
+    on the seven arm joints, viscous damping on the passive axes.  Pinned as
+    an affine map of (q, qd): it vanishes at (q_d(t), dq_d/dt) -- the
+    target's time derivative taken here by central differences of the
+    sinusoid, not from any closed form -- and its Jacobian is -diag(kp) in
+    q and -diag(kd) in qd (finite differences), -b on the passive axes."""
+    pb = synth.make_problem(cfg, N=2, K=1, T=30, n_s=1)
+    a = pb.arm
+    th = pb.theta_true[0]
+    n = pb.n_dof
+
+    def qdes(t):
+        return np.asarray(a["qc"]) + np.asarray(a["amp"]) * np.sin(np.asarray(a["omega"]) * t + np.asarray(a["phase"]))
+
+    rng = np.random.default_rng(3)
+    if cfg == "c4":
+        b_passive = [pb.damping[7]]
+    elif cfg == "box1":
+        b_passive = [th[9], th[10]]
+    else:
+        b_passive = list(a["ujoint_b"])
+    for t in (0.0, 1.37, 4.9):
+        e = 1e-4
+        qdot_des = (-qdes(t + 2 * e) + 8 * qdes(t + e) - 8 * qdes(t - e) + qdes(t - 2 * e)) / (12 * e)
+        q = rng.normal(size=n)
+        qd = rng.normal(size=n)
+        q[:7], qd[:7] = qdes(t), qdot_des
+        tau = orc.tau(pb, th, t, q, qd)
+        np.testing.assert_allclose(tau[:7], 0.0, atol=1e-8 * max(np.max(a["kd"]), 1.0))
+        # passive axes: -b qd whatever q is
+        np.testing.assert_allclose(tau[7:], -np.asarray(b_passive) * qd[7:], rtol=1e-14)
+        J_q = np.zeros((n, n))
+        J_qd = np.zeros((n, n))
+        for j in range(n):
+            h = 1e-3
+            qp, qm = q.copy(), q.copy()
+            qp[j] += h
+            qm[j] -= h
+            J_q[:, j] = (orc.tau(pb, th, t, qp, qd) - orc.tau(pb, th, t, qm, qd)) / (2 * h)
+            qp, qm = qd.copy(), qd.copy()
+            qp[j] += h
+            qm[j] -= h
+            J_qd[:, j] = (orc.tau(pb, th, t, q, qp) - orc.tau(pb, th, t, q, qm)) / (2 * h)
+        want_q = np.zeros((n, n))
+        want_q[:7, :7] = -np.diag(a["kp"])
+        want_qd = np.zeros((n, n))
+        want_qd[:7, :7] = -np.diag(a["kd"])
+        for p, b in enumerate(b_passive):
+            want_qd[7 + p, 7 + p] = -b
+        np.testing.assert_allclose(J_q, want_q, atol=1e-9 * np.max(a["kp"]))
+        np.testing.assert_allclose(J_qd, want_qd, atol=1e-9 * max(np.max(a["kd"]), 1.0))
