@@ -1,11 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of one CSVGD iteration (Algorithm 1) on one MI355X.
 
-Workload (default): the double-pendulum problem -- N = 256 particles,
-M = 4 parameters (2 masses, 2 lengths), K = 4 observed trajectories of
-T = 400 steps at dt = 0.005 s, 10 shooting windows, random initial angles in
-[-pi, pi]; synthetic data (seeded), observations from the library's own
-rollout at the generating parameters plus Gaussian noise.
+Workload (default): the largest single-GPU configuration -- the 7-joint arm
+with a box on a passive hinge holding two 0.2 kg point masses at unknown
+in-plane positions (M = 4), PD-tracking seeded sinusoids, the hinge angle
+observed; N = 2048 particles, K = 1 trajectory of T = 1500 steps at
+dt = 1/240 s, 30 shooting windows of 50 steps.  Synthetic data (seeded):
+observations from the library's own rollout at the generating parameters
+plus Gaussian noise.  --config selects the others (c1 pendulum, c2 double
+pendulum, c3 5-link chain, rigid2, box1, box2).
 
 A step is one full iteration over all particles: reverse-mode gradient of
 the multiple-shooting likelihood and defects (sim_batch_adjoint), the SVGD
@@ -13,9 +16,9 @@ direction with the median-heuristic bandwidth (svgd_phi) and the MDMM/Adam
 update (svgd_step).  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: value = particle-sim-steps/s = N K T per iteration x
-iterations / elapsed, plus the roofline of the dominant kernel (the fused
-window forward+adjoint kernel) and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host's cores.
+iterations / elapsed, plus the roofline of the dominant kernel (the window
+forward+adjoint kernel) and the FP64 CPU oracle timed on a bounded sample
+of the same workload on the host's cores.
 """
 from __future__ import annotations
 
@@ -79,7 +82,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default=None, choices=["c1", "c2", "c3", "c4", "rigid2", "box1", "box2"],
-                    help="workload (default c2; c3 with --metrics)")
+                    help="workload (default c4; c3 with --metrics)")
     ap.add_argument("--metrics", action="store_true",
                     help="time the posterior-consistency metrics (KNN-KL both ways + MMD) between the particles' "
                          "rollouts and 10 held-out trajectories instead of the CSVGD iteration")
@@ -104,6 +107,16 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": 4 * n, "copies": 20}), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(pb, obs, theta, S, target_s):
@@ -135,6 +148,7 @@ def cpu_baseline(pb, obs, theta, S, target_s):
         "value": reps * sel_n * pb.K * pb.T / el,
         "unit": "particle-sim-steps/s",
         "cores": cores,
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": "%d of %d particles, all %d trajectories x %d steps: forward-mode-dual gradient, bandwidth "
                   "and phi rows, %d iteration(s), %.1f s" % (sel_n, n_all, pb.K, pb.T, reps, el),
@@ -286,7 +300,7 @@ def main():
         args.config = args.config or "c3"
         run_metrics(args)
         return
-    args.config = args.config or "c2"
+    args.config = args.config or "c4"
     pb = synth.make_problem(args.config)
     print("setup %s N=%d K=%d T=%d n_s=%d" % (args.config, pb.N, pb.K, pb.T, pb.n_s), file=sys.stderr, flush=True)
     obs = driver.gpu_observations(pb)
@@ -297,7 +311,10 @@ def main():
         run.step()
     torch.cuda.synchronize()
     use_graph = not args.no_graph
-    per_graph = 10 if args.steps % 10 == 0 else 1
+    # iterations per captured graph: at least 20 replays for the percentiles
+    per_graph = max(1, min(10, args.steps // 20))
+    if args.steps % per_graph:
+        per_graph = 1
     if use_graph:
         run.capture(per_graph)
         run.replay()

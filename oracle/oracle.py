@@ -205,17 +205,18 @@ def observe(pb, theta, states):
 
 
 def shooting_init(pb, theta, obs=None):
-    """Default shooting states: each particle's own single-shooting state at step j*h (j >= 1)."""
+    """Default shooting states: each particle's own single-shooting state at
+    step j*h (j >= 1), from one window over the whole trajectory per
+    particle and trajectory (threads over them)."""
+    import dataclasses
+
     N = theta.shape[0]
-    S = np.zeros((N, pb.K, pb.n_s - 1, pb.d_s))
     if pb.n_s == 1:
-        return S
-    for i in range(N):
-        for k in range(pb.K):
-            tr = rollout(pb, theta[i], pb.s0[k], pb.T - pb.h)
-            for j in range(1, pb.n_s):
-                S[i, k, j - 1] = tr[j * pb.h - 1]
-    return S
+        return np.zeros((N, pb.K, 0, pb.d_s))
+    ss = dataclasses.replace(pb, n_s=1, h=pb.T, N=N)
+    st = State(ss, theta, np.zeros((N, pb.K, 0, pb.d_s)))
+    tr = forward(ss, np.zeros((pb.K, pb.T, pb.d_x)), st, traj=True)["traj"]
+    return np.ascontiguousarray(tr[:, :, pb.h - 1 : pb.T - 1 : pb.h])
 
 
 def forward(pb, obs, st: State, sel=None, traj=False):

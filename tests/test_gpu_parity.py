@@ -1,31 +1,11 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Both sides get identical inputs: every float the GPU sees is a float32
-value, and the oracle receives exactly those values in float64.
-
-Tolerances (FP32 arithmetic on the GPU, FP64 in the oracle):
-* states: per window unit, ||x_gpu - x_ref||_inf / max(||x_ref||_inf, 1e-6)
-  <= 1e-4 over the unit's h states;
-* gradients: per particle, ||g_gpu - g_ref||_2 <= 1e-3 sum_{k,j} ||term_kj||_2,
-  the terms being the per-window contributions the gradient sums
-  (w_k d l_kj / d theta for g_obs, seed_kj d g_kj / d theta for g_con); for
-  a gradient without cancellation this is ||g_ref||_2, and near an optimum,
-  where the window terms cancel, it is the error FP32 rounding of each term
-  implies.  A g_con term is linear in its defect vector e = (S - s_end) u
-  twice (through d g_def and through lam + c g_def), so the relative error
-  the GPU's FP32 end state leaves in e (measured per unit, delta_kj) enters
-  it up to three times: term_kj is weighted by 1 + 3 delta_kj / 1e-3.  This
-  matters where a defect is small against the state it is the difference
-  of.  S_dot: per particle ||dS_gpu - dS_ref|| / ||dS_ref|| <= 1e-3;
-* window log-likelihoods: the error the state tolerance implies,
-  sum_t,d |r| w * 1e-4 * max(||x||_inf, 1e-6), plus 1e-9 |l| for the FP64
-  sums (r = residual, w = 1/sigma_obs);
-* defects: | ||e_gpu|| - ||e_ref|| | <= 1e-4 max(||s_end||_inf, 1e-6) sqrt(d_s)
-  on e = (S - s_end) u, since sigma_def sqrt(g_def) = ||e||;
-* bandwidth: exact median (same FP64 arithmetic on both sides), h within
-  1e-15 relative;
-* phi: FP32 sums of N terms, |d phi| <= 1e-4 * (1/N) sum_j k_ij (|G_j| +
-  |grad k|) per component.
+value, and the oracle receives exactly those values in float64.  The bars
+(tests/parity.py) are computed from the oracle's values and the stated
+tolerances only: states 1e-4 per window unit, gradients 1e-3 normwise
+(term sums where the window terms cancel), S_dot 1e-3 normwise, window
+log-likelihoods within what the state tolerance implies.
 """
 import numpy as np
 import pytest
@@ -34,6 +14,8 @@ import torch
 from paper_2109_08815_amd import lib as L
 from paper_2109_08815_amd import synth
 from tests.helpers import f32_problem, print_case, r32, requires_gpu
+from tests.parity import (end_state_rel_err, grad_bar, grad_check, ll_tolerance, normwise, state_rel_err,
+                           update_check)
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -60,60 +42,26 @@ def np64(t):
 
 
 def check_states(pb, traj_gpu, traj_ref):
-    N, K = traj_ref.shape[:2]
-    tg = traj_gpu.reshape(N, K, pb.n_s, pb.h, pb.d_s)
-    tr = traj_ref.reshape(N, K, pb.n_s, pb.h, pb.d_s)
-    err = np.abs(tg - tr).max(axis=(3, 4))
-    scale = np.maximum(np.abs(tr).max(axis=(3, 4)), 1e-6)
-    rel = err / scale
+    rel = state_rel_err(pb, traj_gpu, traj_ref)
     assert rel.max() <= 1e-4, "worst unit rel err %.3e" % rel.max()
     return rel.max()
 
 
-def ll_tolerance(pb, obs, traj_ref, ll_ref):
-    N, K = traj_ref.shape[:2]
-    x = traj_ref[..., pb.obs_index]  # [N, K, T, d_x]
-    r = (obs[None] - x) * pb.w_x
-    tr = traj_ref.reshape(N, K, pb.n_s, pb.h, pb.d_s)
-    scale = np.maximum(np.abs(tr).max(axis=(3, 4)), 1e-6)
-    per = (np.abs(r) * pb.w_x).reshape(N, K, pb.n_s, pb.h, pb.d_x).sum(axis=(3, 4))
-    return 1e-4 * per * scale + 1e-9 * np.abs(ll_ref)
-
-
-def normwise(a, b):
-    a = a.reshape(a.shape[0], -1)
-    b = b.reshape(b.shape[0], -1)
-    den = np.maximum(np.linalg.norm(b, axis=1), 1e-30)
-    return np.linalg.norm(a - b, axis=1) / den
-
-
-def defect_rel_err(pb, job, ref, S, sel=None):
-    """Relative error of each defect vector (S - s_end) u that the GPU's
-    FP32 end states leave, per (particle, trajectory, window)."""
-    es = np64(job.end_states)
-    if sel is not None:
-        es, S = es[sel], S[sel]
-    e_g = (S - es[:, :, : pb.n_s - 1]) * pb.u
-    e_r = (S - ref["end_states"][:, :, : pb.n_s - 1]) * pb.u
-    return np.linalg.norm(e_g - e_r, axis=3) / np.maximum(np.linalg.norm(e_r, axis=3), 1e-30)
-
-
-def grad_err(g_gpu, ref, kind, defect_err=None):
-    """Per-particle error ratio against the summed per-window term norms
-    (con terms weighted by their defects' measured relative error)."""
-    if kind == "obs":
-        terms = ref["wk"][:, :, None, None] * ref["dl_dtheta_unit"]
-        g_ref = ref["g_obs"]
-    else:
-        terms = ref["dcon_dtheta_unit"]
-        g_ref = ref["g_con"]
-    tn = np.linalg.norm(terms, axis=3)
-    if kind == "con" and defect_err is not None:
-        tn = tn.copy()
-        tn[:, :, : defect_err.shape[2]] *= 1.0 + 3.0 * defect_err / 1e-3
-    scale = tn.sum(axis=(1, 2))
-    err = np.linalg.norm(g_gpu - g_ref, axis=1)
-    return err / np.maximum(scale, 1e-30)
+def check_grads(pb, job, ref, S, sel=None, con=True):
+    """g_obs, g_con and S_dot of the particles `sel` against the oracle's."""
+    take = (lambda a: a) if sel is None else (lambda a: a[sel])
+    Ssel = take(S)
+    go = grad_check(take(np64(job.g_obs)), ref, "obs")
+    print("g_obs normwise %.2e (terms/|g| up to %.1f), bar ratio %.3f" % (
+        go["normwise"].max(), go["terms"].max(), go["ratio"].max()), flush=True)
+    assert go["ratio"].max() <= 1.0
+    if con and pb.n_s > 1:
+        gc = grad_check(take(np64(job.g_con)), ref, "con", pb, Ssel)
+        print("g_con normwise %.2e, bar ratio %.3f" % (gc["normwise"].max(), gc["ratio"].max()), flush=True)
+        assert gc["ratio"].max() <= 1.0
+        sd = normwise(take(np64(job.S_dot))[:, :, : pb.n_s - 1], ref["S_dot"])
+        print("S_dot normwise %.2e" % sd.max(), flush=True)
+        assert sd.max() <= 1e-3
 
 
 CASES = [
@@ -183,10 +131,7 @@ def test_adjoint_gradients(orc, cfg, over):
     pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01, lam=True, **over)
     L.sim_batch_adjoint(b)
     ref = orc.gradient(pb, obs, st, per_unit=True)
-    assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
-    if pb.n_s > 1:
-        assert grad_err(np64(job.g_con), ref, "con", defect_rel_err(pb, job, ref, st.S)).max() <= 1e-3
-        assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
+    check_grads(pb, job, ref, st.S)
     assert np.all(np64(job.flags) == 0)
 
 
@@ -200,9 +145,7 @@ def test_adjoint_full_c2_sampled(orc, cfg):
     L.sim_batch_adjoint(b)
     sel = np.arange(0, pb.N, 17)
     ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
-    assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
-    assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
-    assert normwise(np64(job.S_dot)[sel], ref["S_dot"]).max() <= 1e-3
+    check_grads(pb, job, ref, st.S, sel)
     fwd = orc.forward(pb, obs, st, traj=True)
     tol = ll_tolerance(pb, obs, fwd["traj"], fwd["ll_win"])
     assert np.all(np.abs(np64(job.ll_win) - fwd["ll_win"]) <= tol)
@@ -240,8 +183,7 @@ def test_taped_and_reevaluated_double_pendulum_adjoints(orc):
     sel = np.arange(0, n, 37)
     ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
     for job in (big, small):
-        assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
-        assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
+        check_grads(pb, job, ref, st.S, sel)
 
 
 def test_double_pendulum_checkpointed_adjoint_sampled(orc):
@@ -253,9 +195,7 @@ def test_double_pendulum_checkpointed_adjoint_sampled(orc):
     L.sim_batch_adjoint(b)
     sel = np.arange(0, pb.N, 51)
     ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
-    assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
-    assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
-    assert normwise(np64(job.S_dot)[sel], ref["S_dot"]).max() <= 1e-3
+    check_grads(pb, job, ref, st.S, sel)
 
 
 @pytest.mark.slow
@@ -266,13 +206,35 @@ def test_full_c3_sampled(orc):
     L.sim_batch_adjoint(b)
     sel = np.array([0, 1, 63, 64, 511, 1000, 1023])
     ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
-    assert grad_err(np64(job.g_obs)[sel], ref, "obs").max() <= 1e-3
-    assert grad_err(np64(job.g_con)[sel], ref, "con", defect_rel_err(pb, job, ref, st.S, sel)).max() <= 1e-3
-    assert normwise(np64(job.S_dot)[sel], ref["S_dot"]).max() <= 1e-3
-    es_ref = ref["end_states"]
-    es = np64(job.end_states)[sel]
-    rel = np.abs(es - es_ref).max(axis=3) / np.maximum(np.abs(es_ref).max(axis=3), 1e-6)
+    check_grads(pb, job, ref, st.S, sel)
+    rel = end_state_rel_err(np64(job.end_states)[sel], ref["end_states"])
     assert rel.max() <= 1e-4
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("cfg", ["c4", "box2"])
+def test_full_arm_sampled(orc, cfg):
+    """The 7-joint arm at its full size (N=2048, K=1, T=1500 at 240 Hz, 30
+    windows of 50 steps), the launch the benchmark times: with the hinged
+    box (c4) and with two weights in the box on a universal joint (box2).
+    Every window state of a particle sample, their end states and window
+    log-likelihoods, and their gradients against the oracle."""
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.005, lam=True, with_traj=True)
+    L.sim_batch_forward(b)
+    traj = np64(job.traj)
+    L.sim_batch_adjoint(b)
+    sel = np.array([0, 1, 63, 64, 511, 1024, 1500, 2047])
+    ref = orc.gradient(pb, obs, st, sel=sel, per_unit=True)
+    fwd = orc.forward(pb, obs, st, sel=sel, traj=True)
+    rel = state_rel_err(pb, traj[sel], fwd["traj"])
+    print("states %.2e" % rel.max(), flush=True)
+    assert rel.max() <= 1e-4
+    assert end_state_rel_err(np64(job.end_states)[sel], ref["end_states"]).max() <= 1e-4
+    if cfg == "c4":
+        tol = ll_tolerance(pb, obs, fwd["traj"], fwd["ll_win"])
+        assert np.all(np.abs(np64(job.ll_win)[sel] - fwd["ll_win"]) <= tol)
+    check_grads(pb, job, ref, st.S, sel)
+    assert np.all(np64(job.flags) == 0)
 
 
 def set_tensor(t, a):
@@ -418,19 +380,24 @@ def test_step_parity(orc, optimizer, lik, limits):
         assert np.all((got >= pb.lo) & (got <= pb.hi)) and not outside.any()
 
 
-@pytest.mark.parametrize("cfg,lik", [("c2", synth.LIK_MDMM), ("c2", synth.LIK_DEFECT), ("rigid2", synth.LIK_MDMM)])
-def test_csvgd_iteration_sgd(orc, cfg, lik):
+@pytest.mark.parametrize("cfg,lik,over", [("c2", synth.LIK_MDMM, dict(K=3)), ("c2", synth.LIK_DEFECT, dict(K=3)),
+                                          ("rigid2", synth.LIK_MDMM, dict(K=3)),
+                                          ("c4", synth.LIK_MDMM, dict(K=2, T=300, n_s=6)),
+                                          ("box1", synth.LIK_MDMM, dict(K=1, T=192, n_s=4))])
+def test_csvgd_iteration_sgd(orc, cfg, lik, over):
     """One full iteration (adjoint -> phi -> step) from identical inputs,
     with the defects as constraints (CSVGD) or inside p_ms; point-mass and
-    rigid links (M = 11)."""
-    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01, lam=True, N=70, K=3, lik=lik)
+    rigid links (M = 11), the arm with the hinged box and with the box's
+    own parameters on a universal joint (M = 11)."""
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.01 if cfg in ("c2", "rigid2") else 0.005, lam=True,
+                                    N=70, lik=lik, **over)
     th0 = st.theta.copy()
     S0 = st.S.copy()
     L.csvgd_iteration(b, 1, L.PDS_OPT_SGD)
     g = orc.csvgd_iteration(pb, obs, st, 1, optimizer=0)
     assert abs(np64(job.bandwidth)[0] - g["bandwidth"]) <= 1e-15 * g["bandwidth"]
-    assert normwise(np64(job.theta) - th0, st.theta - th0).max() <= 1e-3
-    assert normwise(np64(job.S) - S0, st.S - S0).max() <= 1e-3
+    assert update_check(np64(job.theta), th0, st.theta).max() <= 1.0
+    assert update_check(np64(job.S), S0, st.S).max() <= 1.0
 
 
 def test_batch_matches_single_jobs_bitwise(orc):
@@ -533,7 +500,8 @@ def test_nonfinite_flags(orc):
 
 def test_c1_hundred_iterations(orc):
     """Headline pendulum problem: 100 CSVGD iterations (Adam) on both sides;
-    the particle set's mean and spread agree."""
+    the particle set's mean and covariance agree within 1e-3 relative
+    (componentwise for the mean, Frobenius for the covariance)."""
     pb, obs, st, job, b = make_case(orc, "c1")
     for it in range(1, 101):
         L.csvgd_iteration(b, it)
@@ -541,8 +509,10 @@ def test_c1_hundred_iterations(orc):
     th = np64(job.theta)
     mu, mu_r = th.mean(0), st.theta.mean(0)
     assert np.all(np.abs(mu - mu_r) <= 1e-3 * np.abs(mu_r))
-    sd, sd_r = th.std(0), st.theta.std(0)
-    assert np.all(np.abs(sd - sd_r) <= 2e-2 * sd_r + 1e-3 * np.abs(mu_r))
+    cov, cov_r = np.cov(th.T), np.cov(st.theta.T)
+    rel = np.linalg.norm(cov - cov_r) / np.linalg.norm(cov_r)
+    print("mean %.2e covariance %.2e" % ((np.abs(mu - mu_r) / np.abs(mu_r)).max(), rel), flush=True)
+    assert rel <= 1e-3
 
 
 def test_graph_replays_match_eager(orc):
@@ -615,10 +585,11 @@ def test_autograd_function_matches_oracle(orc):
     st_b = orc.State(pb, pb.particles, st.S, lam_def=bw)
     ref = orc.gradient(pb, obs, st_b, per_unit=True)
     np.testing.assert_allclose(np64(logp), ref["logp"], rtol=1e-4)
+    # the combined gradient d(log p - sum b g_def)/d theta: each channel
+    # within its own bar (tests/parity.py), so their difference within the sum
+    bar = grad_bar(ref, "obs")[0] + grad_bar(ref, "con", pb, st.S)[0]
     gt = ref["g_obs"] - ref["g_con"]
-    scale = (np.linalg.norm(ref["wk"][:, :, None, None] * ref["dl_dtheta_unit"], axis=3).sum(axis=(1, 2))
-             + np.linalg.norm(ref["dcon_dtheta_unit"], axis=3).sum(axis=(1, 2)))
-    assert np.all(np.linalg.norm(np64(th.grad) - gt, axis=1) <= 1e-3 * scale)
+    assert np.all(np.linalg.norm(np64(th.grad) - gt, axis=1) <= bar)
     assert normwise(np64(S.grad), ref["S_dot"]).max() <= 1e-3
 
 
@@ -647,9 +618,7 @@ def test_arm_adjoint_gradients(orc, over):
     pb, obs, st, job, b = make_case(orc, "c4", perturb_S=0.005, lam=True, **over)
     L.sim_batch_adjoint(b)
     ref = orc.gradient(pb, obs, st, per_unit=True)
-    assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
-    assert grad_err(np64(job.g_con), ref, "con", defect_rel_err(pb, job, ref, st.S)).max() <= 1e-3
-    assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
+    check_grads(pb, job, ref, st.S)
     assert np.all(np64(job.flags) == 0)
 
 
@@ -701,10 +670,7 @@ def test_box_universal_joint_adjoint_gradients(orc, cfg, over):
     pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.005, lam=True, **over)
     L.sim_batch_adjoint(b)
     ref = orc.gradient(pb, obs, st, per_unit=True)
-    assert grad_err(np64(job.g_obs), ref, "obs").max() <= 1e-3
-    if pb.n_s > 1:
-        assert grad_err(np64(job.g_con), ref, "con", defect_rel_err(pb, job, ref, st.S)).max() <= 1e-3
-        assert normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], ref["S_dot"]).max() <= 1e-3
+    check_grads(pb, job, ref, st.S)
     assert np.all(np64(job.flags) == 0)
 
 
