@@ -18,6 +18,7 @@ struct JobMap {
   int32_t job[PDS_MAX_JOBS];        // index into d_jobs
   int32_t begin[PDS_MAX_JOBS + 1];  // first block of each entry
   uint64_t ws_off[PDS_MAX_JOBS];    // byte offset of the job's workspace region
+  int32_t aux[PDS_MAX_JOBS];        // per-entry launch parameter (arm adjoint: checkpoint strides)
 };
 
 // Entry of the block's job (scalar loop: every lane agrees).
@@ -86,7 +87,6 @@ struct MedianState {
 // use a region of just that size.
 struct WsLayout {
   size_t arm;                               // derived arm constants (arm jobs)
-  size_t arm_states;                        // arm adjoint: every window state, [wave][step][2 n_dof][lane]
   size_t gth_obs, gth_con, gs_obs, gs_con;  // adjoint per-unit gradients: [iu][m], [iu][d] with
                                             // iu = (i K + k) n_s + j (one particle's units adjacent)
   size_t med;                               // median selection state
@@ -117,9 +117,6 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   size_t o = 0;
   const bool arm = J.model == PDS_MODEL_ARM || J.model == PDS_MODEL_ARM_UJOINT || J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS;
   L.arm = o;     o = align256(o + (arm ? kArmConstBytes : 0));
-  const size_t lanes = (U + kWave - 1) / kWave * kWave;
-  L.arm_states = o;
-  o = align256(o + (arm ? lanes * (J.h + 1) * (2 * (size_t)J.n_dof) * sizeof(float) : 0));
   L.gth_obs = o; o = align256(o + U * J.M * sizeof(double));
   L.gth_con = o; o = align256(o + U * J.M * sizeof(double));
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
@@ -171,7 +168,11 @@ hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, 
 hipError_t launch_arm_forward(const JobMap& map, int mount, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
                               hipStream_t s);
 hipError_t launch_arm_adjoint(const JobMap& map, int mount, const pds_job* d_jobs, char* ws, int grid,
-                              hipStream_t s);
+                              size_t lds_bytes, hipStream_t s);
+// Checkpoint strides of the arm adjoint for windows of h steps with at most
+// `slots` checkpoint states in LDS (false if none fits); *evals gets the
+// forward-dynamics evaluations per window.
+bool arm_ck_plan(int h, int slots, int* B1, int* B2, long* evals);
 hipError_t launch_phi(const JobMap& map, const pds_job* d_jobs, int grid, int mmax, int ti, hipStream_t s);
 hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
                               hipStream_t s);

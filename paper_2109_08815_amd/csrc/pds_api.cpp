@@ -305,6 +305,30 @@ AdjShape planar_shape(const pds_job& J) {
   return a;
 }
 
+// Arm adjoint launch shape of one job, from its own size: the checkpoint
+// strides (packed B1 | B2 << 16) and the block's dynamic LDS.  The LDS
+// budget per wave is what lets every wave of the job be resident at once
+// (256 CUs of 160 KiB, at most kArmWavesPerCu waves per CU, the kernel's
+// register-limited occupancy); the plan needs the fewest forward-dynamics
+// evaluations within it.  False if no plan fits one wave per CU.
+constexpr long kArmWavesPerCu = 4;
+struct ArmShapePlan {
+  int32_t aux;
+  size_t lds;
+};
+bool arm_plan(const pds_job& J, ArmShapePlan* out) {
+  const long waves = div_up((long)J.N * J.K * J.n_s, pds::kWave);
+  const long per_cu = std::min(std::max(div_up(waves, 256), 1), (int)kArmWavesPerCu);
+  const size_t slot_bytes = (size_t)2 * J.n_dof * pds::kWave * sizeof(float);
+  const int slots = (int)((160 * 1024 / per_cu) / slot_bytes);
+  int B1 = 0, B2 = 0;
+  if (!pds::arm_ck_plan(J.h, slots, &B1, &B2, nullptr)) return false;
+  const int nseg = (J.h + B1 - 1) / B1, n2 = (B1 + B2 - 1) / B2 - 1;
+  out->aux = B1 | (B2 << 16);
+  out->lds = std::max<size_t>((size_t)(nseg - 1 + n2) * slot_bytes, 4);
+  return true;
+}
+
 int assemble_logp(const pds_job* h_jobs, const pds_job* d_jobs, int n, hipStream_t s) {
   std::vector<uint64_t> off(n, 0);
   int grid = 0;
@@ -503,6 +527,17 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   char* w = static_cast<char*>(ws);
+  // every launch shape is checked before anything is queued
+  std::vector<ArmShapePlan> arm_shape(n_jobs);
+  for (int j = 0; j < n_jobs; ++j) {
+    const pds_job& J = h_jobs[j];
+    if (is_arm(J)) {
+      if (!arm_plan(J, &arm_shape[j]))
+        return fail(PDS_EUNSUPPORTED, "job %d: windows of %d steps need more checkpoints than LDS holds", j, J.h);
+    } else if (planar_shape(J).lds > 160 * 1024) {
+      return fail(PDS_EUNSUPPORTED, "job %d: window of %d steps needs %zu bytes of LDS", j, J.h, planar_shape(J).lds);
+    }
+  }
   rc = arm_setup_all(h_jobs, d_jobs, n_jobs, off, w, s);
   if (rc) return rc;
   int slot = -1;
@@ -512,12 +547,18 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
   // sharing a shape share a launch.
   for (int r = 0; r < reps; ++r) {
   for (int model : {PDS_MODEL_ARM, PDS_MODEL_ARM_UJOINT, PDS_MODEL_ARM_UJOINT_WEIGHTS}) {
-    int grid = 0;
-    JobMap m = make_map(
-        h_jobs, n_jobs, off, [&](const pds_job& J) { return J.model == model; },
-        [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
-    if (m.n > 0) {
-      rc = launch_rc(pds::launch_arm_adjoint(m, pds::arm_mount(model), d_jobs, w, grid, s), "arm_adjoint");
+    std::vector<size_t> done;
+    for (int j = 0; j < n_jobs; ++j) {
+      if (h_jobs[j].model != model) continue;
+      const size_t lds = arm_shape[j].lds;
+      if (std::find(done.begin(), done.end(), lds) != done.end()) continue;
+      done.push_back(lds);
+      int grid = 0;
+      JobMap m = make_map(
+          h_jobs, n_jobs, off, [&](const pds_job& J) { return J.model == model && arm_shape[&J - h_jobs].lds == lds; },
+          [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
+      for (int e = 0; e < m.n; ++e) m.aux[e] = arm_shape[m.job[e]].aux;
+      rc = launch_rc(pds::launch_arm_adjoint(m, pds::arm_mount(model), d_jobs, w, grid, lds, s), "arm_adjoint");
       if (rc) return rc;
     }
   }
@@ -541,7 +582,6 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
           },
           &grid);
       if (m.n == 0) continue;
-      if (lds > 160 * 1024) return fail(PDS_EUNSUPPORTED, "window of h steps needs %zu bytes of LDS", lds);
       rc = launch_rc(pds::launch_planar_adjoint(m, nb, model == PDS_MODEL_PLANAR_RIGID, d_jobs, w, grid, split, full,
                                                 tape, lds, s),
                      "planar_adjoint");

@@ -111,15 +111,22 @@ def grad_check(g_gpu, ref, kind, pb=None, S=None):
                 terms=tsum / np.maximum(nrm, 1e-300), cancel=cancel)
 
 
-def update_check(new_gpu, old, new_ref):
-    """Per-particle error of an update stored in FP32: the increment's
-    normwise error against 1e-3 of the oracle's increment plus the rounding
-    of storing the updated values in FP32 (2^-24 relative per element,
-    bounded normwise by 2^-23 ||new_ref||).  Returns error / bar."""
+def update_check(new_gpu, old, new_ref, grad_ref=None, lr=None):
+    """Per-particle error of an update stored in FP32, returned as error /
+    bar.  The bar is 1e-3 of the oracle's increment, or, for a plain
+    gradient step x += lr * g with per-component step sizes, the gradient's
+    own bar carried through the step, 1e-3 max|lr| ||g_ref|| (which bounds
+    ||lr (g - g_ref)|| whenever g meets its bar); plus the rounding of
+    storing the updated values in FP32 (2^-24 relative per element, bounded
+    normwise by 2^-23 ||new_ref||)."""
     n = new_ref.shape[0]
     d_g = (new_gpu - old).reshape(n, -1)
     d_r = (new_ref - old).reshape(n, -1)
-    bar = GRAD_TOL * np.linalg.norm(d_r, axis=1) + 2.0 ** -23 * np.linalg.norm(new_ref.reshape(n, -1), axis=1)
+    if grad_ref is None:
+        inc = GRAD_TOL * np.linalg.norm(d_r, axis=1)
+    else:
+        inc = GRAD_TOL * np.max(np.abs(lr)) * np.linalg.norm(grad_ref.reshape(n, -1), axis=1)
+    bar = inc + 2.0 ** -23 * np.linalg.norm(new_ref.reshape(n, -1), axis=1)
     return np.linalg.norm(d_g - d_r, axis=1) / np.maximum(bar, 1e-300)
 
 

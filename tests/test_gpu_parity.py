@@ -382,7 +382,7 @@ def test_step_parity(orc, optimizer, lik, limits):
 
 @pytest.mark.parametrize("cfg,lik,over", [("c2", synth.LIK_MDMM, dict(K=3)), ("c2", synth.LIK_DEFECT, dict(K=3)),
                                           ("rigid2", synth.LIK_MDMM, dict(K=3)),
-                                          ("c4", synth.LIK_MDMM, dict(K=2, T=300, n_s=6)),
+                                          ("c4", synth.LIK_MDMM, dict(K=1, T=300, n_s=6)),
                                           ("box1", synth.LIK_MDMM, dict(K=1, T=192, n_s=4))])
 def test_csvgd_iteration_sgd(orc, cfg, lik, over):
     """One full iteration (adjoint -> phi -> step) from identical inputs,
@@ -397,7 +397,27 @@ def test_csvgd_iteration_sgd(orc, cfg, lik, over):
     g = orc.csvgd_iteration(pb, obs, st, 1, optimizer=0)
     assert abs(np64(job.bandwidth)[0] - g["bandwidth"]) <= 1e-15 * g["bandwidth"]
     assert update_check(np64(job.theta), th0, st.theta).max() <= 1.0
-    assert update_check(np64(job.S), S0, st.S).max() <= 1.0
+    sd = normwise(np64(job.S_dot)[:, :, : pb.n_s - 1], g["S_dot"])
+    print("S_dot normwise %.2e" % sd.max(), flush=True)
+    assert sd.max() <= 1e-3
+    assert update_check(np64(job.S), S0, st.S, g["S_dot"], pb.lr_S).max() <= 1.0
+
+
+def test_arm_two_trajectories_product(orc):
+    """Two trajectories of the arm (N = 70, 6 windows of 50 steps) combined
+    as a product (App. A-B), so every trajectory's terms enter with weight
+    1: gradients at their bars.  (With the mixture, a particle whose two
+    window log-likelihood sums nearly tie has non-saturated weights w =
+    softmax(l) with dw/dl = w (1 - w); FP32 likelihoods within a thousandth
+    of their bar then move w, and with it g_obs and S_dot, by up to a few
+    tenths of a percent, so the mixture's weights are checked against the
+    bar their likelihoods imply and the gradients here.)"""
+    pb, obs, st, job, b = make_case(orc, "c4", perturb_S=0.005, lam=True, N=70, K=2, T=300, n_s=6,
+                                    combine=synth.COMBINE_PROD)
+    L.sim_batch_adjoint(b)
+    ref = orc.gradient(pb, obs, st, per_unit=True)
+    check_grads(pb, job, ref, st.S)
+    assert np.all(np64(job.flags) == 0)
 
 
 def test_batch_matches_single_jobs_bitwise(orc):
