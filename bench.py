@@ -42,26 +42,35 @@ PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (published)
 # kernel's dispatch latency (a few microseconds) to what it brackets.
 KERNEL_REPS = 8
 
+ARM_SOURCES = ("arm.hip", "arm_math.h")
 TRAFFIC_PROFILES = {
-    "c2": ("planar_adjoint_c2_traffic.md", "planar.hip"),
-    "c3": ("planar_adjoint_c3_traffic.md", "planar.hip"),
-    "c4": ("arm_adjoint_c4_traffic.md", "arm.hip"),
-    "rigid2": ("planar_adjoint_rigid2_traffic.md", "planar.hip"),
-    "box1": ("arm_adjoint_box1_traffic.md", "arm.hip"),
-    "box2": ("arm_adjoint_box2_traffic.md", "arm.hip"),
-    "metrics_c3": ("metric_dist_c3_traffic.md", "metrics.hip"),
+    "c2": ("planar_adjoint_c2_traffic.md", ("planar.hip",)),
+    "c3": ("planar_adjoint_c3_traffic.md", ("planar.hip",)),
+    "c4": ("arm_adjoint_c4_traffic.md", ARM_SOURCES),
+    "rigid2": ("planar_adjoint_rigid2_traffic.md", ("planar.hip",)),
+    "box1": ("arm_adjoint_box1_traffic.md", ARM_SOURCES),
+    "box2": ("arm_adjoint_box2_traffic.md", ARM_SOURCES),
+    "metrics_c3": ("metric_dist_c3_traffic.md", ("metrics.hip",)),
 }
+
+
+def source_hash(files):
+    """sha256 of the kernel's source files, concatenated in order."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2109_08815_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(config):
     """HBM bytes per launch of the adjoint kernel from the committed PMC
     summary, or None when none covers this workload or the kernel source
     changed since the counters were taken."""
-    import hashlib
-
     if config not in TRAFFIC_PROFILES:
         return None
-    prof, src = TRAFFIC_PROFILES[config]
+    prof, srcs = TRAFFIC_PROFILES[config]
     path = os.path.join(ROOT, "profiles", prof)
     if not os.path.exists(path):
         return None
@@ -70,8 +79,7 @@ def measured_traffic(config):
         if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "source_sha256"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    h = hashlib.sha256(open(os.path.join(ROOT, "paper_2109_08815_amd", "csrc", src), "rb").read()).hexdigest()
-    if fields.get("source_sha256") != h or "traffic_bytes_per_launch" not in fields:
+    if fields.get("source_sha256") != source_hash(srcs) or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])
 
@@ -345,10 +353,13 @@ def main():
     per_iter = [a.elapsed_time(b) / per_graph for a, b in zip(marks, marks[1:] + [e1])] if marks else []
     if use_graph:
         # kernel timing: the same iteration with plain launches right after,
-        # each window-kernel launch repeated back to back inside its event pair
+        # each window-kernel launch repeated back to back inside its event
+        # pair, with the bandwidth after the adjoint so that no concurrent
+        # kernel takes compute units from the timed one
+        timed = driver.CSVGD([job], overlap=False)
         L.timing_enable(True, reps=KERNEL_REPS)
         for _ in range(min(args.steps, 200)):
-            run.step()
+            timed.step()
         torch.cuda.synchronize()
     kt = L.timing_read()
     L.timing_enable(False)
@@ -399,7 +410,7 @@ def main():
                 pb.n_dof, "rigid" if model == L.PDS_MODEL_PLANAR_RIGID else "point-mass"),
             "kernel_ms": k_ms,
             "kernel_timing": ("HIP events on the kernel's stream, %d back-to-back launches per pair, plain launches "
-                              "after the timed replays" % KERNEL_REPS) if use_graph else
+                              "with the bandwidth serialised, after the timed replays" % KERNEL_REPS) if use_graph else
                              "HIP events on the kernel's stream around each launch in the timed region",
             "flops_per_particle_step": per_step,
         },

@@ -9,8 +9,10 @@
 // chain rule): the forward sweep leaves level-1 checkpoints every B1 steps
 // in LDS; the reverse sweep goes through the segments backwards, refills
 // level-2 checkpoints every B2 steps of the segment from its level-1
-// checkpoint, and reverses each block of B2 steps by rolling forward from
-// its checkpoint to the step being reversed.  (B1, B2) is chosen per job so
+// checkpoint, and reverses each block of B2 steps from its checkpoint: a
+// block of two steps by one roll forward that keeps the first step's
+// dynamics tape in registers while the second is reversed, a longer block
+// by rolling forward to each step being reversed.  (B1, B2) is chosen per job so
 // that the checkpoints fit the LDS every wave of the job can have while all
 // of them are resident, at the least number of forward-dynamics
 // evaluations.  Checkpoints are [slot][component][lane] floats: each lane
@@ -273,14 +275,13 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
     }
     for (int b = nblk - 1; b >= 0; --b) {
       const int x0 = s0 + b * B2, nb = min(B2, s0 + len - x0);
-      for (int t = x0 + nb - 1; t >= x0; --t) {
+      auto load_block = [&]() {
         if (b > 0) get(n1 + b - 1, q, qd);
         else if (c > 0) get(c - 1, q, qd);
         else get_start(q, qd);
-        for (int s = x0; s < t; ++s) AM::step(K, th, (float)(t0 + s) * dt, dt, q, qd);
-        typename AM::Tape T;
-        AM::keep_consts_in_memory();
-        AM::aba(K, th, q, qd, (float)(t0 + t) * dt, T);
+      };
+      // reverse of step t from its state (q, qd) and dynamics tape T
+      auto reverse_step = [&](int t, const typename AM::Tape& T) {
         arm_obs_term<BOX, true>(K, qn, obs + (size_t)t * DX, wx, qb[0]);
         float tb[2][M];
         for (int ch = 0; ch < 2; ++ch)
@@ -289,6 +290,49 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
         for (int ch = 0; ch < 2; ++ch)
           for (int m = 0; m < M; ++m) gm[ch][m] += (double)tb[ch][m];
         for (int d = 0; d < NB; ++d) qn[d] = q[d];
+      };
+      if (B2 == 2 && nb == 2) {
+        // a pair: one roll forward gives both steps' tapes; the first is
+        // kept in registers while the second step is reversed
+        load_block();
+        typename AM::Tape T0, Tc;
+        float q0[NB], qd0[NB];
+  #pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          AM::keep_consts_in_memory();
+          AM::aba(K, th, q, qd, (float)(t0 + x0 + r) * dt, Tc);
+          if (r == 0) {
+            T0 = Tc;
+            for (int d = 0; d < NB; ++d) {
+              q0[d] = q[d];
+              qd0[d] = qd[d];
+              qd[d] = qd[d] + dt * Tc.qdd[d];
+              q[d] = q[d] + dt * qd[d];
+            }
+          }
+        }
+  #pragma unroll 1
+        for (int r = 0; r < 2; ++r) {
+          reverse_step(x0 + 1 - r, Tc);
+          if (r == 0) {
+            Tc = T0;
+            for (int d = 0; d < NB; ++d) {
+              q[d] = q0[d];
+              qd[d] = qd0[d];
+            }
+          }
+        }
+      } else {
+        // any other block: each step's state by rolling forward from the
+        // block's checkpoint
+        for (int t = x0 + nb - 1; t >= x0; --t) {
+          load_block();
+          for (int s = x0; s < t; ++s) AM::step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+          typename AM::Tape T;
+          AM::keep_consts_in_memory();
+          AM::aba(K, th, q, qd, (float)(t0 + t) * dt, T);
+          reverse_step(t, T);
+        }
       }
     }
   }
@@ -315,11 +359,15 @@ static_assert(sizeof(ArmConst) <= kArmConstBytes, "ArmConst must fit its workspa
 // window with at most `slots` checkpoints (level 1: nseg - 1; level 2:
 // ceil(B1 / B2) - 1).  Evaluations: h for the forward sweep, the refill of
 // every segment but the last (its level-2 checkpoints are left by the
-// forward sweep), and L (L + 1) / 2 for a block of L steps in the reverse
-// sweep.  Returns false when no plan fits.
+// forward sweep), and in the reverse sweep one per step for blocks of up to
+// two steps, L (L + 1) / 2 for a block of L > 2 steps.  Returns false when
+// no plan fits.
 bool arm_ck_plan(int h, int slots, int* B1_out, int* B2_out, long* evals_out) {
-  // reverse-sweep evaluations of a segment of len steps in blocks of B2
+  // reverse-sweep evaluations of a segment of len steps in blocks of B2:
+  // one per step for blocks of one or two steps (a pair reuses the tape of
+  // its roll forward), L (L + 1) / 2 for a longer block of L steps
   auto rev = [](long len, long B2) {
+    if (B2 <= 2) return len;
     const long r = len % B2;
     return (len / B2) * B2 * (B2 + 1) / 2 + r * (r + 1) / 2;
   };
