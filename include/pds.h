@@ -23,7 +23,8 @@
  *   allocates or frees device memory and keeps no pointer after a call
  *   returns.  Scratch memory comes from the caller's workspace `ws` of
  *   `ws_bytes` bytes (256-byte aligned), sized by pds_workspace_size(); calls
- *   that need none accept ws = NULL.
+ *   that need none accept ws = NULL.  (svgd_phi_noalloc instead uses a fixed
+ *   array the library's code object holds on every device it is loaded on.)
  * Streams.  Work is queued on `stream` (a hipStream_t passed as void*; NULL
  *   is the default stream).  Calls are asynchronous: no host synchronisation
  *   and no host<->device copy happens inside them.  Calls are re-entrant;
@@ -264,6 +265,22 @@ int svgd_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs,
                    void* stream);
 int svgd_phi_at_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
                           void* stream);
+
+/* svgd_phi for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same bandwidth and phi, bitwise, with the workspace taken from a
+ * fixed array of PDS_NOALLOC_SCRATCH_BYTES bytes that the library holds on
+ * each device it runs on until the process ends (the device of `stream`,
+ * or the current device for the NULL stream).  No allocation happens in
+ * the call.  PDS_EWORKSPACE (nothing queued) when the batch needs more
+ * than the array: pds_workspace_size(h_jobs, n_jobs, PDS_CALL_PHI) bytes,
+ * e.g. about 29 MB for one job of 2048 particles with 30 windows of the
+ * 8-body arm.  Every call on a device shares that device's array and
+ * leaves its contents behind: calls that overlap on one device (on
+ * concurrent streams) race and give undefined results; calls ordered on
+ * one stream, or synchronised, are safe. */
+#define PDS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int svgd_phi_noalloc(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* stream);
 
 /* MDMM update of Sec. III-E / Algorithm 1, simultaneous for all variables:
  * theta_dot = phi - (lam_lim + c g_lim) dg_lim/dtheta - g_con with

@@ -158,6 +158,9 @@ hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, 
 constexpr int kStepCountBlocks = 256;
 constexpr int kStepThreads = 1024;  // threads (one element each) per step-kernel block
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
+// Device address of the fixed workspace array of svgd_phi_noalloc on
+// `device` (looked up once per device).
+hipError_t noalloc_scratch(int device, void** out);
 // Arm box mounts (the kernels' template argument): 0 hinge, 1 universal
 // joint with the box's parameters in theta, 2 universal joint with two
 // point masses in theta.

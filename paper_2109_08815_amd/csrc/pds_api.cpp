@@ -637,6 +637,30 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   return phi_calls(h_jobs, d_jobs, n_jobs, off, static_cast<char*>(ws), (hipStream_t)stream);
 }
 
+int svgd_phi_noalloc(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* stream) {
+  int rc = validate_batch(h_jobs, d_jobs, n_jobs, NEED_PHI);
+  if (rc) return rc;
+  size_t total = 0;
+  std::vector<uint64_t> off = ws_offsets(h_jobs, n_jobs, PDS_CALL_PHI, &total);
+  if (total > PDS_NOALLOC_SCRATCH_BYTES)
+    return fail(PDS_EWORKSPACE, "svgd_phi_noalloc: the batch needs %zu bytes of workspace, above the %llu the "
+                "fixed array holds (use svgd_phi with a workspace)", total,
+                (unsigned long long)PDS_NOALLOC_SCRATCH_BYTES);
+  hipStream_t s = (hipStream_t)stream;
+  int device = 0;
+  hipError_t e = s ? hipStreamGetDevice(s, &device) : hipGetDevice(&device);
+  if (e != hipSuccess) return fail(PDS_ELAUNCH, "svgd_phi_noalloc: device of the stream: %s", hipGetErrorString(e));
+  void* ws = nullptr;
+  e = pds::noalloc_scratch(device, &ws);
+  if (e != hipSuccess) return fail(PDS_ELAUNCH, "svgd_phi_noalloc: workspace array: %s", hipGetErrorString(e));
+  int mmax = 1;
+  for (int j = 0; j < n_jobs; ++j) mmax = h_jobs[j].M > mmax ? h_jobs[j].M : mmax;
+  char* w = static_cast<char*>(ws);
+  rc = bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, w, s);
+  if (rc) return rc;
+  return phi_calls(h_jobs, d_jobs, n_jobs, off, w, s);
+}
+
 int svgd_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
                    void* stream) {
   std::vector<uint64_t> off;

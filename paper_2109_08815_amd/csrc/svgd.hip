@@ -32,6 +32,8 @@
 // reduction over chunks.  Both accumulate in FP32 in a fixed order.
 #include <cmath>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace pds {
@@ -1161,6 +1163,38 @@ hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, 
   if (err != hipSuccess) return err;
   PDS_MEDIAN_LAUNCH(median_final_kernel, mm.grid_large, kMedThreads, mm.large);
   return hipGetLastError();
+}
+
+// Workspace of svgd_phi_noalloc: one fixed array per device, held until the
+// process ends.  Host code never passes the array's name to a kernel (in
+// host code it is a stand-in, not a device address): noalloc_scratch looks
+// up this device's address once, with the device current, and every launch
+// gets that address.
+static __device__ __align__(256) unsigned char scratch[PDS_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(int device, void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) {
+      const hipError_t r = hipSetDevice(cur);
+      if (e == hipSuccess) e = r;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptr[device] = p;
+  }
+  *out = ptr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s) {

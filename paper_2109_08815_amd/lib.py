@@ -61,7 +61,7 @@ class PdsError(RuntimeError):
 
 _lock = threading.Lock()
 _lib = None
-EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
+EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step", "svgd_phi_noalloc",
            "svgd_bandwidth", "svgd_phi_at_bandwidth",
            "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_timing_enable",
            "pds_timing_read", "pds_test_median_shift", "pds_test_adjoint_shape", "pds_job_footprint")
@@ -81,6 +81,8 @@ def lib():
                 fn = getattr(L, name)
                 fn.argtypes = [P, C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p]
                 fn.restype = C.c_int
+            L.svgd_phi_noalloc.argtypes = [P, C.c_void_p, C.c_int32, C.c_void_p]
+            L.svgd_phi_noalloc.restype = C.c_int
             L.svgd_step.argtypes = [P, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p]
             L.svgd_step.restype = C.c_int
             L.pds_workspace_size.argtypes = [P, C.c_int32, C.c_int32]
@@ -281,6 +283,12 @@ def sim_batch_adjoint(b: Batch, stream=None):
 
 def svgd_phi(b: Batch, stream=None):
     _call("svgd_phi", b, stream)
+
+
+def svgd_phi_noalloc(b: Batch, stream=None):
+    """svgd_phi with the library's fixed workspace array (no workspace argument)."""
+    rc = lib().svgd_phi_noalloc(b.h, C.c_void_p(b.d.data_ptr()), b.n, _stream(stream))
+    _check(rc, "svgd_phi_noalloc")
 
 
 def svgd_bandwidth(b: Batch, stream=None):
