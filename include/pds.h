@@ -32,9 +32,20 @@
  * Errors.  Every call returns PDS_OK (0) or a negative code; on error nothing
  *   has been queued and pds_last_error() returns a thread-local message.
  *   Numerical trouble is never an error: it is reported per particle in
- *   job.flags (bit 0 a non-finite state, bit 1 a non-finite log-likelihood
- *   or gradient, bit 2 a parameter outside its limits).  flags are OR-ed
- *   into, never cleared, by the library.
+ *   job.flags (PDS_FLAG_*: bit 0 a non-finite state, bit 1 a non-finite
+ *   log-likelihood or gradient, bit 2 a parameter outside its limits, bit
+ *   3 frozen).  flags are OR-ed into, never cleared, by the library.
+ * Failed particles.  Simulators fail outside the range they were built for
+ *   (Sec. III-D), and one non-finite score would make every phi of its job
+ *   non-finite.  So a particle with bit 0, 1 or 3 set leaves the ensemble:
+ *   svgd_phi (and svgd_phi_at_bandwidth) sums over the N' other particles
+ *   only, divides by N', writes phi = 0 for it and the count N - N' to
+ *   job.n_masked; svgd_step leaves all its variables as they are and sets
+ *   bit 3.  The bandwidth median runs over the particles without bit 3,
+ *   with log N' for their number: it reads theta and bit 3 only, which no
+ *   call but svgd_step changes, so a bandwidth computed concurrently with
+ *   sim_batch_adjoint equals one computed after it.  A particle that fails
+ *   in an iteration therefore leaves the median in the next one.
  *
  * Notation: N particles, M parameters, K observed trajectories of T steps,
  * n_s shooting windows of h = T / n_s steps, n_dof joints, d_s = 2 n_dof
@@ -150,6 +161,12 @@ extern "C" {
 #define PDS_OPT_SGD 0
 #define PDS_OPT_ADAM 1
 
+/* job.flags bits */
+#define PDS_FLAG_STATE 1   /* a non-finite window state */
+#define PDS_FLAG_GRAD 2    /* a non-finite log-likelihood or gradient */
+#define PDS_FLAG_LIMIT 4   /* theta left outside [lo, hi] by svgd_step */
+#define PDS_FLAG_FROZEN 8  /* left out of the ensemble by svgd_step */
+
 /* which-call selector for pds_workspace_size */
 #define PDS_CALL_FORWARD 0
 #define PDS_CALL_LOGLIK 1
@@ -217,6 +234,8 @@ typedef struct pds_job {
                          arguments.  iter_dev[1] is the step's block count,
                          zero before and after every call: allocate both
                          zeroed, and never run two steps of one job at once */
+  int32_t* n_masked;  /* [1] particles left out of the last phi (flag bit 0,
+                         1 or 3), or NULL */
 } pds_job;
 
 /* Rolls out every window (a batched f_sim of Sec. II with the semi-implicit
@@ -246,8 +265,9 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
  * k(a, b) = exp(-||(a - b) / rho||^2 / h) and the median heuristic
  * h = med^2 / log N (Sec. III-A), med the exact FP64 median of the
  * N (N - 1) / 2 scaled pair distances (mean of the two middle values for an
- * even count; h = 1 for N = 1).  Uses g_obs as the score.  Writes bandwidth
- * and phi.  The workspace holds, per job, the selection state, one 8-byte
+ * even count; h = 1 for N = 1), over the particles of the ensemble (see
+ * Failed particles above).  Uses g_obs as the score.  Writes bandwidth,
+ * phi and n_masked.  The workspace holds, per job, the selection state, one 8-byte
  * slot per pair when N (N - 1) / 2 > 16384, and the phi partial sums. */
 int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
              void* stream);
@@ -287,7 +307,8 @@ int svgd_phi_noalloc(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_job
  * g_lim = clamp(theta, lo, hi) - theta; S_dot as computed; lam_lim += eps_lam
  * g_lim; lam_def += eps_lam g_def.  optimizer PDS_OPT_SGD: x += lr x_dot;
  * PDS_OPT_ADAM: Adam (0.9, 0.999, 1e-8) on (theta, S) with -x_dot as the
- * gradient, iteration `iter` >= 1 for bias correction.  Sets flags bit 2 for
+ * gradient, iteration `iter` >= 1 for bias correction.  Particles with flag
+ * bit 0, 1 or 3 keep every variable and get bit 3.  Sets flags bit 2 for
  * particles left outside their limits.  Needs no workspace. */
 int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int32_t optimizer,
               int32_t iter, void* stream);
@@ -298,7 +319,8 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
 /* Device bytes one job occupies in a CSVGD iteration, for admission by
  * HBM footprint: every buffer the pds_job fields point to at the sizes
  * documented above (gdef and S_dot with at least one window, iter_dev with
- * 2 entries; traj, seed_logp and seed_gdef only when non-NULL in *h_job)
+ * 2 entries, n_masked with 1; traj, seed_logp and seed_gdef only when
+ * non-NULL in *h_job)
  * plus its workspace for all calls.  Reads only shapes and the three
  * optional pointers; 0 on invalid shapes (see pds_last_error). */
 size_t pds_job_footprint(const pds_job* h_job);

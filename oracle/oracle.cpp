@@ -741,11 +741,14 @@ int orc_gradient(const OrcModel* md, const OrcProblem* pr, int n_sel, const int*
 // full; the
 // median (mean of the two middle values for an even count) gives
 // h = med^2 / log N.  N = 1 or a vanishing median gives h = 1.
-double orc_bandwidth(int N, int M, const double* theta, const double* rho, double* med_out) {
+double orc_bandwidth(int N, int M, const double* theta, const double* rho, const int* live, double* med_out) {
   std::vector<double> d2;
   d2.reserve((size_t)N * (N - 1) / 2);
+  int n_live = 0;
+  for (int i = 0; i < N; ++i) n_live += (!live || live[i]) ? 1 : 0;
   for (int i = 0; i < N; ++i)
     for (int j = i + 1; j < N; ++j) {
+      if (live && !(live[i] && live[j])) continue;
       double s = 0.0;
       for (int m = 0; m < M; ++m) {
         const double z = (theta[(size_t)i * M + m] - theta[(size_t)j * M + m]) * (1.0 / rho[m]);
@@ -760,18 +763,25 @@ double orc_bandwidth(int N, int M, const double* theta, const double* rho, doubl
     med = 0.5 * (std::sqrt(d2[(P - 1) / 2]) + std::sqrt(d2[P / 2]));
   }
   if (med_out) *med_out = med;
-  if (N <= 1 || med * med < 1e-300) return 1.0;
-  return med * med / std::log((double)N);
+  if (n_live <= 1 || med * med < 1e-300) return 1.0;
+  return med * med / std::log((double)n_live);
 }
 
 // SVGD direction of eq. "svgd_update" with k(a, b) = exp(-||(a - b)/rho||^2 / h):
 // phi_i = (1/N) sum_j [ k(theta_j, theta_i) grad_j + grad_{theta_j} k(theta_j, theta_i) ].
-void orc_phi(int N, int M, const double* theta, const double* grad, const double* rho, double h, int n_sel,
-             const int* sel, double* phi) {
+// With `live` (NULL = every particle) the ensemble is the live particles
+// alone: the sum runs over live j, N is their number, and a particle that
+// is not live gets phi = 0.
+void orc_phi(int N, int M, const double* theta, const double* grad, const double* rho, double h, const int* live,
+             int n_sel, const int* sel, double* phi) {
+  int n_live = 0;
+  for (int j = 0; j < N; ++j) n_live += (!live || live[j]) ? 1 : 0;
   for (int s = 0; s < n_sel; ++s) {
     const int i = sel[s];
     for (int m = 0; m < M; ++m) phi[(size_t)s * M + m] = 0.0;
+    if (live && !live[i]) continue;
     for (int j = 0; j < N; ++j) {
+      if (live && !live[j]) continue;
       double d2 = 0.0;
       for (int m = 0; m < M; ++m) {
         const double z = (theta[(size_t)j * M + m] - theta[(size_t)i * M + m]) / rho[m];
@@ -783,7 +793,7 @@ void orc_phi(int N, int M, const double* theta, const double* grad, const double
         phi[(size_t)s * M + m] += kij * grad[(size_t)j * M + m] + dk;
       }
     }
-    for (int m = 0; m < M; ++m) phi[(size_t)s * M + m] /= (double)N;
+    for (int m = 0; m < M; ++m) phi[(size_t)s * M + m] /= (double)n_live;
   }
 }
 
@@ -794,14 +804,17 @@ void orc_phi(int N, int M, const double* theta, const double* grad, const double
 // optimizer 0: x += lr * x_dot.  optimizer 1: Adam on (theta, S) with -x_dot
 // as the gradient (beta1 0.9, beta2 0.999, eps 1e-8), iteration `it` >= 1.
 // Lagrange multipliers always take plain ascent steps of size eps_lam.
+// Particles with frozen[i] != 0 (frozen may be NULL) keep every variable.
 void orc_mdmm_step(int N, int M, int K, int n_s, int d_s, double c, const double* lo, const double* hi,
                    const double* phi, const double* g_con, const double* S_dot, const double* gdef,
                    const double* lr_theta, const double* lr_S, double eps_lam, int optimizer, int it,
-                   double* theta, double* S, double* lam_lim, double* lam_def, double* adam_m, double* adam_v) {
+                   double* theta, double* S, double* lam_lim, double* lam_def, double* adam_m, double* adam_v,
+                   const int* frozen) {
   const int nS = K * (n_s - 1) * d_s;
   const int stride = M + nS;
   const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
   for (int i = 0; i < N; ++i) {
+    if (frozen && frozen[i]) continue;
     for (int m = 0; m < M; ++m) {
       const size_t im = (size_t)i * M + m;
       const double x = theta[im];

@@ -75,11 +75,11 @@ def lib():
             L.orc_gradient.argtypes = [C.POINTER(OrcModel), C.POINTER(OrcProblem), C.c_int, _I, _D, _D, _D, _D, _D,
                                        _D, _D, _D, _D, _D]
             L.orc_gradient.restype = C.c_int
-            L.orc_bandwidth.argtypes = [C.c_int, C.c_int, _D, _D, _D]
+            L.orc_bandwidth.argtypes = [C.c_int, C.c_int, _D, _D, _I, _D]
             L.orc_bandwidth.restype = C.c_double
-            L.orc_phi.argtypes = [C.c_int, C.c_int, _D, _D, _D, C.c_double, C.c_int, _I, _D]
+            L.orc_phi.argtypes = [C.c_int, C.c_int, _D, _D, _D, C.c_double, _I, C.c_int, _I, _D]
             L.orc_mdmm_step.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _D, _D, _D, _D,
-                                        _D, _D, _D, _D, C.c_double, C.c_int, C.c_int, _D, _D, _D, _D, _D, _D]
+                                        _D, _D, _D, _D, C.c_double, C.c_int, C.c_int, _D, _D, _D, _D, _D, _D, _I]
             _lib = L
     return _lib
 
@@ -90,6 +90,21 @@ def _p(a):
 
 def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _mask(a):
+    """Boolean per-particle mask as a C int array (None stays None)."""
+    return None if a is None else np.ascontiguousarray(np.asarray(a, dtype=bool), dtype=np.int32)
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(_I)
+
+
+# Particle status bits (the oracle's own bookkeeping of the ensemble):
+# a non-finite state, a non-finite likelihood or gradient, and frozen
+# (left out of the ensemble by an earlier update).
+FLAG_STATE, FLAG_GRAD, FLAG_FROZEN = 1, 2, 8
 
 
 def model_struct(pb) -> OrcModel:
@@ -133,6 +148,7 @@ class State:
         nA = M + K * (ns - 1) * ds
         self.adam_m = np.zeros((N, nA)) if adam_m is None else _f64(adam_m).copy()
         self.adam_v = np.zeros((N, nA)) if adam_v is None else _f64(adam_v).copy()
+        self.flags = np.zeros(N, dtype=np.int64)
 
 
 def _problem(pb, obs, st: State, keep):
@@ -270,25 +286,45 @@ def gradient(pb, obs, st: State, sel=None, per_unit=False):
     return out
 
 
-def bandwidth(theta, rho):
+def bandwidth(theta, rho, live=None):
+    """Median-heuristic bandwidth over the particles with ``live`` true (all
+    when None): pairs among them, log of their number."""
     th = _f64(theta)
     N, M = th.shape
     med = C.c_double(0.0)
-    h = lib().orc_bandwidth(N, M, _p(th), _p(_f64(rho)), C.byref(med))
+    lv = _mask(live)
+    h = lib().orc_bandwidth(N, M, _p(th), _p(_f64(rho)), _ip(lv), C.byref(med))
     return h, med.value
 
 
-def phi(theta, grad, rho, h, sel=None):
+def phi(theta, grad, rho, h, sel=None, live=None):
+    """SVGD direction of the rows ``sel`` over the ensemble of particles with
+    ``live`` true (all when None); rows of other particles are zero."""
     th = _f64(theta)
     N, M = th.shape
     sel = np.arange(N, dtype=np.int32) if sel is None else np.ascontiguousarray(sel, dtype=np.int32)
     out = np.zeros((len(sel), M))
-    lib().orc_phi(N, M, _p(th), _p(_f64(grad)), _p(_f64(rho)), float(h), len(sel), sel.ctypes.data_as(_I), _p(out))
+    lv = _mask(live)
+    lib().orc_phi(N, M, _p(th), _p(_f64(grad)), _p(_f64(rho)), float(h), _ip(lv), len(sel), sel.ctypes.data_as(_I),
+                  _p(out))
     return out
 
 
-def mdmm_step(pb, st: State, phi_, g_con, S_dot, gdef, optimizer, it, lr_theta=None, lr_S=None, eps_lam=None):
-    """In-place MDMM / optimizer update of ``st`` (Algorithm 1)."""
+def nonfinite_flags(out):
+    """Status bits of each particle from one gradient evaluation: FLAG_STATE
+    for a non-finite window end state, FLAG_GRAD for a non-finite log
+    likelihood or gradient."""
+    n = out["logp"].shape[0]
+    bad = lambda a: ~np.isfinite(a.reshape(n, -1)).all(axis=1)  # noqa: E731
+    f = np.where(bad(out["end_states"]), FLAG_STATE, 0)
+    g = bad(out["logp"]) | bad(out["g_obs"]) | bad(out["g_con"]) | bad(out["S_dot"])
+    return f | np.where(g, FLAG_GRAD, 0)
+
+
+def mdmm_step(pb, st: State, phi_, g_con, S_dot, gdef, optimizer, it, lr_theta=None, lr_S=None, eps_lam=None,
+              frozen=None):
+    """In-place MDMM / optimizer update of ``st`` (Algorithm 1); particles
+    with ``frozen`` true keep every variable."""
     N = st.theta.shape[0]
     lrt = _f64(pb.lr_theta if lr_theta is None else lr_theta)
     lrs = _f64(pb.lr_S if lr_S is None else lr_S)
@@ -299,16 +335,27 @@ def mdmm_step(pb, st: State, phi_, g_con, S_dot, gdef, optimizer, it, lr_theta=N
     lib().orc_mdmm_step(N, pb.M, pb.K, pb.n_s, pb.d_s, float(pb.c), _p(_f64(pb.lo)), _p(_f64(pb.hi)),
                         _p(_f64(phi_)), _p(_f64(g_con)), _p(np.ascontiguousarray(Sd)), _p(np.ascontiguousarray(gd)),
                         _p(lrt), _p(lrs), float(el), int(optimizer), int(it), _p(st.theta), _p(st.S), _p(st.lam_lim),
-                        _p(st.lam_def), _p(st.adam_m), _p(st.adam_v))
+                        _p(st.lam_def), _p(st.adam_m), _p(st.adam_v), _ip(_mask(frozen)))
     if getattr(pb, "limits", 0) == 1:  # projected limits: clamp the updated theta into the box
-        np.clip(st.theta, pb.lo, pb.hi, out=st.theta)
+        keep = np.ones(N, dtype=bool) if frozen is None else ~np.asarray(frozen, dtype=bool)
+        st.theta[keep] = np.clip(st.theta[keep], pb.lo, pb.hi)
 
 
 def csvgd_iteration(pb, obs, st: State, it, optimizer=1):
-    """One CSVGD iteration (Algorithm 1) on FP64 state; returns intermediates."""
+    """One CSVGD iteration (Algorithm 1) on FP64 state; returns intermediates.
+
+    Particles whose simulation fails (a non-finite state, likelihood or
+    gradient) leave the ensemble: they are left out of the phi sums at once
+    and keep their variables; from the next iteration on (FLAG_FROZEN) they
+    are left out of the bandwidth median as well.  The median is taken over
+    the ensemble as the previous update left it, since it depends on the
+    particles' positions alone."""
+    h, med = bandwidth(st.theta, pb.rho, live=(st.flags & FLAG_FROZEN) == 0)
     g = gradient(pb, obs, st)
-    h, med = bandwidth(st.theta, pb.rho)
-    ph = phi(st.theta, g["g_obs"], pb.rho, h)
-    mdmm_step(pb, st, ph, g["g_con"], g["S_dot"], g["gdef"], optimizer, it)
-    g.update(bandwidth=h, median=med, phi=ph)
+    st.flags |= nonfinite_flags(g)
+    out = (st.flags & (FLAG_STATE | FLAG_GRAD | FLAG_FROZEN)) != 0
+    ph = phi(st.theta, g["g_obs"], pb.rho, h, live=~out)
+    mdmm_step(pb, st, ph, g["g_con"], g["S_dot"], g["gdef"], optimizer, it, frozen=out)
+    st.flags |= np.where(out, FLAG_FROZEN, 0)
+    g.update(bandwidth=h, median=med, phi=ph, flags=st.flags.copy(), n_masked=int(out.sum()))
     return g

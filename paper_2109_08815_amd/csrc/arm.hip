@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   }
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
   float* es = J.end_states + iu * DS;
-  bool bad = false;
+  bool bad = false, bad_ll = false;
   for (int d = 0; d < NB; ++d) {
     es[d] = q[d];
     es[NB + d] = qd[d];
@@ -138,9 +138,10 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
       if (J.lik == PDS_LIK_DEFECT) ll += -0.5 * g + defect_log_norm(J);
     }
     J.ll_win[iu] = ll;
-    bad |= !isfinite(ll);
+    bad_ll = !isfinite(ll);
   }
-  if (bad && J.flags) atomicOr(&J.flags[w.i], 1);
+  const int fl = (bad ? PDS_FLAG_STATE : 0) | (bad_ll ? PDS_FLAG_GRAD : 0);
+  if (fl && J.flags) atomicOr(&J.flags[w.i], fl);
 }
 
 // Adjoint kernel: one lane per unit, both adjoint channels in one reverse
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   ll += (double)h * arm_obs_log_norm<BOX>(J);
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
   float* es = J.end_states + iu * DS;
-  bool bad = false;
+  bool bad = false, bad_g = false;  // non-finite state; likelihood or gradient
   for (int d = 0; d < NB; ++d) {
     es[d] = q[d];
     es[NB + d] = qd[d];
@@ -254,7 +255,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
       qdb[1][d] = sc * e1[d] * J.u[NB + d];
     }
   }
-  bad |= !isfinite(ll);
+  bad_g |= !isfinite(ll);
   J.ll_win[iu] = ll;
 
   // reverse sweep over the segments, each from its checkpoints
@@ -339,7 +340,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   for (int m = 0; m < M; ++m) {
     gth_obs[iu * M + m] = gm[0][m];
     gth_con[iu * M + m] = gm[1][m];
-    bad |= !isfinite(gm[0][m]) || !isfinite(gm[1][m]);
+    bad_g |= !isfinite(gm[0][m]) || !isfinite(gm[1][m]);
   }
   for (int d = 0; d < NB; ++d) {
     gs_obs[iu * DS + d] = qb[0][d];
@@ -347,7 +348,8 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
     gs_con[iu * DS + d] = qb[1][d];
     gs_con[iu * DS + NB + d] = qdb[1][d];
   }
-  if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
+  const int fl = (bad ? PDS_FLAG_STATE : 0) | (bad_g ? PDS_FLAG_GRAD : 0);
+  if (fl && J.flags) atomicOr(&J.flags[w.i], fl);
 }
 
 }  // namespace

@@ -54,7 +54,7 @@ __device__ inline void combine_particle(const pds_job& J, int i) {
     lp = mx + log(z) - log((double)K);
   }
   J.logp[i] = lp;
-  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], PDS_FLAG_GRAD);
 }
 
 // Forward-only path: one thread per particle.
@@ -111,7 +111,7 @@ __device__ inline void sdot_finish(const pds_job& J, int i, int r, const SdotPar
   double v = seed * w * p.a - p.b;
   v -= p.c;
   J.S_dot[(size_t)i * nS + r] = (float)v;
-  if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], 2);
+  if (!isfinite(v) && J.flags) atomicOr(&J.flags[i], PDS_FLAG_GRAD);
 }
 
 // Wave sum over the 64 lanes by a fixed xor tree (every lane gets the sum).
@@ -152,7 +152,7 @@ __device__ inline void combine_wave(const pds_job& J, int i, const double* l, do
   for (int k = lane; k < K; k += kWave) J.wk[(size_t)i * K + k] = w[k];
   if (lane == 0) {
     J.logp[i] = lp;
-    if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+    if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], PDS_FLAG_GRAD);
   }
 }
 
@@ -174,7 +174,7 @@ __device__ inline void combine_sums(const pds_job& J, int i) {
     lp = mx + log(z) - log((double)K);
   }
   J.logp[i] = lp;
-  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], 2);
+  if (!isfinite(lp) && J.flags) atomicOr(&J.flags[i], PDS_FLAG_GRAD);
 }
 
 // Adjoint path: one block per particle.  Every global load of the particle
@@ -264,8 +264,10 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, 
       __syncthreads();
     }
     if (t < m1 - m0) {
-      J.g_obs[(size_t)i * M + m0 + t] = seed * so;
+      const double gob = seed * so;
+      J.g_obs[(size_t)i * M + m0 + t] = gob;
       J.g_con[(size_t)i * M + m0 + t] = scon;
+      if (!(isfinite(gob) && isfinite(scon)) && J.flags) atomicOr(&J.flags[i], PDS_FLAG_GRAD);
     }
   }
   if (inl) {

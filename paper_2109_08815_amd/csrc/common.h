@@ -94,6 +94,7 @@ struct WsLayout {
   size_t cand;                              // median candidates: 64-bit keys of larger jobs, or the
                                             // low-word lists of small jobs (one slot per pair)
   size_t phi_part;                          // phi partial sums (jobs above kPhiFusedMaxN particles)
+  size_t phi_live;                          // live particles of each phi chunk (same jobs)
   size_t total;
 };
 
@@ -129,6 +130,7 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   L.cand = o;    o = align256(o + P * (large ? sizeof(uint64_t) : sizeof(uint32_t)));
   const size_t chunks = J.N > kPhiFusedMaxN ? ((size_t)J.N + kPhiChunk - 1) / kPhiChunk : 0;
   L.phi_part = o; o = align256(o + chunks * (size_t)J.N * J.M * sizeof(float));
+  L.phi_live = o; o = align256(o + chunks * sizeof(uint32_t));
   L.total = o;
   return L;
 }

@@ -138,7 +138,10 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     REQ(g_obs, 8); REQ(g_con, 8);
     if (J.n_s > 1) { REQ(S_dot, 4); if (!J.seed_gdef) REQ(lam_def, 4); }
   }
-  if (need & NEED_PHI) { REQ(rho, 4); REQ(g_obs, 8); REQ(phi, 4); REQ(bandwidth, 8); REQ(theta, 4); }
+  if (need & NEED_PHI) {
+    REQ(rho, 4); REQ(g_obs, 8); REQ(phi, 4); REQ(bandwidth, 8); REQ(theta, 4);
+    if (J.n_masked && !aligned(J.n_masked, 4)) return fail(PDS_EINVAL, "job %d: n_masked is misaligned", idx);
+  }
   if (need & NEED_BW) { REQ(rho, 4); REQ(bandwidth, 8); REQ(theta, 4); }
   if (need & NEED_STEP) {
     REQ(theta, 4); REQ(lo, 4); REQ(hi, 4); REQ(lr_theta, 4); REQ(lam_lim, 4); REQ(phi, 4); REQ(g_con, 8);
@@ -493,7 +496,7 @@ size_t pds_job_footprint(const pds_job* h_job) {
   f32 += 2 * N * (M + K * nsm * ds);                                   // adam_m adam_v
   f32 += N * K * ns * ds + N * K * nsm1 * ds + N * M;                  // end_states S_dot phi
   size_t f64 = N * K * ns + N * K * nsm1 + N + N * K + 2 * N * M + 1;  // ll_win gdef logp wk g_obs g_con bandwidth
-  const size_t i32 = N + 2;                                            // flags iter_dev
+  const size_t i32 = N + 3;                                            // flags iter_dev n_masked
   if (J.traj) f32 += N * K * T * ds;
   if (J.seed_logp) f64 += N;
   if (J.seed_gdef) f64 += N * K * nsm;

@@ -635,7 +635,7 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
   float* es = J.end_states + iu * DS;
 #pragma unroll
   for (int d = 0; d < NB; ++d) { es[d] = q[d]; es[NB + d] = qd[d]; }
-  bool bad = false;
+  bool bad = false, bad_ll = false;
 #pragma unroll
   for (int d = 0; d < NB; ++d) bad |= !isfinite(q[d]) || !isfinite(qd[d]);
   if (with_ll) {
@@ -654,9 +654,10 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
       if (J.lik == PDS_LIK_DEFECT) ll += -0.5 * g + defect_log_norm(J);
     }
     J.ll_win[iu] = ll;
-    bad |= !isfinite(ll);
+    bad_ll = !isfinite(ll);
   }
-  if (bad && J.flags) atomicOr(&J.flags[w.i], 1);
+  const int fl = (bad ? PDS_FLAG_STATE : 0) | (bad_ll ? PDS_FLAG_GRAD : 0);
+  if (fl && J.flags) atomicOr(&J.flags[w.i], fl);
 }
 
 // Segment length of the adjoint's checkpointing: about sqrt(h).
@@ -800,7 +801,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
   }
   ll += (double)h * log_norm_const(J);
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
-  bool bad = false;
+  bool bad = false, bad_g = false;  // non-finite state; likelihood or gradient
 #pragma unroll
   for (int d = 0; d < NB; ++d) bad |= !isfinite(q[d]) || !isfinite(qd[d]);
   if (ch == 0) {
@@ -856,7 +857,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
       }
     }
   }
-  bad |= !isfinite(ll);
+  bad_g |= !isfinite(ll);
   if (ch == 0) J.ll_win[iu] = ll;
 
   // ---- reverse sweep over segments (steps h-1 .. 0 in one descending order) ----
@@ -930,7 +931,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     double* gth = ch == 0 ? gth_obs : gth_con;
     float* gs = ch == 0 ? gs_obs : gs_con;
 #pragma unroll
-    for (int m = 0; m < MP; ++m) bad |= !isfinite(gm_a[m]);
+    for (int m = 0; m < MP; ++m) bad_g |= !isfinite(gm_a[m]);
     store_row<MP>(gth + iu * MP, gm_a);
     float row[DS];
 #pragma unroll
@@ -938,7 +939,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     store_row<DS>(gs + iu * DS, row);
   } else {
 #pragma unroll
-    for (int m = 0; m < MP; ++m) bad |= !isfinite(gm_a[m]) || !isfinite(gm_c[m]);
+    for (int m = 0; m < MP; ++m) bad_g |= !isfinite(gm_a[m]) || !isfinite(gm_c[m]);
     store_row<MP>(gth_obs + iu * MP, gm_a);
     store_row<MP>(gth_con + iu * MP, gm_c);
     float ra[DS], rc[DS];
@@ -952,7 +953,8 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     store_row<DS>(gs_obs + iu * DS, ra);
     store_row<DS>(gs_con + iu * DS, rc);
   }
-  if (bad && J.flags) atomicOr(&J.flags[w.i], 2);
+  const int fl = (bad ? PDS_FLAG_STATE : 0) | (bad_g ? PDS_FLAG_GRAD : 0);
+  if (fl && J.flags) atomicOr(&J.flags[w.i], fl);
 }
 
 }  // namespace

@@ -25,6 +25,15 @@
 // Counts are integers, so the result does not depend on the order in which
 // blocks finish.
 //
+// Failed particles.  Particles with flag bit 3 are out of the median's
+// ensemble: a pair with such an endpoint gets the key kMaskedKey, above
+// every key of a non-negative double, so the ensemble's keys keep their
+// ranks from the bottom, and the targets are the middle ranks of the
+// ensemble's P' = N' (N' - 1) / 2 pairs.  Count kernels skip such pairs.
+// phi leaves out particles with flag bit 0, 1 or 3: each chunk of rows is
+// compacted to its live particles before the sums, and the sums are
+// divided by their number.
+//
 // phi.  Up to kPhiFusedMaxN particles: one block per 16 particles i (4
 // above 128 particles) with every particle's row in LDS and 1024 / 16 (or
 // 1024 / 4) slices of the j range.  Larger jobs: blocks of 64 particles i against
@@ -44,6 +53,36 @@ constexpr int kPairBlock = 64;  // particles i per block
 __device__ inline MedianState* med_state(const pds_job& J, char* ws, uint64_t off) {
   const WsLayout L = ws_layout(J);
   return reinterpret_cast<MedianState*>(ws + off + L.med);
+}
+
+// Flag bits that take a particle out of phi and freeze it in the step.
+constexpr int kOutOfEnsemble = PDS_FLAG_STATE | PDS_FLAG_GRAD | PDS_FLAG_FROZEN;
+// Key of a pair with a frozen endpoint (its sign bit set: above every key).
+constexpr uint64_t kMaskedKey = ~0ull;
+
+// Whether particle i is out of the median's ensemble (flag bit 3).  An
+// atomic load: a concurrent adjoint may OR bits 0 and 1 into the same
+// word; bit 3 changes only in the step kernel.
+__device__ inline bool frozen_particle(const pds_job& J, int i) {
+  return J.flags && (__hip_atomic_load(J.flags + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & PDS_FLAG_FROZEN);
+}
+
+// Whether particle i takes part in phi (no flag bit 0, 1 or 3).
+__device__ inline bool in_phi(const pds_job& J, int i) { return !J.flags || (J.flags[i] & kOutOfEnsemble) == 0; }
+
+// Size N' of the median's ensemble, counted by a block of NT threads into
+// *s (every thread returns it).  Contains two block barriers.
+template <int NT>
+__device__ inline uint32_t ensemble_size(const pds_job& J, uint32_t* s) {
+  uint32_t c = 0;
+  for (int i = threadIdx.x; i < J.N; i += NT) c += frozen_particle(J, i) ? 0u : 1u;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (threadIdx.x == 0) *s = 0u;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) atomicAdd(s, c);
+  __syncthreads();
+  return *s;
 }
 
 // Squared scaled distance in FP64, summed in parameter order.  MM is a
@@ -422,14 +461,15 @@ __device__ void select_keys(const KT* src, uint32_t n, bool src_global, KT* lds,
   out[1] = S.tg[1].lo;
 }
 
-__device__ inline void write_bandwidth(const pds_job& J, uint64_t k0, uint64_t k1) {
-  const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
+// h = med^2 / log N' from the two middle keys of an ensemble of nb
+// particles (h = 1 when it has no pair).
+__device__ inline void write_bandwidth(const pds_job& J, uint64_t k0, uint64_t k1, uint32_t nb) {
   double h = 1.0;
-  if (P > 0) {
+  if (nb > 1) {
     const double a = __longlong_as_double((long long)k0);
     const double c = __longlong_as_double((long long)k1);
     const double med = 0.5 * (sqrt(a) + sqrt(c));
-    const double lg = log((double)J.N);
+    const double lg = log((double)nb);
     if (med * med >= 1e-300 && lg > 0.0) h = med * med / lg;
   }
   J.bandwidth[0] = h;
@@ -491,7 +531,8 @@ __global__ void __launch_bounds__(256) median_keys_kernel(JobMap map, const pds_
   load_inv_rho<MM>(J, inv_rho);
   int i, j;
   pair_of(small ? (uint64_t)k : sample_pair(k, P), J.N, &i, &j);
-  const uint64_t key = pair_key<MM>(J, i, j, inv_rho);
+  const uint64_t key =
+      (frozen_particle(J, i) || frozen_particle(J, j)) ? kMaskedKey : pair_key<MM>(J, i, j, inv_rho);
   reinterpret_cast<uint32_t*>(base + L.khi)[k] = (uint32_t)(key >> 32);
   if (small) reinterpret_cast<uint32_t*>(base + L.klo)[k] = (uint32_t)key;
 }
@@ -506,7 +547,7 @@ template <int NT>
 __device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws, uint64_t ws_off, uint32_t* lbuf,
                                                       SelShared<uint32_t>& S, const uint32_t* khi,
                                                       const uint32_t* klo, uint32_t* lists, uint32_t n, bool small,
-                                                      bool a_open, bool b_open) {
+                                                      bool a_open, bool b_open, uint32_t nb) {
   uint32_t hsel[2];
   select_keys<NT>(khi, n, true, lbuf, (uint32_t)kSelLdsCap, S, hsel, false);
   if (!small) {
@@ -553,17 +594,17 @@ __device__ __attribute__((noinline)) void select_rest(const pds_job& J, char* ws
     lsel[1] = tmp[1];
   }
   if (threadIdx.x == 0)
-    write_bandwidth(J, ((uint64_t)hsel[0] << 32) | lsel[0], ((uint64_t)hsel[1] << 32) | lsel[1]);
+    write_bandwidth(J, ((uint64_t)hsel[0] << 32) | lsel[0], ((uint64_t)hsel[1] << 32) | lsel[1], nb);
 }
 
 // Select kernel, one block per job.  Loads the high words written by the
-// keys kernel into LDS (the first selection level, over [0, 2^32), is
-// histogrammed during the load) and selects two ranks among them: the
-// middle ranks of all pairs for small jobs, which then finish on the low
-// words of the keys sharing the selected high words; for larger jobs the
-// sample's order statistics at the middle ranks' sample positions widened
-// by four binomial standard deviations, stored as the bracket [a, b]
-// (whole high words) for the count kernel.
+// keys kernel into registers and selects two ranks among them: the middle
+// ranks of the ensemble's pairs for small jobs, which then finish on the
+// low words of the keys sharing the selected high words; for larger jobs
+// the sample's order statistics at the middle ranks' sample positions
+// widened by four binomial standard deviations, stored as the bracket
+// [a, b] (whole high words) for the count kernel.  Masked keys (high word
+// kNoKey) take part in no range or count.
 __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_kernel(
     JobMap map, const pds_job* __restrict__ jobs, char* __restrict__ ws, int rank_shift) {
   __shared__ uint32_t lbuf[kSelLdsCap];  // used by select_rest only
@@ -571,13 +612,13 @@ __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_k
   __shared__ uint64_t cand[kDirectMax];
   __shared__ uint32_t cidx[kDirectMax];
   __shared__ SelPair<uint64_t> P64;
-  __shared__ uint32_t s_lo, s_hi, s_cnt;
+  __shared__ uint32_t s_lo, s_hi, s_cnt, s_nb, s_nv;
   constexpr int NT = kMedThreads;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
   if (P == 0) {
-    if (threadIdx.x == 0) write_bandwidth(J, 0ull, 0ull);
+    if (threadIdx.x == 0) write_bandwidth(J, 0ull, 0ull, 1u);
     return;
   }
   const bool small = P <= (uint64_t)kSmallPairs;
@@ -608,16 +649,20 @@ __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_k
     }
   }
   auto key_at = [&](int k) { return 4u * ((k >> 2) * NT + threadIdx.x) + (k & 3); };
-  // while the loads are in flight: clear the histogram and the block's
-  // min / max / candidate count
+  // while the loads are in flight: the ensemble's particles, and clear the
+  // histogram and the block's min / max / key counts
+  uint32_t nbl = 0u;
+  for (int i = threadIdx.x; i < J.N; i += NT) nbl += frozen_particle(J, i) ? 0u : 1u;
   for (int b = threadIdx.x; b < kSelBins; b += NT) S.hist[0][b] = 0u;
   if (threadIdx.x == 0) {
     s_lo = kNoKey;
     s_hi = 0u;
     s_cnt = 0u;
+    s_nb = 0u;
+    s_nv = 0u;
   }
   __syncthreads();
-  uint32_t mn = kNoKey, mx = 0u;
+  uint32_t mn = kNoKey, mx = 0u, nvl = 0u;
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const uint32_t w4[4] = {q[v].x, q[v].y, q[v].z, q[v].w};
@@ -627,6 +672,7 @@ __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_k
       hv[4 * v + c] = h;
       mn = h < mn ? h : mn;
       mx = (h != kNoKey && h > mx) ? h : mx;
+      nvl += h != kNoKey ? 1u : 0u;
     }
   }
 #pragma unroll
@@ -634,26 +680,48 @@ __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_k
     const uint32_t a = (uint32_t)__shfl_xor((int)mn, o), b = (uint32_t)__shfl_xor((int)mx, o);
     mn = a < mn ? a : mn;
     mx = b > mx ? b : mx;
+    nvl += (uint32_t)__shfl_xor((int)nvl, o);
+    nbl += (uint32_t)__shfl_xor((int)nbl, o);
   }
   if ((threadIdx.x & 63) == 0) {
     atomicMin(&s_lo, mn);
     atomicMax(&s_hi, mx);
+    atomicAdd(&s_nv, nvl);
+    atomicAdd(&s_nb, nbl);
   }
   __syncthreads();
   const uint32_t lo = s_lo, hi = s_hi;
+  const uint32_t nb = s_nb, nv = s_nv;  // ensemble particles, unmasked keys in registers
+  const uint64_t Pe = (uint64_t)nb * (nb - 1) / 2;
+  if (Pe == 0 || nv == 0) {
+    // no pair in the ensemble (h = 1), or none in the sample: then the
+    // bracket is every key and the count kernel collects the ensemble's
+    if (threadIdx.x == 0) {
+      if (small || Pe == 0) {
+        write_bandwidth(J, 0ull, 0ull, nb);
+      } else {
+        MedianState* st = med_state(J, ws, map.ws_off[e]);
+        st->a = 0ull;
+        st->b = ~0ull;
+      }
+    }
+    return;
+  }
   uint32_t t0, t1;
   bool a_open = false, b_open = false;
   if (small) {
-    t0 = (uint32_t)((P - 1) / 2);
-    t1 = (uint32_t)(P / 2);
+    t0 = (uint32_t)((Pe - 1) / 2);
+    t1 = (uint32_t)(Pe / 2);
   } else {
+    // sample positions of the ensemble's middle ranks: masked keys sort
+    // above them, so the first nv sample positions hold the ensemble's keys
     const double d = 2.0 * sqrt((double)n) + 2.0;
-    const double c0 = (double)n * (double)((P - 1) / 2) / (double)P - d + rank_shift;
-    const double c1 = (double)n * (double)(P / 2 + 1) / (double)P + d + rank_shift;
-    a_open = c0 < 0.0;
-    b_open = c1 > (double)(n - 1);
-    t0 = a_open ? 0u : (uint32_t)fmin(floor(c0), (double)(n - 1));
-    t1 = b_open ? n - 1 : (uint32_t)fmax(ceil(c1), 0.0);
+    const double c0 = (double)n * (double)((Pe - 1) / 2) / (double)P - d + rank_shift;
+    const double c1 = (double)n * (double)(Pe / 2 + 1) / (double)P + d + rank_shift;
+    a_open = c0 < 0.0 || c0 > (double)(nv - 1);
+    b_open = c1 > (double)(nv - 1);
+    t0 = a_open ? 0u : (uint32_t)floor(c0);
+    t1 = b_open ? nv - 1 : (uint32_t)fmax(ceil(c1), 0.0);
   }
   // First level over the keys' own range [lo, hi]: one histogram for both
   // targets and one block scan over it narrows both.
@@ -695,7 +763,7 @@ __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_k
   __syncthreads();
   const SelTarget<uint32_t> g0 = S.tg[0], g1 = S.tg[1];
   const bool same_bin = g0.lo == g1.lo && g0.hi == g1.hi;
-  const uint32_t need = lo == hi ? n : (same_bin ? S.cnt[0] : S.cnt[0] + S.cnt[1]);
+  const uint32_t need = lo == hi ? nv : (same_bin ? S.cnt[0] : S.cnt[0] + S.cnt[1]);
   if (need <= (uint32_t)kDirectMax) {
     // Direct finish: the indices of the keys in the two bins go to cidx
     // (order immaterial: the ranking below orders by value, then by
@@ -728,7 +796,7 @@ __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_k
     if (threadIdx.x == 0) {
       const uint64_t k0 = P64.tg[0].lo, k1 = P64.tg[1].lo;
       if (small) {
-        write_bandwidth(J, k0, k1);
+        write_bandwidth(J, k0, k1, nb);
       } else {
         MedianState* st = med_state(J, ws, map.ws_off[e]);
         st->a = a_open ? 0ull : (k0 >> 32) << 32;
@@ -738,11 +806,12 @@ __global__ void __launch_bounds__(kMedThreads, kSelWavesPerSimd) median_select_k
     return;
   }
   select_rest<NT>(J, ws, map.ws_off[e], lbuf, S, khi, klo, reinterpret_cast<uint32_t*>(base + L.cand), n, small,
-                  a_open, b_open);
+                  a_open, b_open, nb);
 }
 
-// Keys of every pair inside [lo, hi] into cand (block-scan order); one
-// block, used only when the sampled bracket missed a middle rank.
+// Keys of every ensemble pair inside [lo, hi] into cand (block-scan
+// order); one block, used only when the sampled bracket missed a middle
+// rank.
 template <int MM, int NT>
 __device__ uint32_t collect_pairs(const pds_job& J, const double* inv_rho, uint64_t lo, uint64_t hi, uint64_t* cand,
                                   SelShared<uint64_t>& S) {
@@ -761,8 +830,10 @@ __device__ uint32_t collect_pairs(const pds_job& J, const double* inv_rho, uint6
       if (p < P) {
         int i, j;
         pair_of(p, J.N, &i, &j);
-        key[u] = pair_key<MM>(J, i, j, inv_rho);
-        keep[u] = key[u] >= lo && key[u] <= hi;
+        if (!frozen_particle(J, i) && !frozen_particle(J, j)) {
+          key[u] = pair_key<MM>(J, i, j, inv_rho);
+          keep[u] = key[u] >= lo && key[u] <= hi;
+        }
       }
       cnt += keep[u] ? 1u : 0u;
     }
@@ -777,15 +848,16 @@ __device__ uint32_t collect_pairs(const pds_job& J, const double* inv_rho, uint6
 }
 
 // Count kernel over all pairs of the larger jobs, 64 x 64 pairs per block.
-// Each block adds its number of keys below a and its number of keys inside
-// [a, b] to one packed 64-bit counter and appends the latter to the job's
-// candidate array at the offset the addition returned.
+// Each block adds its number of ensemble keys below a and inside [a, b] to
+// one packed 64-bit counter and appends the latter to the job's candidate
+// array at the offset the addition returned.
 template <int MM>
 __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                    char* __restrict__ ws) {
   __shared__ uint64_t lbuf[kCountTile * kCountTile];
   __shared__ uint32_t wsum[16];
   __shared__ float ti_s[kCountTile * MM], tj_s[kCountTile * MM];
+  __shared__ bool fi_s[kCountTile], fj_s[kCountTile];  // frozen particles of the two tiles
   __shared__ uint32_t less_s;
   __shared__ uint32_t base_s;
   constexpr int NT = kMedThreads;
@@ -805,6 +877,11 @@ __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, c
     ti_s[t] = (r < ni && m < M) ? J.theta[(size_t)(ri + r) * M + m] : 0.f;
     tj_s[t] = (r < nj && m < M) ? J.theta[(size_t)(rj + r) * M + m] : 0.f;
   }
+  if (threadIdx.x < kCountTile) fi_s[threadIdx.x] = threadIdx.x < ni && frozen_particle(J, ri + threadIdx.x);
+  else if (threadIdx.x < 2 * kCountTile) {
+    const int r = threadIdx.x - kCountTile;
+    fj_s[r] = r < nj && frozen_particle(J, rj + r);
+  }
   if (threadIdx.x == 0) less_s = 0u;
   __syncthreads();
   double inv_rho[MM];
@@ -818,7 +895,7 @@ __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, c
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int jl = cg * 4 + q;
-    const bool valid = row < ni && jl < nj && i < rj + jl;
+    const bool valid = row < ni && jl < nj && i < rj + jl && !fi_s[row] && !fj_s[jl];
     key[q] = valid ? key_of(pair_d2<MM>(&ti_s[row * MM], &tj_s[jl * MM], inv_rho, M)) : 0ull;
     nless += (valid && key[q] < a) ? 1u : 0u;
     keep[q] = valid && key[q] >= a && key[q] <= b;
@@ -852,19 +929,26 @@ __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, c
   for (uint32_t c = threadIdx.x; c < total; c += NT) cand[base_s + c] = lbuf[c];
 }
 
-// Final kernel, one block per larger job: both middle keys exactly among
-// the candidates or, if the bracket missed a middle rank, among the keys of
-// the interval that holds both (recomputed from theta).
+// Final kernel, one block per larger job: both middle keys of the
+// ensemble's pairs exactly among the candidates or, if the bracket missed a
+// middle rank, among the keys of the interval that holds both (recomputed
+// from theta).
 template <int MM>
 __global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                    char* __restrict__ ws) {
   __shared__ uint64_t lbuf[kLastCap];
   __shared__ SelShared<uint64_t> S;
+  __shared__ uint32_t s_nb;
   constexpr int NT = kMedThreads;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const MedianState* st = med_state(J, ws, map.ws_off[e]);
-  const uint32_t P = (uint32_t)((uint64_t)J.N * (J.N - 1) / 2);
+  const uint32_t nb = ensemble_size<NT>(J, &s_nb);
+  const uint32_t P = (uint32_t)((uint64_t)nb * (nb - 1) / 2);  // the ensemble's pairs
+  if (P == 0) {
+    if (threadIdx.x == 0) write_bandwidth(J, 0ull, 0ull, nb);
+    return;
+  }
   const WsLayout L = ws_layout(J);
   uint64_t* cand = reinterpret_cast<uint64_t*>(ws + map.ws_off[e] + L.cand);
   const uint64_t a = st->a, b = st->b, packed = st->packed;
@@ -887,13 +971,15 @@ __global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, c
   __syncthreads();
   uint64_t out[2];
   select_keys<NT>((const uint64_t*)cand, n, true, lbuf, (uint32_t)kLastCap, S, out);
-  if (threadIdx.x == 0) write_bandwidth(J, out[0], out[1]);
+  if (threadIdx.x == 0) write_bandwidth(J, out[0], out[1], nb);
 }
 
 // Larger jobs: partial phi of particles i (one per lane) over one chunk
-// of j (many blocks), then a reduction over the chunks in chunk order.  Chunk
-// rows sit in LDS with stride MM, zero beyond M, so the parameter loops
-// run unconditionally (padded terms contribute 0).
+// of j (many blocks), then a reduction over the chunks in chunk order.  The
+// chunk's live rows sit in LDS in particle order with stride MM, zero
+// beyond M, so the parameter loops run unconditionally (padded terms
+// contribute 0); the blocks of the first i range store each chunk's number
+// of live rows for the reduction.
 template <int MM>
 __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                                  char* __restrict__ ws) {
@@ -907,13 +993,22 @@ __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, con
   const int ib = local % nib, jc = local / nib;
   const int j0 = jc * kPhiChunk;
   const int nj = min(kPhiChunk, N - j0);
-  for (int t = threadIdx.x; t < kPhiChunk * MM; t += kPairBlock) {
-    const int r = t / MM, m = t % MM;
-    const bool in = r < nj && m < M;
-    tj_s[t] = in ? J.theta[(size_t)(j0 + r) * M + m] : 0.f;
-    gj_s[t] = in ? (float)J.g_obs[(size_t)(j0 + r) * M + m] : 0.f;
+  static_assert(kPhiChunk <= kPairBlock && kPairBlock == kWave, "one wave compacts the chunk");
+  const bool lv = (int)threadIdx.x < nj && in_phi(J, j0 + threadIdx.x);
+  const uint64_t bal = __ballot(lv);
+  const int nl = __popcll(bal);
+  if (lv) {
+    const int pos = __popcll(bal & ((1ull << threadIdx.x) - 1ull));
+    const size_t src = (size_t)(j0 + threadIdx.x) * M;
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+      tj_s[pos * MM + m] = m < M ? J.theta[src + m] : 0.f;
+      gj_s[pos * MM + m] = m < M ? (float)J.g_obs[src + m] : 0.f;
+    }
   }
   __syncthreads();
+  const WsLayout L = ws_layout(J);
+  if (ib == 0 && threadIdx.x == 0) reinterpret_cast<uint32_t*>(ws + map.ws_off[e] + L.phi_live)[jc] = (uint32_t)nl;
   const int i = ib * kPairBlock + threadIdx.x;
   if (i >= N) return;
   const float h = (float)J.bandwidth[0];
@@ -927,7 +1022,7 @@ __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, con
     ir2[m] = ir[m] * ir[m];
     acc[m] = 0.f;
   }
-  for (int jj = 0; jj < nj; ++jj) {
+  for (int jj = 0; jj < nl; ++jj) {
     float d2 = 0.f;
 #pragma unroll
     for (int m = 0; m < MM; ++m) {
@@ -939,21 +1034,36 @@ __global__ void __launch_bounds__(kPairBlock) phi_partial_kernel(JobMap map, con
 #pragma unroll
     for (int m = 0; m < MM; ++m) acc[m] += k * gj_s[jj * MM + m] + k2h * (ti[m] - tj_s[jj * MM + m]) * ir2[m];
   }
-  const WsLayout L = ws_layout(J);
   float* part = reinterpret_cast<float*>(ws + map.ws_off[e] + L.phi_part);
 #pragma unroll
   for (int m = 0; m < MM; ++m)
     if (m < M) part[((size_t)jc * N + i) * M + m] = acc[m];
 }
 
+// phi_i = (sum of the partials) / N' with N' the live rows of all chunks;
+// 0 for particles out of the ensemble.
 __global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_job* __restrict__ jobs,
                                                          char* __restrict__ ws) {
+  __shared__ uint32_t s_live;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int t = (blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
-  if (t >= J.N * J.M) return;
   const int chunks = (J.N + kPhiChunk - 1) / kPhiChunk;
   const WsLayout L = ws_layout(J);
+  {
+    const uint32_t* lc = reinterpret_cast<const uint32_t*>(ws + map.ws_off[e] + L.phi_live);
+    uint32_t c = 0;
+    for (int q = threadIdx.x; q < chunks; q += 256) c += lc[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (threadIdx.x == 0) s_live = 0u;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicAdd(&s_live, c);
+    __syncthreads();
+  }
+  const uint32_t n_live = s_live;
+  if (J.n_masked && blockIdx.x == map.begin[e] && threadIdx.x == 0) *J.n_masked = J.N - (int)n_live;
+  if (t >= J.N * J.M) return;
   const float* part = reinterpret_cast<const float*>(ws + map.ws_off[e] + L.phi_part);
   const size_t stride = (size_t)J.N * J.M;
   float s = 0.f;
@@ -966,17 +1076,19 @@ __global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_j
     for (int b = 0; b < B; ++b)
       if (c0 + b < chunks) s += v[b];
   }
-  J.phi[t] = s / (float)J.N;
+  J.phi[t] = in_phi(J, t / J.M) ? s / (float)n_live : 0.f;
 }
 
 // Jobs up to kPhiFusedMaxN particles: phi for TI particles i per block
-// (16 up to 128 particles, 4 above: more blocks, each with less work).  The block stages the
-// particles' rows and driving terms in LDS kPhiRows at a time (rows padded
+// (16 up to 128 particles, 4 above: more blocks, each with less work).  The
+// block stages the live particles' rows and driving terms in LDS, from
+// kPhiRows particles at a time, compacted in particle order (rows padded
 // with zeros to MM parameters, so the parameter loops run without
-// branches); thread (il, js) accumulates particle i0 + il over j = js,
-// js + 1024 / TI, ... in that order; the slices of a wave that share il
-// are added by a fixed shuffle tree, then the 16 waves' sums in wave
-// order.  Every sum has a fixed order that depends on N alone.
+// branches); thread (il, js) accumulates particle i0 + il over staged rows
+// js, js + 1024 / TI, ... in that order; the slices of a wave that share
+// il are added by a fixed shuffle tree, then the 16 waves' sums in wave
+// order.  Every sum has a fixed order that depends on N and the flags
+// alone.
 template <int MM, int TI>
 __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_job* __restrict__ jobs) {
   constexpr int kPhiTI = TI;
@@ -985,6 +1097,8 @@ __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_
   __shared__ float tj_s[kPhiRows * MM];
   __shared__ float gj_s[kPhiRows * MM];
   __shared__ float red[kPhiThreads / kWave][kPhiTI * MM];
+  __shared__ uint32_t wlive[kPhiThreads / kWave];
+  static_assert(kPhiRows <= kPhiThreads, "one thread per row of a chunk");
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const int N = J.N, M = J.M;
@@ -1003,19 +1117,35 @@ __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_
     ir2[m] = ir[m] * ir[m];
     acc[m] = 0.f;
   }
+  const int lane = threadIdx.x % kWave;
+  uint32_t n_live = 0;  // live particles of the chunks so far (the same in every thread)
   for (int j0 = 0; j0 < N; j0 += kPhiRows) {
     const int nr = min(kPhiRows, N - j0);
     if (j0 > 0) __syncthreads();  // the previous chunk is consumed
-    for (int t = threadIdx.x; t < nr * MM; t += kPhiThreads) {
-      const int r = t / MM, m = t % MM;
-      const size_t src = (size_t)(j0 + r) * M + (m < M ? m : M - 1);
-      const float th = J.theta[src];
-      const double g = J.g_obs[src];
-      tj_s[t] = m < M ? th : 0.f;
-      gj_s[t] = m < M ? (float)g : 0.f;
+    // thread r < nr owns row j0 + r; live rows go to their rank among the
+    // chunk's live rows
+    const bool lv = (int)threadIdx.x < nr && in_phi(J, j0 + threadIdx.x);
+    const uint64_t bal = __ballot(lv);
+    if (lane == 0) wlive[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, nl = 0;
+#pragma unroll
+    for (int v = 0; v < kPhiThreads / kWave; ++v) {
+      before += v < w ? wlive[v] : 0u;
+      nl += wlive[v];
+    }
+    if (lv) {
+      const uint32_t pos = before + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+      const size_t src = (size_t)(j0 + threadIdx.x) * M;
+#pragma unroll
+      for (int m = 0; m < MM; ++m) {
+        tj_s[pos * MM + m] = m < M ? J.theta[src + m] : 0.f;
+        gj_s[pos * MM + m] = m < M ? (float)J.g_obs[src + m] : 0.f;
+      }
     }
     __syncthreads();
-    for (int jl = js; jl < nr; jl += kSlices) {
+    n_live += nl;
+    for (int jl = js; jl < (int)nl; jl += kSlices) {
       float d2 = 0.f;
 #pragma unroll
       for (int m = 0; m < MM; ++m) {
@@ -1045,12 +1175,16 @@ __global__ void __launch_bounds__(kPhiThreads) phi_kernel(JobMap map, const pds_
     float s = 0.f;
 #pragma unroll
     for (int v = 0; v < kPhiThreads / kWave; ++v) s += red[v][r * MM + m];
-    if (ir_ < N && m < M) J.phi[(size_t)ir_ * M + m] = s / (float)N;
+    if (ir_ < N && m < M) J.phi[(size_t)ir_ * M + m] = in_phi(J, ir_) ? s / (float)n_live : 0.f;
   }
+  if (J.n_masked && blockIdx.x == map.begin[e] && threadIdx.x == 0) *J.n_masked = N - (int)n_live;
 }
 
 // MDMM + optimizer update.  Flat index over theta (N M), S (N K (n_s-1) d_s)
-// and lam_def (N K (n_s-1)).
+// and lam_def (N K (n_s-1)).  Particles out of the ensemble keep every
+// variable; the thread of their first parameter sets flag bit 3.  (That
+// bit is set only where bit 0 or 1 already is, so every thread of the
+// particle takes the same branch whether or not it sees it.)
 __global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pds_job* __restrict__ jobs, int optimizer,
                                                    int iter) {
   const int e = map_entry(map, blockIdx.x);
@@ -1066,7 +1200,10 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pd
   // block-wide wait before the element loads
   const int it = J.iter_dev ? J.iter_dev[0] + 1 : iter;
   const float bc1 = 1.0f - exp2f((float)it * log2f(b1)), bc2 = 1.0f - exp2f((float)it * log2f(b2));
-  if (t < nT) {
+  if (t < nT && !in_phi(J, t / J.M)) {
+    const int i = t / J.M;
+    if (t % J.M == 0 && !(J.flags[i] & PDS_FLAG_FROZEN)) atomicOr(&J.flags[i], PDS_FLAG_FROZEN);
+  } else if (t < nT) {
     const int i = t / J.M, m = t % J.M;
     const float x = J.theta[t];
     const float lo = J.lo[m], hi = J.hi[m];
@@ -1088,8 +1225,8 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pd
     if (J.limits == PDS_LIMITS_PROJECT) xn = fminf(fmaxf(xn, lo), hi);
     J.theta[t] = xn;
     J.lam_lim[t] += J.eps_lam * g;
-    if ((xn < lo || xn > hi) && J.flags) atomicOr(&J.flags[i], 4);
-  } else if (t < nT + nS) {
+    if ((xn < lo || xn > hi) && J.flags) atomicOr(&J.flags[i], PDS_FLAG_LIMIT);
+  } else if (t < nT + nS && in_phi(J, (t - nT) / nSp)) {
     const int r = t - nT;
     const int i = r / nSp, q = r % nSp;
     const int d = q % ds;
@@ -1105,7 +1242,7 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pd
       J.adam_v[a] = vv;
       J.S[r] -= J.lr_S[d] * (mm / bc1) / (sqrtf(vv / bc2) + eps);
     }
-  } else if (t < nT + nS + nL && J.lik != PDS_LIK_DEFECT) {
+  } else if (t >= nT + nS && t < nT + nS + nL && J.lik != PDS_LIK_DEFECT && in_phi(J, (t - nT - nS) / nLp)) {
     const int r = t - nT - nS;
     J.lam_def[r] += J.eps_lam * (float)J.gdef[r];
   }

@@ -31,6 +31,7 @@ PDS_LIMITS_SOFT = 0
 PDS_LIMITS_PROJECT = 1
 PDS_OPT_SGD = 0
 PDS_OPT_ADAM = 1
+PDS_FLAG_STATE, PDS_FLAG_GRAD, PDS_FLAG_LIMIT, PDS_FLAG_FROZEN = 1, 2, 4, 8
 PDS_CALL_FORWARD, PDS_CALL_LOGLIK, PDS_CALL_ADJOINT, PDS_CALL_PHI, PDS_CALL_STEP, PDS_CALL_ALL = range(6)
 PDS_MAX_JOBS = 64
 
@@ -51,7 +52,7 @@ class PdsJob(C.Structure):
         ("theta", _f), ("S", _f), ("lam_lim", _f), ("lam_def", _f), ("adam_m", _f), ("adam_v", _f),
         ("end_states", _f), ("traj", _f), ("ll_win", _f), ("gdef", _f), ("logp", _f), ("wk", _f),
         ("g_obs", _f), ("g_con", _f), ("S_dot", _f), ("phi", _f), ("bandwidth", _f), ("flags", _f),
-        ("iter_dev", _f),
+        ("iter_dev", _f), ("n_masked", _f),
     ]
 
 
@@ -203,6 +204,7 @@ class Job:
         self.bandwidth = torch.zeros(1, dtype=f64, device=dev)
         self.flags = torch.zeros(N, dtype=torch.int32, device=dev)
         self.iter_dev = torch.zeros(2, dtype=torch.int32, device=dev) if device_iter else None
+        self.n_masked = torch.zeros(1, dtype=torch.int32, device=dev)
         self.seed_logp = None if seed_logp is None else _dev(seed_logp, f64, dev)
         self.seed_gdef = None if seed_gdef is None else _dev(seed_gdef, f64, dev)
 
@@ -217,7 +219,7 @@ class Job:
         for name in ("consts", "lo", "hi", "rho", "w_x", "u", "lr_theta", "lr_S", "s0", "obs", "seed_logp",
                      "seed_gdef", "theta", "S", "lam_lim", "lam_def", "adam_m", "adam_v", "end_states", "traj",
                      "ll_win", "gdef", "logp", "wk", "g_obs", "g_con", "S_dot", "phi", "bandwidth", "flags",
-                     "iter_dev"):
+                     "iter_dev", "n_masked"):
             setattr(j, name, _ptr(getattr(self, name)))
         return j
 

@@ -99,6 +99,7 @@ class Record:
     done: float = 0.0
     theta: np.ndarray | None = None
     logp: np.ndarray | None = None
+    n_masked: int = 0  # particles out of the ensemble at the last iteration
 
     @property
     def latency(self) -> float:
@@ -186,6 +187,7 @@ class Engine:
                     rec = records[a.spec.job_id]
                     rec.done = now()
                     rec.theta, rec.logp = a.host[0].numpy().copy(), a.host[1].numpy().copy()
+                    rec.n_masked = int(a.host[2].numpy()[0])
                     finishing.remove(a)
                     sched.release(a.spec)
             t = now()
@@ -229,7 +231,7 @@ class Engine:
             done = [a for a in active if a.iters >= a.spec.iterations]
             if done:
                 for a in done:
-                    a.host = (_to_host(a.job.theta), _to_host(a.job.logp))
+                    a.host = (_to_host(a.job.theta), _to_host(a.job.logp), _to_host(a.job.n_masked))
                     a.event = torch.cuda.Event()
                     a.event.record()
                     a.job = None
@@ -266,6 +268,7 @@ class Engine:
                 ticks += 1
             rec.theta = job.theta.cpu().numpy()
             rec.logp = job.logp.cpu().numpy()
+            rec.n_masked = int(job.n_masked.cpu().numpy()[0])
             rec.done = now()
             del b, job
         torch.cuda.synchronize()
@@ -323,6 +326,8 @@ def _summary(records, wall, ticks, rejected):
         "latency_mean_s": float(lat.mean()) if len(lat) else None,
         "ticks": ticks,
         "jobs_with_nonfinite_particles": nonfinite,
+        "jobs_with_masked_particles": sum(1 for r in recs if r.n_masked > 0),
+        "masked_particles": sum(r.n_masked for r in recs),
         "nonfinite_jobs": [dict(job=r.spec.job_id, family=r.spec.family, N=r.spec.N, K=r.spec.K, T=r.spec.T)
                            for r in recs if not np.isfinite(r.theta).all()],
         "records": records,

@@ -607,6 +607,112 @@ def test_phi_invariances(orc):
     np.testing.assert_allclose(orc.phi(th, G, rho, 1e12), np.tile(G.mean(axis=0), (N, 1)), rtol=1e-9, atol=1e-10)
 
 
+
+# --------------------------------------------------------------------------
+# Particles that leave the ensemble (failed simulations, Sec. III-D)
+# --------------------------------------------------------------------------
+
+def test_masked_median_brute_force(orc):
+    """The median over the live particles is the brute-force median of the
+    pairs among them, h uses the log of their number, and a non-finite
+    row of a masked particle does not reach it."""
+    rng = np.random.default_rng(21)
+    rho = np.array([0.5, 2.0, 1.0])
+    for N, dead in ((9, [0, 4]), (17, [16]), (6, [1, 2, 3, 4]), (5, [0, 1, 2, 3]), (4, [0, 1, 2, 3])):
+        th = rng.normal(size=(N, 3))
+        th[dead] = np.nan
+        live = np.ones(N, dtype=bool)
+        live[dead] = False
+        h, med = orc.bandwidth(th, rho, live=live)
+        idx = np.flatnonzero(live)
+        if len(idx) <= 1:
+            assert h == 1.0
+            continue
+        d = [math.sqrt(sum(((th[i, m] - th[j, m]) / rho[m]) ** 2 for m in range(3)))
+             for i, j in itertools.combinations(idx, 2)]
+        ref = statistics.median(d)
+        assert abs(med - ref) <= 1e-14 * ref
+        assert abs(h - ref * ref / math.log(len(idx))) <= 1e-14 * h
+
+
+def test_masked_phi_is_the_live_ensembles(orc):
+    """phi over the live particles equals phi of the ensemble made of them
+    alone (pinned above by hand-worked values and invariances), rows of
+    masked particles are zero, and NaN or infinite rows of masked
+    particles do not leak into the others."""
+    rng = np.random.default_rng(22)
+    N, M = 15, 3
+    th = rng.normal(size=(N, M))
+    G = rng.normal(size=(N, M))
+    rho = np.array([1.0, 0.3, 2.0])
+    live = np.ones(N, dtype=bool)
+    live[[0, 7, 14]] = False
+    th[7] = np.nan
+    G[0] = np.inf
+    G[14] = np.nan
+    h, _ = orc.bandwidth(th[live], rho)
+    p = orc.phi(th, G, rho, h, live=live)
+    np.testing.assert_allclose(p[live], orc.phi(th[live], G[live], rho, h), rtol=1e-15, atol=0)
+    assert np.all(p[~live] == 0.0)
+    sel = np.array([14, 3, 0], dtype=np.int32)
+    np.testing.assert_array_equal(orc.phi(th, G, rho, h, sel=sel, live=live), p[sel])
+    assert np.all(orc.phi(th, G, rho, h, live=np.zeros(N, dtype=bool)) == 0.0)
+
+
+def test_frozen_particles_keep_their_state(orc):
+    """An MDMM/Adam update with some particles frozen leaves every variable
+    of those particles bitwise as it was and moves the others exactly as
+    an update of the ensemble without them does."""
+    pb = synth.make_problem("c2", N=6, K=2, T=40, n_s=4)
+    rng = np.random.default_rng(23)
+    N, M, K, ns, ds = 6, pb.M, pb.K, pb.n_s, pb.d_s
+    th = pb.lo + rng.uniform(-0.1, 1.1, size=(N, M)) * (pb.hi - pb.lo)  # some outside the limits
+    S = rng.normal(size=(N, K, ns - 1, ds))
+    frozen = np.array([False, True, False, False, True, False])
+    args = (rng.normal(size=(N, M)), rng.normal(size=(N, M)), rng.normal(size=(N, K, ns - 1, ds)),
+            rng.uniform(size=(N, K, ns - 1)))
+    lam = rng.normal(size=(N, M))
+    for optimizer in (0, 1):
+        a = orc.State(pb, th, S, lam_lim=lam, lam_def=rng.normal(size=(N, K, ns - 1)),
+                      adam_m=rng.normal(size=(N, M + K * (ns - 1) * ds)),
+                      adam_v=rng.uniform(size=(N, M + K * (ns - 1) * ds)))
+        before = [x.copy() for x in (a.theta, a.S, a.lam_lim, a.lam_def, a.adam_m, a.adam_v)]
+        keep = ~frozen
+        b = orc.State(pb, th[keep], S[keep], lam_lim=lam[keep], lam_def=a.lam_def[keep], adam_m=a.adam_m[keep],
+                      adam_v=a.adam_v[keep])
+        orc.mdmm_step(pb, a, *args, optimizer, 2, frozen=frozen)
+        orc.mdmm_step(pb, b, *(x[keep] for x in args), optimizer, 2)
+        after = (a.theta, a.S, a.lam_lim, a.lam_def, a.adam_m, a.adam_v)
+        for x0, x1, y in zip(before, after, (b.theta, b.S, b.lam_lim, b.lam_def, b.adam_m, b.adam_v)):
+            np.testing.assert_array_equal(x1[frozen], x0[frozen])
+            np.testing.assert_array_equal(x1[keep], y)
+
+
+def test_failed_particle_leaves_the_ensemble(orc):
+    """A particle whose shooting state is NaN is flagged (state and
+    gradient), left out of phi at once and frozen; the median leaves it out
+    from the next iteration on.  The other particles' phi equals phi of the
+    ensemble without it, at the bandwidth of the ensemble with it."""
+    pb = synth.make_problem("c2", N=12, K=1, T=40, n_s=4)
+    obs = orc.observations(pb)
+    S = orc.shooting_init(pb, pb.particles)
+    S[5, 0, 1, 2] = np.nan
+    st = orc.State(pb, pb.particles, S)
+    th0 = st.theta.copy()
+    live = np.arange(12) != 5
+    g = orc.csvgd_iteration(pb, obs, st, 1)
+    assert g["flags"][5] == orc.FLAG_STATE | orc.FLAG_GRAD | orc.FLAG_FROZEN
+    assert np.all(g["flags"][live] == 0) and g["n_masked"] == 1
+    assert g["bandwidth"] == orc.bandwidth(th0, pb.rho)[0]
+    np.testing.assert_array_equal(g["phi"][live], orc.phi(th0[live], g["g_obs"][live], pb.rho, g["bandwidth"]))
+    assert np.all(g["phi"][5] == 0.0) and np.all(np.isfinite(st.theta))
+    np.testing.assert_array_equal(st.theta[5], th0[5])
+    th1 = st.theta.copy()
+    g2 = orc.csvgd_iteration(pb, obs, st, 2)
+    assert g2["bandwidth"] == orc.bandwidth(th1[live], pb.rho)[0]
+    np.testing.assert_array_equal(st.theta[5], th0[5])
+    assert np.all(np.isfinite(st.theta)) and g2["n_masked"] == 1
+
 def test_mdmm_limits_hand_worked(orc):
     gd = json.load(open(os.path.join(GOLDEN, "mdmm_limits.json")))
     pb = synth.make_problem("toy", N=1, M=1)

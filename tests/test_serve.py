@@ -11,7 +11,7 @@ from helpers import print_case, requires_gpu
 
 BUFFERS = ("consts", "lo", "hi", "rho", "w_x", "u", "lr_theta", "lr_S", "s0", "obs", "theta", "S", "lam_lim",
            "lam_def", "adam_m", "adam_v", "end_states", "traj", "ll_win", "gdef", "logp", "wk", "g_obs", "g_con",
-           "S_dot", "phi", "bandwidth", "flags", "iter_dev", "seed_logp", "seed_gdef")
+           "S_dot", "phi", "bandwidth", "flags", "iter_dev", "n_masked", "seed_logp", "seed_gdef")
 
 
 @pytest.mark.parametrize("config,over", [("c1", dict(K=2, T=1500, n_s=30)), ("c2", {}), ("c2", dict(n_s=1)),
