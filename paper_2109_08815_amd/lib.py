@@ -224,6 +224,14 @@ class Job:
         return j
 
 
+def shape_signature(j: PdsJob) -> tuple:
+    """What the library's launch shapes depend on: a job's sizes and modes,
+    and which optional buffers it has (never their addresses or the
+    scalars, which the kernels read from the device job table)."""
+    return (j.model, j.n_dof, j.M, j.d_x, j.N, j.K, j.T, j.n_s, j.h, j.combine, j.lik, j.limits, bool(j.traj),
+            bool(j.seed_logp), bool(j.seed_gdef), bool(j.iter_dev), bool(j.flags), bool(j.n_masked))
+
+
 class Batch:
     """A batch of jobs: host struct array, device copy and workspace."""
 
@@ -251,6 +259,25 @@ class Batch:
     @property
     def n(self):
         return len(self.jobs)
+
+    def signature(self) -> tuple:
+        return tuple(shape_signature(j) for j in self.h)
+
+    def rebind(self, jobs, stream=None):
+        """Point the batch at other jobs of the same shapes, in the same
+        order, keeping its device job table and workspace: every launch
+        recorded for the batch (a captured graph) then runs on the new
+        jobs.  The table is rewritten in place, ordered on `stream` (default
+        the current one) after the work already queued there."""
+        h = (PdsJob * len(jobs))(*[j.struct() for j in jobs])
+        if tuple(shape_signature(j) for j in h) != self.signature():
+            raise PdsError("rebind needs jobs of the batch's shapes")
+        staging = torch.empty(self.d.numel(), dtype=torch.uint8, pin_memory=True)
+        staging.numpy()[:] = np.frombuffer(bytes(h), dtype=np.uint8)
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        with torch.cuda.stream(s):
+            self.d.copy_(staging, non_blocking=True)
+        self.jobs, self.h = list(jobs), h
 
     def side_stream(self):
         """A second stream of the batch's device (default priority)."""

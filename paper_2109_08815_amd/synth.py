@@ -349,12 +349,15 @@ SERVE_T = (200, 400, 600, 800, 1000, 1200, 1500)
 
 
 def serving_trace(n_jobs: int = 512, seed: int = 5000, iterations: int = 100, rate: float | None = None,
-                  families=("c1", "c2", "c3"), max_log2_n: int = 5, limits: int | None = None) -> list[JobSpec]:
+                  families=("c1", "c2", "c3"), max_log2_n: int = 5, limits: int | None = None,
+                  shape: tuple | None = None) -> list[JobSpec]:
     """The mixed serving workload: family uniform over the planar problems,
     N = 64 * 2^u with u uniform on 0..max_log2_n, T uniform over SERVE_T
     (windows of SERVE_H steps), K uniform on 1..8.  With `rate` (jobs/s)
     the arrivals are a Poisson process, else every job arrives at 0.
-    `limits` sets every job's limits mode (None: each family's default)."""
+    `limits` sets every job's limits mode (None: each family's default).
+    `shape` = (family, N, K, T) gives every job that shape instead
+    (homogeneous traffic; seeds and arrivals as in the mixed trace)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     t = 0.0
@@ -363,6 +366,8 @@ def serving_trace(n_jobs: int = 512, seed: int = 5000, iterations: int = 100, ra
         N = 64 * 2 ** int(rng.integers(max_log2_n + 1))
         T = int(SERVE_T[int(rng.integers(len(SERVE_T)))])
         K = int(rng.integers(1, 9))
+        if shape is not None:
+            fam, N, K, T = shape
         if rate is not None:
             t += float(rng.exponential(1.0 / rate))
         out.append(JobSpec(j, fam, N, K, T, seed=seed * 1000 + j, iterations=iterations,

@@ -103,3 +103,44 @@ def test_batched_serving_equals_jobs_run_alone(graph):
     assert n == len(trace) and bad == 0
     for r in bat["records"].values():
         assert np.isfinite(r.theta).all() and r.done >= r.spec.arrival
+
+
+def test_shape_signature_and_rebind_guard():
+    """Jobs of one shape share a signature whatever their buffers; a batch
+    refuses to rebind to jobs of other shapes (host logic, CPU buffers)."""
+    pb = synth.make_problem("c2", N=64, K=1, T=40, n_s=2)
+    obs = np.zeros((pb.K, pb.T, pb.d_x))
+    a, b = (L.Job(pb, obs, device="cpu", device_iter=True) for _ in range(2))
+    assert L.shape_signature(a.struct()) == L.shape_signature(b.struct())
+    pb2 = synth.make_problem("c2", N=65, K=1, T=40, n_s=2)
+    c = L.Job(pb2, obs, device="cpu", device_iter=True)
+    assert L.shape_signature(c.struct()) != L.shape_signature(a.struct())
+    d = L.Job(pb, obs, device="cpu", device_iter=False)
+    assert L.shape_signature(d.struct()) != L.shape_signature(a.struct())
+    batch = L.Batch([a])
+    with pytest.raises(L.PdsError):
+        batch.rebind([c])
+    with pytest.raises(L.PdsError):
+        batch.rebind([a, b])
+
+
+@pytest.mark.gpu
+@requires_gpu
+@pytest.mark.skip(reason=serve.GRAPH_CACHE_OFF)
+def test_cached_graphs_rebound_to_new_jobs_equal_jobs_run_alone():
+    """Jobs of one shape arriving two at a time through two slots: batches
+    return to shapes seen before, so cached graphs are rebound to new jobs
+    and replayed; every job's results stay bitwise those it gets alone."""
+    print_case("serve-graph-cache")
+    trace = [synth.JobSpec(i, "c2", N=64, K=1, T=200, seed=100 + i, iterations=6, arrival=0.0) for i in range(6)]
+    eng = serve.Engine(budget_bytes=8 << 30, graph_iters=1, max_slots=2, capture_after=1, graph_cache=True)
+    bat = eng.run_batched(trace)
+    seq = eng.run_sequential(trace)
+    assert bat["graph_reuses"] >= 1 and bat["graph_captures"] >= 1
+    n, bad = serve.same_results(bat, seq)
+    assert n == len(trace) and bad == 0
+
+
+def test_graph_cache_is_switched_off():
+    with pytest.raises(RuntimeError, match="switched off"):
+        serve.Engine(graph_iters=1, graph_cache=True)
