@@ -205,11 +205,10 @@ def run_metrics(args):
 
     pb = synth.make_problem(args.config)
     dev = torch.device("cuda")
-    idx = torch.as_tensor(pb.obs_index, device=dev)
-    tr = driver.gpu_rollout(pb, pb.particles, dev)  # [N, K, T, d_s]
-    P = tr[:, 0][:, :, idx].reshape(pb.N, -1).float().contiguous()
+    tr = driver.gpu_observed_rollout(pb, pb.particles, dev)  # [N, K, T, d_x]
+    P = tr[:, 0].reshape(pb.N, -1).float().contiguous()
     del tr
-    tt = driver.gpu_rollout(pb, pb.theta_true[:1], dev)[0, 0][:, idx].reshape(1, -1).double()
+    tt = driver.gpu_observed_rollout(pb, pb.theta_true[:1], dev)[0, 0].reshape(1, -1).double()
     rng = np.random.Generator(np.random.PCG64(pb.seed + 77))
     noise = rng.normal(0.0, pb.sigma_obs, (METRIC_HELD_OUT, tt.shape[1]))
     Q = (tt + torch.as_tensor(noise, device=dev)).float().contiguous()

@@ -236,12 +236,29 @@ typedef struct pds_job {
                          zeroed, and never run two steps of one job at once */
   int32_t* n_masked;  /* [1] particles left out of the last phi (flag bit 0,
                          1 or 3), or NULL */
+  /* ---- optional outputs and seeds ---- */
+  float* traj_obs;    /* [N, K, T, d_x] the observed quantities f_obs of every
+                         visited state, row t-1 for state t as in obs (PLANAR
+                         and PLANAR_RIGID: the first d_x components of (q, qd);
+                         ARM: the hinge angle; ARM_UJOINT*: the box frame), or
+                         NULL (sim_batch_forward only) */
+  double* g_theta;    /* [N, M] g_obs - g_con, the theta counterpart of S_dot
+                         (sim_batch_adjoint), or NULL */
+  const double* cot_gdef; /* [N, K, n_s-1] cotangent of g_def for a
+                         vector-Jacobian product, or NULL.  When set (seed_gdef
+                         must then be NULL) the constraint channel is seeded with
+                         -cot_gdef, so that g_theta and S_dot are d/dtheta and
+                         d/dS of seed_logp log p + sum cot_gdef g_def */
 } pds_job;
 
 /* Rolls out every window (a batched f_sim of Sec. II with the semi-implicit
  * Euler step of App. B-A eq. dynamics; forward dynamics by the Articulated
  * Body Algorithm).  Writes end_states and, where job.traj != NULL, every
- * visited state.  Needs a workspace only for arm jobs. */
+ * visited state; where job.traj_obs != NULL, what the observation model of
+ * eq. combinedlikelihood sees of every visited state (f_obs: for the
+ * universal-joint arm the box frame's forward kinematics), so that observed
+ * trajectories can be synthesised from a rollout.  Needs a workspace only
+ * for arm jobs. */
 int sim_batch_forward(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws,
                       size_t ws_bytes, void* stream);
 
@@ -257,7 +274,9 @@ int loglik_multishoot(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
  * defect terms (App. B-A: chain rule through f_step), recomputing each
  * window from its start state; assembled for the MDMM flow of Sec. III-E /
  * Algorithm 1.  Writes everything loglik_multishoot writes plus g_obs,
- * g_con and S_dot. */
+ * g_con, S_dot and, where job.g_theta != NULL, g_theta.  With cot_gdef
+ * (and seed_logp) the call is the vector-Jacobian product of (log p, g_def)
+ * with respect to (theta, S): g_theta and S_dot. */
 int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws,
                       size_t ws_bytes, void* stream);
 
@@ -316,33 +335,16 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
 /* Workspace bytes the call `which` (PDS_CALL_*) needs for this batch;
  * PDS_CALL_ALL gives the maximum over all calls.  0 on invalid input (see
  * pds_last_error). */
+size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which);
+
 /* Device bytes one job occupies in a CSVGD iteration, for admission by
  * HBM footprint: every buffer the pds_job fields point to at the sizes
  * documented above (gdef and S_dot with at least one window, iter_dev with
- * 2 entries, n_masked with 1; traj, seed_logp and seed_gdef only when
- * non-NULL in *h_job)
- * plus its workspace for all calls.  Reads only shapes and the three
- * optional pointers; 0 on invalid shapes (see pds_last_error). */
+ * 2 entries, n_masked with 1; traj, traj_obs, g_theta, seed_logp, seed_gdef
+ * and cot_gdef only when non-NULL in *h_job) plus its workspace for all
+ * calls.  Reads only shapes and those optional pointers; 0 on invalid
+ * shapes (see pds_last_error). */
 size_t pds_job_footprint(const pds_job* h_job);
-
-/* Testing aid: moves the sampled median bracket of later svgd_phi calls by
- * `ranks` sample positions (default 0), so tests can make it miss the
- * middle ranks and exercise the exact recovery pass.  The bandwidth stays
- * exact for every value; only the time changes.  Process-wide, not
- * synchronised with calls in flight.  PDS_EINVAL if |ranks| > 1e6. */
-int pds_test_median_shift(int32_t ranks);
-
-/* Test hook (host logic only, no device access): the launch shape
- * sim_batch_adjoint gives a planar job (PDS_MODEL_PLANAR or
- * PDS_MODEL_PLANAR_RIGID), read from the shape fields of *h_job (model,
- * n_dof, N, K, n_s, h).  Returns bit 0 = two lanes per window unit (the job
- * has fewer waves than the chip has SIMDs), bit 1 = the whole window in LDS
- * (else sqrt(h) checkpoints), bit 2 = the dynamics tape in LDS as well (two
- * point-mass links); writes the block's dynamic LDS bytes to *lds_bytes.
- * PDS_EINVAL for a null argument, another model or a non-positive size. */
-int pds_test_adjoint_shape(const pds_job* h_job, size_t* lds_bytes);
-
-size_t pds_workspace_size(const pds_job* h_jobs, int32_t n_jobs, int32_t which);
 
 /* ---- Posterior-consistency metrics (Sec. III-F, App. A-D) ----
  * Compares two sets of trajectories, each row one trajectory's

@@ -1,9 +1,11 @@
 """torch.autograd wrapper of the multiple-shooting log-likelihood.
 
 Forward: loglik_multishoot -> (log p [N], g_def [N, K, n_s-1]) in float64.
-Backward: sim_batch_adjoint seeded with the incoming gradients, giving
-d/d theta and d/d S of  sum_i grad_logp_i log p_i + sum grad_gdef * g_def.
-Both directions run entirely in the library's kernels.
+Backward: sim_batch_adjoint as a vector-Jacobian product (seed_logp and
+cot_gdef the incoming gradients), whose g_theta and S_dot are d/d theta and
+d/d S of  sum_i grad_logp_i log p_i + sum grad_gdef * g_def.  Both
+directions run entirely in the library's kernels; this module only copies
+tensors in and out.
 """
 from __future__ import annotations
 
@@ -17,9 +19,9 @@ class MultiShootingLikelihood:
 
     def __init__(self, pb, obs, theta0, S0, lam_def=None, device="cuda"):
         N = theta0.shape[0]
-        self.job = L.Job(pb, obs, theta=theta0, S=S0, device=device,
+        self.job = L.Job(pb, obs, theta=theta0, S=S0, device=device, with_g_theta=True,
                          seed_logp=torch.ones(N, dtype=torch.float64).numpy(),
-                         seed_gdef=torch.zeros((N, pb.K, max(pb.n_s - 1, 1)), dtype=torch.float64).numpy())
+                         cot_gdef=torch.zeros((N, pb.K, max(pb.n_s - 1, 1)), dtype=torch.float64).numpy())
         if lam_def is not None:
             self.job.lam_def.copy_(torch.as_tensor(lam_def, dtype=torch.float32))
         self.batch = L.Batch([self.job])
@@ -48,10 +50,11 @@ class _Fn(torch.autograd.Function):
         j.seed_logp.copy_(grad_logp if grad_logp is not None else torch.zeros(N, dtype=torch.float64,
                                                                                 device=j.device))
         if mod.n_s > 1:
-            g = grad_gdef if grad_gdef is not None else torch.zeros_like(j.gdef[:, :, : mod.n_s - 1])
-            # the adjoint subtracts seed_gdef * dg/dS from S_dot and adds it to g_con
-            j.seed_gdef[:, :, : mod.n_s - 1].copy_(-g)
+            if grad_gdef is None:
+                j.cot_gdef.zero_()
+            else:
+                j.cot_gdef[:, :, : mod.n_s - 1].copy_(grad_gdef)
         L.sim_batch_adjoint(mod.batch)
-        d_theta = (j.g_obs - j.g_con).to(torch.float32)
+        d_theta = j.g_theta.to(torch.float32)
         d_S = j.S_dot[:, :, : mod.n_s - 1].clone() if mod.n_s > 1 else None
         return d_theta, d_S, None

@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   const int t0 = w.j * J.h;
   const float* obs = J.obs + ((size_t)w.k * J.T + t0) * DX;
   float* traj = J.traj ? J.traj + (((size_t)w.i * J.K + w.k) * J.T + t0) * DS : nullptr;
+  float* tobs = J.traj_obs ? J.traj_obs + (((size_t)w.i * J.K + w.k) * J.T + t0) * DX : nullptr;
   float wx[DX];
   for (int d = 0; d < DX; ++d) wx[d] = J.w_x[d];
   double ll = 0.0;
@@ -114,6 +115,15 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
     if (with_ll) ll -= 0.5 * (double)arm_obs_term<BOX, false>(K, q, obs + (size_t)s * DX, wx, nullptr);
     if (traj)
       for (int d = 0; d < NB; ++d) { traj[s * DS + d] = q[d]; traj[s * DS + NB + d] = qd[d]; }
+    if (tobs) {
+      if constexpr (BOX == kHinge) {
+        tobs[s] = q[7];
+      } else {
+        float x[DX];
+        AM::box_frame(K, q, x);
+        for (int d = 0; d < DX; ++d) tobs[(size_t)s * DX + d] = x[d];
+      }
+    }
   }
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
   float* es = J.end_states + iu * DS;
@@ -243,8 +253,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
     J.gdef[id] = g;
     const bool in_lik = J.lik == PDS_LIK_DEFECT;
     if (in_lik) ll += -0.5 * g + defect_log_norm(J);
-    const double seed =
-        J.seed_gdef ? J.seed_gdef[id] : (in_lik ? 0.0 : (double)J.lam_def[id] + (double)J.c * g);
+    const double seed = con_seed(J, id, g, in_lik);
     // d g / d s_end = -2 e u / sigma^2; in the likelihood, d(-g/2) / d s_end = e u / sigma^2
     const float sc = (float)(-2.0 * seed * inv_s2);
     const float so = in_lik ? (float)inv_s2 : 0.f;

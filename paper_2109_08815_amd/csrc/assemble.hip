@@ -7,6 +7,7 @@
 //               w_k = softmax_k l_k; PROD: log p = sum_k l_k, w_k = 1.
 //   g_obs       seed_logp * sum_k w_k sum_j d l_kj / d theta.
 //   g_con       sum_{k,j} seed_gdef_kj d g_def_kj / d theta.
+//   g_theta     g_obs - g_con (optional), the theta counterpart of S_dot.
 //   S_dot       for shooting state S_kj (j >= 1): seed_logp w_k d l_kj / d S_kj
 //               - seed_gdef_kj d g_def_kj / d S_kj - seed_gdef_k(j-1) d g_def_k(j-1) / d S_kj,
 //               the last term the direct dependence of the previous window's
@@ -94,7 +95,7 @@ __device__ inline SdotPart sdot_part(const pds_job& J, int i, int r, const float
   const size_t id = ((size_t)i * J.K + k) * (J.n_s - 1) + (j - 1);
   const double g = J.gdef[id];
   const bool in_lik = J.lik == PDS_LIK_DEFECT;
-  const double sg = J.seed_gdef ? J.seed_gdef[id] : (in_lik ? 0.0 : (double)J.lam_def[id] + (double)J.c * g);
+  const double sg = con_seed(J, id, g, in_lik);
   const float s_next = J.S[id * ds + d];
   const float s_end = J.end_states[(iu - 1) * ds + d];
   const double ud = J.u[d];
@@ -267,6 +268,7 @@ __global__ void __launch_bounds__(kAsmThreads) assemble_grad_kernel(JobMap map, 
       const double gob = seed * so;
       J.g_obs[(size_t)i * M + m0 + t] = gob;
       J.g_con[(size_t)i * M + m0 + t] = scon;
+      if (J.g_theta) J.g_theta[(size_t)i * M + m0 + t] = gob - scon;
       if (!(isfinite(gob) && isfinite(scon)) && J.flags) atomicOr(&J.flags[i], PDS_FLAG_GRAD);
     }
   }

@@ -59,6 +59,16 @@ __device__ inline double defect_log_norm(const pds_job& J) {
   return c;
 }
 
+// Seed of the constraint channel for defect `id` with value g: the caller's
+// seed_gdef, or minus its cotangent cot_gdef (a vector-Jacobian product), or
+// the MDMM multiplier term lam_def + c g (Sec. III-E); 0 when the defects
+// are densities inside p_ms and nothing was given.
+__device__ inline double con_seed(const pds_job& J, size_t id, double g, bool in_lik) {
+  if (J.seed_gdef) return J.seed_gdef[id];
+  if (J.cot_gdef) return -J.cot_gdef[id];
+  return in_lik ? 0.0 : (double)J.lam_def[id] + (double)J.c * g;
+}
+
 constexpr size_t kArmConstBytes = 2048;  // derived arm model constants per job
 
 // Bandwidth median (see svgd.hip).  Up to kSmallPairs pairs one block

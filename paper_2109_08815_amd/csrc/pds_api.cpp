@@ -129,6 +129,7 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     REQ(consts, 4); REQ(theta, 4); REQ(s0, 4); REQ(end_states, 4);
     if (J.n_s > 1) REQ(S, 4);
     if (J.traj && !aligned(J.traj, 4)) return fail(PDS_EINVAL, "job %d: traj is misaligned", idx);
+    if (J.traj_obs && !aligned(J.traj_obs, 4)) return fail(PDS_EINVAL, "job %d: traj_obs is misaligned", idx);
   }
   if (need & (NEED_LL | NEED_ADJ)) {
     REQ(obs, 4); REQ(w_x, 4); REQ(u, 4); REQ(ll_win, 8); REQ(logp, 8); REQ(wk, 8);
@@ -136,7 +137,12 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
   }
   if (need & NEED_ADJ) {
     REQ(g_obs, 8); REQ(g_con, 8);
-    if (J.n_s > 1) { REQ(S_dot, 4); if (!J.seed_gdef) REQ(lam_def, 4); }
+    if (J.seed_gdef && J.cot_gdef) return fail(PDS_EINVAL, "job %d: seed_gdef and cot_gdef are exclusive", idx);
+    if (J.seed_gdef && !aligned(J.seed_gdef, 8)) return fail(PDS_EINVAL, "job %d: seed_gdef is misaligned", idx);
+    if (J.cot_gdef && !aligned(J.cot_gdef, 8)) return fail(PDS_EINVAL, "job %d: cot_gdef is misaligned", idx);
+    if (J.seed_logp && !aligned(J.seed_logp, 8)) return fail(PDS_EINVAL, "job %d: seed_logp is misaligned", idx);
+    if (J.g_theta && !aligned(J.g_theta, 8)) return fail(PDS_EINVAL, "job %d: g_theta is misaligned", idx);
+    if (J.n_s > 1) { REQ(S_dot, 4); if (!J.seed_gdef && !J.cot_gdef) REQ(lam_def, 4); }
   }
   if (need & NEED_PHI) {
     REQ(rho, 4); REQ(g_obs, 8); REQ(phi, 4); REQ(bandwidth, 8); REQ(theta, 4);
@@ -498,8 +504,11 @@ size_t pds_job_footprint(const pds_job* h_job) {
   size_t f64 = N * K * ns + N * K * nsm1 + N + N * K + 2 * N * M + 1;  // ll_win gdef logp wk g_obs g_con bandwidth
   const size_t i32 = N + 3;                                            // flags iter_dev n_masked
   if (J.traj) f32 += N * K * T * ds;
+  if (J.traj_obs) f32 += N * K * T * dx;
+  if (J.g_theta) f64 += N * M;
   if (J.seed_logp) f64 += N;
   if (J.seed_gdef) f64 += N * K * nsm;
+  if (J.cot_gdef) f64 += N * K * nsm;
   return 4 * f32 + 8 * f64 + 4 * i32 + job_ws(J, PDS_CALL_ALL);
 }
 

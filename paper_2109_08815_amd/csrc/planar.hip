@@ -585,6 +585,7 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
   // d_x = NB observes q; d_x = 2 NB the whole state (q, qd)
   const bool obs_v = J.d_x == DS;
   const int DX = obs_v ? DS : NB;
+  float* tobs = J.traj_obs ? J.traj_obs + (((size_t)w.i * J.K + w.k) * J.T + t0) * DX : nullptr;
   float wx[DS];
 #pragma unroll
   for (int d = 0; d < DS; ++d) wx[d] = (d < NB || obs_v) ? J.w_x[d] : 0.f;
@@ -629,6 +630,14 @@ __global__ void __launch_bounds__(kWave) planar_forward_kernel(JobMap map, const
     if (traj) {
 #pragma unroll
       for (int d = 0; d < NB; ++d) { traj[s * DS + d] = q[d]; traj[s * DS + NB + d] = qd[d]; }
+    }
+    if (tobs) {
+#pragma unroll
+      for (int d = 0; d < NB; ++d) tobs[s * DX + d] = q[d];
+      if (obs_v) {
+#pragma unroll
+        for (int d = 0; d < NB; ++d) tobs[s * DX + NB + d] = qd[d];
+      }
     }
   }
   const size_t iu = ((size_t)w.i * J.K + w.k) * J.n_s + w.j;
@@ -834,8 +843,7 @@ __global__ void __launch_bounds__(kWave) planar_adjoint_kernel(JobMap map, const
     if (ch == 0) J.gdef[id] = g;
     const bool in_lik = J.lik == PDS_LIK_DEFECT;
     if (in_lik) ll += -0.5 * g + defect_log_norm(J);
-    const double seed =
-        J.seed_gdef ? J.seed_gdef[id] : (in_lik ? 0.0 : (double)J.lam_def[id] + (double)J.c * g);
+    const double seed = con_seed(J, id, g, in_lik);
     // d g / d s_end = -2 e u / sigma^2; in the likelihood, d(-g/2) / d s_end = e u / sigma^2
     const float sc = (float)(-2.0 * seed * inv_s2);
     const float so = in_lik ? (float)inv_s2 : 0.f;

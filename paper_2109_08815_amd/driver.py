@@ -35,50 +35,28 @@ def gpu_rollout(pb, theta, device="cuda"):
     return job.traj
 
 
-def box_frame_points(pb, q):
-    """Box-frame observation of the universal-joint arm for joint angles q
-    [n, 9]: the box origin and the points 1 m along its x, y, z axes in
-    world coordinates [n, 12].  Per arm joint the modified-DH placement
-    (Rot_x(alpha), Trans_x(a)) then Rot_z(q) Trans_z(d); then the flange
-    offset along z, Rot_x(q_7) and Rot_y(q_8)."""
-    a = pb.arm
-    q = np.asarray(q, dtype=np.float64)
-    n = q.shape[0]
-    Rw = np.broadcast_to(np.eye(3), (n, 3, 3)).copy()
-    o = np.zeros((n, 3))
+def gpu_observed_rollout(pb, theta, device="cuda"):
+    """What the observation model sees of every particle's rollout from
+    every s0_k: the library's f_obs of each visited state (traj_obs), a
+    device tensor [N, K, T, d_x] in stream order on the current stream."""
+    ss = single_shooting(pb)
+    job = L.Job(ss, np.zeros((pb.K, pb.T, pb.d_x)), theta=theta, device=device, with_traj_obs=True)
+    L.sim_batch_forward(L.Batch([job]))
+    return job.traj_obs
 
-    def rot(axis, t):
-        c, s = np.cos(t), np.sin(t)
-        R = np.zeros((len(t), 3, 3))
-        i, j = [(1, 2), (2, 0), (0, 1)][axis]
-        R[:, axis, axis] = 1.0
-        R[:, i, i] = c
-        R[:, j, j] = c
-        R[:, i, j] = -s
-        R[:, j, i] = s
-        return R
 
-    for i in range(7):
-        al = np.full(n, a["dh_alpha"][i])
-        Rw = Rw @ rot(0, al)
-        o = o + Rw @ np.array([a["dh_a"][i], 0.0, 0.0])
-        Rw = Rw @ rot(2, q[:, i])
-        o = o + Rw @ np.array([0.0, 0.0, a["dh_d"][i]])
-    o = o + Rw @ np.array([0.0, 0.0, a["flange_d"]])
-    Rw = Rw @ rot(0, q[:, 7]) @ rot(1, q[:, 8])
-    return np.concatenate([o, o + Rw[:, :, 0], o + Rw[:, :, 1], o + Rw[:, :, 2]], axis=1)
+def gpu_observed(pb, device="cuda"):
+    """f_obs of trajectory k rolled out at theta_true[k] from s0[k], a device
+    tensor [K, T, d_x] (gpu_observed_rollout's (k, k) entries)."""
+    tro = gpu_observed_rollout(pb, pb.theta_true, device)
+    k = torch.arange(pb.K, device=tro.device)
+    return tro[k, k]
 
 
 def gpu_observations(pb, device="cuda"):
-    """Observed trajectories [K, T, d_x]: trajectory k rolled out at theta_true[k] from s0[k] plus noise."""
-    tr = gpu_rollout(pb, pb.theta_true, device)
-    k = torch.arange(pb.K, device=tr.device)
-    if pb.kind in (synth.KIND_ARM_UJOINT, synth.KIND_ARM_UJOINT_WEIGHTS):
-        q = tr[k, k][:, :, : pb.n_dof].double().cpu().numpy()
-        x = np.stack([box_frame_points(pb, q[j]) for j in range(pb.K)])
-        return x + pb.noise
-    x = tr[k, k][:, :, torch.as_tensor(pb.obs_index, device=tr.device)]
-    return x.double().cpu().numpy() + pb.noise
+    """Observed trajectories [K, T, d_x] (host array): gpu_observed plus the
+    problem's noise draws."""
+    return gpu_observed(pb, device).double().cpu().numpy() + pb.noise
 
 
 def gpu_shooting_init_device(pb, theta, device="cuda"):

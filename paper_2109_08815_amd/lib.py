@@ -52,7 +52,7 @@ class PdsJob(C.Structure):
         ("theta", _f), ("S", _f), ("lam_lim", _f), ("lam_def", _f), ("adam_m", _f), ("adam_v", _f),
         ("end_states", _f), ("traj", _f), ("ll_win", _f), ("gdef", _f), ("logp", _f), ("wk", _f),
         ("g_obs", _f), ("g_con", _f), ("S_dot", _f), ("phi", _f), ("bandwidth", _f), ("flags", _f),
-        ("iter_dev", _f), ("n_masked", _f),
+        ("iter_dev", _f), ("n_masked", _f), ("traj_obs", _f), ("g_theta", _f), ("cot_gdef", _f),
     ]
 
 
@@ -166,7 +166,7 @@ class Job:
     """Device buffers and the pds_job struct of one inference problem."""
 
     def __init__(self, pb, obs, theta=None, S=None, device="cuda", with_traj=False, seed_logp=None,
-                 seed_gdef=None, device_iter=False):
+                 seed_gdef=None, device_iter=False, with_traj_obs=False, with_g_theta=False, cot_gdef=None):
         dev = torch.device(device)
         self.pb = pb
         self.device = dev
@@ -193,12 +193,14 @@ class Job:
         self.adam_v = torch.zeros((N, nA), dtype=f32, device=dev)
         self.end_states = torch.zeros((N, K, ns, ds), dtype=f32, device=dev)
         self.traj = torch.zeros((N, K, T, ds), dtype=f32, device=dev) if with_traj else None
+        self.traj_obs = torch.zeros((N, K, T, pb.d_x), dtype=f32, device=dev) if with_traj_obs else None
         self.ll_win = torch.zeros((N, K, ns), dtype=f64, device=dev)
         self.gdef = torch.zeros((N, K, max(nsm, 1)), dtype=f64, device=dev)
         self.logp = torch.zeros(N, dtype=f64, device=dev)
         self.wk = torch.zeros((N, K), dtype=f64, device=dev)
         self.g_obs = torch.zeros((N, M), dtype=f64, device=dev)
         self.g_con = torch.zeros((N, M), dtype=f64, device=dev)
+        self.g_theta = torch.zeros((N, M), dtype=f64, device=dev) if with_g_theta else None
         self.S_dot = torch.zeros((N, K, max(nsm, 1), ds), dtype=f32, device=dev)
         self.phi = torch.zeros((N, M), dtype=f32, device=dev)
         self.bandwidth = torch.zeros(1, dtype=f64, device=dev)
@@ -207,6 +209,7 @@ class Job:
         self.n_masked = torch.zeros(1, dtype=torch.int32, device=dev)
         self.seed_logp = None if seed_logp is None else _dev(seed_logp, f64, dev)
         self.seed_gdef = None if seed_gdef is None else _dev(seed_gdef, f64, dev)
+        self.cot_gdef = None if cot_gdef is None else _dev(cot_gdef, f64, dev)
 
     def struct(self) -> PdsJob:
         pb = self.pb
@@ -219,7 +222,7 @@ class Job:
         for name in ("consts", "lo", "hi", "rho", "w_x", "u", "lr_theta", "lr_S", "s0", "obs", "seed_logp",
                      "seed_gdef", "theta", "S", "lam_lim", "lam_def", "adam_m", "adam_v", "end_states", "traj",
                      "ll_win", "gdef", "logp", "wk", "g_obs", "g_con", "S_dot", "phi", "bandwidth", "flags",
-                     "iter_dev", "n_masked"):
+                     "iter_dev", "n_masked", "traj_obs", "g_theta", "cot_gdef"):
             setattr(j, name, _ptr(getattr(self, name)))
         return j
 
@@ -229,7 +232,8 @@ def shape_signature(j: PdsJob) -> tuple:
     and which optional buffers it has (never their addresses or the
     scalars, which the kernels read from the device job table)."""
     return (j.model, j.n_dof, j.M, j.d_x, j.N, j.K, j.T, j.n_s, j.h, j.combine, j.lik, j.limits, bool(j.traj),
-            bool(j.seed_logp), bool(j.seed_gdef), bool(j.iter_dev), bool(j.flags), bool(j.n_masked))
+            bool(j.seed_logp), bool(j.seed_gdef), bool(j.iter_dev), bool(j.flags), bool(j.n_masked),
+            bool(j.traj_obs), bool(j.g_theta), bool(j.cot_gdef))
 
 
 class Batch:

@@ -126,10 +126,7 @@ def setup_job(spec, device="cuda"):
     pb = spec.problem()
     dev = torch.device(device)
     # observed trajectories: particle k rolled out from s0_k, plus the problem's noise
-    tr = driver.gpu_rollout(pb, pb.theta_true, dev)
-    k = torch.arange(pb.K, device=dev)
-    obs = tr[k, k][:, :, torch.as_tensor(pb.obs_index, device=dev)].double() + torch.as_tensor(pb.noise, device=dev)
-    del tr
+    obs = driver.gpu_observed(pb, dev).double() + torch.as_tensor(pb.noise, device=dev)
     S = driver.gpu_shooting_init_device(pb, pb.particles, dev)
     job = L.Job(pb, obs, theta=pb.particles, S=S, device=device, device_iter=True)
     return job

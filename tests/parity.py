@@ -46,6 +46,26 @@ def state_rel_err(pb, traj_gpu, traj_ref):
     return err / scale
 
 
+def observed_err_ratio(pb, tobs_gpu, x_ref, traj_ref):
+    """Per window unit error of the observed quantities [N, K, n_s] as a
+    fraction of what the state tolerance permits.  Components of the state
+    (planar models, the hinge angle) move by at most the state error; a
+    box-frame point p moves by sum_j |dq_j| |p - o_j|, with |p - o_j| at most
+    the reach R of the chain (every DH offset, the flange offset and the
+    1 m to the farthest observed point), so its bar is n_dof R times the
+    state bar."""
+    N, K = traj_ref.shape[:2]
+    tr = traj_ref.reshape(N, K, pb.n_s, pb.h, pb.d_s)
+    scale = np.maximum(np.abs(tr).max(axis=(3, 4)), 1e-6)
+    gain = 1.0
+    if pb.kind in (5, 6):
+        a = pb.arm
+        reach = np.abs(a["dh_a"]).sum() + np.abs(a["dh_d"]).sum() + abs(a["flange_d"]) + 1.0
+        gain = pb.n_dof * reach
+    err = np.abs(tobs_gpu - x_ref).reshape(N, K, pb.n_s, pb.h, pb.d_x).max(axis=(3, 4))
+    return err / (STATE_TOL * scale * gain)
+
+
 def end_state_rel_err(es_gpu, es_ref):
     """Per window unit relative error of the window end states."""
     return np.abs(es_gpu - es_ref).max(axis=3) / np.maximum(np.abs(es_ref).max(axis=3), 1e-6)

@@ -12,18 +12,21 @@ import pytest
 from paper_2109_08815_amd import lib as L
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "pds.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
-def declared_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)\s*\(", txt, flags=re.M)
+def declared_functions(headers=None):
+    names = []
+    for h in headers or HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\**\s+\**([a-z_0-9]+)\s*\(", txt, flags=re.M)
     return sorted(set(names))
 
 
 def test_header_declares_the_five_calls():
-    names = declared_functions()
+    names = declared_functions([os.path.join(ROOT, "include", "pds.h")])
     for n in ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step",
               "pds_workspace_size", "pds_last_error", "pds_version"):
         assert n in names
@@ -95,6 +98,17 @@ def test_null_buffers_and_batch_size_rejected():
     assert lib.svgd_phi(arr, fake_dev, 0, None, 0, None) == -1
     assert lib.svgd_step(arr, fake_dev, 1, 7, 1, None) == -1
     assert lib.pds_workspace_size(arr, 0, 5) == 0
+
+
+def test_exclusive_constraint_seeds_rejected():
+    """seed_gdef and cot_gdef both set is rejected before anything is queued."""
+    lib = L.lib()
+    fake = C.c_void_p(4096)
+    ptrs = {n: 4096 for n in ("consts", "theta", "s0", "end_states", "S", "obs", "w_x", "u", "ll_win", "logp", "wk",
+                               "gdef", "g_obs", "g_con", "S_dot", "lam_def")}
+    arr = (L.PdsJob * 1)(_job(seed_gdef=4096, cot_gdef=8192, **ptrs))
+    assert lib.sim_batch_adjoint(arr, fake, 1, None, 0, None) == -1
+    assert b"exclusive" in lib.pds_last_error()
 
 
 def test_workspace_size_grows_with_problem():

@@ -14,13 +14,13 @@ import torch
 from paper_2109_08815_amd import lib as L
 from paper_2109_08815_amd import synth
 from tests.helpers import f32_problem, print_case, r32, requires_gpu
-from tests.parity import (end_state_rel_err, grad_bar, grad_check, ll_tolerance, normwise, state_rel_err,
-                           update_check)
+from tests.parity import (end_state_rel_err, grad_bar, grad_check, ll_tolerance, normwise, observed_err_ratio,
+                           state_rel_err, update_check)
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
 
-def make_case(orc, cfg, seed=None, perturb_S=0.0, lam=False, with_traj=False, **over):
+def make_case(orc, cfg, seed=None, perturb_S=0.0, lam=False, with_traj=False, with_traj_obs=False, **over):
     print_case(cfg, seed, over)
     pb = f32_problem(synth.make_problem(cfg, seed=seed, **over))
     obs = r32(orc.observations(pb))
@@ -30,7 +30,7 @@ def make_case(orc, cfg, seed=None, perturb_S=0.0, lam=False, with_traj=False, **
         S = r32(synth.perturb(rng, S, perturb_S))
     lam_def = r32(rng.uniform(0.0, 2.0, (pb.N, pb.K, pb.n_s - 1))) if lam else np.zeros((pb.N, pb.K, pb.n_s - 1))
     st = orc.State(pb, pb.particles, S, lam_def=lam_def)
-    job = L.Job(pb, obs, theta=pb.particles, S=S, with_traj=with_traj)
+    job = L.Job(pb, obs, theta=pb.particles, S=S, with_traj=with_traj, with_traj_obs=with_traj_obs)
     job.lam_def.copy_(torch.as_tensor(lam_def, dtype=torch.float32))
     b = L.Batch([job])
     return pb, obs, st, job, b
@@ -611,6 +611,27 @@ def test_autograd_function_matches_oracle(orc):
     gt = ref["g_obs"] - ref["g_con"]
     assert np.all(np.linalg.norm(np64(th.grad) - gt, axis=1) <= bar)
     assert normwise(np64(S.grad), ref["S_dot"]).max() <= 1e-3
+    # g_theta is the library's own difference of its two channels
+    np.testing.assert_array_equal(np64(mod.job.g_theta), np64(mod.job.g_obs) - np64(mod.job.g_con))
+
+
+@pytest.mark.parametrize("cfg,over", [("c1", dict(N=20, K=2, T=60, n_s=3)), ("c2", dict(N=33, K=2, T=80, n_s=2)),
+                                      ("rigid2", dict(N=20, K=2, T=60, n_s=3)), ("c3", dict(N=20, K=2, T=60, n_s=3)),
+                                      ("c4", dict(N=20, K=1, T=60, n_s=2)), ("box1", dict(N=12, K=1, T=48, n_s=2)),
+                                      ("box2", dict(N=12, K=2, T=48, n_s=2))])
+def test_observed_quantities_match_oracle(orc, cfg, over):
+    """traj_obs (f_obs of every visited state, which set-up uses to
+    synthesise observed trajectories) against the oracle's observation model
+    on its own rollout, within what the state tolerance permits."""
+    pb, obs, st, job, b = make_case(orc, cfg, perturb_S=0.005, with_traj_obs=True, **over)
+    L.sim_batch_forward(b)
+    ref = orc.forward(pb, obs, st, traj=True)
+    tr = ref["traj"]
+    x_ref = np.stack([np.stack([orc.observe(pb, pb.particles[i], tr[i, k]) for k in range(pb.K)])
+                      for i in range(pb.N)])
+    ratio = observed_err_ratio(pb, np64(job.traj_obs), x_ref, tr)
+    print("traj_obs worst ratio to its bar %.3g" % ratio.max(), flush=True)
+    assert ratio.max() <= 1.0
 
 
 ARM_CASES = [
