@@ -39,12 +39,20 @@ __device__ inline KConst& arm_const_of(char* ws, uint64_t off) {
   return *(KConst*)(ws + off);
 }
 
+// The raw constants are first staged in LDS by the whole block (one
+// coalesced load), so the single thread that derives the table reads them
+// from LDS instead of waiting on one global round trip after another.
 __global__ void arm_setup_kernel(JobMap map, const pds_job* __restrict__ jobs, char* __restrict__ ws) {
+  constexpr int kRawMax = 130;  // raw floats of the largest arm model
+  __shared__ float raw[kRawMax];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  if (threadIdx.x == 0)
-    arm_setup(J.consts, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]),
-              J.model == PDS_MODEL_ARM_UJOINT ? kUJoint : (J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? kUJointWeights : kHinge));
+  const int mount =
+      J.model == PDS_MODEL_ARM_UJOINT ? kUJoint : (J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? kUJointWeights : kHinge);
+  const int n = mount == kUJoint ? 117 : (mount == kUJointWeights ? 130 : 126);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) raw[t] = J.consts[t];
+  __syncthreads();
+  if (threadIdx.x == 0) arm_setup(raw, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]), mount);
 }
 
 struct AUnit {

@@ -70,16 +70,23 @@ struct ArmShape {
 constexpr int kArmMaxBodies = 9;
 
 // Per-job constants derived once per call from the caller's raw model
-// description (see pds.h for the raw layout).
+// description (see pds.h for the raw layout).  Each body's constants sit in
+// one 128-byte record, so the kernels fetch a body's constants with a few
+// wide scalar loads instead of one load per array.
+struct ArmBody {
+  float ca, sa;  // cos, sin of the DH twist alpha (arm joints)
+  float ra, rd;  // DH shifts: a along the parent's x, d along the twisted z
+  float m;       // link mass (hinge: body 7 the box alone; joint: body 8 the box)
+  float c[3];    // centre of mass
+  float Ic[6];   // inertia about the centre of mass: xx, xy, xz, yy, yz, zz
+  float Ar[6];   // angular block of the body's spatial inertia, Ic + m (|c|^2 1 - c c^T)
+  float kp, kd, qc, amp, om, ph;  // PD gains and the sinusoidal target (arm joints)
+  float pad[6];
+};
+static_assert(sizeof(ArmBody) == 128, "one 128-byte record per body");
 struct ArmConst {
+  ArmBody b[kArmMaxBodies];
   float g[3];
-  float ca[kArmMaxBodies], sa[kArmMaxBodies];  // cos, sin of the DH twist alpha (arm joints)
-  float ra[kArmMaxBodies], rd[kArmMaxBodies];  // DH shifts: a along the parent's x, d along the twisted z
-  float m[kArmMaxBodies];      // link mass (hinge: body 7 the box alone; joint: body 8 the box)
-  float c[kArmMaxBodies][3];   // centre of mass
-  float Ic[kArmMaxBodies][6];  // inertia about the centre of mass: xx, xy, xz, yy, yz, zz
-  float Ar[kArmMaxBodies][6];  // angular block of the body's spatial inertia, Ic + m (|c|^2 1 - c c^T)
-  float kp[7], kd[7], qc[7], amp[7], om[7], ph[7];
   float bh;                 // hinge damping (universal joint with weights: first axis)
   float b8;                 // universal joint with weights: damping of the second axis
   float pm_m, pm_z;         // point masses: mass each, height in the box frame
@@ -98,57 +105,57 @@ __host__ __device__ inline void arm_setup(const float* raw, ArmConst* K, int mou
     const float* j = raw + 3 + 16 * i;
     float s, c;
     sincosf(j[1], &s, &c);
-    K->ca[i] = c;
-    K->sa[i] = s;
-    K->ra[i] = j[0];
-    K->rd[i] = j[2];
-    K->m[i] = j[3];
-    K->c[i][0] = j[4]; K->c[i][1] = j[5]; K->c[i][2] = j[6];
-    K->Ic[i][0] = j[7]; K->Ic[i][1] = 0.f; K->Ic[i][2] = 0.f;
-    K->Ic[i][3] = j[8]; K->Ic[i][4] = 0.f; K->Ic[i][5] = j[9];
-    K->kp[i] = j[10]; K->kd[i] = j[11]; K->qc[i] = j[12];
-    K->amp[i] = j[13]; K->om[i] = j[14]; K->ph[i] = j[15];
+    K->b[i].ca = c;
+    K->b[i].sa = s;
+    K->b[i].ra = j[0];
+    K->b[i].rd = j[2];
+    K->b[i].m = j[3];
+    K->b[i].c[0] = j[4]; K->b[i].c[1] = j[5]; K->b[i].c[2] = j[6];
+    K->b[i].Ic[0] = j[7]; K->b[i].Ic[1] = 0.f; K->b[i].Ic[2] = 0.f;
+    K->b[i].Ic[3] = j[8]; K->b[i].Ic[4] = 0.f; K->b[i].Ic[5] = j[9];
+    K->b[i].kp = j[10]; K->b[i].kd = j[11]; K->b[i].qc = j[12];
+    K->b[i].amp = j[13]; K->b[i].om = j[14]; K->b[i].ph = j[15];
   }
   const float* h = raw + 3 + 16 * 7;
   for (int b = 7; b < kArmMaxBodies; ++b) {
-    K->ca[b] = 1.f;
-    K->sa[b] = 0.f;
-    K->ra[b] = K->rd[b] = 0.f;
-    for (int d = 0; d < 3; ++d) K->c[b][d] = 0.f;
-    for (int e = 0; e < 6; ++e) K->Ic[b][e] = 0.f;
-    K->m[b] = 0.f;
+    K->b[b].ca = 1.f;
+    K->b[b].sa = 0.f;
+    K->b[b].ra = K->b[b].rd = 0.f;
+    for (int d = 0; d < 3; ++d) K->b[b].c[d] = 0.f;
+    for (int e = 0; e < 6; ++e) K->b[b].Ic[e] = 0.f;
+    K->b[b].m = 0.f;
   }
-  K->rd[7] = h[0];
+  K->b[7].rd = h[0];
   K->bh = K->b8 = K->pm_m = K->pm_z = 0.f;
   if (mount == kUJoint) {
-    K->m[8] = h[1];  // the box; its centre of mass and inertia come from theta
+    K->b[8].m = h[1];  // the box; its centre of mass and inertia come from theta
   } else if (mount == kUJointWeights) {
-    K->m[8] = h[1];
-    K->c[8][0] = h[2]; K->c[8][1] = h[3]; K->c[8][2] = h[4];
-    K->Ic[8][0] = h[5]; K->Ic[8][1] = h[8]; K->Ic[8][2] = h[9];
-    K->Ic[8][3] = h[6]; K->Ic[8][4] = h[10]; K->Ic[8][5] = h[7];
+    K->b[8].m = h[1];
+    K->b[8].c[0] = h[2]; K->b[8].c[1] = h[3]; K->b[8].c[2] = h[4];
+    K->b[8].Ic[0] = h[5]; K->b[8].Ic[1] = h[8]; K->b[8].Ic[2] = h[9];
+    K->b[8].Ic[3] = h[6]; K->b[8].Ic[4] = h[10]; K->b[8].Ic[5] = h[7];
     K->bh = h[11];
     K->b8 = h[12];
     K->pm_m = h[13];
     K->pm_z = h[14];
   } else {
     K->bh = h[1];
-    K->m[7] = h[2];
-    K->c[7][0] = h[3]; K->c[7][1] = h[4]; K->c[7][2] = h[5];
-    K->Ic[7][0] = h[6]; K->Ic[7][1] = 0.f; K->Ic[7][2] = 0.f;
-    K->Ic[7][3] = h[7]; K->Ic[7][4] = 0.f; K->Ic[7][5] = h[8];
+    K->b[7].m = h[2];
+    K->b[7].c[0] = h[3]; K->b[7].c[1] = h[4]; K->b[7].c[2] = h[5];
+    K->b[7].Ic[0] = h[6]; K->b[7].Ic[1] = 0.f; K->b[7].Ic[2] = 0.f;
+    K->b[7].Ic[3] = h[7]; K->b[7].Ic[4] = 0.f; K->b[7].Ic[5] = h[8];
     K->pm_m = h[9];
     K->pm_z = h[10];
   }
   for (int b = 0; b < kArmMaxBodies; ++b) {
-    const float m = K->m[b], cx = K->c[b][0], cy = K->c[b][1], cz = K->c[b][2];
+    const float m = K->b[b].m, cx = K->b[b].c[0], cy = K->b[b].c[1], cz = K->b[b].c[2];
     const float cc = cx * cx + cy * cy + cz * cz;
-    K->Ar[b][0] = K->Ic[b][0] + m * (cc - cx * cx);
-    K->Ar[b][1] = K->Ic[b][1] - m * cx * cy;
-    K->Ar[b][2] = K->Ic[b][2] - m * cx * cz;
-    K->Ar[b][3] = K->Ic[b][3] + m * (cc - cy * cy);
-    K->Ar[b][4] = K->Ic[b][4] - m * cy * cz;
-    K->Ar[b][5] = K->Ic[b][5] + m * (cc - cz * cz);
+    K->b[b].Ar[0] = K->b[b].Ic[0] + m * (cc - cx * cx);
+    K->b[b].Ar[1] = K->b[b].Ic[1] - m * cx * cy;
+    K->b[b].Ar[2] = K->b[b].Ic[2] - m * cx * cz;
+    K->b[b].Ar[3] = K->b[b].Ic[3] + m * (cc - cy * cy);
+    K->b[b].Ar[4] = K->b[b].Ic[4] - m * cy * cz;
+    K->b[b].Ar[5] = K->b[b].Ic[5] + m * (cc - cz * cz);
   }
 }
 
@@ -277,13 +284,13 @@ struct ArmMath {
   __host__ __device__ static inline SV xm(const KC& K, R cq, R sq, SV m) {
     V3 w = m.a, v = m.l;
     if constexpr (I < 7) {
-      const R a = K.ra[I], ca = K.ca[I], sa = K.sa[I];
+      const R a = K.b[I].ra, ca = K.b[I].ca, sa = K.b[I].sa;
       v = v3(v.x, v.y + a * w.z, v.z - a * w.y);
       w = rotT<0>(ca, sa, w);
       v = rotT<0>(ca, sa, v);
     }
     if constexpr (I < 8) {
-      const R d = K.rd[I];
+      const R d = K.b[I].rd;
       v = v3(v.x + d * w.y, v.y - d * w.x, v.z);
     }
     return sv(rotT<axis<I>()>(cq, sq, w), rotT<axis<I>()>(cq, sq, v));
@@ -294,11 +301,11 @@ struct ArmMath {
   __host__ __device__ static inline SV xtf(const KC& K, R cq, R sq, SV f) {
     V3 n = rot<axis<I>()>(cq, sq, f.a), g = rot<axis<I>()>(cq, sq, f.l);
     if constexpr (I < 8) {
-      const R d = K.rd[I];
+      const R d = K.b[I].rd;
       n = v3(n.x - d * g.y, n.y + d * g.x, n.z);
     }
     if constexpr (I < 7) {
-      const R a = K.ra[I], ca = K.ca[I], sa = K.sa[I];
+      const R a = K.b[I].ra, ca = K.b[I].ca, sa = K.b[I].sa;
       n = rot<0>(ca, sa, n);
       g = rot<0>(ca, sa, g);
       n = v3(n.x, n.y - a * g.z, n.z + a * g.y);
@@ -310,11 +317,11 @@ struct ArmMath {
   __host__ __device__ static inline SV minv(const KC& K, R cq, R sq, SV m) {
     V3 w = rot<axis<I>()>(cq, sq, m.a), v = rot<axis<I>()>(cq, sq, m.l);
     if constexpr (I < 8) {
-      const R d = K.rd[I];
+      const R d = K.b[I].rd;
       v = v3(v.x - d * w.y, v.y + d * w.x, v.z);
     }
     if constexpr (I < 7) {
-      const R a = K.ra[I], ca = K.ca[I], sa = K.sa[I];
+      const R a = K.b[I].ra, ca = K.b[I].ca, sa = K.b[I].sa;
       w = rot<0>(ca, sa, w);
       v = rot<0>(ca, sa, v);
       v = v3(v.x, v.y - a * w.z, v.z + a * w.y);
@@ -429,13 +436,13 @@ struct ArmMath {
     rot_sym<axis<I>()>(cq, sq, Ia.A);
     rot_gen<axis<I>()>(cq, sq, Ia.B);
     rot_sym<axis<I>()>(cq, sq, Ia.C);
-    if constexpr (I < 8) shift_z(Ia, R(K.rd[I]));
+    if constexpr (I < 8) shift_z(Ia, R(K.b[I].rd));
     if constexpr (I < 7) {
-      const R ca = K.ca[I], sa = K.sa[I];
+      const R ca = K.b[I].ca, sa = K.b[I].sa;
       rot_sym<0>(ca, sa, Ia.A);
       rot_gen<0>(ca, sa, Ia.B);
       rot_sym<0>(ca, sa, Ia.C);
-      shift_x(Ia, R(K.ra[I]));
+      shift_x(Ia, R(K.b[I].ra));
     }
   }
 
@@ -481,7 +488,7 @@ struct ArmMath {
   template <int I>
   __host__ __device__ static inline Sym6 body_inertia(const KC& K, const R* th) {
     Sym6 S;
-    R m = R(K.m[I]);
+    R m = R(K.b[I].m);
     V3 c;
     if constexpr (BOX == kUJoint && I == 8) {
       R Ic[6];
@@ -497,18 +504,18 @@ struct ArmMath {
       // FP64 host checks: the same block formed in FP64 (the precomputed
       // one is rounded to float), so the forward dynamics and the inertia
       // the reverse step applies agree to FP64 rounding
-      c = v3(K.c[I][0], K.c[I][1], K.c[I][2]);
+      c = v3(K.b[I].c[0], K.b[I].c[1], K.b[I].c[2]);
       const R mx = m * c.x, my = m * c.y, mz = m * c.z;
-      S.A.e[0] = R(K.Ic[I][0]) + my * c.y + mz * c.z;
-      S.A.e[1] = R(K.Ic[I][1]) - mx * c.y;
-      S.A.e[2] = R(K.Ic[I][2]) - mx * c.z;
-      S.A.e[3] = R(K.Ic[I][3]) + mx * c.x + mz * c.z;
-      S.A.e[4] = R(K.Ic[I][4]) - my * c.z;
-      S.A.e[5] = R(K.Ic[I][5]) + mx * c.x + my * c.y;
+      S.A.e[0] = R(K.b[I].Ic[0]) + my * c.y + mz * c.z;
+      S.A.e[1] = R(K.b[I].Ic[1]) - mx * c.y;
+      S.A.e[2] = R(K.b[I].Ic[2]) - mx * c.z;
+      S.A.e[3] = R(K.b[I].Ic[3]) + mx * c.x + mz * c.z;
+      S.A.e[4] = R(K.b[I].Ic[4]) - my * c.z;
+      S.A.e[5] = R(K.b[I].Ic[5]) + mx * c.x + my * c.y;
     } else {
-      c = v3(K.c[I][0], K.c[I][1], K.c[I][2]);
+      c = v3(K.b[I].c[0], K.b[I].c[1], K.b[I].c[2]);
   #pragma unroll
-      for (int e = 0; e < 6; ++e) S.A.e[e] = R(K.Ar[I][e]);
+      for (int e = 0; e < 6; ++e) S.A.e[e] = R(K.b[I].Ar[e]);
     }
     const R mx = m * c.x, my = m * c.y, mz = m * c.z;
     S.B.e[0] = R(0.f); S.B.e[1] = -mz; S.B.e[2] = my;
@@ -530,9 +537,9 @@ struct ArmMath {
       V3 c;
       R Ic[6];
       box_from_theta(th, &c, Ic);
-      r = rbi_mul(R(K.m[I]), c, Ic, x);
+      r = rbi_mul(R(K.b[I].m), c, Ic, x);
     } else {
-      r = rbi_mul(R(K.m[I]), v3(K.c[I][0], K.c[I][1], K.c[I][2]), K.Ic[I], x);
+      r = rbi_mul(R(K.b[I].m), v3(K.b[I].c[0], K.b[I].c[1], K.b[I].c[2]), K.b[I].Ic, x);
     }
     if constexpr (PM && I == BOXB) {
       const R pm = R(K.pm_m), z = R(K.pm_z);
@@ -551,10 +558,10 @@ struct ArmMath {
       else return -(R(K.bh) * qd);
     } else {
       R sn, cs;
-      sincos_r(R(K.om[I]) * time + R(K.ph[I]), &sn, &cs);
-      const R qdes = R(K.qc[I]) + R(K.amp[I]) * sn;
-      const R qddes = R(K.amp[I]) * R(K.om[I]) * cs;
-      return R(K.kp[I]) * (qdes - q) + R(K.kd[I]) * (qddes - qd);
+      sincos_r(R(K.b[I].om) * time + R(K.b[I].ph), &sn, &cs);
+      const R qdes = R(K.b[I].qc) + R(K.b[I].amp) * sn;
+      const R qddes = R(K.b[I].amp) * R(K.b[I].om) * cs;
+      return R(K.b[I].kp) * (qdes - q) + R(K.b[I].kd) * (qddes - qd);
     }
   }
 
@@ -732,8 +739,8 @@ struct ArmMath {
     for (int c = 0; c < 2; ++c) {
   #pragma unroll
       for (int i = 0; i < 7; ++i) {
-        qb[c][i] = qb[c][i] - R(K.kp[i]) * lam[c][i];
-        qdb[c][i] = qdb[c][i] - R(K.kd[i]) * lam[c][i];
+        qb[c][i] = qb[c][i] - R(K.b[i].kp) * lam[c][i];
+        qdb[c][i] = qdb[c][i] - R(K.b[i].kd) * lam[c][i];
       }
       if constexpr (BOX == kHinge) {
         qdb[c][7] = qdb[c][7] - R(K.bh) * lam[c][7];
@@ -806,7 +813,7 @@ struct ArmMath {
           V3 cm;
           R Icb[6];
           box_from_theta(th, &cm, Icb);
-          const R mb = R(K.m[i]);
+          const R mb = R(K.b[i].m);
   #pragma unroll
           for (int term = 0; term < 2; ++term) {
             const SV x = term == 0 ? a : v;
@@ -901,13 +908,13 @@ struct ArmMath {
       constexpr int k = axis<i>();
       keep_consts_in_memory();
       if constexpr (i < 7) {
-        o = o + R(K.ra[i]) * Rw[0];
-        const R ca = K.ca[i], sa = K.sa[i];
+        o = o + R(K.b[i].ra) * Rw[0];
+        const R ca = K.b[i].ca, sa = K.b[i].sa;
         const V3 y = Rw[1], z = Rw[2];
         Rw[1] = ca * y + sa * z;
         Rw[2] = ca * z - sa * y;
       }
-      if constexpr (i < 8) o = o + R(K.rd[i]) * Rw[2];
+      if constexpr (i < 8) o = o + R(K.b[i].rd) * Rw[2];
       constexpr int P = k == 0 ? 1 : (k == 1 ? 2 : 0), Q = k == 0 ? 2 : (k == 1 ? 0 : 1);
       const V3 p = Rw[P], qv = Rw[Q];
       Rw[P] = cs[i] * p + sn[i] * qv;
