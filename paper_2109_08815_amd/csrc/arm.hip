@@ -39,32 +39,65 @@ __device__ inline KConst& arm_const_of(char* ws, uint64_t off) {
   return *(KConst*)(ws + off);
 }
 
-// The raw constants are first staged in LDS by the whole block (one
-// coalesced load), so the single thread that derives the table reads them
-// from LDS instead of waiting on one global round trip after another.
-__global__ void arm_setup_kernel(JobMap map, const pds_job* __restrict__ jobs, char* __restrict__ ws) {
+// Block 0 of a job derives the constants: the raw constants are first
+// staged in LDS by the whole block (one coalesced load), so the single
+// thread that derives the table reads them from LDS instead of waiting on
+// one global round trip after another.  The job's other blocks fill the
+// table of PD targets, one (time step, joint) entry per thread, with the
+// target function every direct evaluation uses.
+constexpr int kSetupThreads = kArmSetupThreads;
+__global__ void __launch_bounds__(kSetupThreads) arm_setup_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                                  char* __restrict__ ws) {
   constexpr int kRawMax = 130;  // raw floats of the largest arm model
   __shared__ float raw[kRawMax];
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
-  const int mount =
-      J.model == PDS_MODEL_ARM_UJOINT ? kUJoint : (J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? kUJointWeights : kHinge);
-  const int n = mount == kUJoint ? 117 : (mount == kUJointWeights ? 130 : 126);
-  for (int t = threadIdx.x; t < n; t += blockDim.x) raw[t] = J.consts[t];
-  __syncthreads();
-  if (threadIdx.x == 0) arm_setup(raw, reinterpret_cast<ArmConst*>(ws + map.ws_off[e]), mount);
+  const int b = blockIdx.x - map.begin[e];
+  char* base = ws + map.ws_off[e];
+  if (b == 0) {
+    const int mount =
+        J.model == PDS_MODEL_ARM_UJOINT ? kUJoint : (J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? kUJointWeights : kHinge);
+    const int n = mount == kUJoint ? 117 : (mount == kUJointWeights ? 130 : 126);
+    for (int t = threadIdx.x; t < n; t += blockDim.x) raw[t] = J.consts[t];
+    __syncthreads();
+    if (threadIdx.x == 0) arm_setup(raw, reinterpret_cast<ArmConst*>(base), mount);
+    return;
+  }
+  const int x = (b - 1) * kSetupThreads + threadIdx.x;  // entry (time step, joint)
+  if (x >= J.T * 7) return;
+  const int t = x / 7, i = x % 7;
+  const float* jr = J.consts + 3 + 16 * i;  // joint i: ..., qc, amp, omega, phase at 12 .. 15
+  float qdes, qddes;
+  pd_target(jr[12], jr[13], jr[14], jr[15], (float)t * J.dt, &qdes, &qddes);
+  float* tab = reinterpret_cast<float*>(base + kArmConstBytes) + (size_t)t * kArmTargets;
+  tab[i] = qdes;
+  tab[7 + i] = qddes;
 }
 
+// Window unit of a lane.  A job's blocks (one wave each) come in groups of
+// ceil(N / 64) per (trajectory k, window j), so every lane of a wave shares
+// (k, j) and the time of each step: the observation row and the PD targets
+// of a step are wave-uniform loads.  Lanes past the last particle (i >= N)
+// have no unit.
 struct AUnit {
   int i, k, j;
 };
-__device__ inline AUnit aunit_of(const pds_job& J, int u) {
+__device__ inline AUnit aunit_of(const pds_job& J, int block, int lane) {
+  const int wpg = (J.N + kWave - 1) / kWave;  // waves per (k, j)
+  const int g = block / wpg;
   AUnit r;
-  r.i = u % J.N;
-  const int kj = u / J.N;
-  r.k = kj / J.n_s;
-  r.j = kj % J.n_s;
+  r.i = (block - g * wpg) * kWave + lane;
+  r.k = g / J.n_s;
+  r.j = g - r.k * J.n_s;
   return r;
+}
+
+// Row of the PD-target table at time step n, read through the constant
+// address space (its wave-uniform reads are scalar loads).
+using CFloat = const __attribute__((address_space(4))) float*;
+using TRow = TargetRow<CFloat>;
+__device__ inline TRow target_row(char* ws, uint64_t off, int n) {
+  return TRow{(CFloat)(ws + off + kArmConstBytes) + (size_t)n * kArmTargets};
 }
 template <int DS>
 __device__ inline const float* astart_ptr(const pds_job& J, const AUnit& w) {
@@ -101,10 +134,8 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   KConst& K = arm_const_of(ws, map.ws_off[e]);
-  const int U = J.N * J.K * J.n_s;
-  const int u = (blockIdx.x - map.begin[e]) * kWave + threadIdx.x;
-  if (u >= U) return;
-  const AUnit w = aunit_of(J, u);
+  const AUnit w = aunit_of(J, blockIdx.x - map.begin[e], threadIdx.x);
+  if (w.i >= J.N) return;
   float th[M];
   for (int m = 0; m < M; ++m) th[m] = J.theta[(size_t)w.i * M + m];
   const float* st = astart_ptr<DS>(J, w);
@@ -119,7 +150,7 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   for (int d = 0; d < DX; ++d) wx[d] = J.w_x[d];
   double ll = 0.0;
   for (int s = 0; s < J.h; ++s) {
-    AM::step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+    AM::step(K, th, target_row(ws, map.ws_off[e], t0 + s), dt, q, qd);
     if (with_ll) ll -= 0.5 * (double)arm_obs_term<BOX, false>(K, q, obs + (size_t)s * DX, wx, nullptr);
     if (traj)
       for (int d = 0; d < NB; ++d) { traj[s * DS + d] = q[d]; traj[s * DS + NB + d] = qd[d]; }
@@ -174,10 +205,9 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   KConst& K = arm_const_of(ws, map.ws_off[e]);
-  const int U = J.N * J.K * J.n_s;
   const int lane = threadIdx.x;
-  const int u = (blockIdx.x - map.begin[e]) * kWave + lane;
-  if (u >= U) return;
+  const AUnit w = aunit_of(J, blockIdx.x - map.begin[e], lane);
+  if (w.i >= J.N) return;
   const WsLayout L = ws_layout(J);
   char* base = ws + map.ws_off[e];
   double* gth_obs = reinterpret_cast<double*>(base + L.gth_obs);
@@ -198,7 +228,6 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   #pragma unroll
     for (int d = 0; d < NB; ++d) { q[d] = p[d * kWave]; qd[d] = p[(NB + d) * kWave]; }
   };
-  const AUnit w = aunit_of(J, u);
   float th[M];
   for (int m = 0; m < M; ++m) th[m] = J.theta[(size_t)w.i * M + m];
   const float* st = astart_ptr<DS>(J, w);
@@ -227,7 +256,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
         put(slot2++, q, qd);
         next2 += B2;
       }
-      AM::step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+      AM::step(K, th, target_row(ws, map.ws_off[e], t0 + s), dt, q, qd);
       ll -= 0.5 * (double)arm_obs_term<BOX, false>(K, q, obs + (size_t)s * DX, wx, nullptr);
     }
   }
@@ -287,7 +316,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
       if (c == 0) get_start(q, qd); else get(c - 1, q, qd);
       int s = s0;
       for (int b = 1; b < nblk; ++b) {
-        for (int r = 0; r < B2; ++r, ++s) AM::step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+        for (int r = 0; r < B2; ++r, ++s) AM::step(K, th, target_row(ws, map.ws_off[e], t0 + s), dt, q, qd);
         put(n1 + b - 1, q, qd);
       }
     }
@@ -318,7 +347,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   #pragma unroll 1
         for (int r = 0; r < 2; ++r) {
           AM::keep_consts_in_memory();
-          AM::aba(K, th, q, qd, (float)(t0 + x0 + r) * dt, Tc);
+          AM::aba(K, th, q, qd, target_row(ws, map.ws_off[e], t0 + x0 + r), Tc);
           if (r == 0) {
             T0 = Tc;
             for (int d = 0; d < NB; ++d) {
@@ -345,10 +374,10 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
         // block's checkpoint
         for (int t = x0 + nb - 1; t >= x0; --t) {
           load_block();
-          for (int s = x0; s < t; ++s) AM::step(K, th, (float)(t0 + s) * dt, dt, q, qd);
+          for (int s = x0; s < t; ++s) AM::step(K, th, target_row(ws, map.ws_off[e], t0 + s), dt, q, qd);
           typename AM::Tape T;
           AM::keep_consts_in_memory();
-          AM::aba(K, th, q, qd, (float)(t0 + t) * dt, T);
+          AM::aba(K, th, q, qd, target_row(ws, map.ws_off[e], t0 + t), T);
           reverse_step(t, T);
         }
       }
@@ -372,6 +401,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
 }  // namespace
 
 static_assert(sizeof(ArmConst) <= kArmConstBytes, "ArmConst must fit its workspace region");
+static_assert(kArmTargets == kArmTargetFloats, "one PD-target row per time step");
 
 // Checkpoint plan of an arm job's adjoint: the level-1 stride B1 and the
 // level-2 stride B2 that need the fewest forward-dynamics evaluations per
@@ -415,7 +445,7 @@ bool arm_ck_plan(int h, int slots, int* B1_out, int* B2_out, long* evals_out) {
 }
 
 hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(arm_setup_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs, ws);
+  hipLaunchKernelGGL(arm_setup_kernel, dim3(grid), dim3(kSetupThreads), 0, s, map, d_jobs, ws);
   return hipGetLastError();
 }
 

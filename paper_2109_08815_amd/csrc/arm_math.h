@@ -92,6 +92,24 @@ struct ArmConst {
   float pm_m, pm_z;         // point masses: mass each, height in the box frame
 };
 
+// Target of arm joint i's PD controller at `time`: the sinusoid q_d =
+// qc + amp sin(om t + ph) and its rate qd_d = amp om cos(om t + ph).  One
+// function for every caller, so a table of targets holds exactly the values
+// a direct evaluation gives.
+template <class R>
+__host__ __device__ PDS_ALWAYS_INLINE void pd_target(R qc, R amp, R om, R ph, R time, R* qdes, R* qddes);
+
+// The 14 targets of one time step, precomputed (q_d of the 7 arm joints,
+// then their qd_d): the kernels pass this instead of the time, so each
+// forward-dynamics evaluation reads its targets instead of evaluating 7
+// sinusoids.  P is a pointer type (the constant address space on the
+// device, so the wave-uniform reads are scalar loads).
+template <class P>
+struct TargetRow {
+  P p;
+};
+constexpr int kArmTargets = 14;  // floats per time step of the target table
+
 // Raw model description -> derived constants.  The caller's consts array:
 // gravity[3]; per arm joint 7 x (a, alpha, d, m, cx, cy, cz, Ixx, Iyy, Izz,
 // kp, kd, qc, amp, omega, phase); then for the hinge flange_d, hinge
@@ -163,6 +181,14 @@ __host__ __device__ inline void sincos_r(float x, float* sn, float* cs) { sincos
 inline void sincos_r(double x, double* sn, double* cs) {
   *sn = std::sin(x);
   *cs = std::cos(x);
+}
+
+template <class R>
+__host__ __device__ PDS_ALWAYS_INLINE void pd_target(R qc, R amp, R om, R ph, R time, R* qdes, R* qddes) {
+  R sn, cs;
+  sincos_r(om * time + ph, &sn, &cs);
+  *qdes = qc + amp * sn;
+  *qddes = amp * om * cs;
 }
 
 // Calls f(std::integral_constant<int, I>) for I = B .. E-1 (up) or E-1 .. B
@@ -550,17 +576,26 @@ struct ArmMath {
 
   // Joint torque at time `time` (PD on the arm, viscous damping on the
   // passive axes).
+  // (`time` is the time itself, or the time step's row of precomputed
+  // targets.)
   template <int I>
-  __host__ __device__ static inline R joint_tau(const KC& K, const R* th, R time, R q, R qd) {
+  __host__ __device__ static PDS_ALWAYS_INLINE void targets(const KC& K, R time, R* qdes, R* qddes) {
+    pd_target(R(K.b[I].qc), R(K.b[I].amp), R(K.b[I].om), R(K.b[I].ph), time, qdes, qddes);
+  }
+  template <int I, class P>
+  __host__ __device__ static PDS_ALWAYS_INLINE void targets(const KC&, TargetRow<P> row, R* qdes, R* qddes) {
+    *qdes = R(row.p[I]);
+    *qddes = R(row.p[7 + I]);
+  }
+  template <int I, class TM>
+  __host__ __device__ static inline R joint_tau(const KC& K, const R* th, TM time, R q, R qd) {
     if constexpr (I >= 7) {
       if constexpr (BOX == kUJoint) return -(th[I + 2] * qd);
       else if constexpr (BOX == kUJointWeights && I == 8) return -(R(K.b8) * qd);
       else return -(R(K.bh) * qd);
     } else {
-      R sn, cs;
-      sincos_r(R(K.b[I].om) * time + R(K.b[I].ph), &sn, &cs);
-      const R qdes = R(K.b[I].qc) + R(K.b[I].amp) * sn;
-      const R qddes = R(K.b[I].amp) * R(K.b[I].om) * cs;
+      R qdes, qddes;
+      targets<I>(K, time, &qdes, &qddes);
       return R(K.b[I].kp) * (qdes - q) + R(K.b[I].kd) * (qddes - qd);
     }
   }
@@ -587,7 +622,8 @@ struct ArmMath {
   }
 
   // Articulated Body Algorithm (three passes over the chain).
-  __host__ __device__ static PDS_ALWAYS_INLINE void aba(const KC& K, const R* th, const R* q, const R* qd, R time,
+  template <class TM>
+  __host__ __device__ static PDS_ALWAYS_INLINE void aba(const KC& K, const R* th, const R* q, const R* qd, TM time,
                                                       Tape& T) {
     R u[NB];
     SV vb[NB];  // body velocities
@@ -628,7 +664,7 @@ struct ArmMath {
       const SV U = sv(v3(IA.A.e[si<0, k>], IA.A.e[si<1, k>], IA.A.e[si<2, k>]),
                       v3(IA.B.e[3 * k], IA.B.e[3 * k + 1], IA.B.e[3 * k + 2]));
       const R invD = recip(comp<k>(U.a));
-      u[i] = joint_tau<i>(K, th, time, q[i], qd[i]) - comp<k>(pA.a);
+      u[i] = joint_tau<i, TM>(K, th, time, q[i], qd[i]) - comp<k>(pA.a);
       T.U[i] = U;
       T.invD[i] = invD;
       if constexpr (i > 0) {
@@ -668,7 +704,8 @@ struct ArmMath {
     T.a_last = ap;
   }
 
-  __host__ __device__ static PDS_ALWAYS_INLINE void step(const KC& K, const R* th, R time, R dt, R* q, R* qd) {
+  template <class TM>
+  __host__ __device__ static PDS_ALWAYS_INLINE void step(const KC& K, const R* th, TM time, R dt, R* q, R* qd) {
     Tape T;
     aba(K, th, q, qd, time, T);
   #pragma unroll
@@ -947,8 +984,8 @@ struct ArmMath {
   // (p - o_j) with z_j and o_j joint j's world axis and origin; with rt_p =
   // w^2 (obs - p) summed as A = sum p x rt_p and B = sum rt_p, the adjoint of
   // q_j is z_j . (A - o_j x B).
-  template <bool ADJ>
-  __host__ __device__ static PDS_ALWAYS_INLINE R box_obs(const KC& K, const R* q, const float* obs, const float* w,
+    template <bool ADJ, class OP>
+  __host__ __device__ static PDS_ALWAYS_INLINE R box_obs(const KC& K, const R* q, OP obs, const float* w,
                                                        R* qb) {
     R cs[NB], sn[NB];
   #pragma unroll

@@ -70,6 +70,12 @@ __device__ inline double con_seed(const pds_job& J, size_t id, double g, bool in
 }
 
 constexpr size_t kArmConstBytes = 2048;  // derived arm model constants per job
+constexpr int kArmTargetFloats = 14;     // PD targets per time step (q_d, qd_d of 7 joints)
+// Workspace of an arm job's model: the derived constants, then the table of
+// PD targets of every time step of its trajectories.
+__host__ __device__ inline size_t arm_model_bytes(const pds_job& J) {
+  return kArmConstBytes + (size_t)J.T * kArmTargetFloats * sizeof(float);
+}
 
 // Bandwidth median (see svgd.hip).  Up to kSmallPairs pairs one block
 // selects exactly; above, a sampled bracket plus a counting pass.
@@ -127,7 +133,7 @@ __host__ __device__ inline WsLayout ws_layout(const pds_job& J) {
   const int ds = 2 * J.n_dof;
   size_t o = 0;
   const bool arm = J.model == PDS_MODEL_ARM || J.model == PDS_MODEL_ARM_UJOINT || J.model == PDS_MODEL_ARM_UJOINT_WEIGHTS;
-  L.arm = o;     o = align256(o + (arm ? kArmConstBytes : 0));
+  L.arm = o;     o = align256(o + (arm ? arm_model_bytes(J) : 0));
   L.gth_obs = o; o = align256(o + U * J.M * sizeof(double));
   L.gth_con = o; o = align256(o + U * J.M * sizeof(double));
   L.gs_obs = o;  o = align256(o + U * ds * sizeof(float));
@@ -179,6 +185,7 @@ hipError_t noalloc_scratch(int device, void** out);
 inline int arm_mount(int model) {
   return model == PDS_MODEL_ARM_UJOINT ? 1 : (model == PDS_MODEL_ARM_UJOINT_WEIGHTS ? 2 : 0);
 }
+constexpr int kArmSetupThreads = 256;  // threads per block of the arm set-up kernel
 hipError_t launch_arm_setup(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, hipStream_t s);
 hipError_t launch_arm_forward(const JobMap& map, int mount, const pds_job* d_jobs, char* ws, int grid, bool with_ll,
                               hipStream_t s);

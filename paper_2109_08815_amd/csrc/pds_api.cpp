@@ -179,7 +179,7 @@ size_t job_ws(const pds_job& J, int which) {
   const WsLayout L = pds::ws_layout(J);
   switch (which) {
     case PDS_CALL_FORWARD:
-    case PDS_CALL_LOGLIK: return is_arm(J) ? pds::align256(pds::kArmConstBytes) : 0;
+    case PDS_CALL_LOGLIK: return is_arm(J) ? pds::align256(pds::arm_model_bytes(J)) : 0;
     case PDS_CALL_STEP: return 0;
     default: return L.total;
   }
@@ -234,11 +234,16 @@ int launch_rc(hipError_t e, const char* what) {
 
 int div_up(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Blocks (one wave each) of an arm window kernel: ceil(N / 64) per
+// (trajectory, window), so that a wave's lanes share their time steps.
+int arm_blocks(const pds_job& J) { return J.K * J.n_s * div_up(J.N, pds::kWave); }
+
 int arm_setup_all(const pds_job* h_jobs, const pds_job* d_jobs, int n, const std::vector<uint64_t>& off, char* w,
                   hipStream_t s) {
   int grid = 0;
   JobMap m = make_map(
-      h_jobs, n, off, [](const pds_job& J) { return is_arm(J); }, [](const pds_job&) { return 1; }, &grid);
+      h_jobs, n, off, [](const pds_job& J) { return is_arm(J); },
+      [](const pds_job& J) { return 1 + div_up((long)J.T * 7, pds::kArmSetupThreads); }, &grid);
   if (m.n == 0) return PDS_OK;
   return launch_rc(pds::launch_arm_setup(m, d_jobs, w, grid, s), "arm_setup");
 }
@@ -258,8 +263,7 @@ int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with
   for (int model : {PDS_MODEL_ARM, PDS_MODEL_ARM_UJOINT, PDS_MODEL_ARM_UJOINT_WEIGHTS}) {
     int grid = 0;
     JobMap m = make_map(
-        h_jobs, n, off, [&](const pds_job& J) { return J.model == model; },
-        [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
+        h_jobs, n, off, [&](const pds_job& J) { return J.model == model; }, arm_blocks, &grid);
     if (m.n > 0) {
       rc = launch_rc(pds::launch_arm_forward(m, pds::arm_mount(model), d_jobs, w, grid, with_ll, s), "arm_forward");
       if (rc) return rc;
@@ -284,8 +288,8 @@ int rollout_calls(const pds_job* h_jobs, const pds_job* d_jobs, int n, bool with
 // Adjoint launch shape of one job, from its own size.  Planar: with fewer
 // waves than SIMDs the two adjoint channels go to two lanes per unit
 // (split); whole windows stay in LDS (full) when every wave of the job can
-// be resident at once, else sqrt(h) checkpoints.  (The arm adjoint keeps
-// its window states in the workspace and has one shape.)
+// be resident at once, else sqrt(h) checkpoints.  (The arm adjoint's shape
+// is arm_plan's.)
 struct AdjShape {
   bool split, full, tape;
   size_t lds;  // dynamic LDS bytes per block
@@ -326,7 +330,7 @@ struct ArmShapePlan {
   size_t lds;
 };
 bool arm_plan(const pds_job& J, ArmShapePlan* out) {
-  const long waves = div_up((long)J.N * J.K * J.n_s, pds::kWave);
+  const long waves = arm_blocks(J);
   const long per_cu = std::min(std::max(div_up(waves, 256), 1), (int)kArmWavesPerCu);
   const size_t slot_bytes = (size_t)2 * J.n_dof * pds::kWave * sizeof(float);
   const int slots = (int)((160 * 1024 / per_cu) / slot_bytes);
@@ -568,7 +572,7 @@ int sim_batch_adjoint(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jo
       int grid = 0;
       JobMap m = make_map(
           h_jobs, n_jobs, off, [&](const pds_job& J) { return J.model == model && arm_shape[&J - h_jobs].lds == lds; },
-          [](const pds_job& J) { return div_up((long)J.N * J.K * J.n_s, pds::kWave); }, &grid);
+          arm_blocks, &grid);
       for (int e = 0; e < m.n; ++e) m.aux[e] = arm_shape[m.job[e]].aux;
       rc = launch_rc(pds::launch_arm_adjoint(m, pds::arm_mount(model), d_jobs, w, grid, lds, s), "arm_adjoint");
       if (rc) return rc;
