@@ -95,8 +95,10 @@ def parse():
                     help="time the posterior-consistency metrics (KNN-KL both ways + MMD) between the particles' "
                          "rollouts and 10 held-out trajectories instead of the CSVGD iteration")
     ap.add_argument("--no-graph", action="store_true", help="plain launches instead of graph replay")
-    ap.add_argument("--no-overlap", action="store_true",
-                    help="compute the kernel bandwidth after the adjoint instead of concurrently with it")
+    ap.add_argument("--bandwidth", choices=["concurrent", "before", "after"], default="concurrent",
+                    help="where the kernel bandwidth runs: on a second stream concurrently with the adjoint "
+                         "(default), or on the iteration's stream before or after it")
+    ap.add_argument("--no-overlap", action="store_true", help="same as --bandwidth after")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -313,7 +315,9 @@ def main():
     obs = driver.gpu_observations(pb)
     S = driver.gpu_shooting_init(pb, pb.particles)
     job = L.Job(pb, obs, theta=pb.particles, S=S, device_iter=True)
-    run = driver.CSVGD([job], overlap=not args.no_overlap)
+    if args.no_overlap:
+        args.bandwidth = "after"
+    run = driver.CSVGD([job], overlap={"concurrent": True, "before": "before", "after": False}[args.bandwidth])
     for _ in range(max(1, args.warmup)):
         run.step()
     torch.cuda.synchronize()
@@ -392,7 +396,8 @@ def main():
                           "box1": "7-joint arm with the box on a universal joint",
                           "box2": "7-joint arm with two weights in the box on a universal joint"}[args.config],
             pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain",
-            "bandwidth": "concurrent with the adjoint" if not args.no_overlap else "after the adjoint"},
+            "bandwidth": {"concurrent": "concurrent with the adjoint", "before": "before the adjoint",
+                          "after": "after the adjoint"}[args.bandwidth]},
         "iters_per_s": args.steps / elapsed,
         "iteration_ms": ({"p10": float(np.percentile(per_iter, 10)), "p50": float(np.percentile(per_iter, 50)),
                           "p90": float(np.percentile(per_iter, 90)), "replays": len(per_iter)} if per_iter else None),

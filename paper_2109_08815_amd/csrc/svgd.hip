@@ -240,7 +240,7 @@ __device__ void sel_histogram(const KT* src, uint32_t n, SelShared<KT>& S, const
   __syncthreads();
   const bool share = sel_shared(t, live);
   const bool use1 = live[1] && !share;
-  constexpr int U = 8;
+  constexpr int U = 16;  // loads in flight per thread
   for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
     KT key[U];
 #pragma unroll
@@ -305,7 +305,7 @@ template <int NT, class KT>
 __device__ uint32_t sel_compact(const KT* src, uint32_t n, KT* dst, uint32_t cap, SelShared<KT>& S) {
   const SelTarget<KT> t0 = S.tg[0], t1 = S.tg[1];
   const bool l0 = t0.lo != t0.hi, l1 = t1.lo != t1.hi;
-  constexpr int U = 8;
+  constexpr int U = 16;  // loads in flight per thread
   uint32_t base = 0;
   for (uint32_t c0 = 0; c0 < n; c0 += NT * U) {
     KT key[U];

@@ -340,11 +340,19 @@ def svgd_step(b: Batch, optimizer=PDS_OPT_ADAM, iteration=1, stream=None):
 def csvgd_iteration(b: Batch, iteration: int, optimizer=PDS_OPT_ADAM, stream=None, overlap=False):
     """One CSVGD iteration (Algorithm 1) over every job of the batch.
 
-    With `overlap` the kernel bandwidth (which depends on theta alone) runs
-    on the batch's side stream concurrently with the adjoint; both streams
-    join before phi.  `stream` (a torch stream, default the current one) is
-    the stream the iteration is ordered on."""
-    if not overlap:
+    The kernel bandwidth depends on theta alone, so it may run anywhere
+    before phi.  `overlap`: False (or "after") computes it after the adjoint,
+    "before" ahead of it on the same stream, True (or "concurrent") on the
+    batch's side stream concurrently with the adjoint, both streams joining
+    before phi.  `stream` (a torch stream, default the current one) is the
+    stream the iteration is ordered on."""
+    if overlap == "before":
+        svgd_bandwidth(b, stream)
+        sim_batch_adjoint(b, stream)
+        svgd_phi_at_bandwidth(b, stream)
+        svgd_step(b, optimizer, iteration, stream)
+        return
+    if not overlap or overlap == "after":
         sim_batch_adjoint(b, stream)
         svgd_phi(b, stream)
         svgd_step(b, optimizer, iteration, stream)
