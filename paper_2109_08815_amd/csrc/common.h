@@ -167,6 +167,10 @@ constexpr int kSdotInline = 512;
 struct MedianMaps {
   JobMap keys, select, count, large;
   int grid_keys, grid_select, grid_count, grid_large;
+  // the narrow chain of larger jobs whose bandwidth runs beside a window
+  // kernel that leaves SIMDs free (one-wave blocks; svgd.hip)
+  JobMap lean_keys, lean_count, lean_final;
+  int grid_lean_keys = 0, grid_lean_count = 0, grid_lean_final = 0;
 };
 hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, int mmax, int rank_shift,
                          hipStream_t s);

@@ -365,27 +365,55 @@ int phi_prologue(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, u
   return PDS_OK;
 }
 
+// Waves the window kernels of sim_batch_adjoint launch for a batch (one
+// wave per arm block; planar blocks of 32 or 64 units).
+long adjoint_waves(const pds_job* h_jobs, int n) {
+  long w = 0;
+  for (int j = 0; j < n; ++j) {
+    const pds_job& J = h_jobs[j];
+    if (is_arm(J)) {
+      w += arm_blocks(J);
+    } else {
+      const long units = (long)J.N * J.K * J.n_s;
+      w += div_up(units, planar_shape(J).split ? pds::kWave / 2 : pds::kWave);
+    }
+  }
+  return w;
+}
+
+// concurrent: the bandwidth runs beside the batch's sim_batch_adjoint
+// (svgd_bandwidth).  Larger jobs then take the narrow chain of one-wave
+// blocks when the window kernels leave at least a CU's worth of SIMDs free
+// (their blocks of 256 or 1024 threads would wait for the window kernels'
+// end); the result is the same exact median either way.
 int bandwidth_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, const std::vector<uint64_t>& off,
-                    int mmax, char* w, hipStream_t s) {
+                    int mmax, char* w, hipStream_t s, bool concurrent) {
   int rc = PDS_OK;
   auto all = [](const pds_job&) { return true; };
   auto npairs = [](const pds_job& J) { return (long)J.N * (J.N - 1) / 2; };
   // bandwidth: keys (or a sample of them), one selecting block per job,
   // then the count and final kernels for jobs above kSmallPairs pairs
+  const bool narrow = concurrent && adjoint_waves(h_jobs, n_jobs) <= 1024 - 4;
   auto large = [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; };
+  auto lean = [&](const pds_job& J) { return narrow && large(J); };
+  auto wide = [&](const pds_job& J) { return !lean(J); };
+  auto wide_large = [&](const pds_job& J) { return large(J) && !lean(J); };
+  auto tiles = [](const pds_job& J) {
+    const long nb = div_up(J.N, pds::kCountTile);
+    return nb * (nb + 1) / 2;
+  };
   pds::MedianMaps mm;
   mm.keys = make_map(
-      h_jobs, n_jobs, off, all,
+      h_jobs, n_jobs, off, wide,
       [&](const pds_job& J) { return div_up(large(J) ? pds::kSampleKeys : npairs(J), 256); }, &mm.grid_keys);
-  mm.select = make_map(h_jobs, n_jobs, off, all, [](const pds_job&) { return 1; }, &mm.grid_select);
-  mm.count = make_map(
-      h_jobs, n_jobs, off, large,
-      [](const pds_job& J) {
-        const long nb = div_up(J.N, pds::kCountTile);
-        return nb * (nb + 1) / 2;
-      },
-      &mm.grid_count);
-  mm.large = make_map(h_jobs, n_jobs, off, large, [](const pds_job&) { return 1; }, &mm.grid_large);
+  mm.select = make_map(h_jobs, n_jobs, off, wide, [](const pds_job&) { return 1; }, &mm.grid_select);
+  mm.count = make_map(h_jobs, n_jobs, off, wide_large, tiles, &mm.grid_count);
+  mm.large = make_map(h_jobs, n_jobs, off, wide_large, [](const pds_job&) { return 1; }, &mm.grid_large);
+  mm.lean_keys = make_map(
+      h_jobs, n_jobs, off, lean, [](const pds_job&) { return div_up(pds::kSampleKeys, pds::kWave); },
+      &mm.grid_lean_keys);
+  mm.lean_count = make_map(h_jobs, n_jobs, off, lean, tiles, &mm.grid_lean_count);
+  mm.lean_final = make_map(h_jobs, n_jobs, off, lean, [](const pds_job&) { return 1; }, &mm.grid_lean_final);
   rc = launch_rc(pds::launch_median(mm, d_jobs, w, mmax, g_median_rank_shift, s), "median");
   if (rc) return rc;
   return PDS_OK;
@@ -648,7 +676,7 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
   int mmax = 1;
   int rc = phi_prologue(h_jobs, d_jobs, n_jobs, NEED_PHI, ws, ws_bytes, &off, &mmax);
   if (rc) return rc;
-  rc = bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, static_cast<char*>(ws), (hipStream_t)stream);
+  rc = bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, static_cast<char*>(ws), (hipStream_t)stream, false);
   if (rc) return rc;
   return phi_calls(h_jobs, d_jobs, n_jobs, off, static_cast<char*>(ws), (hipStream_t)stream);
 }
@@ -672,7 +700,7 @@ int svgd_phi_noalloc(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_job
   int mmax = 1;
   for (int j = 0; j < n_jobs; ++j) mmax = h_jobs[j].M > mmax ? h_jobs[j].M : mmax;
   char* w = static_cast<char*>(ws);
-  rc = bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, w, s);
+  rc = bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, w, s, false);
   if (rc) return rc;
   return phi_calls(h_jobs, d_jobs, n_jobs, off, w, s);
 }
@@ -683,7 +711,7 @@ int svgd_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs,
   int mmax = 1;
   int rc = phi_prologue(h_jobs, d_jobs, n_jobs, NEED_BW, ws, ws_bytes, &off, &mmax);
   if (rc) return rc;
-  return bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, static_cast<char*>(ws), (hipStream_t)stream);
+  return bandwidth_calls(h_jobs, d_jobs, n_jobs, off, mmax, static_cast<char*>(ws), (hipStream_t)stream, true);
 }
 
 int svgd_phi_at_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,

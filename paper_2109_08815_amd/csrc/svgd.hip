@@ -511,7 +511,8 @@ __device__ inline uint64_t sample_pair(uint64_t k, uint64_t P) {
   return __umul64hi(z, P);
 }
 
-// Keys kernel, 256 pairs per block.  Jobs with at most kSmallPairs pairs:
+// Keys kernel, one pair per thread (256-thread blocks, or one-wave blocks
+// for the narrow median below).  Jobs with at most kSmallPairs pairs:
 // every pair's key, split into high and low 32-bit words.  Larger jobs:
 // the high words of a fixed pseudo-random sample of kSampleKeys keys; their
 // first block also clears the count kernel's counter.
@@ -522,7 +523,7 @@ __global__ void __launch_bounds__(256) median_keys_kernel(JobMap map, const pds_
   const pds_job& J = jobs[map.job[e]];
   const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
   const bool small = P <= (uint64_t)kSmallPairs;
-  const uint32_t k = (uint32_t)(blockIdx.x - map.begin[e]) * 256 + threadIdx.x;
+  const uint32_t k = (uint32_t)(blockIdx.x - map.begin[e]) * blockDim.x + threadIdx.x;
   const WsLayout L = ws_layout(J);
   char* base = ws + map.ws_off[e];
   if (!small && k == 0) med_state(J, ws, map.ws_off[e])->packed = 0ull;
@@ -929,17 +930,161 @@ __global__ void __launch_bounds__(kMedThreads) median_count_kernel(JobMap map, c
   for (uint32_t c = threadIdx.x; c < total; c += NT) cand[base_s + c] = lbuf[c];
 }
 
+// ---------------------------------------------------------------------------
+// Narrow median for larger jobs whose bandwidth runs concurrently with a
+// window kernel that leaves whole SIMDs free for its whole duration (the
+// 2048-particle arm job has 960 waves for 1024 SIMDs, one wave per SIMD,
+// LDS nearly full).  Blocks of the kernels above (256 or 1024 threads)
+// cannot be placed beside such a kernel and would wait for its end; these
+// run one wave per block with at most 40 KiB of LDS, so they fit the free
+// SIMDs and finish inside the window kernel's time, slowly but off the
+// critical path.  The results are the same keys: the bracket is the same
+// pair of sample order statistics, the candidates the same keys (in
+// another order), the selection exact.
+// ---------------------------------------------------------------------------
+constexpr int kLeanThreads = 64;
+constexpr int kLeanCap = 4096;     // 32-bit sample keys the bracket kernel holds in LDS
+constexpr int kLeanLastCap = 2048;  // 64-bit candidates the narrow final holds in LDS
+
+// Bracket of a larger job from its sample (as the select kernel computes
+// it): the sample's order statistics at the middle ranks' sample positions
+// widened by four binomial standard deviations, as whole high words.
+__global__ void __launch_bounds__(kLeanThreads) median_bracket_lean_kernel(JobMap map,
+                                                                           const pds_job* __restrict__ jobs,
+                                                                           char* __restrict__ ws, int rank_shift) {
+  constexpr int NT = kLeanThreads;
+  constexpr uint32_t kNoKey = 0xffffffffu;
+  __shared__ uint32_t lbuf[kLeanCap];
+  __shared__ SelShared<uint32_t> S;
+  __shared__ uint32_t s_nb;
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  const uint64_t P = (uint64_t)J.N * (J.N - 1) / 2;
+  const uint32_t n = (uint32_t)kSampleKeys;
+  const WsLayout L = ws_layout(J);
+  const uint32_t* khi = reinterpret_cast<const uint32_t*>(ws + map.ws_off[e] + L.khi);
+  MedianState* st = med_state(J, ws, map.ws_off[e]);
+  const uint32_t nb = ensemble_size<NT>(J, &s_nb);
+  const uint64_t Pe = (uint64_t)nb * (nb - 1) / 2;
+  // unmasked sample keys and their range
+  uint32_t nvl = 0u, mn = kNoKey, mx = 0u;
+  for (uint32_t c = threadIdx.x; c < n; c += NT) {
+    const uint32_t h = khi[c];
+    if (h != kNoKey) {
+      ++nvl;
+      mn = h < mn ? h : mn;
+      mx = h > mx ? h : mx;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    nvl += (uint32_t)__shfl_xor((int)nvl, o);
+    const uint32_t a = (uint32_t)__shfl_xor((int)mn, o), b = (uint32_t)__shfl_xor((int)mx, o);
+    mn = a < mn ? a : mn;
+    mx = b > mx ? b : mx;
+  }
+  const uint32_t nv = nvl;
+  if (Pe == 0 || nv == 0) {
+    if (threadIdx.x == 0) {
+      st->a = 0ull;
+      st->b = ~0ull;
+    }
+    return;
+  }
+  const double d = 2.0 * sqrt((double)n) + 2.0;
+  const double c0 = (double)n * (double)((Pe - 1) / 2) / (double)P - d + rank_shift;
+  const double c1 = (double)n * (double)(Pe / 2 + 1) / (double)P + d + rank_shift;
+  const bool a_open = c0 < 0.0 || c0 > (double)(nv - 1);
+  const bool b_open = c1 > (double)(nv - 1);
+  const uint32_t t0 = a_open ? 0u : (uint32_t)floor(c0);
+  const uint32_t t1 = b_open ? nv - 1 : (uint32_t)fmax(ceil(c1), 0.0);
+  if (threadIdx.x == 0) {
+    S.tg[0] = SelTarget<uint32_t>{mn, mx, t0};
+    S.tg[1] = SelTarget<uint32_t>{mn, mx, t1};
+  }
+  __syncthreads();
+  uint32_t hsel[2];
+  select_keys<NT>(khi, n, true, lbuf, (uint32_t)kLeanCap, S, hsel);
+  if (threadIdx.x == 0) {
+    st->a = a_open ? 0ull : (uint64_t)hsel[0] << 32;
+    st->b = b_open ? ~0ull : (((uint64_t)hsel[1] << 32) | 0xffffffffull);
+  }
+}
+
+// Count kernel of the narrow median: one wave per 64 x 64 tile, four
+// columns per lane at a time; the keys below a are counted and those inside
+// [a, b] appended to the candidate array, one atomic per group of columns.
+template <int MM>
+__global__ void __launch_bounds__(kLeanThreads) median_count_lean_kernel(JobMap map,
+                                                                         const pds_job* __restrict__ jobs,
+                                                                         char* __restrict__ ws) {
+  __shared__ float ti_s[kCountTile * MM], tj_s[kCountTile * MM];
+  __shared__ bool fi_s[kCountTile], fj_s[kCountTile];
+  const int e = map_entry(map, blockIdx.x);
+  const pds_job& J = jobs[map.job[e]];
+  MedianState* st = med_state(J, ws, map.ws_off[e]);
+  const int N = J.N, M = J.M;
+  const int nb = (N + kCountTile - 1) / kCountTile;
+  int bi, bj;
+  tile_of(blockIdx.x - map.begin[e], nb, &bi, &bj);
+  const uint64_t a = st->a, b = st->b;
+  const int ri = bi * kCountTile, rj = bj * kCountTile;
+  const int ni = min(kCountTile, N - ri), nj = min(kCountTile, N - rj);
+  for (int t = threadIdx.x; t < kCountTile * MM; t += kLeanThreads) {
+    const int r = t / MM, m = t % MM;
+    ti_s[t] = (r < ni && m < M) ? J.theta[(size_t)(ri + r) * M + m] : 0.f;
+    tj_s[t] = (r < nj && m < M) ? J.theta[(size_t)(rj + r) * M + m] : 0.f;
+  }
+  const int row = threadIdx.x;
+  fi_s[row] = row < ni && frozen_particle(J, ri + row);
+  fj_s[row] = row < nj && frozen_particle(J, rj + row);
+  __syncthreads();
+  double inv_rho[MM];
+  load_inv_rho<MM>(J, inv_rho);
+  const int i = ri + row;
+  const WsLayout L = ws_layout(J);
+  uint64_t* cand = reinterpret_cast<uint64_t*>(ws + map.ws_off[e] + L.cand);
+  uint32_t nless = 0;
+  for (int cg = 0; cg < kCountTile / 4; ++cg) {
+    uint64_t key[4];
+    bool keep[4];
+    uint32_t nkeep = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jl = cg * 4 + q;
+      const bool valid = row < ni && jl < nj && i < rj + jl && !fi_s[row] && !fj_s[jl];
+      key[q] = valid ? key_of(pair_d2<MM>(&ti_s[row * MM], &tj_s[jl * MM], inv_rho, M)) : 0ull;
+      nless += (valid && key[q] < a) ? 1u : 0u;
+      keep[q] = valid && key[q] >= a && key[q] <= b;
+      nkeep += keep[q] ? 1u : 0u;
+    }
+    const uint32_t inc = wave_scan(nkeep);
+    const uint32_t total = (uint32_t)__shfl((int)inc, 63);
+    if (total == 0) continue;
+    uint32_t base = 0;
+    if (threadIdx.x == 63)
+      base = (uint32_t)(atomicAdd((unsigned long long*)&st->packed, (unsigned long long)total << 32) >> 32);
+    base = (uint32_t)__shfl((int)base, 63);
+    uint32_t o = base + inc - nkeep;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (keep[q]) cand[o++] = key[q];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) nless += __shfl_xor(nless, o);
+  if (threadIdx.x == 0 && nless) atomicAdd((unsigned long long*)&st->packed, (unsigned long long)nless);
+}
+
 // Final kernel, one block per larger job: both middle keys of the
 // ensemble's pairs exactly among the candidates or, if the bracket missed a
 // middle rank, among the keys of the interval that holds both (recomputed
 // from theta).
-template <int MM>
-__global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                                   char* __restrict__ ws) {
-  __shared__ uint64_t lbuf[kLastCap];
+template <int MM, int NT = kMedThreads, int CAP = kLastCap>
+__global__ void __launch_bounds__(NT) median_final_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                          char* __restrict__ ws) {
+  __shared__ uint64_t lbuf[CAP];
   __shared__ SelShared<uint64_t> S;
   __shared__ uint32_t s_nb;
-  constexpr int NT = kMedThreads;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
   const MedianState* st = med_state(J, ws, map.ws_off[e]);
@@ -970,7 +1115,7 @@ __global__ void __launch_bounds__(kMedThreads) median_final_kernel(JobMap map, c
   }
   __syncthreads();
   uint64_t out[2];
-  select_keys<NT>((const uint64_t*)cand, n, true, lbuf, (uint32_t)kLastCap, S, out);
+  select_keys<NT>((const uint64_t*)cand, n, true, lbuf, (uint32_t)CAP, S, out);
   if (threadIdx.x == 0) write_bandwidth(J, out[0], out[1], nb);
 }
 
@@ -1286,20 +1431,42 @@ __global__ void iter_bump_kernel(JobMap map, const pds_job* __restrict__ jobs) {
 
 hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, int mmax, int rank_shift,
                          hipStream_t s) {
+  hipError_t err = hipSuccess;
   if (mm.keys.n > 0) {
     PDS_MEDIAN_LAUNCH(median_keys_kernel, mm.grid_keys, 256, mm.keys);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
+    if ((err = hipGetLastError()) != hipSuccess) return err;
   }
-  hipLaunchKernelGGL(median_select_kernel, dim3(mm.grid_select), dim3(kMedThreads), 0, s, mm.select, d_jobs, ws,
-                     rank_shift);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess || mm.large.n == 0) return err;
-  PDS_MEDIAN_LAUNCH(median_count_kernel, mm.grid_count, kMedThreads, mm.count);
-  err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  PDS_MEDIAN_LAUNCH(median_final_kernel, mm.grid_large, kMedThreads, mm.large);
-  return hipGetLastError();
+  if (mm.select.n > 0) {
+    hipLaunchKernelGGL(median_select_kernel, dim3(mm.grid_select), dim3(kMedThreads), 0, s, mm.select, d_jobs, ws,
+                       rank_shift);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  if (mm.large.n > 0) {
+    PDS_MEDIAN_LAUNCH(median_count_kernel, mm.grid_count, kMedThreads, mm.count);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    PDS_MEDIAN_LAUNCH(median_final_kernel, mm.grid_large, kMedThreads, mm.large);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  if (mm.lean_final.n > 0) {  // the narrow chain (see median_bracket_lean_kernel)
+    PDS_MEDIAN_LAUNCH(median_keys_kernel, mm.grid_lean_keys, kLeanThreads, mm.lean_keys);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(median_bracket_lean_kernel, dim3(mm.grid_lean_final), dim3(kLeanThreads), 0, s,
+                       mm.lean_final, d_jobs, ws, rank_shift);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    PDS_MEDIAN_LAUNCH(median_count_lean_kernel, mm.grid_lean_count, kLeanThreads, mm.lean_count);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (mmax <= 4)
+      hipLaunchKernelGGL((median_final_kernel<4, kLeanThreads, kLeanLastCap>), dim3(mm.grid_lean_final),
+                         dim3(kLeanThreads), 0, s, mm.lean_final, d_jobs, ws);
+    else if (mmax <= 8)
+      hipLaunchKernelGGL((median_final_kernel<8, kLeanThreads, kLeanLastCap>), dim3(mm.grid_lean_final),
+                         dim3(kLeanThreads), 0, s, mm.lean_final, d_jobs, ws);
+    else
+      hipLaunchKernelGGL((median_final_kernel<PDS_MAX_M, kLeanThreads, kLeanLastCap>), dim3(mm.grid_lean_final),
+                         dim3(kLeanThreads), 0, s, mm.lean_final, d_jobs, ws);
+    err = hipGetLastError();
+  }
+  return err;
 }
 
 // Workspace of svgd_phi_noalloc: one fixed array per device, held until the

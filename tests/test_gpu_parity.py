@@ -331,6 +331,35 @@ def test_bandwidth_exact_when_bracket_misses(orc, shift):
     assert abs(h - h_ref) <= 1e-15 * h_ref
 
 
+@pytest.mark.parametrize("shift,n_frozen", [(0, 0), (0, 3), (400, 0), (-20000, 2)])
+def test_narrow_bandwidth_beside_a_small_window_kernel(orc, shift, n_frozen):
+    """svgd_bandwidth of a larger job whose window kernels leave SIMDs free
+    (the 2048-particle arm job: 960 waves for 1024 SIMDs) runs the median
+    in one-wave blocks; the bandwidth is the oracle's exact median, and
+    bitwise svgd_phi's (the wide blocks), also with frozen particles and a
+    bracket moved off the middle ranks (the final kernel's recovery pass)."""
+    print_case("bandwidth-narrow", shift, n_frozen)
+    pb = f32_problem(synth.make_problem("c4"))
+    assert pb.N * pb.K * pb.n_s // 64 < 1024
+    theta = r32(pb.particles)
+    flags = np.zeros(pb.N, np.int32)
+    flags[np.random.default_rng(11).choice(pb.N, n_frozen, replace=False)] = L.PDS_FLAG_FROZEN
+    job = L.Job(pb, np.zeros((pb.K, pb.T, pb.d_x)), theta=theta)
+    set_tensor(job.flags, flags)
+    b = L.Batch([job])
+    try:
+        L.test_median_shift(shift)
+        L.svgd_bandwidth(b)
+        h_narrow = np64(job.bandwidth)[0]
+        L.svgd_phi(b)
+        h_wide = np64(job.bandwidth)[0]
+    finally:
+        L.test_median_shift(0)
+    h_ref, _ = orc.bandwidth(theta, pb.rho, live=flags == 0)
+    assert h_narrow == h_wide
+    assert abs(h_narrow - h_ref) <= 1e-15 * h_ref
+
+
 @pytest.mark.parametrize("groups", [(300, 300), (150, 200, 250), (599, 1), (100, 100), (150, 50), (199, 1),
                                     (64, 64, 72)])
 def test_bandwidth_exact_with_heavy_ties(orc, groups):
