@@ -174,12 +174,11 @@ struct MedianMaps {
 };
 hipError_t launch_median(const MedianMaps& mm, const pds_job* d_jobs, char* ws, int mmax, int rank_shift,
                          hipStream_t s);
-// Step launches of at most this many blocks per job advance the device
-// iteration counter themselves (a completion count); larger ones are
-// followed by iter_bump.
+// A step launch gives each job at most this many blocks (each thread
+// taking every (blocks x threads)-th element), so that the blocks can
+// advance the device iteration counter themselves by a completion count.
 constexpr int kStepCountBlocks = 256;
-constexpr int kStepThreads = 1024;  // threads (one element each) per step-kernel block
-hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s);
+constexpr int kStepThreads = 1024;  // threads per step-kernel block
 // Device address of the fixed workspace array of svgd_phi_noalloc on
 // `device` (looked up once per device).
 hipError_t noalloc_scratch(int device, void** out);

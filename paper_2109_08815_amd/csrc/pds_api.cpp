@@ -735,19 +735,11 @@ int svgd_step(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, int3
   auto blocks = [](const pds_job& J) {
     const long ds = 2 * J.n_dof;
     const long n = (long)J.N * J.M + (long)J.N * J.K * (J.n_s - 1) * ds + (long)J.N * J.K * (J.n_s - 1);
-    return div_up(n, pds::kStepThreads);
+    return std::min(div_up(n, pds::kStepThreads), pds::kStepCountBlocks);
   };
   int grid = 0;
   JobMap m = make_map(h_jobs, n_jobs, off, [](const pds_job&) { return true; }, blocks, &grid);
-  rc = launch_rc(pds::launch_step(m, d_jobs, grid, optimizer, iter, (hipStream_t)stream), "step");
-  if (rc) return rc;
-  int bgrid = 0;
-  JobMap mb = make_map(
-      h_jobs, n_jobs, off,
-      [&](const pds_job& J) { return J.iter_dev != nullptr && blocks(J) > pds::kStepCountBlocks; },
-      [](const pds_job&) { return 1; }, &bgrid);
-  if (mb.n == 0) return PDS_OK;
-  return launch_rc(pds::launch_iter_bump(mb, d_jobs, bgrid, (hipStream_t)stream), "iter_bump");
+  return launch_rc(pds::launch_step(m, d_jobs, grid, optimizer, iter, (hipStream_t)stream), "step");
 }
 
 size_t pds_traj_metrics_workspace(int32_t n, int32_t m, int32_t d) {

@@ -1338,13 +1338,15 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pd
   const int nSp = J.K * (J.n_s - 1) * ds;  // shooting floats per particle
   const int nLp = J.K * (J.n_s - 1);
   const int nT = J.N * J.M, nS = J.N * nSp, nL = J.N * nLp;
-  const int t = (blockIdx.x - map.begin[e]) * kStepThreads + threadIdx.x;
+  const int nb = map.begin[e + 1] - map.begin[e];
   const int stride = J.M + nSp;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   // Adam bias corrections 1 - b^it per thread, b^it = 2^(it log2 b): no
   // block-wide wait before the element loads
   const int it = J.iter_dev ? J.iter_dev[0] + 1 : iter;
   const float bc1 = 1.0f - exp2f((float)it * log2f(b1)), bc2 = 1.0f - exp2f((float)it * log2f(b2));
+  // the job's elements, grid-stride over its (at most kStepCountBlocks) blocks
+  for (int t = (blockIdx.x - map.begin[e]) * kStepThreads + threadIdx.x; t < nT + nS + nL; t += nb * kStepThreads) {
   if (t < nT && !in_phi(J, t / J.M)) {
     const int i = t / J.M;
     if (t % J.M == 0 && !(J.flags[i] & PDS_FLAG_FROZEN)) atomicOr(&J.flags[i], PDS_FLAG_FROZEN);
@@ -1391,14 +1393,15 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pd
     const int r = t - nT - nS;
     J.lam_def[r] += J.eps_lam * (float)J.gdef[r];
   }
-  const int nb = map.begin[e + 1] - map.begin[e];
-  if (J.iter_dev && nb <= kStepCountBlocks) {
+  }
+  if (J.iter_dev) {
     // Advance the device counter once every block of the job is past its
     // use of it: each thread's stores above depend on the value it read,
     // so after the barrier every read of this block has returned.  Blocks
     // count themselves in iter_dev[1] with device-scope atomics; the last
     // one bumps the counter and leaves the count at zero for the next call.
-    // (Same-address atomics serialise: larger jobs use iter_bump_kernel.)
+    // (Same-address atomics serialise: hence at most kStepCountBlocks
+    // blocks per job, each taking several elements.)
     __syncthreads();
     if (threadIdx.x == 0) {
       if (atomicAdd(&J.iter_dev[1], 1) == nb - 1) {
@@ -1407,14 +1410,6 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(JobMap map, const pd
       }
     }
   }
-}
-
-// Advances the device counter after the step kernel of a job with more
-// than kStepCountBlocks blocks.
-__global__ void iter_bump_kernel(JobMap map, const pds_job* __restrict__ jobs) {
-  const int e = map_entry(map, blockIdx.x);
-  const pds_job& J = jobs[map.job[e]];
-  if (threadIdx.x == 0 && J.iter_dev) J.iter_dev[0] += 1;
 }
 
 }  // namespace
@@ -1499,11 +1494,6 @@ hipError_t noalloc_scratch(int device, void** out) {
   }
   *out = ptr[device];
   return hipSuccess;
-}
-
-hipError_t launch_iter_bump(const JobMap& map, const pds_job* d_jobs, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(iter_bump_kernel, dim3(grid), dim3(64), 0, s, map, d_jobs);
-  return hipGetLastError();
 }
 
 hipError_t launch_phi_partial(const JobMap& map, const pds_job* d_jobs, char* ws, int grid, int mmax,
