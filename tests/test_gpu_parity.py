@@ -375,19 +375,23 @@ def test_bandwidth_exact_with_heavy_ties(orc, groups):
     assert abs(_bandwidth_gpu(pb, theta) - h_ref) <= 1e-15 * h_ref
 
 
-@pytest.mark.parametrize("optimizer,lik,limits", [(L.PDS_OPT_SGD, synth.LIK_MDMM, synth.LIMITS_SOFT),
-                                                  (L.PDS_OPT_ADAM, synth.LIK_MDMM, synth.LIMITS_SOFT),
-                                                  (L.PDS_OPT_ADAM, synth.LIK_DEFECT, synth.LIMITS_SOFT),
-                                                  (L.PDS_OPT_ADAM, synth.LIK_MDMM, synth.LIMITS_PROJECT)])
-def test_step_parity(orc, optimizer, lik, limits):
-    print_case("step", optimizer, lik, limits)
-    pb = f32_problem(synth.make_problem("c2", N=70, K=2, T=80, n_s=4, lik=lik, limits=limits))
+@pytest.mark.parametrize("optimizer,lik,limits,cfg,over", [
+    (L.PDS_OPT_SGD, synth.LIK_MDMM, synth.LIMITS_SOFT, "c2", dict(N=70, K=2, T=80, n_s=4)),
+    (L.PDS_OPT_ADAM, synth.LIK_MDMM, synth.LIMITS_SOFT, "c2", dict(N=70, K=2, T=80, n_s=4)),
+    (L.PDS_OPT_ADAM, synth.LIK_DEFECT, synth.LIMITS_SOFT, "c2", dict(N=70, K=2, T=80, n_s=4)),
+    (L.PDS_OPT_ADAM, synth.LIK_MDMM, synth.LIMITS_PROJECT, "c2", dict(N=70, K=2, T=80, n_s=4)),
+    # the arm's full shape: 1.02 million elements, several per thread of 249 blocks
+    (L.PDS_OPT_ADAM, synth.LIK_MDMM, synth.LIMITS_SOFT, "c4", {})])
+def test_step_parity(orc, optimizer, lik, limits, cfg, over):
+    print_case("step", optimizer, lik, limits, cfg)
+    pb = f32_problem(synth.make_problem(cfg, lik=lik, limits=limits, **over))
     rng = np.random.default_rng(5)
     N, K, ns, ds, M = pb.N, pb.K, pb.n_s, pb.d_s, pb.M
     theta = r32(pb.lo - 0.2 + rng.uniform(size=(N, M)) * (pb.hi - pb.lo + 0.4))  # some outside the limits
     S = r32(rng.normal(size=(N, K, ns - 1, ds)))
     obs = np.zeros((K, pb.T, pb.d_x))
-    job = L.Job(pb, obs, theta=theta, S=S)
+    job = L.Job(pb, obs, theta=theta, S=S, device_iter=True)
+    job.iter_dev[0] = 2  # the step uses iteration iter_dev[0] + 1 = 3
     vals = dict(phi=r32(rng.normal(size=(N, M))), g_con=rng.normal(size=(N, M)),
                 S_dot=r32(rng.normal(size=(N, K, ns - 1, ds))), gdef=rng.uniform(size=(N, K, ns - 1)),
                 lam_lim=r32(rng.normal(size=(N, M))), lam_def=r32(rng.uniform(size=(N, K, ns - 1))),
@@ -406,6 +410,8 @@ def test_step_parity(orc, optimizer, lik, limits):
         assert np.all(np.abs((got - old) - dref) <= 1e-5 * np.abs(dref) + 1e-6 * np.abs(old) + 1e-7), name
     np.testing.assert_allclose(np64(job.lam_lim), st.lam_lim, rtol=1e-6, atol=1e-7)
     np.testing.assert_allclose(np64(job.lam_def), st.lam_def, rtol=1e-6, atol=1e-7)
+    # the blocks advanced the counter once and left their completion count at zero
+    assert np64(job.iter_dev).astype(int).tolist() == [3, 0]
     fl = np64(job.flags).astype(int)
     outside = ((st.theta < pb.lo) | (st.theta > pb.hi)).any(axis=1)
     assert np.all(((fl & 4) != 0) == outside)
