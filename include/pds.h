@@ -301,9 +301,10 @@ int svgd_phi(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void*
  * run concurrently with sim_batch_adjoint of the same batch and workspace
  * (nothing may write theta meanwhile).  svgd_bandwidth is meant for that
  * use: when the batch's window kernels leave SIMDs free (fewer than 1020
- * waves), jobs above 256 particles get the median from blocks of one wave
- * each, which fit beside them (larger blocks would wait for their end);
- * the bandwidth is the same. */
+ * waves) and include an arm job with windows of at least 32 steps (long
+ * enough to hide it), jobs above 256 particles get the median from blocks
+ * of one wave each, which fit beside them (larger blocks would wait for
+ * their end); the bandwidth is the same. */
 int svgd_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,
                    void* stream);
 int svgd_phi_at_bandwidth(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, void* ws, size_t ws_bytes,

@@ -383,9 +383,13 @@ long adjoint_waves(const pds_job* h_jobs, int n) {
 
 // concurrent: the bandwidth runs beside the batch's sim_batch_adjoint
 // (svgd_bandwidth).  Larger jobs then take the narrow chain of one-wave
-// blocks when the window kernels leave at least a CU's worth of SIMDs free
-// (their blocks of 256 or 1024 threads would wait for the window kernels'
-// end); the result is the same exact median either way.
+// blocks when the window kernels leave SIMDs free (their blocks of 256 or
+// 1024 threads would wait for the window kernels' end) and run long enough
+// to hide it: the chain takes 0.3 to 0.6 ms, an arm window kernel about
+// 25 us per step of its windows, so the batch must hold an arm job with
+// windows of at least kNarrowMinSteps steps.  The result is the same exact
+// median either way.
+constexpr int kNarrowMinSteps = 32;
 int bandwidth_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs, const std::vector<uint64_t>& off,
                     int mmax, char* w, hipStream_t s, bool concurrent) {
   int rc = PDS_OK;
@@ -393,7 +397,9 @@ int bandwidth_calls(const pds_job* h_jobs, const pds_job* d_jobs, int32_t n_jobs
   auto npairs = [](const pds_job& J) { return (long)J.N * (J.N - 1) / 2; };
   // bandwidth: keys (or a sample of them), one selecting block per job,
   // then the count and final kernels for jobs above kSmallPairs pairs
-  const bool narrow = concurrent && adjoint_waves(h_jobs, n_jobs) <= 1024 - 4;
+  bool long_windows = false;
+  for (int j = 0; j < n_jobs; ++j) long_windows |= is_arm(h_jobs[j]) && h_jobs[j].h >= kNarrowMinSteps;
+  const bool narrow = concurrent && long_windows && adjoint_waves(h_jobs, n_jobs) <= 1024 - 4;
   auto large = [&](const pds_job& J) { return npairs(J) > pds::kSmallPairs; };
   auto lean = [&](const pds_job& J) { return narrow && large(J); };
   auto wide = [&](const pds_job& J) { return !lean(J); };

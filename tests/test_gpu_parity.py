@@ -600,11 +600,13 @@ def test_graph_replays_match_eager(orc):
     assert int(np64(job_b.iter_dev)[0]) == 4
 
 
-@pytest.mark.parametrize("cfg,over", [("c2", dict(N=70, K=3)), ("c3", dict(N=300, K=2, T=100, n_s=2))])
+@pytest.mark.parametrize("cfg,over", [("c2", dict(N=70, K=3)), ("c3", dict(N=300, K=2, T=100, n_s=2)),
+                                      ("c4", dict(N=300, T=300, n_s=6))])
 def test_overlapped_bandwidth_matches_serial_iterations(orc, cfg, over):
     """The bandwidth on a second stream, concurrent with the adjoint, gives
     bitwise the serial iteration's state, with plain launches and in a
-    replayed graph (the second case takes the large-problem median path)."""
+    replayed graph (the second case takes the large-problem median path,
+    the third its narrow one-wave chain beside the arm's window kernel)."""
     from paper_2109_08815_amd import driver
 
     print_case("overlap", cfg, over)
