@@ -91,7 +91,7 @@ constexpr int kSelWavesPerSimd = 5;
 constexpr int kSelBins = 2048;       // bins per selection level (2^11)
 constexpr int kMaxLevels = 8;        // selection levels never exceed 6
 constexpr int kCountTile = 64;       // pairs per count block: 64 x 64
-constexpr int kLastCap = 4096;       // keys the count kernel's last block holds in LDS
+constexpr int kLastCap = 4096;       // candidates the final kernel holds in LDS
 
 struct MedianState {
   uint64_t a, b;    // bracket keys from the sample
