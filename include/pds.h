@@ -185,7 +185,8 @@ typedef struct pds_job {
   int32_t K;          /* trajectories, >= 1 */
   int32_t T;          /* steps per trajectory, T = n_s * h */
   int32_t n_s;        /* shooting windows, >= 1 */
-  int32_t h;          /* steps per window, >= 1 */
+  int32_t h;          /* steps per window, >= 1; N K n_s (2 n_dof + 1) at most
+                       * 2e9 (else PDS_EUNSUPPORTED: flat 32-bit indexes) */
   int32_t combine;    /* PDS_COMBINE_* */
   int32_t lik;        /* PDS_LIK_* */
   int32_t limits;     /* PDS_LIMITS_* */

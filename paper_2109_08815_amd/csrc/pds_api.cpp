@@ -113,7 +113,8 @@ int validate_job(const pds_job& J, int idx, unsigned need) {
     return fail(PDS_EINVAL, "job %d: need N, K, n_s, h >= 1 and T = n_s h (N=%d K=%d T=%d n_s=%d h=%d)", idx, J.N,
                 J.K, J.T, J.n_s, J.h);
   const double units = (double)J.N * J.K * J.n_s;
-  if (units > 2.0e9 || (double)J.N * J.K * (J.n_s) * (2 * J.n_dof) > 2.0e9)
+  // shooting states and multipliers share one flat index in the step kernel
+  if (units > 2.0e9 || (double)J.N * J.K * (J.n_s) * (2 * J.n_dof + 1) > 2.0e9)
     return fail(PDS_EUNSUPPORTED, "job %d: problem too large for 32-bit indexing", idx);
   if (J.N > PDS_MAX_N) return fail(PDS_EUNSUPPORTED, "job %d: N=%d above %d particles", idx, J.N, PDS_MAX_N);
   if (!(J.dt > 0.f) || !std::isfinite(J.dt)) return fail(PDS_EINVAL, "job %d: dt must be > 0", idx);

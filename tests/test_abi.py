@@ -78,6 +78,7 @@ def _job(**kw):
     (dict(combine=5), -1), (dict(N=32769), -2),
     (dict(model=3), -1), (dict(model=3, n_dof=3, M=17, d_x=3), -2), (dict(d_x=3), -1), (dict(limits=2), -1),
     (dict(model=4, n_dof=9, M=11, d_x=1), -1),
+    (dict(N=32768, K=700, n_s=20, h=1, T=20), -2),  # states and multipliers past 32-bit flat indexing
 ])
 def test_invalid_jobs_rejected_on_host(bad, code):
     lib = L.lib()
