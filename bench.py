@@ -371,8 +371,13 @@ def main():
     value = steps_per_iter * args.steps / elapsed
 
     k_ms = float(np.mean(kt)) if len(kt) else float("nan")
-    model = L.model_consts(pb)[0]
-    fwd, rev, transc = L.algorithmic_flops(model, pb.n_dof)
+    model, raw = L.model_consts(pb)
+    if model in (L.PDS_MODEL_ARM, L.PDS_MODEL_ARM_UJOINT, L.PDS_MODEL_ARM_UJOINT_WEIGHTS):
+        # the step the kernels run for this table's kinematic structure
+        fwd, rev, transc, panda = L.arm_algorithmic_flops(model, raw)
+    else:
+        fwd, rev, transc = L.algorithmic_flops(model, pb.n_dof)
+        panda = None
     per_step = fwd + 2 * rev  # forward step + reverse step of each of the two adjoint channels
     achieved = steps_per_iter * per_step / (k_ms / 1e3) / 1e12
     finite = bool(torch.isfinite(job.theta).all().item())
@@ -408,8 +413,9 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": measured_traffic(args.config),
-            "kernel": ("arm_adjoint_kernel<%s>" % {L.PDS_MODEL_ARM: "hinge", L.PDS_MODEL_ARM_UJOINT: "universal joint",
-                                                   L.PDS_MODEL_ARM_UJOINT_WEIGHTS: "universal joint, weights"}[model])
+            "kernel": ("arm_adjoint_kernel<%s>%s" % ({L.PDS_MODEL_ARM: "hinge", L.PDS_MODEL_ARM_UJOINT: "universal joint",
+                                                      L.PDS_MODEL_ARM_UJOINT_WEIGHTS: "universal joint, weights"}[model],
+                                                     ", Panda structure" if panda else ", generic structure"))
             if model in (L.PDS_MODEL_ARM, L.PDS_MODEL_ARM_UJOINT, L.PDS_MODEL_ARM_UJOINT_WEIGHTS) else "planar_adjoint_kernel<%d, %s links>" % (
                 pb.n_dof, "rigid" if model == L.PDS_MODEL_PLANAR_RIGID else "point-mass"),
             "kernel_ms": k_ms,

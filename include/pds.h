@@ -93,7 +93,13 @@ extern "C" {
  * (a, alpha, d, m, c_x, c_y, c_z, I_xx, I_yy, I_zz, kp, kd, qc, amp,
  * omega, phase) with the link inertia diagonal about its centre of mass,
  * then flange_d, b_h, box m, box c[3], box I_xx, I_yy, I_zz, point-mass m,
- * z_m.  Arm jobs need a workspace in every call that rolls out windows. */
+ * z_m.  Arm jobs need a workspace in every call that rolls out windows.
+ * A table with the Panda arm's kinematic structure -- twists (0, -pi/2,
+ * pi/2, pi/2, -pi/2, pi/2, pi/2), each within 2e-7 rad (float rounding),
+ * and a = 0 for joints 0, 1, 2, 5, d = 0 for joints 1, 3, 5, 6 -- runs
+ * kernels compiled for that structure, which take those twists as exact
+ * right angles; any other table runs the generic kernels.  Every value
+ * stays a run-time input in both (all ARM* models). */
 /* PLANAR_RIGID: the planar chain with rigid links, the parameterisation of
  * the paper's physical double pendulum (Sec. IV-B table of estimated
  * parameters): n_dof 1..2 revolute joints about z; link i has mass m_i,
@@ -402,6 +408,15 @@ int32_t pds_version(void);
  * Returns PDS_OK, PDS_EINVAL or PDS_EUNSUPPORTED. */
 int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_step, double* rev_step,
                           double* transcendental);
+
+/* The same for an arm model (PDS_MODEL_ARM*) with the job's raw constants
+ * `consts` (HOST memory, the layout documented with the models): counts
+ * the step functions of the kinematic structure the kernels run for that
+ * table -- the Panda arm's (*panda = 1; the twists and zero offsets of its
+ * modified-DH table, see the ARM model) or the generic one (*panda = 0).
+ * panda may be NULL.  Returns PDS_OK or PDS_EINVAL. */
+int pds_arm_algorithmic_flops(int32_t model, const float* consts, double* fwd_step, double* rev_step,
+                              double* transcendental, int32_t* panda);
 
 /* Kernel timing for benchmarks.  While enabled, every sim_batch_adjoint,
  * loglik_multishoot and traj_metrics call records a pair of HIP events on its

@@ -32,8 +32,8 @@ namespace {
 // address space (written by arm_setup_kernel earlier in the stream, read
 // only afterwards), so their uniform loads are scalar.
 using KConst = const __attribute__((address_space(4))) ArmConst;
-template <int BOX>
-using AMd = ArmMath<float, BOX, KConst>;
+template <int BOX, int DH>
+using AMd = ArmMath<float, BOX, KConst, DH>;
 
 __device__ inline KConst& arm_const_of(char* ws, uint64_t off) {
   return *(KConst*)(ws + off);
@@ -107,7 +107,7 @@ __device__ inline const float* astart_ptr(const pds_job& J, const AUnit& w) {
 
 // Observation term of the state after a step: sum ((obs - x) w)^2 without
 // the constant; with ADJ, the q-adjoint of -1/2 of it is added to qb.
-template <int BOX, bool ADJ>
+template <int BOX, int DH, bool ADJ>
 __device__ __forceinline__ float arm_obs_term(KConst& K, const float* q, const float* obs_row, const float* w,
                                               float* qb) {
   if constexpr (BOX == kHinge) {
@@ -115,7 +115,7 @@ __device__ __forceinline__ float arm_obs_term(KConst& K, const float* q, const f
     if constexpr (ADJ) qb[7] += r * w[0];
     return r * r;
   } else {
-    return AMd<BOX>::template box_obs<ADJ>(K, q, obs_row, w, qb);
+    return AMd<BOX, DH>::template box_obs<ADJ>(K, q, obs_row, w, qb);
   }
 }
 
@@ -126,10 +126,10 @@ __device__ inline double arm_obs_log_norm(const pds_job& J) {
   return c;
 }
 
-template <int BOX>
-__global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                            char* ws, int with_ll) {
-  using AM = AMd<BOX>;
+template <int BOX, int DH>
+__device__ __forceinline__ void arm_forward_body(const JobMap& map, const pds_job* __restrict__ jobs, char* ws,
+                                                 int with_ll) {
+  using AM = AMd<BOX, DH>;
   constexpr int NB = ArmShape<BOX>::NB, DS = ArmShape<BOX>::DS, M = ArmShape<BOX>::M, DX = ArmShape<BOX>::DX;
   const int e = map_entry(map, blockIdx.x);
   const pds_job& J = jobs[map.job[e]];
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   double ll = 0.0;
   for (int s = 0; s < J.h; ++s) {
     AM::step(K, th, target_row(ws, map.ws_off[e], t0 + s), dt, q, qd);
-    if (with_ll) ll -= 0.5 * (double)arm_obs_term<BOX, false>(K, q, obs + (size_t)s * DX, wx, nullptr);
+    if (with_ll) ll -= 0.5 * (double)arm_obs_term<BOX, DH, false>(K, q, obs + (size_t)s * DX, wx, nullptr);
     if (traj)
       for (int d = 0; d < NB; ++d) { traj[s * DS + d] = q[d]; traj[s * DS + NB + d] = qd[d]; }
     if (tobs) {
@@ -193,13 +193,23 @@ __global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pd
   if (fl && J.flags) atomicOr(&J.flags[w.i], fl);
 }
 
+// One kernel per mount; the table's structure (set by the set-up kernel,
+// read as a scalar) selects the compiled variant, uniformly per block.
+template <int BOX>
+__global__ void __launch_bounds__(kWave) arm_forward_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                            char* ws, int with_ll) {
+  if (arm_const_of(ws, map.ws_off[map_entry(map, blockIdx.x)]).dh == kDhPanda)
+    arm_forward_body<BOX, kDhPanda>(map, jobs, ws, with_ll);
+  else
+    arm_forward_body<BOX, kDhGeneric>(map, jobs, ws, with_ll);
+}
+
 // Adjoint kernel: one lane per unit, both adjoint channels in one reverse
 // sweep; only the window start state comes from device memory (see the
 // file comment for the checkpoints).  map.aux[e] = B1 | B2 << 16.
-template <int BOX>
-__global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
-                                                            char* ws) {
-  using AM = AMd<BOX>;
+template <int BOX, int DH>
+__device__ __forceinline__ void arm_adjoint_body(const JobMap& map, const pds_job* __restrict__ jobs, char* ws) {
+  using AM = AMd<BOX, DH>;
   constexpr int NB = ArmShape<BOX>::NB, DS = ArmShape<BOX>::DS, M = ArmShape<BOX>::M, DX = ArmShape<BOX>::DX;
   extern __shared__ float ck[];
   const int e = map_entry(map, blockIdx.x);
@@ -257,7 +267,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
         next2 += B2;
       }
       AM::step(K, th, target_row(ws, map.ws_off[e], t0 + s), dt, q, qd);
-      ll -= 0.5 * (double)arm_obs_term<BOX, false>(K, q, obs + (size_t)s * DX, wx, nullptr);
+      ll -= 0.5 * (double)arm_obs_term<BOX, DH, false>(K, q, obs + (size_t)s * DX, wx, nullptr);
     }
   }
   ll += (double)h * arm_obs_log_norm<BOX>(J);
@@ -329,7 +339,7 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
       };
       // reverse of step t from its state (q, qd) and dynamics tape T
       auto reverse_step = [&](int t, const typename AM::Tape& T) {
-        arm_obs_term<BOX, true>(K, qn, obs + (size_t)t * DX, wx, qb[0]);
+        arm_obs_term<BOX, DH, true>(K, qn, obs + (size_t)t * DX, wx, qb[0]);
         float tb[2][M];
         for (int ch = 0; ch < 2; ++ch)
           for (int m = 0; m < M; ++m) tb[ch][m] = 0.f;
@@ -396,6 +406,15 @@ __global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pd
   }
   const int fl = (bad ? PDS_FLAG_STATE : 0) | (bad_g ? PDS_FLAG_GRAD : 0);
   if (fl && J.flags) atomicOr(&J.flags[w.i], fl);
+}
+
+template <int BOX>
+__global__ void __launch_bounds__(kWave) arm_adjoint_kernel(JobMap map, const pds_job* __restrict__ jobs,
+                                                            char* ws) {
+  if (arm_const_of(ws, map.ws_off[map_entry(map, blockIdx.x)]).dh == kDhPanda)
+    arm_adjoint_body<BOX, kDhPanda>(map, jobs, ws);
+  else
+    arm_adjoint_body<BOX, kDhGeneric>(map, jobs, ws);
 }
 
 }  // namespace
@@ -478,16 +497,10 @@ hipError_t launch_arm_adjoint(const JobMap& map, int mount, const pds_job* d_job
 // which share its primal terms, with the observation seed and the FP64
 // accumulation of the parameter adjoints -- from the same step functions
 // the kernels run, instantiated with the counting scalar.
-template <int BOX>
-static void count_arm(double* fwd, double* rev, double* transc) {
-  using CM = ArmMath<Counted, BOX>;
+template <int BOX, int DH>
+static void count_arm(const ArmConst& K, double* fwd, double* rev, double* transc) {
+  using CM = ArmMath<Counted, BOX, ArmConst, DH>;
   constexpr int NB = ArmShape<BOX>::NB, M = ArmShape<BOX>::M;
-  ArmConst K;
-  std::vector<float> raw(130, 0.5f);  // the longest consts layout
-  raw[0] = 0.f;
-  raw[1] = 0.f;
-  raw[2] = -9.81f;
-  arm_setup(raw.data(), &K, BOX);
   Counted th[11];
   for (int m = 0; m < 11; ++m) th[m] = Counted(0.01f * (m + 1));
   Counted q[NB], qd[NB], qb[2][NB], qdb[2][NB], thb[2][M];
@@ -530,13 +543,28 @@ static void count_arm(double* fwd, double* rev, double* transc) {
   *rev = 0.5 * (rev_both + obs_rev) + M;
 }
 
-void count_arm_flops(int mount, double* fwd, double* rev, double* transc) {
-  if (mount == kUJoint)
-    count_arm<kUJoint>(fwd, rev, transc);
-  else if (mount == kUJointWeights)
-    count_arm<kUJointWeights>(fwd, rev, transc);
+template <int BOX>
+static void count_arm_dh(const ArmConst& K, double* fwd, double* rev, double* transc) {
+  if (K.dh == kDhPanda)
+    count_arm<BOX, kDhPanda>(K, fwd, rev, transc);
   else
-    count_arm<kHinge>(fwd, rev, transc);
+    count_arm<BOX, kDhGeneric>(K, fwd, rev, transc);
+}
+
+int count_arm_flops(int mount, const float* raw, double* fwd, double* rev, double* transc) {
+  std::vector<float> dflt(130, 0.5f);  // the longest consts layout; a generic table
+  dflt[0] = 0.f;
+  dflt[1] = 0.f;
+  dflt[2] = -9.81f;
+  ArmConst K;
+  arm_setup(raw ? raw : dflt.data(), &K, mount);
+  if (mount == kUJoint)
+    count_arm_dh<kUJoint>(K, fwd, rev, transc);
+  else if (mount == kUJointWeights)
+    count_arm_dh<kUJointWeights>(K, fwd, rev, transc);
+  else
+    count_arm_dh<kHinge>(K, fwd, rev, transc);
+  return K.dh;
 }
 
 }  // namespace pds

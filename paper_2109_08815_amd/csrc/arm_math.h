@@ -19,6 +19,8 @@
 // frame, X^T I X, is likewise done as two rotations about axes (R M R^T
 // for the symmetric blocks in 23 flops, 36 for B) and two shifts along axes
 // (A - B R - (B R)^T - R C R, B + R C with R = [r]x and r along one axis).
+// For a table with the Panda arm's structure (ArmDh below) its right-angle
+// twists become signed swaps and its zero offsets vanish at compile time.
 //
 // Reverse step.  With F(q, qd, qdd, theta) = ID(q, qd, qdd; theta) -
 // tau(q, qd, t) = 0 defining qdd, the vector-Jacobian product of forward
@@ -39,6 +41,7 @@
 #pragma once
 
 #include <cmath>
+#include <cstdint>
 #include <type_traits>
 
 #include "sincos.h"
@@ -58,6 +61,19 @@ namespace pds {
 // the box's inertia and the joints' friction known and theta the in-plane
 // positions of two point masses on the box floor (observes the box frame).
 enum ArmBox { kHinge = 0, kUJoint = 1, kUJointWeights = 2 };
+
+// Kinematic structure of the arm's modified-DH table.  Generic: every twist
+// is applied with its cosine and sine and every offset with its value.  The
+// Panda arm's structure (the arm of Sec. IV-C): twists of 0, -90, 90, 90,
+// -90, 90 and 90 degrees, and the offsets a_0, a_1, a_2, a_5 (along x) and
+// d_1, d_3, d_5, d_6 (along z) zero; a right-angle twist is then a signed
+// swap of two axes and a zero offset drops out, both at compile time, while
+// every value in the table stays a run-time input.  The set-up picks the
+// structure from the table itself.
+enum ArmDh { kDhGeneric = 0, kDhPanda = 1 };
+constexpr int kPandaTwist[7] = {0, -1, 1, 1, -1, 1, 1};  // twist / (pi/2)
+constexpr bool kPandaA[7] = {false, false, false, true, true, false, true};
+constexpr bool kPandaD[7] = {true, false, true, false, true, false, false};
 template <int BOX>
 struct ArmShape {
   static constexpr int NB = BOX == kHinge ? 8 : 9;    // bodies = joints
@@ -90,6 +106,7 @@ struct ArmConst {
   float bh;                 // hinge damping (universal joint with weights: first axis)
   float b8;                 // universal joint with weights: damping of the second axis
   float pm_m, pm_z;         // point masses: mass each, height in the box frame
+  int32_t dh;               // ArmDh of the table
 };
 
 // Target of arm joint i's PD controller at `time`: the sinusoid q_d =
@@ -133,6 +150,15 @@ __host__ __device__ inline void arm_setup(const float* raw, ArmConst* K, int mou
     K->b[i].Ic[3] = j[8]; K->b[i].Ic[4] = 0.f; K->b[i].Ic[5] = j[9];
     K->b[i].kp = j[10]; K->b[i].kd = j[11]; K->b[i].qc = j[12];
     K->b[i].amp = j[13]; K->b[i].om = j[14]; K->b[i].ph = j[15];
+  }
+  // the Panda structure: each twist within float rounding of its right
+  // angle, the offsets it has as zeros exactly zero
+  K->dh = kDhPanda;
+  for (int i = 0; i < 7; ++i) {
+    const float* j = raw + 3 + 16 * i;
+    const float tw = 1.5707963267948966f * (float)kPandaTwist[i];
+    if (!(fabsf(j[1] - tw) <= 2e-7f) || (!kPandaA[i] && j[0] != 0.f) || (!kPandaD[i] && j[2] != 0.f))
+      K->dh = kDhGeneric;
   }
   const float* h = raw + 3 + 16 * 7;
   for (int b = 7; b < kArmMaxBodies; ++b) {
@@ -211,7 +237,7 @@ __host__ __device__ PDS_ALWAYS_INLINE void for_bodies_down(F&& f) {
 // KC is the type the model constants are read through: on the device the
 // constant address space, so that their wave-uniform loads become scalar
 // loads into SGPRs instead of vector registers.
-template <class R, int BOX, class KC = ArmConst>
+template <class R, int BOX, class KC = ArmConst, int DH = kDhGeneric>
 struct ArmMath {
   static constexpr int NB = ArmShape<BOX>::NB;
   static constexpr int M = ArmShape<BOX>::M;
@@ -303,19 +329,62 @@ struct ArmMath {
   template <int I>
   __host__ __device__ static constexpr bool massless() { return BOX != kHinge && I == 7; }
 
+  // The table's structure at body I (ArmDh): the twist about x in right
+  // angles (0, +-1; 2: a general twist, its cosine and sine from the
+  // table), and whether the offsets a (along x) and d (along z) enter.
+  // Bodies 7 and 8 have no twist and no a; body 7 has the flange offset d.
+  template <int I>
+  __host__ __device__ static constexpr int twist() {
+    if constexpr (I >= 7) return 0;
+    else if constexpr (DH == kDhPanda) return kPandaTwist[I];
+    else return 2;
+  }
+  template <int I>
+  __host__ __device__ static constexpr bool has_a() {
+    if constexpr (I >= 7) return false;
+    else if constexpr (DH == kDhPanda) return kPandaA[I];
+    else return true;
+  }
+  template <int I>
+  __host__ __device__ static constexpr bool has_d() {
+    if constexpr (I >= 8) return false;
+    else if constexpr (I == 7 || DH != kDhPanda) return true;
+    else return kPandaD[I];
+  }
+  // Body I's twist rotation about x applied to a vector (rot), and its
+  // transpose; a right angle with sign t gives y' = -t z, z' = t y (rot).
+  template <int I>
+  __host__ __device__ static inline V3 twist_rot(const KC& K, V3 p) {
+    constexpr int t = twist<I>();
+    if constexpr (t == 2) return rot<0>(R(K.b[I].ca), R(K.b[I].sa), p);
+    else if constexpr (t == 0) return p;
+    else if constexpr (t == 1) return v3(p.x, -p.z, p.y);
+    else return v3(p.x, p.z, -p.y);
+  }
+  template <int I>
+  __host__ __device__ static inline V3 twist_rotT(const KC& K, V3 p) {
+    constexpr int t = twist<I>();
+    if constexpr (t == 2) return rotT<0>(R(K.b[I].ca), R(K.b[I].sa), p);
+    else if constexpr (t == 0) return p;
+    else if constexpr (t == 1) return v3(p.x, p.z, -p.y);
+    else return v3(p.x, -p.z, p.y);
+  }
+
   // Plucker transform parent -> body I, motion vectors: shift by a along
   // x, rotate by alpha about x, shift by d along z, rotate by q about the
   // joint axis (each a change of coordinates: v - r x w, then R^T).
   template <int I>
   __host__ __device__ static inline SV xm(const KC& K, R cq, R sq, SV m) {
     V3 w = m.a, v = m.l;
-    if constexpr (I < 7) {
-      const R a = K.b[I].ra, ca = K.b[I].ca, sa = K.b[I].sa;
+    if constexpr (has_a<I>()) {
+      const R a = K.b[I].ra;
       v = v3(v.x, v.y + a * w.z, v.z - a * w.y);
-      w = rotT<0>(ca, sa, w);
-      v = rotT<0>(ca, sa, v);
     }
-    if constexpr (I < 8) {
+    if constexpr (I < 7) {
+      w = twist_rotT<I>(K, w);
+      v = twist_rotT<I>(K, v);
+    }
+    if constexpr (has_d<I>()) {
       const R d = K.b[I].rd;
       v = v3(v.x + d * w.y, v.y - d * w.x, v.z);
     }
@@ -326,14 +395,16 @@ struct ArmMath {
   template <int I>
   __host__ __device__ static inline SV xtf(const KC& K, R cq, R sq, SV f) {
     V3 n = rot<axis<I>()>(cq, sq, f.a), g = rot<axis<I>()>(cq, sq, f.l);
-    if constexpr (I < 8) {
+    if constexpr (has_d<I>()) {
       const R d = K.b[I].rd;
       n = v3(n.x - d * g.y, n.y + d * g.x, n.z);
     }
     if constexpr (I < 7) {
-      const R a = K.b[I].ra, ca = K.b[I].ca, sa = K.b[I].sa;
-      n = rot<0>(ca, sa, n);
-      g = rot<0>(ca, sa, g);
+      n = twist_rot<I>(K, n);
+      g = twist_rot<I>(K, g);
+    }
+    if constexpr (has_a<I>()) {
+      const R a = K.b[I].ra;
       n = v3(n.x, n.y - a * g.z, n.z + a * g.y);
     }
     return sv(n, g);
@@ -342,14 +413,16 @@ struct ArmMath {
   template <int I>
   __host__ __device__ static inline SV minv(const KC& K, R cq, R sq, SV m) {
     V3 w = rot<axis<I>()>(cq, sq, m.a), v = rot<axis<I>()>(cq, sq, m.l);
-    if constexpr (I < 8) {
+    if constexpr (has_d<I>()) {
       const R d = K.b[I].rd;
       v = v3(v.x - d * w.y, v.y + d * w.x, v.z);
     }
     if constexpr (I < 7) {
-      const R a = K.b[I].ra, ca = K.b[I].ca, sa = K.b[I].sa;
-      w = rot<0>(ca, sa, w);
-      v = rot<0>(ca, sa, v);
+      w = twist_rot<I>(K, w);
+      v = twist_rot<I>(K, v);
+    }
+    if constexpr (has_a<I>()) {
+      const R a = K.b[I].ra;
       v = v3(v.x, v.y - a * w.z, v.z + a * w.y);
     }
     return sv(w, v);
@@ -393,6 +466,40 @@ struct ArmMath {
       const R bp = B.e[3 * i + P], bq = B.e[3 * i + Q];
       B.e[3 * i + P] = c * bp - s * bq;
       B.e[3 * i + Q] = s * bp + c * bq;
+    }
+  }
+
+  // The same for a right angle with sign S (c = 0, s = S): entries swap
+  // and change sign, no arithmetic.
+  template <int S>
+  __host__ __device__ static inline R sgn(R x) {
+    if constexpr (S > 0) return x; else return -x;
+  }
+  template <int K, int S>
+  __host__ __device__ static inline void rot_sym_r(Sym3& Mx) {
+    constexpr int P = K == 0 ? 1 : (K == 1 ? 2 : 0), Q = K == 0 ? 2 : (K == 1 ? 0 : 1), T = K;
+    const R mpp = Mx.e[si<P, P>], mqq = Mx.e[si<Q, Q>], mpq = Mx.e[si<P, Q>];
+    const R mpt = Mx.e[si<P, T>], mqt = Mx.e[si<Q, T>];
+    Mx.e[si<P, P>] = mqq;
+    Mx.e[si<Q, Q>] = mpp;
+    Mx.e[si<P, Q>] = -mpq;
+    Mx.e[si<P, T>] = sgn<-S>(mqt);
+    Mx.e[si<Q, T>] = sgn<S>(mpt);
+  }
+  template <int K, int S>
+  __host__ __device__ static inline void rot_gen_r(M3& B) {
+    constexpr int P = K == 0 ? 1 : (K == 1 ? 2 : 0), Q = K == 0 ? 2 : (K == 1 ? 0 : 1);
+  #pragma unroll
+    for (int j = 0; j < 3; ++j) {  // rows
+      const R bp = B.e[3 * P + j], bq = B.e[3 * Q + j];
+      B.e[3 * P + j] = sgn<-S>(bq);
+      B.e[3 * Q + j] = sgn<S>(bp);
+    }
+  #pragma unroll
+    for (int i = 0; i < 3; ++i) {  // columns
+      const R bp = B.e[3 * i + P], bq = B.e[3 * i + Q];
+      B.e[3 * i + P] = sgn<-S>(bq);
+      B.e[3 * i + Q] = sgn<S>(bp);
     }
   }
 
@@ -462,14 +569,19 @@ struct ArmMath {
     rot_sym<axis<I>()>(cq, sq, Ia.A);
     rot_gen<axis<I>()>(cq, sq, Ia.B);
     rot_sym<axis<I>()>(cq, sq, Ia.C);
-    if constexpr (I < 8) shift_z(Ia, R(K.b[I].rd));
-    if constexpr (I < 7) {
+    if constexpr (has_d<I>()) shift_z(Ia, R(K.b[I].rd));
+    constexpr int t = twist<I>();
+    if constexpr (t == 2) {
       const R ca = K.b[I].ca, sa = K.b[I].sa;
       rot_sym<0>(ca, sa, Ia.A);
       rot_gen<0>(ca, sa, Ia.B);
       rot_sym<0>(ca, sa, Ia.C);
-      shift_x(Ia, R(K.b[I].ra));
+    } else if constexpr (t != 0) {
+      rot_sym_r<0, t>(Ia.A);
+      rot_gen_r<0, t>(Ia.B);
+      rot_sym_r<0, t>(Ia.C);
     }
+    if constexpr (has_a<I>()) shift_x(Ia, R(K.b[I].ra));
   }
 
   // Rigid-body inertia applied to a motion vector, from (m, c, Ic):
@@ -944,14 +1056,21 @@ struct ArmMath {
       constexpr int i = decltype(Ic)::value;
       constexpr int k = axis<i>();
       keep_consts_in_memory();
-      if constexpr (i < 7) {
-        o = o + R(K.b[i].ra) * Rw[0];
+      if constexpr (has_a<i>()) o = o + R(K.b[i].ra) * Rw[0];
+      constexpr int t = twist<i>();
+      const V3 y = Rw[1], z = Rw[2];
+      if constexpr (t == 2) {
         const R ca = K.b[i].ca, sa = K.b[i].sa;
-        const V3 y = Rw[1], z = Rw[2];
         Rw[1] = ca * y + sa * z;
         Rw[2] = ca * z - sa * y;
+      } else if constexpr (t == 1) {  // ca = 0, sa = 1
+        Rw[1] = z;
+        Rw[2] = -y;
+      } else if constexpr (t == -1) {
+        Rw[1] = -z;
+        Rw[2] = y;
       }
-      if constexpr (i < 8) o = o + R(K.b[i].rd) * Rw[2];
+      if constexpr (has_d<i>()) o = o + R(K.b[i].rd) * Rw[2];
       constexpr int P = k == 0 ? 1 : (k == 1 ? 2 : 0), Q = k == 0 ? 2 : (k == 1 ? 0 : 1);
       const V3 p = Rw[P], qv = Rw[Q];
       Rw[P] = cs[i] * p + sn[i] * qv;

@@ -64,7 +64,8 @@ _lock = threading.Lock()
 _lib = None
 EXPORTS = ("sim_batch_forward", "loglik_multishoot", "sim_batch_adjoint", "svgd_phi", "svgd_step", "svgd_phi_noalloc",
            "svgd_bandwidth", "svgd_phi_at_bandwidth",
-           "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_timing_enable",
+           "pds_workspace_size", "pds_last_error", "pds_version", "pds_algorithmic_flops", "pds_arm_algorithmic_flops",
+           "pds_timing_enable",
            "pds_timing_read", "pds_test_median_shift", "pds_test_adjoint_shape", "pds_job_footprint")
 
 
@@ -92,6 +93,9 @@ def lib():
             L.pds_version.restype = C.c_int32
             L.pds_algorithmic_flops.argtypes = [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
             L.pds_algorithmic_flops.restype = C.c_int
+            L.pds_arm_algorithmic_flops.argtypes = [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                                    C.c_void_p]
+            L.pds_arm_algorithmic_flops.restype = C.c_int
             L.pds_timing_enable.argtypes = [C.c_int32]
             L.pds_timing_enable.restype = C.c_int
             L.pds_timing_read.argtypes = [C.c_void_p, C.c_int32]
@@ -375,6 +379,18 @@ def algorithmic_flops(model: int, n_dof: int):
     rc = lib().pds_algorithmic_flops(int(model), int(n_dof), C.byref(f), C.byref(r), C.byref(t))
     _check(rc, "pds_algorithmic_flops")
     return f.value, r.value, t.value
+
+
+def arm_algorithmic_flops(model: int, consts):
+    """(forward step, reverse step per channel, sin/cos count, Panda
+    structure) for an arm table (host array in the consts layout): the
+    counts of the step functions the kernels run for that table."""
+    raw = np.ascontiguousarray(np.asarray(consts, dtype=np.float32))
+    f, r, t, panda = C.c_double(), C.c_double(), C.c_double(), C.c_int32()
+    rc = lib().pds_arm_algorithmic_flops(int(model), raw.ctypes.data_as(C.c_void_p), C.byref(f), C.byref(r),
+                                         C.byref(t), C.byref(panda))
+    _check(rc, "pds_arm_algorithmic_flops")
+    return f.value, r.value, t.value, bool(panda.value)
 
 
 def timing_enable(on: bool = True, reps: int = 1):

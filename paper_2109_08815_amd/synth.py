@@ -164,7 +164,9 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
     """Build a seeded problem.  ``over`` overrides N, K, T, n_s, dt, sigma_obs,
     sigma_def, c, combine, lik, limits, n_dof (planar families), full_state (planar
     families: observe (q, qd) instead of q), damped, gravity_x (point-mass
-    planar families: joint damping, a gravity component along x), M (toy)."""
+    planar families: joint damping, a gravity component along x), M (toy),
+    generic_dh (arm families: a table off the Panda arm's kinematic
+    structure)."""
     base = dict(CONFIGS.get(config, {}))
     if config == "toy":
         base = dict(family="toy", N=256, K=1, T=50, n_s=1, dt=0.1, sigma_obs=0.5)
@@ -287,6 +289,12 @@ def make_problem(config: str = "c2", seed: int | None = None, **over) -> Problem
     # that family takes smaller steps to keep them positive.
     lr_frac = 1e-3 if fam == "rigid" else 1e-2
     particles = sobol_particles(N, lo, hi)
+    if arm is not None and over.get("generic_dh", False):
+        # a table off the Panda arm's kinematic structure: one twist off its
+        # right angle, two offsets that structure has as zeros
+        arm["dh_alpha"] = arm["dh_alpha"] + np.array([0.0, 0.25, 0.0, 0.0, 0.0, 0.0, 0.0])
+        arm["dh_a"] = arm["dh_a"] + np.array([0.0, 0.04, 0.0, 0.0, 0.0, 0.0, 0.0])
+        arm["dh_d"] = arm["dh_d"] + np.array([0.0, 0.0, 0.0, 0.06, 0.0, 0.0, 0.0])
     d_s = 2 * n
     u = np.ones(d_s)
     lr_S = np.concatenate([np.full(n, 1e-3), np.full(n, 1e-2)])

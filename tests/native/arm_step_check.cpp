@@ -1,5 +1,7 @@
 // Host check of the arm's step functions in FP64 (built with g++ and run by
-// tests/test_arm_step_host.py).  Reads a model (mount, raw constants) and
+// tests/test_arm_step_host.py), compiled for the kinematic structure the
+// set-up finds in the table (Panda or generic; printed first).  Reads a
+// model (mount, raw constants) and
 // states from stdin; prints, per state, the joint accelerations of the
 // library's Articulated Body Algorithm and (universal-joint mounts) the
 // observed box-frame points, for comparison with the oracle; then checks
@@ -14,9 +16,9 @@
 
 using namespace pds;
 
-template <int BOX>
+template <int BOX, int DH>
 int run(const std::vector<float>& raw) {
-  using AM = ArmMath<double, BOX>;
+  using AM = ArmMath<double, BOX, ArmConst, DH>;
   constexpr int NB = ArmShape<BOX>::NB, M = ArmShape<BOX>::M;
   ArmConst K;
   arm_setup(raw.data(), &K, BOX);
@@ -122,7 +124,16 @@ int main() {
     if (scanf("%lf", &v) != 1) return 2;
     raw[i] = (float)v;
   }
-  if (mount == kUJoint) return run<kUJoint>(raw);
-  if (mount == kUJointWeights) return run<kUJointWeights>(raw);
-  return run<kHinge>(raw);
+  // the structure the kernels would run for this table
+  ArmConst K;
+  arm_setup(raw.data(), &K, mount);
+  printf("structure %d\n", K.dh);
+  if (K.dh == kDhPanda) {
+    if (mount == kUJoint) return run<kUJoint, kDhPanda>(raw);
+    if (mount == kUJointWeights) return run<kUJointWeights, kDhPanda>(raw);
+    return run<kHinge, kDhPanda>(raw);
+  }
+  if (mount == kUJoint) return run<kUJoint, kDhGeneric>(raw);
+  if (mount == kUJointWeights) return run<kUJointWeights, kDhGeneric>(raw);
+  return run<kHinge, kDhGeneric>(raw);
 }

@@ -152,6 +152,34 @@ def test_algorithmic_flop_counts():
         assert rf > planar[n - 1][0] and rr > planar[n - 1][1]
 
 
+def test_arm_flop_counts_follow_the_tables_structure():
+    """An arm table with the Panda arm's kinematic structure (the synthetic
+    ones) is counted with that structure's step functions -- fewer FLOPs,
+    the same sin/cos -- and one off it (a general twist, two more offsets)
+    with the generic ones, which pds_algorithmic_flops also counts."""
+    from paper_2109_08815_amd import synth
+    for cfg, nb in (("c4", 8), ("box1", 9), ("box2", 9)):
+        model, raw = L.model_consts(synth.make_problem(cfg, N=4, K=1, T=10, n_s=1))
+        f, r, t, panda = L.arm_algorithmic_flops(model, raw)
+        assert panda
+        g = L.algorithmic_flops(model, nb)
+        assert f < g[0] and r < g[1] and t == g[2]
+        model, raw = L.model_consts(synth.make_problem(cfg, N=4, K=1, T=10, n_s=1, generic_dh=True))
+        assert L.arm_algorithmic_flops(model, raw) == (*g, False)
+    # within float rounding of the right angles still counts as the Panda structure
+    model, raw = L.model_consts(synth.make_problem("c4", N=4, K=1, T=10, n_s=1))
+    raw = np.asarray(raw, np.float32)
+    raw[3 + 16 * 1 + 1] = np.nextafter(raw[3 + 16 * 1 + 1], np.float32(0))
+    assert L.arm_algorithmic_flops(model, raw)[3]
+    raw[3 + 16 * 1 + 1] -= np.float32(1e-5)
+    assert not L.arm_algorithmic_flops(model, raw)[3]
+    lib = L.lib()
+    d = C.c_double()
+    assert lib.pds_arm_algorithmic_flops(L.PDS_MODEL_PLANAR, raw.ctypes.data_as(C.c_void_p), C.byref(d), C.byref(d),
+                                         C.byref(d), None) == -1
+    assert lib.pds_arm_algorithmic_flops(model, None, C.byref(d), C.byref(d), C.byref(d), None) == -1
+
+
 def test_metrics_arguments_rejected_on_host():
     """pds_traj_metrics validates before queueing anything (the fake device
     addresses are never dereferenced)."""

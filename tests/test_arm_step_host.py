@@ -34,11 +34,18 @@ def checker(tmp_path_factory):
 MOUNTS = {"c4": 0, "box1": 1, "box2": 2}
 
 
+@pytest.mark.parametrize("generic", [False, True])
 @pytest.mark.parametrize("cfg", ["c4", "box1", "box2"])
-def test_arm_step_against_oracle(orc, checker, cfg):
-    pb = f32_problem(synth.make_problem(cfg, N=16, K=1, T=30, n_s=1))
+def test_arm_step_against_oracle(orc, checker, cfg, generic):
+    """Both kinematic structures: the synthetic tables have the Panda arm's
+    (its step functions take the twists as exact right angles, so the
+    oracle gets exact multiples of pi/2 where the float table holds their
+    rounding), and a table off that structure runs the generic ones."""
+    pb = f32_problem(synth.make_problem(cfg, N=16, K=1, T=30, n_s=1, generic_dh=generic))
     _, raw = L.model_consts(pb)
     raw = np.asarray(raw, np.float32).astype(np.float64)
+    if not generic:
+        pb.arm["dh_alpha"] = np.round(pb.arm["dh_alpha"] / (np.pi / 2)) * (np.pi / 2)
     rng = np.random.default_rng(21)
     n = pb.n_dof
     cases = []
@@ -54,6 +61,7 @@ def test_arm_step_against_oracle(orc, checker, cfg):
     r = subprocess.run([checker], input="\n".join(lines) + "\n", capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     out = r.stdout.splitlines()
+    assert out[0] == "structure %d" % (0 if generic else 1)
     qdd = [np.array(l.split()[1:], float) for l in out if l.startswith("qdd")]
     obs = [np.array(l.split()[1:], float) for l in out if l.startswith("frame ")]
     worst = 0.0
@@ -62,16 +70,21 @@ def test_arm_step_against_oracle(orc, checker, cfg):
         ref = orc.aba(pb, th, q, qd, tau)
         worst = max(worst, np.abs(a - ref).max() / (1 + np.abs(ref).max()))
     print("ABA vs oracle: worst %.3e" % worst)
-    assert worst < 1e-10
+    # A general twist enters through its float cosine and sine (within 6e-8
+    # of the oracle's FP64 ones); a right angle or a twist within float
+    # rounding of one enters exactly.  A mistake in the algebra is O(1).
+    assert worst < (1e-6 if generic else 1e-10)
     if obs:
         wo = 0.0
         for (th, q, qd, t), x in zip(cases, obs):
             ref = orc.observe(pb, th, np.concatenate([q, qd])[None])[0]
             wo = max(wo, np.abs(x - ref).max())
         print("box frame vs oracle: worst %.3e" % wo)
-        assert wo < 1e-12
+        assert wo < (1e-6 if generic else 1e-12)
     rev = float([l for l in out if l.startswith("reverse")][0].split()[1])
     ob = float([l for l in out if l.startswith("obs_adjoint")][0].split()[1])
     print("reverse vs central differences %.3e, observation adjoint %.3e" % (rev, ob))
     assert rev < 1e-8
-    assert ob < 1e-7
+    # the observation adjoint is the geometric Jacobian of a rigid chain; a
+    # general twist's float cosine and sine are a rotation to within 6e-8
+    assert ob < (1e-6 if generic else 1e-7)

@@ -707,6 +707,7 @@ ARM_CASES = [
     dict(N=33, K=2, T=60, n_s=3),       # two trajectories, short windows (whole window in LDS)
     dict(N=24, K=2, T=60, n_s=3, lik=synth.LIK_DEFECT),
     dict(N=20, K=2, T=60, n_s=2, combine=synth.COMBINE_PROD),
+    dict(N=40, K=1, T=100, n_s=2, generic_dh=True),  # a table off the Panda structure: the generic kernels
 ]
 
 
@@ -735,6 +736,7 @@ BOX_CASES = [
     dict(N=70, K=1, T=96, n_s=2),       # two windows of 48 steps at dt = 1/240
     dict(N=33, K=2, T=60, n_s=3),
     dict(N=24, K=1, T=60, n_s=3, lik=synth.LIK_DEFECT),
+    dict(N=20, K=1, T=96, n_s=2, generic_dh=True),
 ]
 
 
@@ -784,7 +786,7 @@ def test_box_universal_joint_adjoint_gradients(orc, cfg, over):
 
 
 @pytest.mark.parametrize("cfg,over", [("c2", dict(N=16, K=2, T=40, n_s=2)), ("c3", dict(N=16, K=1, T=60, n_s=3)),
-                                      ("c4", dict(N=8, T=60, n_s=2)),
+                                      ("c4", dict(N=8, T=60, n_s=2)), ("c4", dict(N=8, T=60, n_s=2, generic_dh=True)),
                                       ("c2", dict(N=16, K=2, T=60, n_s=3, lik=synth.LIK_DEFECT)),
                                       ("c4", dict(N=8, K=2, T=60, n_s=2, lik=synth.LIK_DEFECT)),
                                       ("rigid2", dict(N=16, K=2, T=40, n_s=2)),
