@@ -97,7 +97,8 @@ struct ArmBody {
   float Ic[6];   // inertia about the centre of mass: xx, xy, xz, yy, yz, zz
   float Ar[6];   // angular block of the body's spatial inertia, Ic + m (|c|^2 1 - c c^T)
   float kp, kd, qc, amp, om, ph;  // PD gains and the sinusoidal target (arm joints)
-  float pad[6];
+  float Id[3];   // the diagonal of Ic (xx, yy, zz), contiguous
+  float pad[3];
 };
 static_assert(sizeof(ArmBody) == 128, "one 128-byte record per body");
 struct ArmConst {
@@ -192,6 +193,9 @@ __host__ __device__ inline void arm_setup(const float* raw, ArmConst* K, int mou
     K->pm_z = h[10];
   }
   for (int b = 0; b < kArmMaxBodies; ++b) {
+    K->b[b].Id[0] = K->b[b].Ic[0];
+    K->b[b].Id[1] = K->b[b].Ic[3];
+    K->b[b].Id[2] = K->b[b].Ic[5];
     const float m = K->b[b].m, cx = K->b[b].c[0], cy = K->b[b].c[1], cz = K->b[b].c[2];
     const float cc = cx * cx + cy * cy + cz * cz;
     K->b[b].Ar[0] = K->b[b].Ic[0] + m * (cc - cx * cx);
@@ -469,6 +473,36 @@ struct ArmMath {
     }
   }
 
+  // The same when row and column K vanish (the angular blocks of an
+  // articulated inertia after its joint's update): P, Q entries only.
+  template <int K>
+  __host__ __device__ static inline void rot_sym_null(R c, R s, Sym3& Mx) {
+    constexpr int P = K == 0 ? 1 : (K == 1 ? 2 : 0), Q = K == 0 ? 2 : (K == 1 ? 0 : 1);
+    const R mpp = Mx.e[si<P, P>], mqq = Mx.e[si<Q, Q>], mpq = Mx.e[si<P, Q>];
+    const R cc = c * c, ss = s * s, cs = c * s;
+    const R two_cs_pq = (cs + cs) * mpq;
+    Mx.e[si<P, P>] = cc * mpp - two_cs_pq + ss * mqq;
+    Mx.e[si<Q, Q>] = ss * mpp + two_cs_pq + cc * mqq;
+    Mx.e[si<P, Q>] = cs * (mpp - mqq) + (cc - ss) * mpq;
+  }
+  template <int K>
+  __host__ __device__ static inline void rot_gen_null(R c, R s, M3& B) {  // row K of B zero
+    constexpr int P = K == 0 ? 1 : (K == 1 ? 2 : 0), Q = K == 0 ? 2 : (K == 1 ? 0 : 1);
+  #pragma unroll
+    for (int j = 0; j < 3; ++j) {  // rows
+      const R bp = B.e[3 * P + j], bq = B.e[3 * Q + j];
+      B.e[3 * P + j] = c * bp - s * bq;
+      B.e[3 * Q + j] = s * bp + c * bq;
+    }
+  #pragma unroll
+    for (int i = 0; i < 3; ++i) {  // columns of rows P and Q
+      if (i == K) continue;
+      const R bp = B.e[3 * i + P], bq = B.e[3 * i + Q];
+      B.e[3 * i + P] = c * bp - s * bq;
+      B.e[3 * i + Q] = s * bp + c * bq;
+    }
+  }
+
   // The same for a right angle with sign S (c = 0, s = S): entries swap
   // and change sign, no arithmetic.
   template <int S>
@@ -522,19 +556,42 @@ struct ArmMath {
                       B[2] * w.x + B[5] * w.y + B[8] * w.z + C[2] * v.x + C[4] * v.y + C[5] * v.z);
     return sv(top, bot);
   }
+  // sym6_mul for an articulated inertia whose angular row and column K
+  // vanish (A's row K, B's row K) times a vector whose K components vanish.
+  template <int K>
+  __host__ __device__ static inline SV sym6_mul_null(const Sym6& I, SV x) {
+    constexpr int P = K == 0 ? 1 : (K == 1 ? 2 : 0), Q = K == 0 ? 2 : (K == 1 ? 0 : 1);
+    const R* A = I.A.e;
+    const R* B = I.B.e;
+    const R* C = I.C.e;
+    const R a[3] = {x.a.x, x.a.y, x.a.z}, l[3] = {x.l.x, x.l.y, x.l.z};
+    R top[3], bot[3];
+    top[K] = R(0.f);
+    top[P] = A[si<P, P>] * a[P] + A[si<P, Q>] * a[Q] + B[3 * P + P] * l[P] + B[3 * P + Q] * l[Q];
+    top[Q] = A[si<P, Q>] * a[P] + A[si<Q, Q>] * a[Q] + B[3 * Q + P] * l[P] + B[3 * Q + Q] * l[Q];
+    bot[0] = B[3 * P + 0] * a[P] + B[3 * Q + 0] * a[Q] + C[si<0, P>] * l[P] + C[si<0, Q>] * l[Q];
+    bot[1] = B[3 * P + 1] * a[P] + B[3 * Q + 1] * a[Q] + C[si<1, P>] * l[P] + C[si<1, Q>] * l[Q];
+    bot[2] = B[3 * P + 2] * a[P] + B[3 * Q + 2] * a[Q] + C[si<2, P>] * l[P] + C[si<2, Q>] * l[Q];
+    return sv(v3(top[0], top[1], top[2]), v3(bot[0], bot[1], bot[2]));
+  }
   // X^T I X for a shift of the frame by d along z (r = d e_z, R = [r]x):
   // A - B R - (B R)^T - R C R and B + R C (C unchanged).
+  // (NULLZ: A's row z and B's row z vanish and stay zero.)
+  template <bool NULLZ = false>
   __host__ __device__ static inline void shift_z(Sym6& I, R d) {
     R* A = I.A.e;
     R* B = I.B.e;
     const R* C = I.C.e;
     const R dd = d * d;
-    const R b00 = B[0], b01 = B[1], b10 = B[3], b11 = B[4], b20 = B[6], b21 = B[7];
+    const R b00 = B[0], b01 = B[1], b10 = B[3], b11 = B[4];
     A[0] = A[0] - (d + d) * b01 + dd * C[3];
     A[1] = A[1] + d * (b00 - b11) - dd * C[1];
-    A[2] = A[2] - d * b21;
     A[3] = A[3] + (d + d) * b10 + dd * C[0];
-    A[4] = A[4] + d * b20;
+    if constexpr (!NULLZ) {
+      const R b20 = B[6], b21 = B[7];
+      A[2] = A[2] - d * b21;
+      A[4] = A[4] + d * b20;
+    }
     // B += R C: row 0 -= d C[1, :], row 1 += d C[0, :]
     B[0] = b00 - d * C[1];
     B[1] = b01 - d * C[3];
@@ -563,13 +620,16 @@ struct ArmMath {
     B[7] = b21 + a * C[3];
     B[8] = b22 + a * C[4];
   }
-  // Articulated inertia of body I seen from its parent, X^T Ia X.
+  // Articulated inertia of body I seen from its parent, X^T Ia X, for Ia
+  // after the joint's update (its angular row and column along the joint
+  // axis zero).
   template <int I>
   __host__ __device__ static inline void congruence(const KC& K, R cq, R sq, Sym6& Ia) {
-    rot_sym<axis<I>()>(cq, sq, Ia.A);
-    rot_gen<axis<I>()>(cq, sq, Ia.B);
-    rot_sym<axis<I>()>(cq, sq, Ia.C);
-    if constexpr (has_d<I>()) shift_z(Ia, R(K.b[I].rd));
+    constexpr int k = axis<I>();
+    rot_sym_null<k>(cq, sq, Ia.A);
+    rot_gen_null<k>(cq, sq, Ia.B);
+    rot_sym<k>(cq, sq, Ia.C);
+    if constexpr (has_d<I>()) shift_z<k == 2>(Ia, R(K.b[I].rd));
     constexpr int t = twist<I>();
     if constexpr (t == 2) {
       const R ca = K.b[I].ca, sa = K.b[I].sa;
@@ -586,11 +646,16 @@ struct ArmMath {
 
   // Rigid-body inertia applied to a motion vector, from (m, c, Ic):
   // I [w; v] = [Ic w + c x p; p] with p = m (v - c x w).
-  template <class T>
+  // (DIAG: Ic is diagonal and holds its xx, yy, zz only.)
+  template <bool DIAG = false, class T>
   __host__ __device__ static inline SV rbi_mul(R m, V3 c, const T* Ic, SV x) {
     const V3 p = m * (x.l - cross(c, x.a));
-    const V3 Iw = v3(Ic[0] * x.a.x + Ic[1] * x.a.y + Ic[2] * x.a.z, Ic[1] * x.a.x + Ic[3] * x.a.y + Ic[4] * x.a.z,
-                     Ic[2] * x.a.x + Ic[4] * x.a.y + Ic[5] * x.a.z);
+    V3 Iw;
+    if constexpr (DIAG)
+      Iw = v3(R(Ic[0]) * x.a.x, R(Ic[1]) * x.a.y, R(Ic[2]) * x.a.z);
+    else
+      Iw = v3(Ic[0] * x.a.x + Ic[1] * x.a.y + Ic[2] * x.a.z, Ic[1] * x.a.x + Ic[3] * x.a.y + Ic[4] * x.a.z,
+              Ic[2] * x.a.x + Ic[4] * x.a.y + Ic[5] * x.a.z);
     return sv(Iw + cross(c, p), p);
   }
   // Point mass m at c: I [w; v] = [c x p; p], p = m (v - c x w).
@@ -677,7 +742,13 @@ struct ArmMath {
       box_from_theta(th, &c, Ic);
       r = rbi_mul(R(K.b[I].m), c, Ic, x);
     } else {
-      r = rbi_mul(R(K.b[I].m), v3(K.b[I].c[0], K.b[I].c[1], K.b[I].c[2]), K.b[I].Ic, x);
+      // the arm links' and the hinged box's inertias about their centres
+      // of mass are diagonal by the constants' layout
+      constexpr bool diag = I < 7 || (BOX == kHinge && I == 7);
+      if constexpr (diag)
+        r = rbi_mul<true>(R(K.b[I].m), v3(K.b[I].c[0], K.b[I].c[1], K.b[I].c[2]), K.b[I].Id, x);
+      else
+        r = rbi_mul(R(K.b[I].m), v3(K.b[I].c[0], K.b[I].c[1], K.b[I].c[2]), K.b[I].Ic, x);
     }
     if constexpr (PM && I == BOXB) {
       const R pm = R(K.pm_m), z = R(K.pm_z);
@@ -780,21 +851,33 @@ struct ArmMath {
       T.U[i] = U;
       T.invD[i] = invD;
       if constexpr (i > 0) {
+        // Ia = IA - U U^T / D.  Its angular row and column k vanish (Ia S =
+        // U - U D / D = 0): they are set to zero instead of computed, and
+        // the products below skip them.
+        constexpr int P = k == 0 ? 1 : (k == 1 ? 2 : 0), Q = k == 0 ? 2 : (k == 1 ? 0 : 1);
+        constexpr int lo = P < Q ? P : Q, hi = P < Q ? Q : P;
         const V3 wa = invD * U.a, wl = invD * U.l;
+        const R wa3[3] = {wa.x, wa.y, wa.z}, ua3[3] = {U.a.x, U.a.y, U.a.z};
+        const R wl3[3] = {wl.x, wl.y, wl.z}, ul3[3] = {U.l.x, U.l.y, U.l.z};
         Sym6& Ia = IA;
-        Ia.A.e[0] = Ia.A.e[0] - wa.x * U.a.x; Ia.A.e[1] = Ia.A.e[1] - wa.x * U.a.y;
-        Ia.A.e[2] = Ia.A.e[2] - wa.x * U.a.z; Ia.A.e[3] = Ia.A.e[3] - wa.y * U.a.y;
-        Ia.A.e[4] = Ia.A.e[4] - wa.y * U.a.z; Ia.A.e[5] = Ia.A.e[5] - wa.z * U.a.z;
-        Ia.C.e[0] = Ia.C.e[0] - wl.x * U.l.x; Ia.C.e[1] = Ia.C.e[1] - wl.x * U.l.y;
-        Ia.C.e[2] = Ia.C.e[2] - wl.x * U.l.z; Ia.C.e[3] = Ia.C.e[3] - wl.y * U.l.y;
-        Ia.C.e[4] = Ia.C.e[4] - wl.y * U.l.z; Ia.C.e[5] = Ia.C.e[5] - wl.z * U.l.z;
-        const R wa3[3] = {wa.x, wa.y, wa.z}, ul3[3] = {U.l.x, U.l.y, U.l.z};
+        Ia.A.e[si<P, P>] = Ia.A.e[si<P, P>] - wa3[P] * ua3[P];
+        Ia.A.e[si<Q, Q>] = Ia.A.e[si<Q, Q>] - wa3[Q] * ua3[Q];
+        Ia.A.e[si<lo, hi>] = Ia.A.e[si<lo, hi>] - wa3[lo] * ua3[hi];
+        Ia.A.e[si<k, k>] = Ia.A.e[si<P, k>] = Ia.A.e[si<Q, k>] = R(0.f);
   #pragma unroll
         for (int r = 0; r < 3; ++r)
   #pragma unroll
-          for (int c = 0; c < 3; ++c) Ia.B.e[3 * r + c] = Ia.B.e[3 * r + c] - wa3[r] * ul3[c];
+          for (int c = r; c < 3; ++c) {
+            const int e = r == 0 ? c : (r == 1 ? 2 + c : 5);
+            Ia.C.e[e] = Ia.C.e[e] - wl3[r] * ul3[c];
+          }
+  #pragma unroll
+        for (int r = 0; r < 3; ++r)
+  #pragma unroll
+          for (int c = 0; c < 3; ++c)
+            Ia.B.e[3 * r + c] = r == k ? R(0.f) : Ia.B.e[3 * r + c] - wa3[r] * ul3[c];
         const SV ci = crmS<k>(vb[i], qd[i]);
-        const SV pa = pA + sym6_mul(Ia, ci) + (u[i] * invD) * U;
+        const SV pa = pA + sym6_mul_null<k>(Ia, ci) + (u[i] * invD) * U;
         congruence<i>(K, T.cs[i], T.sn[i], Ia);
         IAc = Ia;
         pAc = xtf<i>(K, T.cs[i], T.sn[i], pa);
