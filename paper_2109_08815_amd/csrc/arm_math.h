@@ -275,18 +275,33 @@ struct ArmMath {
   __host__ __device__ static inline void add_along(V3& v, R s) {  // v += s e_K
     if constexpr (K == 0) v.x = v.x + s; else if constexpr (K == 1) v.y = v.y + s; else v.z = v.z + s;
   }
-  // e_K x v and v x (s e_K)
-  template <int K>
-  __host__ __device__ static inline V3 ex(V3 v) {
-    if constexpr (K == 0) return v3(R(0.f), -v.z, v.y);
-    else if constexpr (K == 1) return v3(v.z, R(0.f), -v.x);
-    else return v3(-v.y, v.x, R(0.f));
-  }
+  // v x (s e_K)
   template <int K>
   __host__ __device__ static inline V3 xe(V3 v, R s) {
     if constexpr (K == 0) return v3(R(0.f), s * v.z, -(s * v.y));
     else if constexpr (K == 1) return v3(-(s * v.z), R(0.f), s * v.x);
     else return v3(s * v.y, -(s * v.x), R(0.f));
+  }
+
+  // Products with e_K x . without the component that vanishes: x . (e_K x
+  // y), v += s (e_K x m), and a += v x (s e_K).
+  template <int K>
+  __host__ __device__ static inline R dot_ex(V3 x, V3 y) {
+    if constexpr (K == 0) return x.z * y.y - x.y * y.z;
+    else if constexpr (K == 1) return x.x * y.z - x.z * y.x;
+    else return x.y * y.x - x.x * y.y;
+  }
+  template <int K>
+  __host__ __device__ static inline void add_ex(V3& v, R s, V3 m) {
+    if constexpr (K == 0) { v.y = v.y - s * m.z; v.z = v.z + s * m.y; }
+    else if constexpr (K == 1) { v.x = v.x + s * m.z; v.z = v.z - s * m.x; }
+    else { v.x = v.x - s * m.y; v.y = v.y + s * m.x; }
+  }
+  template <int K>
+  __host__ __device__ static inline void add_xe(V3& a, V3 v, R s) {
+    if constexpr (K == 0) { a.y = a.y + s * v.z; a.z = a.z - s * v.y; }
+    else if constexpr (K == 1) { a.x = a.x - s * v.z; a.z = a.z + s * v.x; }
+    else { a.x = a.x + s * v.y; a.y = a.y - s * v.x; }
   }
 
   // Rotation by an angle (c = cos, s = sin) about coordinate axis K applied
@@ -319,11 +334,18 @@ struct ArmMath {
   // v x m  and  v x* f
   __host__ __device__ static inline SV crm(SV v, SV m) { return sv(cross(v.a, m.a), cross(v.a, m.l) + cross(v.l, m.a)); }
   __host__ __device__ static inline SV crf(SV v, SV f) { return sv(cross(v.a, f.a) + cross(v.l, f.l), cross(v.a, f.l)); }
-  // with v = (e_K; 0): e_K x m, e_K x* f (the same map), and v x (s e_K; 0)
-  template <int K>
-  __host__ __device__ static inline SV crS(SV m) { return sv(ex<K>(m.a), ex<K>(m.l)); }
+  // with S = (e_K; 0): v x (s S)
   template <int K>
   __host__ __device__ static inline SV crmS(SV v, R s) { return sv(xe<K>(v.a, s), xe<K>(v.l, s)); }
+  // x . (S x* y) (S x* is S x on motion and force vectors alike) and
+  // m += v x (s S), skipping the vanishing terms
+  template <int K>
+  __host__ __device__ static inline R sdot_crS(SV x, SV y) { return dot_ex<K>(x.a, y.a) + dot_ex<K>(x.l, y.l); }
+  template <int K>
+  __host__ __device__ static inline void add_crmS(SV& m, SV v, R s) {
+    add_xe<K>(m.a, v.a, s);
+    add_xe<K>(m.l, v.l, s);
+  }
 
   // Joint axis of body I: arm joints about z, the hinge (or ring) about x,
   // the universal joint's box about y.
@@ -837,10 +859,15 @@ struct ArmMath {
         const SV h = body_mul<i>(K, th, vb[i]);
         pA = crf(vb[i], h);
         if constexpr (i < NB - 1) {
+          // a body's own B has a zero diagonal and its C is m times the
+          // identity (body_inertia): those entries take the child's alone
   #pragma unroll
-          for (int e = 0; e < 6; ++e) { IA.A.e[e] = IA.A.e[e] + IAc.A.e[e]; IA.C.e[e] = IA.C.e[e] + IAc.C.e[e]; }
+          for (int e = 0; e < 6; ++e) {
+            IA.A.e[e] = IA.A.e[e] + IAc.A.e[e];
+            IA.C.e[e] = (e == 1 || e == 2 || e == 4) ? IAc.C.e[e] : IA.C.e[e] + IAc.C.e[e];
+          }
   #pragma unroll
-          for (int e = 0; e < 9; ++e) IA.B.e[e] = IA.B.e[e] + IAc.B.e[e];
+          for (int e = 0; e < 9; ++e) IA.B.e[e] = (e % 4 == 0) ? IAc.B.e[e] : IA.B.e[e] + IAc.B.e[e];
           pA = pA + pAc;
         }
       }
@@ -889,7 +916,7 @@ struct ArmMath {
       constexpr int k = axis<i>();
       keep_consts_in_memory();
       SV a1 = xm<i>(K, T.cs[i], T.sn[i], ap);
-      if constexpr (i > 0) a1 = a1 + crmS<k>(vb[i], qd[i]);
+      if constexpr (i > 0) add_crmS<k>(a1, vb[i], qd[i]);
       const R qdd = (u[i] - sdot(T.U[i], a1)) * T.invD[i];
       T.qdd[i] = qdd;
       add_along<k>(a1.a, qdd);
@@ -1023,15 +1050,12 @@ struct ArmMath {
         ft = body_mul<i>(K, th, a) + crf(v, h);
         if constexpr (i < NB - 1) ft = ft + ftc;
       }
-      const SV ci = crmS<k>(v, qd[i]);
       // X_i a_{i-1} and X_i v_{i-1}, read off this body's own terms
-      SV ya = a - ci;
+      SV ya = a;
+      add_crmS<k>(ya, v, -qd[i]);
       add_along<k>(ya.a, -T.qdd[i]);
-      const SV Sya = crS<k>(ya);
       SV yv = v;
       add_along<k>(yv.a, -qd[i]);
-      const SV Syv = crS<k>(yv);
-      const SV Sft = crS<k>(ft);
   #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const SV fb = ftb[c];
@@ -1090,7 +1114,7 @@ struct ArmMath {
         // = (X_i ftb_{i-1}) . (S x* ft_i)
         SV xf = fb;
         add_along<k>(xf.a, lam[c][i]);
-        if constexpr (i > 0) qb[c][i] = qb[c][i] + sdot(xf, Sft);
+        if constexpr (i > 0) qb[c][i] = qb[c][i] + sdot_crS<k>(xf, ft);
         // f = I a + v x* (I v):  a_bar += I fb;  v_bar += -fb x* h - I (v x fb)
         if constexpr (!massless<i>()) {
           const SV Ifb = body_mul<i>(K, th, fb);
@@ -1104,12 +1128,13 @@ struct ArmMath {
           }
         }
         // a_i = X_i a_{i-1} + v_i x (S qd_i) + S qdd_i (qdd held fixed)
-        vbar[c] = vbar[c] + qd[i] * crS<k>(abar[c]);
+        add_ex<k>(vbar[c].a, qd[i], abar[c].a);
+        add_ex<k>(vbar[c].l, qd[i], abar[c].l);
         qdb[c][i] = qdb[c][i] - comp<k>(crf(v, abar[c]).a) + comp<k>(vbar[c].a);
         // d/dq (abar . X a_prev) = -abar . (S x X a_prev), likewise for v
-        qb[c][i] = qb[c][i] - sdot(abar[c], Sya);
+        qb[c][i] = qb[c][i] - sdot_crS<k>(abar[c], ya);
         if constexpr (i > 0) {
-          qb[c][i] = qb[c][i] - sdot(vbar[c], Syv);
+          qb[c][i] = qb[c][i] - sdot_crS<k>(vbar[c], yv);
           abar[c] = xtf<i>(K, T.cs[i], T.sn[i], abar[c]);
           vbar[c] = xtf<i>(K, T.cs[i], T.sn[i], vbar[c]);
           ftb[c] = minv<i>(K, T.cs[i], T.sn[i], xf);
