@@ -551,7 +551,9 @@ static void count_arm_dh(const ArmConst& K, double* fwd, double* rev, double* tr
     count_arm<BOX, kDhGeneric>(K, fwd, rev, transc);
 }
 
-int count_arm_flops(int mount, const float* raw, double* fwd, double* rev, double* transc) {
+// raw: the job's raw constants (host memory), or NULL for a generic table;
+// returns the table's kinematic structure (ArmDh), whose step it counted.
+static int count_arm_table(int mount, const float* raw, double* fwd, double* rev, double* transc) {
   std::vector<float> dflt(130, 0.5f);  // the longest consts layout; a generic table
   dflt[0] = 0.f;
   dflt[1] = 0.f;
@@ -567,4 +569,18 @@ int count_arm_flops(int mount, const float* raw, double* fwd, double* rev, doubl
   return K.dh;
 }
 
+void count_arm_flops(int mount, double* fwd, double* rev, double* transc) {
+  count_arm_table(mount, nullptr, fwd, rev, transc);
+}
+
 }  // namespace pds
+
+extern "C" int pds_arm_algorithmic_flops(int32_t model, const float* consts, double* fwd_step, double* rev_step,
+                                         double* transcendental, int32_t* panda) {
+  if (!consts || !fwd_step || !rev_step || !transcendental) return PDS_EINVAL;
+  if (model != PDS_MODEL_ARM && model != PDS_MODEL_ARM_UJOINT && model != PDS_MODEL_ARM_UJOINT_WEIGHTS)
+    return PDS_EINVAL;
+  const int dh = pds::count_arm_table(pds::arm_mount(model), consts, fwd_step, rev_step, transcendental);
+  if (panda) *panda = dh == pds::kDhPanda ? 1 : 0;
+  return PDS_OK;
+}

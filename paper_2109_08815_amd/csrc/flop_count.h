@@ -42,8 +42,6 @@ inline void sincos_r(Counted x, Counted* sn, Counted* cs) {
 
 // Arm model: forward step, reverse step of one adjoint channel, sin/cos
 // per step (implemented in arm.hip).
-// raw: the job's raw constants (host memory), or NULL for a generic table;
-// returns the table's kinematic structure (ArmDh), whose step it counted.
-int count_arm_flops(int mount, const float* raw, double* fwd, double* rev, double* transc);
+void count_arm_flops(int mount, double* fwd, double* rev, double* transc);
 
 }  // namespace pds

@@ -25,7 +25,6 @@
 // sums over steps are accumulated in FP64.
 #include <cmath>
 
-#include "arm_math.h"
 #include "common.h"
 #include "sincos.h"
 #include "flop_count.h"
@@ -1077,7 +1076,7 @@ extern "C" int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_s
                                      double* transcendental) {
   if (!fwd_step || !rev_step || !transcendental) return PDS_EINVAL;
   if (model == PDS_MODEL_ARM || model == PDS_MODEL_ARM_UJOINT || model == PDS_MODEL_ARM_UJOINT_WEIGHTS) {
-    count_arm_flops(pds::arm_mount(model), nullptr, fwd_step, rev_step, transcendental);
+    count_arm_flops(pds::arm_mount(model), fwd_step, rev_step, transcendental);
     return PDS_OK;
   }
   if (model == PDS_MODEL_PLANAR_RIGID) {
@@ -1097,16 +1096,6 @@ extern "C" int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_s
     case 5: count_planar<5, false>(fwd_step, rev_step, transcendental); break;
     default: return PDS_EUNSUPPORTED;
   }
-  return PDS_OK;
-}
-
-extern "C" int pds_arm_algorithmic_flops(int32_t model, const float* consts, double* fwd_step, double* rev_step,
-                                         double* transcendental, int32_t* panda) {
-  if (!consts || !fwd_step || !rev_step || !transcendental) return PDS_EINVAL;
-  if (model != PDS_MODEL_ARM && model != PDS_MODEL_ARM_UJOINT && model != PDS_MODEL_ARM_UJOINT_WEIGHTS)
-    return PDS_EINVAL;
-  const int dh = count_arm_flops(pds::arm_mount(model), consts, fwd_step, rev_step, transcendental);
-  if (panda) *panda = dh == kDhPanda ? 1 : 0;
   return PDS_OK;
 }
 
