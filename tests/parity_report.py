@@ -1,5 +1,6 @@
 """Measured error of the HIP path against the FP64 oracle, per result and
-workload (run on a GPU: ``python -m tests.parity_report [out.json]``).
+workload (run on a GPU: ``python -m tests.parity_report [out.json]
+[--workloads c1 ... box2] [--no-drift]``).
 
 For every workload at its full size, from identical float32 inputs: the
 window states, window log-likelihoods, log p, mixture weights, both theta
@@ -143,10 +144,16 @@ FIELDS = [("states", "states"), ("end_states", "end states"), ("ll_win_rel", "â„
 
 
 def main():
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("out", nargs="?", help="JSON file for the rows and the drift curve")
+    ap.add_argument("--workloads", nargs="*", default=WORKLOADS, choices=WORKLOADS)
+    ap.add_argument("--no-drift", action="store_true", help="skip the pendulum's 100-iteration drift curve")
+    args = ap.parse_args()
     torch.cuda.set_device(0)
     L.lib()
-    rows = [measure(c) for c in WORKLOADS]
-    curve = drift_c1()
+    rows = [measure(c) for c in args.workloads]
+    curve = [] if args.no_drift else drift_c1()
     print("| workload | " + " | ".join(n for _, n in FIELDS) + " |")
     print("|---" * (len(FIELDS) + 1) + "|")
     for r in rows:
@@ -156,8 +163,8 @@ def main():
         if c["it"] in (1, 2, 5, 10, 20, 50, 100):
             print("c1 drift it %3d: mean %.2e cov %.2e particle %.2e" % (c["it"], c["mean_rel"], c["cov_rel"],
                                                                        c["particle_max"]))
-    if len(sys.argv) > 1:
-        json.dump({"rows": rows, "c1_drift": curve}, open(sys.argv[1], "w"), indent=1)
+    if args.out:
+        json.dump({"rows": rows, "c1_drift": curve}, open(args.out, "w"), indent=1)
 
 
 if __name__ == "__main__":
