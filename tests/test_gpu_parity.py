@@ -481,6 +481,31 @@ def test_batch_matches_single_jobs_bitwise(orc):
             np.testing.assert_array_equal(a, np64(t))
 
 
+def test_arm_structures_share_a_launch_bitwise(orc):
+    """Arm jobs of one shape share their window-kernel launches; a table
+    with the Panda structure and one off it in the same launch each take
+    their own compiled variant (chosen per block) and give bitwise their
+    solo results."""
+    print_case("batch-structures")
+    cases = [make_case(orc, "c4", perturb_S=0.01, lam=True, N=40, T=100, n_s=2),
+             make_case(orc, "c4", perturb_S=0.01, lam=True, N=40, T=100, n_s=2, generic_dh=True),
+             make_case(orc, "box2", perturb_S=0.01, lam=True, N=24, T=96, n_s=2, generic_dh=True)]
+    solo = []
+    for pb, obs, st, job, b in cases:
+        L.csvgd_iteration(b, 1)
+        solo.append([np64(t) for t in (job.theta, job.S, job.logp, job.g_obs, job.g_con, job.phi)])
+    fresh = [L.Job(pb, obs, theta=pb.particles, S=st.S) for pb, obs, st, _, _ in cases]
+    for (pb, obs, st, job, b), f in zip(cases, fresh):
+        f.lam_def.copy_(torch.as_tensor(st.lam_def, dtype=torch.float32))
+    bb = L.Batch(fresh)
+    L.csvgd_iteration(bb, 1)
+    for s, f in zip(solo, fresh):
+        for a, t in zip(s, (f.theta, f.S, f.logp, f.g_obs, f.g_con, f.phi)):
+            np.testing.assert_array_equal(a, np64(t))
+    # (the second c4 table is the first moved off the Panda structure)
+    assert not np.array_equal(solo[0][3], solo[1][3])
+
+
 def test_batch_of_unlike_sizes_matches_single_jobs_bitwise(orc):
     """A job small enough for the two-lanes-per-unit adjoint shares a batch
     with one too large for it: each still takes its own launch shape and
