@@ -99,6 +99,8 @@ def parse():
                     help="where the kernel bandwidth runs: on a second stream concurrently with the adjoint "
                          "(default), or on the iteration's stream before or after it")
     ap.add_argument("--no-overlap", action="store_true", help="same as --bandwidth after")
+    ap.add_argument("--generic-dh", action="store_true",
+                    help="arm configurations: a table off the Panda arm's kinematic structure (generic kernels)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -310,7 +312,7 @@ def main():
         run_metrics(args)
         return
     args.config = args.config or "c4"
-    pb = synth.make_problem(args.config)
+    pb = synth.make_problem(args.config, generic_dh=args.generic_dh)
     print("setup %s N=%d K=%d T=%d n_s=%d" % (args.config, pb.N, pb.K, pb.T, pb.n_s), file=sys.stderr, flush=True)
     obs = driver.gpu_observations(pb)
     S = driver.gpu_shooting_init(pb, pb.particles)
@@ -400,7 +402,8 @@ def main():
                           "rigid2": "rigid-link double pendulum",
                           "box1": "7-joint arm with the box on a universal joint",
                           "box2": "7-joint arm with two weights in the box on a universal joint"}[args.config],
-            pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s), "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain",
+            pb.N, pb.M, pb.K, pb.T, pb.dt, pb.n_s) + (", table off the Panda structure" if args.generic_dh else ""),
+            "launch": ("graph of %d iterations" % per_graph) if use_graph else "plain",
             "bandwidth": {"concurrent": "concurrent with the adjoint", "before": "before the adjoint",
                           "after": "after the adjoint"}[args.bandwidth]},
         "iters_per_s": args.steps / elapsed,
