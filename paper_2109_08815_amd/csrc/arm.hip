@@ -16,7 +16,10 @@
 // that the checkpoints fit the LDS every wave of the job can have while all
 // of them are resident, at the least number of forward-dynamics
 // evaluations.  Checkpoints are [slot][component][lane] floats: each lane
-// owns a bank, so the accesses are conflict-free.
+// owns a bank, so the accesses are conflict-free.  Each kernel holds two
+// compiled variants of the window code, for the Panda arm's kinematic
+// structure and for any other table (ArmDh); the set-up kernel derives
+// which one a job's table has, and each block branches on it once.
 #include <cmath>
 #include <vector>
 
