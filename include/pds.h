@@ -404,8 +404,10 @@ int32_t pds_version(void);
  * (reverse of the same + observation seed + FP64 parameter accumulation),
  * counted by running the library's own step functions on the host with a
  * counting scalar type (add, sub, mul, div = 1 each); sin/cos evaluations
- * are returned separately.  In-window recomputation is not counted.
- * Returns PDS_OK, PDS_EINVAL or PDS_EUNSUPPORTED. */
+ * are returned separately.  In-window recomputation is not counted.  For the
+ * arm models this is the generic kinematic structure's step (a given table's
+ * own: pds_arm_algorithmic_flops).  Returns PDS_OK, PDS_EINVAL or
+ * PDS_EUNSUPPORTED. */
 int pds_algorithmic_flops(int32_t model, int32_t n_dof, double* fwd_step, double* rev_step,
                           double* transcendental);
 
