@@ -423,6 +423,7 @@ def test_step_parity(orc, optimizer, lik, limits, cfg, over):
 @pytest.mark.parametrize("cfg,lik,over", [("c2", synth.LIK_MDMM, dict(K=3)), ("c2", synth.LIK_DEFECT, dict(K=3)),
                                           ("rigid2", synth.LIK_MDMM, dict(K=3)),
                                           ("c4", synth.LIK_MDMM, dict(K=1, T=300, n_s=6)),
+                                          ("c4", synth.LIK_MDMM, dict(K=1, T=300, n_s=6, generic_dh=True)),
                                           ("box1", synth.LIK_MDMM, dict(K=1, T=192, n_s=4))])
 def test_csvgd_iteration_sgd(orc, cfg, lik, over):
     """One full iteration (adjoint -> phi -> step) from identical inputs,
