@@ -136,7 +136,9 @@ __device__ inline void combine_wave(const pds_job& J, int i, const double* l, do
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
   double lp;
-  if (J.combine == PDS_COMBINE_PROD) {
+  if (J.combine == PDS_COMBINE_PROD || K == 1) {
+    // (one trajectory: the mixture's weight is 1 and its log-sum-exp the
+    // trajectory's sum, exactly, so both combinations coincide)
     for (int k = lane; k < K; k += kWave) w[k] = 1.0;
     lp = wave_sum(ls);
   } else {
