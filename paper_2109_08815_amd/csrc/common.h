@@ -119,7 +119,7 @@ constexpr int kPhiThreads = 1024;  // threads per block of the one-kernel phi
 // particles i per block of the one-kernel phi: kPhiTISmall up to
 // kPhiTIMaxN particles, kPhiTILarge above
 constexpr int kPhiTISmall = 16;
-constexpr int kPhiTILarge = 4;
+constexpr int kPhiTILarge = 8;
 constexpr int kPhiTIMaxN = 128;
 inline int phi_ti(int N) { return N <= kPhiTIMaxN ? kPhiTISmall : kPhiTILarge; }
 constexpr int kPhiRows = 512;       // particle rows per LDS chunk of the one-kernel phi

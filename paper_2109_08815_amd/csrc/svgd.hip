@@ -1225,7 +1225,7 @@ __global__ void __launch_bounds__(256) phi_reduce_kernel(JobMap map, const pds_j
 }
 
 // Jobs up to kPhiFusedMaxN particles: phi for TI particles i per block
-// (16 up to 128 particles, 4 above: more blocks, each with less work).  The
+// (16 up to 128 particles, 8 above: more blocks, each with less work).  The
 // block stages the live particles' rows and driving terms in LDS, from
 // kPhiRows particles at a time, compacted in particle order (rows padded
 // with zeros to MM parameters, so the parameter loops run without
